@@ -1,0 +1,36 @@
+"""Small helpers shared by the tests (no method arithmetic)."""
+import numpy as np
+
+
+def live_masks(board):
+    """Boolean masks of the entries each oracle array actually carries: E edges
+    that are updated (not on the outer wall, not PEC) and H faces that exist."""
+    nx, ny, nz = board.nx, board.ny, board.nz
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                             indexing="ij")
+    pec = board.pec_edge_mask
+    m = {}
+    m["ex"] = (ii < nx) & (jj >= 1) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 1) == 0)
+    m["ey"] = (ii >= 1) & (ii < nx) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 2) == 0)
+    m["ez"] = (ii >= 1) & (ii < nx) & (jj >= 1) & (jj < ny) & (kk < nz) & ((pec & 4) == 0)
+    m["hx"] = (jj < ny) & (kk < nz)
+    m["hy"] = (ii < nx) & (kk < nz)
+    m["hz"] = (ii < nx) & (jj < ny)
+    for a, f in (("ddx", "ex"), ("ddy", "ey"), ("ddz", "ez"),
+                 ("bbx", "hx"), ("bby", "hy"), ("bbz", "hz")):
+        m[a] = m[f]
+    return m
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def rel_max(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))

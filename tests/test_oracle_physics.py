@@ -1,0 +1,204 @@
+"""Physical pins of the FP64 oracle: closed forms and the paper's printed values.
+
+* P5  PEC cavity: FFT peaks at the closed-form discrete TM_mn0 resonances
+* P7  UPML reflection below -40 dB against a large-domain reference
+* P9  the wavefront reaches the board's y edge after ~300 ps (Results, Fig. 4 text)
+* Eq. 9 with eps_r = 4.0 reproduces Table 1's predicted column
+* P6  the Table 1 board's FDTD peaks against the paper's modelled column (loose)
+"""
+import os
+
+import numpy as np
+import pytest
+
+import boardgen
+
+C0 = 299792458.0
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_resonances.txt")
+
+
+def _peaks_near(oracle, series, dt, f_targets, tol_bins):
+    n = series.shape[-1]
+    n_fft = oracle.default_nfft(n)
+    X = np.abs(oracle.probe_fft(series, n_fft))
+    f = oracle.bin_freqs(n_fft, dt)
+    bin_phys = 1.0 / (n * dt)
+    pk = oracle.find_peaks(X, f, f_min=0.5 * min(f_targets), rel=0.01)
+    miss = [ft for ft in f_targets if np.min(np.abs(pk - ft)) > tol_bins * bin_phys]
+    return miss, pk, bin_phys
+
+
+def test_p5_pec_cavity_resonances(oracle_mod):
+    # 48 x 40 mm cavity on the paper's 2 / 2 / 0.4 mm grid: coarse enough that the
+    # grid's dispersion shift of the upper modes exceeds one FFT bin
+    nx, ny, nz = 24, 20, 2
+    dx = dy = 2e-3
+    dz = 0.4e-3
+    eps_r = 4.4
+    b = boardgen.cavity_box(nx, ny, nz, dx, dy, dz, eps_r, steps=30000)
+    si, sj, pi_, pj = 3, 3, 20, 16
+    b.sources = [boardgen.Source(si, sj, 0, boardgen.DGAUSS, 1e6, 100e-12, 25e-12)]
+    b.probes = [(pi_, pj, 1)]
+    r = oracle_mod.run(b, threads=8)
+    dt = r.dt
+    v = C0 / np.sqrt(eps_r)
+    a, bb = nx * dx, ny * dy
+    modes = []
+    for m in range(1, 12):
+        for n in range(1, 12):
+            fc = v / 2 * np.hypot(m / a, n / bb)                     # continuum
+            s2 = (v * dt) ** 2 * (np.sin(m * np.pi / (2 * nx)) ** 2 / dx ** 2
+                                  + np.sin(n * np.pi / (2 * ny)) ** 2 / dy ** 2)
+            fd = np.arcsin(np.sqrt(s2)) / (np.pi * dt)                # discrete
+            w = abs(np.sin(m * np.pi * si / nx) * np.sin(n * np.pi * sj / ny)
+                    * np.sin(m * np.pi * pi_ / nx) * np.sin(n * np.pi * pj / ny))
+            if fc < 10e9:
+                modes.append((fc, fd, w))
+    bin_phys = 1.0 / (b.steps * dt)
+    fds = np.array([m[1] for m in modes])
+    targets = [fd for (fc, fd, w) in modes
+               if w >= 0.1 and np.sort(np.abs(fds - fd))[1] >= 3 * bin_phys]
+    assert len(targets) >= 10
+    miss, pk, _ = _peaks_near(oracle_mod, r.probes[0], dt, targets, 1.0)
+    assert not miss, (miss, bin_phys)
+    # the discrete-dispersion shift is resolved: high modes sit nearer the discrete
+    # frequency than the continuum one
+    hi = [(fc, fd) for (fc, fd, w) in modes
+          if fd in targets and fc - fd > 1.5 * bin_phys]
+    assert hi
+    for fc, fd in hi:
+        near = pk[np.argmin(np.abs(pk - fd))]
+        assert abs(near - fd) < abs(near - fc)
+
+
+def _reflection_db(oracle, npml, half_small=12, half_big=60):
+    """Air box with PML on every face, Ez source at the centre, probe two cells
+    in front of the -x PML; reference = the same geometry in a big box."""
+    d = 1e-3
+    wave = (boardgen.DGAUSS, 1e6, 40e-12, 10e-12)
+
+    def box(half):
+        n = 2 * half + 2 * npml
+        eps, mask = boardgen.air(n, n, n)
+        c = n // 2
+        b = boardgen.Board(f"pml{npml}", n, n, n, d, d, d, eps, mask,
+                           npml=(npml,) * 6, steps=260)
+        b.sources = [boardgen.Source(c, c, c, *wave)]
+        b.probes = [(c - half_small + 2, c, c)]   # same offset from the source in both
+        return b
+
+    small, big = box(half_small), box(half_big)
+    e = oracle.run(small, threads=8).probes[0]
+    e_ref = oracle.run(big, threads=8).probes[0]
+    return 20 * np.log10(np.abs(e - e_ref).max() / np.abs(e_ref).max())
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("npml", [8, 10, 12])
+def test_p7_upml_reflection(oracle_mod, npml):
+    assert _reflection_db(oracle_mod, npml) < -40.0
+
+
+def test_p7_no_pml_reflects(oracle_mod):
+    """Sanity of the pin itself: without absorption the same geometry reflects."""
+    d = 1e-3
+    n = 2 * 12 + 16
+    eps, mask = boardgen.air(n, n, n)
+    c = n // 2
+    b = boardgen.Board("nopml", n, n, n, d, d, d, eps, mask, npml=(8,) * 6, steps=260)
+    b.pml_R = 1.0          # sigma_max = 0: the layer is plain air, the wall is PEC
+    b.sources = [boardgen.Source(c, c, c, boardgen.DGAUSS, 1e6, 40e-12, 10e-12)]
+    b.probes = [(c - 12 + 2, c, c)]
+    e = oracle_mod.run(b, threads=8).probes[0]
+    eps2, mask2 = boardgen.air(2 * 60 + 16, 2 * 60 + 16, 2 * 60 + 16)
+    c2 = (2 * 60 + 16) // 2
+    big = boardgen.Board("big", 136, 136, 136, d, d, d, eps2, mask2, npml=(8,) * 6, steps=260)
+    big.sources = [boardgen.Source(c2, c2, c2, boardgen.DGAUSS, 1e6, 40e-12, 10e-12)]
+    big.probes = [(c2 - 12 + 2, c2, c2)]      # same offset from the source
+    e_ref = oracle_mod.run(big, threads=8).probes[0]
+    assert 20 * np.log10(np.abs(e - e_ref).max() / np.abs(e_ref).max()) > -20.0
+
+
+def test_p9_arrival_at_board_edge(oracle_mod):
+    """The paper's Fig. 4 board (100 x 60 x 0.8 mm, 2/2/0.4 mm cells, dt = 1 ps,
+    source at the centre, air around): the wave reaches the y edge after about
+    300 ps = t0 + 30 mm sqrt(eps_r)/c0 with t0 = 100 ps, eps_r = 4."""
+    b, lay = boardgen.plane_stack("fig4", (50, 30), 2, 6, 8, 6, 6, 8,
+                                  2e-3, 2e-3, 0.4e-3, 4.0)
+    b.dt = 1e-12
+    ci = (lay["bi0"] + lay["bi1"]) // 2
+    cj = (lay["bj0"] + lay["bj1"]) // 2
+    b.sources = [boardgen.Source(ci, cj, lay["kg"], boardgen.DGAUSS, 1e6, 100e-12, 50e-12)]
+    b.probes = [(ci, cj + 1, lay["kg"]), (ci, lay["bj1"] - 1, lay["kg"]),
+                (ci, lay["bj1"], lay["kg"])]
+    r = oracle_mod.run(b, nsteps=600, threads=8)
+    t = (np.arange(600) + 1) * r.dt
+
+    def onset(e, frac=0.05):
+        return t[np.argmax(np.abs(e) >= frac * np.abs(e).max())]
+
+    # the front travels at c0/sqrt(eps_r) between the two in-board probes
+    delay = onset(r.probes[1]) - onset(r.probes[0])
+    travel = (lay["bj1"] - 1 - (cj + 1)) * b.dy * np.sqrt(4.0) / C0
+    assert abs(delay - travel) < 0.1 * travel
+    # the pulse peak reaches the y edge (30 mm from the source) near the paper's 300 ps
+    t_edge = t[np.argmax(np.abs(r.probes[2]))]
+    assert abs(t_edge - 300e-12) < 40e-12, t_edge
+
+
+def _table1():
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            m, n, pred, lab, mod = line.split()
+            rows.append((int(m), int(n), float(pred), lab, float(mod)))
+    return rows
+
+
+def _eq9(m, n, eps_r, Lx, Ly, Lz):
+    return C0 / np.sqrt(eps_r) * np.hypot(m / (2 * (Lx + Lz / 2)), n / (2 * (Ly + Lz / 2)))
+
+
+def test_eq9_reproduces_table1_predicted_column():
+    rows = _table1()
+    # the paper omits eps_r: the least-squares fit of Eq. 9 to its column is ~4.0
+    g = np.array([_eq9(m, n, 1.0, 40e-3, 30e-3, 0.8e-3) / 1e9 for m, n, *_ in rows])
+    pred = np.array([r[2] for r in rows])
+    eps_fit = (np.sum(g * g) / np.sum(g * pred)) ** 2
+    assert abs(eps_fit - 4.0) < 0.01
+    for m, n, p, _lab, _mod in rows:
+        f = _eq9(m, n, eps_fit, 40e-3, 30e-3, 0.8e-3) / 1e9
+        assert abs(f - p) <= 0.01, (m, n, f, p)
+
+
+def test_table1_modelled_within_paper_spread():
+    """The paper's modelled peaks sit within -3.6 % .. +1.9 % of Eq. 9."""
+    dev = [(mod - _eq9(m, n, 4.0, 40e-3, 30e-3, 0.8e-3) / 1e9) / mod
+           for m, n, _p, _l, mod in _table1()]
+    assert min(dev) > -0.04 and max(dev) < 0.02
+
+
+@pytest.mark.slow
+def test_p6_table1_board_peaks(oracle_mod):
+    """Context parity, loosely pinned: the paper states neither the air gap, the PML
+    depth nor how its planes meet the grid, and it drives the board through a
+    10-ohm resistive source.  With a current source at the same corner, the
+    spectrum's peaks nearest to each of the 22 modelled frequencies of Table 1 lie
+    within 2 % of it in the median and within 6 % at worst (the paper's own
+    modelled values spread from -3.6 % to +1.9 % around Eq. 9)."""
+    b = boardgen.table1_board(steps=30000)
+    r = oracle_mod.run(b, threads=8)
+    rows = _table1()
+    n_fft = oracle_mod.default_nfft(b.steps)
+    X = np.abs(oracle_mod.probe_fft(r.probes[0], n_fft))
+    f = oracle_mod.bin_freqs(n_fft, r.dt)
+    pk = oracle_mod.find_peaks(X, f, f_min=1.0e9, rel=0.002)
+    dev = []
+    for (m, n, pred, lab, mod) in rows:
+        near = pk[np.argmin(np.abs(pk - mod * 1e9))]
+        dev.append(abs(near - mod * 1e9) / (mod * 1e9))
+    dev = np.array(dev)
+    assert np.median(dev) <= 0.02, dev
+    assert dev.max() <= 0.06, dev

@@ -1,0 +1,361 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+* P1  brute-force sparse-matrix leapfrog (Kronecker curls, diagonal coefficients)
+* P2  PML off: a plain Yee loop written with array slices, and E == D / eps
+* P3  discrete energy of a lossless PEC box is invariant
+* P4  eigen-angles of the one-step map == closed-form discrete dispersion
+* P8  linearity, reciprocity and mirror symmetry
+* P10 the probe FFT against a direct DFT
+* Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
+"""
+import numpy as np
+import pytest
+
+import boardgen
+import bruteforce
+from _util import live_masks, rel_max
+
+C0 = 299792458.0
+MU0 = 4e-7 * np.pi
+EPS0 = 1.0 / (MU0 * C0 ** 2)
+
+
+def _random_state(oracle, board, seed, aux=True):
+    st = oracle.new_state(board)
+    m = live_masks(board)
+    rng = np.random.default_rng(seed)
+    for n in oracle.FIELD_NAMES:
+        if n.startswith(("dd", "bb")) and not aux:
+            continue
+        st[n][...] = np.where(m[n], rng.standard_normal(st[n].shape), 0.0)
+    # give H a physical scale relative to E so both curls matter
+    for n in ("hx", "hy", "hz"):
+        st[n] /= 376.73
+    for n in ("ddx", "ddy", "ddz"):
+        st[n] *= EPS0
+    for n in ("bbx", "bby", "bbz"):
+        st[n] *= MU0 / 376.73
+    return st
+
+
+BF_NAME = {"ddx": "dx", "ddy": "dy", "ddz": "dz", "bbx": "bx", "bby": "by", "bbz": "bz"}
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p1_bruteforce_sources_from_zero(oracle_mod, seed):
+    b = boardgen.random_tiny(seed, steps=40)
+    # make the pulses fire inside the short window
+    for s in b.sources:
+        s.t0 = 15 * oracle_mod.time_step(b)
+        s.sigma = 4 * oracle_mod.time_step(b)
+    r = oracle_mod.run(b)
+    bf, probes = bruteforce.run(b, r.dt, b.steps)
+    for n in oracle_mod.FIELD_NAMES:
+        ref = bf[BF_NAME.get(n, n)]
+        assert np.abs(ref).max() > 0, n
+        assert rel_max(r.state[n], ref) < 1e-12, n
+    assert rel_max(r.probes, probes) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_p1_bruteforce_random_state(oracle_mod, seed):
+    b = boardgen.random_tiny(seed, nx=9, ny=11, nz=7, npml=3, steps=6)
+    b.sources = []
+    st = _random_state(oracle_mod, b, seed)
+    init = {BF_NAME.get(n, n): st[n].copy() for n in oracle_mod.FIELD_NAMES}
+    r = oracle_mod.run(b, state=st)
+    bf, _ = bruteforce.run(b, r.dt, b.steps, init=init)
+    for n in oracle_mod.FIELD_NAMES:
+        assert rel_max(r.state[n], bf[BF_NAME.get(n, n)]) < 1e-12, n
+
+
+def _plain_yee(board, dt, st, nsteps):
+    """Textbook Yee in a PEC box (no PML), E and H only, array slices."""
+    ex, ey, ez, hx, hy, hz = (st[n].copy() for n in ("ex", "ey", "ez", "hx", "hy", "hz"))
+    nx, ny, nz = board.nx, board.ny, board.nz
+    er = board.eps_r_cell.astype(np.float64)
+    ex_eps = EPS0 * 0.25 * (er[:-1, :-1, :] + er[1:, :-1, :] + er[:-1, 1:, :] + er[1:, 1:, :])
+    ey_eps = EPS0 * 0.25 * (er[:-1, :, :-1] + er[1:, :, :-1] + er[:-1, :, 1:] + er[1:, :, 1:])
+    ez_eps = EPS0 * 0.25 * (er[:, :-1, :-1] + er[:, 1:, :-1] + er[:, :-1, 1:] + er[:, 1:, 1:])
+    pec = board.pec_edge_mask
+    dx, dy, dz = board.dx, board.dy, board.dz
+    for _ in range(nsteps):
+        hx[:nz, :ny, :] -= dt / MU0 * ((ez[:nz, 1:, :] - ez[:nz, :-1, :]) / dy
+                                       - (ey[1:, :ny, :] - ey[:-1, :ny, :]) / dz)
+        hy[:nz, :, :nx] -= dt / MU0 * ((ex[1:, :, :nx] - ex[:-1, :, :nx]) / dz
+                                       - (ez[:nz, :, 1:] - ez[:nz, :, :-1]) / dx)
+        hz[:, :ny, :nx] -= dt / MU0 * ((ey[:, :ny, 1:] - ey[:, :ny, :-1]) / dx
+                                       - (ex[:, 1:, :nx] - ex[:, :-1, :nx]) / dy)
+        ex[1:nz, 1:ny, :nx] += dt / ex_eps * ((hz[1:nz, 1:ny, :nx] - hz[1:nz, :ny - 1, :nx]) / dy
+                                              - (hy[1:nz, 1:ny, :nx] - hy[:nz - 1, 1:ny, :nx]) / dz)
+        ey[1:nz, :ny, 1:nx] += dt / ey_eps * ((hx[1:nz, :ny, 1:nx] - hx[:nz - 1, :ny, 1:nx]) / dz
+                                              - (hz[1:nz, :ny, 1:nx] - hz[1:nz, :ny, :nx - 1]) / dx)
+        ez[:nz, 1:ny, 1:nx] += dt / ez_eps * ((hy[:nz, 1:ny, 1:nx] - hy[:nz, 1:ny, :nx - 1]) / dx
+                                              - (hx[:nz, 1:ny, 1:nx] - hx[:nz, :ny - 1, 1:nx]) / dy)
+        ex[(pec & 1) != 0] = 0.0
+        ey[(pec & 2) != 0] = 0.0
+        ez[(pec & 4) != 0] = 0.0
+    return dict(ex=ex, ey=ey, ez=ez, hx=hx, hy=hy, hz=hz)
+
+
+def _inhomogeneous_box(seed, nx=12, ny=10, nz=8):
+    rng = np.random.default_rng(seed)
+    b = boardgen.cavity_box(nx, ny, nz, 1e-3, 0.8e-3, 0.3e-3, 1.0, steps=60)
+    b.eps_r_cell[:] = rng.choice([1.0, 2.5, 4.4], size=b.eps_r_cell.shape).astype(np.float32)
+    boardgen.pec_sheet(b.pec_edge_mask, nz // 2, 2, nx - 3, 3, ny - 2)
+    return b
+
+
+def test_p2_pml_off_is_plain_yee(oracle_mod):
+    b = _inhomogeneous_box(7)
+    st = _random_state(oracle_mod, b, 7, aux=False)
+    r0 = {n: st[n].copy() for n in oracle_mod.FIELD_NAMES}
+    r = oracle_mod.run(b, state=st)
+    ref = _plain_yee(b, r.dt, r0, b.steps)
+    for n in ("ex", "ey", "ez", "hx", "hy", "hz"):
+        assert rel_max(r.state[n], ref[n]) < 1e-12, n
+
+
+def test_p2_e_equals_d_over_eps_without_pml(oracle_mod):
+    b = _inhomogeneous_box(8)
+    b.sources = [boardgen.Source(5, 5, 2, boardgen.GAUSS, 1e6, 20e-12, 5e-12)]
+    r = oracle_mod.run(b, nsteps=80)
+    s = bruteforce.Stepper(b, r.dt)
+    for e, d in (("ex", "ddx"), ("ey", "ddy"), ("ez", "ddz")):
+        m = live_masks(b)[e]
+        ratio_ref = r.state[d][m] / s.eps[e][m]
+        assert rel_max(r.state[e][m], ratio_ref) < 1e-12, e
+
+
+def _energy(b, e_now, h_a, h_b, eps):
+    """Discrete Yee energy W^n = 1/2 sum eps (E^n)^2 V + 1/2 sum mu0 H^{n-1/2} H^{n+1/2} V
+    (uniform dual volumes V = dx dy dz); invariant for a lossless source-free PEC box."""
+    V = b.dx * b.dy * b.dz
+    m = live_masks(b)
+    w = 0.0
+    for e in ("ex", "ey", "ez"):
+        w += 0.5 * np.sum(eps[e][m[e]] * e_now[e][m[e]] ** 2) * V
+    for h in ("hx", "hy", "hz"):
+        w += 0.5 * MU0 * np.sum(h_a[h][m[h]] * h_b[h][m[h]]) * V
+    return w
+
+
+def _energy_series(b, states, eps):
+    """states[n] = (E^{n+1}, H^{n+1/2}) after step n; W^{n+1} pairs E^{n+1} with
+    H^{n+1/2} H^{n+3/2}."""
+    return np.array([_energy(b, states[n][0], states[n][1], states[n + 1][1], eps)
+                     for n in range(len(states) - 1)])
+
+
+def _snap(st):
+    return ({e: st[e].copy() for e in ("ex", "ey", "ez")},
+            {h: st[h].copy() for h in ("hx", "hy", "hz")})
+
+
+def test_p3_energy_invariant_lossless_box(oracle_mod):
+    b = _inhomogeneous_box(9)
+    st = _random_state(oracle_mod, b, 9, aux=False)
+    eps = bruteforce.Stepper(b, oracle_mod.time_step(b)).eps
+    states = []
+    for _ in range(150):
+        oracle_mod.run(b, nsteps=1, state=st)
+        states.append(_snap(st))
+    W = _energy_series(b, states, eps)
+    assert np.all(np.isfinite(W)) and W[0] > 0
+    assert np.abs(W - W[0]).max() / W[0] < 1e-12
+
+
+def test_p3_energy_breaks_with_a_flipped_curl_sign(oracle_mod):
+    """Sanity of the pin itself: a mistake in one curl sign breaks invariance."""
+    b = _inhomogeneous_box(10)
+    st = _random_state(oracle_mod, b, 10, aux=False)
+    s = bruteforce.Stepper(b, oracle_mod.time_step(b))
+    flat = {bruteforce_name(n): st[n].ravel().copy() for n in oracle_mod.FIELD_NAMES}
+    shape = st["ex"].shape
+
+    def run(stepper):
+        f = {k: v.copy() for k, v in flat.items()}
+        states = []
+        for n in range(120):
+            stepper.step(f, n)
+            states.append(_snap({k: f[k].reshape(shape) for k in
+                                 ("ex", "ey", "ez", "hx", "hy", "hz")}))
+        W = _energy_series(b, states, stepper.eps)
+        return np.abs(W - W[0]).max() / abs(W[0])
+
+    assert run(s) < 1e-12                   # the matrix form conserves it too
+    h1, D1, h2, D2 = s.curlH["ex"]          # flip d(Hy)/dz inside curl_x H
+    s.curlH["ex"] = (h1, D1, h2, -D2)
+    assert run(s) > 1e-6
+
+
+def bruteforce_name(n):
+    return BF_NAME.get(n, n)
+
+
+def _discrete_modes(nx, ny, nz, dx, dy, dz, v, dt):
+    """Closed-form eigen-angles omega*dt of the Yee grid in a PEC box."""
+    out = []
+    for p in range(nx):
+        for q in range(ny):
+            for r in range(nz):
+                zeros = (p == 0) + (q == 0) + (r == 0)
+                mult = {0: 2, 1: 1}.get(zeros, 0)
+                if mult == 0:
+                    continue
+                s2 = (v * dt) ** 2 * (np.sin(p * np.pi / (2 * nx)) ** 2 / dx ** 2
+                                      + np.sin(q * np.pi / (2 * ny)) ** 2 / dy ** 2
+                                      + np.sin(r * np.pi / (2 * nz)) ** 2 / dz ** 2)
+                w = 2 * np.arcsin(np.sqrt(s2))
+                out += [w] * mult
+    return np.sort(np.array(out))
+
+
+def test_p4_one_step_map_eigenangles(oracle_mod):
+    nx, ny, nz = 4, 3, 3
+    eps_r = 2.0
+    b = boardgen.cavity_box(nx, ny, nz, 1.0e-3, 1.3e-3, 0.7e-3, eps_r, steps=1)
+    dt = oracle_mod.time_step(b)
+    m = live_masks(b)
+    unknowns = [(n, idx) for n in ("ex", "ey", "ez", "hx", "hy", "hz")
+                for idx in zip(*np.nonzero(m[n]))]
+    N = len(unknowns)
+    # scale E and H so the map is orthogonal-like (eigenvalues are scale-free anyway)
+    M = np.zeros((N, N))
+    for col, (n, idx) in enumerate(unknowns):
+        st = oracle_mod.new_state(b)
+        st[n][idx] = 1.0
+        oracle_mod.run(b, nsteps=1, state=st)
+        M[:, col] = [st[nn][ii] for (nn, ii) in unknowns]
+    lam = np.linalg.eigvals(M)
+    assert np.abs(np.abs(lam) - 1).max() < 1e-9
+    ang = np.sort(np.abs(np.angle(lam)))
+    nonzero = ang[ang > 1e-6]
+    # each oscillating mode contributes the pair exp(+-i w dt)
+    got = np.sort(nonzero)[::2]
+    want = _discrete_modes(nx, ny, nz, b.dx, b.dy, b.dz, C0 / np.sqrt(eps_r), dt)
+    assert len(nonzero) == 2 * len(want)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-9)
+
+
+def test_p8_linearity(oracle_mod):
+    b = boardgen.random_tiny(11, steps=60)
+    for s in b.sources:
+        s.t0 = 20 * oracle_mod.time_step(b)
+        s.sigma = 5 * oracle_mod.time_step(b)
+    both = oracle_mod.run(b).probes
+    parts = []
+    for s in b.sources:
+        bi = boardgen.random_tiny(11, steps=60)
+        bi.sources = [s]
+        parts.append(oracle_mod.run(bi).probes)
+    assert rel_max(both, parts[0] + parts[1]) < 1e-12
+    # scaling
+    b2 = boardgen.random_tiny(11, steps=60)
+    b2.sources = [boardgen.Source(s.i, s.j, s.k, s.waveform, -3.5 * s.J0, s.t0, s.sigma)
+                  for s in b.sources]
+    assert rel_max(oracle_mod.run(b2).probes, -3.5 * both) < 1e-12
+
+
+def test_p8_reciprocity_lossless(oracle_mod):
+    b = _inhomogeneous_box(12, nx=14, ny=12, nz=6)
+    a_pt, b_pt = (3, 4, 2), (10, 8, 3)
+    outs = []
+    for src, prb in ((a_pt, b_pt), (b_pt, a_pt)):
+        bb = _inhomogeneous_box(12, nx=14, ny=12, nz=6)
+        bb.pec_edge_mask[:] = b.pec_edge_mask
+        bb.sources = [boardgen.Source(*src, boardgen.DGAUSS, 1e6, 10e-12, 3e-12)]
+        bb.probes = [prb]
+        outs.append(oracle_mod.run(bb, nsteps=300).probes[0])
+    assert np.abs(outs[0]).max() > 0
+    assert rel_max(outs[0], outs[1]) < 1e-10
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+def test_p8_mirror_symmetry_with_pml(oracle_mod, axis):
+    """A board symmetric about a mid plane (PML on both sides) gives mirror-equal
+    probes: catches a misplaced node/half-node coefficient on that axis."""
+    nx, ny, nz = 16, 14, 12
+    ci, cj, ck = nx // 2, ny // 2, nz // 2
+    eps, mask = boardgen.air(nx, ny, nz)
+    # cell blocks symmetric about x = ci, y = cj and z = ck
+    eps[4:8, 5:9, 3:13] = 3.0
+    eps[4:8, 3:11, 6:10] = 2.0
+    b = boardgen.Board("mirror", nx, ny, nz, 1e-3, 0.9e-3, 0.5e-3, eps, mask,
+                       npml=(3, 3, 4, 4, 2, 2), steps=120)
+    w = (boardgen.DGAUSS, 1e6, 30e-12, 8e-12)
+    if axis == "x":       # Ez on the plane x = ci is even under x -> -x
+        b.sources = [boardgen.Source(ci, 5, 4, *w)]
+        b.probes = [(ci - 5, 9, 3), (ci + 5, 9, 3)]
+    elif axis == "y":
+        b.sources = [boardgen.Source(5, cj, 4, *w)]
+        b.probes = [(9, cj - 4, 3), (9, cj + 4, 3)]
+    else:
+        # Ez(k+1/2) maps to -Ez(2 ck - 1 - k + 1/2) under z -> -z; two equal sources
+        # at k = ck-1 and k = ck make the configuration odd, so Ez is even
+        b.sources = [boardgen.Source(5, 4, ck - 1, *w), boardgen.Source(5, 4, ck, *w)]
+        b.probes = [(9, 4, ck - 4), (9, 4, ck + 3)]
+    r = oracle_mod.run(b)
+    assert np.abs(r.probes[0]).max() > 0
+    assert rel_max(r.probes[0], r.probes[1]) < 1e-11
+
+
+def test_p10_probe_fft_against_direct_dft(oracle_mod):
+    rng = np.random.default_rng(5)
+    e = rng.standard_normal(300)
+    n_fft = 512
+    X = oracle_mod.probe_fft(e, n_fft)
+    s = np.arange(300)
+    k = np.arange(n_fft // 2 + 1)
+    direct = (e[None, :] * np.exp(-2j * np.pi * np.outer(k, s) / n_fft)).sum(1)
+    assert np.abs(X - direct).max() / np.abs(direct).max() < 1e-12
+
+
+def test_eq7_time_step_values(oracle_mod):
+    # the paper's grid: dx = dy = 2 mm, dz = 0.4 mm -> Eq. 7 with c0
+    dtc = oracle_mod._load().or_cfl_dt(2e-3, 2e-3, 0.4e-3)
+    want = 1.0 / (C0 * np.sqrt(2 / 2e-3 ** 2 + 1 / 0.4e-3 ** 2))
+    assert abs(dtc - want) / want < 1e-15
+    assert abs(dtc - 1.28389e-12) < 1e-17
+    # config 1 at courant 0.99 -> 0.6355 ps
+    assert abs(oracle_mod.time_step(boardgen.config1()) - 0.6355e-12) < 1e-16
+    # the paper's 1 ps step is below the limit; 1.33 ps equals dz / c0
+    assert 1e-12 < dtc and abs(0.4e-3 / C0 - 1.334e-12) < 1e-15
+
+
+def test_dt_override_is_used(oracle_mod):
+    b = boardgen.table1_board(steps=10)
+    assert oracle_mod.time_step(b) == 1e-12
+
+
+def test_waveforms(oracle_mod):
+    # Gaussian: peak J0 at t0, J0 e^{-1/2} one sigma away
+    assert oracle_mod.waveform(0, 2.0, 1e-10, 3e-11, 1e-10) == 2.0
+    assert abs(oracle_mod.waveform(0, 2.0, 1e-10, 3e-11, 1.3e-10) - 2 * np.exp(-0.5)) < 1e-15
+    # differentiated Gaussian (Eq. 8 read with the square): odd about t0, extremum at tau/sqrt2
+    t0, tau = 1e-10, 5e-11
+    assert oracle_mod.waveform(1, 1.0, t0, tau, t0) == 0.0
+    a = oracle_mod.waveform(1, 1.0, t0, tau, t0 + 2e-11)
+    assert abs(a + oracle_mod.waveform(1, 1.0, t0, tau, t0 - 2e-11)) < 1e-15
+    tt = t0 + tau / np.sqrt(2)
+    g = [oracle_mod.waveform(1, 1.0, t0, tau, tt + d) for d in (-1e-14, 0, 1e-14)]
+    assert g[1] > g[0] and g[1] > g[2]
+
+
+def test_eq5_grading_hand_values(oracle_mod):
+    """sigma_max = -(m+1) ln R / (2 eta0 N delta): 9.168 S/m in x and 45.84 S/m in z
+    for the 48 x 40 mm board (N = 8, 1 mm / 0.2 mm cells, m = 3, R = 1e-6); zero at
+    the PML interface, sigma_max (depth/N)^3 inside, kappa = 1."""
+    b = boardgen.config1()
+    sx_wall, kx = oracle_mod.sigma_kappa(b, 0, 0.0)
+    sz_wall, _ = oracle_mod.sigma_kappa(b, 2, float(b.nz))
+    assert abs(sx_wall - 9.1676) < 1e-3 and abs(sz_wall - 45.838) < 1e-2 and kx == 1.0
+    assert oracle_mod.sigma_kappa(b, 0, 8.0) == (0.0, 1.0)           # interface node
+    assert oracle_mod.sigma_kappa(b, 1, 30.5) == (0.0, 1.0)          # interior
+    s_half, _ = oracle_mod.sigma_kappa(b, 0, 4.0)                    # half depth
+    assert abs(s_half - sx_wall / 8) < 1e-12
+    s_hi, _ = oracle_mod.sigma_kappa(b, 0, b.nx - 0.5)               # 7.5 cells deep, +x side
+    assert abs(s_hi - sx_wall * (7.5 / 8) ** 3) < 1e-12
+    b2 = boardgen.config1()
+    b2.pml_kappa_max = 5.0
+    assert abs(oracle_mod.sigma_kappa(b2, 2, 2.0)[1] - (1 + 4 * (6 / 8) ** 3)) < 1e-12
