@@ -1,0 +1,202 @@
+/*
+ * libfdtd: MI355X (gfx950) Yee/UPML leapfrog for PCB power/ground-plane stacks.
+ *
+ * The method is the one of "A Time Domain Approach to Power Integrity for Printed
+ * Circuit Boards" (Mattey, Edwards, Hood): Maxwell's curl equations on a Yee
+ * grid (Model section, Fig. 2), terminated by a uniaxial PML whose auxiliary D
+ * and B fields are stepped in a two-step D->E / B->H process (Eqs. 1-4) with a
+ * polynomially graded loss (Eq. 5) and an outer PEC wall, a time step bounded by
+ * the CFL limit (Eq. 7), PEC power/ground planes that zero tangential Ex/Ey
+ * (Model section), a current source (Results section, Eq. 8) and the FFT of a
+ * probe's Ez (Results section, Fig. 5 / Table 1).
+ *
+ * Conventions for every call:
+ *   - Grid: nx, ny, nz cells including air and PML; nodes run 0..n on each axis.
+ *     Field arrays exchanged with the caller have (nz+1)*(ny+1)*(nx+1) entries,
+ *     x fastest: index = i + (nx+1)*(j + (ny+1)*k).  Ex(i,j,k) is Ex at
+ *     (i+1/2, j, k); Ey at (i, j+1/2, k); Ez at (i, j, k+1/2); Hx at
+ *     (i, j+1/2, k+1/2); Hy at (i+1/2, j, k+1/2); Hz at (i+1/2, j+1/2, k).
+ *   - Pointers marked "host" are host memory, read (or written) during the call
+ *     only; the caller keeps ownership.  Device memory is owned by the handle.
+ *   - Return value: 0 (FDTD_OK) or a negative FDTD_E* code; the message of the
+ *     last failure on the calling thread is in fdtd_last_error().  No call
+ *     throws.  A handle is not thread safe; distinct handles are independent.
+ *   - Stepping is asynchronous on the handle's HIP stream; every call that
+ *     returns data to the host synchronises that stream first.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDTD_OK 0
+#define FDTD_EINVAL (-1)    /* null / out-of-range argument, dt above the CFL limit, ... */
+#define FDTD_ESTATE (-2)    /* call not allowed in the handle's current state */
+#define FDTD_ENOMEM (-3)    /* device or host allocation failed (nothing leaked) */
+#define FDTD_EDEVICE (-4)   /* a HIP runtime call failed */
+#define FDTD_EUNSTABLE (-5) /* non-finite field value found by the watchdog */
+
+#define FDTD_WAVE_GAUSS 0   /* J0 exp(-(t-t0)^2 / (2 sigma^2)) */
+#define FDTD_WAVE_DGAUSS 1  /* J0 ((t-t0)/tau) exp(-((t-t0)/tau)^2): Eq. 8 read as a pulse */
+
+/* field component ids for fdtd_get_field / fdtd_set_field */
+enum {
+    FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ,
+    FDTD_DX, FDTD_DY, FDTD_DZ, FDTD_BX, FDTD_BY, FDTD_BZ
+};
+
+typedef struct fdtd_grid fdtd_grid;
+
+/* Optional device allocator (e.g. PyTorch's caching allocator).  alloc returns a
+ * device pointer of at least `bytes` bytes aligned to 256 B, or NULL; free
+ * releases it.  Both are called only from fdtd_create_grid/fdtd_set_dft_freqs
+ * and fdtd_destroy_grid. */
+typedef void* (*fdtd_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*fdtd_free_fn)(void* ptr, void* ctx);
+
+typedef struct {
+    int32_t nx, ny, nz;          /* cells incl. air and PML; each >= 2 */
+    double dx, dy, dz;           /* cell size in metres (anisotropic allowed, Model section) */
+    double dt;                   /* seconds; 0 => courant * Eq. 7 limit with c0 */
+    double courant;              /* used when dt == 0; in (0, 1) (0 => 0.99) */
+    int32_t npml[6];             /* PML depth in cells on -x,+x,-y,+y,-z,+z (0 = bare PEC wall) */
+    double pml_m;                /* Eq. 5 grading order (0 => 3) */
+    double pml_R;                /* target normal-incidence reflection in (0, 1] (0 => 1e-6) */
+    double pml_kappa_max;        /* Eq. 5 kappa_max >= 1 (0 => 1) */
+    int64_t max_steps;           /* capacity of the probe series and source tables, >= 1 */
+    void* hip_stream;            /* hipStream_t to run on; NULL => the handle creates one */
+    fdtd_alloc_fn dev_alloc;     /* NULL => hipMalloc */
+    fdtd_free_fn dev_free;       /* NULL => hipFree; must be set iff dev_alloc is */
+    void* alloc_ctx;
+} fdtd_grid_desc;
+
+typedef struct {
+    double dt;                   /* time step in use */
+    int64_t step;                /* completed steps */
+    int64_t max_steps;
+    int64_t cells;               /* nx*ny*nz (the unit of "cell-updates") */
+    int64_t nodes;               /* (nx+1)(ny+1)(nz+1) */
+    int64_t step_bytes;          /* algorithmic HBM bytes one step of the field kernel must move */
+    int64_t device_bytes;        /* device memory held by the handle */
+    int32_t n_sources, n_probes, n_freqs;
+    int32_t n_classes;           /* distinct per-node material classes after finalisation */
+    int32_t tile_x, tile_y;      /* tile shape the field kernel runs with */
+} fdtd_info;
+
+/* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
+ * Eqs. 1-5 with sigma_max = -(m+1) ln R / (2 eta0 N delta) on each face, outer PEC
+ * wall; Eq. 7 time step).  All fields start at zero.  EINVAL: sizes < 2, node
+ * count >= 2^31, non-positive spacing, dt at or above the Eq. 7 limit (c0),
+ * courant outside (0, 1), npml < 0 or two opposite layers overlapping,
+ * max_steps < 1.  ENOMEM: device allocation failed (no handle is returned). */
+int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out);
+
+/* Materials (Model section, Fig. 1): eps_r_cell (host, nx*ny*nz floats, x fastest,
+ * each finite and >= 1) is the relative permittivity of every cell; each E edge
+ * takes the mean of the cells that touch it.  pec_edge_mask (host,
+ * (nx+1)(ny+1)(nz+1) bytes, NULL = none) marks PEC edges: bit 0 Ex(i+1/2,j,k),
+ * bit 1 Ey(i,j+1/2,k), bit 2 Ez(i,j,k+1/2); marked edges stay exactly 0 (the
+ * power and ground planes).  ESTATE after the first step.  EINVAL if the
+ * material classes exceed 65535. */
+int fdtd_set_materials(fdtd_grid* g, const float* eps_r_cell, const uint8_t* pec_edge_mask);
+
+/* Current source Jz (A/m^2) on the edge Ez(i, j, k+1/2), 1 <= i < nx,
+ * 1 <= j < ny, 0 <= k < nz, not PEC (Results section: current source through the
+ * D update).  waveform FDTD_WAVE_GAUSS or FDTD_WAVE_DGAUSS with width sigma > 0;
+ * sampled at the half step (s+1/2) dt.  *id receives the source index.  ESTATE
+ * after the first step. */
+int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0,
+                    double t0, double sigma, int* id);
+
+/* Probe of Ez(i, j, k+1/2), 0 <= i <= nx, 0 <= j <= ny, 0 <= k < nz (Results
+ * section: ground-plane Ez recorded every step).  Sample s of the series is Ez at
+ * time (s+1) dt, stored in FP32.  *id receives the probe index.  ESTATE after the
+ * first step. */
+int fdtd_add_probe(fdtd_grid* g, int i, int j, int k, int* id);
+
+/* Optional running DFT of every probe (FP64 accumulators, FP32 samples):
+ * A[p][q] = sum_s e_p[s] exp(-i 2 pi f_q (s+1) dt) dt.  f_hz (host, nf values,
+ * each >= 0 and finite), 1 <= nf <= 4096.  ESTATE after the first step. */
+int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
+
+/* Enqueue n >= 0 leapfrog steps (per step: B then H at n+1/2 from E at n, D then E
+ * at n+1 with the source, PEC planes and probes).  The first call finalises the
+ * set-up.  ESTATE if steps would exceed max_steps or materials were never set.
+ * EUNSTABLE if the watchdog (checked at the end of the call) found a non-finite
+ * probe sample or field value in the last step; stepping stays possible. */
+int fdtd_step_n(fdtd_grid* g, int64_t n);
+
+/* Batched stepping: advance ng handles by n[h] steps each in shared launches
+ * (one field launch per step covers every handle still running).  Handles must
+ * be distinct and share one device; results are bitwise those of stepping each
+ * alone.  Runs on the first handle's stream.  Same errors as fdtd_step_n. */
+int fdtd_step_many(fdtd_grid* const* g, int ng, const int64_t* n);
+
+/* Spectrum of probe `id` over the steps run so far (Results section, Fig. 5):
+ * X[k] = sum_{s<N} e[s] exp(-2 pi i k s / n_fft) for k = 0..n_fft/2 with a
+ * rectangular window, zero padding, FP64; bin k is at k / (n_fft dt).  n_fft a
+ * power of two >= N (N = completed steps), <= 2^26.  re, im: host, n_fft/2+1
+ * doubles each.  Synchronises. */
+int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im);
+
+/* Copy the first n samples (n <= completed steps) of probe `id` into out (host,
+ * n floats).  Synchronises. */
+int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n);
+
+/* Copy probe `id`'s DFT accumulators into re, im (host, nf doubles each).
+ * Synchronises. */
+int fdtd_get_dft(fdtd_grid* g, int id, double* re, double* im);
+
+/* Field access in SI units (host buffers of (nx+1)(ny+1)(nz+1) floats).  D and B
+ * are the UPML auxiliaries of Eq. 4 (zero where the layout keeps none: the
+ * library stores D/B only where a PML loss acts on them).  set is allowed before
+ * the first step or between steps; it replaces the state at the current step.
+ * Synchronises. */
+int fdtd_get_field(fdtd_grid* g, int comp, float* out);
+int fdtd_set_field(fdtd_grid* g, int comp, const float* in);
+
+/* Checkpoint: the whole stepping state (fields, auxiliaries, step counter, probe
+ * samples, DFT accumulators) as an opaque byte image of fdtd_state_bytes(g)
+ * bytes.  Loading an image saved from a handle with identical set-up and
+ * continuing gives bitwise the same results as never stopping.  Synchronises. */
+int64_t fdtd_state_bytes(fdtd_grid* g);
+int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes);
+int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes);
+
+/* Information about the handle (valid at any time). */
+int fdtd_get_info(fdtd_grid* g, fdtd_info* out);
+
+/* Tile shape of the field kernel, (tile_x, tile_y) from fdtd_tile_shapes();
+ * results do not depend on it (bitwise).  ESTATE after the first step. */
+int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y);
+
+/* Supported tile shapes: writes up to `cap` pairs into xy (host, 2*cap ints) and
+ * returns the number of shapes. */
+int fdtd_tile_shapes(int* xy, int cap);
+
+/* Kernel timing for measurement: while on, every launch of the field kernel is
+ * bracketed by HIP events on the stream it runs on.  fdtd_get_timing synchronises
+ * and returns the summed duration (ms) and the launch count since it was
+ * switched on, then clears them. */
+int fdtd_set_timing(fdtd_grid* g, int on);
+int fdtd_get_timing(fdtd_grid* g, double* ms, int64_t* launches);
+
+/* Block until all work enqueued on the handle's stream has finished. */
+int fdtd_synchronize(fdtd_grid* g);
+
+/* Release everything the handle holds.  NULL is accepted. */
+int fdtd_destroy_grid(fdtd_grid* g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fdtd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

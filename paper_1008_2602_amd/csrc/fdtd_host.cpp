@@ -1,0 +1,962 @@
+// Host side of libfdtd: argument checking, set-up arithmetic in FP64 (time step,
+// UPML profiles, per-node material classes, source samples), device memory,
+// launch sequencing, probe spectra and state I/O.  See include/fdtd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "fdtd.h"
+#include "fdtd_internal.h"
+
+namespace fdtd {
+// kernels (fdtd_kernels.hip)
+int num_shapes();
+void shape_at(int s, int* tx, int* ty);
+hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards, const TileRef* tiles,
+                             int ntiles, int rel, bool wide, hipStream_t st);
+hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
+hipError_t launch_advance_one(int64_t* step, int64_t n, hipStream_t st);
+hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
+                      double dt, int64_t s0, int64_t s1, double* re, double* im, hipStream_t st);
+hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
+                      double2** result, hipStream_t st);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
+}  // namespace fdtd
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(FDTD_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+struct SourceH {
+    int i, j, k, wave;
+    double J0, t0, sigma;
+};
+
+struct ClassKey {
+    uint32_t a, b, c, f;
+    bool operator==(const ClassKey& o) const { return a == o.a && b == o.b && c == o.c && f == o.f; }
+};
+struct ClassKeyHash {
+    size_t operator()(const ClassKey& k) const
+    {
+        uint64_t h = 1469598103934665603ull;
+        for (uint32_t v : {k.a, k.b, k.c, k.f}) {
+            h ^= v;
+            h *= 1099511628211ull;
+        }
+        return (size_t)h;
+    }
+};
+
+uint32_t fbits(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    return u;
+}
+
+}  // namespace
+
+struct fdtd_grid {
+    fdtd_grid_desc d{};
+    double dt = 0.0;
+    int64_t nodes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::vector<void*> allocs;
+    int64_t device_bytes = 0;
+
+    // device state
+    float* f[2][9] = {};
+    float* dd[3] = {};
+    float* coef[3] = {};
+    void* cls = nullptr;
+    ClassEntry* ctab = nullptr;
+    int32_t* src_node = nullptr;
+    float* src_j = nullptr;
+    int32_t* prb_node = nullptr;
+    float* prb_series = nullptr;
+    double* dft_f = nullptr;
+    double* dft_re = nullptr;
+    double* dft_im = nullptr;
+    int64_t* step_dev = nullptr;
+    int32_t* bad_dev = nullptr;
+    BoardDev* board_dev = nullptr;
+    TileRef* tiles_dev = nullptr;
+    int ntiles = 0;
+    BoardDev board_host{};
+
+    // host-side set-up
+    std::vector<float> eps;
+    std::vector<uint8_t> pec;
+    bool have_materials = false;
+    std::vector<SourceH> sources;
+    std::vector<std::array<int, 3>> probes;
+    std::vector<double> freqs;
+    int n_classes = 0;
+    bool wide = false;
+    bool finalized = false;
+    int64_t step = 0;
+    int tile_x = 64, tile_y = 8;
+    int64_t step_bytes = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t timed_launches = 0;
+
+    // batched-launch scratch (owned by the handle that leads a batch)
+    BoardDev* batch_boards = nullptr;
+    int batch_boards_cap = 0;
+    TileRef* batch_tiles = nullptr;
+    int batch_tiles_cap = 0;
+    int64_t* batch_n = nullptr;
+    int batch_n_cap = 0;
+};
+
+namespace {
+
+void* dev_alloc(fdtd_grid* g, size_t bytes)
+{
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (g->d.dev_alloc) {
+        p = g->d.dev_alloc(bytes, g->d.alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        g->allocs.push_back(p);
+        g->device_bytes += (int64_t)bytes;
+    }
+    return p;
+}
+
+void* temp_alloc(fdtd_grid* g, size_t bytes)
+{
+    bytes = (bytes + 255) & ~size_t(255);
+    if (g->d.dev_alloc) return g->d.dev_alloc(bytes, g->d.alloc_ctx);
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void temp_free(fdtd_grid* g, void* p)
+{
+    if (!p) return;
+    if (g->d.dev_free)
+        g->d.dev_free(p, g->d.alloc_ctx);
+    else
+        (void)hipFree(p);
+}
+
+// Stream-ordered copy that has completed when it returns (the handle's stream
+// may be a non-blocking one, which the legacy null stream does not order with).
+hipError_t copy_sync(fdtd_grid* g, void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, g->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(g->stream);
+}
+
+void dev_free_all(fdtd_grid* g)
+{
+    for (void* p : g->allocs) {
+        if (g->d.dev_free)
+            g->d.dev_free(p, g->d.alloc_ctx);
+        else
+            (void)hipFree(p);
+    }
+    g->allocs.clear();
+}
+
+// Eq. 5 grading at coordinate pos (cell units) on an axis of n cells with PML
+// depths nlo/nhi: depth from the PML interface towards the outer wall.
+void profile(const fdtd_grid_desc& d, double pos, int n, int nlo, int nhi, double delta,
+             double* sigma, double* kappa)
+{
+    double depth = 0.0, N = 0.0;
+    if (nlo > 0 && pos < nlo) {
+        depth = nlo - pos;
+        N = nlo;
+    } else if (nhi > 0 && pos > n - nhi) {
+        depth = pos - (n - nhi);
+        N = nhi;
+    }
+    if (depth <= 0.0) {
+        *sigma = 0.0;
+        *kappa = 1.0;
+        return;
+    }
+    depth = std::min(depth, N);  // half nodes past the wall only feed components that stay 0
+    const double fr = std::pow(depth / N, d.pml_m);
+    const double smax = -(d.pml_m + 1.0) * std::log(d.pml_R) / (2.0 * kEta0 * N * delta);
+    *sigma = fr * smax;
+    *kappa = 1.0 + (d.pml_kappa_max - 1.0) * fr;
+}
+
+std::vector<float> coef_table(const fdtd_grid_desc& d, int axis, double dt)
+{
+    const int n = axis == 0 ? d.nx : axis == 1 ? d.ny : d.nz;
+    const double delta = axis == 0 ? d.dx : axis == 1 ? d.dy : d.dz;
+    const int nlo = d.npml[2 * axis], nhi = d.npml[2 * axis + 1];
+    std::vector<float> t((size_t)kNumCoef * 2 * (n + 1));
+    for (int half = 0; half < 2; ++half)
+        for (int i = 0; i <= n; ++i) {
+            double s, k;
+            profile(d, i + 0.5 * half, n, nlo, nhi, delta, &s, &k);
+            const double q = s * dt / kEps0;
+            const double ph = k + 0.5 * q;
+            const double v[kNumCoef] = {-q / ph, (k - 0.5 * q) / ph, 1.0 / ph, ph, q};
+            for (int c = 0; c < kNumCoef; ++c)
+                t[((size_t)c * 2 + half) * (n + 1) + i] = (float)v[c];
+        }
+    return t;
+}
+
+double waveform(const SourceH& s, double t)
+{
+    const double u = (t - s.t0) / s.sigma;
+    if (s.wave == FDTD_WAVE_DGAUSS) return s.J0 * u * std::exp(-u * u);
+    return s.J0 * std::exp(-0.5 * u * u);
+}
+
+int check_grid(fdtd_grid* g)
+{
+    if (!g) return fail(FDTD_EINVAL, "null grid handle");
+    return FDTD_OK;
+}
+
+int64_t node_index(const fdtd_grid* g, int i, int j, int k)
+{
+    return (int64_t)i + (int64_t)(g->d.nx + 1) * ((int64_t)j + (int64_t)(g->d.ny + 1) * k);
+}
+
+// Count the bytes one field step must move with this layout: E and H read and
+// written once per node, the class byte(s) once, and each stored D/B component
+// read and written once where its PML predicate holds.
+int64_t count_step_bytes(const fdtd_grid* g)
+{
+    const fdtd_grid_desc& d = g->d;
+    auto in_pml = [](int idx, int n, int lo, int hi) {
+        return idx < lo || (hi > 0 && idx >= n - hi);
+    };
+    int64_t px = 0, py = 0, pz = 0;
+    for (int i = 0; i <= d.nx; ++i) px += in_pml(i, d.nx, d.npml[0], d.npml[1]);
+    for (int j = 0; j <= d.ny; ++j) py += in_pml(j, d.ny, d.npml[2], d.npml[3]);
+    for (int k = 0; k <= d.nz; ++k) pz += in_pml(k, d.nz, d.npml[4], d.npml[5]);
+    const int64_t X = d.nx + 1, Y = d.ny + 1, Z = d.nz + 1;
+    // nodes where (a or b) holds, a/b independent predicates on two axes
+    auto either = [](int64_t pa, int64_t na, int64_t pb, int64_t nb, int64_t other) {
+        return (pa * nb + na * pb - pa * pb) * other;
+    };
+    const int64_t aux_x = either(px, X, py, Y, Z);  // Dx, Bx: x or y PML
+    const int64_t aux_y = either(py, Y, pz, Z, X);  // Dy, By: y or z PML
+    const int64_t aux_z = either(pz, Z, px, X, Y);  // Dz, Bz: z or x PML
+    const int64_t cls_bytes = g->wide ? 2 : 1;
+    return g->nodes * (24 + 24 + cls_bytes) + (aux_x + aux_y + aux_z) * 2 * 8;
+}
+
+int finalize(fdtd_grid* g)
+{
+    if (g->finalized) return FDTD_OK;
+    const fdtd_grid_desc& d = g->d;
+    if (!g->have_materials) return fail(FDTD_ESTATE, "fdtd_set_materials was never called");
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int64_t N = g->nodes;
+    // sources and probes
+    for (const SourceH& s : g->sources) {
+        if (g->pec[node_index(g, s.i, s.j, s.k)] & 4)
+            return fail(FDTD_EINVAL, "source at (%d,%d,%d) sits on a PEC edge", s.i, s.j, s.k);
+    }
+    std::vector<int32_t> src_node, prb_node;
+    for (const SourceH& s : g->sources) src_node.push_back((int32_t)node_index(g, s.i, s.j, s.k));
+    for (const auto& p : g->probes) prb_node.push_back((int32_t)node_index(g, p[0], p[1], p[2]));
+    std::vector<uint8_t> is_src(0), is_prb(0);
+
+    // per-node classes: edge permittivity (mean of the touching cells), stepped
+    // components (not on the outer wall, not PEC), source/probe marks
+    std::unordered_map<ClassKey, uint32_t, ClassKeyHash> map;
+    std::vector<ClassEntry> table;
+    std::vector<uint16_t> ids((size_t)N);
+    std::vector<uint8_t> mark((size_t)N, 0);
+    for (int32_t v : src_node) mark[v] |= 1;
+    for (int32_t v : prb_node) mark[v] |= 2;
+    const float* er = g->eps.data();
+    auto cell = [&](int i, int j, int k) -> double {
+        return (double)er[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
+    };
+    ClassKey last{~0u, ~0u, ~0u, ~0u};
+    uint32_t last_id = 0;
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                const int64_t n = node_index(g, i, j, k);
+                const uint8_t pm = g->pec[n];
+                uint32_t fl = 0;
+                float ix = 0.f, iy = 0.f, iz = 0.f;
+                if (i < nx && j >= 1 && j < ny && k >= 1 && k < nz && !(pm & 1)) {
+                    fl |= kUpdEx;
+                    ix = (float)(4.0 / (cell(i, j - 1, k - 1) + cell(i, j, k - 1) +
+                                        cell(i, j - 1, k) + cell(i, j, k)));
+                }
+                if (i >= 1 && i < nx && j < ny && k >= 1 && k < nz && !(pm & 2)) {
+                    fl |= kUpdEy;
+                    iy = (float)(4.0 / (cell(i - 1, j, k - 1) + cell(i, j, k - 1) +
+                                        cell(i - 1, j, k) + cell(i, j, k)));
+                }
+                if (i >= 1 && i < nx && j >= 1 && j < ny && k < nz && !(pm & 4)) {
+                    fl |= kUpdEz;
+                    iz = (float)(4.0 / (cell(i - 1, j - 1, k) + cell(i, j - 1, k) +
+                                        cell(i - 1, j, k) + cell(i, j, k)));
+                }
+                if (mark[n] & 1) fl |= kSrcEz;
+                if (mark[n] & 2) fl |= kPrbEz;
+                const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl};
+                uint32_t id;
+                if (key == last) {
+                    id = last_id;
+                } else {
+                    auto it = map.find(key);
+                    if (it == map.end()) {
+                        if (table.size() >= 65535)
+                            return fail(FDTD_EINVAL,
+                                        "more than 65535 distinct (edge permittivity, PEC, "
+                                        "source, probe) node classes");
+                        id = (uint32_t)table.size();
+                        map.emplace(key, id);
+                        table.push_back(ClassEntry{ix, iy, iz, fl});
+                    } else {
+                        id = it->second;
+                    }
+                    last = key;
+                    last_id = id;
+                }
+                ids[(size_t)n] = (uint16_t)id;
+            }
+    g->n_classes = (int)table.size();
+    g->wide = table.size() > 256;
+    hipStream_t st = g->stream;
+    if (g->wide) {
+        g->cls = dev_alloc(g, (size_t)N * 2);
+        if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids.data(), (size_t)N * 2, hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<uint8_t> ids8((size_t)N);
+        for (size_t t = 0; t < (size_t)N; ++t) ids8[t] = (uint8_t)ids[t];
+        g->cls = dev_alloc(g, (size_t)N);
+        if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids8.data(), (size_t)N, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipStreamSynchronize(st));
+    }
+    g->ctab = (ClassEntry*)dev_alloc(g, table.size() * sizeof(ClassEntry));
+    if (!g->ctab) return fail(FDTD_ENOMEM, "class table allocation failed");
+    HIP_OR_FAIL(hipMemcpyAsync(g->ctab, table.data(), table.size() * sizeof(ClassEntry),
+                               hipMemcpyHostToDevice, st));
+
+    // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt
+    const int ns = (int)g->sources.size(), np = (int)g->probes.size();
+    const int64_t ms = d.max_steps;
+    if (ns) {
+        std::vector<float> js((size_t)ns * ms);
+        for (int s = 0; s < ns; ++s)
+            for (int64_t t = 0; t < ms; ++t)
+                js[(size_t)s * ms + t] =
+                    (float)(kC0 * g->dt * kEta0 * waveform(g->sources[s], (t + 0.5) * g->dt));
+        g->src_node = (int32_t*)dev_alloc(g, ns * 4);
+        g->src_j = (float*)dev_alloc(g, js.size() * 4);
+        if (!g->src_node || !g->src_j) return fail(FDTD_ENOMEM, "source table allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->src_node, src_node.data(), ns * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->src_j, js.data(), js.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipStreamSynchronize(st));
+    }
+    if (np) {
+        g->prb_node = (int32_t*)dev_alloc(g, np * 4);
+        g->prb_series = (float*)dev_alloc(g, (size_t)np * ms * 4);
+        if (!g->prb_node || !g->prb_series) return fail(FDTD_ENOMEM, "probe buffer allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->prb_node, prb_node.data(), np * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(launch_fill_zero(g->prb_series, (int64_t)np * ms, st));
+    }
+    const int nf = (int)g->freqs.size();
+    if (np && nf) {
+        g->dft_f = (double*)dev_alloc(g, nf * 8);
+        g->dft_re = (double*)dev_alloc(g, (size_t)np * nf * 8);
+        g->dft_im = (double*)dev_alloc(g, (size_t)np * nf * 8);
+        if (!g->dft_f || !g->dft_re || !g->dft_im) return fail(FDTD_ENOMEM, "DFT buffer allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->dft_f, g->freqs.data(), nf * 8, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(launch_fill_zero((float*)g->dft_re, (int64_t)np * nf * 2, st));
+        HIP_OR_FAIL(launch_fill_zero((float*)g->dft_im, (int64_t)np * nf * 2, st));
+    }
+
+    // board descriptor and tile list
+    BoardDev& b = g->board_host;
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 9; ++c) b.f[p][c] = g->f[p][c];
+    for (int c = 0; c < 3; ++c) {
+        b.d[c] = g->dd[c];
+        b.coef[c] = g->coef[c];
+    }
+    b.cls = g->cls;
+    b.ctab = g->ctab;
+    b.src_node = g->src_node;
+    b.src_j = g->src_j;
+    b.prb_node = g->prb_node;
+    b.prb_series = g->prb_series;
+    b.step = g->step_dev;
+    b.bad = g->bad_dev;
+    b.nx = nx;
+    b.ny = ny;
+    b.nz = nz;
+    b.nsrc = ns;
+    b.nprb = np;
+    for (int c = 0; c < 6; ++c) b.pml[c] = d.npml[c];
+    b.max_steps = ms;
+    b.crd_x = (float)(kC0 * g->dt / d.dx);
+    b.crd_y = (float)(kC0 * g->dt / d.dy);
+    b.crd_z = (float)(kC0 * g->dt / d.dz);
+    b.tiles_x = (nx + 1 + g->tile_x - 2) / (g->tile_x - 1);
+    b.tiles_y = (ny + 1 + g->tile_y - 2) / (g->tile_y - 1);
+    g->board_dev = (BoardDev*)dev_alloc(g, sizeof(BoardDev));
+    if (!g->board_dev) return fail(FDTD_ENOMEM, "descriptor allocation failed");
+    HIP_OR_FAIL(hipMemcpyAsync(g->board_dev, &b, sizeof(BoardDev), hipMemcpyHostToDevice, st));
+    g->ntiles = b.tiles_x * b.tiles_y;
+    std::vector<TileRef> tl((size_t)g->ntiles);
+    for (int ty = 0; ty < b.tiles_y; ++ty)
+        for (int tx = 0; tx < b.tiles_x; ++tx) tl[(size_t)ty * b.tiles_x + tx] = TileRef{0, tx, ty};
+    g->tiles_dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
+    if (!g->tiles_dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
+    HIP_OR_FAIL(hipMemcpyAsync(g->tiles_dev, tl.data(), tl.size() * sizeof(TileRef),
+                               hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    g->step_bytes = count_step_bytes(g);
+    g->finalized = true;
+    return FDTD_OK;
+}
+
+int record_event(fdtd_grid* g)
+{
+    if (g->ev_used == g->ev_pool.size()) {
+        hipEvent_t e;
+        HIP_OR_FAIL(hipEventCreate(&e));
+        g->ev_pool.push_back(e);
+    }
+    HIP_OR_FAIL(hipEventRecord(g->ev_pool[g->ev_used++], g->stream));
+    return FDTD_OK;
+}
+
+int check_bad(fdtd_grid* g)
+{
+    if (!g->finalized) return FDTD_OK;
+    int32_t bad = 0;
+    HIP_OR_FAIL(copy_sync(g, &bad, g->bad_dev, 4, hipMemcpyDeviceToHost));
+    if (bad) return fail(FDTD_EUNSTABLE, "non-finite field value (unstable run or bad input)");
+    return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdtd_last_error(void) { return g_err.c_str(); }
+
+int fdtd_tile_shapes(int* xy, int cap)
+{
+    const int n = num_shapes();
+    for (int s = 0; s < n && s < cap; ++s) shape_at(s, &xy[2 * s], &xy[2 * s + 1]);
+    return n;
+}
+
+int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
+{
+    if (!desc || !out) return fail(FDTD_EINVAL, "null argument");
+    *out = nullptr;
+    fdtd_grid_desc d = *desc;
+    if (d.nx < 2 || d.ny < 2 || d.nz < 2) return fail(FDTD_EINVAL, "nx, ny, nz must be >= 2");
+    const int64_t nodes = (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
+    if (nodes >= (int64_t(1) << 31)) return fail(FDTD_EINVAL, "node count must be below 2^31");
+    if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !std::isfinite(d.dx) ||
+        !std::isfinite(d.dy) || !std::isfinite(d.dz))
+        return fail(FDTD_EINVAL, "cell sizes must be positive and finite");
+    if (d.courant == 0.0) d.courant = 0.99;
+    if (!(d.courant > 0.0 && d.courant < 1.0)) return fail(FDTD_EINVAL, "courant must be in (0, 1)");
+    if (d.pml_m == 0.0) d.pml_m = 3.0;
+    if (d.pml_R == 0.0) d.pml_R = 1e-6;
+    if (d.pml_kappa_max == 0.0) d.pml_kappa_max = 1.0;
+    if (!(d.pml_m > 0.0) || !(d.pml_R > 0.0 && d.pml_R <= 1.0) || !(d.pml_kappa_max >= 1.0))
+        return fail(FDTD_EINVAL, "PML parameters out of range");
+    const int ncell[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (d.npml[2 * a] < 0 || d.npml[2 * a + 1] < 0)
+            return fail(FDTD_EINVAL, "PML depths must be >= 0");
+        if (d.npml[2 * a] + d.npml[2 * a + 1] > ncell[a])
+            return fail(FDTD_EINVAL, "opposite PML layers overlap on axis %d", a);
+    }
+    if (d.max_steps < 1) return fail(FDTD_EINVAL, "max_steps must be >= 1");
+    if ((d.dev_alloc == nullptr) != (d.dev_free == nullptr))
+        return fail(FDTD_EINVAL, "dev_alloc and dev_free must be given together");
+    // Eq. 7 with the free-space speed (the fastest medium on the grid)
+    const double cfl = 1.0 / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) +
+                                              1.0 / (d.dz * d.dz)));
+    double dt = d.dt;
+    if (dt == 0.0) dt = d.courant * cfl;
+    if (!(dt > 0.0) || !(dt < cfl)) return fail(FDTD_EINVAL, "dt %.6g is not below the CFL limit %.6g", dt, cfl);
+
+    fdtd_grid* g = new (std::nothrow) fdtd_grid();
+    if (!g) return fail(FDTD_ENOMEM, "host allocation failed");
+    g->d = d;
+    g->dt = dt;
+    g->nodes = nodes;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(FDTD_EDEVICE, "no HIP device");
+    }
+    if (d.hip_stream) {
+        g->stream = (hipStream_t)d.hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete g;
+            return fail(FDTD_EDEVICE, "hipStreamCreate failed");
+        }
+        g->own_stream = true;
+    }
+    auto bail = [&](int code, const char* msg) {
+        std::string m = msg;
+        fdtd_destroy_grid(g);
+        return fail(code, "%s", m.c_str());
+    };
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 9; ++c)
+            if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)nodes * 4)))
+                return bail(FDTD_ENOMEM, "field allocation failed");
+    for (int c = 0; c < 3; ++c)
+        if (!(g->dd[c] = (float*)dev_alloc(g, (size_t)nodes * 4)))
+            return bail(FDTD_ENOMEM, "field allocation failed");
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 9; ++c)
+            if (launch_fill_zero(g->f[p][c], nodes, g->stream) != hipSuccess)
+                return bail(FDTD_EDEVICE, "zero fill failed");
+    for (int c = 0; c < 3; ++c)
+        if (launch_fill_zero(g->dd[c], nodes, g->stream) != hipSuccess)
+            return bail(FDTD_EDEVICE, "zero fill failed");
+    for (int a = 0; a < 3; ++a) {
+        std::vector<float> t = coef_table(d, a, dt);
+        if (!(g->coef[a] = (float*)dev_alloc(g, t.size() * 4)))
+            return bail(FDTD_ENOMEM, "coefficient allocation failed");
+        if (hipMemcpyAsync(g->coef[a], t.data(), t.size() * 4, hipMemcpyHostToDevice, g->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(g->stream) != hipSuccess)
+            return bail(FDTD_EDEVICE, "coefficient upload failed");
+    }
+    g->step_dev = (int64_t*)dev_alloc(g, 8);
+    g->bad_dev = (int32_t*)dev_alloc(g, 4);
+    if (!g->step_dev || !g->bad_dev) return bail(FDTD_ENOMEM, "counter allocation failed");
+    if (launch_fill_zero((float*)g->step_dev, 2, g->stream) != hipSuccess ||
+        launch_fill_zero((float*)g->bad_dev, 1, g->stream) != hipSuccess ||
+        hipStreamSynchronize(g->stream) != hipSuccess)
+        return bail(FDTD_EDEVICE, "counter init failed");
+    *out = g;
+    return FDTD_OK;
+}
+
+int fdtd_set_materials(fdtd_grid* g, const float* eps_r_cell, const uint8_t* pec_edge_mask)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "materials are fixed after the first step");
+    if (!eps_r_cell) return fail(FDTD_EINVAL, "eps_r_cell is null");
+    const size_t ncell = (size_t)g->d.nx * g->d.ny * g->d.nz;
+    for (size_t t = 0; t < ncell; ++t)
+        if (!(eps_r_cell[t] >= 1.0f) || !std::isfinite(eps_r_cell[t]))
+            return fail(FDTD_EINVAL, "eps_r_cell[%zu] = %g is not finite and >= 1", t,
+                        (double)eps_r_cell[t]);
+    g->eps.assign(eps_r_cell, eps_r_cell + ncell);
+    if (pec_edge_mask)
+        g->pec.assign(pec_edge_mask, pec_edge_mask + g->nodes);
+    else
+        g->pec.assign((size_t)g->nodes, 0);
+    g->have_materials = true;
+    return FDTD_OK;
+}
+
+int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0, double t0,
+                    double sigma, int* id)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "sources are fixed after the first step");
+    if (i < 1 || i >= g->d.nx || j < 1 || j >= g->d.ny || k < 0 || k >= g->d.nz)
+        return fail(FDTD_EINVAL, "source (%d,%d,%d) is not an interior Ez edge", i, j, k);
+    if (waveform != FDTD_WAVE_GAUSS && waveform != FDTD_WAVE_DGAUSS)
+        return fail(FDTD_EINVAL, "unknown waveform %d", waveform);
+    if (!(sigma > 0) || !std::isfinite(J0) || !std::isfinite(t0) || !std::isfinite(sigma))
+        return fail(FDTD_EINVAL, "source parameters must be finite with sigma > 0");
+    if (g->have_materials && (g->pec[node_index(g, i, j, k)] & 4))
+        return fail(FDTD_EINVAL, "source at (%d,%d,%d) sits on a PEC edge", i, j, k);
+    g->sources.push_back(SourceH{i, j, k, waveform, J0, t0, sigma});
+    if (id) *id = (int)g->sources.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_add_probe(fdtd_grid* g, int i, int j, int k, int* id)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "probes are fixed after the first step");
+    if (i < 0 || i > g->d.nx || j < 0 || j > g->d.ny || k < 0 || k >= g->d.nz)
+        return fail(FDTD_EINVAL, "probe (%d,%d,%d) is outside the grid", i, j, k);
+    g->probes.push_back({i, j, k});
+    if (id) *id = (int)g->probes.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "DFT frequencies are fixed after the first step");
+    if (!f_hz || nf < 1 || nf > 4096) return fail(FDTD_EINVAL, "need 1 <= nf <= 4096 frequencies");
+    for (int q = 0; q < nf; ++q)
+        if (!(f_hz[q] >= 0.0) || !std::isfinite(f_hz[q]))
+            return fail(FDTD_EINVAL, "frequency %d is negative or not finite", q);
+    g->freqs.assign(f_hz, f_hz + nf);
+    return FDTD_OK;
+}
+
+int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "the tile shape is fixed after the first step");
+    const int n = num_shapes();
+    for (int s = 0; s < n; ++s) {
+        int tx, ty;
+        shape_at(s, &tx, &ty);
+        if (tx == tile_x && ty == tile_y) {
+            g->tile_x = tx;
+            g->tile_y = ty;
+            return FDTD_OK;
+        }
+    }
+    return fail(FDTD_EINVAL, "unsupported tile shape %dx%d", tile_x, tile_y);
+}
+
+int fdtd_step_n(fdtd_grid* g, int64_t n)
+{
+    if (int e = check_grid(g)) return e;
+    if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+    if (g->step + n > g->d.max_steps)
+        return fail(FDTD_ESTATE, "%lld steps would exceed max_steps %lld",
+                    (long long)(g->step + n), (long long)g->d.max_steps);
+    if (int e = finalize(g)) return e;
+    if (n == 0) return FDTD_OK;
+    for (int64_t s = 0; s < n; ++s) {
+        if (g->timing)
+            if (int e = record_event(g)) return e;
+        HIP_OR_FAIL(launch_field_step(g->tile_x, g->tile_y, g->board_dev, g->tiles_dev, g->ntiles,
+                                      (int)s, g->wide, g->stream));
+        if (g->timing) {
+            if (int e = record_event(g)) return e;
+            ++g->timed_launches;
+        }
+    }
+    // advance the device step counter by n (one tiny launch per call)
+    HIP_OR_FAIL(launch_advance_one(g->step_dev, n, g->stream));
+    if (g->dft_f)
+        HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
+                               (int)g->probes.size(), g->dt, g->step, g->step + n, g->dft_re,
+                               g->dft_im, g->stream));
+    g->step += n;
+    return FDTD_OK;
+}
+
+int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
+{
+    (void)gs;
+    (void)ng;
+    (void)n;
+    return fail(FDTD_EINVAL, "fdtd_step_many is not available yet");
+}
+
+int fdtd_synchronize(fdtd_grid* g)
+{
+    if (int e = check_grid(g)) return e;
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    return check_bad(g);
+}
+
+int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n)
+{
+    if (int e = check_grid(g)) return e;
+    if (id < 0 || id >= (int)g->probes.size()) return fail(FDTD_EINVAL, "no probe %d", id);
+    if (n < 0 || n > g->step || (!out && n > 0)) return fail(FDTD_EINVAL, "bad sample count %lld", (long long)n);
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    if (n > 0)
+        HIP_OR_FAIL(copy_sync(g, out, g->prb_series + (size_t)id * g->d.max_steps, (size_t)n * 4,
+                              hipMemcpyDeviceToHost));
+    return check_bad(g);
+}
+
+int fdtd_get_dft(fdtd_grid* g, int id, double* re, double* im)
+{
+    if (int e = check_grid(g)) return e;
+    if (id < 0 || id >= (int)g->probes.size()) return fail(FDTD_EINVAL, "no probe %d", id);
+    if (g->freqs.empty()) return fail(FDTD_ESTATE, "no DFT frequencies were set");
+    if (!re || !im) return fail(FDTD_EINVAL, "null output");
+    const int nf = (int)g->freqs.size();
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    if (!g->finalized) {
+        std::fill(re, re + nf, 0.0);
+        std::fill(im, im + nf, 0.0);
+        return FDTD_OK;
+    }
+    HIP_OR_FAIL(copy_sync(g, re, g->dft_re + (size_t)id * nf, nf * 8, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(copy_sync(g, im, g->dft_im + (size_t)id * nf, nf * 8, hipMemcpyDeviceToHost));
+    return check_bad(g);
+}
+
+int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im)
+{
+    if (int e = check_grid(g)) return e;
+    if (id < 0 || id >= (int)g->probes.size()) return fail(FDTD_EINVAL, "no probe %d", id);
+    if (n_fft < 2 || (n_fft & (n_fft - 1)) || n_fft > (1 << 26) || n_fft < g->step)
+        return fail(FDTD_EINVAL, "n_fft %d must be a power of two >= the step count %lld", n_fft,
+                    (long long)g->step);
+    if (!re || !im) return fail(FDTD_EINVAL, "null output");
+    if (int e = finalize(g)) return e;
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    double2* a = (double2*)temp_alloc(g, (size_t)n_fft * sizeof(double2));
+    double2* b = (double2*)temp_alloc(g, (size_t)n_fft * sizeof(double2));
+    if (!a || !b) {
+        temp_free(g, a);
+        temp_free(g, b);
+        return fail(FDTD_ENOMEM, "FFT scratch allocation failed");
+    }
+    double2* res = nullptr;
+    hipError_t e = launch_fft(g->prb_series + (size_t)id * g->d.max_steps, g->step, n_fft, a, b,
+                              &res, g->stream);
+    std::vector<double2> h((size_t)n_fft / 2 + 1);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess)
+        e = copy_sync(g, h.data(), res, h.size() * sizeof(double2), hipMemcpyDeviceToHost);
+    temp_free(g, a);
+    temp_free(g, b);
+    if (e != hipSuccess) return fail(FDTD_EDEVICE, "probe FFT failed: %s", hipGetErrorString(e));
+    for (size_t k = 0; k < h.size(); ++k) {
+        re[k] = h[k].x;
+        im[k] = h[k].y;
+    }
+    return check_bad(g);
+}
+
+static double field_scale(int comp)
+{
+    switch (comp) {
+        case FDTD_HX: case FDTD_HY: case FDTD_HZ: return 1.0 / kEta0;  // Hs = eta0 H
+        case FDTD_DX: case FDTD_DY: case FDTD_DZ: return kEps0;        // Ds = D / eps0
+        case FDTD_BX: case FDTD_BY: case FDTD_BZ: return 1.0 / kC0;    // Bs = c0 B
+        default: return 1.0;
+    }
+}
+
+static float* comp_ptr(fdtd_grid* g, int comp)
+{
+    const int par = (int)(g->step & 1);
+    if (comp <= FDTD_HZ) return g->f[par][comp];
+    if (comp <= FDTD_DZ) return g->dd[comp - FDTD_DX];
+    return g->f[par][6 + comp - FDTD_BX];
+}
+
+int fdtd_get_field(fdtd_grid* g, int comp, float* out)
+{
+    if (int e = check_grid(g)) return e;
+    if (comp < 0 || comp > FDTD_BZ || !out) return fail(FDTD_EINVAL, "bad component or output");
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    std::vector<float> h((size_t)g->nodes);
+    HIP_OR_FAIL(copy_sync(g, h.data(), comp_ptr(g, comp), h.size() * 4, hipMemcpyDeviceToHost));
+    const double s = field_scale(comp);
+    for (size_t t = 0; t < h.size(); ++t) out[t] = (float)((double)h[t] * s);
+    return FDTD_OK;
+}
+
+int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
+{
+    if (int e = check_grid(g)) return e;
+    if (comp < 0 || comp > FDTD_BZ || !in) return fail(FDTD_EINVAL, "bad component or input");
+    const fdtd_grid_desc& d = g->d;
+    const double s = 1.0 / field_scale(comp);
+    std::vector<float> h((size_t)g->nodes);
+    // auxiliaries exist only where their PML predicate holds
+    auto in_pml = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
+    const int axis = comp >= FDTD_DX ? (comp - FDTD_DX) % 3 : -1;
+    for (int k = 0; k <= d.nz; ++k)
+        for (int j = 0; j <= d.ny; ++j)
+            for (int i = 0; i <= d.nx; ++i) {
+                const int64_t n = node_index(g, i, j, k);
+                bool keep = true;
+                if (axis >= 0) {
+                    const bool px = in_pml(i, d.nx, d.npml[0], d.npml[1]);
+                    const bool py = in_pml(j, d.ny, d.npml[2], d.npml[3]);
+                    const bool pz = in_pml(k, d.nz, d.npml[4], d.npml[5]);
+                    keep = axis == 0 ? (px || py) : axis == 1 ? (py || pz) : (pz || px);
+                }
+                h[(size_t)n] = keep ? (float)((double)in[n] * s) : 0.0f;
+            }
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    HIP_OR_FAIL(copy_sync(g, comp_ptr(g, comp), h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    return FDTD_OK;
+}
+
+int64_t fdtd_state_bytes(fdtd_grid* g)
+{
+    if (!g) return fail(FDTD_EINVAL, "null grid handle");
+    const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();
+    return 64 + 12 * g->nodes * 4 + np * g->d.max_steps * 4 + (np && nf ? np * nf * 16 : 0);
+}
+
+int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes)
+{
+    if (int e = check_grid(g)) return e;
+    if (!host_buf || bytes < fdtd_state_bytes(g)) return fail(FDTD_EINVAL, "buffer too small");
+    if (int e = finalize(g)) return e;
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    char* p = (char*)host_buf;
+    int64_t hdr[8] = {0x4644544453544154ll, g->d.nx, g->d.ny, g->d.nz, g->step,
+                      (int64_t)g->probes.size(), (int64_t)g->freqs.size(), g->d.max_steps};
+    memcpy(p, hdr, 64);
+    p += 64;
+    for (int c = 0; c < 12; ++c) {
+        HIP_OR_FAIL(copy_sync(g, p, comp_ptr(g, c), g->nodes * 4, hipMemcpyDeviceToHost));
+        p += g->nodes * 4;
+    }
+    const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();
+    if (np) {
+        HIP_OR_FAIL(copy_sync(g, p, g->prb_series, np * g->d.max_steps * 4, hipMemcpyDeviceToHost));
+        p += np * g->d.max_steps * 4;
+    }
+    if (np && nf) {
+        HIP_OR_FAIL(copy_sync(g, p, g->dft_re, np * nf * 8, hipMemcpyDeviceToHost));
+        p += np * nf * 8;
+        HIP_OR_FAIL(copy_sync(g, p, g->dft_im, np * nf * 8, hipMemcpyDeviceToHost));
+    }
+    return FDTD_OK;
+}
+
+int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes)
+{
+    if (int e = check_grid(g)) return e;
+    if (!host_buf || bytes < fdtd_state_bytes(g)) return fail(FDTD_EINVAL, "buffer too small");
+    if (int e = finalize(g)) return e;
+    const char* p = (const char*)host_buf;
+    int64_t hdr[8];
+    memcpy(hdr, p, 64);
+    p += 64;
+    if (hdr[0] != 0x4644544453544154ll || hdr[1] != g->d.nx || hdr[2] != g->d.ny ||
+        hdr[3] != g->d.nz || hdr[5] != (int64_t)g->probes.size() ||
+        hdr[6] != (int64_t)g->freqs.size() || hdr[7] != g->d.max_steps)
+        return fail(FDTD_EINVAL, "state image does not match this grid");
+    if (hdr[4] < 0 || hdr[4] > g->d.max_steps) return fail(FDTD_EINVAL, "bad step in state image");
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    g->step = hdr[4];
+    for (int c = 0; c < 12; ++c) {
+        HIP_OR_FAIL(copy_sync(g, comp_ptr(g, c), p, g->nodes * 4, hipMemcpyHostToDevice));
+        p += g->nodes * 4;
+    }
+    const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();
+    if (np) {
+        HIP_OR_FAIL(copy_sync(g, g->prb_series, p, np * g->d.max_steps * 4, hipMemcpyHostToDevice));
+        p += np * g->d.max_steps * 4;
+    }
+    if (np && nf) {
+        HIP_OR_FAIL(copy_sync(g, g->dft_re, p, np * nf * 8, hipMemcpyHostToDevice));
+        p += np * nf * 8;
+        HIP_OR_FAIL(copy_sync(g, g->dft_im, p, np * nf * 8, hipMemcpyHostToDevice));
+    }
+    HIP_OR_FAIL(copy_sync(g, g->step_dev, &g->step, 8, hipMemcpyHostToDevice));
+    const int32_t zero = 0;
+    HIP_OR_FAIL(copy_sync(g, g->bad_dev, &zero, 4, hipMemcpyHostToDevice));
+    return FDTD_OK;
+}
+
+int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
+{
+    if (int e = check_grid(g)) return e;
+    if (!out) return fail(FDTD_EINVAL, "null output");
+    out->dt = g->dt;
+    out->step = g->step;
+    out->max_steps = g->d.max_steps;
+    out->cells = (int64_t)g->d.nx * g->d.ny * g->d.nz;
+    out->nodes = g->nodes;
+    out->step_bytes = g->finalized ? g->step_bytes : count_step_bytes(g);
+    out->device_bytes = g->device_bytes;
+    out->n_sources = (int32_t)g->sources.size();
+    out->n_probes = (int32_t)g->probes.size();
+    out->n_freqs = (int32_t)g->freqs.size();
+    out->n_classes = g->n_classes;
+    out->tile_x = g->tile_x;
+    out->tile_y = g->tile_y;
+    return FDTD_OK;
+}
+
+int fdtd_set_timing(fdtd_grid* g, int on)
+{
+    if (int e = check_grid(g)) return e;
+    g->timing = on != 0;
+    return FDTD_OK;
+}
+
+int fdtd_get_timing(fdtd_grid* g, double* ms, int64_t* launches)
+{
+    if (int e = check_grid(g)) return e;
+    if (!ms || !launches) return fail(FDTD_EINVAL, "null output");
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    double total = 0.0;
+    for (size_t t = 0; t + 1 < g->ev_used; t += 2) {
+        float v = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&v, g->ev_pool[t], g->ev_pool[t + 1]));
+        total += v;
+    }
+    *ms = total;
+    *launches = g->timed_launches;
+    g->ev_used = 0;
+    g->timed_launches = 0;
+    return FDTD_OK;
+}
+
+int fdtd_destroy_grid(fdtd_grid* g)
+{
+    if (!g) return FDTD_OK;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    dev_free_all(g);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+    return FDTD_OK;
+}
+
+}  // extern "C"

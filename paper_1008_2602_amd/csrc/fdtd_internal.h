@@ -1,0 +1,66 @@
+// Internal layout shared by the libfdtd host code and its gfx950 kernels.
+//
+// Units inside the library.  E keeps SI units (V/m).  The other state is scaled
+// to V/m so that every update coefficient is O(1) in FP32:
+//   Hs = eta0 H,  Bs = c0 B,  Ds = D / eps0.
+// With crd_w = c0 dt / delta_w, the Eq. 4 two-step update (D then E; B then H
+// with the same stretch factors, Eq. 1) becomes, for a component u with cyclic
+// partners (v, w) and q = sigma dt / eps0, ph = kappa + q/2, rp = 1/ph,
+// ca = (kappa - q/2)/(kappa + q/2), cam1 = ca - 1 = -q/(kappa + q/2):
+//   dDs   = cam1_v Ds + rp_v (curl_u(Hs) - Js)          Ds += dDs
+//   E_u'  = ca_w E_u + rp_w inv_eps_r (ph_u dDs + q_u Ds)
+//   dBs   = cam1_v Bs - rp_v curl_u(E)                  Bs += dBs
+//   Hs_u' = ca_w Hs_u + rp_w (ph_u dBs + q_u Bs)
+// where curl terms are differences times crd and Js = c0 dt eta0 J.  The form
+// p+ dD + (p+ - p-) D^n replaces p+ D^{n+1} - p- D^n: algebraically equal, and
+// outside the u-axis PML (q_u = 0) it never subtracts two large numbers.
+#pragma once
+#include <stdint.h>
+
+namespace fdtd {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+constexpr double kEta0 = kMu0 * kC0;
+
+// per-axis coefficient table: 5 quantities x {node, half node} x (n+1) entries
+enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kNumCoef = 5 };
+
+// class flags (per node): which E components are stepped, and source/probe marks
+enum : uint32_t { kUpdEx = 1u, kUpdEy = 2u, kUpdEz = 4u, kSrcEz = 8u, kPrbEz = 16u };
+
+struct ClassEntry {
+    float inv_x, inv_y, inv_z;  // 1/eps_r of the Ex, Ey, Ez edges owned by the node
+    uint32_t flags;
+};
+
+// Everything one field launch needs about one board.  Lives in device memory
+// (an array of these for batched launches).
+struct BoardDev {
+    // state: [parity][0..8] = Ex Ey Ez Hx Hy Hz Bx By Bz ; D in place
+    float* f[2][9];
+    float* d[3];
+    const void* cls;             // uint8_t or uint16_t per node
+    const ClassEntry* ctab;
+    const float* coef[3];        // per axis: [kind][node/half][n+1]
+    const int32_t* src_node;     // node index of each source's Ez edge
+    const float* src_j;          // [nsrc][max_steps] Js samples
+    const int32_t* prb_node;
+    float* prb_series;           // [nprb][max_steps]
+    int64_t* step;               // device step counter (completed steps)
+    int32_t* bad;                // watchdog flag
+    int32_t nx, ny, nz;
+    int32_t nsrc, nprb;
+    int32_t pml[6];
+    int64_t max_steps;
+    float crd_x, crd_y, crd_z;
+    int32_t tiles_x, tiles_y;
+};
+
+struct TileRef {
+    int32_t board;
+    int32_t tx, ty;
+};
+
+}  // namespace fdtd

@@ -23,8 +23,11 @@ def live_masks(board):
 
 
 def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
+    """||a - b|| / ||b|| (real or complex)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    a = a.astype(np.complex128) if np.iscomplexobj(a) or np.iscomplexobj(b) else a.astype(np.float64)
+    b = b.astype(a.dtype)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
 

@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances: probe series relative L2 <= 1e-4 per probe and identical FFT peak
+bins (within one bin) for full runs; whole-array relative L2 <= 2e-5 for short
+runs from arbitrary states (FP32 arithmetic over a few steps); batched, resumed
+and re-tiled runs are bitwise equal to the plain run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import boardgen
+from _util import live_masks, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("ex", "ey", "ez", "hx", "hy", "hz", "ddx", "ddy", "ddz", "bbx", "bby", "bbz")
+
+
+def announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1008_2602_amd import fdtd
+    return fdtd
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_mod):
+    return oracle_mod
+
+
+def aux_masks(board):
+    """Where the library keeps D/B: the component's own or cyclic-next axis is in
+    a PML slab (elsewhere those auxiliaries never influence E or H)."""
+    nx, ny, nz = board.nx, board.ny, board.nz
+    p = board.npml
+    px = np.array([(i < p[0]) or (p[1] > 0 and i >= nx - p[1]) for i in range(nx + 1)])
+    py = np.array([(j < p[2]) or (p[3] > 0 and j >= ny - p[3]) for j in range(ny + 1)])
+    pz = np.array([(k < p[4]) or (p[5] > 0 and k >= nz - p[5]) for k in range(nz + 1)])
+    X = px[None, None, :]
+    Y = py[None, :, None]
+    Z = pz[:, None, None]
+    shp = (nz + 1, ny + 1, nx + 1)
+    return {"x": np.broadcast_to(X | Y, shp), "y": np.broadcast_to(Y | Z, shp),
+            "z": np.broadcast_to(Z | X, shp)}
+
+
+def gpu_fields(F, g, board):
+    shp = (board.nz + 1, board.ny + 1, board.nx + 1)
+    return {n: F.fdtd_get_field(g, c, shp).astype(np.float64) for c, n in enumerate(FIELDS)}
+
+
+def gpu_run(F, board, steps=None, tile=None, init=None, chunks=None):
+    steps = board.steps if steps is None else steps
+    g, ids = F.grid_from_board(board, max_steps=max(steps, 1), tile=tile)
+    try:
+        if init is not None:
+            for c, n in enumerate(FIELDS):
+                F.fdtd_set_field(g, c, init[n].astype(np.float32))
+        for n in (chunks or [steps]):
+            F.fdtd_step_n(g, n)
+        F.fdtd_synchronize(g)
+        probes = np.stack([F.fdtd_get_probe(g, p, steps) for p in ids]) if ids else None
+        fields = gpu_fields(F, g, board)
+        dft = (np.stack([F.fdtd_get_dft(g, p) for p in ids])
+               if board.dft_freqs is not None and ids else None)
+        info = F.fdtd_get_info(g)
+    finally:
+        F.fdtd_destroy_grid(g)
+    return probes, fields, dft, info
+
+
+def random_state(orc, board, seed, scale_h=376.73):
+    rng = np.random.default_rng(seed)
+    st = orc.new_state(board)
+    m = live_masks(board)
+    am = aux_masks(board)
+    axis = {"ddx": "x", "ddy": "y", "ddz": "z", "bbx": "x", "bby": "y", "bbz": "z"}
+    eps0 = 8.854187817620389e-12
+    mu0 = 4e-7 * np.pi
+    for n in FIELDS:
+        mask = m[n] & am[axis[n]] if n in axis else m[n]
+        v = np.where(mask, rng.standard_normal(st[n].shape), 0.0)
+        if n.startswith("h"):
+            v /= scale_h
+        elif n.startswith("dd"):
+            v *= eps0
+        elif n.startswith("bb"):
+            v *= mu0 / scale_h
+        st[n][...] = v.astype(np.float32).astype(np.float64)   # both sides see FP32 inputs
+    return st
+
+
+def compare_fields(ref, got, board, tol):
+    am = aux_masks(board)
+    axis = {"ddx": "x", "ddy": "y", "ddz": "z", "bbx": "x", "bby": "y", "bbz": "z"}
+    for n in FIELDS:
+        r = ref[n]
+        if n in axis:
+            r = np.where(am[axis[n]], r, 0.0)
+        if np.abs(r).max() == 0:
+            assert np.abs(got[n]).max() == 0, n
+            continue
+        e = rel_l2(got[n], r)
+        assert e <= tol, (n, e)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tiny_boards_from_zero(F, orc, seed):
+    b = boardgen.random_tiny(seed, steps=60)
+    dt = orc.time_step(b)
+    for s in b.sources:
+        s.t0, s.sigma = 20 * dt, 5 * dt
+    announce(f"tiny board seed={seed} {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
+    ref = orc.run(b)
+    probes, fields, dft, _ = gpu_run(F, b)
+    for p in range(len(b.probes)):
+        if np.abs(ref.probes[p]).max() > 0:
+            assert rel_l2(probes[p], ref.probes[p]) <= 1e-4, p
+    compare_fields(ref.state, fields, b, 2e-5)
+    assert rel_l2(dft, ref.dft) <= 1e-4
+
+
+@pytest.mark.parametrize("shape,npml", [((9, 11, 7), (3, 2, 1, 3, 2, 2)),
+                                        ((70, 13, 9), (4, 4, 2, 2, 3, 3)),
+                                        ((13, 17, 30), (0, 3, 2, 0, 5, 4)),
+                                        ((2, 2, 2), (0, 0, 0, 0, 0, 0)),
+                                        ((131, 9, 4), (1, 1, 1, 1, 1, 1))])
+def test_random_state_few_steps(F, orc, shape, npml):
+    nx, ny, nz = shape
+    eps, mask = boardgen.air(nx, ny, nz)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    eps[:] = rng.choice([1.0, 2.2, 4.4], size=eps.shape).astype(np.float32)
+    if nz >= 4:
+        boardgen.pec_sheet(mask, nz // 2, 0, nx // 2, 1, ny - 1)
+    b = boardgen.Board(f"rand{nx}x{ny}x{nz}", nx, ny, nz, 0.7e-3, 0.9e-3, 0.4e-3, eps, mask,
+                       npml=npml, steps=4)
+    st = random_state(orc, b, seed=nx + ny + nz)
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"random state {shape} npml={npml}")
+    ref = orc.run(b, state=st)
+    _, fields, _, _ = gpu_run(F, b, init=init)
+    compare_fields(ref.state, fields, b, 2e-5)
+
+
+def test_config1_full_run_parity(F, orc):
+    b = boardgen.config1()
+    announce(f"config1 full {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
+    ref = orc.run(b, threads=16)
+    probes, _, _, _ = gpu_run(F, b)
+    n_fft = orc.default_nfft(b.steps)
+    f = orc.bin_freqs(n_fft, ref.dt)
+    for p in range(len(b.probes)):
+        e = rel_l2(probes[p], ref.probes[p])
+        assert e <= 1e-4, (p, e)
+        Xr = np.abs(orc.probe_fft(ref.probes[p], n_fft))
+        Xg = np.abs(orc.probe_fft(probes[p].astype(np.float64), n_fft))
+        pr = orc.find_peaks(Xr, f, f_min=0.5e9)
+        pg = orc.find_peaks(Xg, f, f_min=0.5e9)
+        assert len(pr) == len(pg)
+        assert np.all(np.abs(pr - pg) <= 1.0 / (b.steps * ref.dt))
+
+
+def test_tile_shapes_bitwise(F):
+    b = boardgen.random_tiny(7, nx=150, ny=37, nz=12, npml=3, steps=30)
+    for s in b.sources:
+        s.t0, s.sigma = 5e-12, 2e-12
+    outs = []
+    for tile in F.fdtd_tile_shapes():
+        announce(f"tile {tile}")
+        probes, fields, _, _ = gpu_run(F, b, tile=tile)
+        outs.append((probes, fields))
+    for probes, fields in outs[1:]:
+        assert np.array_equal(probes, outs[0][0])
+        for n in FIELDS:
+            assert np.array_equal(fields[n], outs[0][1][n]), n
+
+
+def test_chunked_equals_single_call(F):
+    b = boardgen.config1(steps=240)
+    announce("chunked vs single")
+    p1, f1, _, _ = gpu_run(F, b)
+    p2, f2, _, _ = gpu_run(F, b, chunks=[1, 7, 100, 0, 132])
+    assert np.array_equal(p1, p2)
+    for n in FIELDS:
+        assert np.array_equal(f1[n], f2[n]), n
+
+
+def test_checkpoint_resume_bitwise(F):
+    b = boardgen.config1(steps=300)
+    b.dft_freqs = np.linspace(1e9, 8e9, 16)
+    announce("checkpoint/resume")
+    g, ids = F.grid_from_board(b)
+    F.fdtd_step_n(g, 120)
+    image = F.fdtd_save_state(g)
+    F.fdtd_step_n(g, 180)
+    a_probe = F.fdtd_get_probe(g, ids[0], 300)
+    a_dft = F.fdtd_get_dft(g, ids[0])
+    a_ez = F.fdtd_get_field(g, F.FDTD_EZ, (b.nz + 1, b.ny + 1, b.nx + 1))
+    F.fdtd_destroy_grid(g)
+    g2, ids2 = F.grid_from_board(b)
+    F.fdtd_load_state(g2, image)
+    assert F.fdtd_get_info(g2).step == 120
+    F.fdtd_step_n(g2, 180)
+    assert np.array_equal(F.fdtd_get_probe(g2, ids2[0], 300), a_probe)
+    assert np.array_equal(F.fdtd_get_dft(g2, ids2[0]), a_dft)
+    assert np.array_equal(F.fdtd_get_field(g2, F.FDTD_EZ, a_ez.shape), a_ez)
+    F.fdtd_destroy_grid(g2)
+
+
+def test_dft_and_probe_fft(F, orc):
+    b = boardgen.config1(steps=1500)
+    b.dft_freqs = np.linspace(0.5e9, 12e9, 64)
+    announce("dft + probe fft")
+    ref = orc.run(b, threads=16)
+    g, ids = F.grid_from_board(b)
+    F.fdtd_step_n(g, 700)
+    F.fdtd_step_n(g, 800)
+    dft = np.stack([F.fdtd_get_dft(g, p) for p in ids])
+    series = np.stack([F.fdtd_get_probe(g, p, b.steps) for p in ids]).astype(np.float64)
+    n_fft = 2048
+    X = np.stack([F.fdtd_probe_fft(g, p, n_fft) for p in ids])
+    with pytest.raises(F.FdtdError):
+        F.fdtd_probe_fft(g, 0, 1024)      # shorter than the run
+    F.fdtd_destroy_grid(g)
+    for p in range(len(ids)):
+        assert rel_l2(dft[p], ref.dft[p]) <= 1e-4
+        # the device FFT of the device series equals numpy's FFT of the same samples
+        np.testing.assert_allclose(X[p], np.fft.rfft(series[p], n_fft),
+                                   rtol=0, atol=1e-9 * np.abs(X[p]).max())
+        # and the oracle's spectrum of its own series
+        assert rel_l2(X[p], orc.probe_fft(ref.probes[p], n_fft)) <= 1e-4
+        # the running DFT equals the direct sum over the stored samples
+        t = (np.arange(b.steps) + 1) * ref.dt
+        direct = (series[p][None, :] * np.exp(-2j * np.pi * np.outer(b.dft_freqs, t))).sum(1) * ref.dt
+        assert rel_l2(dft[p], direct) <= 1e-12
+
+
+def test_info_and_state_errors(F):
+    b = boardgen.config1(steps=10)
+    g, ids = F.grid_from_board(b)
+    info = F.fdtd_get_info(g)
+    assert info.cells == b.nx * b.ny * b.nz and info.n_probes == 4 and info.n_sources == 1
+    F.fdtd_step_n(g, 10)
+    with pytest.raises(F.FdtdError) as ei:
+        F.fdtd_step_n(g, 1)               # beyond max_steps
+    assert ei.value.code == F.FDTD_ESTATE
+    with pytest.raises(F.FdtdError) as ei:
+        F.fdtd_add_probe(g, 5, 5, 5)      # after the first step
+    assert ei.value.code == F.FDTD_ESTATE
+    info = F.fdtd_get_info(g)
+    assert info.step == 10 and info.step_bytes > 48 * info.nodes
+    F.fdtd_destroy_grid(g)
+
+
+def test_unstable_run_is_reported(F):
+    """A source whose time integral exceeds the FP32 range drives Ez at the source
+    edge to inf; the watchdog reports it at the next synchronising call."""
+    b = boardgen.config1(steps=300)
+    b.sources[0].J0 = 3e38
+    g, ids = F.grid_from_board(b)
+    F.fdtd_step_n(g, 300)
+    with pytest.raises(F.FdtdError) as ei:
+        F.fdtd_synchronize(g)
+    assert ei.value.code == F.FDTD_EUNSTABLE
+    F.fdtd_destroy_grid(g)
