@@ -440,6 +440,7 @@ int finalize(fdtd_grid* g)
     b.nz = nz;
     b.nsrc = ns;
     b.nprb = np;
+    b.nclass = (int32_t)table.size();
     for (int c = 0; c < 6; ++c) b.pml[c] = d.npml[c];
     b.max_steps = ms;
     b.crd_x = (float)(kC0 * g->dt / d.dx);
@@ -555,19 +556,22 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
         fdtd_destroy_grid(g);
         return fail(code, "%s", m.c_str());
     };
+    // every field array carries kGuard zero words past its last node: the kernels
+    // read out-of-range neighbours from there and never write them
+    const int64_t padded = nodes + kGuard;
     for (int p = 0; p < 2; ++p)
         for (int c = 0; c < 9; ++c)
-            if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)nodes * 4)))
+            if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
                 return bail(FDTD_ENOMEM, "field allocation failed");
     for (int c = 0; c < 3; ++c)
-        if (!(g->dd[c] = (float*)dev_alloc(g, (size_t)nodes * 4)))
+        if (!(g->dd[c] = (float*)dev_alloc(g, (size_t)padded * 4)))
             return bail(FDTD_ENOMEM, "field allocation failed");
     for (int p = 0; p < 2; ++p)
         for (int c = 0; c < 9; ++c)
-            if (launch_fill_zero(g->f[p][c], nodes, g->stream) != hipSuccess)
+            if (launch_fill_zero(g->f[p][c], padded, g->stream) != hipSuccess)
                 return bail(FDTD_EDEVICE, "zero fill failed");
     for (int c = 0; c < 3; ++c)
-        if (launch_fill_zero(g->dd[c], nodes, g->stream) != hipSuccess)
+        if (launch_fill_zero(g->dd[c], padded, g->stream) != hipSuccess)
             return bail(FDTD_EDEVICE, "zero fill failed");
     for (int a = 0; a < 3; ++a) {
         std::vector<float> t = coef_table(d, a, dt);

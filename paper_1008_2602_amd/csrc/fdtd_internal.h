@@ -24,6 +24,9 @@ constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
 constexpr double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
 constexpr double kEta0 = kMu0 * kC0;
 
+// zero words allocated past the last node of every field array
+constexpr int64_t kGuard = 64;
+
 // per-axis coefficient table: 5 quantities x {node, half node} x (n+1) entries
 enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kNumCoef = 5 };
 
@@ -52,6 +55,7 @@ struct BoardDev {
     int32_t* bad;                // watchdog flag
     int32_t nx, ny, nz;
     int32_t nsrc, nprb;
+    int32_t nclass;
     int32_t pml[6];
     int64_t max_steps;
     float crd_x, crd_y, crd_z;

@@ -23,12 +23,31 @@
 
 namespace fdtd {
 
-__device__ __forceinline__ float ld_or0(const float* __restrict__ p, int i, int j, int k,
-                                        int nx, int ny, int nz, int sy, int sz)
+// Global-address-space views of the board's buffers: loads and stores through
+// them are global_* instructions (counted in vmcnt only), so LDS barriers never
+// wait on outstanding HBM traffic.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const float cgfloat;
+typedef __attribute__((address_space(4))) const float kfloat;  // uniform, scalar loads
+
+// Branch-free staging load: out-of-range nodes read the guard word (index
+// `guard`, one past the last node, kept at zero) instead of selecting after
+// the load, so the load's latency is not exposed where it is issued.
+__device__ __forceinline__ float ld_or0(cgfloat* __restrict__ p, int i, int j, int k, int nx,
+                                        int ny, int nz, int sy, int sz, int guard)
 {
-    return (i >= 0 && i <= nx && j >= 0 && j <= ny && k >= 0 && k <= nz)
-               ? p[i + j * sy + k * sz]
-               : 0.0f;
+    const bool ok = ((unsigned)i <= (unsigned)nx) & ((unsigned)j <= (unsigned)ny) &
+                    ((unsigned)k <= (unsigned)nz);
+    return p[ok ? i + j * sy + k * sz : guard];
+}
+
+// Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks
+// a contiguous run of the tile list (neighbouring tiles share halos in its L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b & 7, slot = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + slot;
 }
 
 template <int TX, int TY, typename CT>
@@ -42,11 +61,14 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
     __shared__ float sHx[TY][TX];
     __shared__ float sHy[TY][TX];
     __shared__ float sHz[TY][TX];
+    // class table in LDS when the class index is one byte (<= 256 classes)
+    constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
+    __shared__ ClassEntry sTab[kLdsClasses];
 
-    const TileRef t = tiles[blockIdx.x];
+    const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoardDev& B = boards[t.board];
     const int nx = B.nx, ny = B.ny, nz = B.nz;
-    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
+    const int sy = nx + 1, sz = (nx + 1) * (ny + 1), guard = sz * (nz + 1);
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int ox = t.tx * (TX - 1) - 1, oy = t.ty * (TY - 1) - 1;
@@ -55,39 +77,44 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
     const bool own = col_ok && tx > 0 && ty > 0;
     const int64_t step = *B.step + rel;
     const int par = (int)(step & 1);
-    const float* __restrict__ sEx_g = B.f[par][0];
-    const float* __restrict__ sEy_g = B.f[par][1];
-    const float* __restrict__ sEz_g = B.f[par][2];
-    const float* __restrict__ hxo_g = B.f[par][3];
-    const float* __restrict__ hyo_g = B.f[par][4];
-    const float* __restrict__ hzo_g = B.f[par][5];
-    const float* __restrict__ bxo_g = B.f[par][6];
-    const float* __restrict__ byo_g = B.f[par][7];
-    const float* __restrict__ bzo_g = B.f[par][8];
-    float* __restrict__ dEx = B.f[par ^ 1][0];
-    float* __restrict__ dEy = B.f[par ^ 1][1];
-    float* __restrict__ dEz = B.f[par ^ 1][2];
-    float* __restrict__ dHx = B.f[par ^ 1][3];
-    float* __restrict__ dHy = B.f[par ^ 1][4];
-    float* __restrict__ dHz = B.f[par ^ 1][5];
-    float* __restrict__ dBx = B.f[par ^ 1][6];
-    float* __restrict__ dBy = B.f[par ^ 1][7];
-    float* __restrict__ dBz = B.f[par ^ 1][8];
-    float* __restrict__ Dx = B.d[0];
-    float* __restrict__ Dy = B.d[1];
-    float* __restrict__ Dz = B.d[2];
-    const CT* __restrict__ cls = static_cast<const CT*>(B.cls);
+    cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
+    cgfloat* __restrict__ gEy = (cgfloat*)B.f[par][1];
+    cgfloat* __restrict__ gEz = (cgfloat*)B.f[par][2];
+    cgfloat* __restrict__ gHx = (cgfloat*)B.f[par][3];
+    cgfloat* __restrict__ gHy = (cgfloat*)B.f[par][4];
+    cgfloat* __restrict__ gHz = (cgfloat*)B.f[par][5];
+    cgfloat* __restrict__ gBx = (cgfloat*)B.f[par][6];
+    cgfloat* __restrict__ gBy = (cgfloat*)B.f[par][7];
+    cgfloat* __restrict__ gBz = (cgfloat*)B.f[par][8];
+    gfloat* __restrict__ dEx = (gfloat*)B.f[par ^ 1][0];
+    gfloat* __restrict__ dEy = (gfloat*)B.f[par ^ 1][1];
+    gfloat* __restrict__ dEz = (gfloat*)B.f[par ^ 1][2];
+    gfloat* __restrict__ dHx = (gfloat*)B.f[par ^ 1][3];
+    gfloat* __restrict__ dHy = (gfloat*)B.f[par ^ 1][4];
+    gfloat* __restrict__ dHz = (gfloat*)B.f[par ^ 1][5];
+    gfloat* __restrict__ dBx = (gfloat*)B.f[par ^ 1][6];
+    gfloat* __restrict__ dBy = (gfloat*)B.f[par ^ 1][7];
+    gfloat* __restrict__ dBz = (gfloat*)B.f[par ^ 1][8];
+    gfloat* __restrict__ Dx = (gfloat*)B.d[0];
+    gfloat* __restrict__ Dy = (gfloat*)B.d[1];
+    gfloat* __restrict__ Dz = (gfloat*)B.d[2];
+    const __attribute__((address_space(1))) CT* __restrict__ cls =
+        (const __attribute__((address_space(1))) CT*)B.cls;
+    const __attribute__((address_space(1))) ClassEntry* __restrict__ ctab =
+        (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
+    const int pml_zlo = B.pml[4], pml_zhi = B.pml[5];
 
-    // PML membership of this column (x, y) and per plane (z): where D/B are kept
+    // PML membership of this column (x, y); per plane for z: where D/B are kept
     const bool px = (i < B.pml[0]) || (B.pml[1] > 0 && i >= nx - B.pml[1]);
     const bool py = (j < B.pml[2]) || (B.pml[3] > 0 && j >= ny - B.pml[3]);
+    auto in_pz = [&](int k) { return (k < pml_zlo) || (pml_zhi > 0 && k >= nz - pml_zhi); };
 
     // per-axis coefficients of this column (node n / half node h)
     const int ic = min(max(i, 0), nx), jc = min(max(j, 0), ny);
-    const float* __restrict__ cx = B.coef[0];
-    const float* __restrict__ cy = B.coef[1];
-    const float* __restrict__ cz = B.coef[2];
+    cgfloat* __restrict__ cx = (cgfloat*)B.coef[0];
+    cgfloat* __restrict__ cy = (cgfloat*)B.coef[1];
+    kfloat* __restrict__ cz = (kfloat*)B.coef[2];
     const int nx1 = nx + 1, ny1 = ny + 1, nz1 = nz + 1;
 #define CX(kind, half) cx[((kind) * 2 + (half)) * nx1 + ic]
 #define CY(kind, half) cy[((kind) * 2 + (half)) * ny1 + jc]
@@ -102,17 +129,58 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
 #undef CX
 #undef CY
 
-    // prologue: Ex, Ey of plane 0 into LDS slot 0
+    // extra staging element of this thread: column a = TX (rows 0..TY) or row
+    // b = TY (columns 0..TX-1); the rest of the block stages nothing extra
+    const bool has_extra = tid < TY + 1 + TX;
+    const int ea = tid < TY + 1 ? TX : tid - (TY + 1);
+    const int eb = tid < TY + 1 ? tid : TY;
+    const int ei = ox + ea, ej = oy + eb;
+
+    // prologue: Ex, Ey of plane 0 into LDS slot 0; prefetch plane 0's operands
+    sEx[0][ty][tx] = ld_or0(gEx, i, j, 0, nx, ny, nz, sy, sz, guard);
+    sEy[0][ty][tx] = ld_or0(gEy, i, j, 0, nx, ny, nz, sy, sz, guard);
+    if (has_extra) {
+        sEx[0][eb][ea] = ld_or0(gEx, ei, ej, 0, nx, ny, nz, sy, sz, guard);
+        sEy[0][eb][ea] = ld_or0(gEy, ei, ej, 0, nx, ny, nz, sy, sz, guard);
+    }
+    // prefetched operands of the plane about to be computed
+    float pEx = ld_or0(gEx, i, j, 1, nx, ny, nz, sy, sz, guard);
+    float pEy = ld_or0(gEy, i, j, 1, nx, ny, nz, sy, sz, guard);
+    float pEz = ld_or0(gEz, i, j, 0, nx, ny, nz, sy, sz, guard);
+    float qEx = 0.f, qEy = 0.f, qEz = 0.f;
+    if (has_extra) {
+        qEx = ld_or0(gEx, ei, ej, 1, nx, ny, nz, sy, sz, guard);
+        qEy = ld_or0(gEy, ei, ej, 1, nx, ny, nz, sy, sz, guard);
+        qEz = ld_or0(gEz, ei, ej, 0, nx, ny, nz, sy, sz, guard);
+    }
+    const int node0 = i + j * sy;
+    float pHx = 0.f, pHy = 0.f, pHz = 0.f, pBx = 0.f, pBy = 0.f, pBz = 0.f;
+    float pDx = 0.f, pDy = 0.f, pDz = 0.f;
+    CT pC = 0;
+    if (sizeof(CT) == 1) {
+        for (int e = tid; e < kLdsClasses; e += TX * TY) {
+            const int c = min(e, B.nclass - 1);
+            sTab[e].inv_x = ctab[c].inv_x;
+            sTab[e].inv_y = ctab[c].inv_y;
+            sTab[e].inv_z = ctab[c].inv_z;
+            sTab[e].flags = ctab[c].flags;
+        }
+    }
     {
-        sEx[0][ty][tx] = ld_or0(sEx_g, i, j, 0, nx, ny, nz, sy, sz);
-        sEy[0][ty][tx] = ld_or0(sEy_g, i, j, 0, nx, ny, nz, sy, sz);
-        if (tid < TY + 1) {  // extra column a = TX
-            sEx[0][tid][TX] = ld_or0(sEx_g, ox + TX, oy + tid, 0, nx, ny, nz, sy, sz);
-            sEy[0][tid][TX] = ld_or0(sEy_g, ox + TX, oy + tid, 0, nx, ny, nz, sy, sz);
-        } else if (tid < TY + 1 + TX) {  // extra row b = TY
-            const int a = tid - (TY + 1);
-            sEx[0][TY][a] = ld_or0(sEx_g, ox + a, oy + TY, 0, nx, ny, nz, sy, sz);
-            sEy[0][TY][a] = ld_or0(sEy_g, ox + a, oy + TY, 0, nx, ny, nz, sy, sz);
+        const bool pz0 = in_pz(0);
+        if (col_ok) {
+            pHx = gHx[node0];
+            pHy = gHy[node0];
+            pHz = gHz[node0];
+            if (px || py) pBx = gBx[node0];
+            if (py || pz0) pBy = gBy[node0];
+            if (pz0 || px) pBz = gBz[node0];
+        }
+        if (own) {
+            pC = cls[node0];
+            if (px || py) pDx = Dx[node0];
+            if (py || pz0) pDy = Dy[node0];
+            if (pz0 || px) pDz = Dz[node0];
         }
     }
     float hx_prev = 0.0f, hy_prev = 0.0f;
@@ -120,45 +188,53 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
 
     for (int k = 0; k <= nz; ++k) {
         const int cur = k & 1, nxt = cur ^ 1;
-        const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= nz - B.pml[5]);
+        const bool pz = in_pz(k);
         const bool nbx = px || py, nby = py || pz, nbz = pz || px;
-        const int node = i + j * sy + k * sz;
+        const int node = node0 + k * sz;
 
-        // ---- phase A: stage E^n, load own old H/B/D ----
-        sEx[nxt][ty][tx] = ld_or0(sEx_g, i, j, k + 1, nx, ny, nz, sy, sz);
-        sEy[nxt][ty][tx] = ld_or0(sEy_g, i, j, k + 1, nx, ny, nz, sy, sz);
-        sEz[ty][tx] = ld_or0(sEz_g, i, j, k, nx, ny, nz, sy, sz);
-        if (tid < TY + 1) {
-            const int ii = ox + TX, jj = oy + tid;
-            sEx[nxt][tid][TX] = ld_or0(sEx_g, ii, jj, k + 1, nx, ny, nz, sy, sz);
-            sEy[nxt][tid][TX] = ld_or0(sEy_g, ii, jj, k + 1, nx, ny, nz, sy, sz);
-            sEz[tid][TX] = ld_or0(sEz_g, ii, jj, k, nx, ny, nz, sy, sz);
-        } else if (tid < TY + 1 + TX) {
-            const int a = tid - (TY + 1);
-            const int ii = ox + a, jj = oy + TY;
-            sEx[nxt][TY][a] = ld_or0(sEx_g, ii, jj, k + 1, nx, ny, nz, sy, sz);
-            sEy[nxt][TY][a] = ld_or0(sEy_g, ii, jj, k + 1, nx, ny, nz, sy, sz);
-            sEz[TY][a] = ld_or0(sEz_g, ii, jj, k, nx, ny, nz, sy, sz);
+        // ---- stage this plane's prefetched E into LDS, take own operands ----
+        sEx[nxt][ty][tx] = pEx;
+        sEy[nxt][ty][tx] = pEy;
+        sEz[ty][tx] = pEz;
+        if (has_extra) {
+            sEx[nxt][eb][ea] = qEx;
+            sEy[nxt][eb][ea] = qEy;
+            sEz[eb][ea] = qEz;
         }
-        float hxo = 0.f, hyo = 0.f, hzo = 0.f, bxo = 0.f, byo = 0.f, bzo = 0.f;
-        float dxo = 0.f, dyo = 0.f, dzo = 0.f;
-        uint32_t c = 0;
-        if (col_ok) {
-            hxo = hxo_g[node];
-            hyo = hyo_g[node];
-            hzo = hzo_g[node];
-            if (nbx) bxo = bxo_g[node];
-            if (nby) byo = byo_g[node];
-            if (nbz) bzo = bzo_g[node];
+        const float hxo = pHx, hyo = pHy, hzo = pHz, bxo = pBx, byo = pBy, bzo = pBz;
+        const float dxo = pDx, dyo = pDy, dzo = pDz;
+        const CT c = pC;
+
+        // ---- prefetch the next plane's operands (in flight during this plane) ----
+        if (k < nz) {
+            const int k1 = k + 1;
+            const bool pz1 = in_pz(k1);
+            pEx = ld_or0(gEx, i, j, k1 + 1, nx, ny, nz, sy, sz, guard);
+            pEy = ld_or0(gEy, i, j, k1 + 1, nx, ny, nz, sy, sz, guard);
+            pEz = ld_or0(gEz, i, j, k1, nx, ny, nz, sy, sz, guard);
+            if (has_extra) {
+                qEx = ld_or0(gEx, ei, ej, k1 + 1, nx, ny, nz, sy, sz, guard);
+                qEy = ld_or0(gEy, ei, ej, k1 + 1, nx, ny, nz, sy, sz, guard);
+                qEz = ld_or0(gEz, ei, ej, k1, nx, ny, nz, sy, sz, guard);
+            }
+            const int n1 = node + sz;
+            if (col_ok) {
+                pHx = gHx[n1];
+                pHy = gHy[n1];
+                pHz = gHz[n1];
+                pBx = (px || py) ? gBx[n1] : 0.f;
+                pBy = (py || pz1) ? gBy[n1] : 0.f;
+                pBz = (pz1 || px) ? gBz[n1] : 0.f;
+            }
             if (own) {
-                c = cls[node];
-                if (nbx) dxo = Dx[node];
-                if (nby) dyo = Dy[node];
-                if (nbz) dzo = Dz[node];
+                pC = cls[n1];
+                pDx = (px || py) ? Dx[n1] : 0.f;
+                pDy = (py || pz1) ? Dy[n1] : 0.f;
+                pDz = (pz1 || px) ? Dz[n1] : 0.f;
             }
         }
         // z coefficients of this plane (uniform over the block)
-        const float* czk = cz + k;
+        kfloat* czk = cz + k;
         const float z_cam1_n = czk[(kCam1 * 2 + 0) * nz1], z_ca_n = czk[(kCa * 2 + 0) * nz1],
                     z_rp_n = czk[(kRp * 2 + 0) * nz1], z_ph_n = czk[(kPh * 2 + 0) * nz1],
                     z_q_n = czk[(kQ * 2 + 0) * nz1];
@@ -167,32 +243,30 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
                     z_q_h = czk[(kQ * 2 + 1) * nz1];
         __syncthreads();
 
-        // ---- phase C: B then H of plane k (own + halo columns) ----
+        // ---- B then H of plane k (own + halo columns) ----
         float hxn = 0.f, hyn = 0.f, hzn = 0.f;
         const float exo = sEx[cur][ty][tx], eyo = sEy[cur][ty][tx], ezo = sEz[ty][tx];
         if (col_ok) {
             // Hx(i, j+1/2, k+1/2): Bx uses y at j+1/2; Hx uses z at k+1/2, x at i
             const float cxe = (sEz[ty + 1][tx] - ezo) * crdy - (sEy[nxt][ty][tx] - eyo) * crdz;
             const float dbx = fmaf(y_cam1_h, bxo, -y_rp_h * cxe);
-            const float bxn = bxo + dbx;
             hxn = fmaf(z_ca_h, hxo, z_rp_h * fmaf(x_ph_n, dbx, x_q_n * bxo));
             // Hy(i+1/2, j, k+1/2): By uses z at k+1/2; Hy uses x at i+1/2, y at j
             const float cye = (sEx[nxt][ty][tx] - exo) * crdz - (sEz[ty][tx + 1] - ezo) * crdx;
             const float dby = fmaf(z_cam1_h, byo, -z_rp_h * cye);
-            const float byn = byo + dby;
             hyn = fmaf(x_ca_h, hyo, x_rp_h * fmaf(y_ph_n, dby, y_q_n * byo));
             // Hz(i+1/2, j+1/2, k): Bz uses x at i+1/2; Hz uses y at j+1/2, z at k
-            const float cze = (sEy[cur][ty][tx + 1] - eyo) * crdx - (sEx[cur][ty + 1][tx] - exo) * crdy;
+            const float cze =
+                (sEy[cur][ty][tx + 1] - eyo) * crdx - (sEx[cur][ty + 1][tx] - exo) * crdy;
             const float dbz = fmaf(x_cam1_h, bzo, -x_rp_h * cze);
-            const float bzn = bzo + dbz;
             hzn = fmaf(y_ca_h, hzo, y_rp_h * fmaf(z_ph_n, dbz, z_q_n * bzo));
             if (own) {
                 dHx[node] = hxn;
                 dHy[node] = hyn;
                 dHz[node] = hzn;
-                if (nbx) dBx[node] = bxn;
-                if (nby) dBy[node] = byn;
-                if (nbz) dBz[node] = bzn;
+                if (nbx) dBx[node] = bxo + dbx;
+                if (nby) dBy[node] = byo + dby;
+                if (nbz) dBz[node] = bzo + dbz;
             }
         }
         sHx[ty][tx] = hxn;
@@ -200,9 +274,17 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
         sHz[ty][tx] = hzn;
         __syncthreads();
 
-        // ---- phase F: D then E of plane k (own columns) ----
+        // ---- D then E of plane k (own columns) ----
         if (own) {
-            const ClassEntry ce = B.ctab[c];
+            ClassEntry ce;
+            if (sizeof(CT) == 1) {
+                ce = sTab[c];
+            } else {
+                ce.inv_x = ctab[c].inv_x;
+                ce.inv_y = ctab[c].inv_y;
+                ce.inv_z = ctab[c].inv_z;
+                ce.flags = ctab[c].flags;
+            }
             // Ex(i+1/2, j, k): Dx uses y at j; Ex uses z at k, x at i+1/2
             const float chx = (hzn - sHz[ty - 1][tx]) * crdy - (hyn - hy_prev) * crdz;
             const float ddx = fmaf(y_cam1_n, dxo, y_rp_n * chx);
@@ -214,10 +296,14 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
             // Ez(i, j, k+1/2): Dz uses x at i; Ez uses y at j, z at k+1/2
             float js = 0.0f;
             if (ce.flags & kSrcEz) {
+                const __attribute__((address_space(1))) int32_t* sn =
+                    (const __attribute__((address_space(1))) int32_t*)B.src_node;
+                cgfloat* sj = (cgfloat*)B.src_j;
                 for (int s = 0; s < B.nsrc; ++s)
-                    if (B.src_node[s] == node) js += B.src_j[s * ms + step];
+                    if (sn[s] == node) js += sj[s * ms + step];
             }
-            const float chz = ((hyn - sHy[ty][tx - 1]) * crdx - (hxn - sHx[ty - 1][tx]) * crdy) - js;
+            const float chz =
+                ((hyn - sHy[ty][tx - 1]) * crdx - (hxn - sHx[ty - 1][tx]) * crdy) - js;
             const float ddz = fmaf(x_cam1_n, dzo, x_rp_n * chz);
             float ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * dzo)));
             exn = (ce.flags & kUpdEx) ? exn : 0.0f;
@@ -230,10 +316,13 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
             if (nby && (ce.flags & kUpdEy)) Dy[node] = dyo + ddy;
             if (nbz && (ce.flags & kUpdEz)) Dz[node] = dzo + ddz;
             if (ce.flags & kPrbEz) {
+                const __attribute__((address_space(1))) int32_t* pn =
+                    (const __attribute__((address_space(1))) int32_t*)B.prb_node;
+                gfloat* ps = (gfloat*)B.prb_series;
                 for (int p = 0; p < B.nprb; ++p)
-                    if (B.prb_node[p] == node) B.prb_series[p * ms + step] = ezn;
+                    if (pn[p] == node) ps[p * ms + step] = ezn;
             }
-            if (!isfinite(exn + eyn + ezn)) *B.bad = 1;
+            if (!isfinite(exn + eyn + ezn)) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
         }
         hx_prev = hxn;
         hy_prev = hyn;
