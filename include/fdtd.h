@@ -125,17 +125,28 @@ int fdtd_add_probe(fdtd_grid* g, int i, int j, int k, int* id);
 int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
 
 /* Enqueue n >= 0 leapfrog steps (per step: B then H at n+1/2 from E at n, D then E
- * at n+1 with the source, PEC planes and probes).  The first call finalises the
- * set-up.  ESTATE if steps would exceed max_steps or materials were never set.
- * EUNSTABLE if the watchdog (checked at the end of the call) found a non-finite
- * probe sample or field value in the last step; stepping stays possible. */
+ * at n+1 with the source, PEC planes and probes; Model section, Eqs. 3-4).  The
+ * first call finalises the set-up.  Whole chunks of 32 steps replay one captured
+ * HIP graph; the rest are plain launches (results are identical either way).
+ * ESTATE if steps would exceed max_steps or materials were never set.  The field
+ * kernel flags any non-finite E value; every synchronising call after that
+ * (getters, fdtd_synchronize, fdtd_probe_fft) returns FDTD_EUNSTABLE. */
 int fdtd_step_n(fdtd_grid* g, int64_t n);
 
 /* Batched stepping: advance ng handles by n[h] steps each in shared launches
- * (one field launch per step covers every handle still running).  Handles must
- * be distinct and share one device; results are bitwise those of stepping each
- * alone.  Runs on the first handle's stream.  Same errors as fdtd_step_n. */
+ * (one field launch per step covers every handle still running; handles whose
+ * class index widths differ go to two launches).  Handles must be distinct and
+ * share one device; results are bitwise those of stepping each alone.  Runs on
+ * the first handle's stream, ordered after (and before) work on the other
+ * handles' streams by events; uses the first handle's tile shape.  Same errors
+ * as fdtd_step_n. */
 int fdtd_step_many(fdtd_grid* const* g, int ng, const int64_t* n);
+
+/* Upper bound of the device memory (bytes) fdtd_create_grid with this
+ * descriptor, plus the given numbers of sources, probes and DFT frequencies, can
+ * allocate over the handle's life (for admission by HBM footprint).  Negative
+ * FDTD_EINVAL on a bad descriptor. */
+int64_t fdtd_estimate_bytes(const fdtd_grid_desc* desc, int n_sources, int n_probes, int n_freqs);
 
 /* Spectrum of probe `id` over the steps run so far (Results section, Fig. 5):
  * X[k] = sum_{s<N} e[s] exp(-2 pi i k s / n_fft) for k = 0..n_fft/2 with a

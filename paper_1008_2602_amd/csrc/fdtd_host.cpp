@@ -136,6 +136,11 @@ struct fdtd_grid {
     size_t ev_used = 0;
     int64_t timed_launches = 0;
 
+    // graph of kGraphChunk steps (field launches + counter advance), replayed by step_n
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_failed = false;
+    hipEvent_t sync_ev = nullptr;
+
     // batched-launch scratch (owned by the handle that leads a batch)
     BoardDev* batch_boards = nullptr;
     int batch_boards_cap = 0;
@@ -670,16 +675,9 @@ int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y)
     return fail(FDTD_EINVAL, "unsupported tile shape %dx%d", tile_x, tile_y);
 }
 
-int fdtd_step_n(fdtd_grid* g, int64_t n)
+static int enqueue_steps(fdtd_grid* g, int64_t s0, int64_t n)
 {
-    if (int e = check_grid(g)) return e;
-    if (n < 0) return fail(FDTD_EINVAL, "negative step count");
-    if (g->step + n > g->d.max_steps)
-        return fail(FDTD_ESTATE, "%lld steps would exceed max_steps %lld",
-                    (long long)(g->step + n), (long long)g->d.max_steps);
-    if (int e = finalize(g)) return e;
-    if (n == 0) return FDTD_OK;
-    for (int64_t s = 0; s < n; ++s) {
+    for (int64_t s = s0; s < s0 + n; ++s) {
         if (g->timing)
             if (int e = record_event(g)) return e;
         HIP_OR_FAIL(launch_field_step(g->tile_x, g->tile_y, g->board_dev, g->tiles_dev, g->ntiles,
@@ -689,8 +687,57 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
             ++g->timed_launches;
         }
     }
-    // advance the device step counter by n (one tiny launch per call)
-    HIP_OR_FAIL(launch_advance_one(g->step_dev, n, g->stream));
+    return FDTD_OK;
+}
+
+// Capture kGraphChunk field launches and the counter advance into one graph.
+// The kernels take the step from the device counter, so the same graph serves
+// every chunk.  Any failure leaves plain launches in use.
+static void build_graph(fdtd_grid* g)
+{
+    if (g->graph_exec || g->graph_failed) return;
+    g->graph_failed = true;
+    if (!g->own_stream && g->stream == nullptr) return;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
+    bool ok = true;
+    for (int s = 0; s < kGraphChunk && ok; ++s)
+        ok = launch_field_step(g->tile_x, g->tile_y, g->board_dev, g->tiles_dev, g->ntiles, s,
+                               g->wide, g->stream) == hipSuccess;
+    if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, g->stream) == hipSuccess;
+    const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
+    if (ok && ended && graph &&
+        hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess)
+        g->graph_failed = false;
+    else
+        g->graph_exec = nullptr;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+}
+
+int fdtd_step_n(fdtd_grid* g, int64_t n)
+{
+    if (int e = check_grid(g)) return e;
+    if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+    if (g->step + n > g->d.max_steps)
+        return fail(FDTD_ESTATE, "%lld steps would exceed max_steps %lld",
+                    (long long)(g->step + n), (long long)g->d.max_steps);
+    if (int e = finalize(g)) return e;
+    if (n == 0) return FDTD_OK;
+    int64_t done = 0;
+    if (!g->timing && n >= kGraphChunk) {
+        build_graph(g);
+        if (g->graph_exec) {
+            for (; done + kGraphChunk <= n; done += kGraphChunk)
+                HIP_OR_FAIL(hipGraphLaunch(g->graph_exec, g->stream));
+        }
+    }
+    if (done < n) {
+        // kernels add the launch-relative step to the device counter, which the
+        // graphs above have already advanced
+        if (int e = enqueue_steps(g, 0, n - done)) return e;
+        HIP_OR_FAIL(launch_advance_one(g->step_dev, n - done, g->stream));
+    }
     if (g->dft_f)
         HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
                                (int)g->probes.size(), g->dt, g->step, g->step + n, g->dft_re,
@@ -699,12 +746,136 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
     return FDTD_OK;
 }
 
+static int ensure_event(fdtd_grid* g)
+{
+    if (!g->sync_ev) HIP_OR_FAIL(hipEventCreateWithFlags(&g->sync_ev, hipEventDisableTiming));
+    return FDTD_OK;
+}
+
 int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
 {
-    (void)gs;
-    (void)ng;
-    (void)n;
-    return fail(FDTD_EINVAL, "fdtd_step_many is not available yet");
+    if (!gs || !n || ng < 1) return fail(FDTD_EINVAL, "need at least one handle and step counts");
+    for (int h = 0; h < ng; ++h) {
+        if (!gs[h]) return fail(FDTD_EINVAL, "null handle %d", h);
+        if (n[h] < 0) return fail(FDTD_EINVAL, "negative step count for handle %d", h);
+        for (int o = 0; o < h; ++o)
+            if (gs[o] == gs[h]) return fail(FDTD_EINVAL, "handle %d appears twice", h);
+        if (gs[h]->device != gs[0]->device) return fail(FDTD_EINVAL, "handles on different devices");
+        if (gs[h]->step + n[h] > gs[h]->d.max_steps)
+            return fail(FDTD_ESTATE, "handle %d: steps would exceed max_steps", h);
+    }
+    for (int h = 0; h < ng; ++h)
+        if (int e = finalize(gs[h])) return e;
+    fdtd_grid* lead = gs[0];
+    hipStream_t st = lead->stream;
+    const int tx = lead->tile_x, ty = lead->tile_y;
+
+    // order boards by step count (descending): at step s the boards still running
+    // form a prefix, and so do their tiles; narrow and wide class maps go to
+    // separate launches (the kernel is specialised on the class index width)
+    std::vector<int> order(ng);
+    for (int h = 0; h < ng; ++h) order[h] = h;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (gs[a]->wide != gs[b]->wide) return gs[a]->wide < gs[b]->wide;
+        return n[a] > n[b];
+    });
+    std::vector<BoardDev> boards(ng);
+    std::vector<int64_t> nn(ng);
+    std::vector<TileRef> tiles;
+    int group_start[2] = {-1, -1}, group_tiles0[2] = {0, 0};
+    std::vector<int64_t> tiles_upto(ng);  // tiles of boards order[0..b] within the group
+    int64_t max_n = 0;
+    for (int b = 0; b < ng; ++b) {
+        fdtd_grid* g = gs[order[b]];
+        const int w = g->wide ? 1 : 0;
+        if (group_start[w] < 0) {
+            group_start[w] = b;
+            group_tiles0[w] = (int)tiles.size();
+        }
+        boards[b] = g->board_host;
+        nn[b] = n[order[b]];
+        max_n = std::max(max_n, nn[b]);
+        const int tiles_x = (g->d.nx + 1 + tx - 2) / (tx - 1);
+        const int tiles_y = (g->d.ny + 1 + ty - 2) / (ty - 1);
+        for (int y = 0; y < tiles_y; ++y)
+            for (int x = 0; x < tiles_x; ++x) tiles.push_back(TileRef{b, x, y});
+        tiles_upto[b] = (int64_t)tiles.size();
+    }
+    // device scratch held by the lead handle
+    if (lead->batch_boards_cap < ng) {
+        lead->batch_boards = (BoardDev*)dev_alloc(lead, sizeof(BoardDev) * (size_t)ng);
+        lead->batch_n = (int64_t*)dev_alloc(lead, sizeof(int64_t) * (size_t)ng);
+        if (!lead->batch_boards || !lead->batch_n) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
+        lead->batch_boards_cap = ng;
+    }
+    if (lead->batch_tiles_cap < (int)tiles.size()) {
+        lead->batch_tiles = (TileRef*)dev_alloc(lead, sizeof(TileRef) * tiles.size());
+        if (!lead->batch_tiles) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
+        lead->batch_tiles_cap = (int)tiles.size();
+    }
+    // order after the work already queued on every handle's stream
+    for (int h = 1; h < ng; ++h) {
+        if (gs[h]->stream == st) continue;
+        if (int e = ensure_event(gs[h])) return e;
+        HIP_OR_FAIL(hipEventRecord(gs[h]->sync_ev, gs[h]->stream));
+        HIP_OR_FAIL(hipStreamWaitEvent(st, gs[h]->sync_ev, 0));
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_boards, boards.data(), sizeof(BoardDev) * (size_t)ng,
+                               hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_tiles, tiles.data(), sizeof(TileRef) * tiles.size(),
+                               hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, nn.data(), sizeof(int64_t) * (size_t)ng,
+                               hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));  // the host arrays above are locals
+    for (int w = 0; w < 2; ++w) {
+        if (group_start[w] < 0) continue;
+        const int b0 = group_start[w];
+        int b1 = b0;
+        while (b1 < ng && gs[order[b1]]->wide == (w == 1)) ++b1;
+        int active = b1;  // boards [b0, active) still running
+        for (int64_t s = 0; s < max_n; ++s) {
+            while (active > b0 && nn[active - 1] <= s) --active;
+            if (active == b0) break;
+            const int ntiles = (int)(tiles_upto[active - 1] - group_tiles0[w]);
+            HIP_OR_FAIL(launch_field_step(tx, ty, lead->batch_boards,
+                                          lead->batch_tiles + group_tiles0[w], ntiles, (int)s,
+                                          w == 1, st));
+        }
+    }
+    HIP_OR_FAIL(launch_advance(lead->batch_boards, ng, lead->batch_n, st));
+    for (int h = 0; h < ng; ++h) {
+        fdtd_grid* g = gs[h];
+        if (g->dft_f && n[h] > 0)
+            HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
+                                   (int)g->probes.size(), g->dt, g->step, g->step + n[h],
+                                   g->dft_re, g->dft_im, st));
+        g->step += n[h];
+    }
+    // later work on every handle's own stream orders after the batch
+    if (int e = ensure_event(lead)) return e;
+    HIP_OR_FAIL(hipEventRecord(lead->sync_ev, st));
+    for (int h = 1; h < ng; ++h)
+        if (gs[h]->stream != st) HIP_OR_FAIL(hipStreamWaitEvent(gs[h]->stream, lead->sync_ev, 0));
+    return FDTD_OK;
+}
+
+int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes, int n_freqs)
+{
+    if (!d || d->nx < 2 || d->ny < 2 || d->nz < 2 || d->max_steps < 1 || n_sources < 0 ||
+        n_probes < 0 || n_freqs < 0)
+        return fail(FDTD_EINVAL, "bad descriptor or counts");
+    auto r = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    const int64_t nodes = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    int64_t t = 21 * r((nodes + kGuard) * 4);                                   // fields
+    t += r(2 * nodes);                                                          // class map (upper bound)
+    t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
+    t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +
+         r((int64_t)kNumCoef * 2 * (d->nz + 1) * 4);                            // coefficients
+    t += r(4 * (int64_t)n_sources) + r(4 * (int64_t)n_sources * d->max_steps);   // sources
+    t += r(4 * (int64_t)n_probes) + r(4 * (int64_t)n_probes * d->max_steps);     // probes
+    t += r(8 * (int64_t)n_freqs) + 2 * r(8 * (int64_t)n_probes * n_freqs);       // DFT
+    t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * (nodes / 64 + 64)); // small buffers
+    return t;
 }
 
 int fdtd_synchronize(fdtd_grid* g)
@@ -957,6 +1128,8 @@ int fdtd_destroy_grid(fdtd_grid* g)
     if (!g) return FDTD_OK;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    if (g->sync_ev) (void)hipEventDestroy(g->sync_ev);
     dev_free_all(g);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

@@ -24,6 +24,9 @@ constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
 constexpr double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
 constexpr double kEta0 = kMu0 * kC0;
 
+// steps per replayable graph in fdtd_step_n
+constexpr int kGraphChunk = 32;
+
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;
 

@@ -20,7 +20,8 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfdtd.so")
+# FDTD_LIBRARY may point at another build of the same library (same ABI)
+LIB_PATH = os.environ.get("FDTD_LIBRARY") or os.path.join(_HERE, "libfdtd.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fdtd.h")
 
 if not os.path.exists(LIB_PATH):
@@ -85,6 +86,7 @@ _sigs = {
     "fdtd_get_field": ([_P, C.c_int, _P], C.c_int),
     "fdtd_set_field": ([_P, C.c_int, _P], C.c_int),
     "fdtd_state_bytes": ([_P], C.c_int64),
+    "fdtd_estimate_bytes": ([C.POINTER(fdtd_grid_desc), C.c_int, C.c_int, C.c_int], C.c_int64),
     "fdtd_save_state": ([_P, _P, C.c_int64], C.c_int),
     "fdtd_load_state": ([_P, _P, C.c_int64], C.c_int),
     "fdtd_get_info": ([_P, C.POINTER(fdtd_info)], C.c_int),
@@ -161,9 +163,8 @@ class TorchAllocator:
 # --------------------------------------------------------------------------
 # the C calls
 
-def fdtd_create_grid(nx, ny, nz, dx, dy, dz, *, dt=0.0, courant=0.99, npml=(8,) * 6,
-                     pml_m=3.0, pml_R=1e-6, pml_kappa_max=1.0, max_steps=1,
-                     hip_stream=None, allocator: Optional[TorchAllocator] = None):
+def _desc(nx, ny, nz, dx, dy, dz, dt, courant, npml, pml_m, pml_R, pml_kappa_max, max_steps,
+          hip_stream, allocator):
     d = fdtd_grid_desc()
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.dx, d.dy, d.dz = float(dx), float(dy), float(dz)
@@ -174,6 +175,14 @@ def fdtd_create_grid(nx, ny, nz, dx, dy, dz, *, dt=0.0, courant=0.99, npml=(8,) 
     d.hip_stream = hip_stream
     if allocator is not None:
         d.dev_alloc, d.dev_free = allocator.alloc, allocator.free
+    return d
+
+
+def fdtd_create_grid(nx, ny, nz, dx, dy, dz, *, dt=0.0, courant=0.99, npml=(8,) * 6,
+                     pml_m=3.0, pml_R=1e-6, pml_kappa_max=1.0, max_steps=1,
+                     hip_stream=None, allocator: Optional[TorchAllocator] = None):
+    d = _desc(nx, ny, nz, dx, dy, dz, dt, courant, npml, pml_m, pml_R, pml_kappa_max,
+              max_steps, hip_stream, allocator)
     h = C.c_void_p()
     _check(_lib.fdtd_create_grid(C.byref(d), C.byref(h)))
     return h
@@ -262,6 +271,28 @@ def fdtd_save_state(g) -> bytes:
 def fdtd_load_state(g, image: bytes):
     buf = C.create_string_buffer(image, len(image))
     _check(_lib.fdtd_load_state(g, buf, len(image)))
+
+
+def fdtd_estimate_bytes(nx, ny, nz, dx, dy, dz, *, n_sources=0, n_probes=0, n_freqs=0,
+                        dt=0.0, courant=0.99, npml=(8,) * 6, pml_m=3.0, pml_R=1e-6,
+                        pml_kappa_max=1.0, max_steps=1) -> int:
+    d = _desc(nx, ny, nz, dx, dy, dz, dt, courant, npml, pml_m, pml_R, pml_kappa_max,
+              max_steps, None, None)
+    v = _lib.fdtd_estimate_bytes(C.byref(d), int(n_sources), int(n_probes), int(n_freqs))
+    if v < 0:
+        raise FdtdError(int(v), fdtd_last_error())
+    return int(v)
+
+
+def board_bytes(board, max_steps: Optional[int] = None) -> int:
+    """Upper bound of the device bytes a handle for ``board`` holds."""
+    b = board
+    return fdtd_estimate_bytes(b.nx, b.ny, b.nz, b.dx, b.dy, b.dz, n_sources=len(b.sources),
+                               n_probes=len(b.probes),
+                               n_freqs=0 if b.dft_freqs is None else len(b.dft_freqs),
+                               dt=b.dt, courant=b.courant, npml=b.npml, pml_m=b.pml_m,
+                               pml_R=b.pml_R, pml_kappa_max=b.pml_kappa_max,
+                               max_steps=int(max_steps if max_steps is not None else b.steps))
 
 
 def fdtd_get_info(g) -> fdtd_info:

@@ -272,3 +272,78 @@ def test_unstable_run_is_reported(F):
         F.fdtd_synchronize(g)
     assert ei.value.code == F.FDTD_EUNSTABLE
     F.fdtd_destroy_grid(g)
+
+
+def _small_variants(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        b = boardgen.variant_board(rng, i, steps=int(rng.integers(40, 160)),
+                                   n_xy=(int(rng.integers(40, 130)), int(rng.integers(40, 130))),
+                                   nz=int(rng.integers(24, 40)))
+        for s in b.sources:
+            s.t0, s.sigma = 30e-12, 8e-12
+        b.dft_freqs = np.linspace(1e9, 20e9, 8)
+        out.append(b)
+    return out
+
+
+def test_step_many_bitwise_equals_alone(F):
+    boards = _small_variants(11, 6)
+    # one board with a wide (uint16) class map: many distinct permittivities
+    rng = np.random.default_rng(3)
+    boards[2].eps_r_cell[:] = rng.choice([1.0, 2.5, 4.4],
+                                         size=boards[2].eps_r_cell.shape).astype(np.float32)
+    announce(f"step_many over {len(boards)} boards, steps {[b.steps for b in boards]}")
+    alone = []
+    for b in boards:
+        p, f, d, info = gpu_run(F, b)
+        alone.append((p, f, d))
+        if b is boards[2]:
+            assert info.n_classes > 256
+    handles = [F.grid_from_board(b) for b in boards]
+    gs = [h for h, _ in handles]
+    # two batched calls with uneven counts, then the remainders
+    first = [b.steps // 3 for b in boards]
+    F.fdtd_step_many(gs, first)
+    F.fdtd_step_many(gs[::-1], [b.steps - f for b, f in zip(boards, first)][::-1])
+    for (g, ids), b, (p, f, d) in zip(handles, boards, alone):
+        pb = np.stack([F.fdtd_get_probe(g, q, b.steps) for q in ids])
+        assert np.array_equal(pb, p)
+        fb = gpu_fields(F, g, b)
+        for n in FIELDS:
+            assert np.array_equal(fb[n], f[n]), (b.name, n)
+        db = np.stack([F.fdtd_get_dft(g, q) for q in ids])
+        assert np.allclose(db, d, rtol=1e-12, atol=0)
+        F.fdtd_destroy_grid(g)
+
+
+def test_graph_replays_match_eager(F):
+    """Graph-replayed chunks (timing off) against eager launches (timing on), with
+    synchronisation and host reads between every replay."""
+    b = boardgen.config1(steps=32 * 6)
+    ga, ida = F.grid_from_board(b)
+    gb, idb = F.grid_from_board(b)
+    F.fdtd_set_timing(gb, True)            # forces plain launches
+    shp = (b.nz + 1, b.ny + 1, b.nx + 1)
+    for c in range(6):
+        announce(f"graph chunk {c}")
+        F.fdtd_step_n(ga, 32)
+        F.fdtd_step_n(gb, 32)
+        F.fdtd_synchronize(ga)
+        F.fdtd_synchronize(gb)
+        for comp in (F.FDTD_EX, F.FDTD_EZ, F.FDTD_HY, F.FDTD_BZ):
+            assert np.array_equal(F.fdtd_get_field(ga, comp, shp), F.fdtd_get_field(gb, comp, shp))
+    assert np.array_equal(F.fdtd_get_probe(ga, ida[0], b.steps), F.fdtd_get_probe(gb, idb[0], b.steps))
+    F.fdtd_destroy_grid(ga)
+    F.fdtd_destroy_grid(gb)
+
+
+def test_estimate_bytes_bounds_allocation(F):
+    for b in _small_variants(5, 3) + [boardgen.config1()]:
+        est = F.board_bytes(b)
+        g, _ = F.grid_from_board(b)
+        F.fdtd_step_n(g, 1)
+        used = F.fdtd_get_info(g).device_bytes
+        F.fdtd_destroy_grid(g)
+        assert used <= est < 1.3 * used + (2 << 20), (b.name, used, est)
