@@ -114,6 +114,7 @@ struct fdtd_grid {
     BoardDev* board_dev = nullptr;
     TileRef* tiles_dev = nullptr;
     int ntiles = 0;
+    int tiles_cap = 0;
     BoardDev board_host{};
 
     // host-side set-up
@@ -293,6 +294,10 @@ int64_t count_step_bytes(const fdtd_grid* g)
     return g->nodes * (24 + 24 + cls_bytes) + (aux_x + aux_y + aux_z) * 2 * 8;
 }
 
+}  // namespace
+static int upload_tiles(fdtd_grid* g);
+namespace {
+
 int finalize(fdtd_grid* g)
 {
     if (g->finalized) return FDTD_OK;
@@ -451,20 +456,9 @@ int finalize(fdtd_grid* g)
     b.crd_x = (float)(kC0 * g->dt / d.dx);
     b.crd_y = (float)(kC0 * g->dt / d.dy);
     b.crd_z = (float)(kC0 * g->dt / d.dz);
-    b.tiles_x = (nx + 1 + g->tile_x - 2) / (g->tile_x - 1);
-    b.tiles_y = (ny + 1 + g->tile_y - 2) / (g->tile_y - 1);
     g->board_dev = (BoardDev*)dev_alloc(g, sizeof(BoardDev));
     if (!g->board_dev) return fail(FDTD_ENOMEM, "descriptor allocation failed");
-    HIP_OR_FAIL(hipMemcpyAsync(g->board_dev, &b, sizeof(BoardDev), hipMemcpyHostToDevice, st));
-    g->ntiles = b.tiles_x * b.tiles_y;
-    std::vector<TileRef> tl((size_t)g->ntiles);
-    for (int ty = 0; ty < b.tiles_y; ++ty)
-        for (int tx = 0; tx < b.tiles_x; ++tx) tl[(size_t)ty * b.tiles_x + tx] = TileRef{0, tx, ty};
-    g->tiles_dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
-    if (!g->tiles_dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
-    HIP_OR_FAIL(hipMemcpyAsync(g->tiles_dev, tl.data(), tl.size() * sizeof(TileRef),
-                               hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(hipStreamSynchronize(st));
+    if (int e = upload_tiles(g)) return e;
     g->step_bytes = count_step_bytes(g);
     g->finalized = true;
     return FDTD_OK;
@@ -658,10 +652,35 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
     return FDTD_OK;
 }
 
+static int upload_tiles(fdtd_grid* g)
+{
+    BoardDev& b = g->board_host;
+    b.tiles_x = (g->d.nx + 1 + g->tile_x - 2) / (g->tile_x - 1);
+    b.tiles_y = (g->d.ny + 1 + g->tile_y - 2) / (g->tile_y - 1);
+    const int nt = b.tiles_x * b.tiles_y;
+    std::vector<TileRef> tl((size_t)nt);
+    for (int ty = 0; ty < b.tiles_y; ++ty)
+        for (int tx = 0; tx < b.tiles_x; ++tx) tl[(size_t)ty * b.tiles_x + tx] = TileRef{0, tx, ty};
+    if (nt > g->tiles_cap) {
+        g->tiles_dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
+        if (!g->tiles_dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
+        g->tiles_cap = nt;
+    }
+    HIP_OR_FAIL(copy_sync(g, g->tiles_dev, tl.data(), tl.size() * sizeof(TileRef),
+                          hipMemcpyHostToDevice));
+    HIP_OR_FAIL(copy_sync(g, g->board_dev, &b, sizeof(BoardDev), hipMemcpyHostToDevice));
+    g->ntiles = nt;
+    if (g->graph_exec) {
+        (void)hipGraphExecDestroy(g->graph_exec);
+        g->graph_exec = nullptr;
+    }
+    g->graph_failed = false;
+    return FDTD_OK;
+}
+
 int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y)
 {
     if (int e = check_grid(g)) return e;
-    if (g->finalized) return fail(FDTD_ESTATE, "the tile shape is fixed after the first step");
     const int n = num_shapes();
     for (int s = 0; s < n; ++s) {
         int tx, ty;
@@ -669,7 +688,7 @@ int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y)
         if (tx == tile_x && ty == tile_y) {
             g->tile_x = tx;
             g->tile_y = ty;
-            return FDTD_OK;
+            return g->finalized ? upload_tiles(g) : FDTD_OK;
         }
     }
     return fail(FDTD_EINVAL, "unsupported tile shape %dx%d", tile_x, tile_y);

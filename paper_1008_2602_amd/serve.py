@@ -1,0 +1,214 @@
+"""Continuous-batching solve server over libfdtd.
+
+Board-solve requests arrive over time.  At every chunk boundary the server
+  1. admits waiting requests, oldest first, while their device footprint fits in
+     the budget (a younger request may pass an older one that does not fit, until
+     the older one has waited ``max_bypass_s``; after that nothing passes it);
+  2. advances every resident board by up to ``chunk`` steps in shared launches
+     (``fdtd_step_many``), so requests that arrived while others were running
+     join them on the device;
+  3. finishes the boards that reached their step count (probe series and DFT
+     read back, handle destroyed, footprint released).
+Fields stay resident on the device between chunks.  Latency is completion time
+minus arrival time.  The executor is pluggable: ``GpuExecutor`` drives the
+library, tests drive the same scheduler with a modelled executor on the CPU.
+"""
+from __future__ import annotations
+
+import heapq
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class SolveRequest:
+    rid: int
+    arrival_s: float
+    board: Any                      # boardgen.Board-like (geometry, sources, probes, steps)
+    steps: Optional[int] = None     # default board.steps
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.steps if self.steps is not None else self.board.steps)
+
+
+@dataclass
+class SolveResult:
+    rid: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    steps: int
+    cells: int
+    probes: Optional[np.ndarray] = None
+    dft: Optional[np.ndarray] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+    @property
+    def wait_s(self) -> float:
+        return self.admit_s - self.arrival_s
+
+
+@dataclass
+class _Resident:
+    req: SolveRequest
+    handle: Any
+    probe_ids: List[int]
+    done: int
+    bytes: int
+    admit_s: float
+
+
+class GpuExecutor:
+    """Runs boards through libfdtd on the current device."""
+
+    def __init__(self, allocator=None, tile=None, collect=True):
+        from . import fdtd as F
+        self.F = F
+        self.allocator = allocator
+        self.tile = tile
+        self.collect = collect
+
+    def footprint(self, req: SolveRequest) -> int:
+        return self.F.board_bytes(req.board, max_steps=req.n_steps)
+
+    def create(self, req: SolveRequest):
+        g, ids = self.F.grid_from_board(req.board, max_steps=req.n_steps,
+                                        allocator=self.allocator, tile=self.tile)
+        return g, ids
+
+    def step(self, handles: Sequence, ns: Sequence[int]) -> None:
+        self.F.fdtd_step_many(list(handles), list(ns))
+        self.F.fdtd_synchronize(handles[0])
+
+    def finish(self, handle, probe_ids, req: SolveRequest):
+        F = self.F
+        probes = dft = None
+        if self.collect:
+            probes = np.stack([F.fdtd_get_probe(handle, p, req.n_steps) for p in probe_ids]) \
+                if probe_ids else np.zeros((0, req.n_steps), np.float32)
+            if req.board.dft_freqs is not None and probe_ids:
+                dft = np.stack([F.fdtd_get_dft(handle, p) for p in probe_ids])
+        F.fdtd_destroy_grid(handle)
+        return probes, dft
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def wait_until(self, t: float) -> None:
+        d = t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, chunk: int = 500,
+                 max_resident: Optional[int] = None, max_bypass_s: float = 5.0,
+                 log: Optional[Callable[[dict], None]] = None):
+        if budget_bytes <= 0 or chunk <= 0:
+            raise ValueError("budget and chunk must be positive")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.chunk = int(chunk)
+        self.max_resident = max_resident
+        self.max_bypass_s = float(max_bypass_s)
+        self.log = log
+        self.chunks = 0
+        self.peak_bytes = 0
+        self.peak_resident = 0
+        self.rejected: List[int] = []
+
+    def run(self, requests: Sequence[SolveRequest]) -> List[SolveResult]:
+        ex = self.ex
+        pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        foot = {}
+        for r in pending:
+            foot[r.rid] = ex.footprint(r)
+            if foot[r.rid] > self.budget:
+                self.rejected.append(r.rid)
+        pending = [r for r in pending if r.rid not in set(self.rejected)]
+        t0 = ex.now()
+        waiting: List[SolveRequest] = []
+        resident: List[_Resident] = []
+        used = 0
+        results: List[SolveResult] = []
+        nxt = 0
+        while nxt < len(pending) or waiting or resident:
+            now = ex.now() - t0
+            while nxt < len(pending) and pending[nxt].arrival_s <= now:
+                waiting.append(pending[nxt])
+                nxt += 1
+            # admission: oldest first; younger requests may pass a blocked one until
+            # it has waited max_bypass_s
+            admitted = []
+            blocked_since = None
+            for r in list(waiting):
+                if self.max_resident is not None and len(resident) >= self.max_resident:
+                    break
+                fits = used + foot[r.rid] <= self.budget
+                if not fits:
+                    if blocked_since is None:
+                        blocked_since = r.arrival_s
+                    if now - blocked_since >= self.max_bypass_s:
+                        break
+                    continue
+                h, ids = ex.create(r)
+                used += foot[r.rid]
+                resident.append(_Resident(r, h, ids, 0, foot[r.rid], ex.now() - t0))
+                waiting.remove(r)
+                admitted.append(r.rid)
+            self.peak_bytes = max(self.peak_bytes, used)
+            self.peak_resident = max(self.peak_resident, len(resident))
+            if not resident:
+                if nxt < len(pending):
+                    ex.wait_until(t0 + pending[nxt].arrival_s)
+                    continue
+                if waiting:
+                    raise RuntimeError("a waiting request can never be admitted")
+                break
+            ns = [min(self.chunk, e.req.n_steps - e.done) for e in resident]
+            ex.step([e.handle for e in resident], ns)
+            self.chunks += 1
+            for e, n in zip(resident, ns):
+                e.done += n
+            fin_t = ex.now() - t0
+            still = []
+            for e in resident:
+                if e.done >= e.req.n_steps:
+                    probes, dft = ex.finish(e.handle, e.probe_ids, e.req)
+                    used -= e.bytes
+                    b = e.req.board
+                    results.append(SolveResult(e.req.rid, e.req.arrival_s, e.admit_s, fin_t,
+                                               e.req.n_steps, b.nx * b.ny * b.nz, probes, dft))
+                else:
+                    still.append(e)
+            resident = still
+            if self.log:
+                self.log(dict(t=fin_t, chunk=self.chunks, resident=len(resident),
+                              waiting=len(waiting), used=used, admitted=admitted))
+        return sorted(results, key=lambda r: r.rid)
+
+
+def summarize(results: Sequence[SolveResult], wall_s: Optional[float] = None) -> Dict[str, float]:
+    if not results:
+        return {"completed": 0}
+    lat = np.array([r.latency_s for r in results])
+    wait = np.array([r.wait_s for r in results])
+    span = wall_s if wall_s is not None else max(r.finish_s for r in results) - min(
+        r.arrival_s for r in results)
+    cell_updates = float(sum(r.cells * r.steps for r in results))
+    return {
+        "completed": len(results),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_wait_s": float(wait.mean()),
+        "solves_per_s": len(results) / span if span > 0 else float("inf"),
+        "gcell_updates_per_s": cell_updates / span / 1e9 if span > 0 else float("inf"),
+        "span_s": span,
+    }

@@ -1,0 +1,158 @@
+"""Serving scheduler logic on the CPU with a modelled executor (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_1008_2602_amd.serve import Server, SolveRequest, summarize
+
+
+class _B:
+    def __init__(self, nx, ny, nz, steps):
+        self.nx, self.ny, self.nz, self.steps = nx, ny, nz, steps
+        self.dft_freqs = None
+
+
+class ModelExecutor:
+    """Modelled device: a chunk takes sum(cells * steps) / rate seconds; the
+    footprint is 100 bytes per cell; results are a deterministic function of
+    the request id and the steps it was advanced by."""
+
+    def __init__(self, rate=1e9):
+        self.rate = rate
+        self.t = 0.0
+        self.live = {}
+        self.max_live = 0
+        self.batches = []
+
+    def footprint(self, req):
+        b = req.board
+        return b.nx * b.ny * b.nz * 100
+
+    def create(self, req):
+        self.live[req.rid] = 0
+        self.max_live = max(self.max_live, len(self.live))
+        return req.rid, [0]
+
+    def step(self, handles, ns):
+        self.batches.append(list(handles))
+        work = 0
+        for h, n in zip(handles, ns):
+            self.live[h] += n
+            b = self.reqs[h].board
+            work += b.nx * b.ny * b.nz * n
+        self.t += work / self.rate
+
+    def finish(self, h, ids, req):
+        steps = self.live.pop(h)
+        assert steps == req.n_steps
+        return np.full((1, 3), float(h)), None
+
+    def now(self):
+        return self.t
+
+    def wait_until(self, t):
+        self.t = max(self.t, t)
+
+
+def _requests(n, seed=0, rate=2.0, big_every=0):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(n):
+        t += rng.exponential(1.0 / rate)
+        if big_every and r % big_every == big_every - 1:
+            b = _B(400, 400, 60, 400)
+        else:
+            b = _B(int(rng.integers(100, 300)), int(rng.integers(100, 300)), 30,
+                   int(rng.integers(200, 900)))
+        out.append(SolveRequest(r, t, b))
+    return out
+
+
+def _run(reqs, budget, chunk=100, **kw):
+    ex = ModelExecutor()
+    ex.reqs = {r.rid: r for r in reqs}
+    used_log = []
+    srv = Server(ex, budget, chunk=chunk, log=lambda d: used_log.append(d), **kw)
+    res = srv.run(reqs)
+    return ex, srv, res, used_log
+
+
+def test_every_request_completes_with_its_own_result():
+    reqs = _requests(40)
+    ex, srv, res, log = _run(reqs, budget=4 * 300 * 300 * 30 * 100)
+    assert [r.rid for r in res] == list(range(40))
+    for r in res:
+        assert r.probes[0, 0] == r.rid
+        assert r.finish_s >= r.admit_s >= r.arrival_s
+        # cannot finish faster than its own work at the full device rate
+        assert r.finish_s - r.admit_s >= r.cells * r.steps / ex.rate - 1e-12
+
+
+def test_budget_is_never_exceeded():
+    reqs = _requests(60, seed=1, rate=10.0)
+    budget = 3 * 250 * 250 * 30 * 100
+    ex, srv, res, log = _run(reqs, budget=budget)
+    assert all(d["used"] <= budget for d in log)
+    assert srv.peak_bytes <= budget
+    assert len(res) == 60
+
+
+def test_arrivals_join_running_batches():
+    reqs = _requests(30, seed=2, rate=5.0)
+    ex, srv, res, log = _run(reqs, budget=10 ** 12)
+    # some chunk after the first admitted new work while other boards were resident
+    joined = [d for d in log[1:] if d["admitted"] and d["resident"] > len(d["admitted"])]
+    assert joined
+    assert max(len(b) for b in ex.batches) > 1
+
+
+def test_large_request_bypass_is_bounded():
+    # a budget that fits one large board or several small ones
+    reqs = _requests(40, seed=3, rate=20.0, big_every=10)
+    budget = 400 * 400 * 60 * 100
+    ex, srv, res, log = _run(reqs, budget=budget, max_bypass_s=0.5)
+    assert len(res) == 40
+    big = [r for r in res if r.cells == 400 * 400 * 60]
+    assert big
+    small = [r for r in res if r.cells != 400 * 400 * 60]
+    # once a big request has waited max_bypass_s, nothing younger is admitted before it
+    for b in big:
+        younger = [s for s in small if s.arrival_s > b.arrival_s and s.admit_s > b.arrival_s + 0.5 + 1e-9]
+        assert all(s.admit_s >= b.admit_s for s in younger)
+
+
+def test_oversized_request_is_rejected():
+    reqs = _requests(5, seed=4)
+    reqs.append(SolveRequest(99, 0.1, _B(2000, 2000, 64, 10)))
+    ex, srv, res, log = _run(reqs, budget=10 ** 9)
+    assert srv.rejected == [99]
+    assert 99 not in [r.rid for r in res]
+
+
+def test_summary_percentiles():
+    reqs = _requests(50, seed=5)
+    ex, srv, res, log = _run(reqs, budget=10 ** 12)
+    s = summarize(res)
+    lat = np.array([r.latency_s for r in res])
+    assert s["completed"] == 50
+    assert s["p50_latency_s"] == pytest.approx(np.percentile(lat, 50))
+    assert s["p99_latency_s"] == pytest.approx(np.percentile(lat, 99))
+    assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+    assert s["gcell_updates_per_s"] > 0
+
+
+def test_tuner_picks_and_caches(tmp_path):
+    from paper_1008_2602_amd import tune
+    calls = []
+
+    def t(shape):
+        calls.append(shape)
+        return {(64, 8): 2.0, (64, 16): 1.5, (32, 8): 3.0}[shape]
+
+    path = str(tmp_path / "c.json")
+    best, tim = tune.tune("k", t, [(64, 8), (64, 16), (32, 8)], path)
+    assert best == (64, 16) and len(calls) == 3
+    best2, tim2 = tune.tune("k", t, [(64, 8), (64, 16), (32, 8)], path)
+    assert best2 == (64, 16) and len(calls) == 3 and tim2 == {}
+    best3, _ = tune.tune("k", t, [(64, 8), (32, 8)], path, refresh=True)
+    assert best3 == (64, 8)
