@@ -7,7 +7,19 @@ large-board workload: 1048 x 792 x 88 cells (1024 x 768 x 64 interior + a
 12-cell PML on every face), the running FP64 DFT of every probe at 256
 frequencies folded in once per timed call.  Prints one JSON line.
 
+Beside it, the same line carries
+  * "batched": 64 uneven board variants advanced together by fdtd_step_many
+    (one field launch per step over all boards), Gcell-updates/s and the HBM
+    fraction on algorithmic bytes;
+  * "served": seeded Poisson arrivals of board variants (5 % large 800x800x64
+    boards) at 0.7x the measured batched capacity, admitted by device footprint
+    into 85 % of free HBM, advanced in 500-step chunks, each finished solve
+    read back with its probe spectra; p50/p99 latency and throughput.  The step
+    count per solve is reduced (default 1000 instead of 8000) so the run stays
+    short; the number is stated in the output.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                  [--only single|batch|serve]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -77,42 +89,17 @@ def cpu_baseline(board, budget_s=20.0):
                       f"calibration steps ({dt:.1f} s; FP64, unified D/B storage)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--tile", default="")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one MI355X: this build has no multi-GPU path "
-              "(boards shard whole across GPUs by design; see DESIGN.md).", file=sys.stderr)
-        sys.exit(2)
-
+def run_single(F, torch, K, W, tile):
     import numpy as np
-    import torch
-
-    torch.cuda.set_device(0)
-    if args.copy_calibration:
-        copy_calibration()
-        return
-
     import boardgen
-    from paper_1008_2602_amd import fdtd as F
-
     board = boardgen.config3()
-    K, W = int(args.steps), int(args.warmup)
-    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else (64, 16)
     stream = torch.cuda.current_stream().cuda_stream
+    if tile is None:
+        from paper_1008_2602_amd import tune
+        tile = tune.tune_board(board)
     g, ids = F.grid_from_board(board, max_steps=W + K, hip_stream=stream, tile=tile)
-    info = F.fdtd_get_info(g)
     F.fdtd_step_n(g, W)
     F.fdtd_synchronize(g)
-
     F.fdtd_set_timing(g, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -125,47 +112,161 @@ def main():
     probe0 = F.fdtd_get_probe(g, ids[0], W + K)
     F.fdtd_destroy_grid(g)
     assert np.all(np.isfinite(probe0))
+    return board, tile, info, wall, kern_ms, launches
 
-    cells = board.cells
-    value = cells * K / wall / 1e9
-    per_launch_s = kern_ms / 1e3 / launches
-    achieved = info.step_bytes / per_launch_s / 1e9
-    traffic = measured_traffic()
-    out = {
-        "metric": "Gcell-updates/s + % HBM roofline (1 GPU); served solves p50/p99 latency",
-        "value": round(value, 3),
+
+def run_batch(F, torch, K, W):
+    """The 64-board variant batch, all boards advanced by K steps together."""
+    import boardgen
+    from paper_1008_2602_amd import tune
+    boards = boardgen.config4(steps=W + K)
+    tile = tune.tune_batch(boards)
+    handles = [F.grid_from_board(b, max_steps=W + K) for b in boards]
+    gs = [h for h, _ in handles]
+    F.fdtd_set_tile(gs[0], *tile)
+    F.fdtd_step_many(gs, [W] * len(gs))
+    F.fdtd_synchronize(gs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_many(gs, [K] * len(gs))
+    F.fdtd_synchronize(gs[0])
+    wall = time.perf_counter() - t0
+    step_bytes = sum(F.fdtd_get_info(g).step_bytes for g in gs)
+    for g in gs:
+        F.fdtd_destroy_grid(g)
+    cells = sum(b.cells for b in boards)
+    return {
+        "workload": f"{len(boards)} board variants (in-plane 100-600 cells, z 24-64, eps_r "
+                    f"3.5-4.8, 8-cell PML), {cells} cells in all, one launch per step",
+        "value": round(cells * K / wall / 1e9, 3),
         "unit": "Gcell-updates/s",
-        "n_gpus": 1,
         "steps": K,
-        "warmup": W,
         "ms_per_step": round(wall / K * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "large-board HBM stress: 1048x792x88 cells (1024x768x64 interior "
-                        "+ 12-cell UPML per face), eps_r 4.2 slab, two PEC power islands, "
-                        "8 Gaussian Jz sources, 64 probes, FP64 DFT at 256 frequencies",
-            "cells": cells,
-            "tile": f"{tile[0]}x{tile[1]}",
-            "dt_s": info.dt,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "field_step",
-            "algorithmic_bytes_per_launch": info.step_bytes,
-            "avg_launch_ms": round(per_launch_s * 1e3, 4),
-        },
+        "tile": f"{tile[0]}x{tile[1]}",
+        "hbm_frac_algorithmic": round(step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
+    }, cells / len(boards)
+
+
+def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
+    import numpy as np
+    import boardgen
+    from paper_1008_2602_amd.serve import GpuExecutor, Server, summarize
+    capacity = capacity_gcells * 1e9 / (mean_cells * steps)           # boards per second
+    rate = 0.7 * capacity
+    reqs = boardgen.config5(rate, n_requests=n_requests, steps=steps)
+    from paper_1008_2602_amd.serve import SolveRequest
+    requests = [SolveRequest(r.rid, r.arrival_s, r.board) for r in reqs]
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+
+    class FftExecutor(GpuExecutor):
+        def finish(self, handle, probe_ids, req):
+            n_fft = 1
+            while n_fft < req.n_steps:
+                n_fft *= 2
+            spectra = [self.F.fdtd_probe_fft(handle, p, n_fft) for p in probe_ids]
+            assert all(np.all(np.isfinite(x)) for x in spectra)
+            return super().finish(handle, probe_ids, req)
+
+    srv = Server(FftExecutor(allocator=F.TorchAllocator()), budget, chunk=500)
+    t0 = time.perf_counter()
+    res = srv.run(requests)
+    wall = time.perf_counter() - t0
+    s = summarize(res, wall_s=wall)
+    return {
+        "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x measured "
+                    f"capacity) of board variants, 5% 800x800x64, {steps} steps each, "
+                    f"500-step chunks, probe FFT per solve",
+        "p50_latency_s": round(s["p50_latency_s"], 4),
+        "p99_latency_s": round(s["p99_latency_s"], 4),
+        "solves_per_s": round(s["solves_per_s"], 4),
+        "gcell_updates_per_s": round(s["gcell_updates_per_s"], 3),
+        "completed": s["completed"],
+        "peak_resident": srv.peak_resident,
+        "budget_gb": round(budget / 1e9, 1),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(board)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--tile", default="", help="field-kernel tile, e.g. 64x16 (default: autotuned)")
+    ap.add_argument("--only", choices=["single", "batch", "serve"], default=None)
+    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path "
+              "(boards shard whole across GPUs by design; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_1008_2602_amd import fdtd as F
+
+    K, W = int(args.steps), int(args.warmup)
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+    out = {}
+    if args.only in (None, "single"):
+        board, tile, info, wall, kern_ms, launches = run_single(F, torch, K, W, tile)
+        cells = board.cells
+        per_launch_s = kern_ms / 1e3 / launches
+        achieved = info.step_bytes / per_launch_s / 1e9
+        out.update({
+            "metric": "Gcell-updates/s + % HBM roofline (1 GPU); served solves p50/p99 latency",
+            "value": round(cells * K / wall / 1e9, 3),
+            "unit": "Gcell-updates/s",
+            "n_gpus": 1,
+            "steps": K,
+            "warmup": W,
+            "ms_per_step": round(wall / K * 1e3, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {
+                "workload": "large-board HBM stress: 1048x792x88 cells (1024x768x64 interior "
+                            "+ 12-cell UPML per face), eps_r 4.2 slab, two PEC power islands, "
+                            "8 Gaussian Jz sources, 64 probes, FP64 DFT at 256 frequencies",
+                "cells": cells,
+                "tile": f"{tile[0]}x{tile[1]}",
+                "dt_s": info.dt,
+            },
+            "roofline": {
+                "bound": "hbm",
+                "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "field_step",
+                "algorithmic_bytes_per_launch": info.step_bytes,
+                "avg_launch_ms": round(per_launch_s * 1e3, 4),
+            },
+        })
+    if args.only in (None, "batch", "serve"):
+        batch, mean_cells = run_batch(F, torch, args.batch_steps, 5)
+        if args.only != "serve":
+            out["batched"] = batch
+        if args.only in (None, "serve"):
+            out["served"] = run_serve(F, torch, batch["value"], mean_cells,
+                                      args.serve_requests, args.serve_steps)
+    if args.only in (None, "single") and not args.no_cpu_baseline:
+        import boardgen
+        out["cpu_baseline"] = cpu_baseline(boardgen.config3())
     print(json.dumps(out), flush=True)
 
 

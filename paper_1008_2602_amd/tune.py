@@ -17,10 +17,12 @@ Shape = Tuple[int, int]
 
 
 def cache_path() -> str:
+    """FDTD_TUNE_CACHE, else the package's tile_cache.json (shipped with the
+    choices measured on MI355X for the standard workloads)."""
     p = os.environ.get("FDTD_TUNE_CACHE")
     if p:
         return p
-    return os.path.join(os.path.expanduser("~"), ".cache", "fdtd_mi355x", "tiles.json")
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_cache.json")
 
 
 def _load(path: str) -> Dict[str, list]:
