@@ -182,8 +182,11 @@ int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes);
 /* Information about the handle (valid at any time). */
 int fdtd_get_info(fdtd_grid* g, fdtd_info* out);
 
-/* Tile shape of the field kernel, (tile_x, tile_y) from fdtd_tile_shapes();
- * results do not depend on it (bitwise).  ESTATE after the first step. */
+/* Tile shape of the field kernel, (tile_x, tile_y) from fdtd_tile_shapes(): a
+ * block of tile_x*tile_y + 64 threads advances tile_x columns (aligned to 128
+ * bytes of the padded device rows) by tile_y-1 rows, recomputing H on one halo
+ * row and one halo column.  Results do not depend on it (bitwise).  May be
+ * changed between steps; EINVAL for an unsupported shape. */
 int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y);
 
 /* Supported tile shapes: writes up to `cap` pairs into xy (host, 2*cap ints) and

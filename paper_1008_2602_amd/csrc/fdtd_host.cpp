@@ -89,7 +89,9 @@ uint32_t fbits(float x)
 struct fdtd_grid {
     fdtd_grid_desc d{};
     double dt = 0.0;
-    int64_t nodes = 0;
+    int64_t nodes = 0;      // (nx+1)(ny+1)(nz+1) grid nodes
+    int64_t pitch = 0;      // device row pitch in nodes: nx+1 rounded up to 32
+    int64_t dnodes = 0;     // device nodes per field array: pitch (ny+1)(nz+1)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -196,6 +198,28 @@ hipError_t copy_sync(fdtd_grid* g, void* dst, const void* src, size_t bytes, hip
     return hipStreamSynchronize(g->stream);
 }
 
+// Copy one field array between the packed host layout ((nx+1) nodes per row)
+// and the padded device layout (pitch nodes per row).
+hipError_t copy_field_sync(fdtd_grid* g, void* dst, const void* src, hipMemcpyKind kind)
+{
+    const size_t row = (size_t)(g->d.nx + 1) * 4, prow = (size_t)g->pitch * 4;
+    const size_t rows = (size_t)(g->d.ny + 1) * (g->d.nz + 1);
+    const bool to_dev = kind == hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpy2DAsync(dst, to_dev ? prow : row, src, to_dev ? row : prow, row, rows,
+                                    kind, g->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(g->stream);
+}
+
+int64_t row_pitch(int nx) { return ((int64_t)nx + 1 + 31) / 32 * 32; }
+
+// Tiles of a TX x TY block: TX aligned columns each, TY-1 rows each (one halo row)
+void tile_counts(int nx, int ny, int tx, int ty, int* cx, int* cy)
+{
+    *cx = (nx + 1 + tx - 1) / tx;
+    *cy = (ny + 1 + ty - 2) / (ty - 1);
+}
+
 void dev_free_all(fdtd_grid* g)
 {
     for (void* p : g->allocs) {
@@ -264,9 +288,16 @@ int check_grid(fdtd_grid* g)
     return FDTD_OK;
 }
 
+// index into the packed host arrays (PEC mask, field images)
 int64_t node_index(const fdtd_grid* g, int i, int j, int k)
 {
     return (int64_t)i + (int64_t)(g->d.nx + 1) * ((int64_t)j + (int64_t)(g->d.ny + 1) * k);
+}
+
+// index into the padded device arrays
+int64_t dev_index(const fdtd_grid* g, int i, int j, int k)
+{
+    return (int64_t)i + g->pitch * ((int64_t)j + (int64_t)(g->d.ny + 1) * k);
 }
 
 // Count the bytes one field step must move with this layout: E and H read and
@@ -304,25 +335,25 @@ int finalize(fdtd_grid* g)
     const fdtd_grid_desc& d = g->d;
     if (!g->have_materials) return fail(FDTD_ESTATE, "fdtd_set_materials was never called");
     const int nx = d.nx, ny = d.ny, nz = d.nz;
-    const int64_t N = g->nodes;
+    const int64_t N = g->nodes, ND = g->dnodes;
     // sources and probes
     for (const SourceH& s : g->sources) {
         if (g->pec[node_index(g, s.i, s.j, s.k)] & 4)
             return fail(FDTD_EINVAL, "source at (%d,%d,%d) sits on a PEC edge", s.i, s.j, s.k);
     }
     std::vector<int32_t> src_node, prb_node;
-    for (const SourceH& s : g->sources) src_node.push_back((int32_t)node_index(g, s.i, s.j, s.k));
-    for (const auto& p : g->probes) prb_node.push_back((int32_t)node_index(g, p[0], p[1], p[2]));
+    for (const SourceH& s : g->sources) src_node.push_back((int32_t)dev_index(g, s.i, s.j, s.k));
+    for (const auto& p : g->probes) prb_node.push_back((int32_t)dev_index(g, p[0], p[1], p[2]));
     std::vector<uint8_t> is_src(0), is_prb(0);
 
     // per-node classes: edge permittivity (mean of the touching cells), stepped
     // components (not on the outer wall, not PEC), source/probe marks
     std::unordered_map<ClassKey, uint32_t, ClassKeyHash> map;
     std::vector<ClassEntry> table;
-    std::vector<uint16_t> ids((size_t)N);
+    std::vector<uint16_t> ids((size_t)ND, 0);   // padding columns keep class 0, never read
     std::vector<uint8_t> mark((size_t)N, 0);
-    for (int32_t v : src_node) mark[v] |= 1;
-    for (int32_t v : prb_node) mark[v] |= 2;
+    for (const SourceH& s : g->sources) mark[node_index(g, s.i, s.j, s.k)] |= 1;
+    for (const auto& p : g->probes) mark[node_index(g, p[0], p[1], p[2])] |= 2;
     const float* er = g->eps.data();
     auto cell = [&](int i, int j, int k) -> double {
         return (double)er[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
@@ -373,21 +404,22 @@ int finalize(fdtd_grid* g)
                     last = key;
                     last_id = id;
                 }
-                ids[(size_t)n] = (uint16_t)id;
+                ids[(size_t)dev_index(g, i, j, k)] = (uint16_t)id;
             }
     g->n_classes = (int)table.size();
     g->wide = table.size() > 256;
     hipStream_t st = g->stream;
     if (g->wide) {
-        g->cls = dev_alloc(g, (size_t)N * 2);
+        g->cls = dev_alloc(g, (size_t)ND * 2);
         if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
-        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids.data(), (size_t)N * 2, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids.data(), (size_t)ND * 2, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipStreamSynchronize(st));
     } else {
-        std::vector<uint8_t> ids8((size_t)N);
-        for (size_t t = 0; t < (size_t)N; ++t) ids8[t] = (uint8_t)ids[t];
-        g->cls = dev_alloc(g, (size_t)N);
+        std::vector<uint8_t> ids8((size_t)ND);
+        for (size_t t = 0; t < (size_t)ND; ++t) ids8[t] = (uint8_t)ids[t];
+        g->cls = dev_alloc(g, (size_t)ND);
         if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
-        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids8.data(), (size_t)N, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids8.data(), (size_t)ND, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
     }
     g->ctab = (ClassEntry*)dev_alloc(g, table.size() * sizeof(ClassEntry));
@@ -448,6 +480,7 @@ int finalize(fdtd_grid* g)
     b.nx = nx;
     b.ny = ny;
     b.nz = nz;
+    b.pitch = (int32_t)g->pitch;
     b.nsrc = ns;
     b.nprb = np;
     b.nclass = (int32_t)table.size();
@@ -504,7 +537,11 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     fdtd_grid_desc d = *desc;
     if (d.nx < 2 || d.ny < 2 || d.nz < 2) return fail(FDTD_EINVAL, "nx, ny, nz must be >= 2");
     const int64_t nodes = (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
-    if (nodes >= (int64_t(1) << 31)) return fail(FDTD_EINVAL, "node count must be below 2^31");
+    const int64_t pitch = row_pitch(d.nx);
+    const int64_t dnodes = pitch * (d.ny + 1) * (d.nz + 1);
+    if (dnodes + kGuard >= (int64_t(1) << 31))
+        return fail(FDTD_EINVAL, "padded node count (row pitch %lld) must be below 2^31",
+                    (long long)pitch);
     if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !std::isfinite(d.dx) ||
         !std::isfinite(d.dy) || !std::isfinite(d.dz))
         return fail(FDTD_EINVAL, "cell sizes must be positive and finite");
@@ -537,6 +574,8 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     g->d = d;
     g->dt = dt;
     g->nodes = nodes;
+    g->pitch = pitch;
+    g->dnodes = dnodes;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return fail(FDTD_EDEVICE, "no HIP device");
@@ -557,7 +596,7 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     };
     // every field array carries kGuard zero words past its last node: the kernels
     // read out-of-range neighbours from there and never write them
-    const int64_t padded = nodes + kGuard;
+    const int64_t padded = dnodes + kGuard;
     for (int p = 0; p < 2; ++p)
         for (int c = 0; c < 9; ++c)
             if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
@@ -655,8 +694,7 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
 static int upload_tiles(fdtd_grid* g)
 {
     BoardDev& b = g->board_host;
-    b.tiles_x = (g->d.nx + 1 + g->tile_x - 2) / (g->tile_x - 1);
-    b.tiles_y = (g->d.ny + 1 + g->tile_y - 2) / (g->tile_y - 1);
+    tile_counts(g->d.nx, g->d.ny, g->tile_x, g->tile_y, &b.tiles_x, &b.tiles_y);
     const int nt = b.tiles_x * b.tiles_y;
     std::vector<TileRef> tl((size_t)nt);
     for (int ty = 0; ty < b.tiles_y; ++ty)
@@ -814,8 +852,8 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         boards[b] = g->board_host;
         nn[b] = n[order[b]];
         max_n = std::max(max_n, nn[b]);
-        const int tiles_x = (g->d.nx + 1 + tx - 2) / (tx - 1);
-        const int tiles_y = (g->d.ny + 1 + ty - 2) / (ty - 1);
+        int tiles_x, tiles_y;
+        tile_counts(g->d.nx, g->d.ny, tx, ty, &tiles_x, &tiles_y);
         for (int y = 0; y < tiles_y; ++y)
             for (int x = 0; x < tiles_x; ++x) tiles.push_back(TileRef{b, x, y});
         tiles_upto[b] = (int64_t)tiles.size();
@@ -884,7 +922,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
         n_probes < 0 || n_freqs < 0)
         return fail(FDTD_EINVAL, "bad descriptor or counts");
     auto r = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    const int64_t nodes = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    const int64_t nodes = row_pitch(d->nx) * (d->ny + 1) * (d->nz + 1);      // padded rows
     int64_t t = 21 * r((nodes + kGuard) * 4);                                   // fields
     t += r(2 * nodes);                                                          // class map (upper bound)
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
@@ -893,7 +931,8 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     t += r(4 * (int64_t)n_sources) + r(4 * (int64_t)n_sources * d->max_steps);   // sources
     t += r(4 * (int64_t)n_probes) + r(4 * (int64_t)n_probes * d->max_steps);     // probes
     t += r(8 * (int64_t)n_freqs) + 2 * r(8 * (int64_t)n_probes * n_freqs);       // DFT
-    t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * (nodes / 64 + 64)); // small buffers
+    const int64_t max_tiles = ((d->nx + 64) / 64) * ((d->ny + 3) / 3);         // 64 x 4, the most tiles
+    t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * max_tiles);        // small buffers
     return t;
 }
 
@@ -992,7 +1031,7 @@ int fdtd_get_field(fdtd_grid* g, int comp, float* out)
     if (comp < 0 || comp > FDTD_BZ || !out) return fail(FDTD_EINVAL, "bad component or output");
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     std::vector<float> h((size_t)g->nodes);
-    HIP_OR_FAIL(copy_sync(g, h.data(), comp_ptr(g, comp), h.size() * 4, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(copy_field_sync(g, h.data(), comp_ptr(g, comp), hipMemcpyDeviceToHost));
     const double s = field_scale(comp);
     for (size_t t = 0; t < h.size(); ++t) out[t] = (float)((double)h[t] * s);
     return FDTD_OK;
@@ -1022,7 +1061,7 @@ int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
                 h[(size_t)n] = keep ? (float)((double)in[n] * s) : 0.0f;
             }
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
-    HIP_OR_FAIL(copy_sync(g, comp_ptr(g, comp), h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(copy_field_sync(g, comp_ptr(g, comp), h.data(), hipMemcpyHostToDevice));
     return FDTD_OK;
 }
 
@@ -1045,7 +1084,7 @@ int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes)
     memcpy(p, hdr, 64);
     p += 64;
     for (int c = 0; c < 12; ++c) {
-        HIP_OR_FAIL(copy_sync(g, p, comp_ptr(g, c), g->nodes * 4, hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(copy_field_sync(g, p, comp_ptr(g, c), hipMemcpyDeviceToHost));
         p += g->nodes * 4;
     }
     const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();
@@ -1078,7 +1117,7 @@ int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes)
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     g->step = hdr[4];
     for (int c = 0; c < 12; ++c) {
-        HIP_OR_FAIL(copy_sync(g, comp_ptr(g, c), p, g->nodes * 4, hipMemcpyHostToDevice));
+        HIP_OR_FAIL(copy_field_sync(g, comp_ptr(g, c), p, hipMemcpyHostToDevice));
         p += g->nodes * 4;
     }
     const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();

@@ -57,6 +57,7 @@ struct BoardDev {
     int64_t* step;               // device step counter (completed steps)
     int32_t* bad;                // watchdog flag
     int32_t nx, ny, nz;
+    int32_t pitch;               // row pitch in nodes: nx+1 rounded up to 32 (128 bytes)
     int32_t nsrc, nprb;
     int32_t nclass;
     int32_t pml[6];

@@ -2,14 +2,19 @@
 //
 // field_step: one full leapfrog step (Model section: B->H then D->E, Eqs. 1-4)
 // for one tile of columns of one board, fused in a single pass.  A block owns a
-// (TX-1) x (TY-1) patch of (i, j) columns and marches along z.  Per z plane it
-//   1. stages E^n of planes k+1 (Ex, Ey) and k (Ez) for (TX+1) x (TY+1) columns
+// TX x (TY-1) patch of (i, j) columns, starting on a 128-byte boundary of the
+// padded rows, and marches along z.  Its TY*TX/64 row waves cover the patch plus
+// the row below it (a halo owned by the neighbouring tile); one more wave
+// stages the extra row and columns and recomputes the halo column left of the
+// patch.  Per z plane the block
+//   1. stages E^n of planes k+1 (Ex, Ey) and k (Ez) for (TX+2) x (TY+1) columns
 //      in LDS (Ex, Ey of plane k are kept from the previous plane),
-//   2. computes B/H^{n+1/2} of plane k for all TX x TY columns (the first column
-//      and row are a halo owned by the neighbouring tiles, recomputed here so
-//      that no second pass over H is needed),
+//   2. computes B/H^{n+1/2} of plane k for the patch, the halo row and the halo
+//      column, so that no second pass over H is needed,
 //   3. computes D/E^{n+1} of plane k for the owned columns from the new H of
 //      planes k (LDS) and k-1 (registers).
+// Staging loads run two planes ahead and column operands one plane ahead; the
+// plane loop is unrolled by two so no register in flight is ever moved.
 // State is ping-ponged (E, H, B read from one copy, written to the other) so
 // halo recomputation never sees a neighbour's already-updated values; D is only
 // read by its owner and is updated in place.  D and B are stored and moved only
@@ -30,17 +35,6 @@ typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(4))) const float kfloat;  // uniform, scalar loads
 
-// Branch-free staging load: out-of-range nodes read the guard word (index
-// `guard`, one past the last node, kept at zero) instead of selecting after
-// the load, so the load's latency is not exposed where it is issued.
-__device__ __forceinline__ float ld_or0(cgfloat* __restrict__ p, int i, int j, int k, int nx,
-                                        int ny, int nz, int sy, int sz, int guard)
-{
-    const bool ok = ((unsigned)i <= (unsigned)nx) & ((unsigned)j <= (unsigned)ny) &
-                    ((unsigned)k <= (unsigned)nz);
-    return p[ok ? i + j * sy + k * sz : guard];
-}
-
 // Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks
 // a contiguous run of the tile list (neighbouring tiles share halos in its L2).
 __device__ __forceinline__ int xcd_tile(int b, int nb)
@@ -51,16 +45,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 }
 
 template <int TX, int TY, typename CT>
-__global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict__ boards,
-                                                     const TileRef* __restrict__ tiles,
-                                                     int rel)
+__global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __restrict__ boards,
+                                                          const TileRef* __restrict__ tiles,
+                                                          int rel)
 {
-    __shared__ float sEx[2][TY + 1][TX + 1];
-    __shared__ float sEy[2][TY + 1][TX + 1];
-    __shared__ float sEz[TY + 1][TX + 1];
-    __shared__ float sHx[TY][TX];
-    __shared__ float sHy[TY][TX];
-    __shared__ float sHz[TY][TX];
+    static_assert(TX % 64 == 0 && TY + 1 <= 32 && TX * TY + 64 <= 1024, "tile shape");
+    // LDS staging: columns i0-1 .. i0+TX (index c = i - i0 + 1), rows j0-1 .. j0-1+TY
+    __shared__ float sEx[2][TY + 1][TX + 2];
+    __shared__ float sEy[2][TY + 1][TX + 2];
+    __shared__ float sEz[TY + 1][TX + 2];
+    // new H of the plane: column 0 is the halo column i0-1 (Hy, Hz only)
+    __shared__ float sHx[TY][TX + 1];
+    __shared__ float sHy[TY][TX + 1];
+    __shared__ float sHz[TY][TX + 1];
     // class table in LDS when the class index is one byte (<= 256 classes)
     constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
     __shared__ ClassEntry sTab[kLdsClasses];
@@ -68,13 +65,18 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const BoardDev& B = boards[t.board];
     const int nx = B.nx, ny = B.ny, nz = B.nz;
-    const int sy = nx + 1, sz = (nx + 1) * (ny + 1), guard = sz * (nz + 1);
+    const int sy = B.pitch, sz = B.pitch * (ny + 1), guard = sz * (nz + 1);
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    const int ox = t.tx * (TX - 1) - 1, oy = t.ty * (TY - 1) - 1;
-    const int i = ox + tx, j = oy + ty;
-    const bool col_ok = (i >= 0) && (i <= nx) && (j >= 0) && (j <= ny);
-    const bool own = col_ok && tx > 0 && ty > 0;
+    // waves 0 .. TY*TX/64-1 own whole rows; the last wave handles the halo column
+    // and the staging of the extra row and columns
+    const bool main_wave = __builtin_amdgcn_readfirstlane(tid) < TX * TY;
+    const int tx = tid % TX;
+    const int ty = __builtin_amdgcn_readfirstlane(tid / TX);   // == TY in the extra wave
+    const int lane = tid & 63;
+    const int i0 = t.tx * TX, j0 = t.ty * (TY - 1);
+    const int i = i0 + tx, j = j0 - 1 + ty;
+    const bool col_ok = main_wave && (i <= nx) && (j >= 0) && (j <= ny);
+    const bool own = col_ok && ty > 0;
     const int64_t step = *B.step + rel;
     const int par = (int)(step & 1);
     cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
@@ -104,61 +106,18 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
         (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
     const int pml_zlo = B.pml[4], pml_zhi = B.pml[5];
-
-    // PML membership of this column (x, y); per plane for z: where D/B are kept
-    const bool px = (i < B.pml[0]) || (B.pml[1] > 0 && i >= nx - B.pml[1]);
-    const bool py = (j < B.pml[2]) || (B.pml[3] > 0 && j >= ny - B.pml[3]);
+    auto in_px = [&](int ii) { return (ii < B.pml[0]) || (B.pml[1] > 0 && ii >= nx - B.pml[1]); };
+    auto in_py = [&](int jj) { return (jj < B.pml[2]) || (B.pml[3] > 0 && jj >= ny - B.pml[3]); };
     auto in_pz = [&](int k) { return (k < pml_zlo) || (pml_zhi > 0 && k >= nz - pml_zhi); };
-
-    // per-axis coefficients of this column (node n / half node h)
-    const int ic = min(max(i, 0), nx), jc = min(max(j, 0), ny);
     cgfloat* __restrict__ cx = (cgfloat*)B.coef[0];
     cgfloat* __restrict__ cy = (cgfloat*)B.coef[1];
     kfloat* __restrict__ cz = (kfloat*)B.coef[2];
     const int nx1 = nx + 1, ny1 = ny + 1, nz1 = nz + 1;
-#define CX(kind, half) cx[((kind) * 2 + (half)) * nx1 + ic]
-#define CY(kind, half) cy[((kind) * 2 + (half)) * ny1 + jc]
-    const float x_cam1_n = CX(kCam1, 0), x_ca_n = CX(kCa, 0), x_rp_n = CX(kRp, 0),
-                x_ph_n = CX(kPh, 0), x_q_n = CX(kQ, 0);
-    const float x_cam1_h = CX(kCam1, 1), x_ca_h = CX(kCa, 1), x_rp_h = CX(kRp, 1),
-                x_ph_h = CX(kPh, 1), x_q_h = CX(kQ, 1);
-    const float y_cam1_n = CY(kCam1, 0), y_ca_n = CY(kCa, 0), y_rp_n = CY(kRp, 0),
-                y_ph_n = CY(kPh, 0), y_q_n = CY(kQ, 0);
-    const float y_cam1_h = CY(kCam1, 1), y_ca_h = CY(kCa, 1), y_rp_h = CY(kRp, 1),
-                y_ph_h = CY(kPh, 1), y_q_h = CY(kQ, 1);
-#undef CX
-#undef CY
+    auto CXf = [&](int kind, int half, int ii) { return cx[(kind * 2 + half) * nx1 + min(max(ii, 0), nx)]; };
+    auto CYf = [&](int kind, int half, int jj) { return cy[(kind * 2 + half) * ny1 + min(max(jj, 0), ny)]; };
 
-    // extra staging element of this thread: column a = TX (rows 0..TY) or row
-    // b = TY (columns 0..TX-1); the rest of the block stages nothing extra
-    const bool has_extra = tid < TY + 1 + TX;
-    const int ea = tid < TY + 1 ? TX : tid - (TY + 1);
-    const int eb = tid < TY + 1 ? tid : TY;
-    const int ei = ox + ea, ej = oy + eb;
-
-    // prologue: Ex, Ey of plane 0 into LDS slot 0; prefetch plane 0's operands
-    sEx[0][ty][tx] = ld_or0(gEx, i, j, 0, nx, ny, nz, sy, sz, guard);
-    sEy[0][ty][tx] = ld_or0(gEy, i, j, 0, nx, ny, nz, sy, sz, guard);
-    if (has_extra) {
-        sEx[0][eb][ea] = ld_or0(gEx, ei, ej, 0, nx, ny, nz, sy, sz, guard);
-        sEy[0][eb][ea] = ld_or0(gEy, ei, ej, 0, nx, ny, nz, sy, sz, guard);
-    }
-    // prefetched operands of the plane about to be computed
-    float pEx = ld_or0(gEx, i, j, 1, nx, ny, nz, sy, sz, guard);
-    float pEy = ld_or0(gEy, i, j, 1, nx, ny, nz, sy, sz, guard);
-    float pEz = ld_or0(gEz, i, j, 0, nx, ny, nz, sy, sz, guard);
-    float qEx = 0.f, qEy = 0.f, qEz = 0.f;
-    if (has_extra) {
-        qEx = ld_or0(gEx, ei, ej, 1, nx, ny, nz, sy, sz, guard);
-        qEy = ld_or0(gEy, ei, ej, 1, nx, ny, nz, sy, sz, guard);
-        qEz = ld_or0(gEz, ei, ej, 0, nx, ny, nz, sy, sz, guard);
-    }
-    const int node0 = i + j * sy;
-    float pHx = 0.f, pHy = 0.f, pHz = 0.f, pBx = 0.f, pBy = 0.f, pBz = 0.f;
-    float pDx = 0.f, pDy = 0.f, pDz = 0.f;
-    CT pC = 0;
     if (sizeof(CT) == 1) {
-        for (int e = tid; e < kLdsClasses; e += TX * TY) {
+        for (int e = tid; e < kLdsClasses; e += TX * TY + 64) {
             const int c = min(e, B.nclass - 1);
             sTab[e].inv_x = ctab[c].inv_x;
             sTab[e].inv_y = ctab[c].inv_y;
@@ -166,166 +125,271 @@ __global__ __launch_bounds__(TX* TY) void field_step(const BoardDev* __restrict_
             sTab[e].flags = ctab[c].flags;
         }
     }
-    {
-        const bool pz0 = in_pz(0);
-        if (col_ok) {
-            pHx = gHx[node0];
-            pHy = gHy[node0];
-            pHz = gHz[node0];
-            if (px || py) pBx = gBx[node0];
-            if (py || pz0) pBy = gBy[node0];
-            if (pz0 || px) pBz = gBz[node0];
-        }
-        if (own) {
-            pC = cls[node0];
-            if (px || py) pDx = Dx[node0];
-            if (py || pz0) pDy = Dy[node0];
-            if (pz0 || px) pDz = Dz[node0];
-        }
-    }
-    float hx_prev = 0.0f, hy_prev = 0.0f;
-    const int64_t ms = B.max_steps;
+    auto node_at = [&](int ii, int jj, int k) {
+        const bool ok = ((unsigned)ii <= (unsigned)nx) & ((unsigned)jj <= (unsigned)ny) &
+                        ((unsigned)k <= (unsigned)nz);
+        return ok ? ii + jj * sy + k * sz : guard;
+    };
 
-    for (int k = 0; k <= nz; ++k) {
-        const int cur = k & 1, nxt = cur ^ 1;
-        const bool pz = in_pz(k);
-        const bool nbx = px || py, nby = py || pz, nbz = pz || px;
-        const int node = node0 + k * sz;
-
-        // ---- stage this plane's prefetched E into LDS, take own operands ----
-        sEx[nxt][ty][tx] = pEx;
-        sEy[nxt][ty][tx] = pEy;
-        sEz[ty][tx] = pEz;
-        if (has_extra) {
-            sEx[nxt][eb][ea] = qEx;
-            sEy[nxt][eb][ea] = qEy;
-            sEz[eb][ea] = qEz;
-        }
-        const float hxo = pHx, hyo = pHy, hzo = pHz, bxo = pBx, byo = pBy, bzo = pBz;
-        const float dxo = pDx, dyo = pDy, dzo = pDz;
-        const CT c = pC;
-
-        // ---- prefetch the next plane's operands (in flight during this plane) ----
-        if (k < nz) {
-            const int k1 = k + 1;
-            const bool pz1 = in_pz(k1);
-            pEx = ld_or0(gEx, i, j, k1 + 1, nx, ny, nz, sy, sz, guard);
-            pEy = ld_or0(gEy, i, j, k1 + 1, nx, ny, nz, sy, sz, guard);
-            pEz = ld_or0(gEz, i, j, k1, nx, ny, nz, sy, sz, guard);
-            if (has_extra) {
-                qEx = ld_or0(gEx, ei, ej, k1 + 1, nx, ny, nz, sy, sz, guard);
-                qEy = ld_or0(gEy, ei, ej, k1 + 1, nx, ny, nz, sy, sz, guard);
-                qEz = ld_or0(gEz, ei, ej, k1, nx, ny, nz, sy, sz, guard);
+    if (main_wave) {
+        // ------------------------------------------------------------ owned rows
+        const bool px = in_px(i), py = in_py(j);
+        const float x_cam1_n = CXf(kCam1, 0, i), x_ca_n = CXf(kCa, 0, i), x_rp_n = CXf(kRp, 0, i),
+                    x_ph_n = CXf(kPh, 0, i), x_q_n = CXf(kQ, 0, i);
+        const float x_cam1_h = CXf(kCam1, 1, i), x_ca_h = CXf(kCa, 1, i), x_rp_h = CXf(kRp, 1, i),
+                    x_ph_h = CXf(kPh, 1, i), x_q_h = CXf(kQ, 1, i);
+        const float y_cam1_n = CYf(kCam1, 0, j), y_ca_n = CYf(kCa, 0, j), y_rp_n = CYf(kRp, 0, j),
+                    y_ph_n = CYf(kPh, 0, j), y_q_n = CYf(kQ, 0, j);
+        const float y_cam1_h = CYf(kCam1, 1, j), y_ca_h = CYf(kCa, 1, j), y_rp_h = CYf(kRp, 1, j),
+                    y_ph_h = CYf(kPh, 1, j), y_q_h = CYf(kQ, 1, j);
+        const int c = tx + 1;
+        const int node0 = i + j * sy;
+        struct Stage { float ex, ey, ez; };
+        struct Col { float hx, hy, hz, bx, by, bz, dx, dy, dz; CT c; };
+        auto load_stage = [&](int p) {
+            Stage s;
+            s.ex = gEx[node_at(i, j, p + 1)];
+            s.ey = gEy[node_at(i, j, p + 1)];
+            s.ez = gEz[node_at(i, j, p)];
+            return s;
+        };
+        auto load_col = [&](int p, Col& o) {
+            o = Col{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
+            if (col_ok && p <= nz) {
+                const int n = node0 + p * sz;
+                const bool pz = in_pz(p);
+                o.hx = gHx[n];
+                o.hy = gHy[n];
+                o.hz = gHz[n];
+                if (px || py) o.bx = gBx[n];
+                if (py || pz) o.by = gBy[n];
+                if (pz || px) o.bz = gBz[n];
+                if (own) {
+                    o.c = cls[n];
+                    if (px || py) o.dx = Dx[n];
+                    if (py || pz) o.dy = Dy[n];
+                    if (pz || px) o.dz = Dz[n];
+                }
             }
-            const int n1 = node + sz;
+        };
+        sEx[0][ty][c] = gEx[node_at(i, j, 0)];
+        sEy[0][ty][c] = gEy[node_at(i, j, 0)];
+        Stage s0 = load_stage(0), s1 = load_stage(1);
+        Col cA, cB;
+        load_col(0, cA);
+        float hx_prev = 0.0f, hy_prev = 0.0f;
+        bool bad = false;
+        const int64_t ms = B.max_steps;
+
+        auto plane_step = [&](int k, Stage& st, const Col& o, Col& nxt_col) {
+            const int cur = k & 1, nxt = cur ^ 1;
+            const bool pz = in_pz(k);
+            const bool nbx = px || py, nby = py || pz, nbz = pz || px;
+            const int node = node0 + k * sz;
+            sEx[nxt][ty][c] = st.ex;
+            sEy[nxt][ty][c] = st.ey;
+            sEz[ty][c] = st.ez;
+            st = load_stage(k + 2);
+            load_col(k + 1, nxt_col);
+            kfloat* czk = cz + k;
+            const float z_cam1_n = czk[(kCam1 * 2 + 0) * nz1], z_ca_n = czk[(kCa * 2 + 0) * nz1],
+                        z_rp_n = czk[(kRp * 2 + 0) * nz1], z_ph_n = czk[(kPh * 2 + 0) * nz1],
+                        z_q_n = czk[(kQ * 2 + 0) * nz1];
+            const float z_cam1_h = czk[(kCam1 * 2 + 1) * nz1], z_ca_h = czk[(kCa * 2 + 1) * nz1],
+                        z_rp_h = czk[(kRp * 2 + 1) * nz1], z_ph_h = czk[(kPh * 2 + 1) * nz1],
+                        z_q_h = czk[(kQ * 2 + 1) * nz1];
+            __syncthreads();
+
+            // ---- B then H of plane k (own columns; row 0 is the y halo) ----
+            float hxn = 0.f, hyn = 0.f, hzn = 0.f;
+            const float exo = sEx[cur][ty][c], eyo = sEy[cur][ty][c], ezo = sEz[ty][c];
             if (col_ok) {
-                pHx = gHx[n1];
-                pHy = gHy[n1];
-                pHz = gHz[n1];
-                pBx = (px || py) ? gBx[n1] : 0.f;
-                pBy = (py || pz1) ? gBy[n1] : 0.f;
-                pBz = (pz1 || px) ? gBz[n1] : 0.f;
+                // Hx(i, j+1/2, k+1/2): Bx uses y at j+1/2; Hx uses z at k+1/2, x at i
+                const float cxe = (sEz[ty + 1][c] - ezo) * crdy - (sEy[nxt][ty][c] - eyo) * crdz;
+                const float dbx = fmaf(y_cam1_h, o.bx, -y_rp_h * cxe);
+                hxn = fmaf(z_ca_h, o.hx, z_rp_h * fmaf(x_ph_n, dbx, x_q_n * o.bx));
+                // Hy(i+1/2, j, k+1/2): By uses z at k+1/2; Hy uses x at i+1/2, y at j
+                const float cye = (sEx[nxt][ty][c] - exo) * crdz - (sEz[ty][c + 1] - ezo) * crdx;
+                const float dby = fmaf(z_cam1_h, o.by, -z_rp_h * cye);
+                hyn = fmaf(x_ca_h, o.hy, x_rp_h * fmaf(y_ph_n, dby, y_q_n * o.by));
+                // Hz(i+1/2, j+1/2, k): Bz uses x at i+1/2; Hz uses y at j+1/2, z at k
+                const float cze = (sEy[cur][ty][c + 1] - eyo) * crdx - (sEx[cur][ty + 1][c] - exo) * crdy;
+                const float dbz = fmaf(x_cam1_h, o.bz, -x_rp_h * cze);
+                hzn = fmaf(y_ca_h, o.hz, y_rp_h * fmaf(z_ph_n, dbz, z_q_n * o.bz));
+                if (own) {
+                    dHx[node] = hxn;
+                    dHy[node] = hyn;
+                    dHz[node] = hzn;
+                    if (nbx) dBx[node] = o.bx + dbx;
+                    if (nby) dBy[node] = o.by + dby;
+                    if (nbz) dBz[node] = o.bz + dbz;
+                }
             }
-            if (own) {
-                pC = cls[n1];
-                pDx = (px || py) ? Dx[n1] : 0.f;
-                pDy = (py || pz1) ? Dy[n1] : 0.f;
-                pDz = (pz1 || px) ? Dz[n1] : 0.f;
-            }
-        }
-        // z coefficients of this plane (uniform over the block)
-        kfloat* czk = cz + k;
-        const float z_cam1_n = czk[(kCam1 * 2 + 0) * nz1], z_ca_n = czk[(kCa * 2 + 0) * nz1],
-                    z_rp_n = czk[(kRp * 2 + 0) * nz1], z_ph_n = czk[(kPh * 2 + 0) * nz1],
-                    z_q_n = czk[(kQ * 2 + 0) * nz1];
-        const float z_cam1_h = czk[(kCam1 * 2 + 1) * nz1], z_ca_h = czk[(kCa * 2 + 1) * nz1],
-                    z_rp_h = czk[(kRp * 2 + 1) * nz1], z_ph_h = czk[(kPh * 2 + 1) * nz1],
-                    z_q_h = czk[(kQ * 2 + 1) * nz1];
-        __syncthreads();
+            sHx[ty][c] = hxn;
+            sHy[ty][c] = hyn;
+            sHz[ty][c] = hzn;
+            __syncthreads();
 
-        // ---- B then H of plane k (own + halo columns) ----
-        float hxn = 0.f, hyn = 0.f, hzn = 0.f;
-        const float exo = sEx[cur][ty][tx], eyo = sEy[cur][ty][tx], ezo = sEz[ty][tx];
-        if (col_ok) {
-            // Hx(i, j+1/2, k+1/2): Bx uses y at j+1/2; Hx uses z at k+1/2, x at i
-            const float cxe = (sEz[ty + 1][tx] - ezo) * crdy - (sEy[nxt][ty][tx] - eyo) * crdz;
-            const float dbx = fmaf(y_cam1_h, bxo, -y_rp_h * cxe);
-            hxn = fmaf(z_ca_h, hxo, z_rp_h * fmaf(x_ph_n, dbx, x_q_n * bxo));
-            // Hy(i+1/2, j, k+1/2): By uses z at k+1/2; Hy uses x at i+1/2, y at j
-            const float cye = (sEx[nxt][ty][tx] - exo) * crdz - (sEz[ty][tx + 1] - ezo) * crdx;
-            const float dby = fmaf(z_cam1_h, byo, -z_rp_h * cye);
-            hyn = fmaf(x_ca_h, hyo, x_rp_h * fmaf(y_ph_n, dby, y_q_n * byo));
-            // Hz(i+1/2, j+1/2, k): Bz uses x at i+1/2; Hz uses y at j+1/2, z at k
-            const float cze =
-                (sEy[cur][ty][tx + 1] - eyo) * crdx - (sEx[cur][ty + 1][tx] - exo) * crdy;
-            const float dbz = fmaf(x_cam1_h, bzo, -x_rp_h * cze);
-            hzn = fmaf(y_ca_h, hzo, y_rp_h * fmaf(z_ph_n, dbz, z_q_n * bzo));
+            // ---- D then E of plane k (own columns) ----
             if (own) {
-                dHx[node] = hxn;
-                dHy[node] = hyn;
-                dHz[node] = hzn;
-                if (nbx) dBx[node] = bxo + dbx;
-                if (nby) dBy[node] = byo + dby;
-                if (nbz) dBz[node] = bzo + dbz;
+                ClassEntry ce;
+                if (sizeof(CT) == 1) {
+                    ce = sTab[o.c];
+                } else {
+                    ce.inv_x = ctab[o.c].inv_x;
+                    ce.inv_y = ctab[o.c].inv_y;
+                    ce.inv_z = ctab[o.c].inv_z;
+                    ce.flags = ctab[o.c].flags;
+                }
+                // Ex(i+1/2, j, k): Dx uses y at j; Ex uses z at k, x at i+1/2
+                const float chx = (hzn - sHz[ty - 1][c]) * crdy - (hyn - hy_prev) * crdz;
+                const float ddx = fmaf(y_cam1_n, o.dx, y_rp_n * chx);
+                float exn = fmaf(z_ca_n, exo, z_rp_n * (ce.inv_x * fmaf(x_ph_h, ddx, x_q_h * o.dx)));
+                // Ey(i, j+1/2, k): Dy uses z at k; Ey uses x at i, y at j+1/2
+                const float chy = (hxn - hx_prev) * crdz - (hzn - sHz[ty][c - 1]) * crdx;
+                const float ddy = fmaf(z_cam1_n, o.dy, z_rp_n * chy);
+                float eyn = fmaf(x_ca_n, eyo, x_rp_n * (ce.inv_y * fmaf(y_ph_h, ddy, y_q_h * o.dy)));
+                // Ez(i, j, k+1/2): Dz uses x at i; Ez uses y at j, z at k+1/2
+                float js = 0.0f;
+                if (ce.flags & kSrcEz) {
+                    const __attribute__((address_space(1))) int32_t* sn =
+                        (const __attribute__((address_space(1))) int32_t*)B.src_node;
+                    cgfloat* sj = (cgfloat*)B.src_j;
+                    for (int s = 0; s < B.nsrc; ++s)
+                        if (sn[s] == node) js += sj[s * ms + step];
+                }
+                const float chz = ((hyn - sHy[ty][c - 1]) * crdx - (hxn - sHx[ty - 1][c]) * crdy) - js;
+                const float ddz = fmaf(x_cam1_n, o.dz, x_rp_n * chz);
+                float ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * o.dz)));
+                exn = (ce.flags & kUpdEx) ? exn : 0.0f;
+                eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
+                ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
+                dEx[node] = exn;
+                dEy[node] = eyn;
+                dEz[node] = ezn;
+                if (nbx && (ce.flags & kUpdEx)) Dx[node] = o.dx + ddx;
+                if (nby && (ce.flags & kUpdEy)) Dy[node] = o.dy + ddy;
+                if (nbz && (ce.flags & kUpdEz)) Dz[node] = o.dz + ddz;
+                if (ce.flags & kPrbEz) {
+                    const __attribute__((address_space(1))) int32_t* pn =
+                        (const __attribute__((address_space(1))) int32_t*)B.prb_node;
+                    gfloat* ps = (gfloat*)B.prb_series;
+                    for (int p = 0; p < B.nprb; ++p)
+                        if (pn[p] == node) ps[p * ms + step] = ezn;
+                }
+                bad |= !isfinite(exn + eyn + ezn);
+            }
+            hx_prev = hxn;
+            hy_prev = hyn;
+        };
+        for (int k = 0; k <= nz; k += 2) {
+            plane_step(k, s0, cA, cB);
+            if (k + 1 <= nz) plane_step(k + 1, s1, cB, cA);
+        }
+        if (bad) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
+    } else {
+        // ------------------------------------------------------------ extra wave
+        // staging of row TY (columns i0 .. i0+TX-1, TX/64 per lane) and of the
+        // columns i0-1 (lanes 0..TY) and i0+TX (lanes 32..32+TY); the new Hy, Hz
+        // of the halo column i0-1 for rows 1..TY-1 (lanes 1..TY-1)
+        constexpr int R = TX / 64;
+        const int jr = j0 - 1 + TY;
+        const int cc = lane < 32 ? 0 : TX + 1;          // staging column of this lane
+        const int cr = lane & 31;                       // its row
+        const bool col_lane = cr <= TY;
+        const int ic_ = i0 - 1 + cc, jc_ = j0 - 1 + cr;
+        // halo column
+        const bool halo = lane >= 1 && lane < TY;
+        const int ih = i0 - 1, jh = j0 - 1 + lane;
+        const bool h_ok = halo && ih >= 0 && jh >= 0 && jh <= ny;
+        const bool hpx = in_px(ih), hpy = in_py(jh);
+        const float hx_rp_h = CXf(kRp, 1, ih), hx_ca_h = CXf(kCa, 1, ih), hx_cam1_h = CXf(kCam1, 1, ih);
+        const float hy_ph_n = CYf(kPh, 0, jh), hy_q_n = CYf(kQ, 0, jh), hy_ca_h = CYf(kCa, 1, jh),
+                    hy_rp_h = CYf(kRp, 1, jh);
+        const int hnode0 = ih + jh * sy;
+        struct XStage { float rx[R], ry[R], rz[R], cx_, cy_, cz_; };
+        struct XCol { float hy, hz, by, bz; };
+        auto load_xstage = [&](int p) {
+            XStage s;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ii = i0 + lane + 64 * r;
+                s.rx[r] = gEx[node_at(ii, jr, p + 1)];
+                s.ry[r] = gEy[node_at(ii, jr, p + 1)];
+                s.rz[r] = gEz[node_at(ii, jr, p)];
+            }
+            const int ii = col_lane ? ic_ : -1;
+            s.cx_ = gEx[node_at(ii, jc_, p + 1)];
+            s.cy_ = gEy[node_at(ii, jc_, p + 1)];
+            s.cz_ = gEz[node_at(ii, jc_, p)];
+            return s;
+        };
+        auto load_xcol = [&](int p, XCol& o) {
+            o = XCol{0.f, 0.f, 0.f, 0.f};
+            if (h_ok && p <= nz) {
+                const int n = hnode0 + p * sz;
+                const bool pz = in_pz(p);
+                o.hy = gHy[n];
+                o.hz = gHz[n];
+                if (hpy || pz) o.by = gBy[n];
+                if (pz || hpx) o.bz = gBz[n];
+            }
+        };
+        {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ii = i0 + lane + 64 * r;
+                sEx[0][TY][1 + lane + 64 * r] = gEx[node_at(ii, jr, 0)];
+                sEy[0][TY][1 + lane + 64 * r] = gEy[node_at(ii, jr, 0)];
+            }
+            if (col_lane) {
+                sEx[0][cr][cc] = gEx[node_at(ic_, jc_, 0)];
+                sEy[0][cr][cc] = gEy[node_at(ic_, jc_, 0)];
             }
         }
-        sHx[ty][tx] = hxn;
-        sHy[ty][tx] = hyn;
-        sHz[ty][tx] = hzn;
-        __syncthreads();
-
-        // ---- D then E of plane k (own columns) ----
-        if (own) {
-            ClassEntry ce;
-            if (sizeof(CT) == 1) {
-                ce = sTab[c];
-            } else {
-                ce.inv_x = ctab[c].inv_x;
-                ce.inv_y = ctab[c].inv_y;
-                ce.inv_z = ctab[c].inv_z;
-                ce.flags = ctab[c].flags;
+        XStage s0 = load_xstage(0), s1 = load_xstage(1);
+        XCol hA, hB;
+        load_xcol(0, hA);
+        auto plane_step = [&](int k, XStage& st, const XCol& o, XCol& nxt_col) {
+            const int cur = k & 1, nxt = cur ^ 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sEx[nxt][TY][1 + lane + 64 * r] = st.rx[r];
+                sEy[nxt][TY][1 + lane + 64 * r] = st.ry[r];
+                sEz[TY][1 + lane + 64 * r] = st.rz[r];
             }
-            // Ex(i+1/2, j, k): Dx uses y at j; Ex uses z at k, x at i+1/2
-            const float chx = (hzn - sHz[ty - 1][tx]) * crdy - (hyn - hy_prev) * crdz;
-            const float ddx = fmaf(y_cam1_n, dxo, y_rp_n * chx);
-            float exn = fmaf(z_ca_n, exo, z_rp_n * (ce.inv_x * fmaf(x_ph_h, ddx, x_q_h * dxo)));
-            // Ey(i, j+1/2, k): Dy uses z at k; Ey uses x at i, y at j+1/2
-            const float chy = (hxn - hx_prev) * crdz - (hzn - sHz[ty][tx - 1]) * crdx;
-            const float ddy = fmaf(z_cam1_n, dyo, z_rp_n * chy);
-            float eyn = fmaf(x_ca_n, eyo, x_rp_n * (ce.inv_y * fmaf(y_ph_h, ddy, y_q_h * dyo)));
-            // Ez(i, j, k+1/2): Dz uses x at i; Ez uses y at j, z at k+1/2
-            float js = 0.0f;
-            if (ce.flags & kSrcEz) {
-                const __attribute__((address_space(1))) int32_t* sn =
-                    (const __attribute__((address_space(1))) int32_t*)B.src_node;
-                cgfloat* sj = (cgfloat*)B.src_j;
-                for (int s = 0; s < B.nsrc; ++s)
-                    if (sn[s] == node) js += sj[s * ms + step];
+            if (col_lane) {
+                sEx[nxt][cr][cc] = st.cx_;
+                sEy[nxt][cr][cc] = st.cy_;
+                sEz[cr][cc] = st.cz_;
             }
-            const float chz =
-                ((hyn - sHy[ty][tx - 1]) * crdx - (hxn - sHx[ty - 1][tx]) * crdy) - js;
-            const float ddz = fmaf(x_cam1_n, dzo, x_rp_n * chz);
-            float ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * dzo)));
-            exn = (ce.flags & kUpdEx) ? exn : 0.0f;
-            eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
-            ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
-            dEx[node] = exn;
-            dEy[node] = eyn;
-            dEz[node] = ezn;
-            if (nbx && (ce.flags & kUpdEx)) Dx[node] = dxo + ddx;
-            if (nby && (ce.flags & kUpdEy)) Dy[node] = dyo + ddy;
-            if (nbz && (ce.flags & kUpdEz)) Dz[node] = dzo + ddz;
-            if (ce.flags & kPrbEz) {
-                const __attribute__((address_space(1))) int32_t* pn =
-                    (const __attribute__((address_space(1))) int32_t*)B.prb_node;
-                gfloat* ps = (gfloat*)B.prb_series;
-                for (int p = 0; p < B.nprb; ++p)
-                    if (pn[p] == node) ps[p * ms + step] = ezn;
+            st = load_xstage(k + 2);
+            load_xcol(k + 1, nxt_col);
+            kfloat* czk = cz + k;
+            const float z_cam1_h = czk[(kCam1 * 2 + 1) * nz1], z_rp_h = czk[(kRp * 2 + 1) * nz1];
+            const float z_ph_n = czk[(kPh * 2 + 0) * nz1], z_q_n = czk[(kQ * 2 + 0) * nz1];
+            __syncthreads();
+            // Hy, Hz of the halo column i0-1 (needed by Ey, Ez of column i0)
+            float hyn = 0.f, hzn = 0.f;
+            if (h_ok) {
+                const float exo = sEx[cur][lane][0], eyo = sEy[cur][lane][0], ezo = sEz[lane][0];
+                const float cye = (sEx[nxt][lane][0] - exo) * crdz - (sEz[lane][1] - ezo) * crdx;
+                const float dby = fmaf(z_cam1_h, o.by, -z_rp_h * cye);
+                hyn = fmaf(hx_ca_h, o.hy, hx_rp_h * fmaf(hy_ph_n, dby, hy_q_n * o.by));
+                const float cze = (sEy[cur][lane][1] - eyo) * crdx - (sEx[cur][lane + 1][0] - exo) * crdy;
+                const float dbz = fmaf(hx_cam1_h, o.bz, -hx_rp_h * cze);
+                hzn = fmaf(hy_ca_h, o.hz, hy_rp_h * fmaf(z_ph_n, dbz, z_q_n * o.bz));
             }
-            if (!isfinite(exn + eyn + ezn)) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
+            if (halo) {
+                sHy[lane][0] = hyn;
+                sHz[lane][0] = hzn;
+            }
+            __syncthreads();
+        };
+        for (int k = 0; k <= nz; k += 2) {
+            plane_step(k, s0, hA, hB);
+            if (k + 1 <= nz) plane_step(k + 1, s1, hB, hA);
         }
-        hx_prev = hxn;
-        hy_prev = hyn;
     }
 }
 
@@ -409,7 +473,8 @@ __global__ void fill_zero(float* __restrict__ p, int64_t n)
 struct Shape {
     int tx, ty;
 };
-static const Shape kShapes[] = {{64, 8}, {64, 4}, {64, 16}, {128, 4}, {32, 8}, {32, 16}};
+static const Shape kShapes[] = {{64, 15}, {64, 12}, {64, 8},  {64, 4},  {64, 10},
+                                {64, 14}, {128, 7}, {128, 4}, {128, 6}, {128, 5}};
 static const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 int num_shapes() { return kNumShapes; }
@@ -424,10 +489,10 @@ static hipError_t launch_tt(const BoardDev* boards, const TileRef* tiles, int nt
                             bool wide, hipStream_t st)
 {
     if (wide)
-        hipLaunchKernelGGL((field_step<TX, TY, uint16_t>), dim3(ntiles), dim3(TX * TY), 0, st,
+        hipLaunchKernelGGL((field_step<TX, TY, uint16_t>), dim3(ntiles), dim3(TX * TY + 64), 0, st,
                            boards, tiles, rel);
     else
-        hipLaunchKernelGGL((field_step<TX, TY, uint8_t>), dim3(ntiles), dim3(TX * TY), 0, st,
+        hipLaunchKernelGGL((field_step<TX, TY, uint8_t>), dim3(ntiles), dim3(TX * TY + 64), 0, st,
                            boards, tiles, rel);
     return hipGetLastError();
 }
@@ -436,12 +501,11 @@ hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards,
                              const TileRef* tiles, int ntiles, int rel, bool wide,
                              hipStream_t st)
 {
-    if (tile_x == 64 && tile_y == 8) return launch_tt<64, 8>(boards, tiles, ntiles, rel, wide, st);
-    if (tile_x == 64 && tile_y == 4) return launch_tt<64, 4>(boards, tiles, ntiles, rel, wide, st);
-    if (tile_x == 64 && tile_y == 16) return launch_tt<64, 16>(boards, tiles, ntiles, rel, wide, st);
-    if (tile_x == 128 && tile_y == 4) return launch_tt<128, 4>(boards, tiles, ntiles, rel, wide, st);
-    if (tile_x == 32 && tile_y == 8) return launch_tt<32, 8>(boards, tiles, ntiles, rel, wide, st);
-    if (tile_x == 32 && tile_y == 16) return launch_tt<32, 16>(boards, tiles, ntiles, rel, wide, st);
+#define SHAPE(X, Y) \
+    if (tile_x == X && tile_y == Y) return launch_tt<X, Y>(boards, tiles, ntiles, rel, wide, st);
+    SHAPE(64, 15) SHAPE(64, 12) SHAPE(64, 8) SHAPE(64, 4) SHAPE(64, 10) SHAPE(64, 14)
+    SHAPE(128, 7) SHAPE(128, 4) SHAPE(128, 6) SHAPE(128, 5)
+#undef SHAPE
     return hipErrorInvalidValue;
 }
 

@@ -49,6 +49,15 @@ def batch_key(boards: Sequence) -> str:
     return "batch:" + ";".join(sorted(board_key(b) for b in boards))
 
 
+def cached(key: str, shapes: Sequence[Shape], path: Optional[str] = None) -> Optional[Shape]:
+    """The cached choice for ``key`` if it is one of ``shapes``, else None."""
+    data = _load(path or cache_path())
+    if key not in data:
+        return None
+    best = tuple(data[key][0])
+    return best if best in {tuple(s) for s in shapes} else None
+
+
 def pick(timings: Dict[Shape, float]) -> Shape:
     """Fastest shape; ties go to the first listed (the default ordering)."""
     best = None
@@ -60,12 +69,15 @@ def pick(timings: Dict[Shape, float]) -> Shape:
 
 def tune(key: str, time_shape: Callable[[Shape], float], shapes: Iterable[Shape],
          path: Optional[str] = None, refresh: bool = False) -> Tuple[Shape, Dict[Shape, float]]:
-    """Return the cached shape for ``key`` or time every shape and cache the best."""
+    """Return the cached shape for ``key`` or time every shape and cache the best.
+    A cached shape that is no longer among ``shapes`` is timed again."""
     path = path or cache_path()
+    shapes = [tuple(s) for s in shapes]
+    hit = cached(key, shapes, path)
+    if hit is not None and not refresh:
+        return hit, {}
     data = _load(path)
-    if key in data and not refresh:
-        return tuple(data[key][0]), {}
-    timings = {tuple(s): float(time_shape(tuple(s))) for s in shapes}
+    timings = {s: float(time_shape(s)) for s in shapes}
     best = pick(timings)
     data[key] = [list(best), {f"{s[0]}x{s[1]}": t for s, t in timings.items()}]
     _store(path, data)
@@ -105,9 +117,9 @@ def tune_board(board, steps: int = 6, warm: int = 2, path: Optional[str] = None,
         finally:
             F.fdtd_destroy_grid(g)
 
-    data = _load(path or cache_path())
-    if board_key(board) in data and not refresh:
-        return tuple(data[board_key(board)][0])
+    hit = cached(board_key(board), shapes, path)
+    if hit is not None and not refresh:
+        return hit
     return run()
 
 
@@ -115,10 +127,10 @@ def tune_batch(boards: Sequence, steps: int = 4, warm: int = 1, path: Optional[s
                refresh: bool = False) -> Shape:
     from . import fdtd as F
     key = batch_key(boards)
-    data = _load(path or cache_path())
-    if key in data and not refresh:
-        return tuple(data[key][0])
     shapes = F.fdtd_tile_shapes()
+    hit = cached(key, shapes, path)
+    if hit is not None and not refresh:
+        return hit
     total = len(shapes) * (steps + warm) + 1
     gs = [_scratch(F, b, total) for b in boards]
     try:

@@ -19,7 +19,7 @@ def test_binding_wraps_every_header_symbol():
 
 def test_tile_shapes_listed():
     shapes = F.fdtd_tile_shapes()
-    assert (64, 8) in shapes and all(tx * ty <= 1024 for tx, ty in shapes)
+    assert (64, 8) in shapes and all(tx % 64 == 0 and tx * ty + 64 <= 1024 for tx, ty in shapes)
 
 
 @pytest.mark.parametrize("kw,frag", [

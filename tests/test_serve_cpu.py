@@ -156,3 +156,10 @@ def test_tuner_picks_and_caches(tmp_path):
     assert best2 == (64, 16) and len(calls) == 3 and tim2 == {}
     best3, _ = tune.tune("k", t, [(64, 8), (32, 8)], path, refresh=True)
     assert best3 == (64, 8)
+    # a cached shape the library no longer offers is timed again, not returned
+    tune.tune("k", t, [(64, 8), (64, 16), (32, 8)], path, refresh=True)
+    n = len(calls)
+    best4, tim4 = tune.tune("k", t, [(64, 8), (32, 8)], path)
+    assert best4 == (64, 8) and len(calls) == n + 2 and set(tim4) == {(64, 8), (32, 8)}
+    assert tune.cached("k", [(64, 8)], path) == (64, 8)
+    assert tune.cached("k", [(32, 8)], path) is None
