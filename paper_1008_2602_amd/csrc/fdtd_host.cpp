@@ -350,7 +350,10 @@ int finalize(fdtd_grid* g)
     // components (not on the outer wall, not PEC), source/probe marks
     std::unordered_map<ClassKey, uint32_t, ClassKeyHash> map;
     std::vector<ClassEntry> table;
-    std::vector<uint16_t> ids((size_t)ND, 0);   // padding columns keep class 0, never read
+    // padding columns keep class 0 and are never read; kGuard class-0 entries past
+    // the last node serve the kernel's reads for absent nodes
+    const int64_t NC = ND + kGuard;
+    std::vector<uint16_t> ids((size_t)NC, 0);
     std::vector<uint8_t> mark((size_t)N, 0);
     for (const SourceH& s : g->sources) mark[node_index(g, s.i, s.j, s.k)] |= 1;
     for (const auto& p : g->probes) mark[node_index(g, p[0], p[1], p[2])] |= 2;
@@ -410,16 +413,16 @@ int finalize(fdtd_grid* g)
     g->wide = table.size() > 256;
     hipStream_t st = g->stream;
     if (g->wide) {
-        g->cls = dev_alloc(g, (size_t)ND * 2);
+        g->cls = dev_alloc(g, (size_t)NC * 2);
         if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
-        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids.data(), (size_t)ND * 2, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids.data(), (size_t)NC * 2, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
     } else {
-        std::vector<uint8_t> ids8((size_t)ND);
-        for (size_t t = 0; t < (size_t)ND; ++t) ids8[t] = (uint8_t)ids[t];
-        g->cls = dev_alloc(g, (size_t)ND);
+        std::vector<uint8_t> ids8((size_t)NC);
+        for (size_t t = 0; t < (size_t)NC; ++t) ids8[t] = (uint8_t)ids[t];
+        g->cls = dev_alloc(g, (size_t)NC);
         if (!g->cls) return fail(FDTD_ENOMEM, "class map allocation failed");
-        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids8.data(), (size_t)ND, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->cls, ids8.data(), (size_t)NC, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
     }
     g->ctab = (ClassEntry*)dev_alloc(g, table.size() * sizeof(ClassEntry));
@@ -924,7 +927,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     auto r = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nodes = row_pitch(d->nx) * (d->ny + 1) * (d->nz + 1);      // padded rows
     int64_t t = 21 * r((nodes + kGuard) * 4);                                   // fields
-    t += r(2 * nodes);                                                          // class map (upper bound)
+    t += r(2 * (nodes + kGuard));                                               // class map (upper bound)
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
     t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +
          r((int64_t)kNumCoef * 2 * (d->nz + 1) * 4);                            // coefficients

@@ -153,24 +153,23 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             s.ez = gEz[node_at(i, j, p)];
             return s;
         };
+        // every load is issued on every path (absent operands read the zero
+        // guard words), so the wait counts stay exact and the prefetch overlaps
         auto load_col = [&](int p, Col& o) {
-            o = Col{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
-            if (col_ok && p <= nz) {
-                const int n = node0 + p * sz;
-                const bool pz = in_pz(p);
-                o.hx = gHx[n];
-                o.hy = gHy[n];
-                o.hz = gHz[n];
-                if (px || py) o.bx = gBx[n];
-                if (py || pz) o.by = gBy[n];
-                if (pz || px) o.bz = gBz[n];
-                if (own) {
-                    o.c = cls[n];
-                    if (px || py) o.dx = Dx[n];
-                    if (py || pz) o.dy = Dy[n];
-                    if (pz || px) o.dz = Dz[n];
-                }
-            }
+            const int n = node0 + p * sz;
+            const bool pz = in_pz(p);
+            const bool okp = col_ok && p <= nz, ownp = own && p <= nz;
+            const int nh = okp ? n : guard;
+            o.hx = gHx[nh];
+            o.hy = gHy[nh];
+            o.hz = gHz[nh];
+            o.bx = gBx[okp && (px || py) ? n : guard];
+            o.by = gBy[okp && (py || pz) ? n : guard];
+            o.bz = gBz[okp && (pz || px) ? n : guard];
+            o.c = cls[ownp ? n : guard];
+            o.dx = Dx[ownp && (px || py) ? n : guard];
+            o.dy = Dy[ownp && (py || pz) ? n : guard];
+            o.dz = Dz[ownp && (pz || px) ? n : guard];
         };
         sEx[0][ty][c] = gEx[node_at(i, j, 0)];
         sEy[0][ty][c] = gEy[node_at(i, j, 0)];
@@ -325,15 +324,13 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             return s;
         };
         auto load_xcol = [&](int p, XCol& o) {
-            o = XCol{0.f, 0.f, 0.f, 0.f};
-            if (h_ok && p <= nz) {
-                const int n = hnode0 + p * sz;
-                const bool pz = in_pz(p);
-                o.hy = gHy[n];
-                o.hz = gHz[n];
-                if (hpy || pz) o.by = gBy[n];
-                if (pz || hpx) o.bz = gBz[n];
-            }
+            const int n = hnode0 + p * sz;
+            const bool pz = in_pz(p);
+            const bool okp = h_ok && p <= nz;
+            o.hy = gHy[okp ? n : guard];
+            o.hz = gHz[okp ? n : guard];
+            o.by = gBy[okp && (hpy || pz) ? n : guard];
+            o.bz = gBz[okp && (pz || hpx) ? n : guard];
         };
         {
 #pragma unroll
