@@ -6,16 +6,18 @@ def live_masks(board):
     """Boolean masks of the entries each oracle array actually carries: E edges
     that are updated (not on the outer wall, not PEC) and H faces that exist."""
     nx, ny, nz = board.nx, board.ny, board.nz
-    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
-                             indexing="ij")
+    kk = np.arange(nz + 1)[:, None, None]
+    jj = np.arange(ny + 1)[None, :, None]
+    ii = np.arange(nx + 1)[None, None, :]
+    shp = (nz + 1, ny + 1, nx + 1)
     pec = board.pec_edge_mask
     m = {}
     m["ex"] = (ii < nx) & (jj >= 1) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 1) == 0)
     m["ey"] = (ii >= 1) & (ii < nx) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 2) == 0)
     m["ez"] = (ii >= 1) & (ii < nx) & (jj >= 1) & (jj < ny) & (kk < nz) & ((pec & 4) == 0)
-    m["hx"] = (jj < ny) & (kk < nz)
-    m["hy"] = (ii < nx) & (kk < nz)
-    m["hz"] = (ii < nx) & (jj < ny)
+    m["hx"] = np.broadcast_to((jj < ny) & (kk < nz), shp)
+    m["hy"] = np.broadcast_to((ii < nx) & (kk < nz), shp)
+    m["hz"] = np.broadcast_to((ii < nx) & (jj < ny), shp)
     for a, f in (("ddx", "ex"), ("ddy", "ey"), ("ddz", "ez"),
                  ("bbx", "hx"), ("bby", "hy"), ("bbz", "hz")):
         m[a] = m[f]
