@@ -22,6 +22,7 @@ int num_shapes();
 void shape_at(int s, int* tx, int* ty);
 hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards, const TileRef* tiles,
                              int ntiles, int rel, bool wide, hipStream_t st);
+int field_step_occupancy(int tile_x, int tile_y, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, hipStream_t st);
 hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
@@ -130,7 +131,8 @@ struct fdtd_grid {
     bool wide = false;
     bool finalized = false;
     int64_t step = 0;
-    int tile_x = 64, tile_y = 8;
+    int tile_x = 64, tile_y = 15;
+    int cus = 0;            // compute units of the device
     int64_t step_bytes = 0;
 
     // timing
@@ -218,6 +220,87 @@ void tile_counts(int nx, int ny, int tx, int ty, int* cx, int* cy)
 {
     *cx = (nx + 1 + tx - 1) / tx;
     *cy = (ny + 1 + ty - 2) / (ty - 1);
+}
+
+constexpr int kXcds = 8;   // the kernel deals block b to XCD b % 8 (xcd_tile)
+
+// Work list of one field launch.  Tiles arrive in board order, row-major within
+// a board.  They are cut into kXcds contiguous runs of about equal plane count,
+// one per XCD, so that neighbouring tiles share halos in that XCD's L2.  On each
+// XCD the tiles left over after its last full round of concurrent blocks would
+// leave most of the XCD idle in that round; they are split in z into S pieces
+// (S chosen to shorten the estimated tail, each piece after the first pays one
+// recomputed plane).  Pieces go piece-major so that concurrent pieces are
+// spatial neighbours at the same depth.  Every run is padded with idle entries
+// to the common length, so the launch has kXcds * length blocks.
+void build_work(const std::vector<TileRef>& tiles, int slots_per_xcd, std::vector<TileRef>& out)
+{
+    out.clear();
+    const size_t T = tiles.size();
+    if (T == 0) return;
+    double W = 0.0;
+    for (const TileRef& t : tiles) W += t.ke - t.kb;
+    std::vector<std::vector<TileRef>> runs(kXcds);
+    size_t idx = 0;
+    double acc = 0.0;
+    for (int x = 0; x < kXcds; ++x) {
+        const double target = W * (x + 1) / kXcds;
+        std::vector<TileRef> whole;
+        while (idx < T && (x == kXcds - 1 || acc + 0.5 * (tiles[idx].ke - tiles[idx].kb) <= target)) {
+            whole.push_back(tiles[idx]);
+            acc += tiles[idx].ke - tiles[idx].kb;
+            ++idx;
+        }
+        const size_t n = whole.size(), C = (size_t)std::max(1, slots_per_xcd);
+        const size_t m = n % C;  // tiles of the partial last round
+        int S = 1;
+        if (m > 0) {
+            double pbar = 0.0;
+            for (size_t q = n - m; q < n; ++q) pbar += whole[q].ke - whole[q].kb;
+            pbar /= (double)m;
+            double best = pbar;
+            for (int cand = 2; cand <= 8 && pbar / cand >= 3.0; ++cand) {
+                const double rounds = std::ceil((double)(m * cand) / (double)C);
+                const double cost = rounds * (pbar / cand + 1.0);
+                if (cost < 0.97 * best) {
+                    best = cost;
+                    S = cand;
+                }
+            }
+        }
+        std::vector<TileRef>& r = runs[x];
+        r.assign(whole.begin(), whole.end() - (S > 1 ? (std::ptrdiff_t)m : 0));
+        if (S > 1)
+            for (int piece = 0; piece < S; ++piece)
+                for (size_t q = n - m; q < n; ++q) {
+                    TileRef t = whole[q];
+                    const int planes = t.ke - t.kb;
+                    t.ke = t.kb + (int)((int64_t)planes * (piece + 1) / S);
+                    t.kb = t.kb + (int)((int64_t)planes * piece / S);
+                    if (t.kb < t.ke) r.push_back(t);   // a shallow tile may give fewer pieces
+                }
+    }
+    size_t L = 0;
+    for (const auto& r : runs) L = std::max(L, r.size());
+    out.reserve(L * kXcds);
+    for (const auto& r : runs) {
+        out.insert(out.end(), r.begin(), r.end());
+        out.insert(out.end(), L - r.size(), TileRef{-1, 0, 0, 0, 0});
+    }
+}
+
+// Whole tiles of board b (row-major), all planes.
+void board_tiles(int b, int nx, int ny, int nz, int tx, int ty, std::vector<TileRef>& out)
+{
+    int cx, cy;
+    tile_counts(nx, ny, tx, ty, &cx, &cy);
+    for (int y = 0; y < cy; ++y)
+        for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz + 1});
+}
+
+int slots_per_xcd(const fdtd_grid* g, int tx, int ty, bool wide)
+{
+    return std::max(1, g->cus / kXcds) * field_step_occupancy(tx, ty, wide);
 }
 
 void dev_free_all(fdtd_grid* g)
@@ -579,7 +662,9 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     g->nodes = nodes;
     g->pitch = pitch;
     g->dnodes = dnodes;
-    if (hipGetDevice(&g->device) != hipSuccess) {
+    if (hipGetDevice(&g->device) != hipSuccess ||
+        hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device) !=
+            hipSuccess) {
         delete g;
         return fail(FDTD_EDEVICE, "no HIP device");
     }
@@ -698,10 +783,10 @@ static int upload_tiles(fdtd_grid* g)
 {
     BoardDev& b = g->board_host;
     tile_counts(g->d.nx, g->d.ny, g->tile_x, g->tile_y, &b.tiles_x, &b.tiles_y);
-    const int nt = b.tiles_x * b.tiles_y;
-    std::vector<TileRef> tl((size_t)nt);
-    for (int ty = 0; ty < b.tiles_y; ++ty)
-        for (int tx = 0; tx < b.tiles_x; ++tx) tl[(size_t)ty * b.tiles_x + tx] = TileRef{0, tx, ty};
+    std::vector<TileRef> whole, tl;
+    board_tiles(0, g->d.nx, g->d.ny, g->d.nz, g->tile_x, g->tile_y, whole);
+    build_work(whole, slots_per_xcd(g, g->tile_x, g->tile_y, g->wide), tl);
+    const int nt = (int)tl.size();
     if (nt > g->tiles_cap) {
         g->tiles_dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
         if (!g->tiles_dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
@@ -841,25 +926,44 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     });
     std::vector<BoardDev> boards(ng);
     std::vector<int64_t> nn(ng);
-    std::vector<TileRef> tiles;
-    int group_start[2] = {-1, -1}, group_tiles0[2] = {0, 0};
-    std::vector<int64_t> tiles_upto(ng);  // tiles of boards order[0..b] within the group
     int64_t max_n = 0;
     for (int b = 0; b < ng; ++b) {
-        fdtd_grid* g = gs[order[b]];
-        const int w = g->wide ? 1 : 0;
-        if (group_start[w] < 0) {
-            group_start[w] = b;
-            group_tiles0[w] = (int)tiles.size();
-        }
-        boards[b] = g->board_host;
+        boards[b] = gs[order[b]]->board_host;
         nn[b] = n[order[b]];
         max_n = std::max(max_n, nn[b]);
-        int tiles_x, tiles_y;
-        tile_counts(g->d.nx, g->d.ny, tx, ty, &tiles_x, &tiles_y);
-        for (int y = 0; y < tiles_y; ++y)
-            for (int x = 0; x < tiles_x; ++x) tiles.push_back(TileRef{b, x, y});
-        tiles_upto[b] = (int64_t)tiles.size();
+    }
+    // Each class width forms a group [b0, b1) of the order; at step s the boards
+    // still running are a prefix [b0, active) of it.  One balanced work list per
+    // distinct prefix, all in one device buffer.
+    struct Span {
+        int w;
+        int64_t s0, s1;  // steps s0 .. s1-1 run this list
+        int off, count;
+    };
+    std::vector<Span> spans;
+    std::vector<TileRef> items, whole, list;
+    for (int w = 0; w < 2; ++w) {
+        int b0 = 0;
+        while (b0 < ng && gs[order[b0]]->wide != (w == 1)) ++b0;
+        if (b0 == ng) continue;
+        int b1 = b0;
+        while (b1 < ng && gs[order[b1]]->wide == (w == 1)) ++b1;
+        int64_t s = 0;
+        for (int active = b1; active > b0 && s < max_n;) {
+            const int64_t s_end = nn[active - 1];  // boards [b0, active) all run through s_end
+            if (s_end > s) {
+                whole.clear();
+                for (int b = b0; b < active; ++b) {
+                    const fdtd_grid* g = gs[order[b]];
+                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, ty, whole);
+                }
+                build_work(whole, slots_per_xcd(lead, tx, ty, w == 1), list);
+                spans.push_back(Span{w, s, s_end, (int)items.size(), (int)list.size()});
+                items.insert(items.end(), list.begin(), list.end());
+                s = s_end;
+            }
+            --active;
+        }
     }
     // device scratch held by the lead handle
     if (lead->batch_boards_cap < ng) {
@@ -868,10 +972,10 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         if (!lead->batch_boards || !lead->batch_n) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
         lead->batch_boards_cap = ng;
     }
-    if (lead->batch_tiles_cap < (int)tiles.size()) {
-        lead->batch_tiles = (TileRef*)dev_alloc(lead, sizeof(TileRef) * tiles.size());
+    if (lead->batch_tiles_cap < (int)items.size()) {
+        lead->batch_tiles = (TileRef*)dev_alloc(lead, sizeof(TileRef) * items.size());
         if (!lead->batch_tiles) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
-        lead->batch_tiles_cap = (int)tiles.size();
+        lead->batch_tiles_cap = (int)items.size();
     }
     // order after the work already queued on every handle's stream
     for (int h = 1; h < ng; ++h) {
@@ -882,26 +986,16 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     HIP_OR_FAIL(hipMemcpyAsync(lead->batch_boards, boards.data(), sizeof(BoardDev) * (size_t)ng,
                                hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_tiles, tiles.data(), sizeof(TileRef) * tiles.size(),
-                               hipMemcpyHostToDevice, st));
+    if (!items.empty())
+        HIP_OR_FAIL(hipMemcpyAsync(lead->batch_tiles, items.data(), sizeof(TileRef) * items.size(),
+                                   hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, nn.data(), sizeof(int64_t) * (size_t)ng,
                                hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));  // the host arrays above are locals
-    for (int w = 0; w < 2; ++w) {
-        if (group_start[w] < 0) continue;
-        const int b0 = group_start[w];
-        int b1 = b0;
-        while (b1 < ng && gs[order[b1]]->wide == (w == 1)) ++b1;
-        int active = b1;  // boards [b0, active) still running
-        for (int64_t s = 0; s < max_n; ++s) {
-            while (active > b0 && nn[active - 1] <= s) --active;
-            if (active == b0) break;
-            const int ntiles = (int)(tiles_upto[active - 1] - group_tiles0[w]);
-            HIP_OR_FAIL(launch_field_step(tx, ty, lead->batch_boards,
-                                          lead->batch_tiles + group_tiles0[w], ntiles, (int)s,
-                                          w == 1, st));
-        }
-    }
+    for (const Span& sp : spans)
+        for (int64_t s = sp.s0; s < sp.s1; ++s)
+            HIP_OR_FAIL(launch_field_step(tx, ty, lead->batch_boards, lead->batch_tiles + sp.off,
+                                          sp.count, (int)s, sp.w == 1, st));
     HIP_OR_FAIL(launch_advance(lead->batch_boards, ng, lead->batch_n, st));
     for (int h = 0; h < ng; ++h) {
         fdtd_grid* g = gs[h];
@@ -935,7 +1029,8 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     t += r(4 * (int64_t)n_probes) + r(4 * (int64_t)n_probes * d->max_steps);     // probes
     t += r(8 * (int64_t)n_freqs) + 2 * r(8 * (int64_t)n_probes * n_freqs);       // DFT
     const int64_t max_tiles = ((d->nx + 64) / 64) * ((d->ny + 3) / 3);         // 64 x 4, the most tiles
-    t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * max_tiles);        // small buffers
+    const int64_t max_items = kXcds * (max_tiles + 7 * 256);                    // pieces and padding
+    t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * max_items);        // small buffers
     return t;
 }
 

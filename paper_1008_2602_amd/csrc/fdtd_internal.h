@@ -66,9 +66,12 @@ struct BoardDev {
     int32_t tiles_x, tiles_y;
 };
 
+// One work item of the field kernel: tile (tx, ty) of a board, planes kb..ke-1.
+// board < 0 marks an idle entry that pads an XCD's share of the launch.
 struct TileRef {
     int32_t board;
     int32_t tx, ty;
+    int32_t kb, ke;
 };
 
 }  // namespace fdtd

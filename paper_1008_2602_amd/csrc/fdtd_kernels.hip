@@ -63,6 +63,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
     __shared__ ClassEntry sTab[kLdsClasses];
 
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (t.board < 0) return;   // idle entry padding an XCD's list
     const BoardDev& B = boards[t.board];
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int sy = B.pitch, sz = B.pitch * (ny + 1), guard = sz * (nz + 1);
@@ -75,6 +76,9 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
     const int lane = tid & 63;
     const int i0 = t.tx * TX, j0 = t.ty * (TY - 1);
     const int i = i0 + tx, j = j0 - 1 + ty;
+    // planes kb .. ke-1 are stepped; a piece that starts above the bottom first
+    // recomputes H of plane kb-1 (not stored) for the z-differences of plane kb
+    const int kb = t.kb, ke = t.ke, k0 = kb > 0 ? kb - 1 : 0;
     const bool col_ok = main_wave && (i <= nx) && (j >= 0) && (j <= ny);
     const bool own = col_ok && ty > 0;
     const int64_t step = *B.step + rel;
@@ -159,29 +163,32 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             const int n = node0 + p * sz;
             const bool pz = in_pz(p);
             const bool okp = col_ok && p <= nz, ownp = own && p <= nz;
+            const bool live = ownp && p >= kb;   // E of this plane is stepped here
             const int nh = okp ? n : guard;
+            // the halo row only feeds Hx and Hz to the row above it
             o.hx = gHx[nh];
-            o.hy = gHy[nh];
+            o.hy = gHy[ownp ? n : guard];
             o.hz = gHz[nh];
             o.bx = gBx[okp && (px || py) ? n : guard];
-            o.by = gBy[okp && (py || pz) ? n : guard];
+            o.by = gBy[ownp && (py || pz) ? n : guard];
             o.bz = gBz[okp && (pz || px) ? n : guard];
-            o.c = cls[ownp ? n : guard];
-            o.dx = Dx[ownp && (px || py) ? n : guard];
-            o.dy = Dy[ownp && (py || pz) ? n : guard];
-            o.dz = Dz[ownp && (pz || px) ? n : guard];
+            o.c = cls[live ? n : guard];
+            o.dx = Dx[live && (px || py) ? n : guard];
+            o.dy = Dy[live && (py || pz) ? n : guard];
+            o.dz = Dz[live && (pz || px) ? n : guard];
         };
-        sEx[0][ty][c] = gEx[node_at(i, j, 0)];
-        sEy[0][ty][c] = gEy[node_at(i, j, 0)];
-        Stage s0 = load_stage(0), s1 = load_stage(1);
+        sEx[0][ty][c] = gEx[node_at(i, j, k0)];
+        sEy[0][ty][c] = gEy[node_at(i, j, k0)];
+        Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
         Col cA, cB;
-        load_col(0, cA);
+        load_col(k0, cA);
         float hx_prev = 0.0f, hy_prev = 0.0f;
         bool bad = false;
         const int64_t ms = B.max_steps;
 
         auto plane_step = [&](int k, Stage& st, const Col& o, Col& nxt_col) {
-            const int cur = k & 1, nxt = cur ^ 1;
+            const int cur = (k - k0) & 1, nxt = cur ^ 1;
+            const bool live = k >= kb;
             const bool pz = in_pz(k);
             const bool nbx = px || py, nby = py || pz, nbz = pz || px;
             const int node = node0 + k * sz;
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                 const float cze = (sEy[cur][ty][c + 1] - eyo) * crdx - (sEx[cur][ty + 1][c] - exo) * crdy;
                 const float dbz = fmaf(x_cam1_h, o.bz, -x_rp_h * cze);
                 hzn = fmaf(y_ca_h, o.hz, y_rp_h * fmaf(z_ph_n, dbz, z_q_n * o.bz));
-                if (own) {
+                if (own && live) {
                     dHx[node] = hxn;
                     dHy[node] = hyn;
                     dHz[node] = hzn;
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             __syncthreads();
 
             // ---- D then E of plane k (own columns) ----
-            if (own) {
+            if (own && live) {
                 ClassEntry ce;
                 if (sizeof(CT) == 1) {
                     ce = sTab[o.c];
@@ -281,16 +288,18 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             hx_prev = hxn;
             hy_prev = hyn;
         };
-        for (int k = 0; k <= nz; k += 2) {
+        for (int k = k0; k < ke; k += 2) {
             plane_step(k, s0, cA, cB);
-            if (k + 1 <= nz) plane_step(k + 1, s1, cB, cA);
+            if (k + 1 < ke) plane_step(k + 1, s1, cB, cA);
         }
         if (bad) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
     } else {
         // ------------------------------------------------------------ extra wave
         // staging of row TY (columns i0 .. i0+TX-1, TX/64 per lane) and of the
         // columns i0-1 (lanes 0..TY) and i0+TX (lanes 32..32+TY); the new Hy, Hz
-        // of the halo column i0-1 for rows 1..TY-1 (lanes 1..TY-1)
+        // of the halo column i0-1 for rows 1..TY-1 (lanes 1..TY-1).  Only what
+        // the stencil reads is loaded: row TY feeds Hx (Ez) and Hz (Ex) of row
+        // TY-1, column i0+TX feeds Hy (Ez) and Hz (Ey) of column i0+TX-1.
         constexpr int R = TX / 64;
         const int jr = j0 - 1 + TY;
         const int cc = lane < 32 ? 0 : TX + 1;          // staging column of this lane
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
         const float hy_ph_n = CYf(kPh, 0, jh), hy_q_n = CYf(kQ, 0, jh), hy_ca_h = CYf(kCa, 1, jh),
                     hy_rp_h = CYf(kRp, 1, jh);
         const int hnode0 = ih + jh * sy;
-        struct XStage { float rx[R], ry[R], rz[R], cx_, cy_, cz_; };
+        struct XStage { float rx[R], rz[R], cx_, cy_, cz_; };
         struct XCol { float hy, hz, by, bz; };
         auto load_xstage = [&](int p) {
             XStage s;
@@ -314,11 +323,10 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             for (int r = 0; r < R; ++r) {
                 const int ii = i0 + lane + 64 * r;
                 s.rx[r] = gEx[node_at(ii, jr, p + 1)];
-                s.ry[r] = gEy[node_at(ii, jr, p + 1)];
                 s.rz[r] = gEz[node_at(ii, jr, p)];
             }
             const int ii = col_lane ? ic_ : -1;
-            s.cx_ = gEx[node_at(ii, jc_, p + 1)];
+            s.cx_ = gEx[node_at(cc == 0 ? ii : -1, jc_, p + 1)];
             s.cy_ = gEy[node_at(ii, jc_, p + 1)];
             s.cz_ = gEz[node_at(ii, jc_, p)];
             return s;
@@ -336,23 +344,21 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int ii = i0 + lane + 64 * r;
-                sEx[0][TY][1 + lane + 64 * r] = gEx[node_at(ii, jr, 0)];
-                sEy[0][TY][1 + lane + 64 * r] = gEy[node_at(ii, jr, 0)];
+                sEx[0][TY][1 + lane + 64 * r] = gEx[node_at(ii, jr, k0)];
             }
             if (col_lane) {
-                sEx[0][cr][cc] = gEx[node_at(ic_, jc_, 0)];
-                sEy[0][cr][cc] = gEy[node_at(ic_, jc_, 0)];
+                sEx[0][cr][cc] = gEx[node_at(cc == 0 ? ic_ : -1, jc_, k0)];
+                sEy[0][cr][cc] = gEy[node_at(ic_, jc_, k0)];
             }
         }
-        XStage s0 = load_xstage(0), s1 = load_xstage(1);
+        XStage s0 = load_xstage(k0), s1 = load_xstage(k0 + 1);
         XCol hA, hB;
-        load_xcol(0, hA);
+        load_xcol(k0, hA);
         auto plane_step = [&](int k, XStage& st, const XCol& o, XCol& nxt_col) {
-            const int cur = k & 1, nxt = cur ^ 1;
+            const int cur = (k - k0) & 1, nxt = cur ^ 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 sEx[nxt][TY][1 + lane + 64 * r] = st.rx[r];
-                sEy[nxt][TY][1 + lane + 64 * r] = st.ry[r];
                 sEz[TY][1 + lane + 64 * r] = st.rz[r];
             }
             if (col_lane) {
@@ -383,9 +389,9 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             }
             __syncthreads();
         };
-        for (int k = 0; k <= nz; k += 2) {
+        for (int k = k0; k < ke; k += 2) {
             plane_step(k, s0, hA, hB);
-            if (k + 1 <= nz) plane_step(k + 1, s1, hB, hA);
+            if (k + 1 < ke) plane_step(k + 1, s1, hB, hA);
         }
     }
 }
@@ -492,6 +498,28 @@ static hipError_t launch_tt(const BoardDev* boards, const TileRef* tiles, int nt
         hipLaunchKernelGGL((field_step<TX, TY, uint8_t>), dim3(ntiles), dim3(TX * TY + 64), 0, st,
                            boards, tiles, rel);
     return hipGetLastError();
+}
+
+template <int TX, int TY>
+static int occupancy_tt(bool wide)
+{
+    int n = 0;
+    hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step<TX, TY, uint16_t>, TX * TY + 64, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step<TX, TY, uint8_t>, TX * TY + 64, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+// Blocks of the field kernel that one compute unit holds at once.
+int field_step_occupancy(int tile_x, int tile_y, bool wide)
+{
+#define SHAPE(X, Y) \
+    if (tile_x == X && tile_y == Y) return occupancy_tt<X, Y>(wide);
+    SHAPE(64, 15) SHAPE(64, 12) SHAPE(64, 8) SHAPE(64, 4) SHAPE(64, 10) SHAPE(64, 14)
+    SHAPE(128, 7) SHAPE(128, 4) SHAPE(128, 6) SHAPE(128, 5)
+#undef SHAPE
+    return 1;
 }
 
 hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards,
