@@ -33,9 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "field_step_config3_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "field_step_1048x792x88_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1008_2602_amd", "csrc", f)
-                  for f in ("fdtd_kernels.hip", "fdtd_internal.h")]
+                  for f in ("fdtd_kernels.hip", "fdtd_internal.h", "fdtd_host.cpp")]
 
 
 def kernel_hash() -> str:
@@ -92,7 +92,7 @@ def cpu_baseline(board, budget_s=20.0):
 def run_single(F, torch, K, W, tile):
     import numpy as np
     import boardgen
-    board = boardgen.config3()
+    board = boardgen.large_board()
     stream = torch.cuda.current_stream().cuda_stream
     if tile is None:
         from paper_1008_2602_amd import tune
@@ -119,7 +119,7 @@ def run_batch(F, torch, K, W):
     """The 64-board variant batch, all boards advanced by K steps together."""
     import boardgen
     from paper_1008_2602_amd import tune
-    boards = boardgen.config4(steps=W + K)
+    boards = boardgen.variant_batch(steps=W + K)
     tile = tune.tune_batch(boards)
     handles = [F.grid_from_board(b, max_steps=W + K) for b in boards]
     gs = [h for h, _ in handles]
@@ -153,7 +153,7 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
     from paper_1008_2602_amd.serve import GpuExecutor, Server, summarize
     capacity = capacity_gcells * 1e9 / (mean_cells * steps)           # boards per second
     rate = 0.7 * capacity
-    reqs = boardgen.config5(rate, n_requests=n_requests, steps=steps)
+    reqs = boardgen.served_requests(rate, n_requests=n_requests, steps=steps)
     from paper_1008_2602_amd.serve import SolveRequest
     requests = [SolveRequest(r.rid, r.arrival_s, r.board) for r in reqs]
     free, _total = torch.cuda.mem_get_info()
@@ -266,7 +266,7 @@ def main():
                                       args.serve_requests, args.serve_steps)
     if args.only in (None, "single") and not args.no_cpu_baseline:
         import boardgen
-        out["cpu_baseline"] = cpu_baseline(boardgen.config3())
+        out["cpu_baseline"] = cpu_baseline(boardgen.large_board())
     print(json.dumps(out), flush=True)
 
 

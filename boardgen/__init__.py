@@ -176,13 +176,13 @@ def _interior_xy(rng: np.random.Generator, lay: dict, n: int, margin: int = 1
 # the five workload configurations
 # ----------------------------------------------------------------------------
 
-def config1(seed: int = 1001, steps: int = 3000) -> Board:
+def small_board(seed: int = 1001, steps: int = 3000) -> Board:
     """48 x 40 mm board, 1 mm in-plane cells, 0.2 mm dz, 1.0 mm FR4 (eps_r 4.4)
     between two PEC sheets; 8 air + 8 PML cells on every side; grid 80 x 72 x 37;
     Gaussian Jz (t0 = 120 ps, sigma = 30 ps) at a seeded dielectric edge; four Ez
     probes on the first Ez row above the ground sheet; 3000 steps at 0.99 Courant."""
     rng = np.random.default_rng(seed)
-    b, lay = plane_stack("config1-48x40mm", (48, 40), 5, 8, 8, 8, 8, 8,
+    b, lay = plane_stack("small-48x40mm", (48, 40), 5, 8, 8, 8, 8, 8,
                          1e-3, 1e-3, 0.2e-3, 4.4)
     (si, sj), *pr = _interior_xy(rng, lay, 5)
     sk = int(rng.integers(lay["kg"], lay["kt"]))
@@ -194,12 +194,12 @@ def config1(seed: int = 1001, steps: int = 3000) -> Board:
     return b
 
 
-def config2(seed: int = 1002, steps: int = 20000) -> Board:
+def realistic_board(seed: int = 1002, steps: int = 20000) -> Board:
     """200 x 160 mm board, 0.5 mm in-plane cells, 0.1 mm dz, 1.6 mm FR4 (eps_r 4.4);
     12-cell air gap, 10-cell PML; grid 444 x 364 x 60; Gaussian Jz with
     sigma = 20 ps (t0 = 4 sigma); 16 probes; 20000 steps."""
     rng = np.random.default_rng(seed)
-    b, lay = plane_stack("config2-200x160mm", (400, 320), 16, 12, 10, 12, 12, 10,
+    b, lay = plane_stack("realistic-200x160mm", (400, 320), 16, 12, 10, 12, 12, 10,
                          0.5e-3, 0.5e-3, 0.1e-3, 4.4)
     (si, sj), *pr = _interior_xy(rng, lay, 17)
     sk = int(rng.integers(lay["kg"], lay["kt"]))
@@ -229,7 +229,7 @@ def _disjoint_islands(rng: np.random.Generator, bx: int, by: int
     raise RuntimeError("could not place two disjoint islands")
 
 
-def config3(seed: int = 1003, steps: int = 10000) -> Board:
+def large_board(seed: int = 1003, steps: int = 10000) -> Board:
     """Large-board HBM stress case: 1024 x 768 x 64 interior cells plus a 12-cell
     PML on every face (grid 1048 x 792 x 88), dx = dy = 0.2 mm, dz = 0.1 mm,
     eps_r 4.2 slab of 16 cells centred in z (24 air cells above and below), a
@@ -259,7 +259,7 @@ def config3(seed: int = 1003, steps: int = 10000) -> Board:
     lay = dict(bi0=bi0, bi1=bi0 + bx, bj0=bj0, bj1=bj0 + by, kg=kg, kt=kt,
                islands=islands)
     probes = [(i, j, kg) for (i, j) in _interior_xy(rng, lay, 64)]
-    b = Board(name="config3-1048x792x88", nx=nx, ny=ny, nz=nz,
+    b = Board(name="large-1048x792x88", nx=nx, ny=ny, nz=nz,
               dx=0.2e-3, dy=0.2e-3, dz=0.1e-3, eps_r_cell=eps, pec_edge_mask=mask,
               npml=(12, 12, 12, 12, 12, 12), sources=sources, probes=probes,
               steps=steps,
@@ -299,7 +299,7 @@ def variant_board(rng: np.random.Generator, idx: int, steps: int = 8000,
     return b
 
 
-def config4(seed: int = 1004, n_boards: int = 64, steps: int = 8000) -> List[Board]:
+def variant_batch(seed: int = 1004, n_boards: int = 64, steps: int = 8000) -> List[Board]:
     """64 uneven board variants for one batched launch (see variant_board)."""
     rng = np.random.default_rng(seed)
     return [variant_board(rng, i, steps) for i in range(n_boards)]
@@ -312,9 +312,9 @@ class Request:
     board: Board
 
 
-def config5(rate_per_s: float, seed: int = 1005, n_requests: int = 512,
-            steps: int = 8000, large_frac: float = 0.05,
-            large_xyz: Tuple[int, int, int] = (800, 800, 64)) -> List[Request]:
+def served_requests(rate_per_s: float, seed: int = 1005, n_requests: int = 512,
+                    steps: int = 8000, large_frac: float = 0.05,
+                    large_xyz: Tuple[int, int, int] = (800, 800, 64)) -> List[Request]:
     """Served solves: Poisson arrivals at ``rate_per_s`` of boards drawn from the
     batched-variant distribution plus ``large_frac`` large boards."""
     rng = np.random.default_rng(seed)

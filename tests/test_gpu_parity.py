@@ -165,9 +165,9 @@ def test_random_state_few_steps(F, orc, shape, npml):
     compare_fields(ref.state, fields, b, 2e-5)
 
 
-def test_config1_full_run_parity(F, orc):
-    b = boardgen.config1()
-    announce(f"config1 full {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
+def test_small_board_full_run_parity(F, orc):
+    b = boardgen.small_board()
+    announce(f"small board full {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
     ref = orc.run(b, threads=16)
     probes, _, _, _ = gpu_run(F, b)
     n_fft = orc.default_nfft(b.steps)
@@ -189,21 +189,21 @@ def _bench_tile(board):
     return tune.tune_board(board)
 
 
-def test_config3_full_size_from_zero(F, orc):
+def test_large_board_full_size_from_zero(F, orc):
     """The large-board workload at its full size (1048x792x88 cells, both PEC
     islands, 8 sources, 64 probes, 256 DFT frequencies) in the benchmark's tile:
     every field array, every probe series and the DFT against the oracle.  The
     sources fire inside the 200-step window (t0 = (24 + 4s) dt, sigma = 6 dt)."""
-    b = boardgen.config3(steps=200)
+    b = boardgen.large_board(steps=200)
     dt = orc.time_step(b)
     for s_idx, s in enumerate(b.sources):
         s.t0, s.sigma = (24 + 4 * s_idx) * dt, 6 * dt
     tile = _bench_tile(b)
-    announce(f"config3 full size {b.nx}x{b.ny}x{b.nz} steps={b.steps} tile={tile}: oracle")
+    announce(f"large board full size {b.nx}x{b.ny}x{b.nz} steps={b.steps} tile={tile}: oracle")
     ref = orc.run(b, threads=16)
-    announce("config3 full size: gpu")
+    announce("large board full size: gpu")
     probes, fields, dft, _ = gpu_run(F, b, tile=tile)
-    announce("config3 full size: compare")
+    announce("large board full size: compare")
     peak = np.abs(ref.probes).max()
     assert peak > 0
     checked = 0
@@ -220,22 +220,22 @@ def test_config3_full_size_from_zero(F, orc):
     assert rel_l2(dft, ref.dft) <= 1e-4
 
 
-def test_config3_full_size_random_state(F, orc):
+def test_large_board_full_size_random_state(F, orc):
     """Full-size large board from an arbitrary state (every live node and every
     kept D/B nonzero, so all PML slabs, edges, corners, island rims and tile
     seams are exercised), three steps in the benchmark's tile."""
-    b = boardgen.config3(steps=3)
+    b = boardgen.large_board(steps=3)
     b.sources, b.probes, b.dft_freqs = [], [], None
     tile = _bench_tile(b)
-    announce(f"config3 full size random state tile={tile}: setup")
+    announce(f"large board full size random state tile={tile}: setup")
     st = random_state(orc, b, seed=3)
     init = {n: st[n].copy() for n in FIELDS}
-    announce("config3 full size random state: oracle")
+    announce("large board full size random state: oracle")
     ref = orc.run(b, state=st, threads=16)
-    announce("config3 full size random state: gpu")
+    announce("large board full size random state: gpu")
     _, fields, _, _ = gpu_run(F, b, init=init, tile=tile)
     del init
-    announce("config3 full size random state: compare")
+    announce("large board full size random state: compare")
     compare_fields(ref.state, fields, b, 2e-5)
 
 
@@ -255,7 +255,7 @@ def test_tile_shapes_bitwise(F):
 
 
 def test_chunked_equals_single_call(F):
-    b = boardgen.config1(steps=240)
+    b = boardgen.small_board(steps=240)
     announce("chunked vs single")
     p1, f1, _, _ = gpu_run(F, b)
     p2, f2, _, _ = gpu_run(F, b, chunks=[1, 7, 100, 0, 132])
@@ -265,7 +265,7 @@ def test_chunked_equals_single_call(F):
 
 
 def test_checkpoint_resume_bitwise(F):
-    b = boardgen.config1(steps=300)
+    b = boardgen.small_board(steps=300)
     b.dft_freqs = np.linspace(1e9, 8e9, 16)
     announce("checkpoint/resume")
     g, ids = F.grid_from_board(b)
@@ -287,7 +287,7 @@ def test_checkpoint_resume_bitwise(F):
 
 
 def test_dft_and_probe_fft(F, orc):
-    b = boardgen.config1(steps=1500)
+    b = boardgen.small_board(steps=1500)
     b.dft_freqs = np.linspace(0.5e9, 12e9, 64)
     announce("dft + probe fft")
     ref = orc.run(b, threads=16)
@@ -315,7 +315,7 @@ def test_dft_and_probe_fft(F, orc):
 
 
 def test_info_and_state_errors(F):
-    b = boardgen.config1(steps=10)
+    b = boardgen.small_board(steps=10)
     g, ids = F.grid_from_board(b)
     info = F.fdtd_get_info(g)
     assert info.cells == b.nx * b.ny * b.nz and info.n_probes == 4 and info.n_sources == 1
@@ -334,7 +334,7 @@ def test_info_and_state_errors(F):
 def test_unstable_run_is_reported(F):
     """A source whose time integral exceeds the FP32 range drives Ez at the source
     edge to inf; the watchdog reports it at the next synchronising call."""
-    b = boardgen.config1(steps=300)
+    b = boardgen.small_board(steps=300)
     b.sources[0].J0 = 3e38
     g, ids = F.grid_from_board(b)
     F.fdtd_step_n(g, 300)
@@ -391,7 +391,7 @@ def test_step_many_bitwise_equals_alone(F):
 def test_graph_replays_match_eager(F):
     """Graph-replayed chunks (timing off) against eager launches (timing on), with
     synchronisation and host reads between every replay."""
-    b = boardgen.config1(steps=32 * 6)
+    b = boardgen.small_board(steps=32 * 6)
     ga, ida = F.grid_from_board(b)
     gb, idb = F.grid_from_board(b)
     F.fdtd_set_timing(gb, True)            # forces plain launches
@@ -410,7 +410,7 @@ def test_graph_replays_match_eager(F):
 
 
 def test_estimate_bytes_bounds_allocation(F):
-    for b in _small_variants(5, 3) + [boardgen.config1()]:
+    for b in _small_variants(5, 3) + [boardgen.small_board()]:
         est = F.board_bytes(b)
         g, _ = F.grid_from_board(b)
         F.fdtd_step_n(g, 1)

@@ -69,7 +69,7 @@ def test_served_results_equal_alone_and_oracle(F, oracle_mod):
 
 def test_autotuned_tile_keeps_results(F, tmp_path):
     from paper_1008_2602_amd import tune
-    b = boardgen.config1(steps=64)
+    b = boardgen.small_board(steps=64)
     path = str(tmp_path / "tiles.json")
     shape = tune.tune_board(b, path=path)
     assert shape in F.fdtd_tile_shapes()

@@ -318,7 +318,7 @@ def test_eq7_time_step_values(oracle_mod):
     assert abs(dtc - want) / want < 1e-15
     assert abs(dtc - 1.28389e-12) < 1e-17
     # config 1 at courant 0.99 -> 0.6355 ps
-    assert abs(oracle_mod.time_step(boardgen.config1()) - 0.6355e-12) < 1e-16
+    assert abs(oracle_mod.time_step(boardgen.small_board()) - 0.6355e-12) < 1e-16
     # the paper's 1 ps step is below the limit; 1.33 ps equals dz / c0
     assert 1e-12 < dtc and abs(0.4e-3 / C0 - 1.334e-12) < 1e-15
 
@@ -346,7 +346,7 @@ def test_eq5_grading_hand_values(oracle_mod):
     """sigma_max = -(m+1) ln R / (2 eta0 N delta): 9.168 S/m in x and 45.84 S/m in z
     for the 48 x 40 mm board (N = 8, 1 mm / 0.2 mm cells, m = 3, R = 1e-6); zero at
     the PML interface, sigma_max (depth/N)^3 inside, kappa = 1."""
-    b = boardgen.config1()
+    b = boardgen.small_board()
     sx_wall, kx = oracle_mod.sigma_kappa(b, 0, 0.0)
     sz_wall, _ = oracle_mod.sigma_kappa(b, 2, float(b.nz))
     assert abs(sx_wall - 9.1676) < 1e-3 and abs(sz_wall - 45.838) < 1e-2 and kx == 1.0
@@ -356,6 +356,6 @@ def test_eq5_grading_hand_values(oracle_mod):
     assert abs(s_half - sx_wall / 8) < 1e-12
     s_hi, _ = oracle_mod.sigma_kappa(b, 0, b.nx - 0.5)               # 7.5 cells deep, +x side
     assert abs(s_hi - sx_wall * (7.5 / 8) ** 3) < 1e-12
-    b2 = boardgen.config1()
+    b2 = boardgen.small_board()
     b2.pml_kappa_max = 5.0
     assert abs(oracle_mod.sigma_kappa(b2, 2, 2.0)[1] - (1 + 4 * (6 / 8) ** 3)) < 1e-12
