@@ -86,6 +86,7 @@ typedef struct {
     int32_t n_sources, n_probes, n_freqs;
     int32_t n_classes;           /* distinct per-node material classes after finalisation */
     int32_t tile_x, tile_y;      /* tile shape the field kernel runs with */
+    int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
 } fdtd_info;
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
@@ -182,16 +183,22 @@ int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes);
 /* Information about the handle (valid at any time). */
 int fdtd_get_info(fdtd_grid* g, fdtd_info* out);
 
-/* Tile shape of the field kernel, (tile_x, tile_y) from fdtd_tile_shapes(): a
- * block of tile_x*tile_y + 64 threads advances tile_x columns (aligned to 128
- * bytes of the padded device rows) by tile_y-1 rows, recomputing H on one halo
- * row and one halo column.  Results do not depend on it (bitwise).  May be
- * changed between steps; EINVAL for an unsupported shape. */
-int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y);
+/* Tile shape of the field kernel, (tile_x, tile_y, steps) from
+ * fdtd_tile_shapes() (Model section: the leapfrog of Eqs. 1-4, fused per pass).
+ *   steps = 1: a block of tile_x*tile_y + 64 threads advances tile_x columns
+ *     (aligned to 128 bytes of the padded device rows) by tile_y-1 rows through
+ *     one full step, recomputing H on one halo row and one halo column.
+ *   steps = 2: a block of 64*tile_y + 128 threads advances 64 columns by
+ *     tile_y-3 rows through two full steps in one pass over memory; the first
+ *     step is recomputed on a two-cell halo and never stored.  An odd step count
+ *     ends with one step of the 64x15 one-step shape.
+ * Results do not depend on the shape (bitwise).  May be changed between steps;
+ * EINVAL for an unsupported shape.  The default is the two-step 64x10. */
+int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y, int steps);
 
-/* Supported tile shapes: writes up to `cap` pairs into xy (host, 2*cap ints) and
- * returns the number of shapes. */
-int fdtd_tile_shapes(int* xy, int cap);
+/* Supported tile shapes: writes up to `cap` triples (tile_x, tile_y, steps) into
+ * xys (host, 3*cap ints) and returns the number of shapes. */
+int fdtd_tile_shapes(int* xys, int cap);
 
 /* Kernel timing for measurement: while on, every launch of the field kernel is
  * bracketed by HIP events on the stream it runs on.  fdtd_get_timing synchronises

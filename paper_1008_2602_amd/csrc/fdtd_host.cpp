@@ -21,10 +21,15 @@ namespace fdtd {
 int num_shapes();
 void shape_at(int s, int* tx, int* ty);
 hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards, const TileRef* tiles,
-                             int ntiles, int rel, bool wide, hipStream_t st);
+                             int ntiles, int rel, int flip, bool wide, hipStream_t st);
 int field_step_occupancy(int tile_x, int tile_y, bool wide);
+int num_shapes2();
+void shape2_at(int s, int* tx, int* ty);
+hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
+                              int rel, int flip, bool wide, hipStream_t st);
+int field_step2_occupancy(int tile_y, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
-hipError_t launch_advance_one(int64_t* step, int64_t n, hipStream_t st);
+hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
 hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
                       double dt, int64_t s0, int64_t s1, double* re, double* im, hipStream_t st);
 hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
@@ -101,7 +106,7 @@ struct fdtd_grid {
 
     // device state
     float* f[2][9] = {};
-    float* dd[3] = {};
+    float* dd[2][3] = {};
     float* coef[3] = {};
     void* cls = nullptr;
     ClassEntry* ctab = nullptr;
@@ -115,8 +120,12 @@ struct fdtd_grid {
     int64_t* step_dev = nullptr;
     int32_t* bad_dev = nullptr;
     BoardDev* board_dev = nullptr;
-    TileRef* tiles_dev = nullptr;
+    TileRef* tiles_dev = nullptr;   // work list of the current tile shape
     int ntiles = 0;
+    TileRef* tiles1_dev = nullptr;  // one-step list for the odd step of a two-step shape
+    int ntiles1 = 0;
+    int tiles1_cap = 0;
+    int buf = 0;                    // field buffer (0/1) holding the current step
     int tiles_cap = 0;
     BoardDev board_host{};
 
@@ -131,7 +140,7 @@ struct fdtd_grid {
     bool wide = false;
     bool finalized = false;
     int64_t step = 0;
-    int tile_x = 64, tile_y = 15;
+    int tile_x = 64, tile_y = 10, tile_steps = 2;
     int cus = 0;            // compute units of the device
     int64_t step_bytes = 0;
 
@@ -215,11 +224,26 @@ hipError_t copy_field_sync(fdtd_grid* g, void* dst, const void* src, hipMemcpyKi
 
 int64_t row_pitch(int nx) { return ((int64_t)nx + 1 + 31) / 32 * 32; }
 
-// Tiles of a TX x TY block: TX aligned columns each, TY-1 rows each (one halo row)
-void tile_counts(int nx, int ny, int tx, int ty, int* cx, int* cy)
+// Owned rows of a tile: the one-step kernel spends one row of its TY on the halo,
+// the two-step kernel three.
+int owned_rows(int ty, int steps) { return steps == 2 ? ty - 3 : ty - 1; }
+
+// The one-step shape that takes the odd step of a two-step shape.
+constexpr int kOddX = 64, kOddY = 15;
+
+// Tiles of a shape: tx aligned columns and `rows` owned rows each
+void tile_counts(int nx, int ny, int tx, int rows, int* cx, int* cy)
 {
     *cx = (nx + 1 + tx - 1) / tx;
-    *cy = (ny + 1 + ty - 2) / (ty - 1);
+    *cy = (ny + 1 + rows - 1) / rows;
+}
+
+// One launch of the field kernel of a shape (one or two steps per pass).
+hipError_t launch_pass(int tx, int ty, int steps, const BoardDev* boards, const TileRef* tiles,
+                       int ntiles, int rel, int flip, bool wide, hipStream_t st)
+{
+    if (steps == 2) return launch_field_step2(ty, boards, tiles, ntiles, rel, flip, wide, st);
+    return launch_field_step(tx, ty, boards, tiles, ntiles, rel, flip, wide, st);
 }
 
 constexpr int kXcds = 8;   // the kernel deals block b to XCD b % 8 (xcd_tile)
@@ -290,17 +314,18 @@ void build_work(const std::vector<TileRef>& tiles, int slots_per_xcd, std::vecto
 }
 
 // Whole tiles of board b (row-major), all planes.
-void board_tiles(int b, int nx, int ny, int nz, int tx, int ty, std::vector<TileRef>& out)
+void board_tiles(int b, int nx, int ny, int nz, int tx, int rows, std::vector<TileRef>& out)
 {
     int cx, cy;
-    tile_counts(nx, ny, tx, ty, &cx, &cy);
+    tile_counts(nx, ny, tx, rows, &cx, &cy);
     for (int y = 0; y < cy; ++y)
         for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz + 1});
 }
 
-int slots_per_xcd(const fdtd_grid* g, int tx, int ty, bool wide)
+int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide)
 {
-    return std::max(1, g->cus / kXcds) * field_step_occupancy(tx, ty, wide);
+    const int occ = steps == 2 ? field_step2_occupancy(ty, wide) : field_step_occupancy(tx, ty, wide);
+    return std::max(1, g->cus / kXcds) * occ;
 }
 
 void dev_free_all(fdtd_grid* g)
@@ -552,7 +577,8 @@ int finalize(fdtd_grid* g)
     for (int p = 0; p < 2; ++p)
         for (int c = 0; c < 9; ++c) b.f[p][c] = g->f[p][c];
     for (int c = 0; c < 3; ++c) {
-        b.d[c] = g->dd[c];
+        b.d[0][c] = g->dd[0][c];
+        b.d[1][c] = g->dd[1][c];
         b.coef[c] = g->coef[c];
     }
     b.cls = g->cls;
@@ -609,11 +635,17 @@ extern "C" {
 
 const char* fdtd_last_error(void) { return g_err.c_str(); }
 
-int fdtd_tile_shapes(int* xy, int cap)
+int fdtd_tile_shapes(int* xys, int cap)
 {
-    const int n = num_shapes();
-    for (int s = 0; s < n && s < cap; ++s) shape_at(s, &xy[2 * s], &xy[2 * s + 1]);
-    return n;
+    const int n1 = num_shapes(), n2 = num_shapes2();
+    for (int q = 0; q < n1 + n2 && q < cap; ++q) {
+        if (q < n1)
+            shape_at(q, &xys[3 * q], &xys[3 * q + 1]);
+        else
+            shape2_at(q - n1, &xys[3 * q], &xys[3 * q + 1]);
+        xys[3 * q + 2] = q < n1 ? 1 : 2;
+    }
+    return n1 + n2;
 }
 
 int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
@@ -689,16 +721,18 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
         for (int c = 0; c < 9; ++c)
             if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
                 return bail(FDTD_ENOMEM, "field allocation failed");
-    for (int c = 0; c < 3; ++c)
-        if (!(g->dd[c] = (float*)dev_alloc(g, (size_t)padded * 4)))
-            return bail(FDTD_ENOMEM, "field allocation failed");
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 3; ++c)
+            if (!(g->dd[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
+                return bail(FDTD_ENOMEM, "field allocation failed");
     for (int p = 0; p < 2; ++p)
         for (int c = 0; c < 9; ++c)
             if (launch_fill_zero(g->f[p][c], padded, g->stream) != hipSuccess)
                 return bail(FDTD_EDEVICE, "zero fill failed");
-    for (int c = 0; c < 3; ++c)
-        if (launch_fill_zero(g->dd[c], padded, g->stream) != hipSuccess)
-            return bail(FDTD_EDEVICE, "zero fill failed");
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 3; ++c)
+            if (launch_fill_zero(g->dd[p][c], padded, g->stream) != hipSuccess)
+                return bail(FDTD_EDEVICE, "zero fill failed");
     for (int a = 0; a < 3; ++a) {
         std::vector<float> t = coef_table(d, a, dt);
         if (!(g->coef[a] = (float*)dev_alloc(g, t.size() * 4)))
@@ -708,10 +742,10 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
             hipStreamSynchronize(g->stream) != hipSuccess)
             return bail(FDTD_EDEVICE, "coefficient upload failed");
     }
-    g->step_dev = (int64_t*)dev_alloc(g, 8);
+    g->step_dev = (int64_t*)dev_alloc(g, 16);   // step count, field buffer index
     g->bad_dev = (int32_t*)dev_alloc(g, 4);
     if (!g->step_dev || !g->bad_dev) return bail(FDTD_ENOMEM, "counter allocation failed");
-    if (launch_fill_zero((float*)g->step_dev, 2, g->stream) != hipSuccess ||
+    if (launch_fill_zero((float*)g->step_dev, 4, g->stream) != hipSuccess ||
         launch_fill_zero((float*)g->bad_dev, 1, g->stream) != hipSuccess ||
         hipStreamSynchronize(g->stream) != hipSuccess)
         return bail(FDTD_EDEVICE, "counter init failed");
@@ -779,23 +813,36 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
     return FDTD_OK;
 }
 
+// Work list of the handle's board for a shape, in device memory (reallocated when
+// it grows).
+static int upload_list(fdtd_grid* g, int tx, int ty, int steps, TileRef** dev, int* n, int* cap)
+{
+    std::vector<TileRef> whole, tl;
+    board_tiles(0, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, steps), whole);
+    build_work(whole, slots_per_xcd(g, tx, ty, steps, g->wide), tl);
+    const int nt = (int)tl.size();
+    if (nt > *cap) {
+        *dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
+        if (!*dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
+        *cap = nt;
+    }
+    HIP_OR_FAIL(copy_sync(g, *dev, tl.data(), tl.size() * sizeof(TileRef), hipMemcpyHostToDevice));
+    *n = nt;
+    return FDTD_OK;
+}
+
 static int upload_tiles(fdtd_grid* g)
 {
     BoardDev& b = g->board_host;
-    tile_counts(g->d.nx, g->d.ny, g->tile_x, g->tile_y, &b.tiles_x, &b.tiles_y);
-    std::vector<TileRef> whole, tl;
-    board_tiles(0, g->d.nx, g->d.ny, g->d.nz, g->tile_x, g->tile_y, whole);
-    build_work(whole, slots_per_xcd(g, g->tile_x, g->tile_y, g->wide), tl);
-    const int nt = (int)tl.size();
-    if (nt > g->tiles_cap) {
-        g->tiles_dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
-        if (!g->tiles_dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
-        g->tiles_cap = nt;
-    }
-    HIP_OR_FAIL(copy_sync(g, g->tiles_dev, tl.data(), tl.size() * sizeof(TileRef),
-                          hipMemcpyHostToDevice));
+    tile_counts(g->d.nx, g->d.ny, g->tile_x, owned_rows(g->tile_y, g->tile_steps), &b.tiles_x,
+                &b.tiles_y);
+    if (int e = upload_list(g, g->tile_x, g->tile_y, g->tile_steps, &g->tiles_dev, &g->ntiles,
+                            &g->tiles_cap))
+        return e;
+    if (g->tile_steps == 2)
+        if (int e = upload_list(g, kOddX, kOddY, 1, &g->tiles1_dev, &g->ntiles1, &g->tiles1_cap))
+            return e;
     HIP_OR_FAIL(copy_sync(g, g->board_dev, &b, sizeof(BoardDev), hipMemcpyHostToDevice));
-    g->ntiles = nt;
     if (g->graph_exec) {
         (void)hipGraphExecDestroy(g->graph_exec);
         g->graph_exec = nullptr;
@@ -804,39 +851,68 @@ static int upload_tiles(fdtd_grid* g)
     return FDTD_OK;
 }
 
-int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y)
+int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y, int steps)
 {
     if (int e = check_grid(g)) return e;
-    const int n = num_shapes();
-    for (int s = 0; s < n; ++s) {
-        int tx, ty;
-        shape_at(s, &tx, &ty);
-        if (tx == tile_x && ty == tile_y) {
-            g->tile_x = tx;
-            g->tile_y = ty;
-            return g->finalized ? upload_tiles(g) : FDTD_OK;
+    bool found = false;
+    if (steps == 1) {
+        for (int q = 0; q < num_shapes() && !found; ++q) {
+            int tx, ty;
+            shape_at(q, &tx, &ty);
+            found = tx == tile_x && ty == tile_y;
+        }
+    } else if (steps == 2) {
+        for (int q = 0; q < num_shapes2() && !found; ++q) {
+            int tx, ty;
+            shape2_at(q, &tx, &ty);
+            found = tx == tile_x && ty == tile_y;
         }
     }
-    return fail(FDTD_EINVAL, "unsupported tile shape %dx%d", tile_x, tile_y);
+    if (!found)
+        return fail(FDTD_EINVAL, "unsupported tile shape %dx%d with %d steps per pass", tile_x,
+                    tile_y, steps);
+    g->tile_x = tile_x;
+    g->tile_y = tile_y;
+    g->tile_steps = steps;
+    return g->finalized ? upload_tiles(g) : FDTD_OK;
 }
 
-static int enqueue_steps(fdtd_grid* g, int64_t s0, int64_t n)
+// One field launch of the handle's shape (two steps, or one with the odd-step
+// shape when `single`), optionally bracketed by timing events.
+static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
 {
-    for (int64_t s = s0; s < s0 + n; ++s) {
-        if (g->timing)
-            if (int e = record_event(g)) return e;
-        HIP_OR_FAIL(launch_field_step(g->tile_x, g->tile_y, g->board_dev, g->tiles_dev, g->ntiles,
-                                      (int)s, g->wide, g->stream));
-        if (g->timing) {
-            if (int e = record_event(g)) return e;
-            ++g->timed_launches;
-        }
+    if (g->timing)
+        if (int e = record_event(g)) return e;
+    if (single && g->tile_steps == 2)
+        HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, g->board_dev, g->tiles1_dev, g->ntiles1, rel, flip,
+                                g->wide, g->stream));
+    else
+        HIP_OR_FAIL(launch_pass(g->tile_x, g->tile_y, g->tile_steps, g->board_dev, g->tiles_dev,
+                                g->ntiles, rel, flip, g->wide, g->stream));
+    if (g->timing) {
+        if (int e = record_event(g)) return e;
+        ++g->timed_launches;
     }
     return FDTD_OK;
 }
 
-// Capture kGraphChunk field launches and the counter advance into one graph.
-// The kernels take the step from the device counter, so the same graph serves
+// Enqueue n steps as launches of the handle's shape (two-step shapes end with
+// one single step when n is odd); returns the launch count through *launches.
+static int enqueue_steps(fdtd_grid* g, int64_t n, int64_t* launches)
+{
+    const int per = g->tile_steps;
+    int64_t l = 0, s = 0;
+    for (; s + per <= n; s += per, ++l)
+        if (int e = enqueue_launch(g, false, (int)s, (int)(l & 1))) return e;
+    for (; s < n; ++s, ++l)
+        if (int e = enqueue_launch(g, true, (int)s, (int)(l & 1))) return e;
+    *launches = l;
+    return FDTD_OK;
+}
+
+// Capture the launches of kGraphChunk steps and the counter advance into one
+// graph.  The kernels take the step and the field buffer from the device
+// counters, and a chunk has an even number of launches, so the same graph serves
 // every chunk.  Any failure leaves plain launches in use.
 static void build_graph(fdtd_grid* g)
 {
@@ -846,10 +922,11 @@ static void build_graph(fdtd_grid* g)
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
     bool ok = true;
-    for (int s = 0; s < kGraphChunk && ok; ++s)
-        ok = launch_field_step(g->tile_x, g->tile_y, g->board_dev, g->tiles_dev, g->ntiles, s,
-                               g->wide, g->stream) == hipSuccess;
-    if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, g->stream) == hipSuccess;
+    const int per = g->tile_steps, nl = kGraphChunk / per;
+    for (int l = 0; l < nl && ok; ++l)
+        ok = launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev, g->ntiles, l * per,
+                         l & 1, g->wide, g->stream) == hipSuccess;
+    if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, nl, g->stream) == hipSuccess;
     const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
     if (ok && ended && graph &&
         hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess)
@@ -869,25 +946,30 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
                     (long long)(g->step + n), (long long)g->d.max_steps);
     if (int e = finalize(g)) return e;
     if (n == 0) return FDTD_OK;
-    int64_t done = 0;
+    int64_t done = 0, launches = 0;
     if (!g->timing && n >= kGraphChunk) {
         build_graph(g);
         if (g->graph_exec) {
-            for (; done + kGraphChunk <= n; done += kGraphChunk)
+            for (; done + kGraphChunk <= n; done += kGraphChunk) {
                 HIP_OR_FAIL(hipGraphLaunch(g->graph_exec, g->stream));
+                launches += kGraphChunk / g->tile_steps;
+            }
         }
     }
     if (done < n) {
-        // kernels add the launch-relative step to the device counter, which the
-        // graphs above have already advanced
-        if (int e = enqueue_steps(g, 0, n - done)) return e;
-        HIP_OR_FAIL(launch_advance_one(g->step_dev, n - done, g->stream));
+        // kernels add the launch-relative step and buffer to the device counters,
+        // which the graphs above have already advanced
+        int64_t l = 0;
+        if (int e = enqueue_steps(g, n - done, &l)) return e;
+        HIP_OR_FAIL(launch_advance_one(g->step_dev, n - done, l, g->stream));
+        launches += l;
     }
     if (g->dft_f)
         HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
                                (int)g->probes.size(), g->dt, g->step, g->step + n, g->dft_re,
                                g->dft_im, g->stream));
     g->step += n;
+    g->buf = (int)((g->buf + launches) & 1);
     return FDTD_OK;
 }
 
@@ -913,9 +995,9 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         if (int e = finalize(gs[h])) return e;
     fdtd_grid* lead = gs[0];
     hipStream_t st = lead->stream;
-    const int tx = lead->tile_x, ty = lead->tile_y;
+    const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
 
-    // order boards by step count (descending): at step s the boards still running
+    // order boards by step count (descending): at pass s the boards still running
     // form a prefix, and so do their tiles; narrow and wide class maps go to
     // separate launches (the kernel is specialised on the class index width)
     std::vector<int> order(ng);
@@ -924,21 +1006,32 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         if (gs[a]->wide != gs[b]->wide) return gs[a]->wide < gs[b]->wide;
         return n[a] > n[b];
     });
-    std::vector<BoardDev> boards(ng);
-    std::vector<int64_t> nn(ng);
-    int64_t max_n = 0;
+    // board b runs np[b] passes of `per` steps, then (two-step shapes) one single
+    // step when its count is odd.  boards[ng + b] is the copy the single-step
+    // launch reads: its step and buffer offsets skip the board's own passes.
+    std::vector<BoardDev> boards(2 * (size_t)ng);
+    std::vector<int64_t> np(ng), odd(ng), adv(2 * (size_t)ng);
+    int64_t max_np = 0;
     for (int b = 0; b < ng; ++b) {
+        const int64_t nb = n[order[b]];
+        np[b] = nb / per;
+        odd[b] = nb - np[b] * per;
+        max_np = std::max(max_np, np[b]);
         boards[b] = gs[order[b]]->board_host;
-        nn[b] = n[order[b]];
-        max_n = std::max(max_n, nn[b]);
+        boards[ng + b] = boards[b];
+        boards[ng + b].rel0 = (int32_t)(np[b] * per);
+        boards[ng + b].flip0 = (int32_t)(np[b] & 1);
+        adv[2 * b] = nb;
+        adv[2 * b + 1] = np[b] + odd[b];
     }
-    // Each class width forms a group [b0, b1) of the order; at step s the boards
+    // Each class width forms a group [b0, b1) of the order; at pass s the boards
     // still running are a prefix [b0, active) of it.  One balanced work list per
-    // distinct prefix, all in one device buffer.
+    // distinct prefix, plus one for the single-step tail, all in one buffer.
     struct Span {
-        int w;
-        int64_t s0, s1;  // steps s0 .. s1-1 run this list
+        int w, steps;
+        int64_t s0, s1;   // passes s0 .. s1-1 run this list
         int off, count;
+        bool tail;        // the single-step launch (reads boards[ng..])
     };
     std::vector<Span> spans;
     std::vector<TileRef> items, whole, list;
@@ -949,26 +1042,37 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         int b1 = b0;
         while (b1 < ng && gs[order[b1]]->wide == (w == 1)) ++b1;
         int64_t s = 0;
-        for (int active = b1; active > b0 && s < max_n;) {
-            const int64_t s_end = nn[active - 1];  // boards [b0, active) all run through s_end
+        for (int active = b1; active > b0 && s < max_np;) {
+            const int64_t s_end = np[active - 1];  // boards [b0, active) all run through s_end
             if (s_end > s) {
                 whole.clear();
                 for (int b = b0; b < active; ++b) {
                     const fdtd_grid* g = gs[order[b]];
-                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, ty, whole);
+                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, per), whole);
                 }
-                build_work(whole, slots_per_xcd(lead, tx, ty, w == 1), list);
-                spans.push_back(Span{w, s, s_end, (int)items.size(), (int)list.size()});
+                build_work(whole, slots_per_xcd(lead, tx, ty, per, w == 1), list);
+                spans.push_back(Span{w, per, s, s_end, (int)items.size(), (int)list.size(), false});
                 items.insert(items.end(), list.begin(), list.end());
                 s = s_end;
             }
             --active;
         }
+        whole.clear();
+        for (int b = b0; b < b1; ++b)
+            if (odd[b]) {
+                const fdtd_grid* g = gs[order[b]];
+                board_tiles(b, g->d.nx, g->d.ny, g->d.nz, kOddX, owned_rows(kOddY, 1), whole);
+            }
+        if (!whole.empty()) {
+            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1), list);
+            spans.push_back(Span{w, 1, 0, 1, (int)items.size(), (int)list.size(), true});
+            items.insert(items.end(), list.begin(), list.end());
+        }
     }
     // device scratch held by the lead handle
     if (lead->batch_boards_cap < ng) {
-        lead->batch_boards = (BoardDev*)dev_alloc(lead, sizeof(BoardDev) * (size_t)ng);
-        lead->batch_n = (int64_t*)dev_alloc(lead, sizeof(int64_t) * (size_t)ng);
+        lead->batch_boards = (BoardDev*)dev_alloc(lead, sizeof(BoardDev) * 2 * (size_t)ng);
+        lead->batch_n = (int64_t*)dev_alloc(lead, sizeof(int64_t) * 2 * (size_t)ng);
         if (!lead->batch_boards || !lead->batch_n) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
         lead->batch_boards_cap = ng;
     }
@@ -984,19 +1088,29 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         HIP_OR_FAIL(hipEventRecord(gs[h]->sync_ev, gs[h]->stream));
         HIP_OR_FAIL(hipStreamWaitEvent(st, gs[h]->sync_ev, 0));
     }
-    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_boards, boards.data(), sizeof(BoardDev) * (size_t)ng,
+    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_boards, boards.data(), sizeof(BoardDev) * boards.size(),
                                hipMemcpyHostToDevice, st));
     if (!items.empty())
         HIP_OR_FAIL(hipMemcpyAsync(lead->batch_tiles, items.data(), sizeof(TileRef) * items.size(),
                                    hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, nn.data(), sizeof(int64_t) * (size_t)ng,
+    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, adv.data(), sizeof(int64_t) * adv.size(),
                                hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));  // the host arrays above are locals
-    for (const Span& sp : spans)
-        for (int64_t s = sp.s0; s < sp.s1; ++s)
-            HIP_OR_FAIL(launch_field_step(tx, ty, lead->batch_boards, lead->batch_tiles + sp.off,
-                                          sp.count, (int)s, sp.w == 1, st));
+    for (const Span& sp : spans) {
+        if (sp.tail) {
+            HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, lead->batch_boards + ng,
+                                    lead->batch_tiles + sp.off, sp.count, 0, 0, sp.w == 1, st));
+            continue;
+        }
+        for (int64_t q = sp.s0; q < sp.s1; ++q)
+            HIP_OR_FAIL(launch_pass(tx, ty, sp.steps, lead->batch_boards, lead->batch_tiles + sp.off,
+                                    sp.count, (int)(q * sp.steps), (int)(q & 1), sp.w == 1, st));
+    }
     HIP_OR_FAIL(launch_advance(lead->batch_boards, ng, lead->batch_n, st));
+    for (int b = 0; b < ng; ++b) {
+        fdtd_grid* g = gs[order[b]];
+        g->buf = (int)((g->buf + adv[2 * b + 1]) & 1);
+    }
     for (int h = 0; h < ng; ++h) {
         fdtd_grid* g = gs[h];
         if (g->dft_f && n[h] > 0)
@@ -1020,7 +1134,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
         return fail(FDTD_EINVAL, "bad descriptor or counts");
     auto r = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nodes = row_pitch(d->nx) * (d->ny + 1) * (d->nz + 1);      // padded rows
-    int64_t t = 21 * r((nodes + kGuard) * 4);                                   // fields
+    int64_t t = 24 * r((nodes + kGuard) * 4);                                   // fields
     t += r(2 * (nodes + kGuard));                                               // class map (upper bound)
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
     t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +
@@ -1029,7 +1143,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     t += r(4 * (int64_t)n_probes) + r(4 * (int64_t)n_probes * d->max_steps);     // probes
     t += r(8 * (int64_t)n_freqs) + 2 * r(8 * (int64_t)n_probes * n_freqs);       // DFT
     const int64_t max_tiles = ((d->nx + 64) / 64) * ((d->ny + 3) / 3);         // 64 x 4, the most tiles
-    const int64_t max_items = kXcds * (max_tiles + 7 * 256);                    // pieces and padding
+    const int64_t max_items = 2 * kXcds * (max_tiles + 7 * 256);                // two lists, pieces, padding
     t += 8 * 256 + r(sizeof(BoardDev)) + r(sizeof(TileRef) * max_items);        // small buffers
     return t;
 }
@@ -1117,9 +1231,9 @@ static double field_scale(int comp)
 
 static float* comp_ptr(fdtd_grid* g, int comp)
 {
-    const int par = (int)(g->step & 1);
+    const int par = g->buf;
     if (comp <= FDTD_HZ) return g->f[par][comp];
-    if (comp <= FDTD_DZ) return g->dd[comp - FDTD_DX];
+    if (comp <= FDTD_DZ) return g->dd[g->buf][comp - FDTD_DX];
     return g->f[par][6 + comp - FDTD_BX];
 }
 
@@ -1251,6 +1365,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->n_classes = g->n_classes;
     out->tile_x = g->tile_x;
     out->tile_y = g->tile_y;
+    out->tile_steps = g->tile_steps;
     return FDTD_OK;
 }
 

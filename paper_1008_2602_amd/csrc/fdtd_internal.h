@@ -44,9 +44,11 @@ struct ClassEntry {
 // Everything one field launch needs about one board.  Lives in device memory
 // (an array of these for batched launches).
 struct BoardDev {
-    // state: [parity][0..8] = Ex Ey Ez Hx Hy Hz Bx By Bz ; D in place
+    // state: [buffer][0..8] = Ex Ey Ez Hx Hy Hz Bx By Bz and [buffer][0..2] =
+    // Dx Dy Dz.  Every launch reads one buffer and writes the other (one or two
+    // steps per launch), so a block may read any neighbour's fields as they were
     float* f[2][9];
-    float* d[3];
+    float* d[2][3];
     const void* cls;             // uint8_t or uint16_t per node
     const ClassEntry* ctab;
     const float* coef[3];        // per axis: [kind][node/half][n+1]
@@ -54,7 +56,7 @@ struct BoardDev {
     const float* src_j;          // [nsrc][max_steps] Js samples
     const int32_t* prb_node;
     float* prb_series;           // [nprb][max_steps]
-    int64_t* step;               // device step counter (completed steps)
+    int64_t* step;               // [0] completed steps, [1] buffer (0/1) holding the fields
     int32_t* bad;                // watchdog flag
     int32_t nx, ny, nz;
     int32_t pitch;               // row pitch in nodes: nx+1 rounded up to 32 (128 bytes)
@@ -64,6 +66,9 @@ struct BoardDev {
     int64_t max_steps;
     float crd_x, crd_y, crd_z;
     int32_t tiles_x, tiles_y;
+    // added to a launch's step and buffer offsets (nonzero only in the one-step
+    // tail launch of a batch, whose boards have done different numbers of pairs)
+    int32_t rel0, flip0;
 };
 
 // One work item of the field kernel: tile (tx, ty) of a board, planes kb..ke-1.

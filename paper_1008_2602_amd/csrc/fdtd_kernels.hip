@@ -15,39 +15,24 @@
 //      planes k (LDS) and k-1 (registers).
 // Staging loads run two planes ahead and column operands one plane ahead; the
 // plane loop is unrolled by two so no register in flight is ever moved.
-// State is ping-ponged (E, H, B read from one copy, written to the other) so
-// halo recomputation never sees a neighbour's already-updated values; D is only
-// read by its owner and is updated in place.  D and B are stored and moved only
-// where a PML loss acts on them (elsewhere the update reduces to plain Yee with
-// those terms exactly zero).  Sources and probes are folded into the same pass
-// through per-node material classes.
+// State is ping-ponged (E, H, B and D read from one copy, written to the other)
+// so halo recomputation never sees a neighbour's already-updated values.  D and
+// B are stored and moved only where a PML loss acts on them (elsewhere the
+// update reduces to plain Yee with those terms exactly zero).  Sources and
+// probes are folded into the same pass through per-node material classes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fdtd_device.h"
 #include "fdtd_internal.h"
 
 namespace fdtd {
 
-// Global-address-space views of the board's buffers: loads and stores through
-// them are global_* instructions (counted in vmcnt only), so LDS barriers never
-// wait on outstanding HBM traffic.
-typedef __attribute__((address_space(1))) float gfloat;
-typedef __attribute__((address_space(1))) const float cgfloat;
-typedef __attribute__((address_space(4))) const float kfloat;  // uniform, scalar loads
-
-// Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks
-// a contiguous run of the tile list (neighbouring tiles share halos in its L2).
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int x = b & 7, slot = b >> 3;
-    const int q = nb >> 3, r = nb & 7;
-    return x * q + min(x, r) + slot;
-}
 
 template <int TX, int TY, typename CT>
 __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __restrict__ boards,
                                                           const TileRef* __restrict__ tiles,
-                                                          int rel)
+                                                          int rel, int flip)
 {
     static_assert(TX % 64 == 0 && TY + 1 <= 32 && TX * TY + 64 <= 1024, "tile shape");
     // LDS staging: columns i0-1 .. i0+TX (index c = i - i0 + 1), rows j0-1 .. j0-1+TY
@@ -81,8 +66,8 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
     const int kb = t.kb, ke = t.ke, k0 = kb > 0 ? kb - 1 : 0;
     const bool col_ok = main_wave && (i <= nx) && (j >= 0) && (j <= ny);
     const bool own = col_ok && ty > 0;
-    const int64_t step = *B.step + rel;
-    const int par = (int)(step & 1);
+    const int64_t step = B.step[0] + B.rel0 + rel;
+    const int par = (int)((B.step[1] + B.flip0 + flip) & 1);
     cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
     cgfloat* __restrict__ gEy = (cgfloat*)B.f[par][1];
     cgfloat* __restrict__ gEz = (cgfloat*)B.f[par][2];
@@ -101,9 +86,12 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
     gfloat* __restrict__ dBx = (gfloat*)B.f[par ^ 1][6];
     gfloat* __restrict__ dBy = (gfloat*)B.f[par ^ 1][7];
     gfloat* __restrict__ dBz = (gfloat*)B.f[par ^ 1][8];
-    gfloat* __restrict__ Dx = (gfloat*)B.d[0];
-    gfloat* __restrict__ Dy = (gfloat*)B.d[1];
-    gfloat* __restrict__ Dz = (gfloat*)B.d[2];
+    cgfloat* __restrict__ Dx = (cgfloat*)B.d[par][0];
+    cgfloat* __restrict__ Dy = (cgfloat*)B.d[par][1];
+    cgfloat* __restrict__ Dz = (cgfloat*)B.d[par][2];
+    gfloat* __restrict__ dDx = (gfloat*)B.d[par ^ 1][0];
+    gfloat* __restrict__ dDy = (gfloat*)B.d[par ^ 1][1];
+    gfloat* __restrict__ dDz = (gfloat*)B.d[par ^ 1][2];
     const __attribute__((address_space(1))) CT* __restrict__ cls =
         (const __attribute__((address_space(1))) CT*)B.cls;
     const __attribute__((address_space(1))) ClassEntry* __restrict__ ctab =
@@ -273,9 +261,9 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                 dEx[node] = exn;
                 dEy[node] = eyn;
                 dEz[node] = ezn;
-                if (nbx && (ce.flags & kUpdEx)) Dx[node] = o.dx + ddx;
-                if (nby && (ce.flags & kUpdEy)) Dy[node] = o.dy + ddy;
-                if (nbz && (ce.flags & kUpdEz)) Dz[node] = o.dz + ddz;
+                if (nbx) dDx[node] = (ce.flags & kUpdEx) ? o.dx + ddx : o.dx;
+                if (nby) dDy[node] = (ce.flags & kUpdEy) ? o.dy + ddy : o.dy;
+                if (nbz) dDz[node] = (ce.flags & kUpdEz) ? o.dz + ddz : o.dz;
                 if (ce.flags & kPrbEz) {
                     const __attribute__((address_space(1))) int32_t* pn =
                         (const __attribute__((address_space(1))) int32_t*)B.prb_node;
@@ -397,15 +385,23 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
 }
 
 // Advance each board's device step counter by n after a batch of launches.
+// Advance each board's device counters after a batch of launches: n[2b] steps
+// done in n[2b+1] launches (each launch swaps the field buffers).
 __global__ void advance_steps(BoardDev* boards, int nb, const int64_t* n)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nb) *boards[b].step += n[b];
+    if (b < nb) {
+        boards[b].step[0] += n[2 * b];
+        boards[b].step[1] = (boards[b].step[1] + n[2 * b + 1]) & 1;
+    }
 }
 
-__global__ void advance_one(int64_t* step, int64_t n)
+__global__ void advance_one(int64_t* step, int64_t n, int64_t launches)
 {
-    if (threadIdx.x == 0) *step += n;
+    if (threadIdx.x == 0) {
+        step[0] += n;
+        step[1] = (step[1] + launches) & 1;
+    }
 }
 
 // Running DFT (FP64): for probe p and frequency q add the samples s in [s0, s1):
@@ -489,14 +485,14 @@ void shape_at(int s, int* tx, int* ty)
 
 template <int TX, int TY>
 static hipError_t launch_tt(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel,
-                            bool wide, hipStream_t st)
+                            int flip, bool wide, hipStream_t st)
 {
     if (wide)
         hipLaunchKernelGGL((field_step<TX, TY, uint16_t>), dim3(ntiles), dim3(TX * TY + 64), 0, st,
-                           boards, tiles, rel);
+                           boards, tiles, rel, flip);
     else
         hipLaunchKernelGGL((field_step<TX, TY, uint8_t>), dim3(ntiles), dim3(TX * TY + 64), 0, st,
-                           boards, tiles, rel);
+                           boards, tiles, rel, flip);
     return hipGetLastError();
 }
 
@@ -523,11 +519,11 @@ int field_step_occupancy(int tile_x, int tile_y, bool wide)
 }
 
 hipError_t launch_field_step(int tile_x, int tile_y, const BoardDev* boards,
-                             const TileRef* tiles, int ntiles, int rel, bool wide,
+                             const TileRef* tiles, int ntiles, int rel, int flip, bool wide,
                              hipStream_t st)
 {
 #define SHAPE(X, Y) \
-    if (tile_x == X && tile_y == Y) return launch_tt<X, Y>(boards, tiles, ntiles, rel, wide, st);
+    if (tile_x == X && tile_y == Y) return launch_tt<X, Y>(boards, tiles, ntiles, rel, flip, wide, st);
     SHAPE(64, 15) SHAPE(64, 12) SHAPE(64, 8) SHAPE(64, 4) SHAPE(64, 10) SHAPE(64, 14)
     SHAPE(128, 7) SHAPE(128, 4) SHAPE(128, 6) SHAPE(128, 5)
 #undef SHAPE
@@ -540,9 +536,9 @@ hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_advance_one(int64_t* step, int64_t n, hipStream_t st)
+hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_one, dim3(1), dim3(64), 0, st, step, n);
+    hipLaunchKernelGGL(advance_one, dim3(1), dim3(64), 0, st, step, n, launches);
     return hipGetLastError();
 }
 

@@ -1,0 +1,482 @@
+// gfx950 two-step field kernel of libfdtd.
+//
+// field_step2 advances a tile by two full leapfrog steps (Model section: B->H
+// then D->E, Eqs. 1-4, twice) in one pass over HBM.  Step n+1's fields never
+// leave the compute unit: they live in LDS and registers while the block
+// marches along z, one plane behind for the second step.  Each step widens the
+// dependence cone by one cell, so the block recomputes the first step on a
+// two-cell halo:
+//
+//   H^{n+1/2}   on rows j0-2 .. j0+Hh,   columns i0-2 .. i0+W   (H1)
+//   E^{n+1}     on rows j0-1 .. j0+Hh,   columns i0-1 .. i0+W   (E1)
+//   H^{n+3/2}   on rows j0-1 .. j0+Hh-1, columns i0-1 .. i0+W-1 (H2)
+//   E^{n+2}     on rows j0   .. j0+Hh-1, columns i0   .. i0+W-1 (E2, owned)
+//
+// with W = 64 aligned columns and Hh = TY-3 owned rows.  TY row waves cover
+// columns i0..i0+63 of the H1 rows; helper wave A takes the three halo columns
+// (i0-2, i0-1, i0+W) and stages column i0+W+1, helper wave B stages the row
+// above.  Per front plane k the block
+//   1. stages E^n of planes k+1 (Ex, Ey) and k (Ez) in LDS,
+//   2. computes H1 of plane k, then E1 of plane k (from H1 of planes k and k-1),
+//   3. computes H2 of plane k-1 (from E1 of planes k-1 and k, both in LDS),
+//   4. computes E2 of plane k-1 on the owned patch and stores E2, H2 and the
+//      kept D/B of step n+2.
+// Every per-node update is written with exactly the expressions of the one-step
+// kernel, so the two kernels give bitwise equal fields.  Fields are read from
+// one buffer and written to the other, as in the one-step kernel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fdtd_device.h"
+#include "fdtd_internal.h"
+
+namespace fdtd {
+
+// coefficient set of one axis at one node position (node "n" and half-node "h")
+struct AxisCoef {
+    float cam1_n, ca_n, rp_n, ph_n, q_n;
+    float cam1_h, ca_h, rp_h, ph_h, q_h;
+};
+
+template <int TY, typename CT>
+__global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __restrict__ boards,
+                                                             const TileRef* __restrict__ tiles,
+                                                             int rel, int flip)
+{
+    constexpr int W = 64;            // owned columns
+    constexpr int SC = W + 4;        // LDS columns: c = i - (i0 - 2), i0-2 .. i0+W+1
+    constexpr int NT = 64 * TY + 128;
+    static_assert(TY >= 5 && 4 * TY + 4 <= 64 && NT <= 1024, "tile shape");
+    __shared__ float sE0x[2][TY + 1][SC];
+    __shared__ float sE0y[2][TY + 1][SC];
+    __shared__ float sE0z[TY + 1][SC];
+    __shared__ float sH1x[TY][SC];
+    __shared__ float sH1y[TY][SC];
+    __shared__ float sH1z[TY][SC];
+    __shared__ float sE1x[2][TY][SC];
+    __shared__ float sE1y[2][TY][SC];
+    __shared__ float sE1z[2][TY][SC];
+    __shared__ float sH2x[TY][SC];
+    __shared__ float sH2y[TY][SC];
+    __shared__ float sH2z[TY][SC];
+    constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
+    __shared__ ClassEntry sTab[kLdsClasses];
+
+    const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (t.board < 0) return;   // idle entry padding an XCD's list
+    const BoardDev& B = boards[t.board];
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int sy = B.pitch, sz = B.pitch * (ny + 1), guard = sz * (nz + 1);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int i0 = t.tx * W, j0 = t.ty * (TY - 3);
+
+    // ---- lane roles: LDS position (r, c) and which stages it computes
+    int r, c;
+    bool comp = true;   // computes H1 (else it only stages E)
+    if (wave < TY) {
+        r = wave;
+        c = lane + 2;
+    } else if (wave == TY) {
+        if (lane < 3 * TY) {
+            const int g = lane / TY;
+            r = lane - g * TY;
+            c = g == 0 ? 0 : (g == 1 ? 1 : W + 2);
+        } else if (lane < 4 * TY) {
+            r = lane - 3 * TY;
+            c = W + 3;
+            comp = false;
+        } else {
+            // the four corners of the row above; lanes past them repeat the last
+            // corner (same value to the same place)
+            const int q = lane - 4 * TY;
+            r = TY;
+            c = q == 0 ? 0 : (q == 1 ? 1 : (q == 2 ? W + 2 : W + 3));
+            comp = false;
+        }
+    } else {
+        r = TY;
+        c = lane + 2;
+        comp = false;
+    }
+    const int i = i0 - 2 + c, j = j0 - 2 + r;
+    const bool rH1 = comp;
+    const bool rE1 = rH1 && r >= 1 && c >= 1;
+    const bool rH2 = rE1 && r <= TY - 2 && c <= W + 1;
+    const bool rE2 = rH2 && r >= 2 && c >= 2;
+    const bool ib = ((unsigned)i <= (unsigned)nx) & ((unsigned)j <= (unsigned)ny);
+    const bool own = rE2 && ib;
+
+    const int kb = t.kb, ke = t.ke, k0 = kb > 2 ? kb - 2 : 0;
+    const int64_t step = B.step[0] + rel;
+    const int par = (int)((B.step[1] + flip) & 1);
+    cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
+    cgfloat* __restrict__ gEy = (cgfloat*)B.f[par][1];
+    cgfloat* __restrict__ gEz = (cgfloat*)B.f[par][2];
+    cgfloat* __restrict__ gHx = (cgfloat*)B.f[par][3];
+    cgfloat* __restrict__ gHy = (cgfloat*)B.f[par][4];
+    cgfloat* __restrict__ gHz = (cgfloat*)B.f[par][5];
+    cgfloat* __restrict__ gBx = (cgfloat*)B.f[par][6];
+    cgfloat* __restrict__ gBy = (cgfloat*)B.f[par][7];
+    cgfloat* __restrict__ gBz = (cgfloat*)B.f[par][8];
+    gfloat* __restrict__ dEx = (gfloat*)B.f[par ^ 1][0];
+    gfloat* __restrict__ dEy = (gfloat*)B.f[par ^ 1][1];
+    gfloat* __restrict__ dEz = (gfloat*)B.f[par ^ 1][2];
+    gfloat* __restrict__ dHx = (gfloat*)B.f[par ^ 1][3];
+    gfloat* __restrict__ dHy = (gfloat*)B.f[par ^ 1][4];
+    gfloat* __restrict__ dHz = (gfloat*)B.f[par ^ 1][5];
+    gfloat* __restrict__ dBx = (gfloat*)B.f[par ^ 1][6];
+    gfloat* __restrict__ dBy = (gfloat*)B.f[par ^ 1][7];
+    gfloat* __restrict__ dBz = (gfloat*)B.f[par ^ 1][8];
+    cgfloat* __restrict__ Dx = (cgfloat*)B.d[par][0];
+    cgfloat* __restrict__ Dy = (cgfloat*)B.d[par][1];
+    cgfloat* __restrict__ Dz = (cgfloat*)B.d[par][2];
+    gfloat* __restrict__ dDx = (gfloat*)B.d[par ^ 1][0];
+    gfloat* __restrict__ dDy = (gfloat*)B.d[par ^ 1][1];
+    gfloat* __restrict__ dDz = (gfloat*)B.d[par ^ 1][2];
+    const __attribute__((address_space(1))) CT* __restrict__ cls =
+        (const __attribute__((address_space(1))) CT*)B.cls;
+    const __attribute__((address_space(1))) ClassEntry* __restrict__ ctab =
+        (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
+    const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
+    const int pml_zlo = B.pml[4], pml_zhi = B.pml[5];
+    auto in_px = [&](int ii) { return (ii < B.pml[0]) || (B.pml[1] > 0 && ii >= nx - B.pml[1]); };
+    auto in_py = [&](int jj) { return (jj < B.pml[2]) || (B.pml[3] > 0 && jj >= ny - B.pml[3]); };
+    auto in_pz = [&](int k) { return (k < pml_zlo) || (pml_zhi > 0 && k >= nz - pml_zhi); };
+    cgfloat* __restrict__ cxp = (cgfloat*)B.coef[0];
+    cgfloat* __restrict__ cyp = (cgfloat*)B.coef[1];
+    kfloat* __restrict__ czp = (kfloat*)B.coef[2];
+    const int nx1 = nx + 1, ny1 = ny + 1, nz1 = nz + 1;
+    auto axis_coef = [&](cgfloat* tab, int n1, int idx) {
+        const int q = min(max(idx, 0), n1 - 1);
+        AxisCoef a;
+        a.cam1_n = tab[(kCam1 * 2 + 0) * n1 + q];
+        a.ca_n = tab[(kCa * 2 + 0) * n1 + q];
+        a.rp_n = tab[(kRp * 2 + 0) * n1 + q];
+        a.ph_n = tab[(kPh * 2 + 0) * n1 + q];
+        a.q_n = tab[(kQ * 2 + 0) * n1 + q];
+        a.cam1_h = tab[(kCam1 * 2 + 1) * n1 + q];
+        a.ca_h = tab[(kCa * 2 + 1) * n1 + q];
+        a.rp_h = tab[(kRp * 2 + 1) * n1 + q];
+        a.ph_h = tab[(kPh * 2 + 1) * n1 + q];
+        a.q_h = tab[(kQ * 2 + 1) * n1 + q];
+        return a;
+    };
+    auto z_coef = [&](int k) {
+        kfloat* z = czp + min(max(k, 0), nz);
+        AxisCoef a;
+        a.cam1_n = z[(kCam1 * 2 + 0) * nz1];
+        a.ca_n = z[(kCa * 2 + 0) * nz1];
+        a.rp_n = z[(kRp * 2 + 0) * nz1];
+        a.ph_n = z[(kPh * 2 + 0) * nz1];
+        a.q_n = z[(kQ * 2 + 0) * nz1];
+        a.cam1_h = z[(kCam1 * 2 + 1) * nz1];
+        a.ca_h = z[(kCa * 2 + 1) * nz1];
+        a.rp_h = z[(kRp * 2 + 1) * nz1];
+        a.ph_h = z[(kPh * 2 + 1) * nz1];
+        a.q_h = z[(kQ * 2 + 1) * nz1];
+        return a;
+    };
+
+    if (sizeof(CT) == 1) {
+        for (int e = tid; e < kLdsClasses; e += NT) {
+            const int q = min(e, B.nclass - 1);
+            sTab[e].inv_x = ctab[q].inv_x;
+            sTab[e].inv_y = ctab[q].inv_y;
+            sTab[e].inv_z = ctab[q].inv_z;
+            sTab[e].flags = ctab[q].flags;
+        }
+    }
+    auto class_entry = [&](CT id) {
+        ClassEntry ce;
+        if (sizeof(CT) == 1) {
+            ce = sTab[id];
+        } else {
+            ce.inv_x = ctab[id].inv_x;
+            ce.inv_y = ctab[id].inv_y;
+            ce.inv_z = ctab[id].inv_z;
+            ce.flags = ctab[id].flags;
+        }
+        return ce;
+    };
+    auto node_at = [&](int ii, int jj, int k) {
+        const bool ok = ((unsigned)ii <= (unsigned)nx) & ((unsigned)jj <= (unsigned)ny) &
+                        ((unsigned)k <= (unsigned)nz);
+        return ok ? ii + jj * sy + k * sz : guard;
+    };
+
+    const bool px = in_px(i), py = in_py(j);
+    const AxisCoef X = axis_coef(cxp, nx1, i), Y = axis_coef(cyp, ny1, j);
+    const int node0 = i + j * sy;
+    const int64_t ms = B.max_steps;
+
+    struct Stage { float ex, ey, ez; };
+    struct Col { float hx, hy, hz, bx, by, bz, dx, dy, dz; CT c; };
+    auto load_stage = [&](int p) {
+        Stage s;
+        s.ex = gEx[node_at(i, j, p + 1)];
+        s.ey = gEy[node_at(i, j, p + 1)];
+        s.ez = gEz[node_at(i, j, p)];
+        return s;
+    };
+    // every load is issued on every path (absent operands read the zero guard
+    // words), so the wait counts stay exact
+    auto load_col = [&](int p, Col& o) {
+        const int n = node0 + p * sz;
+        const bool pz = in_pz(p);
+        const bool okh = rH1 && ib && p <= nz, oke = rE1 && ib && p <= nz;
+        const int nh = okh ? n : guard;
+        o.hx = gHx[nh];
+        o.hy = gHy[nh];
+        o.hz = gHz[nh];
+        o.bx = gBx[okh && (px || py) ? n : guard];
+        o.by = gBy[okh && (py || pz) ? n : guard];
+        o.bz = gBz[okh && (pz || px) ? n : guard];
+        o.c = cls[oke ? n : guard];
+        o.dx = Dx[oke && (px || py) ? n : guard];
+        o.dy = Dy[oke && (py || pz) ? n : guard];
+        o.dz = Dz[oke && (pz || px) ? n : guard];
+    };
+    auto source_sum = [&](int node, int64_t s) {
+        float js = 0.0f;
+        const __attribute__((address_space(1))) int32_t* sn =
+            (const __attribute__((address_space(1))) int32_t*)B.src_node;
+        cgfloat* sj = (cgfloat*)B.src_j;
+        for (int q = 0; q < B.nsrc; ++q)
+            if (sn[q] == node) js += sj[q * ms + s];
+        return js;
+    };
+    auto record_probe = [&](int node, int64_t s, float ez) {
+        const __attribute__((address_space(1))) int32_t* pn =
+            (const __attribute__((address_space(1))) int32_t*)B.prb_node;
+        gfloat* ps = (gfloat*)B.prb_series;
+        for (int q = 0; q < B.nprb; ++q)
+            if (pn[q] == node) ps[q * ms + s] = ez;
+    };
+
+    // staging of the first plane
+    sE0x[0][r][c] = gEx[node_at(i, j, k0)];
+    sE0y[0][r][c] = gEy[node_at(i, j, k0)];
+    Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
+    Col cA, cB;
+    load_col(k0, cA);
+
+    // carried from the previous front plane (k-1): H1, B1, own E1, D1 and class;
+    // H2 of plane k-2
+    float p_h1x = 0.f, p_h1y = 0.f, p_h1z = 0.f, p_b1x = 0.f, p_b1y = 0.f, p_b1z = 0.f;
+    float p_e1x = 0.f, p_e1y = 0.f, p_e1z = 0.f, p_d1x = 0.f, p_d1y = 0.f, p_d1z = 0.f;
+    CT p_c = 0;
+    float p_h2x = 0.f, p_h2y = 0.f;
+    bool bad = false;
+
+    auto plane_step = [&](int k, Stage& st, const Col& o, Col& nxt_col) {
+        const int cur = (k - k0) & 1, nxt = cur ^ 1;
+        const int m = k - 1;   // plane of the second step
+        // ---- stage E^n
+        sE0x[nxt][r][c] = st.ex;
+        sE0y[nxt][r][c] = st.ey;
+        sE0z[r][c] = st.ez;
+        st = load_stage(k + 2);
+        load_col(k + 1, nxt_col);
+        const AxisCoef Zk = z_coef(k);
+        __syncthreads();
+
+        // ---- H1 of plane k: B then H, step n -> n+1/2
+        const bool okk = ib && k <= nz;
+        const bool pz = in_pz(k);
+        float h1x = 0.f, h1y = 0.f, h1z = 0.f, b1x = 0.f, b1y = 0.f, b1z = 0.f;
+        if (rH1) {
+            if (okk) {
+                const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
+                const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
+                const float dbx = fmaf(Y.cam1_h, o.bx, -Y.rp_h * cxe);
+                h1x = fmaf(Zk.ca_h, o.hx, Zk.rp_h * fmaf(X.ph_n, dbx, X.q_n * o.bx));
+                const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
+                const float dby = fmaf(Zk.cam1_h, o.by, -Zk.rp_h * cye);
+                h1y = fmaf(X.ca_h, o.hy, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * o.by));
+                const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
+                const float dbz = fmaf(X.cam1_h, o.bz, -X.rp_h * cze);
+                h1z = fmaf(Y.ca_h, o.hz, Y.rp_h * fmaf(Zk.ph_n, dbz, Zk.q_n * o.bz));
+                b1x = (px || py) ? o.bx + dbx : 0.f;
+                b1y = (py || pz) ? o.by + dby : 0.f;
+                b1z = (pz || px) ? o.bz + dbz : 0.f;
+            }
+            sH1x[r][c] = h1x;
+            sH1y[r][c] = h1y;
+            sH1z[r][c] = h1z;
+        }
+        __syncthreads();
+
+        // ---- E1 of plane k: D then E, step n -> n+1
+        float e1x = 0.f, e1y = 0.f, e1z = 0.f, d1x = 0.f, d1y = 0.f, d1z = 0.f;
+        const int e = cur;   // E1 plane slot of plane k (plane k-1 is in e ^ 1)
+        if (rE1) {
+            if (okk) {
+                const ClassEntry ce = class_entry(o.c);
+                const int node = node0 + k * sz;
+                const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
+                const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
+                const float ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
+                float exn = fmaf(Zk.ca_n, exo, Zk.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * o.dx)));
+                const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
+                const float ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
+                float eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
+                float js = 0.0f;
+                if (ce.flags & kSrcEz) js = source_sum(node, step);
+                const float chz = ((h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy) - js;
+                const float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
+                float ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
+                e1x = (ce.flags & kUpdEx) ? exn : 0.0f;
+                e1y = (ce.flags & kUpdEy) ? eyn : 0.0f;
+                e1z = (ce.flags & kUpdEz) ? ezn : 0.0f;
+                d1x = ((px || py) && (ce.flags & kUpdEx)) ? o.dx + ddx : o.dx;
+                d1y = ((py || pz) && (ce.flags & kUpdEy)) ? o.dy + ddy : o.dy;
+                d1z = ((pz || px) && (ce.flags & kUpdEz)) ? o.dz + ddz : o.dz;
+                if (own && k >= kb && k < ke && (ce.flags & kPrbEz)) record_probe(node, step, e1z);
+            }
+            sE1x[e][r][c] = e1x;
+            sE1y[e][r][c] = e1y;
+            sE1z[e][r][c] = e1z;
+        }
+        __syncthreads();
+
+        // ---- H2 of plane m = k-1: B then H, step n+1/2 -> n+3/2
+        const bool okm = ib && m >= 0 && m <= nz;
+        const bool livem = m >= kb && m < ke;
+        const AxisCoef Zm = z_coef(m);
+        const bool pzm = in_pz(m);
+        float h2x = 0.f, h2y = 0.f, h2z = 0.f;
+        if (rH2) {
+            if (okm) {
+                const int pe = e ^ 1;
+                const float exo = sE1x[pe][r][c], eyo = sE1y[pe][r][c], ezo = sE1z[pe][r][c];
+                const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
+                const float dbx = fmaf(Y.cam1_h, p_b1x, -Y.rp_h * cxe);
+                h2x = fmaf(Zm.ca_h, p_h1x, Zm.rp_h * fmaf(X.ph_n, dbx, X.q_n * p_b1x));
+                const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
+                const float dby = fmaf(Zm.cam1_h, p_b1y, -Zm.rp_h * cye);
+                h2y = fmaf(X.ca_h, p_h1y, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * p_b1y));
+                const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
+                const float dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
+                h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
+                if (own && livem) {
+                    const int node = node0 + m * sz;
+                    dHx[node] = h2x;
+                    dHy[node] = h2y;
+                    dHz[node] = h2z;
+                    if (px || py) dBx[node] = p_b1x + dbx;
+                    if (py || pzm) dBy[node] = p_b1y + dby;
+                    if (pzm || px) dBz[node] = p_b1z + dbz;
+                }
+            }
+            sH2x[r][c] = h2x;
+            sH2y[r][c] = h2y;
+            sH2z[r][c] = h2z;
+        }
+        __syncthreads();
+
+        // ---- E2 of plane m on the owned patch: D then E, step n+1 -> n+2
+        if (own && livem) {
+            const ClassEntry ce = class_entry(p_c);
+            const int node = node0 + m * sz;
+            const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
+            const float ddx = fmaf(Y.cam1_n, p_d1x, Y.rp_n * chx);
+            float exn = fmaf(Zm.ca_n, p_e1x, Zm.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * p_d1x)));
+            const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
+            const float ddy = fmaf(Zm.cam1_n, p_d1y, Zm.rp_n * chy);
+            float eyn = fmaf(X.ca_n, p_e1y, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * p_d1y)));
+            float js = 0.0f;
+            if (ce.flags & kSrcEz) js = source_sum(node, step + 1);
+            const float chz = ((h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy) - js;
+            const float ddz = fmaf(X.cam1_n, p_d1z, X.rp_n * chz);
+            float ezn = fmaf(Y.ca_n, p_e1z, Y.rp_n * (ce.inv_z * fmaf(Zm.ph_h, ddz, Zm.q_h * p_d1z)));
+            exn = (ce.flags & kUpdEx) ? exn : 0.0f;
+            eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
+            ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
+            dEx[node] = exn;
+            dEy[node] = eyn;
+            dEz[node] = ezn;
+            if (px || py) dDx[node] = (ce.flags & kUpdEx) ? p_d1x + ddx : p_d1x;
+            if (py || pzm) dDy[node] = (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y;
+            if (pzm || px) dDz[node] = (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z;
+            if (ce.flags & kPrbEz) record_probe(node, step + 1, ezn);
+            bad |= !isfinite(exn + eyn + ezn);
+        }
+        // plane k's step-one values become the carried ones
+        p_h1x = h1x; p_h1y = h1y; p_h1z = h1z;
+        p_b1x = b1x; p_b1y = b1y; p_b1z = b1z;
+        p_e1x = e1x; p_e1y = e1y; p_e1z = e1z;
+        p_d1x = d1x; p_d1y = d1y; p_d1z = d1z;
+        p_c = o.c;
+        p_h2x = h2x; p_h2y = h2y;
+    };
+    for (int k = k0; k <= ke; k += 2) {
+        plane_step(k, s0, cA, cB);
+        if (k + 1 <= ke) plane_step(k + 1, s1, cB, cA);
+    }
+    if (bad) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
+}
+
+// ---------------------------------------------------------------------------
+struct Shape2 {
+    int tx, ty;
+};
+// 64*TY + 128 threads: up to TY = 10 the block has at most 12 waves, three per
+// SIMD, which leaves the kernel the 157 VGPRs it needs without spilling
+static const Shape2 kShapes2[] = {{64, 10}, {64, 9}, {64, 8}};
+static const int kNumShapes2 = sizeof(kShapes2) / sizeof(kShapes2[0]);
+
+int num_shapes2() { return kNumShapes2; }
+void shape2_at(int s, int* tx, int* ty)
+{
+    *tx = kShapes2[s].tx;
+    *ty = kShapes2[s].ty;
+}
+
+template <int TY>
+static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel,
+                            int flip, bool wide, hipStream_t st)
+{
+    if (wide)
+        hipLaunchKernelGGL((field_step2<TY, uint16_t>), dim3(ntiles), dim3(64 * TY + 128), 0, st,
+                           boards, tiles, rel, flip);
+    else
+        hipLaunchKernelGGL((field_step2<TY, uint8_t>), dim3(ntiles), dim3(64 * TY + 128), 0, st,
+                           boards, tiles, rel, flip);
+    return hipGetLastError();
+}
+
+template <int TY>
+static int occupancy2_t(bool wide)
+{
+    int n = 0;
+    hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step2<TY, uint16_t>, 64 * TY + 128, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step2<TY, uint8_t>, 64 * TY + 128, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int field_step2_occupancy(int tile_y, bool wide)
+{
+    switch (tile_y) {
+        case 10: return occupancy2_t<10>(wide);
+        case 9: return occupancy2_t<9>(wide);
+        case 8: return occupancy2_t<8>(wide);
+        default: return 1;
+    }
+}
+
+hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
+                              int rel, int flip, bool wide, hipStream_t st)
+{
+    switch (tile_y) {
+        case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, st);
+        case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, st);
+        case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fdtd

@@ -61,7 +61,8 @@ class fdtd_info(C.Structure):
                 ("cells", C.c_int64), ("nodes", C.c_int64), ("step_bytes", C.c_int64),
                 ("device_bytes", C.c_int64),
                 ("n_sources", C.c_int32), ("n_probes", C.c_int32), ("n_freqs", C.c_int32),
-                ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
+                ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+                ("tile_steps", C.c_int32)]
 
 
 class FdtdError(RuntimeError):
@@ -90,7 +91,7 @@ _sigs = {
     "fdtd_save_state": ([_P, _P, C.c_int64], C.c_int),
     "fdtd_load_state": ([_P, _P, C.c_int64], C.c_int),
     "fdtd_get_info": ([_P, C.POINTER(fdtd_info)], C.c_int),
-    "fdtd_set_tile": ([_P, C.c_int, C.c_int], C.c_int),
+    "fdtd_set_tile": ([_P, C.c_int, C.c_int, C.c_int], C.c_int),
     "fdtd_tile_shapes": ([_P, C.c_int], C.c_int),
     "fdtd_set_timing": ([_P, C.c_int], C.c_int),
     "fdtd_get_timing": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -301,14 +302,15 @@ def fdtd_get_info(g) -> fdtd_info:
     return out
 
 
-def fdtd_set_tile(g, tile_x: int, tile_y: int):
-    _check(_lib.fdtd_set_tile(g, int(tile_x), int(tile_y)))
+def fdtd_set_tile(g, tile_x: int, tile_y: int, steps: int = 1):
+    _check(_lib.fdtd_set_tile(g, int(tile_x), int(tile_y), int(steps)))
 
 
 def fdtd_tile_shapes() -> List[tuple]:
-    buf = (C.c_int * 64)()
+    """(tile_x, tile_y, steps per pass) of every supported field-kernel shape."""
+    buf = (C.c_int * 96)()
     n = _lib.fdtd_tile_shapes(buf, 32)
-    return [(buf[2 * s], buf[2 * s + 1]) for s in range(min(n, 32))]
+    return [(buf[3 * s], buf[3 * s + 1], buf[3 * s + 2]) for s in range(min(n, 32))]
 
 
 def fdtd_set_timing(g, on: bool):

@@ -1,7 +1,7 @@
 """Tile-shape autotuner for the field kernel.
 
 The field kernel's results do not depend on its tile shape (bitwise), only its
-speed does.  ``tune_board`` / ``tune_batch`` time every supported shape on
+speed does.  A shape is (tile_x, tile_y, steps per pass); timings are per step.  ``tune_board`` / ``tune_batch`` time every supported shape on
 scratch handles with the same geometry and materials (zero fields, no sources),
 keep the fastest, and cache the choice in a JSON file keyed by the geometry, so
 the live solve never runs a timing step.
@@ -13,7 +13,7 @@ import os
 import time
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
-Shape = Tuple[int, int]
+Shape = Tuple[int, ...]   # (tile_x, tile_y, steps per pass)
 
 
 def cache_path() -> str:
@@ -79,7 +79,7 @@ def tune(key: str, time_shape: Callable[[Shape], float], shapes: Iterable[Shape]
     data = _load(path)
     timings = {s: float(time_shape(s)) for s in shapes}
     best = pick(timings)
-    data[key] = [list(best), {f"{s[0]}x{s[1]}": t for s, t in timings.items()}]
+    data[key] = [list(best), {"x".join(str(v) for v in s): t for s, t in timings.items()}]
     _store(path, data)
     return best, timings
 
@@ -109,9 +109,9 @@ def tune_board(board, steps: int = 6, warm: int = 2, path: Optional[str] = None,
                 F.fdtd_set_timing(g, True)
                 F.fdtd_get_timing(g)          # clears
                 F.fdtd_step_n(g, steps)
-                ms, n = F.fdtd_get_timing(g)
+                ms, _ = F.fdtd_get_timing(g)
                 F.fdtd_set_timing(g, False)
-                return ms / max(n, 1)
+                return ms / steps        # per step: a two-step shape makes half the launches
             best, _ = tune(board_key(board), time_shape, shapes, path, refresh)
             return best
         finally:

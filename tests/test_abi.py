@@ -19,7 +19,9 @@ def test_binding_wraps_every_header_symbol():
 
 def test_tile_shapes_listed():
     shapes = F.fdtd_tile_shapes()
-    assert (64, 8) in shapes and all(tx % 64 == 0 and tx * ty + 64 <= 1024 for tx, ty in shapes)
+    assert (64, 8, 1) in shapes and (64, 10, 2) in shapes
+    assert all(tx % 64 == 0 and (tx * ty + 64 if st == 1 else 64 * ty + 128) <= 1024
+               for tx, ty, st in shapes)
 
 
 @pytest.mark.parametrize("kw,frag", [

@@ -16,6 +16,7 @@ from _util import live_masks, rel_l2
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("ex", "ey", "ez", "hx", "hy", "hz", "ddx", "ddy", "ddz", "bbx", "bby", "bbz")
+TWO_STEP = (64, 10, 2)   # a two-steps-per-pass shape of the field kernel
 
 
 def announce(msg):
@@ -148,7 +149,8 @@ def test_tiny_boards_from_zero(F, orc, seed):
                                         ((13, 17, 30), (0, 3, 2, 0, 5, 4)),
                                         ((2, 2, 2), (0, 0, 0, 0, 0, 0)),
                                         ((131, 9, 4), (1, 1, 1, 1, 1, 1))])
-def test_random_state_few_steps(F, orc, shape, npml):
+@pytest.mark.parametrize("tile", [None, TWO_STEP])
+def test_random_state_few_steps(F, orc, shape, npml, tile):
     nx, ny, nz = shape
     eps, mask = boardgen.air(nx, ny, nz)
     rng = np.random.default_rng(nx * 1000 + ny)
@@ -156,12 +158,12 @@ def test_random_state_few_steps(F, orc, shape, npml):
     if nz >= 4:
         boardgen.pec_sheet(mask, nz // 2, 0, nx // 2, 1, ny - 1)
     b = boardgen.Board(f"rand{nx}x{ny}x{nz}", nx, ny, nz, 0.7e-3, 0.9e-3, 0.4e-3, eps, mask,
-                       npml=npml, steps=4)
+                       npml=npml, steps=4 if tile is None else 5)
     st = random_state(orc, b, seed=nx + ny + nz)
     init = {n: st[n].copy() for n in FIELDS}
-    announce(f"random state {shape} npml={npml}")
+    announce(f"random state {shape} npml={npml} tile={tile}")
     ref = orc.run(b, state=st)
-    _, fields, _, _ = gpu_run(F, b, init=init)
+    _, fields, _, _ = gpu_run(F, b, init=init, tile=tile)
     compare_fields(ref.state, fields, b, 2e-5)
 
 
@@ -240,7 +242,9 @@ def test_large_board_full_size_random_state(F, orc):
 
 
 def test_tile_shapes_bitwise(F):
-    b = boardgen.random_tiny(7, nx=150, ny=37, nz=12, npml=3, steps=30)
+    """Every shape, one- and two-step (an odd count ends on one single step),
+    gives the same bits as the first."""
+    b = boardgen.random_tiny(7, nx=150, ny=37, nz=12, npml=3, steps=31)
     for s in b.sources:
         s.t0, s.sigma = 5e-12, 2e-12
     outs = []
@@ -264,22 +268,23 @@ def test_chunked_equals_single_call(F):
         assert np.array_equal(f1[n], f2[n]), n
 
 
-def test_checkpoint_resume_bitwise(F):
+@pytest.mark.parametrize("tile", [None, TWO_STEP])
+def test_checkpoint_resume_bitwise(F, tile):
     b = boardgen.small_board(steps=300)
     b.dft_freqs = np.linspace(1e9, 8e9, 16)
-    announce("checkpoint/resume")
-    g, ids = F.grid_from_board(b)
-    F.fdtd_step_n(g, 120)
+    announce(f"checkpoint/resume tile={tile}")
+    g, ids = F.grid_from_board(b, tile=tile)
+    F.fdtd_step_n(g, 121)
     image = F.fdtd_save_state(g)
-    F.fdtd_step_n(g, 180)
+    F.fdtd_step_n(g, 179)
     a_probe = F.fdtd_get_probe(g, ids[0], 300)
     a_dft = F.fdtd_get_dft(g, ids[0])
     a_ez = F.fdtd_get_field(g, F.FDTD_EZ, (b.nz + 1, b.ny + 1, b.nx + 1))
     F.fdtd_destroy_grid(g)
-    g2, ids2 = F.grid_from_board(b)
+    g2, ids2 = F.grid_from_board(b, tile=tile)
     F.fdtd_load_state(g2, image)
-    assert F.fdtd_get_info(g2).step == 120
-    F.fdtd_step_n(g2, 180)
+    assert F.fdtd_get_info(g2).step == 121
+    F.fdtd_step_n(g2, 179)
     assert np.array_equal(F.fdtd_get_probe(g2, ids2[0], 300), a_probe)
     assert np.array_equal(F.fdtd_get_dft(g2, ids2[0]), a_dft)
     assert np.array_equal(F.fdtd_get_field(g2, F.FDTD_EZ, a_ez.shape), a_ez)
@@ -358,7 +363,8 @@ def _small_variants(seed, n):
     return out
 
 
-def test_step_many_bitwise_equals_alone(F):
+@pytest.mark.parametrize("tile", [None, TWO_STEP])
+def test_step_many_bitwise_equals_alone(F, tile):
     boards = _small_variants(11, 6)
     # one board with a wide (uint16) class map: many distinct permittivities
     rng = np.random.default_rng(3)
@@ -371,9 +377,10 @@ def test_step_many_bitwise_equals_alone(F):
         alone.append((p, f, d))
         if b is boards[2]:
             assert info.n_classes > 256
-    handles = [F.grid_from_board(b) for b in boards]
+    handles = [F.grid_from_board(b, tile=tile) for b in boards]
     gs = [h for h, _ in handles]
-    # two batched calls with uneven counts, then the remainders
+    # two batched calls with uneven counts, then the remainders (the lead handle's
+    # shape runs the batch)
     first = [b.steps // 3 for b in boards]
     F.fdtd_step_many(gs, first)
     F.fdtd_step_many(gs[::-1], [b.steps - f for b, f in zip(boards, first)][::-1])
@@ -388,12 +395,13 @@ def test_step_many_bitwise_equals_alone(F):
         F.fdtd_destroy_grid(g)
 
 
-def test_graph_replays_match_eager(F):
+@pytest.mark.parametrize("tile", [None, TWO_STEP])
+def test_graph_replays_match_eager(F, tile):
     """Graph-replayed chunks (timing off) against eager launches (timing on), with
     synchronisation and host reads between every replay."""
     b = boardgen.small_board(steps=32 * 6)
-    ga, ida = F.grid_from_board(b)
-    gb, idb = F.grid_from_board(b)
+    ga, ida = F.grid_from_board(b, tile=tile)
+    gb, idb = F.grid_from_board(b, tile=tile)
     F.fdtd_set_timing(gb, True)            # forces plain launches
     shp = (b.nz + 1, b.ny + 1, b.nx + 1)
     for c in range(6):

@@ -75,7 +75,7 @@ def test_autotuned_tile_keeps_results(F, tmp_path):
     assert shape in F.fdtd_tile_shapes()
     assert tune.tune_board(b, path=path) == shape          # cached
     out = []
-    for tile in (shape, (64, 8)):
+    for tile in (shape, (64, 8, 1)):
         g, ids = F.grid_from_board(b, tile=tile)
         F.fdtd_step_n(g, b.steps)
         out.append(F.fdtd_get_probe(g, ids[0], b.steps))
