@@ -91,8 +91,10 @@ typedef struct {
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
  * Eqs. 1-5 with sigma_max = -(m+1) ln R / (2 eta0 N delta) on each face, outer PEC
- * wall; Eq. 7 time step).  All fields start at zero.  EINVAL: sizes < 2, node
- * count >= 2^31, non-positive spacing, dt at or above the Eq. 7 limit (c0),
+ * wall; Eq. 7 time step).  All fields start at zero.  EINVAL: sizes < 2, more
+ * than about 3.5e8 nodes once rows are padded to 32 nodes (the x, y and z arrays
+ * of a field share one 4 GiB window), non-positive spacing, dt at or above the
+ * Eq. 7 limit (c0),
  * courant outside (0, 1), npml < 0 or two opposite layers overlapping,
  * max_steps < 1.  ENOMEM: device allocation failed (no handle is returned). */
 int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out);
@@ -193,7 +195,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out);
  *     step is recomputed on a two-cell halo and never stored.  An odd step count
  *     ends with one step of the 64x15 one-step shape.
  * Results do not depend on the shape (bitwise).  May be changed between steps;
- * EINVAL for an unsupported shape.  The default is the two-step 64x10. */
+ * EINVAL for an unsupported shape.  The default is the two-step 64x14. */
 int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y, int steps);
 
 /* Supported tile shapes: writes up to `cap` triples (tile_x, tile_y, steps) into

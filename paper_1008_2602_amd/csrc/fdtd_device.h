@@ -11,6 +11,26 @@ typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(4))) const float kfloat;  // uniform, scalar loads
 
+// Access at a 32-bit byte offset from a uniform base.  Base (scalar registers)
+// plus a zero-extended 32-bit offset is the global instructions' scalar-base
+// form, so no 64-bit address arithmetic runs per lane and one offset serves every
+// array of the same layout.  The library keeps padded arrays below 2^30 nodes,
+// so every byte offset fits in 32 bits.
+typedef __attribute__((address_space(1))) char gbyte;
+__device__ __forceinline__ float ld_at(const float* base, uint32_t off)
+{
+    return *(const __attribute__((address_space(1))) float*)((const gbyte*)base + off);
+}
+__device__ __forceinline__ void st_at(float* base, uint32_t off, float v)
+{
+    *(__attribute__((address_space(1))) float*)((gbyte*)base + off) = v;
+}
+template <typename T>
+__device__ __forceinline__ T ld_at_t(const void* base, uint32_t off)
+{
+    return *(const __attribute__((address_space(1))) T*)((const gbyte*)base + off);
+}
+
 // Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks
 // a contiguous run of the tile list (neighbouring tiles share halos in its L2).
 __device__ __forceinline__ int xcd_tile(int b, int nb)

@@ -98,6 +98,7 @@ struct fdtd_grid {
     int64_t nodes = 0;      // (nx+1)(ny+1)(nz+1) grid nodes
     int64_t pitch = 0;      // device row pitch in nodes: nx+1 rounded up to 32
     int64_t dnodes = 0;     // device nodes per field array: pitch (ny+1)(nz+1)
+    int64_t cstride = 0;    // bytes between the x, y, z arrays of one field
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -140,7 +141,7 @@ struct fdtd_grid {
     bool wide = false;
     bool finalized = false;
     int64_t step = 0;
-    int tile_x = 64, tile_y = 10, tile_steps = 2;
+    int tile_x = 64, tile_y = 14, tile_steps = 2;
     int cus = 0;            // compute units of the device
     int64_t step_bytes = 0;
 
@@ -223,6 +224,10 @@ hipError_t copy_field_sync(fdtd_grid* g, void* dst, const void* src, hipMemcpyKi
 }
 
 int64_t row_pitch(int nx) { return ((int64_t)nx + 1 + 31) / 32 * 32; }
+
+// Bytes between the x, y and z arrays of one field (padded nodes + guard words,
+// rounded up to 256 bytes).
+int64_t component_stride(int64_t dnodes) { return ((dnodes + kGuard) * 4 + 255) / 256 * 256; }
 
 // Owned rows of a tile: the one-step kernel spends one row of its TY on the halo,
 // the two-step kernel three.
@@ -593,6 +598,7 @@ int finalize(fdtd_grid* g)
     b.ny = ny;
     b.nz = nz;
     b.pitch = (int32_t)g->pitch;
+    b.cstride = (uint32_t)g->cstride;
     b.nsrc = ns;
     b.nprb = np;
     b.nclass = (int32_t)table.size();
@@ -657,9 +663,12 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     const int64_t nodes = (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     const int64_t pitch = row_pitch(d.nx);
     const int64_t dnodes = pitch * (d.ny + 1) * (d.nz + 1);
-    if (dnodes + kGuard >= (int64_t(1) << 31))
-        return fail(FDTD_EINVAL, "padded node count (row pitch %lld) must be below 2^31",
-                    (long long)pitch);
+    const int64_t cstride = component_stride(dnodes);
+    if (3 * cstride >= (int64_t(1) << 32))
+        return fail(FDTD_EINVAL,
+                    "grid too large: the three components of a field (%lld padded nodes each, "
+                    "row pitch %lld) must fit a 4 GiB window",
+                    (long long)dnodes, (long long)pitch);
     if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !std::isfinite(d.dx) ||
         !std::isfinite(d.dy) || !std::isfinite(d.dz))
         return fail(FDTD_EINVAL, "cell sizes must be positive and finite");
@@ -715,24 +724,24 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
         return fail(code, "%s", m.c_str());
     };
     // every field array carries kGuard zero words past its last node: the kernels
-    // read out-of-range neighbours from there and never write them
-    const int64_t padded = dnodes + kGuard;
+    // read out-of-range neighbours from there and never write them.  E, H, B and
+    // D are one allocation per copy each, holding the x, y and z arrays at a
+    // fixed stride, so one base address and a 32-bit offset reach all three.
     for (int p = 0; p < 2; ++p)
-        for (int c = 0; c < 9; ++c)
-            if (!(g->f[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
-                return bail(FDTD_ENOMEM, "field allocation failed");
-    for (int p = 0; p < 2; ++p)
-        for (int c = 0; c < 3; ++c)
-            if (!(g->dd[p][c] = (float*)dev_alloc(g, (size_t)padded * 4)))
-                return bail(FDTD_ENOMEM, "field allocation failed");
-    for (int p = 0; p < 2; ++p)
-        for (int c = 0; c < 9; ++c)
-            if (launch_fill_zero(g->f[p][c], padded, g->stream) != hipSuccess)
+        for (int q = 0; q < 4; ++q) {
+            char* blk = (char*)dev_alloc(g, (size_t)(3 * cstride));
+            if (!blk) return bail(FDTD_ENOMEM, "field allocation failed");
+            if (launch_fill_zero((float*)blk, 3 * cstride / 4, g->stream) != hipSuccess)
                 return bail(FDTD_EDEVICE, "zero fill failed");
-    for (int p = 0; p < 2; ++p)
-        for (int c = 0; c < 3; ++c)
-            if (launch_fill_zero(g->dd[p][c], padded, g->stream) != hipSuccess)
-                return bail(FDTD_EDEVICE, "zero fill failed");
+            for (int c = 0; c < 3; ++c) {
+                float* a = (float*)(blk + c * cstride);
+                if (q < 3)
+                    g->f[p][3 * q + c] = a;
+                else
+                    g->dd[p][c] = a;
+            }
+        }
+    g->cstride = cstride;
     for (int a = 0; a < 3; ++a) {
         std::vector<float> t = coef_table(d, a, dt);
         if (!(g->coef[a] = (float*)dev_alloc(g, t.size() * 4)))
@@ -1134,7 +1143,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
         return fail(FDTD_EINVAL, "bad descriptor or counts");
     auto r = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nodes = row_pitch(d->nx) * (d->ny + 1) * (d->nz + 1);      // padded rows
-    int64_t t = 24 * r((nodes + kGuard) * 4);                                   // fields
+    int64_t t = 8 * r(3 * component_stride(nodes));                             // fields
     t += r(2 * (nodes + kGuard));                                               // class map (upper bound)
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
     t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +

@@ -60,6 +60,7 @@ struct BoardDev {
     int32_t* bad;                // watchdog flag
     int32_t nx, ny, nz;
     int32_t pitch;               // row pitch in nodes: nx+1 rounded up to 32 (128 bytes)
+    uint32_t cstride;            // bytes from a field's x array to its y array (y to z alike)
     int32_t nsrc, nprb;
     int32_t nclass;
     int32_t pml[6];

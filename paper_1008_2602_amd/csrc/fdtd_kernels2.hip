@@ -61,6 +61,8 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
     __shared__ float sH2z[TY][SC];
     constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
     __shared__ ClassEntry sTab[kLdsClasses];
+    // z coefficients of planes k (slot k&1) and k-1, staged by the last wave
+    __shared__ float sZ[2][10];
 
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (t.board < 0) return;   // idle entry padding an XCD's list
@@ -110,33 +112,22 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
 
     const int kb = t.kb, ke = t.ke, k0 = kb > 2 ? kb - 2 : 0;
     const int64_t step = B.step[0] + rel;
-    const int par = (int)((B.step[1] + flip) & 1);
-    cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
-    cgfloat* __restrict__ gEy = (cgfloat*)B.f[par][1];
-    cgfloat* __restrict__ gEz = (cgfloat*)B.f[par][2];
-    cgfloat* __restrict__ gHx = (cgfloat*)B.f[par][3];
-    cgfloat* __restrict__ gHy = (cgfloat*)B.f[par][4];
-    cgfloat* __restrict__ gHz = (cgfloat*)B.f[par][5];
-    cgfloat* __restrict__ gBx = (cgfloat*)B.f[par][6];
-    cgfloat* __restrict__ gBy = (cgfloat*)B.f[par][7];
-    cgfloat* __restrict__ gBz = (cgfloat*)B.f[par][8];
-    gfloat* __restrict__ dEx = (gfloat*)B.f[par ^ 1][0];
-    gfloat* __restrict__ dEy = (gfloat*)B.f[par ^ 1][1];
-    gfloat* __restrict__ dEz = (gfloat*)B.f[par ^ 1][2];
-    gfloat* __restrict__ dHx = (gfloat*)B.f[par ^ 1][3];
-    gfloat* __restrict__ dHy = (gfloat*)B.f[par ^ 1][4];
-    gfloat* __restrict__ dHz = (gfloat*)B.f[par ^ 1][5];
-    gfloat* __restrict__ dBx = (gfloat*)B.f[par ^ 1][6];
-    gfloat* __restrict__ dBy = (gfloat*)B.f[par ^ 1][7];
-    gfloat* __restrict__ dBz = (gfloat*)B.f[par ^ 1][8];
-    cgfloat* __restrict__ Dx = (cgfloat*)B.d[par][0];
-    cgfloat* __restrict__ Dy = (cgfloat*)B.d[par][1];
-    cgfloat* __restrict__ Dz = (cgfloat*)B.d[par][2];
-    gfloat* __restrict__ dDx = (gfloat*)B.d[par ^ 1][0];
-    gfloat* __restrict__ dDy = (gfloat*)B.d[par ^ 1][1];
-    gfloat* __restrict__ dDz = (gfloat*)B.d[par ^ 1][2];
-    const __attribute__((address_space(1))) CT* __restrict__ cls =
-        (const __attribute__((address_space(1))) CT*)B.cls;
+    // uniform by construction; readfirstlane lets the compiler keep the array
+    // bases it selects in scalar registers
+    const int par = __builtin_amdgcn_readfirstlane((int)((B.step[1] + flip) & 1));
+    // one base per field and copy; y and z sit cs and 2 cs bytes after x
+    const float* gE = B.f[par][0];
+    const float* gH = B.f[par][3];
+    const float* gB = B.f[par][6];
+    const float* gD = B.d[par][0];
+    float* dE = B.f[par ^ 1][0];
+    float* dH = B.f[par ^ 1][3];
+    float* dB = B.f[par ^ 1][6];
+    float* dD = B.d[par ^ 1][0];
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride;
+    // byte offsets (4 bytes per node) into the field arrays
+    const uint32_t szb = (uint32_t)sz * 4u, guardb = (uint32_t)guard * 4u;
+    const void* cls = B.cls;
     const __attribute__((address_space(1))) ClassEntry* __restrict__ ctab =
         (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
@@ -163,21 +154,24 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         a.q_h = tab[(kQ * 2 + 1) * n1 + q];
         return a;
     };
+    // z coefficients from the LDS ring (entry kind*2 + half of the table)
     auto z_coef = [&](int k) {
-        kfloat* z = czp + min(max(k, 0), nz);
+        const float* z = sZ[k & 1];
         AxisCoef a;
-        a.cam1_n = z[(kCam1 * 2 + 0) * nz1];
-        a.ca_n = z[(kCa * 2 + 0) * nz1];
-        a.rp_n = z[(kRp * 2 + 0) * nz1];
-        a.ph_n = z[(kPh * 2 + 0) * nz1];
-        a.q_n = z[(kQ * 2 + 0) * nz1];
-        a.cam1_h = z[(kCam1 * 2 + 1) * nz1];
-        a.ca_h = z[(kCa * 2 + 1) * nz1];
-        a.rp_h = z[(kRp * 2 + 1) * nz1];
-        a.ph_h = z[(kPh * 2 + 1) * nz1];
-        a.q_h = z[(kQ * 2 + 1) * nz1];
+        a.cam1_n = z[kCam1 * 2 + 0];
+        a.ca_n = z[kCa * 2 + 0];
+        a.rp_n = z[kRp * 2 + 0];
+        a.ph_n = z[kPh * 2 + 0];
+        a.q_n = z[kQ * 2 + 0];
+        a.cam1_h = z[kCam1 * 2 + 1];
+        a.ca_h = z[kCa * 2 + 1];
+        a.rp_h = z[kRp * 2 + 1];
+        a.ph_h = z[kPh * 2 + 1];
+        a.q_h = z[kQ * 2 + 1];
         return a;
     };
+    const bool z_lane = wave == TY + 1 && lane < 10;   // writes entry `lane` of the ring
+    const int zent = lane % 10;
 
     if (sizeof(CT) == 1) {
         for (int e = tid; e < kLdsClasses; e += NT) {
@@ -200,43 +194,48 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         }
         return ce;
     };
+    // byte offset of node (ii, jj, k), or of the guard words when it is off the grid
     auto node_at = [&](int ii, int jj, int k) {
         const bool ok = ((unsigned)ii <= (unsigned)nx) & ((unsigned)jj <= (unsigned)ny) &
                         ((unsigned)k <= (unsigned)nz);
-        return ok ? ii + jj * sy + k * sz : guard;
+        return ok ? (uint32_t)(ii + jj * sy + k * sz) * 4u : guardb;
     };
 
     const bool px = in_px(i), py = in_py(j);
     const AxisCoef X = axis_coef(cxp, nx1, i), Y = axis_coef(cyp, ny1, j);
-    const int node0 = i + j * sy;
+    const int node0 = i + j * sy;               // used only where ib holds
+    const uint32_t node0b = (uint32_t)node0 * 4u;
     const int64_t ms = B.max_steps;
 
-    struct Stage { float ex, ey, ez; };
+    struct Stage { float ex, ey, ez, z; };
     struct Col { float hx, hy, hz, bx, by, bz, dx, dy, dz; CT c; };
     auto load_stage = [&](int p) {
         Stage s;
-        s.ex = gEx[node_at(i, j, p + 1)];
-        s.ey = gEy[node_at(i, j, p + 1)];
-        s.ez = gEz[node_at(i, j, p)];
+        const uint32_t up = node_at(i, j, p + 1);
+        s.ex = ld_at(gE, up);
+        s.ey = ld_at(gE, up + cs);
+        s.ez = ld_at(gE, node_at(i, j, p) + cs2);
+        s.z = czp[zent * nz1 + min(p, nz)];       // every lane loads one (exact wait counts)
         return s;
     };
     // every load is issued on every path (absent operands read the zero guard
     // words), so the wait counts stay exact
     auto load_col = [&](int p, Col& o) {
-        const int n = node0 + p * sz;
+        const uint32_t n = node0b + (uint32_t)p * szb;
         const bool pz = in_pz(p);
         const bool okh = rH1 && ib && p <= nz, oke = rE1 && ib && p <= nz;
-        const int nh = okh ? n : guard;
-        o.hx = gHx[nh];
-        o.hy = gHy[nh];
-        o.hz = gHz[nh];
-        o.bx = gBx[okh && (px || py) ? n : guard];
-        o.by = gBy[okh && (py || pz) ? n : guard];
-        o.bz = gBz[okh && (pz || px) ? n : guard];
-        o.c = cls[oke ? n : guard];
-        o.dx = Dx[oke && (px || py) ? n : guard];
-        o.dy = Dy[oke && (py || pz) ? n : guard];
-        o.dz = Dz[oke && (pz || px) ? n : guard];
+        const uint32_t nh = okh ? n : guardb;
+        o.hx = ld_at(gH, nh);
+        o.hy = ld_at(gH, nh + cs);
+        o.hz = ld_at(gH, nh + cs2);
+        o.bx = ld_at(gB, okh && (px || py) ? n : guardb);
+        o.by = ld_at(gB, (okh && (py || pz) ? n : guardb) + cs);
+        o.bz = ld_at(gB, (okh && (pz || px) ? n : guardb) + cs2);
+        const uint32_t ne = oke ? n : guardb;
+        o.c = ld_at_t<CT>(cls, sizeof(CT) == 1 ? ne >> 2 : ne >> 1);
+        o.dx = ld_at(gD, oke && (px || py) ? n : guardb);
+        o.dy = ld_at(gD, (oke && (py || pz) ? n : guardb) + cs);
+        o.dz = ld_at(gD, (oke && (pz || px) ? n : guardb) + cs2);
     };
     auto source_sum = [&](int node, int64_t s) {
         float js = 0.0f;
@@ -256,8 +255,8 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
     };
 
     // staging of the first plane
-    sE0x[0][r][c] = gEx[node_at(i, j, k0)];
-    sE0y[0][r][c] = gEy[node_at(i, j, k0)];
+    sE0x[0][r][c] = ld_at(gE, node_at(i, j, k0));
+    sE0y[0][r][c] = ld_at(gE, node_at(i, j, k0) + cs);
     Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
     Col cA, cB;
     load_col(k0, cA);
@@ -277,10 +276,11 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         sE0x[nxt][r][c] = st.ex;
         sE0y[nxt][r][c] = st.ey;
         sE0z[r][c] = st.ez;
+        if (z_lane) sZ[k & 1][lane] = st.z;
         st = load_stage(k + 2);
         load_col(k + 1, nxt_col);
-        const AxisCoef Zk = z_coef(k);
         __syncthreads();
+        const AxisCoef Zk = z_coef(k);
 
         // ---- H1 of plane k: B then H, step n -> n+1/2
         const bool okk = ib && k <= nz;
@@ -361,13 +361,13 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
                 const float dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
                 h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
                 if (own && livem) {
-                    const int node = node0 + m * sz;
-                    dHx[node] = h2x;
-                    dHy[node] = h2y;
-                    dHz[node] = h2z;
-                    if (px || py) dBx[node] = p_b1x + dbx;
-                    if (py || pzm) dBy[node] = p_b1y + dby;
-                    if (pzm || px) dBz[node] = p_b1z + dbz;
+                    const uint32_t nb = node0b + (uint32_t)m * szb;
+                    st_at(dH, nb, h2x);
+                    st_at(dH, nb + cs, h2y);
+                    st_at(dH, nb + cs2, h2z);
+                    if (px || py) st_at(dB, nb, p_b1x + dbx);
+                    if (py || pzm) st_at(dB, nb + cs, p_b1y + dby);
+                    if (pzm || px) st_at(dB, nb + cs2, p_b1z + dbz);
                 }
             }
             sH2x[r][c] = h2x;
@@ -394,12 +394,13 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
             exn = (ce.flags & kUpdEx) ? exn : 0.0f;
             eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
             ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
-            dEx[node] = exn;
-            dEy[node] = eyn;
-            dEz[node] = ezn;
-            if (px || py) dDx[node] = (ce.flags & kUpdEx) ? p_d1x + ddx : p_d1x;
-            if (py || pzm) dDy[node] = (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y;
-            if (pzm || px) dDz[node] = (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z;
+            const uint32_t nb = node0b + (uint32_t)m * szb;
+            st_at(dE, nb, exn);
+            st_at(dE, nb + cs, eyn);
+            st_at(dE, nb + cs2, ezn);
+            if (px || py) st_at(dD, nb, (ce.flags & kUpdEx) ? p_d1x + ddx : p_d1x);
+            if (py || pzm) st_at(dD, nb + cs, (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y);
+            if (pzm || px) st_at(dD, nb + cs2, (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z);
             if (ce.flags & kPrbEz) record_probe(node, step + 1, ezn);
             bad |= !isfinite(exn + eyn + ezn);
         }
@@ -422,9 +423,10 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
 struct Shape2 {
     int tx, ty;
 };
-// 64*TY + 128 threads: up to TY = 10 the block has at most 12 waves, three per
-// SIMD, which leaves the kernel the 157 VGPRs it needs without spilling
-static const Shape2 kShapes2[] = {{64, 10}, {64, 9}, {64, 8}};
+// 64*TY + 128 threads.  TY = 14 and 12 run four waves per SIMD (128 VGPRs, a few
+// spilled); TY <= 10 runs three (the kernel's 131 VGPRs fit).  Taller tiles
+// recompute fewer halo rows per owned row.
+static const Shape2 kShapes2[] = {{64, 14}, {64, 12}, {64, 10}, {64, 9}, {64, 8}};
 static const int kNumShapes2 = sizeof(kShapes2) / sizeof(kShapes2[0]);
 
 int num_shapes2() { return kNumShapes2; }
@@ -461,6 +463,8 @@ static int occupancy2_t(bool wide)
 int field_step2_occupancy(int tile_y, bool wide)
 {
     switch (tile_y) {
+        case 14: return occupancy2_t<14>(wide);
+        case 12: return occupancy2_t<12>(wide);
         case 10: return occupancy2_t<10>(wide);
         case 9: return occupancy2_t<9>(wide);
         case 8: return occupancy2_t<8>(wide);
@@ -472,6 +476,8 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
                               int rel, int flip, bool wide, hipStream_t st)
 {
     switch (tile_y) {
+        case 14: return launch2_t<14>(boards, tiles, ntiles, rel, flip, wide, st);
+        case 12: return launch2_t<12>(boards, tiles, ntiles, rel, flip, wide, st);
         case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, st);
         case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, st);
         case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, st);

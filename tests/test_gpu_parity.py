@@ -16,7 +16,7 @@ from _util import live_masks, rel_l2
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("ex", "ey", "ez", "hx", "hy", "hz", "ddx", "ddy", "ddz", "bbx", "bby", "bbz")
-TWO_STEP = (64, 10, 2)   # a two-steps-per-pass shape of the field kernel
+TWO_STEP = (64, 10, 2)   # a two-steps-per-pass shape other than the default 64x14x2
 
 
 def announce(msg):
