@@ -67,33 +67,21 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
     const bool col_ok = main_wave && (i <= nx) && (j >= 0) && (j <= ny);
     const bool own = col_ok && ty > 0;
     const int64_t step = B.step[0] + B.rel0 + rel;
-    const int par = (int)((B.step[1] + B.flip0 + flip) & 1);
-    cgfloat* __restrict__ gEx = (cgfloat*)B.f[par][0];
-    cgfloat* __restrict__ gEy = (cgfloat*)B.f[par][1];
-    cgfloat* __restrict__ gEz = (cgfloat*)B.f[par][2];
-    cgfloat* __restrict__ gHx = (cgfloat*)B.f[par][3];
-    cgfloat* __restrict__ gHy = (cgfloat*)B.f[par][4];
-    cgfloat* __restrict__ gHz = (cgfloat*)B.f[par][5];
-    cgfloat* __restrict__ gBx = (cgfloat*)B.f[par][6];
-    cgfloat* __restrict__ gBy = (cgfloat*)B.f[par][7];
-    cgfloat* __restrict__ gBz = (cgfloat*)B.f[par][8];
-    gfloat* __restrict__ dEx = (gfloat*)B.f[par ^ 1][0];
-    gfloat* __restrict__ dEy = (gfloat*)B.f[par ^ 1][1];
-    gfloat* __restrict__ dEz = (gfloat*)B.f[par ^ 1][2];
-    gfloat* __restrict__ dHx = (gfloat*)B.f[par ^ 1][3];
-    gfloat* __restrict__ dHy = (gfloat*)B.f[par ^ 1][4];
-    gfloat* __restrict__ dHz = (gfloat*)B.f[par ^ 1][5];
-    gfloat* __restrict__ dBx = (gfloat*)B.f[par ^ 1][6];
-    gfloat* __restrict__ dBy = (gfloat*)B.f[par ^ 1][7];
-    gfloat* __restrict__ dBz = (gfloat*)B.f[par ^ 1][8];
-    cgfloat* __restrict__ Dx = (cgfloat*)B.d[par][0];
-    cgfloat* __restrict__ Dy = (cgfloat*)B.d[par][1];
-    cgfloat* __restrict__ Dz = (cgfloat*)B.d[par][2];
-    gfloat* __restrict__ dDx = (gfloat*)B.d[par ^ 1][0];
-    gfloat* __restrict__ dDy = (gfloat*)B.d[par ^ 1][1];
-    gfloat* __restrict__ dDz = (gfloat*)B.d[par ^ 1][2];
-    const __attribute__((address_space(1))) CT* __restrict__ cls =
-        (const __attribute__((address_space(1))) CT*)B.cls;
+    // uniform by construction; readfirstlane lets the compiler keep the array
+    // bases it selects in scalar registers (scalar-base 32-bit addressing)
+    const int par = __builtin_amdgcn_readfirstlane((int)((B.step[1] + B.flip0 + flip) & 1));
+    // one base per field and copy; y and z sit cs and 2 cs bytes after x
+    const float* gE = B.f[par][0];
+    const float* gH = B.f[par][3];
+    const float* gB = B.f[par][6];
+    const float* gD = B.d[par][0];
+    float* dE = B.f[par ^ 1][0];
+    float* dH = B.f[par ^ 1][3];
+    float* dB = B.f[par ^ 1][6];
+    float* dD = B.d[par ^ 1][0];
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride;
+    const uint32_t szb = (uint32_t)sz * 4u, guardb = (uint32_t)guard * 4u;
+    const void* cls = B.cls;
     const __attribute__((address_space(1))) ClassEntry* __restrict__ ctab =
         (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
@@ -117,10 +105,11 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             sTab[e].flags = ctab[c].flags;
         }
     }
+    // byte offset of node (ii, jj, k), or of the guard words when it is off the grid
     auto node_at = [&](int ii, int jj, int k) {
         const bool ok = ((unsigned)ii <= (unsigned)nx) & ((unsigned)jj <= (unsigned)ny) &
                         ((unsigned)k <= (unsigned)nz);
-        return ok ? ii + jj * sy + k * sz : guard;
+        return ok ? (uint32_t)(ii + jj * sy + k * sz) * 4u : guardb;
     };
 
     if (main_wave) {
@@ -135,38 +124,41 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
         const float y_cam1_h = CYf(kCam1, 1, j), y_ca_h = CYf(kCa, 1, j), y_rp_h = CYf(kRp, 1, j),
                     y_ph_h = CYf(kPh, 1, j), y_q_h = CYf(kQ, 1, j);
         const int c = tx + 1;
-        const int node0 = i + j * sy;
+        const int node0 = i + j * sy;               // used only where col_ok holds
+        const uint32_t node0b = (uint32_t)node0 * 4u;
         struct Stage { float ex, ey, ez; };
         struct Col { float hx, hy, hz, bx, by, bz, dx, dy, dz; CT c; };
         auto load_stage = [&](int p) {
             Stage s;
-            s.ex = gEx[node_at(i, j, p + 1)];
-            s.ey = gEy[node_at(i, j, p + 1)];
-            s.ez = gEz[node_at(i, j, p)];
+            const uint32_t up = node_at(i, j, p + 1);
+            s.ex = ld_at(gE, up);
+            s.ey = ld_at(gE, up + cs);
+            s.ez = ld_at(gE, node_at(i, j, p) + cs2);
             return s;
         };
         // every load is issued on every path (absent operands read the zero
         // guard words), so the wait counts stay exact and the prefetch overlaps
         auto load_col = [&](int p, Col& o) {
-            const int n = node0 + p * sz;
+            const uint32_t n = node0b + (uint32_t)p * szb;
             const bool pz = in_pz(p);
             const bool okp = col_ok && p <= nz, ownp = own && p <= nz;
             const bool live = ownp && p >= kb;   // E of this plane is stepped here
-            const int nh = okp ? n : guard;
+            const uint32_t nh = okp ? n : guardb;
             // the halo row only feeds Hx and Hz to the row above it
-            o.hx = gHx[nh];
-            o.hy = gHy[ownp ? n : guard];
-            o.hz = gHz[nh];
-            o.bx = gBx[okp && (px || py) ? n : guard];
-            o.by = gBy[ownp && (py || pz) ? n : guard];
-            o.bz = gBz[okp && (pz || px) ? n : guard];
-            o.c = cls[live ? n : guard];
-            o.dx = Dx[live && (px || py) ? n : guard];
-            o.dy = Dy[live && (py || pz) ? n : guard];
-            o.dz = Dz[live && (pz || px) ? n : guard];
+            o.hx = ld_at(gH, nh);
+            o.hy = ld_at(gH, (ownp ? n : guardb) + cs);
+            o.hz = ld_at(gH, nh + cs2);
+            o.bx = ld_at(gB, okp && (px || py) ? n : guardb);
+            o.by = ld_at(gB, (ownp && (py || pz) ? n : guardb) + cs);
+            o.bz = ld_at(gB, (okp && (pz || px) ? n : guardb) + cs2);
+            const uint32_t ne = live ? n : guardb;
+            o.c = ld_at_t<CT>(cls, sizeof(CT) == 1 ? ne >> 2 : ne >> 1);
+            o.dx = ld_at(gD, live && (px || py) ? n : guardb);
+            o.dy = ld_at(gD, (live && (py || pz) ? n : guardb) + cs);
+            o.dz = ld_at(gD, (live && (pz || px) ? n : guardb) + cs2);
         };
-        sEx[0][ty][c] = gEx[node_at(i, j, k0)];
-        sEy[0][ty][c] = gEy[node_at(i, j, k0)];
+        sEx[0][ty][c] = ld_at(gE, node_at(i, j, k0));
+        sEy[0][ty][c] = ld_at(gE, node_at(i, j, k0) + cs);
         Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
         Col cA, cB;
         load_col(k0, cA);
@@ -180,6 +172,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
             const bool pz = in_pz(k);
             const bool nbx = px || py, nby = py || pz, nbz = pz || px;
             const int node = node0 + k * sz;
+            const uint32_t nb = node0b + (uint32_t)k * szb;
             sEx[nxt][ty][c] = st.ex;
             sEy[nxt][ty][c] = st.ey;
             sEz[ty][c] = st.ez;
@@ -211,12 +204,12 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                 const float dbz = fmaf(x_cam1_h, o.bz, -x_rp_h * cze);
                 hzn = fmaf(y_ca_h, o.hz, y_rp_h * fmaf(z_ph_n, dbz, z_q_n * o.bz));
                 if (own && live) {
-                    dHx[node] = hxn;
-                    dHy[node] = hyn;
-                    dHz[node] = hzn;
-                    if (nbx) dBx[node] = o.bx + dbx;
-                    if (nby) dBy[node] = o.by + dby;
-                    if (nbz) dBz[node] = o.bz + dbz;
+                    st_at(dH, nb, hxn);
+                    st_at(dH, nb + cs, hyn);
+                    st_at(dH, nb + cs2, hzn);
+                    if (nbx) st_at(dB, nb, o.bx + dbx);
+                    if (nby) st_at(dB, nb + cs, o.by + dby);
+                    if (nbz) st_at(dB, nb + cs2, o.bz + dbz);
                 }
             }
             sHx[ty][c] = hxn;
@@ -258,12 +251,12 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                 exn = (ce.flags & kUpdEx) ? exn : 0.0f;
                 eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
                 ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
-                dEx[node] = exn;
-                dEy[node] = eyn;
-                dEz[node] = ezn;
-                if (nbx) dDx[node] = (ce.flags & kUpdEx) ? o.dx + ddx : o.dx;
-                if (nby) dDy[node] = (ce.flags & kUpdEy) ? o.dy + ddy : o.dy;
-                if (nbz) dDz[node] = (ce.flags & kUpdEz) ? o.dz + ddz : o.dz;
+                st_at(dE, nb, exn);
+                st_at(dE, nb + cs, eyn);
+                st_at(dE, nb + cs2, ezn);
+                if (nbx) st_at(dD, nb, (ce.flags & kUpdEx) ? o.dx + ddx : o.dx);
+                if (nby) st_at(dD, nb + cs, (ce.flags & kUpdEy) ? o.dy + ddy : o.dy);
+                if (nbz) st_at(dD, nb + cs2, (ce.flags & kUpdEz) ? o.dz + ddz : o.dz);
                 if (ce.flags & kPrbEz) {
                     const __attribute__((address_space(1))) int32_t* pn =
                         (const __attribute__((address_space(1))) int32_t*)B.prb_node;
@@ -302,7 +295,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
         const float hx_rp_h = CXf(kRp, 1, ih), hx_ca_h = CXf(kCa, 1, ih), hx_cam1_h = CXf(kCam1, 1, ih);
         const float hy_ph_n = CYf(kPh, 0, jh), hy_q_n = CYf(kQ, 0, jh), hy_ca_h = CYf(kCa, 1, jh),
                     hy_rp_h = CYf(kRp, 1, jh);
-        const int hnode0 = ih + jh * sy;
+        const uint32_t hnode0b = (uint32_t)(ih + jh * sy) * 4u;   // used only where h_ok holds
         struct XStage { float rx[R], rz[R], cx_, cy_, cz_; };
         struct XCol { float hy, hz, by, bz; };
         auto load_xstage = [&](int p) {
@@ -310,33 +303,33 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int ii = i0 + lane + 64 * r;
-                s.rx[r] = gEx[node_at(ii, jr, p + 1)];
-                s.rz[r] = gEz[node_at(ii, jr, p)];
+                s.rx[r] = ld_at(gE, node_at(ii, jr, p + 1));
+                s.rz[r] = ld_at(gE, node_at(ii, jr, p) + cs2);
             }
             const int ii = col_lane ? ic_ : -1;
-            s.cx_ = gEx[node_at(cc == 0 ? ii : -1, jc_, p + 1)];
-            s.cy_ = gEy[node_at(ii, jc_, p + 1)];
-            s.cz_ = gEz[node_at(ii, jc_, p)];
+            s.cx_ = ld_at(gE, node_at(cc == 0 ? ii : -1, jc_, p + 1));
+            s.cy_ = ld_at(gE, node_at(ii, jc_, p + 1) + cs);
+            s.cz_ = ld_at(gE, node_at(ii, jc_, p) + cs2);
             return s;
         };
         auto load_xcol = [&](int p, XCol& o) {
-            const int n = hnode0 + p * sz;
+            const uint32_t n = hnode0b + (uint32_t)p * szb;
             const bool pz = in_pz(p);
             const bool okp = h_ok && p <= nz;
-            o.hy = gHy[okp ? n : guard];
-            o.hz = gHz[okp ? n : guard];
-            o.by = gBy[okp && (hpy || pz) ? n : guard];
-            o.bz = gBz[okp && (pz || hpx) ? n : guard];
+            o.hy = ld_at(gH, (okp ? n : guardb) + cs);
+            o.hz = ld_at(gH, (okp ? n : guardb) + cs2);
+            o.by = ld_at(gB, (okp && (hpy || pz) ? n : guardb) + cs);
+            o.bz = ld_at(gB, (okp && (pz || hpx) ? n : guardb) + cs2);
         };
         {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int ii = i0 + lane + 64 * r;
-                sEx[0][TY][1 + lane + 64 * r] = gEx[node_at(ii, jr, k0)];
+                sEx[0][TY][1 + lane + 64 * r] = ld_at(gE, node_at(ii, jr, k0));
             }
             if (col_lane) {
-                sEx[0][cr][cc] = gEx[node_at(cc == 0 ? ic_ : -1, jc_, k0)];
-                sEy[0][cr][cc] = gEy[node_at(ic_, jc_, k0)];
+                sEx[0][cr][cc] = ld_at(gE, node_at(cc == 0 ? ic_ : -1, jc_, k0));
+                sEy[0][cr][cc] = ld_at(gE, node_at(ic_, jc_, k0) + cs);
             }
         }
         XStage s0 = load_xstage(k0), s1 = load_xstage(k0 + 1);
