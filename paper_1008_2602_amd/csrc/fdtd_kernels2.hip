@@ -194,27 +194,24 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         }
         return ce;
     };
-    // byte offset of node (ii, jj, k), or of the guard words when it is off the grid
-    auto node_at = [&](int ii, int jj, int k) {
-        const bool ok = ((unsigned)ii <= (unsigned)nx) & ((unsigned)jj <= (unsigned)ny) &
-                        ((unsigned)k <= (unsigned)nz);
-        return ok ? (uint32_t)(ii + jj * sy + k * sz) * 4u : guardb;
-    };
+
 
     const bool px = in_px(i), py = in_py(j);
     const AxisCoef X = axis_coef(cxp, nx1, i), Y = axis_coef(cyp, ny1, j);
-    const int node0 = i + j * sy;               // used only where ib holds
-    const uint32_t node0b = (uint32_t)node0 * 4u;
+    // byte offset of this lane's node in plane 0 (meaningful only where ib holds)
+    const uint32_t node0b = (uint32_t)(i + j * sy) * 4u;
+    // byte offset of this lane's node in plane p, or of the guard words
+    auto at_plane = [&](int p) { return ib && (unsigned)p <= (unsigned)nz ? node0b + (uint32_t)p * szb : guardb; };
     const int64_t ms = B.max_steps;
 
     struct Stage { float ex, ey, ez, z; };
     struct Col { float hx, hy, hz, bx, by, bz, dx, dy, dz; CT c; };
     auto load_stage = [&](int p) {
         Stage s;
-        const uint32_t up = node_at(i, j, p + 1);
+        const uint32_t up = at_plane(p + 1);
         s.ex = ld_at(gE, up);
         s.ey = ld_at(gE, up + cs);
-        s.ez = ld_at(gE, node_at(i, j, p) + cs2);
+        s.ez = ld_at(gE, at_plane(p) + cs2);
         s.z = czp[zent * nz1 + min(p, nz)];       // every lane loads one (exact wait counts)
         return s;
     };
@@ -255,8 +252,8 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
     };
 
     // staging of the first plane
-    sE0x[0][r][c] = ld_at(gE, node_at(i, j, k0));
-    sE0y[0][r][c] = ld_at(gE, node_at(i, j, k0) + cs);
+    sE0x[0][r][c] = ld_at(gE, at_plane(k0));
+    sE0y[0][r][c] = ld_at(gE, at_plane(k0) + cs);
     Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
     Col cA, cB;
     load_col(k0, cA);
@@ -314,7 +311,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         if (rE1) {
             if (okk) {
                 const ClassEntry ce = class_entry(o.c);
-                const int node = node0 + k * sz;
+                const int node = (int)(node0b >> 2) + k * sz;   // node index (source/probe match)
                 const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
                 const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
                 const float ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
@@ -379,7 +376,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         // ---- E2 of plane m on the owned patch: D then E, step n+1 -> n+2
         if (own && livem) {
             const ClassEntry ce = class_entry(p_c);
-            const int node = node0 + m * sz;
+            const int node = (int)(node0b >> 2) + m * sz;
             const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
             const float ddx = fmaf(Y.cam1_n, p_d1x, Y.rp_n * chx);
             float exn = fmaf(Zm.ca_n, p_e1x, Zm.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * p_d1x)));
