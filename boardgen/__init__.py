@@ -52,6 +52,7 @@ class Source:
     J0: float = 1.0e6          # A/m^2 (1 A/mm^2, Results section)
     t0: float = 120e-12        # s
     sigma: float = 30e-12      # s (standard deviation for GAUSS, tau for DGAUSS)
+    R: float = 0.0             # > 0: resistive voltage source, J0 is then V0 in volts
 
 
 @dataclass

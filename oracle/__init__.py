@@ -52,6 +52,7 @@ class _Problem(C.Structure):
                 ("eps_r_cell", C.c_void_p), ("pec_mask", C.c_void_p),
                 ("nsrc", C.c_int32), ("src_ijk", C.c_void_p), ("src_wave", C.c_void_p),
                 ("src_J0", C.c_void_p), ("src_t0", C.c_void_p), ("src_sigma", C.c_void_p),
+                ("src_R", C.c_void_p),
                 ("nprobe", C.c_int32), ("probe_ijk", C.c_void_p),
                 ("nfreq", C.c_int32), ("freqs", C.c_void_p)]
 
@@ -114,6 +115,13 @@ class Problem:
         self.src_J0 = np.array([s.J0 for s in b.sources], np.float64)
         self.src_t0 = np.array([s.t0 for s in b.sources], np.float64)
         self.src_sigma = np.array([s.sigma for s in b.sources], np.float64)
+        self.src_R = np.array([getattr(s, "R", 0.0) for s in b.sources], np.float64)
+        for s in b.sources:
+            if getattr(s, "R", 0.0) > 0.0:
+                in_pml = ((s.i < b.npml[0] or s.i >= b.nx - b.npml[1]) or
+                          (s.j < b.npml[2] or s.j >= b.ny - b.npml[3]) or
+                          (s.k < b.npml[4] or s.k >= b.nz - b.npml[5]))
+                assert not in_pml, "a resistive source must sit outside every PML slab"
         self.probe_ijk = np.array(b.probes, np.int32).reshape(len(b.probes), 3)
         self.freqs = (np.zeros(0) if b.dft_freqs is None
                       else np.ascontiguousarray(b.dft_freqs, dtype=np.float64))
@@ -131,6 +139,7 @@ class Problem:
         p.src_J0 = self.src_J0.ctypes.data
         p.src_t0 = self.src_t0.ctypes.data
         p.src_sigma = self.src_sigma.ctypes.data
+        p.src_R = self.src_R.ctypes.data
         p.nprobe = len(b.probes)
         p.probe_ijk = self.probe_ijk.ctypes.data
         p.nfreq = len(self.freqs)

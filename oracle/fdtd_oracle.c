@@ -21,7 +21,12 @@
  *   - sigma and kappa are graded polynomially from the PML interface to the
  *     outer PEC wall (Eq. 5, read as (depth/d)^m);
  *   - the power and ground planes zero the tangential Ex, Ey on their edges;
- *   - a current source enters the D_z update as -J_z at the half step.
+ *   - a current source enters the D_z update as -J_z at the half step;
+ *   - a resistive voltage source (Results section, the Table 1 run, built with
+ *     semi-explicit update coefficients) is a lumped element on one E_z edge of
+ *     the interior: its current density (dz Ebar - V_s)/(R dx dy) enters like
+ *     J_z, with Ebar the mean of E_z^n and E_z^{n+1}, and the update is solved
+ *     for E_z^{n+1}.
  * Every array is stored for every node (the paper's unified storage of D and B
  * beside E and H).  Loops are plain triple loops in FP64, with no tiling.
  *
@@ -63,6 +68,8 @@ typedef struct {
     const double* src_J0;
     const double* src_t0;
     const double* src_sigma;
+    const double* src_R;       /* NULL or per source: 0 current source (J0 in A/m^2),
+                                  > 0 resistive voltage source (J0 = V0 in volts) */
     int32_t nprobe;
     const int32_t* probe_ijk;  /* 3*nprobe, Ez(i,j,k+1/2) */
     int32_t nfreq;
@@ -276,14 +283,33 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     double eps = OR_EPS0 * 0.25 *
                         ((double)er[CELL(i - 1, j - 1, k)] + (double)er[CELL(i, j - 1, k)] +
                          (double)er[CELL(i - 1, j, k)] + (double)er[CELL(i, j, k)]);
-                    double J = 0.0;
+                    double J = 0.0, g_l = 0.0, j_v = 0.0;
                     for (int q = 0; q < p->nsrc; ++q)
                         if (p->src_ijk[3 * q] == i && p->src_ijk[3 * q + 1] == j &&
-                            p->src_ijk[3 * q + 2] == k)
-                            J += or_waveform(p->src_wave[q], p->src_J0[q], p->src_t0[q],
-                                             p->src_sigma[q], tJ);
+                            p->src_ijk[3 * q + 2] == k) {
+                            const double w = or_waveform(p->src_wave[q], p->src_J0[q],
+                                                         p->src_t0[q], p->src_sigma[q], tJ);
+                            if (p->src_R && p->src_R[q] > 0.0) {
+                                /* lumped current density = g_l Ebar - j_v */
+                                g_l += p->dz / (p->src_R[q] * p->dx * p->dy);
+                                j_v += w / (p->src_R[q] * p->dx * p->dy);
+                            } else {
+                                J += w;
+                            }
+                        }
                     double curl = (hy[c] - hy[IX(i - 1, j, k)]) * rdx
                                 - (hx[c] - hx[IX(i, j - 1, k)]) * rdy - J;
+                    if (g_l != 0.0) {
+                        /* resistive source on an interior edge (kappa 1, sigma 0, so
+                         * D = eps E and the D update is D += dt (curl - J_lumped)):
+                         * eps (E' - E)/dt = curl - g_l (E' + E)/2 + j_v, solved for E' */
+                        const double beta = 0.5 * dt * g_l / eps;
+                        const double e_n = ((1.0 - beta) * ez[c] + dt / eps * (curl + j_v)) /
+                                           (1.0 + beta);
+                        Dz[c] += eps * (e_n - ez[c]);
+                        ez[c] = e_n;
+                        continue;
+                    }
                     double d_o = Dz[c];
                     double d_n = X.a_n[i] * d_o + X.b_n[i] * curl;
                     Dz[c] = d_n;

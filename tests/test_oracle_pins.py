@@ -6,6 +6,7 @@
 * P4  eigen-angles of the one-step map == closed-form discrete dispersion
 * P8  linearity, reciprocity and mirror symmetry
 * P10 the probe FFT against a direct DFT
+* P11 resistive voltage source: discrete energy balance, R -> infinity limits
 * Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
 """
 import numpy as np
@@ -359,3 +360,104 @@ def test_eq5_grading_hand_values(oracle_mod):
     b2 = boardgen.small_board()
     b2.pml_kappa_max = 5.0
     assert abs(oracle_mod.sigma_kappa(b2, 2, 2.0)[1] - (1 + 4 * (6 / 8) ** 3)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P11  resistive voltage source (Results section, the Table 1 run): a lumped
+# element on one E_z edge, current density (dz Ebar - V_s)/(R dx dy)
+# ---------------------------------------------------------------------------
+
+def _resistive_run(oracle_mod, b, st, nsteps, ijk):
+    dt = oracle_mod.time_step(b)
+    eps = bruteforce.Stepper(b, dt).eps
+    states = [_snap(st)]
+    for _ in range(nsteps):
+        oracle_mod.run(b, nsteps=1, state=st)
+        states.append(_snap(st))
+    i, j, k = ijk
+    ez = np.array([s[0]["ez"][k, j, i] for s in states])
+    return dt, eps, states, ez
+
+
+def _lumped_balance(oracle_mod, b, src, dt, eps, states, ez):
+    """Residual and scale of the discrete Poynting balance
+    W^{n+1} - W^n = -dt (Vbar - V_s) Vbar / R,  Vbar = dz (E^{n+1} + E^n) / 2,
+    with V_s taken at the half step.  states[0] is the initial (E^0, H^{-1/2});
+    the energy W^n pairs E^n with H^{n-1/2} H^{n+1/2}."""
+    W = np.array([_energy(b, states[n][0], states[n][1], states[n + 1][1], eps)
+                  for n in range(len(states) - 1)])
+    n = np.arange(len(W) - 1)
+    vbar = b.dz * 0.5 * (ez[n + 1] + ez[n])
+    vs = np.array([oracle_mod.waveform(src.waveform, src.J0, src.t0, src.sigma,
+                                       (m + 0.5) * dt) for m in n])
+    dW = W[1:] - W[:-1]
+    loss = -dt * (vbar - vs) * vbar / src.R
+    return dict(res=dW - loss, dW=dW, vbar=vbar, vs=vs,
+                diss=dt * vbar * vbar / src.R, gain=dt * vs * vbar / src.R)
+
+
+def test_p11_resistor_energy_balance_no_drive(oracle_mod):
+    """V_s = 0: the resistor only dissipates, exactly dt Vbar^2 / R per step."""
+    b = _inhomogeneous_box(21)
+    src = boardgen.Source(5, 4, 2, boardgen.GAUSS, 0.0, 20e-12, 5e-12, R=10.0)
+    b.sources = [src]
+    st = _random_state(oracle_mod, b, 21, aux=False)
+    st["ez"][2, 4, 5] *= 30.0     # a large start value at the resistor
+    dt, eps, states, ez = _resistive_run(oracle_mod, b, st, 160, (5, 4, 2))
+    r = _lumped_balance(oracle_mod, b, src, dt, eps, states, ez)
+    W0 = _energy(b, states[0][0], states[0][1], states[1][1], eps)
+    assert np.all(r["dW"] <= 1e-13 * W0)                 # never gains energy
+    assert r["diss"].sum() > 1e-3 * W0                   # the loss is far above the residual
+    assert np.abs(r["res"]).max() < 1e-11 * W0
+
+
+def test_p11_resistor_energy_balance_driven(oracle_mod):
+    """V_s != 0 from rest: source power dt V_s Vbar / R in, dt Vbar^2 / R lost."""
+    b = _inhomogeneous_box(22)
+    src = boardgen.Source(6, 5, 3, boardgen.GAUSS, 5.0, 40e-12, 10e-12, R=10.0)
+    b.sources = [src]
+    st = oracle_mod.new_state(b)
+    dt, eps, states, ez = _resistive_run(oracle_mod, b, st, 220, (6, 5, 3))
+    r = _lumped_balance(oracle_mod, b, src, dt, eps, states, ez)
+    scale = np.abs(r["gain"]).sum()
+    assert scale > 0 and r["diss"].sum() > 1e-3 * scale
+    assert np.abs(r["res"]).max() < 1e-11 * scale
+    # the balance tells the oracle's update from plausible mistakes: a flipped
+    # source sign, or a resistor taken explicitly at E^n instead of at Ebar
+    flipped = r["dW"] + dt * (r["vbar"] + r["vs"]) * r["vbar"] / src.R
+    assert np.abs(flipped).max() > 1e-3 * scale
+    e_n = b.dz * ez[:len(r["dW"])]
+    explicit = r["dW"] + dt * (e_n - r["vs"]) * r["vbar"] / src.R
+    assert np.abs(explicit).max() > 1e3 * np.abs(r["res"]).max()
+
+
+def test_p11_resistor_tends_to_a_current_source(oracle_mod):
+    """R -> infinity with V_s = -J R dx dy held fixed: the lumped current density
+    (dz Ebar - V_s)/(R dx dy) tends to the plain current density J (Eq. 4 with
+    -J in the D_z update); the difference shrinks like 1/R."""
+    b = _inhomogeneous_box(23)
+    b.probes = [(4, 6, 2), (8, 3, 5)]
+    J = 1e6
+    ref_b = _inhomogeneous_box(23)
+    ref_b.probes = b.probes
+    ref_b.sources = [boardgen.Source(6, 5, 3, boardgen.GAUSS, J, 40e-12, 10e-12)]
+    ref = oracle_mod.run(ref_b, nsteps=200).probes
+    errs = []
+    for R in (1e6, 1e8):
+        b.sources = [boardgen.Source(6, 5, 3, boardgen.GAUSS, -J * R * b.dx * b.dy,
+                                     40e-12, 10e-12, R=R)]
+        got = oracle_mod.run(b, nsteps=200).probes
+        errs.append(rel_max(got, ref))
+    assert errs[0] < 1e-3 and errs[1] < 1e-5
+    assert 50 < errs[0] / errs[1] < 200
+
+
+def test_p11_resistor_zero_drive_infinite_r_is_no_source(oracle_mod):
+    b = _inhomogeneous_box(24)
+    st0 = _random_state(oracle_mod, b, 24, aux=False)
+    st1 = {n: (v.copy() if isinstance(v, np.ndarray) else v) for n, v in st0.items()}
+    oracle_mod.run(b, nsteps=50, state=st0)
+    b.sources = [boardgen.Source(6, 5, 3, boardgen.GAUSS, 0.0, 40e-12, 10e-12, R=1e30)]
+    oracle_mod.run(b, nsteps=50, state=st1)
+    for n in ("ex", "ey", "ez", "hx", "hy", "hz"):
+        assert rel_max(st1[n], st0[n]) < 1e-14, n
