@@ -53,6 +53,7 @@ class Source:
     t0: float = 120e-12        # s
     sigma: float = 30e-12      # s (standard deviation for GAUSS, tau for DGAUSS)
     R: float = 0.0             # > 0: resistive voltage source, J0 is then V0 in volts
+                               # (an EMF raising node k+1 over node k, in series with R)
 
 
 @dataclass

@@ -24,9 +24,10 @@
  *   - a current source enters the D_z update as -J_z at the half step;
  *   - a resistive voltage source (Results section, the Table 1 run, built with
  *     semi-explicit update coefficients) is a lumped element on one E_z edge of
- *     the interior: its current density (dz Ebar - V_s)/(R dx dy) enters like
- *     J_z, with Ebar the mean of E_z^n and E_z^{n+1}, and the update is solved
- *     for E_z^{n+1}.
+ *     the interior: an EMF V_s that raises node k+1 over node k, in series with
+ *     R.  Its branch current density (dz Ebar + V_s)/(R dx dy) enters like J_z,
+ *     with Ebar the mean of E_z^n and E_z^{n+1}, and the update is solved for
+ *     E_z^{n+1}; open-circuited it holds dz E_z = -V_s.
  * Every array is stored for every node (the paper's unified storage of D and B
  * beside E and H).  Loops are plain triple loops in FP64, with no tiling.
  *
@@ -283,16 +284,16 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     double eps = OR_EPS0 * 0.25 *
                         ((double)er[CELL(i - 1, j - 1, k)] + (double)er[CELL(i, j - 1, k)] +
                          (double)er[CELL(i - 1, j, k)] + (double)er[CELL(i, j, k)]);
-                    double J = 0.0, g_l = 0.0, j_v = 0.0;
+                    double J = 0.0, g_l = 0.0;
                     for (int q = 0; q < p->nsrc; ++q)
                         if (p->src_ijk[3 * q] == i && p->src_ijk[3 * q + 1] == j &&
                             p->src_ijk[3 * q + 2] == k) {
                             const double w = or_waveform(p->src_wave[q], p->src_J0[q],
                                                          p->src_t0[q], p->src_sigma[q], tJ);
                             if (p->src_R && p->src_R[q] > 0.0) {
-                                /* lumped current density = g_l Ebar - j_v */
+                                /* branch current density = g_l Ebar + V_s/(R dx dy) */
                                 g_l += p->dz / (p->src_R[q] * p->dx * p->dy);
-                                j_v += w / (p->src_R[q] * p->dx * p->dy);
+                                J += w / (p->src_R[q] * p->dx * p->dy);
                             } else {
                                 J += w;
                             }
@@ -301,10 +302,11 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                                 - (hx[c] - hx[IX(i, j - 1, k)]) * rdy - J;
                     if (g_l != 0.0) {
                         /* resistive source on an interior edge (kappa 1, sigma 0, so
-                         * D = eps E and the D update is D += dt (curl - J_lumped)):
-                         * eps (E' - E)/dt = curl - g_l (E' + E)/2 + j_v, solved for E' */
+                         * D = eps E and the D update is D += dt (curl - J_branch)):
+                         * eps (E' - E)/dt = curl - g_l (E' + E)/2, solved for E'
+                         * (curl already holds -V_s/(R dx dy)) */
                         const double beta = 0.5 * dt * g_l / eps;
-                        const double e_n = ((1.0 - beta) * ez[c] + dt / eps * (curl + j_v)) /
+                        const double e_n = ((1.0 - beta) * ez[c] + dt / eps * curl) /
                                            (1.0 + beta);
                         Dz[c] += eps * (e_n - ez[c]);
                         ez[c] = e_n;

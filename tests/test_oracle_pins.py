@@ -364,7 +364,8 @@ def test_eq5_grading_hand_values(oracle_mod):
 
 # ---------------------------------------------------------------------------
 # P11  resistive voltage source (Results section, the Table 1 run): a lumped
-# element on one E_z edge, current density (dz Ebar - V_s)/(R dx dy)
+# element on one E_z edge, an EMF V_s raising node k+1 over node k in series
+# with R, branch current density (dz Ebar + V_s)/(R dx dy)
 # ---------------------------------------------------------------------------
 
 def _resistive_run(oracle_mod, b, st, nsteps, ijk):
@@ -381,7 +382,7 @@ def _resistive_run(oracle_mod, b, st, nsteps, ijk):
 
 def _lumped_balance(oracle_mod, b, src, dt, eps, states, ez):
     """Residual and scale of the discrete Poynting balance
-    W^{n+1} - W^n = -dt (Vbar - V_s) Vbar / R,  Vbar = dz (E^{n+1} + E^n) / 2,
+    W^{n+1} - W^n = -dt (Vbar + V_s) Vbar / R,  Vbar = dz (E^{n+1} + E^n) / 2,
     with V_s taken at the half step.  states[0] is the initial (E^0, H^{-1/2});
     the energy W^n pairs E^n with H^{n-1/2} H^{n+1/2}."""
     W = np.array([_energy(b, states[n][0], states[n][1], states[n + 1][1], eps)
@@ -391,9 +392,9 @@ def _lumped_balance(oracle_mod, b, src, dt, eps, states, ez):
     vs = np.array([oracle_mod.waveform(src.waveform, src.J0, src.t0, src.sigma,
                                        (m + 0.5) * dt) for m in n])
     dW = W[1:] - W[:-1]
-    loss = -dt * (vbar - vs) * vbar / src.R
+    loss = -dt * (vbar + vs) * vbar / src.R
     return dict(res=dW - loss, dW=dW, vbar=vbar, vs=vs,
-                diss=dt * vbar * vbar / src.R, gain=dt * vs * vbar / src.R)
+                diss=dt * vbar * vbar / src.R, gain=-dt * vs * vbar / src.R)
 
 
 def test_p11_resistor_energy_balance_no_drive(oracle_mod):
@@ -412,7 +413,7 @@ def test_p11_resistor_energy_balance_no_drive(oracle_mod):
 
 
 def test_p11_resistor_energy_balance_driven(oracle_mod):
-    """V_s != 0 from rest: source power dt V_s Vbar / R in, dt Vbar^2 / R lost."""
+    """V_s != 0 from rest: source power -dt V_s Vbar / R in, dt Vbar^2 / R lost."""
     b = _inhomogeneous_box(22)
     src = boardgen.Source(6, 5, 3, boardgen.GAUSS, 5.0, 40e-12, 10e-12, R=10.0)
     b.sources = [src]
@@ -424,16 +425,16 @@ def test_p11_resistor_energy_balance_driven(oracle_mod):
     assert np.abs(r["res"]).max() < 1e-11 * scale
     # the balance tells the oracle's update from plausible mistakes: a flipped
     # source sign, or a resistor taken explicitly at E^n instead of at Ebar
-    flipped = r["dW"] + dt * (r["vbar"] + r["vs"]) * r["vbar"] / src.R
+    flipped = r["dW"] + dt * (r["vbar"] - r["vs"]) * r["vbar"] / src.R
     assert np.abs(flipped).max() > 1e-3 * scale
     e_n = b.dz * ez[:len(r["dW"])]
-    explicit = r["dW"] + dt * (e_n - r["vs"]) * r["vbar"] / src.R
+    explicit = r["dW"] + dt * (e_n + r["vs"]) * r["vbar"] / src.R
     assert np.abs(explicit).max() > 1e3 * np.abs(r["res"]).max()
 
 
 def test_p11_resistor_tends_to_a_current_source(oracle_mod):
-    """R -> infinity with V_s = -J R dx dy held fixed: the lumped current density
-    (dz Ebar - V_s)/(R dx dy) tends to the plain current density J (Eq. 4 with
+    """R -> infinity with V_s = J R dx dy held fixed: the branch current density
+    (dz Ebar + V_s)/(R dx dy) tends to the plain current density J (Eq. 4 with
     -J in the D_z update); the difference shrinks like 1/R."""
     b = _inhomogeneous_box(23)
     b.probes = [(4, 6, 2), (8, 3, 5)]
@@ -444,7 +445,7 @@ def test_p11_resistor_tends_to_a_current_source(oracle_mod):
     ref = oracle_mod.run(ref_b, nsteps=200).probes
     errs = []
     for R in (1e6, 1e8):
-        b.sources = [boardgen.Source(6, 5, 3, boardgen.GAUSS, -J * R * b.dx * b.dy,
+        b.sources = [boardgen.Source(6, 5, 3, boardgen.GAUSS, J * R * b.dx * b.dy,
                                      40e-12, 10e-12, R=R)]
         got = oracle_mod.run(b, nsteps=200).probes
         errs.append(rel_max(got, ref))
