@@ -336,20 +336,32 @@ def served_requests(rate_per_s: float, seed: int = 1005, n_requests: int = 512,
 # small boards used by tests
 # ----------------------------------------------------------------------------
 
-def table1_board(steps: int = 30000, air_cells: int = 6, pml_cells: int = 8) -> Board:
+def table1_board(steps: int = 30000, air_cells: int = 6, pml_cells: int = 8,
+                 source: str = "current") -> Board:
     """The geometry of the paper's Table 1 run: a 40 x 30 x 0.8 mm board with
-    2 / 2 / 0.4 mm cells (20 x 15 x 2 board cells), dt = 1 ps, a current source at
-    one board corner and an Ez probe at the opposite corner, both on the first Ez
-    row above the ground plane.  The paper does not state eps_r, the air gap or
-    the PML depth; eps_r = 4.0 reproduces its predicted column."""
+    2 / 2 / 0.4 mm cells (20 x 15 x 2 board cells), dt = 1 ps, a source at one
+    board corner and an Ez probe at the opposite corner, both on the first Ez row
+    above the ground plane.  The paper does not state eps_r, the air gap or the
+    PML depth; eps_r = 4.0 reproduces its predicted column.
+
+    source "current": a DGAUSS current density of 1 A/mm^2 on the corner edge.
+    source "resistive": the paper's resistive voltage source, V0 = 5 V and
+    R = 10 ohm with the same DGAUSS shape, as a lumped element on that one edge
+    (the other Ez edge of the two-cell gap stays dielectric, so the element sees
+    the board through that edge's capacitance)."""
     b, lay = plane_stack("table1-40x30mm", (20, 15), 2, air_cells, pml_cells,
                          air_cells, air_cells, pml_cells, 2e-3, 2e-3, 0.4e-3, 4.0)
     b.dt = 1e-12
-    b.sources = [Source(lay["bi0"] + 1, lay["bj0"] + 1, lay["kg"], DGAUSS,
-                        1.0e6, 100e-12, 50e-12)]
-    b.probes = [(lay["bi1"] - 1, lay["bj1"] - 1, lay["kg"])]
+    si, sj, kg = lay["bi0"] + 1, lay["bj0"] + 1, lay["kg"]
+    if source == "current":
+        b.sources = [Source(si, sj, kg, DGAUSS, 1.0e6, 100e-12, 50e-12)]
+    elif source == "resistive":
+        b.sources = [Source(si, sj, kg, DGAUSS, 5.0, 100e-12, 50e-12, R=10.0)]
+    else:
+        raise ValueError(source)
+    b.probes = [(lay["bi1"] - 1, lay["bj1"] - 1, kg)]
     b.steps = steps
-    b.meta = dict(layout=lay)
+    b.meta = dict(layout=lay, source=source)
     b.check()
     return b
 

@@ -111,16 +111,40 @@ int fdtd_set_materials(fdtd_grid* g, const float* eps_r_cell, const uint8_t* pec
 /* Current source Jz (A/m^2) on the edge Ez(i, j, k+1/2), 1 <= i < nx,
  * 1 <= j < ny, 0 <= k < nz, not PEC (Results section: current source through the
  * D update).  waveform FDTD_WAVE_GAUSS or FDTD_WAVE_DGAUSS with width sigma > 0;
- * sampled at the half step (s+1/2) dt.  *id receives the source index.  ESTATE
- * after the first step. */
+ * sampled at the half step (s+1/2) dt.  *id receives the source index.  EINVAL
+ * if the edge holds a resistive voltage source; ESTATE after the first step. */
 int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0,
                     double t0, double sigma, int* id);
+
+/* Resistive voltage source on the edge Ez(i, j, k+1/2) (Results section, the
+ * Table 1 run: amplitude V0 in volts, source resistance R in ohms, semi-explicit
+ * update coefficients): an EMF V_s(t) = V0 * waveform that raises node k+1 over
+ * node k, in series with R.  Its branch current density (dz Ebar + V_s)/(R dx dy),
+ * with Ebar the mean of Ez at steps n and n+1, enters the Ez update like a
+ * current source and the update is solved for Ez^{n+1}; open-circuited the edge
+ * holds dz Ez = -V_s, and as R grows it tends to a current source of
+ * V0 / (R dx dy).  V_s is sampled at the half step (s+1/2) dt.  Index ranges,
+ * waveform and width as fdtd_add_source; *id receives the index in the same
+ * source list.  EINVAL if R is not finite and > 0, the edge is PEC, lies in a PML
+ * slab (i < npml[0], i >= nx - npml[1], likewise in y, k < npml[4] or
+ * k >= nz - npml[5]) or holds another source; ESTATE after the first step. */
+int fdtd_add_voltage_source(fdtd_grid* g, int i, int j, int k, int waveform, double V0,
+                            double t0, double sigma, double R, int* id);
 
 /* Probe of Ez(i, j, k+1/2), 0 <= i <= nx, 0 <= j <= ny, 0 <= k < nz (Results
  * section: ground-plane Ez recorded every step).  Sample s of the series is Ez at
  * time (s+1) dt, stored in FP32.  *id receives the probe index.  ESTATE after the
  * first step. */
 int fdtd_add_probe(fdtd_grid* g, int i, int j, int k, int* id);
+
+/* Plane-voltage probe: V = -sum_{k=k0}^{k1-1} Ez(i, j, k+1/2) dz, the potential of
+ * node (i, j, k1) over node (i, j, k0) along the column (Results section: the
+ * voltage between the power and ground planes), 0 <= i <= nx, 0 <= j <= ny,
+ * 0 <= k0 < k1 <= nz.  Built from k1-k0 Ez probes (added to the probe list with
+ * consecutive indices, so they count in fdtd_info.n_probes and carry DFT
+ * accumulators if frequencies are set).  *id receives the voltage-probe index.
+ * ESTATE after the first step. */
+int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id);
 
 /* Optional running DFT of every probe (FP64 accumulators, FP32 samples):
  * A[p][q] = sum_s e_p[s] exp(-i 2 pi f_q (s+1) dt) dt.  f_hz (host, nf values,
@@ -161,6 +185,11 @@ int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im);
 /* Copy the first n samples (n <= completed steps) of probe `id` into out (host,
  * n floats).  Synchronises. */
 int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n);
+
+/* Copy the first n samples (n <= completed steps) of voltage probe `id` into out
+ * (host, n doubles): sample s is V at time (s+1) dt in volts, the FP32 Ez samples
+ * summed in FP64 upwards in k.  Synchronises. */
+int fdtd_get_voltage(fdtd_grid* g, int id, double* out, int64_t n);
 
 /* Copy probe `id`'s DFT accumulators into re, im (host, nf doubles each).
  * Synchronises. */

@@ -31,6 +31,19 @@ __device__ __forceinline__ T ld_at_t(const void* base, uint32_t off)
     return *(const __attribute__((address_space(1))) T*)((const gbyte*)base + off);
 }
 
+// Ez^{n+1} on the edge of a resistive voltage source (Results section, the
+// Table 1 run): EMF V_s in series with R across the edge, outside every PML (so
+// the edge's kappa is 1 and its sigma 0, and D never enters).  In the scaled
+// units the branch current is beta (E^n + E^{n+1}) + js, beta = c0 dt eta0 dz /
+// (2 R dx dy) and js its Norton part, already subtracted in chz; with b =
+// beta / eps_r the update (E' - E) / inv_eps_r = chz - beta (E + E') solved for E'
+// is ((1 - b) E + inv_eps_r chz) / (1 + b).
+__device__ __forceinline__ float resistive_ez(float e_old, float chz, float inv_eps, float beta)
+{
+    const float b = inv_eps * beta;
+    return (fmaf(-b, e_old, e_old) + inv_eps * chz) / (1.0f + b);
+}
+
 // Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks
 // a contiguous run of the tile list (neighbouring tiles share halos in its L2).
 __device__ __forceinline__ int xcd_tile(int b, int nb)

@@ -65,6 +65,11 @@ int fail(int code, const char* fmt, ...)
 struct SourceH {
     int i, j, k, wave;
     double J0, t0, sigma;
+    double R;   // 0: current source (J0 in A/m^2); > 0: resistive voltage source (J0 = V0)
+};
+
+struct VoltageProbeH {
+    int first, count;   // Ez probes first .. first+count-1, one per z cell
 };
 
 struct ClassKey {
@@ -113,6 +118,7 @@ struct fdtd_grid {
     ClassEntry* ctab = nullptr;
     int32_t* src_node = nullptr;
     float* src_j = nullptr;
+    float* src_beta = nullptr;
     int32_t* prb_node = nullptr;
     float* prb_series = nullptr;
     double* dft_f = nullptr;
@@ -136,6 +142,7 @@ struct fdtd_grid {
     bool have_materials = false;
     std::vector<SourceH> sources;
     std::vector<std::array<int, 3>> probes;
+    std::vector<VoltageProbeH> vprobes;
     std::vector<double> freqs;
     int n_classes = 0;
     bool wide = false;
@@ -543,20 +550,29 @@ int finalize(fdtd_grid* g)
     HIP_OR_FAIL(hipMemcpyAsync(g->ctab, table.data(), table.size() * sizeof(ClassEntry),
                                hipMemcpyHostToDevice, st));
 
-    // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt
+    // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt.  A resistive
+    // voltage source (R > 0) carries its Norton current c0 dt eta0 V_s / (R dx dy)
+    // there and beta = c0 dt eta0 dz / (2 R dx dy), half its lumped conductance.
     const int ns = (int)g->sources.size(), np = (int)g->probes.size();
     const int64_t ms = d.max_steps;
     if (ns) {
-        std::vector<float> js((size_t)ns * ms);
-        for (int s = 0; s < ns; ++s)
+        std::vector<float> js((size_t)ns * ms), beta((size_t)ns, 0.f);
+        const double sc = kC0 * g->dt * kEta0;
+        for (int s = 0; s < ns; ++s) {
+            const SourceH& q = g->sources[s];
+            const double scale = q.R > 0.0 ? sc / (q.R * d.dx * d.dy) : sc;
+            if (q.R > 0.0) beta[s] = (float)(0.5 * sc * d.dz / (q.R * d.dx * d.dy));
             for (int64_t t = 0; t < ms; ++t)
-                js[(size_t)s * ms + t] =
-                    (float)(kC0 * g->dt * kEta0 * waveform(g->sources[s], (t + 0.5) * g->dt));
+                js[(size_t)s * ms + t] = (float)(scale * waveform(q, (t + 0.5) * g->dt));
+        }
         g->src_node = (int32_t*)dev_alloc(g, ns * 4);
         g->src_j = (float*)dev_alloc(g, js.size() * 4);
-        if (!g->src_node || !g->src_j) return fail(FDTD_ENOMEM, "source table allocation failed");
+        g->src_beta = (float*)dev_alloc(g, ns * 4);
+        if (!g->src_node || !g->src_j || !g->src_beta)
+            return fail(FDTD_ENOMEM, "source table allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->src_node, src_node.data(), ns * 4, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipMemcpyAsync(g->src_j, js.data(), js.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->src_beta, beta.data(), ns * 4, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
     }
     if (np) {
@@ -590,6 +606,7 @@ int finalize(fdtd_grid* g)
     b.ctab = g->ctab;
     b.src_node = g->src_node;
     b.src_j = g->src_j;
+    b.src_beta = g->src_beta;
     b.prb_node = g->prb_node;
     b.prb_series = g->prb_series;
     b.step = g->step_dev;
@@ -781,8 +798,11 @@ int fdtd_set_materials(fdtd_grid* g, const float* eps_r_cell, const uint8_t* pec
     return FDTD_OK;
 }
 
-int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0, double t0,
-                    double sigma, int* id)
+namespace {
+
+// shared checks of fdtd_add_source and fdtd_add_voltage_source
+int check_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0, double t0,
+                 double sigma)
 {
     if (int e = check_grid(g)) return e;
     if (g->finalized) return fail(FDTD_ESTATE, "sources are fixed after the first step");
@@ -794,7 +814,43 @@ int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0, 
         return fail(FDTD_EINVAL, "source parameters must be finite with sigma > 0");
     if (g->have_materials && (g->pec[node_index(g, i, j, k)] & 4))
         return fail(FDTD_EINVAL, "source at (%d,%d,%d) sits on a PEC edge", i, j, k);
-    g->sources.push_back(SourceH{i, j, k, waveform, J0, t0, sigma});
+    return FDTD_OK;
+}
+
+// a resistive source owns its edge: no second source of either kind may share it
+bool edge_has_resistor(const fdtd_grid* g, int i, int j, int k, bool any)
+{
+    for (const SourceH& s : g->sources)
+        if (s.i == i && s.j == j && s.k == k && (any || s.R > 0.0)) return true;
+    return false;
+}
+
+}  // namespace
+
+int fdtd_add_source(fdtd_grid* g, int i, int j, int k, int waveform, double J0, double t0,
+                    double sigma, int* id)
+{
+    if (int e = check_source(g, i, j, k, waveform, J0, t0, sigma)) return e;
+    if (edge_has_resistor(g, i, j, k, false))
+        return fail(FDTD_EINVAL, "edge (%d,%d,%d) already holds a resistive source", i, j, k);
+    g->sources.push_back(SourceH{i, j, k, waveform, J0, t0, sigma, 0.0});
+    if (id) *id = (int)g->sources.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_add_voltage_source(fdtd_grid* g, int i, int j, int k, int waveform, double V0,
+                            double t0, double sigma, double R, int* id)
+{
+    if (int e = check_source(g, i, j, k, waveform, V0, t0, sigma)) return e;
+    if (!(R > 0.0) || !std::isfinite(R))
+        return fail(FDTD_EINVAL, "source resistance must be finite and > 0");
+    const int* p = g->d.npml;
+    if (i < p[0] || i >= g->d.nx - p[1] || j < p[2] || j >= g->d.ny - p[3] || k < p[4] ||
+        k >= g->d.nz - p[5])
+        return fail(FDTD_EINVAL, "resistive source (%d,%d,%d) lies in a PML slab", i, j, k);
+    if (edge_has_resistor(g, i, j, k, true))
+        return fail(FDTD_EINVAL, "edge (%d,%d,%d) already holds a source", i, j, k);
+    g->sources.push_back(SourceH{i, j, k, waveform, V0, t0, sigma, R});
     if (id) *id = (int)g->sources.size() - 1;
     return FDTD_OK;
 }
@@ -807,6 +863,19 @@ int fdtd_add_probe(fdtd_grid* g, int i, int j, int k, int* id)
         return fail(FDTD_EINVAL, "probe (%d,%d,%d) is outside the grid", i, j, k);
     g->probes.push_back({i, j, k});
     if (id) *id = (int)g->probes.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "probes are fixed after the first step");
+    if (i < 0 || i > g->d.nx || j < 0 || j > g->d.ny || k0 < 0 || k1 <= k0 || k1 > g->d.nz)
+        return fail(FDTD_EINVAL, "voltage probe (%d,%d,%d..%d) is outside the grid", i, j, k0, k1);
+    const int first = (int)g->probes.size();
+    for (int k = k0; k < k1; ++k) g->probes.push_back({i, j, k});
+    g->vprobes.push_back(VoltageProbeH{first, k1 - k0});
+    if (id) *id = (int)g->vprobes.size() - 1;
     return FDTD_OK;
 }
 
@@ -1148,7 +1217,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
     t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +
          r((int64_t)kNumCoef * 2 * (d->nz + 1) * 4);                            // coefficients
-    t += r(4 * (int64_t)n_sources) + r(4 * (int64_t)n_sources * d->max_steps);   // sources
+    t += 2 * r(4 * (int64_t)n_sources) + r(4 * (int64_t)n_sources * d->max_steps);   // sources
     t += r(4 * (int64_t)n_probes) + r(4 * (int64_t)n_probes * d->max_steps);     // probes
     t += r(8 * (int64_t)n_freqs) + 2 * r(8 * (int64_t)n_probes * n_freqs);       // DFT
     const int64_t max_tiles = ((d->nx + 64) / 64) * ((d->ny + 3) / 3);         // 64 x 4, the most tiles
@@ -1173,6 +1242,28 @@ int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n)
     if (n > 0)
         HIP_OR_FAIL(copy_sync(g, out, g->prb_series + (size_t)id * g->d.max_steps, (size_t)n * 4,
                               hipMemcpyDeviceToHost));
+    return check_bad(g);
+}
+
+int fdtd_get_voltage(fdtd_grid* g, int id, double* out, int64_t n)
+{
+    if (int e = check_grid(g)) return e;
+    if (id < 0 || id >= (int)g->vprobes.size()) return fail(FDTD_EINVAL, "no voltage probe %d", id);
+    if (n < 0 || n > g->step || (!out && n > 0)) return fail(FDTD_EINVAL, "bad sample count %lld", (long long)n);
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    if (n == 0) return check_bad(g);
+    const VoltageProbeH& v = g->vprobes[id];
+    std::vector<float> ez((size_t)v.count * n);
+    for (int q = 0; q < v.count; ++q)
+        HIP_OR_FAIL(copy_sync(g, ez.data() + (size_t)q * n,
+                              g->prb_series + (size_t)(v.first + q) * g->d.max_steps,
+                              (size_t)n * 4, hipMemcpyDeviceToHost));
+    // V = -sum_k Ez(k+1/2) dz, summed upwards in z
+    for (int64_t s = 0; s < n; ++s) {
+        double acc = 0.0;
+        for (int q = 0; q < v.count; ++q) acc += (double)ez[(size_t)q * n + s];
+        out[s] = -g->d.dz * acc;
+    }
     return check_bad(g);
 }
 

@@ -54,6 +54,7 @@ struct BoardDev {
     const float* coef[3];        // per axis: [kind][node/half][n+1]
     const int32_t* src_node;     // node index of each source's Ez edge
     const float* src_j;          // [nsrc][max_steps] Js samples
+    const float* src_beta;       // [nsrc] 0, or a resistive source's beta (lumped conductance)
     const int32_t* prb_node;
     float* prb_series;           // [nprb][max_steps]
     int64_t* step;               // [0] completed steps, [1] buffer (0/1) holding the fields

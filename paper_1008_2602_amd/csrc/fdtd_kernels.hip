@@ -237,17 +237,27 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                 const float ddy = fmaf(z_cam1_n, o.dy, z_rp_n * chy);
                 float eyn = fmaf(x_ca_n, eyo, x_rp_n * (ce.inv_y * fmaf(y_ph_h, ddy, y_q_h * o.dy)));
                 // Ez(i, j, k+1/2): Dz uses x at i; Ez uses y at j, z at k+1/2
-                float js = 0.0f;
+                const float chz = (hyn - sHy[ty][c - 1]) * crdx - (hxn - sHx[ty - 1][c]) * crdy;
+                float ddz = fmaf(x_cam1_n, o.dz, x_rp_n * chz);
+                float ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * o.dz)));
                 if (ce.flags & kSrcEz) {
+                    // source edge: the sources' Js enters the D_z curl, and a
+                    // resistive source's update is solved for Ez^{n+1}
                     const __attribute__((address_space(1))) int32_t* sn =
                         (const __attribute__((address_space(1))) int32_t*)B.src_node;
                     cgfloat* sj = (cgfloat*)B.src_j;
+                    cgfloat* sb = (cgfloat*)B.src_beta;
+                    float js = 0.0f, bs = 0.0f;
                     for (int s = 0; s < B.nsrc; ++s)
-                        if (sn[s] == node) js += sj[s * ms + step];
+                        if (sn[s] == node) {
+                            js += sj[s * ms + step];
+                            bs += sb[s];
+                        }
+                    const float chs = chz - js;
+                    ddz = fmaf(x_cam1_n, o.dz, x_rp_n * chs);
+                    ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * o.dz)));
+                    if (bs != 0.0f) ezn = resistive_ez(ezo, chs, ce.inv_z, bs);
                 }
-                const float chz = ((hyn - sHy[ty][c - 1]) * crdx - (hxn - sHx[ty - 1][c]) * crdy) - js;
-                const float ddz = fmaf(x_cam1_n, o.dz, x_rp_n * chz);
-                float ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * o.dz)));
                 exn = (ce.flags & kUpdEx) ? exn : 0.0f;
                 eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
                 ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;

@@ -234,14 +234,25 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         o.dy = ld_at(gD, (oke && (py || pz) ? n : guardb) + cs);
         o.dz = ld_at(gD, (oke && (pz || px) ? n : guardb) + cs2);
     };
-    auto source_sum = [&](int node, int64_t s) {
-        float js = 0.0f;
+    // Ez of a source edge: the sources' Js of step s enters the D_z curl, and a
+    // resistive source's update is solved for Ez^{n+1}.  Recomputes ddz and ezn
+    // from the plain curl, so edges without a source never carry the extra terms.
+    auto source_ez = [&](int node, int64_t s, float chz, float e_old, float d_old,
+                         float inv_z, const AxisCoef& Zc, float& ddz, float& ezn) {
         const __attribute__((address_space(1))) int32_t* sn =
             (const __attribute__((address_space(1))) int32_t*)B.src_node;
         cgfloat* sj = (cgfloat*)B.src_j;
+        cgfloat* sb = (cgfloat*)B.src_beta;
+        float js = 0.0f, bs = 0.0f;
         for (int q = 0; q < B.nsrc; ++q)
-            if (sn[q] == node) js += sj[q * ms + s];
-        return js;
+            if (sn[q] == node) {
+                js += sj[q * ms + s];
+                bs += sb[q];
+            }
+        const float chs = chz - js;
+        ddz = fmaf(X.cam1_n, d_old, X.rp_n * chs);
+        ezn = fmaf(Y.ca_n, e_old, Y.rp_n * (inv_z * fmaf(Zc.ph_h, ddz, Zc.q_h * d_old)));
+        if (bs != 0.0f) ezn = resistive_ez(e_old, chs, inv_z, bs);
     };
     auto record_probe = [&](int node, int64_t s, float ez) {
         const __attribute__((address_space(1))) int32_t* pn =
@@ -319,11 +330,10 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
                 const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
                 const float ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
                 float eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
-                float js = 0.0f;
-                if (ce.flags & kSrcEz) js = source_sum(node, step);
-                const float chz = ((h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy) - js;
-                const float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
+                const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
+                float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
                 float ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
+                if (ce.flags & kSrcEz) source_ez(node, step, chz, ezo, o.dz, ce.inv_z, Zk, ddz, ezn);
                 e1x = (ce.flags & kUpdEx) ? exn : 0.0f;
                 e1y = (ce.flags & kUpdEy) ? eyn : 0.0f;
                 e1z = (ce.flags & kUpdEz) ? ezn : 0.0f;
@@ -383,11 +393,10 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
             const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
             const float ddy = fmaf(Zm.cam1_n, p_d1y, Zm.rp_n * chy);
             float eyn = fmaf(X.ca_n, p_e1y, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * p_d1y)));
-            float js = 0.0f;
-            if (ce.flags & kSrcEz) js = source_sum(node, step + 1);
-            const float chz = ((h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy) - js;
-            const float ddz = fmaf(X.cam1_n, p_d1z, X.rp_n * chz);
+            const float chz = (h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy;
+            float ddz = fmaf(X.cam1_n, p_d1z, X.rp_n * chz);
             float ezn = fmaf(Y.ca_n, p_e1z, Y.rp_n * (ce.inv_z * fmaf(Zm.ph_h, ddz, Zm.q_h * p_d1z)));
+            if (ce.flags & kSrcEz) source_ez(node, step + 1, chz, p_e1z, p_d1z, ce.inv_z, Zm, ddz, ezn);
             exn = (ce.flags & kUpdEx) ? exn : 0.0f;
             eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
             ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;

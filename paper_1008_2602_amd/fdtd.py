@@ -77,7 +77,13 @@ _sigs = {
     "fdtd_set_materials": ([_P, _P, _P], C.c_int),
     "fdtd_add_source": ([_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                          C.c_double, C.POINTER(C.c_int)], C.c_int),
+    "fdtd_add_voltage_source": ([_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)],
+                                C.c_int),
     "fdtd_add_probe": ([_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "fdtd_add_voltage_probe": ([_P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)],
+                               C.c_int),
+    "fdtd_get_voltage": ([_P, C.c_int, _P, C.c_int64], C.c_int),
     "fdtd_set_dft_freqs": ([_P, _P, C.c_int], C.c_int),
     "fdtd_step_n": ([_P, C.c_int64], C.c_int),
     "fdtd_step_many": ([_P, C.c_int, _P], C.c_int),
@@ -202,9 +208,22 @@ def fdtd_add_source(g, i, j, k, waveform, J0, t0, sigma) -> int:
     return out.value
 
 
+def fdtd_add_voltage_source(g, i, j, k, waveform, V0, t0, sigma, R) -> int:
+    out = C.c_int()
+    _check(_lib.fdtd_add_voltage_source(g, int(i), int(j), int(k), int(waveform), float(V0),
+                                        float(t0), float(sigma), float(R), C.byref(out)))
+    return out.value
+
+
 def fdtd_add_probe(g, i, j, k) -> int:
     out = C.c_int()
     _check(_lib.fdtd_add_probe(g, int(i), int(j), int(k), C.byref(out)))
+    return out.value
+
+
+def fdtd_add_voltage_probe(g, i, j, k0, k1) -> int:
+    out = C.c_int()
+    _check(_lib.fdtd_add_voltage_probe(g, int(i), int(j), int(k0), int(k1), C.byref(out)))
     return out.value
 
 
@@ -233,6 +252,12 @@ def fdtd_probe_fft(g, pid: int, n_fft: int) -> np.ndarray:
 def fdtd_get_probe(g, pid: int, n: int) -> np.ndarray:
     out = np.zeros(int(n), np.float32)
     _check(_lib.fdtd_get_probe(g, int(pid), _ptr(out) if n else None, int(n)))
+    return out
+
+
+def fdtd_get_voltage(g, vid: int, n: int) -> np.ndarray:
+    out = np.zeros(int(n), np.float64)
+    _check(_lib.fdtd_get_voltage(g, int(vid), _ptr(out) if n else None, int(n)))
     return out
 
 
@@ -348,7 +373,10 @@ def grid_from_board(board, max_steps: Optional[int] = None, hip_stream=None,
     try:
         fdtd_set_materials(g, b.eps_r_cell, b.pec_edge_mask)
         for s in b.sources:
-            fdtd_add_source(g, s.i, s.j, s.k, s.waveform, s.J0, s.t0, s.sigma)
+            if getattr(s, "R", 0.0) > 0.0:
+                fdtd_add_voltage_source(g, s.i, s.j, s.k, s.waveform, s.J0, s.t0, s.sigma, s.R)
+            else:
+                fdtd_add_source(g, s.i, s.j, s.k, s.waveform, s.J0, s.t0, s.sigma)
         ids = [fdtd_add_probe(g, i, j, k) for (i, j, k) in b.probes]
         if b.dft_freqs is not None and len(b.dft_freqs):
             fdtd_set_dft_freqs(g, b.dft_freqs)
