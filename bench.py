@@ -16,10 +16,13 @@ Beside it, the same line carries
     into 85 % of free HBM, advanced in 500-step chunks, each finished solve
     read back with its probe spectra; p50/p99 latency and throughput.  The step
     count per solve is reduced (default 1000 instead of 8000) so the run stays
-    short; the number is stated in the output.
+    short; the number is stated in the output;
+  * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
+    one solve, and a 64-board sweep of its source resistance, with the oracle's
+    time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve]
+                  [--only single|batch|serve|table1]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -149,6 +152,94 @@ def run_batch(F, torch, K, W):
     }, cells / len(boards)
 
 
+def run_table1(F, torch, n_sweep=64, kernel_steps=200):
+    """The paper's Table 1 run (40 x 30 x 0.8 mm board, 5 V / 10 ohm DGAUSS
+    resistive corner source, opposite-corner ground-plane Ez probe and the plane
+    voltage there, 30000 steps of 1 ps) as one solve, with its probe spectrum;
+    then the source-resistance sweep the paper proposes (n_sweep copies, R from
+    1 ohm to 1 kohm) advanced together by fdtd_step_many.  The board is small
+    (62k cells), so one solve is bound by launch latency, not HBM; the kernel's
+    own duration is timed apart over kernel_steps further steps."""
+    import numpy as np
+    import boardgen
+    from paper_1008_2602_amd import tune
+    b = boardgen.table1_board(steps=30000, source="resistive")
+    N = b.steps
+    lay = b.meta["layout"]
+    pi, pj, _ = b.probes[0]
+    tile = tune.tune_board(b)
+    g, ids = F.grid_from_board(b, max_steps=N + kernel_steps, tile=tile)
+    vid = F.fdtd_add_voltage_probe(g, pi, pj, lay["kg"], lay["kt"])
+    F.fdtd_step_n(g, 0)                  # set-up (tables, work lists) outside the timing
+    F.fdtd_synchronize(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_n(g, N)
+    n_fft = 1
+    while n_fft < N:
+        n_fft *= 2
+    spec = F.fdtd_probe_fft(g, ids[0], n_fft)
+    volt = F.fdtd_get_voltage(g, vid, N)
+    wall = time.perf_counter() - t0
+    assert np.all(np.isfinite(spec)) and np.all(np.isfinite(volt))
+    F.fdtd_set_timing(g, True)
+    F.fdtd_step_n(g, kernel_steps)
+    kern_ms, launches = F.fdtd_get_timing(g)
+    info = F.fdtd_get_info(g)
+    F.fdtd_destroy_grid(g)
+    per_launch_s = kern_ms / 1e3 / launches
+    launch_bytes = info.step_bytes * kernel_steps / launches
+
+    boards = []
+    for r in np.geomspace(1.0, 1000.0, n_sweep):
+        bb = boardgen.table1_board(steps=N, source="resistive")
+        bb.sources[0].R = float(r)
+        boards.append(bb)
+    stile = tune.tune_batch(boards)
+    gs = [F.grid_from_board(bb, max_steps=N)[0] for bb in boards]
+    F.fdtd_set_tile(gs[0], *stile)
+    for h in gs:
+        F.fdtd_step_n(h, 0)
+    F.fdtd_synchronize(gs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_many(gs, [N] * len(gs))
+    F.fdtd_synchronize(gs[0])
+    sweep_wall = time.perf_counter() - t0
+    for h in gs:
+        F.fdtd_destroy_grid(h)
+    return {
+        "workload": f"Table 1 run: {b.nx}x{b.ny}x{b.nz} cells (40x30x0.8 mm board, 2/2/0.4 mm "
+                    f"cells, eps_r 4.0, 6 air + 8 PML cells), 5 V / 10 ohm DGAUSS resistive "
+                    f"corner source, {N} steps of 1 ps, probe FFT ({n_fft} points) and plane "
+                    f"voltage read back",
+        "tile": "x".join(str(v) for v in tile),
+        "wall_s": round(wall, 4),
+        "ms_per_step": round(wall / N * 1e3, 5),
+        "gcell_updates_per_s": round(b.cells * N / wall / 1e9, 3),
+        "kernel_avg_launch_us": round(per_launch_s * 1e6, 2),
+        "kernel_hbm_frac_algorithmic": round(launch_bytes / per_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+        "r_sweep": {
+            "boards": len(boards),
+            "R_ohm": [1.0, 1000.0],
+            "tile": "x".join(str(v) for v in stile),
+            "wall_s": round(sweep_wall, 3),
+            "gcell_updates_per_s": round(b.cells * N * len(boards) / sweep_wall / 1e9, 3),
+        },
+    }, b
+
+
+def table1_cpu(board):
+    """The oracle's whole Table 1 run (it is small enough to run in full)."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.run(board, threads=None)
+    dt = time.perf_counter() - t0
+    return {"value": round(board.cells * board.steps / dt / 1e9, 4),
+            "unit": "Gcell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the whole {board.steps}-step run ({dt:.1f} s; FP64)"}
+
+
 def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
     import numpy as np
     import boardgen
@@ -197,7 +288,7 @@ def main():
     ap.add_argument("--tile", default="",
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
-    ap.add_argument("--only", choices=["single", "batch", "serve"], default=None)
+    ap.add_argument("--only", choices=["single", "batch", "serve", "table1"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -276,6 +367,10 @@ def main():
         if args.only in (None, "serve"):
             out["served"] = run_serve(F, torch, batch["value"], mean_cells,
                                       args.serve_requests, args.serve_steps)
+    if args.only in (None, "table1"):
+        out["table1"], t1_board = run_table1(F, torch)
+        if not args.no_cpu_baseline:
+            out["table1"]["cpu_baseline"] = table1_cpu(t1_board)
     if args.only in (None, "single") and not args.no_cpu_baseline:
         import boardgen
         out["cpu_baseline"] = cpu_baseline(boardgen.large_board())
