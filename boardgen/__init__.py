@@ -77,6 +77,8 @@ class Board:
     probes: List[Tuple[int, int, int]] = field(default_factory=list)
     steps: int = 1000
     dft_freqs: Optional[np.ndarray] = None
+    # (k, frequencies in Hz): running DFT of Ez(i, j, k+1/2) over the whole plane k
+    plane_dft: Optional[Tuple[int, np.ndarray]] = None
     meta: dict = field(default_factory=dict)
 
     @property

@@ -54,7 +54,8 @@ class _Problem(C.Structure):
                 ("src_J0", C.c_void_p), ("src_t0", C.c_void_p), ("src_sigma", C.c_void_p),
                 ("src_R", C.c_void_p),
                 ("nprobe", C.c_int32), ("probe_ijk", C.c_void_p),
-                ("nfreq", C.c_int32), ("freqs", C.c_void_p)]
+                ("nfreq", C.c_int32), ("freqs", C.c_void_p),
+                ("plane_k", C.c_int32), ("nplane_freq", C.c_int32), ("plane_freqs", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -70,7 +71,7 @@ def _load():
         build(force=False)
         lib = C.CDLL(_LIB)
         lib.or_run.argtypes = [C.POINTER(_Problem), C.POINTER(_State), C.c_int64,
-                               C.c_void_p, C.c_void_p, C.c_void_p]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.or_run.restype = C.c_int
         lib.or_time_step.argtypes = [C.POINTER(_Problem)]
         lib.or_time_step.restype = C.c_double
@@ -125,6 +126,11 @@ class Problem:
         self.probe_ijk = np.array(b.probes, np.int32).reshape(len(b.probes), 3)
         self.freqs = (np.zeros(0) if b.dft_freqs is None
                       else np.ascontiguousarray(b.dft_freqs, dtype=np.float64))
+        pd = getattr(b, "plane_dft", None)
+        self.plane_k = -1 if pd is None else int(pd[0])
+        self.plane_freqs = (np.zeros(0) if pd is None
+                            else np.ascontiguousarray(pd[1], dtype=np.float64))
+        assert self.plane_k < b.nz
         p = _Problem()
         p.nx, p.ny, p.nz = b.nx, b.ny, b.nz
         p.dx, p.dy, p.dz = b.dx, b.dy, b.dz
@@ -144,6 +150,9 @@ class Problem:
         p.probe_ijk = self.probe_ijk.ctypes.data
         p.nfreq = len(self.freqs)
         p.freqs = self.freqs.ctypes.data
+        p.plane_k = self.plane_k
+        p.nplane_freq = len(self.plane_freqs)
+        p.plane_freqs = self.plane_freqs.ctypes.data
         self.c = p
 
     @property
@@ -164,11 +173,14 @@ class Result:
     probes: np.ndarray           # (nprobe, nsteps) float64
     dft: Optional[np.ndarray]    # (nprobe, nfreq) complex128, accumulated over the run
     state: Dict[str, np.ndarray]
+    plane_dft: Optional[np.ndarray] = None   # (nfreq, ny+1, nx+1) complex128, accumulated
 
 
 def run(board, nsteps: Optional[int] = None, state: Optional[Dict[str, np.ndarray]] = None,
-        threads: Optional[int] = None, dft: Optional[np.ndarray] = None) -> Result:
-    """Advance ``state`` (zero fields if None) by ``nsteps`` (default board.steps)."""
+        threads: Optional[int] = None, dft: Optional[np.ndarray] = None,
+        plane_dft: Optional[np.ndarray] = None) -> Result:
+    """Advance ``state`` (zero fields if None) by ``nsteps`` (default board.steps).
+    ``dft`` and ``plane_dft`` carry accumulators over from an earlier call."""
     lib = _load()
     if threads is not None:
         lib.or_set_num_threads(int(threads))
@@ -187,12 +199,19 @@ def run(board, nsteps: Optional[int] = None, state: Optional[Dict[str, np.ndarra
         dft = np.zeros((P, F), np.complex128)
     re = np.ascontiguousarray(dft.real.copy())
     im = np.ascontiguousarray(dft.imag.copy())
+    FP = len(prob.plane_freqs) if prob.plane_k >= 0 else 0
+    if plane_dft is None:
+        plane_dft = np.zeros((FP, board.ny + 1, board.nx + 1), np.complex128)
+    assert plane_dft.shape == (FP, board.ny + 1, board.nx + 1)
+    pre = np.ascontiguousarray(plane_dft.real.copy())
+    pim = np.ascontiguousarray(plane_dft.imag.copy())
     if n > 0:
         lib.or_run(C.byref(prob.c), C.byref(cs), n, series.ctypes.data,
-                   re.ctypes.data if F else None, im.ctypes.data if F else None)
+                   re.ctypes.data if F else None, im.ctypes.data if F else None,
+                   pre.ctypes.data if FP else None, pim.ctypes.data if FP else None)
     st["step"] = int(cs.step)
     return Result(dt=prob.dt, probes=series[:, :n], dft=(re + 1j * im) if F else None,
-                  state=st)
+                  state=st, plane_dft=(pre + 1j * pim) if FP else None)
 
 
 def sigma_kappa(board, axis: int, pos: float):

@@ -75,6 +75,9 @@ typedef struct {
     const int32_t* probe_ijk;  /* 3*nprobe, Ez(i,j,k+1/2) */
     int32_t nfreq;
     const double* freqs;       /* Hz */
+    int32_t plane_k;           /* >= 0: running DFT of Ez(i, j, plane_k+1/2) over the plane */
+    int32_t nplane_freq;
+    const double* plane_freqs; /* Hz */
 } or_problem;
 
 typedef struct {
@@ -170,10 +173,14 @@ double or_waveform(int wave, double J0, double t0, double sigma, double t)
  * nsteps samples (row p, column s = Ez at the probe at time (step+s+1) dt);
  * dft_re/dft_im (nprobe x nfreq) are accumulated, not cleared:
  *   A_pq += e_p[s] exp(-i 2 pi f_q (s+1) dt) dt.
+ * plane_re/plane_im (nplane_freq x (ny+1) x (nx+1)) accumulate the same sum for
+ * every node (i, j) of Ez on plane plane_k (the field at the ground plane over
+ * the whole board, Results section, Figs. 3-5).
  * Any output pointer may be NULL.  Returns 0.
  */
 int or_run(const or_problem* p, or_state* st, int64_t nsteps,
-           double* probe_series, double* dft_re, double* dft_im)
+           double* probe_series, double* dft_re, double* dft_im,
+           double* plane_re, double* plane_im)
 {
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const double dt = or_time_step(p);
@@ -330,6 +337,21 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     dft_re[(size_t)q * p->nfreq + f] += e * cos(ph) * dt;
                     dft_im[(size_t)q * p->nfreq + f] -= e * sin(ph) * dt;
                 }
+        }
+        if (p->plane_k >= 0 && plane_re && plane_im) {
+            const size_t np = (size_t)(nx + 1) * (size_t)(ny + 1);
+            for (int f = 0; f < p->nplane_freq; ++f) {
+                const double ph = 2.0 * OR_PI * p->plane_freqs[f] * (double)(n + 1) * dt;
+                const double cph = cos(ph), sph = sin(ph);
+                double* re = plane_re + (size_t)f * np;
+                double* im = plane_im + (size_t)f * np;
+                for (int j = 0; j <= ny; ++j)
+                    for (int i = 0; i <= nx; ++i) {
+                        const double e = ez[IX(i, j, p->plane_k)];
+                        re[(size_t)j * (nx + 1) + i] += e * cph * dt;
+                        im[(size_t)j * (nx + 1) + i] -= e * sph * dt;
+                    }
+            }
         }
         st->step = n + 1;
     }

@@ -7,6 +7,7 @@
 * P8  linearity, reciprocity and mirror symmetry
 * P10 the probe FFT against a direct DFT
 * P11 resistive voltage source: discrete energy balance, R -> infinity limits
+* P12 plane-wide DFT: closed form on a cavity eigenmode, agreement with the probe DFT
 * Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
 """
 import numpy as np
@@ -462,3 +463,71 @@ def test_p11_resistor_zero_drive_infinite_r_is_no_source(oracle_mod):
     oracle_mod.run(b, nsteps=50, state=st1)
     for n in ("ex", "ey", "ez", "hx", "hy", "hz"):
         assert rel_max(st1[n], st0[n]) < 1e-14, n
+
+
+# ---------------------------------------------------------------------------
+# P12  running DFT of Ez over a whole plane (the ground-plane field of the
+# Results section, Figs. 3-5, taken in the frequency domain)
+# ---------------------------------------------------------------------------
+
+def test_p12_plane_dft_of_a_cavity_eigenmode_closed_form(oracle_mod):
+    """A TM_pq0 eigenmode of the Yee grid in a PEC box, started consistently
+    (E^0 = A S, H^{-1/2} = (dt / 2 mu0) curl E^0), evolves as E^n = A cos(n theta) S
+    with sin(theta/2) = c dt sqrt(lambda)/2, lambda the discrete Laplacian
+    eigenvalue.  Its plane DFT is then the closed form
+    A S(i, j) sum_s cos((s+1) theta) exp(-i 2 pi f (s+1) dt) dt on every node."""
+    nx, ny, nz, er = 12, 9, 3, 2.2
+    dx, dy, dz = 1e-3, 1.3e-3, 0.5e-3
+    b = boardgen.cavity_box(nx, ny, nz, dx, dy, dz, er, steps=400)
+    dt = oracle_mod.time_step(b)
+    p, q, A = 2, 1, 3.0
+    ii = np.arange(nx + 1)
+    jj = np.arange(ny + 1)
+    S = np.outer(np.sin(q * np.pi * jj / ny), np.sin(p * np.pi * ii / nx))   # [j, i]
+    st = oracle_mod.new_state(b)
+    st["ez"][:nz] = A * S[None]
+    # H^{-1/2} = (dt / (2 mu0)) curl E^0: Hx(i, j+1/2) from dEz/dy, Hy(i+1/2, j) from -dEz/dx
+    ez0 = A * S
+    st["hx"][:nz, :ny, :] = dt / (2 * MU0) * ((ez0[1:, :] - ez0[:-1, :]) / dy)[None]
+    st["hy"][:nz, :, :nx] = dt / (2 * MU0) * (-(ez0[:, 1:] - ez0[:, :-1]) / dx)[None]
+    c = C0 / np.sqrt(float(np.float32(er)))     # the board stores eps_r in FP32
+    lam = 4 * np.sin(p * np.pi / (2 * nx)) ** 2 / dx ** 2 + 4 * np.sin(q * np.pi / (2 * ny)) ** 2 / dy ** 2
+    theta = 2 * np.arcsin(c * dt * np.sqrt(lam) / 2)
+    f_mode = theta / (2 * np.pi * dt)
+    freqs = np.array([0.0, 0.5 * f_mode, f_mode, 1.3 * f_mode])
+    b.plane_dft = (1, freqs)
+    r = oracle_mod.run(b, state=st)
+    n = np.arange(1, b.steps + 1)
+    for fi, f in enumerate(freqs):
+        amp = np.sum(np.cos(n * theta) * np.exp(-2j * np.pi * f * n * dt)) * dt
+        ref = A * amp * S
+        got = r.plane_dft[fi]
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(A * dt * b.steps), (fi, np.abs(got - ref).max())
+    # the pin sees a transposed plane, a dropped dt or a flipped imaginary sign
+    good = r.plane_dft[3]
+    ref2 = A * np.sum(np.cos(n * theta) * np.exp(-2j * np.pi * freqs[3] * n * dt)) * dt * S
+    assert np.abs(np.conj(good) - ref2).max() > 1e-3 * np.abs(ref2).max()
+    assert np.abs(good / dt - ref2).max() > 1e-3 * np.abs(ref2).max()
+    assert np.abs(good.T[:ny + 1, :ny + 1] - ref2[:, :ny + 1]).max() > 1e-3 * np.abs(ref2).max()
+
+
+def test_p12_plane_dft_equals_probe_dft_on_its_nodes(oracle_mod):
+    """The plane accumulators and the probe accumulators are separate code paths
+    with the same definition: on a board with sources and PML they agree exactly
+    at every probed node of the plane, and the plane is zero on PEC edges."""
+    b = boardgen.random_tiny(31, nx=13, ny=11, nz=9, npml=2, steps=70)
+    k = 3
+    rng = np.random.default_rng(5)
+    b.probes = [(int(rng.integers(0, b.nx + 1)), int(rng.integers(0, b.ny + 1)), k)
+                for _ in range(12)]
+    b.plane_dft = (k, b.dft_freqs)
+    r = oracle_mod.run(b)
+    for q, (i, j, _k) in enumerate(b.probes):
+        assert np.array_equal(r.plane_dft[:, j, i], r.dft[q]), (i, j)
+    assert np.abs(r.plane_dft).max() > 0
+    pec = (b.pec_edge_mask[k] & 4) != 0
+    assert np.all(r.plane_dft[:, pec] == 0)
+    # carried accumulators: two halves equal one run
+    h1 = oracle_mod.run(b, nsteps=30)
+    h2 = oracle_mod.run(b, nsteps=40, state=h1.state, plane_dft=h1.plane_dft)
+    assert np.allclose(h2.plane_dft, r.plane_dft, rtol=0, atol=1e-12 * np.abs(r.plane_dft).max())
