@@ -87,6 +87,8 @@ typedef struct {
     int32_t n_classes;           /* distinct per-node material classes after finalisation */
     int32_t tile_x, tile_y;      /* tile shape the field kernel runs with */
     int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
+    int32_t plane_k;             /* plane of the plane DFT, -1 if none */
+    int32_t plane_nf;            /* its number of frequencies */
 } fdtd_info;
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
@@ -151,6 +153,19 @@ int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id);
  * each >= 0 and finite), 1 <= nf <= 4096.  ESTATE after the first step. */
 int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
 
+/* Plane DFT: the running DFT of Ez(i, j, k+1/2) over every node of the node plane
+ * k (0 <= k < nz; the ground-plane field of the Results section, Figs. 3-5, in the
+ * frequency domain): A_f(i, j) = sum_s Ez_s(i, j) exp(-i 2 pi f (s+1) dt) dt, FP32
+ * samples and FP64 accumulators, the probe DFT's definition on every node.  f_hz
+ * (host, nf values, each >= 0 and finite), 1 <= nf <= 256.  The field kernels
+ * store the plane's Ez of every step into a 32-step ring; a separate kernel folds
+ * it into the accumulators every 32 steps and at the end of every stepping call,
+ * so results do not depend on how steps are split into calls.  Device memory:
+ * 128 + 16 nf bytes per plane node (rows padded to 32 nodes).  One plane per
+ * handle; EINVAL if the padded plane exceeds 2^25 nodes; ESTATE after the first
+ * step. */
+int fdtd_set_plane_dft(fdtd_grid* g, int k, const double* f_hz, int nf);
+
 /* Enqueue n >= 0 leapfrog steps (per step: B then H at n+1/2 from E at n, D then E
  * at n+1 with the source, PEC planes and probes; Model section, Eqs. 3-4).  The
  * first call finalises the set-up.  Whole chunks of 32 steps replay one captured
@@ -195,6 +210,11 @@ int fdtd_get_voltage(fdtd_grid* g, int id, double* out, int64_t n);
  * Synchronises. */
 int fdtd_get_dft(fdtd_grid* g, int id, double* re, double* im);
 
+/* Copy the plane-DFT accumulators into re, im (host, nf*(ny+1)*(nx+1) doubles
+ * each, frequency-major then y then x).  ESTATE if no plane DFT was set.
+ * Synchronises. */
+int fdtd_get_plane_dft(fdtd_grid* g, double* re, double* im);
+
 /* Field access in SI units (host buffers of (nx+1)(ny+1)(nz+1) floats).  D and B
  * are the UPML auxiliaries of Eq. 4 (zero where the layout keeps none: the
  * library stores D/B only where a PML loss acts on them).  set is allowed before
@@ -203,8 +223,13 @@ int fdtd_get_dft(fdtd_grid* g, int id, double* re, double* im);
 int fdtd_get_field(fdtd_grid* g, int comp, float* out);
 int fdtd_set_field(fdtd_grid* g, int comp, const float* in);
 
+/* Snapshot of one component on node plane k (0 <= k <= nz) in SI units: out (host,
+ * (ny+1)(nx+1) floats, x fastest), e.g. Ez on the ground plane at the current
+ * step for the animations of the Results section (Figs. 3, 4).  Synchronises. */
+int fdtd_get_plane(fdtd_grid* g, int comp, int k, float* out);
+
 /* Checkpoint: the whole stepping state (fields, auxiliaries, step counter, probe
- * samples, DFT accumulators) as an opaque byte image of fdtd_state_bytes(g)
+ * samples, DFT and plane-DFT accumulators) as an opaque byte image of fdtd_state_bytes(g)
  * bytes.  Loading an image saved from a handle with identical set-up and
  * continuing gives bitwise the same results as never stopping.  Synchronises. */
 int64_t fdtd_state_bytes(fdtd_grid* g);

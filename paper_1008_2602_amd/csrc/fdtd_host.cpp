@@ -26,10 +26,13 @@ int field_step_occupancy(int tile_x, int tile_y, bool wide);
 int num_shapes2();
 void shape2_at(int s, int* tx, int* ty);
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
-                              int rel, int flip, bool wide, hipStream_t st);
+                              int rel, int flip, bool wide, bool plane, hipStream_t st);
 int field_step2_occupancy(int tile_y, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
+hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
+                             double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
+                             double* re, double* im, hipStream_t st);
 hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
                       double dt, int64_t s0, int64_t s1, double* re, double* im, hipStream_t st);
 hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
@@ -124,6 +127,10 @@ struct fdtd_grid {
     double* dft_f = nullptr;
     double* dft_re = nullptr;
     double* dft_im = nullptr;
+    float* plane_ring = nullptr;    // kPlaneRing slots of one padded plane
+    double* plane_f = nullptr;
+    double* plane_re = nullptr;     // [nf][ny+1][pitch]
+    double* plane_im = nullptr;
     int64_t* step_dev = nullptr;
     int32_t* bad_dev = nullptr;
     BoardDev* board_dev = nullptr;
@@ -144,6 +151,8 @@ struct fdtd_grid {
     std::vector<std::array<int, 3>> probes;
     std::vector<VoltageProbeH> vprobes;
     std::vector<double> freqs;
+    int plane_k = -1;               // plane-DFT node plane, -1: none
+    std::vector<double> plane_freqs;
     int n_classes = 0;
     bool wide = false;
     bool finalized = false;
@@ -250,11 +259,13 @@ void tile_counts(int nx, int ny, int tx, int rows, int* cx, int* cy)
     *cy = (ny + 1 + rows - 1) / rows;
 }
 
-// One launch of the field kernel of a shape (one or two steps per pass).
+// One launch of the field kernel of a shape (one or two steps per pass); plane:
+// some board of the launch keeps a plane DFT.
 hipError_t launch_pass(int tx, int ty, int steps, const BoardDev* boards, const TileRef* tiles,
-                       int ntiles, int rel, int flip, bool wide, hipStream_t st)
+                       int ntiles, int rel, int flip, bool wide, bool plane, hipStream_t st)
 {
-    if (steps == 2) return launch_field_step2(ty, boards, tiles, ntiles, rel, flip, wide, st);
+    if (steps == 2)
+        return launch_field_step2(ty, boards, tiles, ntiles, rel, flip, wide, plane, st);
     return launch_field_step(tx, ty, boards, tiles, ntiles, rel, flip, wide, st);
 }
 
@@ -507,6 +518,7 @@ int finalize(fdtd_grid* g)
                 }
                 if (mark[n] & 1) fl |= kSrcEz;
                 if (mark[n] & 2) fl |= kPrbEz;
+                if (k == g->plane_k) fl |= kPlnEz;
                 const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl};
                 uint32_t id;
                 if (key == last) {
@@ -593,6 +605,24 @@ int finalize(fdtd_grid* g)
         HIP_OR_FAIL(launch_fill_zero((float*)g->dft_im, (int64_t)np * nf * 2, st));
     }
 
+    // plane DFT: sample ring (zeroed, so padding columns hold zeros) and FP64
+    // accumulators in the padded row layout
+    if (g->plane_k >= 0) {
+        const int64_t pn = g->pitch * (d.ny + 1);
+        const int pf = (int)g->plane_freqs.size();
+        g->plane_ring = (float*)dev_alloc(g, (size_t)kPlaneRing * pn * 4);
+        g->plane_f = (double*)dev_alloc(g, (size_t)pf * 8);
+        g->plane_re = (double*)dev_alloc(g, (size_t)pf * pn * 8);
+        g->plane_im = (double*)dev_alloc(g, (size_t)pf * pn * 8);
+        if (!g->plane_ring || !g->plane_f || !g->plane_re || !g->plane_im)
+            return fail(FDTD_ENOMEM, "plane DFT allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->plane_f, g->plane_freqs.data(), (size_t)pf * 8,
+                                   hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(launch_fill_zero(g->plane_ring, (int64_t)kPlaneRing * pn, st));
+        HIP_OR_FAIL(launch_fill_zero((float*)g->plane_re, (int64_t)pf * pn * 2, st));
+        HIP_OR_FAIL(launch_fill_zero((float*)g->plane_im, (int64_t)pf * pn * 2, st));
+    }
+
     // board descriptor and tile list
     BoardDev& b = g->board_host;
     for (int p = 0; p < 2; ++p)
@@ -624,6 +654,7 @@ int finalize(fdtd_grid* g)
     b.crd_x = (float)(kC0 * g->dt / d.dx);
     b.crd_y = (float)(kC0 * g->dt / d.dy);
     b.crd_z = (float)(kC0 * g->dt / d.dz);
+    b.plane_ring = g->plane_ring;
     g->board_dev = (BoardDev*)dev_alloc(g, sizeof(BoardDev));
     if (!g->board_dev) return fail(FDTD_ENOMEM, "descriptor allocation failed");
     if (int e = upload_tiles(g)) return e;
@@ -879,6 +910,23 @@ int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id)
     return FDTD_OK;
 }
 
+int fdtd_set_plane_dft(fdtd_grid* g, int k, const double* f_hz, int nf)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "the plane DFT is fixed after the first step");
+    if (k < 0 || k >= g->d.nz) return fail(FDTD_EINVAL, "plane %d is not an Ez plane (0 <= k < nz)", k);
+    if (!f_hz || nf < 1 || nf > 256) return fail(FDTD_EINVAL, "need 1 <= nf <= 256 frequencies");
+    for (int q = 0; q < nf; ++q)
+        if (!(f_hz[q] >= 0.0) || !std::isfinite(f_hz[q]))
+            return fail(FDTD_EINVAL, "frequency %d is negative or not finite", q);
+    // ring slots are addressed with 32-bit byte offsets
+    if ((int64_t)kPlaneRing * g->pitch * (g->d.ny + 1) * 4 >= (int64_t(1) << 32))
+        return fail(FDTD_EINVAL, "plane too large for the plane DFT (more than 2^25 padded nodes)");
+    g->plane_k = k;
+    g->plane_freqs.assign(f_hz, f_hz + nf);
+    return FDTD_OK;
+}
+
 int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
 {
     if (int e = check_grid(g)) return e;
@@ -955,6 +1003,17 @@ int fdtd_set_tile(fdtd_grid* g, int tile_x, int tile_y, int steps)
     return g->finalized ? upload_tiles(g) : FDTD_OK;
 }
 
+// Fold the plane-DFT samples of steps [step + rel_from, step + rel_to) into the
+// accumulators (step: the device counter when the fold runs).
+static int fold_plane(fdtd_grid* g, int64_t rel_from, int64_t rel_to, hipStream_t st)
+{
+    if (g->plane_k < 0) return FDTD_OK;
+    HIP_OR_FAIL(launch_plane_fold(g->plane_ring, g->pitch * (g->d.ny + 1), g->plane_f,
+                                  (int)g->plane_freqs.size(), g->dt, g->step_dev, rel_from, rel_to,
+                                  g->plane_re, g->plane_im, st));
+    return FDTD_OK;
+}
+
 // One field launch of the handle's shape (two steps, or one with the odd-step
 // shape when `single`), optionally bracketed by timing events.
 static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
@@ -963,10 +1022,10 @@ static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
         if (int e = record_event(g)) return e;
     if (single && g->tile_steps == 2)
         HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, g->board_dev, g->tiles1_dev, g->ntiles1, rel, flip,
-                                g->wide, g->stream));
+                                g->wide, g->plane_k >= 0, g->stream));
     else
         HIP_OR_FAIL(launch_pass(g->tile_x, g->tile_y, g->tile_steps, g->board_dev, g->tiles_dev,
-                                g->ntiles, rel, flip, g->wide, g->stream));
+                                g->ntiles, rel, flip, g->wide, g->plane_k >= 0, g->stream));
     if (g->timing) {
         if (int e = record_event(g)) return e;
         ++g->timed_launches;
@@ -1003,8 +1062,9 @@ static void build_graph(fdtd_grid* g)
     const int per = g->tile_steps, nl = kGraphChunk / per;
     for (int l = 0; l < nl && ok; ++l)
         ok = launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev, g->ntiles, l * per,
-                         l & 1, g->wide, g->stream) == hipSuccess;
+                         l & 1, g->wide, g->plane_k >= 0, g->stream) == hipSuccess;
     if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, nl, g->stream) == hipSuccess;
+    if (ok) ok = fold_plane(g, -kGraphChunk, 0, g->stream) == FDTD_OK;
     const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
     if (ok && ended && graph &&
         hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0) == hipSuccess)
@@ -1034,13 +1094,17 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
             }
         }
     }
-    if (done < n) {
+    while (done < n) {
         // kernels add the launch-relative step and buffer to the device counters,
-        // which the graphs above have already advanced
+        // which the graphs above have already advanced; with a plane DFT the ring
+        // is folded at least every kPlaneRing steps
+        const int64_t m = g->plane_k >= 0 ? std::min<int64_t>(n - done, kPlaneRing) : n - done;
         int64_t l = 0;
-        if (int e = enqueue_steps(g, n - done, &l)) return e;
-        HIP_OR_FAIL(launch_advance_one(g->step_dev, n - done, l, g->stream));
+        if (int e = enqueue_steps(g, m, &l)) return e;
+        HIP_OR_FAIL(launch_advance_one(g->step_dev, m, l, g->stream));
+        if (int e = fold_plane(g, -m, 0, g->stream)) return e;
         launches += l;
+        done += m;
     }
     if (g->dft_f)
         HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
@@ -1057,6 +1121,8 @@ static int ensure_event(fdtd_grid* g)
     return FDTD_OK;
 }
 
+static int step_many_round(fdtd_grid* const* gs, int ng, const int64_t* n);
+
 int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
 {
     if (!gs || !n || ng < 1) return fail(FDTD_EINVAL, "need at least one handle and step counts");
@@ -1071,6 +1137,28 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     for (int h = 0; h < ng; ++h)
         if (int e = finalize(gs[h])) return e;
+    bool planes = false;
+    for (int h = 0; h < ng; ++h) planes |= gs[h]->plane_k >= 0;
+    if (!planes) return step_many_round(gs, ng, n);
+    // plane DFTs fold their rings at least every kPlaneRing steps: rounds of at
+    // most that many steps per handle
+    std::vector<int64_t> left(n, n + ng), r(ng);
+    for (bool more = true; more;) {
+        more = false;
+        for (int h = 0; h < ng; ++h) {
+            r[h] = std::min<int64_t>(left[h], kPlaneRing);
+            left[h] -= r[h];
+            more |= left[h] > 0;
+        }
+        if (int e = step_many_round(gs, ng, r.data())) return e;
+    }
+    return FDTD_OK;
+}
+
+// One batched stepping of validated, finalised handles (the body of
+// fdtd_step_many; with plane DFTs every n[h] <= kPlaneRing).
+static int step_many_round(fdtd_grid* const* gs, int ng, const int64_t* n)
+{
     fdtd_grid* lead = gs[0];
     hipStream_t st = lead->stream;
     const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
@@ -1174,15 +1262,18 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, adv.data(), sizeof(int64_t) * adv.size(),
                                hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));  // the host arrays above are locals
+    bool planes = false;
+    for (int h = 0; h < ng; ++h) planes |= gs[h]->plane_k >= 0;
     for (const Span& sp : spans) {
         if (sp.tail) {
             HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, lead->batch_boards + ng,
-                                    lead->batch_tiles + sp.off, sp.count, 0, 0, sp.w == 1, st));
+                                    lead->batch_tiles + sp.off, sp.count, 0, 0, sp.w == 1, planes, st));
             continue;
         }
         for (int64_t q = sp.s0; q < sp.s1; ++q)
             HIP_OR_FAIL(launch_pass(tx, ty, sp.steps, lead->batch_boards, lead->batch_tiles + sp.off,
-                                    sp.count, (int)(q * sp.steps), (int)(q & 1), sp.w == 1, st));
+                                    sp.count, (int)(q * sp.steps), (int)(q & 1), sp.w == 1, planes,
+                                    st));
     }
     HIP_OR_FAIL(launch_advance(lead->batch_boards, ng, lead->batch_n, st));
     for (int b = 0; b < ng; ++b) {
@@ -1191,6 +1282,8 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     for (int h = 0; h < ng; ++h) {
         fdtd_grid* g = gs[h];
+        if (n[h] > 0)
+            if (int e = fold_plane(g, -n[h], 0, st)) return e;
         if (g->dft_f && n[h] > 0)
             HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
                                    (int)g->probes.size(), g->dt, g->step, g->step + n[h],
@@ -1285,6 +1378,26 @@ int fdtd_get_dft(fdtd_grid* g, int id, double* re, double* im)
     return check_bad(g);
 }
 
+int fdtd_get_plane_dft(fdtd_grid* g, double* re, double* im)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->plane_k < 0) return fail(FDTD_ESTATE, "no plane DFT was set");
+    if (!re || !im) return fail(FDTD_EINVAL, "null output");
+    const int nf = (int)g->plane_freqs.size();
+    const size_t row = (size_t)(g->d.nx + 1) * 8, prow = (size_t)g->pitch * 8;
+    const size_t rows = (size_t)nf * (g->d.ny + 1);
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    if (!g->finalized) {
+        std::fill(re, re + rows * (g->d.nx + 1), 0.0);
+        std::fill(im, im + rows * (g->d.nx + 1), 0.0);
+        return FDTD_OK;
+    }
+    HIP_OR_FAIL(hipMemcpy2DAsync(re, row, g->plane_re, prow, row, rows, hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(hipMemcpy2DAsync(im, row, g->plane_im, prow, row, rows, hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    return check_bad(g);
+}
+
 int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im)
 {
     if (int e = check_grid(g)) return e;
@@ -1349,6 +1462,24 @@ int fdtd_get_field(fdtd_grid* g, int comp, float* out)
     return FDTD_OK;
 }
 
+int fdtd_get_plane(fdtd_grid* g, int comp, int k, float* out)
+{
+    if (int e = check_grid(g)) return e;
+    if (comp < 0 || comp > FDTD_BZ || !out) return fail(FDTD_EINVAL, "bad component or output");
+    if (k < 0 || k > g->d.nz) return fail(FDTD_EINVAL, "plane %d is outside 0..nz", k);
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    const size_t row = (size_t)(g->d.nx + 1) * 4, prow = (size_t)g->pitch * 4;
+    const float* src = comp_ptr(g, comp) + (size_t)k * g->pitch * (g->d.ny + 1);
+    HIP_OR_FAIL(hipMemcpy2DAsync(out, row, src, prow, row, (size_t)g->d.ny + 1,
+                                 hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    const double sc = field_scale(comp);
+    const size_t nn = (size_t)(g->d.nx + 1) * (g->d.ny + 1);
+    if (sc != 1.0)
+        for (size_t t = 0; t < nn; ++t) out[t] = (float)((double)out[t] * sc);
+    return check_bad(g);
+}
+
 int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
 {
     if (int e = check_grid(g)) return e;
@@ -1377,11 +1508,17 @@ int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
     return FDTD_OK;
 }
 
+// checkpoint header: magic, nx, ny, nz, step, probes, probe frequencies,
+// max_steps, plane-DFT plane, plane frequencies
+constexpr int kStateHeader = 80;
+
 int64_t fdtd_state_bytes(fdtd_grid* g)
 {
     if (!g) return fail(FDTD_EINVAL, "null grid handle");
     const int64_t np = (int64_t)g->probes.size(), nf = (int64_t)g->freqs.size();
-    return 64 + 12 * g->nodes * 4 + np * g->d.max_steps * 4 + (np && nf ? np * nf * 16 : 0);
+    const int64_t pf = g->plane_k >= 0 ? (int64_t)g->plane_freqs.size() : 0;
+    return kStateHeader + 12 * g->nodes * 4 + np * g->d.max_steps * 4 + (np && nf ? np * nf * 16 : 0) +
+           pf * (g->d.nx + 1) * (g->d.ny + 1) * 16;
 }
 
 int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes)
@@ -1391,10 +1528,11 @@ int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes)
     if (int e = finalize(g)) return e;
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     char* p = (char*)host_buf;
-    int64_t hdr[8] = {0x4644544453544154ll, g->d.nx, g->d.ny, g->d.nz, g->step,
-                      (int64_t)g->probes.size(), (int64_t)g->freqs.size(), g->d.max_steps};
-    memcpy(p, hdr, 64);
-    p += 64;
+    int64_t hdr[kStateHeader / 8] = {0x4644544453544154ll, g->d.nx, g->d.ny, g->d.nz, g->step,
+                                     (int64_t)g->probes.size(), (int64_t)g->freqs.size(),
+                                     g->d.max_steps, g->plane_k, (int64_t)g->plane_freqs.size()};
+    memcpy(p, hdr, kStateHeader);
+    p += kStateHeader;
     for (int c = 0; c < 12; ++c) {
         HIP_OR_FAIL(copy_field_sync(g, p, comp_ptr(g, c), hipMemcpyDeviceToHost));
         p += g->nodes * 4;
@@ -1408,6 +1546,12 @@ int fdtd_save_state(fdtd_grid* g, void* host_buf, int64_t bytes)
         HIP_OR_FAIL(copy_sync(g, p, g->dft_re, np * nf * 8, hipMemcpyDeviceToHost));
         p += np * nf * 8;
         HIP_OR_FAIL(copy_sync(g, p, g->dft_im, np * nf * 8, hipMemcpyDeviceToHost));
+        p += np * nf * 8;
+    }
+    if (g->plane_k >= 0) {
+        // the ring is always folded when a call returns: the accumulators are the state
+        const int64_t pn = (int64_t)g->plane_freqs.size() * (g->d.nx + 1) * (g->d.ny + 1);
+        if (int e = fdtd_get_plane_dft(g, (double*)p, (double*)p + pn)) return e;
     }
     return FDTD_OK;
 }
@@ -1418,12 +1562,13 @@ int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes)
     if (!host_buf || bytes < fdtd_state_bytes(g)) return fail(FDTD_EINVAL, "buffer too small");
     if (int e = finalize(g)) return e;
     const char* p = (const char*)host_buf;
-    int64_t hdr[8];
-    memcpy(hdr, p, 64);
-    p += 64;
+    int64_t hdr[kStateHeader / 8];
+    memcpy(hdr, p, kStateHeader);
+    p += kStateHeader;
     if (hdr[0] != 0x4644544453544154ll || hdr[1] != g->d.nx || hdr[2] != g->d.ny ||
         hdr[3] != g->d.nz || hdr[5] != (int64_t)g->probes.size() ||
-        hdr[6] != (int64_t)g->freqs.size() || hdr[7] != g->d.max_steps)
+        hdr[6] != (int64_t)g->freqs.size() || hdr[7] != g->d.max_steps ||
+        hdr[8] != g->plane_k || hdr[9] != (int64_t)g->plane_freqs.size())
         return fail(FDTD_EINVAL, "state image does not match this grid");
     if (hdr[4] < 0 || hdr[4] > g->d.max_steps) return fail(FDTD_EINVAL, "bad step in state image");
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
@@ -1441,6 +1586,15 @@ int fdtd_load_state(fdtd_grid* g, const void* host_buf, int64_t bytes)
         HIP_OR_FAIL(copy_sync(g, g->dft_re, p, np * nf * 8, hipMemcpyHostToDevice));
         p += np * nf * 8;
         HIP_OR_FAIL(copy_sync(g, g->dft_im, p, np * nf * 8, hipMemcpyHostToDevice));
+        p += np * nf * 8;
+    }
+    if (g->plane_k >= 0) {
+        const size_t row = (size_t)(g->d.nx + 1) * 8, prow = (size_t)g->pitch * 8;
+        const size_t rows = g->plane_freqs.size() * (size_t)(g->d.ny + 1);
+        HIP_OR_FAIL(hipMemcpy2DAsync(g->plane_re, prow, p, row, row, rows, hipMemcpyHostToDevice, g->stream));
+        p += rows * row;
+        HIP_OR_FAIL(hipMemcpy2DAsync(g->plane_im, prow, p, row, row, rows, hipMemcpyHostToDevice, g->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     }
     HIP_OR_FAIL(copy_sync(g, g->step_dev, &g->step, 8, hipMemcpyHostToDevice));
     const int32_t zero = 0;
@@ -1466,6 +1620,8 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->tile_x = g->tile_x;
     out->tile_y = g->tile_y;
     out->tile_steps = g->tile_steps;
+    out->plane_k = g->plane_k;
+    out->plane_nf = (int32_t)g->plane_freqs.size();
     return FDTD_OK;
 }
 

@@ -27,6 +27,11 @@ constexpr double kEta0 = kMu0 * kC0;
 // steps per replayable graph in fdtd_step_n
 constexpr int kGraphChunk = 32;
 
+// slots of the plane-DFT sample ring (one plane of Ez per step); folded into the
+// accumulators at least every kPlaneRing steps
+constexpr int kPlaneRing = 32;
+static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly once");
+
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;
 
@@ -34,7 +39,8 @@ constexpr int64_t kGuard = 64;
 enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kNumCoef = 5 };
 
 // class flags (per node): which E components are stepped, and source/probe marks
-enum : uint32_t { kUpdEx = 1u, kUpdEy = 2u, kUpdEz = 4u, kSrcEz = 8u, kPrbEz = 16u };
+// (kPlnEz: the node lies on the plane-DFT plane, its Ez goes to the sample ring)
+enum : uint32_t { kUpdEx = 1u, kUpdEy = 2u, kUpdEz = 4u, kSrcEz = 8u, kPrbEz = 16u, kPlnEz = 32u };
 
 struct ClassEntry {
     float inv_x, inv_y, inv_z;  // 1/eps_r of the Ex, Ey, Ez edges owned by the node
@@ -71,6 +77,9 @@ struct BoardDev {
     // added to a launch's step and buffer offsets (nonzero only in the one-step
     // tail launch of a batch, whose boards have done different numbers of pairs)
     int32_t rel0, flip0;
+    // plane DFT: Ez of the nodes flagged kPlnEz goes to slot (step mod kPlaneRing)
+    // of the ring, each slot one node plane of the field layout
+    float* plane_ring;
 };
 
 // One work item of the field kernel: tile (tx, ty) of a board, planes kb..ke-1.

@@ -274,6 +274,8 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                     for (int p = 0; p < B.nprb; ++p)
                         if (pn[p] == node) ps[p * ms + step] = ezn;
                 }
+                if (ce.flags & kPlnEz)   // plane-DFT sample into ring slot step mod kPlaneRing
+                    st_at(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * szb + node0b, ezn);
                 bad |= !isfinite(exn + eyn + ezn);
             }
             hx_prev = hxn;
@@ -434,6 +436,61 @@ __global__ void dft_accumulate(const float* __restrict__ series, int64_t max_ste
     im[p * nf + q] += ai * dt;
 }
 
+// Fold the ring samples of steps [s0, s1) (s1 - s0 <= kPlaneRing; s0, s1 are
+// the device step counter plus rel_from, rel_to) into the plane accumulators:
+// A_f(node) += e_s(node) exp(-i 2 pi f (s+1) dt) dt for each s in order, the
+// probe DFT's definition applied to every node of the plane.  Every sample is
+// added to the accumulator on its own, so the result does not depend on how the
+// steps were grouped into folds.  One thread per node (padded row layout); the
+// twiddles (times dt) of kPlaneFreqs frequencies at a time sit in LDS.
+constexpr int kPlaneFreqs = 8;
+__global__ __launch_bounds__(256) void plane_fold(const float* __restrict__ ring, int64_t plane_nodes,
+                                                  const double* __restrict__ freqs, int nf, double dt,
+                                                  const int64_t* __restrict__ step, int64_t rel_from,
+                                                  int64_t rel_to, double* __restrict__ re,
+                                                  double* __restrict__ im)
+{
+    static_assert(kPlaneFreqs * kPlaneRing == 256, "one twiddle per thread");
+    __shared__ double tc[kPlaneFreqs][kPlaneRing], ts[kPlaneFreqs][kPlaneRing];
+    const int64_t s0 = step[0] + rel_from;
+    const int n = (int)(rel_to - rel_from);
+    const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = node < plane_nodes;
+    float e[kPlaneRing];
+#pragma unroll
+    for (int q = 0; q < kPlaneRing; ++q)
+        e[q] = (ok && q < n) ? ring[(int64_t)((s0 + q) & (kPlaneRing - 1)) * plane_nodes + node] : 0.0f;
+    const int tf = threadIdx.x / kPlaneRing, tq = threadIdx.x % kPlaneRing;
+    for (int f0 = 0; f0 < nf; f0 += kPlaneFreqs) {
+        if (f0 + tf < nf && tq < n) {
+            double turns = freqs[f0 + tf] * dt * (double)(s0 + tq + 1);
+            turns -= floor(turns);
+            double sn, cs;
+            sincospi(2.0 * turns, &sn, &cs);
+            tc[tf][tq] = cs * dt;
+            ts[tf][tq] = -sn * dt;
+        }
+        __syncthreads();
+        if (ok) {
+            const int fe = min(kPlaneFreqs, nf - f0);
+            for (int fl = 0; fl < fe; ++fl) {
+                const int64_t a = (int64_t)(f0 + fl) * plane_nodes + node;
+                double ar = re[a], ai = im[a];
+#pragma unroll
+                for (int q = 0; q < kPlaneRing; ++q)
+                    if (q < n) {
+                        const double v = (double)e[q];
+                        ar = fma(v, tc[fl][q], ar);
+                        ai = fma(v, ts[fl][q], ai);
+                    }
+                re[a] = ar;
+                im[a] = ai;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Zero-padded complex FP64 input for the probe FFT.
 __global__ void fft_load(const float* __restrict__ series, int64_t n_samples, int n_fft,
                          double2* __restrict__ out)
@@ -553,6 +610,17 @@ hipError_t launch_dft(const float* series, int64_t max_steps, const double* freq
     dim3 grid((nf + 63) / 64, np);
     hipLaunchKernelGGL(dft_accumulate, grid, dim3(64), 0, st, series, max_steps, freqs, nf, np,
                        dt, s0, s1, re, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
+                             double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
+                             double* re, double* im, hipStream_t st)
+{
+    if (nf <= 0 || rel_to <= rel_from) return hipSuccess;
+    if (rel_to - rel_from > kPlaneRing) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(plane_fold, dim3((unsigned)((plane_nodes + 255) / 256)), dim3(256), 0, st,
+                       ring, plane_nodes, freqs, nf, dt, step, rel_from, rel_to, re, im);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ struct AxisCoef {
     float cam1_h, ca_h, rp_h, ph_h, q_h;
 };
 
-template <int TY, typename CT>
+template <int TY, typename CT, bool PL>
 __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __restrict__ boards,
                                                              const TileRef* __restrict__ tiles,
                                                              int rel, int flip)
@@ -261,6 +261,11 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         for (int q = 0; q < B.nprb; ++q)
             if (pn[q] == node) ps[q * ms + s] = ez;
     };
+    // Ez of the plane-DFT plane at step s into ring slot s mod kPlaneRing (slots
+    // are node planes of the field layout)
+    auto plane_sample = [&](int64_t s, float ez) {
+        st_at(B.plane_ring, (uint32_t)(s & (kPlaneRing - 1)) * szb + node0b, ez);
+    };
 
     // staging of the first plane
     sE0x[0][r][c] = ld_at(gE, at_plane(k0));
@@ -341,6 +346,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
                 d1y = ((py || pz) && (ce.flags & kUpdEy)) ? o.dy + ddy : o.dy;
                 d1z = ((pz || px) && (ce.flags & kUpdEz)) ? o.dz + ddz : o.dz;
                 if (own && k >= kb && k < ke && (ce.flags & kPrbEz)) record_probe(node, step, e1z);
+                if (PL && own && k >= kb && k < ke && (ce.flags & kPlnEz)) plane_sample(step, e1z);
             }
             sE1x[e][r][c] = e1x;
             sE1y[e][r][c] = e1y;
@@ -408,6 +414,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
             if (py || pzm) st_at(dD, nb + cs, (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y);
             if (pzm || px) st_at(dD, nb + cs2, (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z);
             if (ce.flags & kPrbEz) record_probe(node, step + 1, ezn);
+            if (PL && (ce.flags & kPlnEz)) plane_sample(step + 1, ezn);
             bad |= !isfinite(exn + eyn + ezn);
         }
         // plane k's step-one values become the carried ones
@@ -442,16 +449,28 @@ void shape2_at(int s, int* tx, int* ty)
     *ty = kShapes2[s].ty;
 }
 
-template <int TY>
-static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel,
-                            int flip, bool wide, hipStream_t st)
+template <int TY, bool PL>
+static void launch2_tp(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
+                       bool wide, hipStream_t st)
 {
     if (wide)
-        hipLaunchKernelGGL((field_step2<TY, uint16_t>), dim3(ntiles), dim3(64 * TY + 128), 0, st,
-                           boards, tiles, rel, flip);
+        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL>), dim3(ntiles), dim3(64 * TY + 128), 0,
+                           st, boards, tiles, rel, flip);
     else
-        hipLaunchKernelGGL((field_step2<TY, uint8_t>), dim3(ntiles), dim3(64 * TY + 128), 0, st,
-                           boards, tiles, rel, flip);
+        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL>), dim3(ntiles), dim3(64 * TY + 128), 0,
+                           st, boards, tiles, rel, flip);
+}
+
+// plane: some board of the launch keeps a plane DFT (the variant with the ring
+// store; the other never spends registers on it)
+template <int TY>
+static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel,
+                            int flip, bool wide, bool plane, hipStream_t st)
+{
+    if (plane)
+        launch2_tp<TY, true>(boards, tiles, ntiles, rel, flip, wide, st);
+    else
+        launch2_tp<TY, false>(boards, tiles, ntiles, rel, flip, wide, st);
     return hipGetLastError();
 }
 
@@ -460,9 +479,9 @@ static int occupancy2_t(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -479,14 +498,14 @@ int field_step2_occupancy(int tile_y, bool wide)
 }
 
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
-                              int rel, int flip, bool wide, hipStream_t st)
+                              int rel, int flip, bool wide, bool plane, hipStream_t st)
 {
     switch (tile_y) {
-        case 14: return launch2_t<14>(boards, tiles, ntiles, rel, flip, wide, st);
-        case 12: return launch2_t<12>(boards, tiles, ntiles, rel, flip, wide, st);
-        case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, st);
-        case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, st);
-        case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, st);
+        case 14: return launch2_t<14>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 12: return launch2_t<12>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, plane, st);
         default: return hipErrorInvalidValue;
     }
 }

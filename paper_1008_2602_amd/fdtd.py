@@ -62,7 +62,7 @@ class fdtd_info(C.Structure):
                 ("device_bytes", C.c_int64),
                 ("n_sources", C.c_int32), ("n_probes", C.c_int32), ("n_freqs", C.c_int32),
                 ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("tile_steps", C.c_int32)]
+                ("tile_steps", C.c_int32), ("plane_k", C.c_int32), ("plane_nf", C.c_int32)]
 
 
 class FdtdError(RuntimeError):
@@ -85,6 +85,9 @@ _sigs = {
                                C.c_int),
     "fdtd_get_voltage": ([_P, C.c_int, _P, C.c_int64], C.c_int),
     "fdtd_set_dft_freqs": ([_P, _P, C.c_int], C.c_int),
+    "fdtd_set_plane_dft": ([_P, C.c_int, _P, C.c_int], C.c_int),
+    "fdtd_get_plane_dft": ([_P, _P, _P], C.c_int),
+    "fdtd_get_plane": ([_P, C.c_int, C.c_int, _P], C.c_int),
     "fdtd_step_n": ([_P, C.c_int64], C.c_int),
     "fdtd_step_many": ([_P, C.c_int, _P], C.c_int),
     "fdtd_probe_fft": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
@@ -230,6 +233,26 @@ def fdtd_add_voltage_probe(g, i, j, k0, k1) -> int:
 def fdtd_set_dft_freqs(g, f_hz: Sequence[float]):
     f = np.ascontiguousarray(f_hz, dtype=np.float64)
     _check(_lib.fdtd_set_dft_freqs(g, _ptr(f), len(f)))
+
+
+def fdtd_set_plane_dft(g, k: int, f_hz: Sequence[float]):
+    f = np.ascontiguousarray(f_hz, dtype=np.float64)
+    _check(_lib.fdtd_set_plane_dft(g, int(k), _ptr(f), len(f)))
+
+
+def fdtd_get_plane_dft(g, ny: int, nx: int) -> np.ndarray:
+    """(nf, ny+1, nx+1) complex128."""
+    nf = fdtd_get_info(g).plane_nf
+    re = np.zeros((nf, ny + 1, nx + 1))
+    im = np.zeros((nf, ny + 1, nx + 1))
+    _check(_lib.fdtd_get_plane_dft(g, _ptr(re), _ptr(im)))
+    return re + 1j * im
+
+
+def fdtd_get_plane(g, comp: int, k: int, ny: int, nx: int) -> np.ndarray:
+    out = np.zeros((ny + 1, nx + 1), np.float32)
+    _check(_lib.fdtd_get_plane(g, int(comp), int(k), _ptr(out)))
+    return out
 
 
 def fdtd_step_n(g, n: int):
@@ -380,6 +403,8 @@ def grid_from_board(board, max_steps: Optional[int] = None, hip_stream=None,
         ids = [fdtd_add_probe(g, i, j, k) for (i, j, k) in b.probes]
         if b.dft_freqs is not None and len(b.dft_freqs):
             fdtd_set_dft_freqs(g, b.dft_freqs)
+        if getattr(b, "plane_dft", None) is not None:
+            fdtd_set_plane_dft(g, b.plane_dft[0], b.plane_dft[1])
         if tile is not None:
             fdtd_set_tile(g, *tile)
     except Exception:

@@ -42,7 +42,12 @@ def _store(path: str, data: Dict[str, list]) -> None:
 
 
 def board_key(board) -> str:
-    return f"{board.nx}x{board.ny}x{board.nz}/pml{'-'.join(str(v) for v in board.npml)}"
+    """Grid size and PML; a plane DFT selects other kernel variants, so it is part
+    of the key."""
+    key = f"{board.nx}x{board.ny}x{board.nz}/pml{'-'.join(str(v) for v in board.npml)}"
+    if getattr(board, "plane_dft", None) is not None:
+        key += "/plane"
+    return key
 
 
 def batch_key(boards: Sequence) -> str:
