@@ -17,12 +17,14 @@ Beside it, the same line carries
     read back with its probe spectra; p50/p99 latency and throughput.  The step
     count per solve is reduced (default 1000 instead of 8000) so the run stays
     short; the number is stated in the output;
+  * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
+    over the whole plane, against the plain step;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
     one solve, and a 64-board sweep of its source resistance, with the oracle's
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1]
+                  [--only single|batch|serve|table1|plane]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -117,6 +119,48 @@ def run_single(F, torch, K, W, tile):
     F.fdtd_destroy_grid(g)
     assert np.all(np.isfinite(probe0))
     return board, tile, info, wall, kern_ms, launches
+
+
+def run_plane_dft(F, torch, K, W, plain_ms_per_step):
+    """The large board with the plane DFT of its ground-plane Ez (the row above
+    the ground sheet) at 16 frequencies, 0.5-8 GHz: ms per step against the plain
+    path, and the fold kernel's algorithmic bytes (each fold reads 32 FP32 samples
+    and reads and writes an FP64 complex accumulator per frequency, per padded
+    plane node; the field kernel adds one 4-byte ring store per plane node and
+    step)."""
+    import numpy as np
+    import boardgen
+    from paper_1008_2602_amd import tune
+    board = boardgen.large_board()
+    nf = 16
+    board.plane_dft = (board.meta["layout"]["kg"], np.linspace(0.5e9, 8e9, nf))
+    tile = tune.tune_board(board)
+    g, _ = F.grid_from_board(board, max_steps=W + K, tile=tile)
+    F.fdtd_step_n(g, W)
+    F.fdtd_synchronize(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_n(g, K)
+    F.fdtd_synchronize(g)
+    wall = time.perf_counter() - t0
+    plane = F.fdtd_get_plane_dft(g, board.ny, board.nx)
+    F.fdtd_destroy_grid(g)
+    assert np.all(np.isfinite(plane))
+    pitch = (board.nx + 1 + 31) // 32 * 32
+    plane_nodes = pitch * (board.ny + 1)
+    ms = wall / K * 1e3
+    return {
+        "workload": f"large board {board.nx}x{board.ny}x{board.nz} with the plane DFT of Ez at "
+                    f"k={board.plane_dft[0]} (above the ground sheet), {nf} frequencies 0.5-8 GHz",
+        "tile": "x".join(str(v) for v in tile),
+        "steps": K,
+        "ms_per_step": round(ms, 4),
+        "overhead_vs_plain": round(ms / plain_ms_per_step - 1.0, 4),
+        "gcell_updates_per_s": round(board.cells * K / wall / 1e9, 3),
+        "fold_launches": -(-K // 32),
+        "fold_bytes_per_launch": int(plane_nodes * (32 * 4 + nf * 32)),
+        "ring_store_bytes_per_step": int(plane_nodes * 4),
+    }
 
 
 def run_batch(F, torch, K, W):
@@ -288,7 +332,8 @@ def main():
     ap.add_argument("--tile", default="",
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
-    ap.add_argument("--only", choices=["single", "batch", "serve", "table1"], default=None)
+    ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane"],
+                    default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -367,6 +412,12 @@ def main():
         if args.only in (None, "serve"):
             out["served"] = run_serve(F, torch, batch["value"], mean_cells,
                                       args.serve_requests, args.serve_steps)
+    if args.only in (None, "plane"):
+        plain = out.get("ms_per_step")
+        if plain is None:
+            _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
+            plain = wall0 / K * 1e3
+        out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:

@@ -261,10 +261,13 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         for (int q = 0; q < B.nprb; ++q)
             if (pn[q] == node) ps[q * ms + s] = ez;
     };
-    // Ez of the plane-DFT plane at step s into ring slot s mod kPlaneRing (slots
-    // are node planes of the field layout)
-    auto plane_sample = [&](int64_t s, float ez) {
-        st_at(B.plane_ring, (uint32_t)(s & (kPlaneRing - 1)) * szb + node0b, ez);
+    // Ez of the plane-DFT plane at step (launch step + extra) into ring slot
+    // step mod kPlaneRing (slots are node planes of the field layout).  The step
+    // is read afresh here (volatile): a loop-invariant slot offset would be
+    // hoisted out of the plane loop and held in registers the hot path needs.
+    auto plane_sample = [&](int extra, float ez) {
+        const int64_t now = *(const volatile int64_t*)B.step + rel + extra;
+        st_at(B.plane_ring, (uint32_t)(now & (kPlaneRing - 1)) * szb + node0b, ez);
     };
 
     // staging of the first plane
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
                 d1y = ((py || pz) && (ce.flags & kUpdEy)) ? o.dy + ddy : o.dy;
                 d1z = ((pz || px) && (ce.flags & kUpdEz)) ? o.dz + ddz : o.dz;
                 if (own && k >= kb && k < ke && (ce.flags & kPrbEz)) record_probe(node, step, e1z);
-                if (PL && own && k >= kb && k < ke && (ce.flags & kPlnEz)) plane_sample(step, e1z);
+                if (PL && own && k >= kb && k < ke && (ce.flags & kPlnEz)) plane_sample(0, e1z);
             }
             sE1x[e][r][c] = e1x;
             sE1y[e][r][c] = e1y;
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
             if (py || pzm) st_at(dD, nb + cs, (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y);
             if (pzm || px) st_at(dD, nb + cs2, (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z);
             if (ce.flags & kPrbEz) record_probe(node, step + 1, ezn);
-            if (PL && (ce.flags & kPlnEz)) plane_sample(step + 1, ezn);
+            if (PL && (ce.flags & kPlnEz)) plane_sample(1, ezn);
             bad |= !isfinite(exn + eyn + ezn);
         }
         // plane k's step-one values become the carried ones
