@@ -19,12 +19,14 @@ Beside it, the same line carries
     short; the number is stated in the output;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
+  * "zconv": the z-convergence study (1..15 cells across the dielectric) as
+    one batched call;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
     one solve, and a 64-board sweep of its source resistance, with the oracle's
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1|plane]
+                  [--only single|batch|serve|table1|plane|zconv]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -160,6 +162,43 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
         "fold_launches": -(-K // 32),
         "fold_bytes_per_launch": int(plane_nodes * (32 * 4 + nf * 32)),
         "ring_store_bytes_per_step": int(plane_nodes * 4),
+    }
+
+
+def run_zconv(F, torch, steps=4000):
+    """The z-convergence study of the Results section: the Table 1 footprint with
+    the 0.8 mm dielectric cut into 1..15 z cells (15 boards, 48x43x21 .. 48x43x91),
+    all advanced together by one fdtd_step_many call.  Reports the wall time and
+    how far 2 cells sit from 15 (ground-plane Ez, relative L2 over the series and
+    the far-corner peak)."""
+    import numpy as np
+    import boardgen
+    boards = [boardgen.zconv_board(n, steps=steps) for n in range(1, 16)]
+    hs = [F.grid_from_board(b, max_steps=steps) for b in boards]
+    gs = [g for g, _ in hs]
+    for g in gs:
+        F.fdtd_step_n(g, 0)
+    F.fdtd_synchronize(gs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_many(gs, [steps] * len(gs))
+    F.fdtd_synchronize(gs[0])
+    wall = time.perf_counter() - t0
+    series = [np.stack([F.fdtd_get_probe(g, p, steps) for p in ids]).astype(np.float64)
+              for g, ids in hs]
+    for g in gs:
+        F.fdtd_destroy_grid(g)
+    ref, two = series[-1], series[1]
+    rel = max(float(np.linalg.norm(two[p] - ref[p]) / np.linalg.norm(ref[p])) for p in range(3))
+    corner = float(abs(np.abs(two[2]).max() - np.abs(ref[2]).max()) / np.abs(ref[2]).max())
+    cells = sum(b.cells for b in boards)
+    return {
+        "workload": "z-convergence family: 40x30x0.8 mm board, 1..15 cells across the dielectric "
+                    f"(15 boards, {cells} cells in all), {steps} steps, one batched call",
+        "wall_s": round(wall, 3),
+        "gcell_updates_per_s": round(cells * steps / wall / 1e9, 3),
+        "two_vs_fifteen_rel_l2": round(rel, 5),
+        "two_vs_fifteen_corner_peak": round(corner, 6),
     }
 
 
@@ -332,7 +371,7 @@ def main():
     ap.add_argument("--tile", default="",
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
-    ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane"],
+    ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv"],
                     default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -418,6 +457,8 @@ def main():
             _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
+    if args.only in (None, "zconv"):
+        out["zconv"] = run_zconv(F, torch)
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:

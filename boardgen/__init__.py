@@ -368,6 +368,35 @@ def table1_board(steps: int = 30000, air_cells: int = 6, pml_cells: int = 8,
     return b
 
 
+def zconv_board(n_diel: int, steps: int = 4000, n_diel_max: int = 15, air_xy: int = 6,
+                pml: int = 8) -> Board:
+    """The z-convergence study of the Results section: the Table 1 board
+    (40 x 30 mm, 2 mm in-plane cells, eps_r 4.0) with its 0.8 mm dielectric cut
+    into n_diel z cells (dz = 0.8 mm / n_diel) and 1.6 mm of air above and below
+    (2 n_diel cells), 8 PML cells.  The DGAUSS current filament (1 A/mm^2,
+    t0 = 100 ps, tau = 50 ps) spans the whole gap at the board centre, so the
+    injected current does not depend on dz; Ez is probed on the ground-plane row
+    (the first Ez edge above the ground sheet) at the centre, off-centre and near
+    a corner.  Every member of the family uses the time step of the finest grid
+    (n_diel_max cells, 0.99 x Eq. 7), so their sample times coincide."""
+    assert 1 <= n_diel <= n_diel_max
+    dz = 0.8e-3 / n_diel
+    b, lay = plane_stack(f"zconv-{n_diel}", (20, 15), n_diel, air_xy, pml,
+                         2 * n_diel, 2 * n_diel, pml, 2e-3, 2e-3, dz, 4.0)
+    c0 = 299792458.0
+    dzf = 0.8e-3 / n_diel_max
+    b.dt = 0.99 / (c0 * np.sqrt(2.0 / (2e-3) ** 2 + 1.0 / dzf ** 2))
+    ci, cj = (lay["bi0"] + lay["bi1"]) // 2, (lay["bj0"] + lay["bj1"]) // 2
+    b.sources = [Source(ci, cj, k, DGAUSS, 1.0e6, 100e-12, 50e-12)
+                 for k in range(lay["kg"], lay["kt"])]
+    kg = lay["kg"]
+    b.probes = [(ci, cj, kg), (ci + 5, cj + 3, kg), (lay["bi1"] - 1, lay["bj1"] - 1, kg)]
+    b.steps = steps
+    b.meta = dict(layout=lay, n_diel=n_diel)
+    b.check()
+    return b
+
+
 def random_tiny(seed: int, nx: int = 10, ny: int = 9, nz: int = 8, npml: int = 2,
                 steps: int = 40) -> Board:
     """A tiny board with every feature: PML on all faces (may differ per face),
