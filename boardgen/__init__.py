@@ -73,6 +73,9 @@ class Board:
     pml_m: float = 3.0
     pml_R: float = 1e-6
     pml_kappa_max: float = 1.0
+    # Eq. 2's eps_rw: True divides each PML sigma by the relative permittivity at
+    # the field location; False takes eps_rw = 1 (the same wherever the PML is air)
+    pml_eps_rw: bool = False
     sources: List[Source] = field(default_factory=list)
     probes: List[Tuple[int, int, int]] = field(default_factory=list)
     steps: int = 1000

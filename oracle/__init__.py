@@ -55,6 +55,7 @@ class _Problem(C.Structure):
                 ("src_R", C.c_void_p),
                 ("nprobe", C.c_int32), ("probe_ijk", C.c_void_p),
                 ("nfreq", C.c_int32), ("freqs", C.c_void_p),
+                ("pml_eps_rw", C.c_int32),
                 ("plane_k", C.c_int32), ("nplane_freq", C.c_int32), ("plane_freqs", C.c_void_p)]
 
 
@@ -150,6 +151,7 @@ class Problem:
         p.probe_ijk = self.probe_ijk.ctypes.data
         p.nfreq = len(self.freqs)
         p.freqs = self.freqs.ctypes.data
+        p.pml_eps_rw = 1 if getattr(b, "pml_eps_rw", False) else 0
         p.plane_k = self.plane_k
         p.nplane_freq = len(self.plane_freqs)
         p.plane_freqs = self.plane_freqs.ctypes.data

@@ -20,6 +20,10 @@
  *     process"), and likewise B then H using the same s (mu2 = mu1 s in Eq. 1);
  *   - sigma and kappa are graded polynomially from the PML interface to the
  *     outer PEC wall (Eq. 5, read as (depth/d)^m);
+ *   - with pml_eps_rw set, Eq. 2's s_w = kappa_w + sigma_w / (j w eps0 eps_rw)
+ *     takes eps_rw as the relative permittivity at each field location: the
+ *     edge mean for E and D, the mean of the two cells sharing the face for H
+ *     and B (Eq. 1 puts the same s-bar on mu); otherwise eps_rw = 1;
  *   - the power and ground planes zero the tangential Ex, Ey on their edges;
  *   - a current source enters the D_z update as -J_z at the half step;
  *   - a resistive voltage source (Results section, the Table 1 run, built with
@@ -75,6 +79,8 @@ typedef struct {
     const int32_t* probe_ijk;  /* 3*nprobe, Ez(i,j,k+1/2) */
     int32_t nfreq;
     const double* freqs;       /* Hz */
+    int32_t pml_eps_rw;        /* 1: Eq. 2's sigma_w / eps_rw with the local eps_r at each
+                                  field location; 0: eps_rw = 1 */
     int32_t plane_k;           /* >= 0: running DFT of Ez(i, j, plane_k+1/2) over the plane */
     int32_t nplane_freq;
     const double* plane_freqs; /* Hz */
@@ -125,11 +131,18 @@ static void or_profile(double pos, int n, int nlo, int nhi, double delta,
     *kappa = 1.0 + (p->pml_kappa_max - 1.0) * frac;
 }
 
-/* Per-axis 1-D coefficients at nodes (pos = i) and half nodes (pos = i + 1/2). */
+/* Per-axis 1-D coefficients at nodes (pos = i) and half nodes (pos = i + 1/2),
+ * with the raw sigma and kappa they come from. */
 typedef struct {
     double *a_n, *b_n, *pp_n, *pm_n;   /* n+1 entries, node i */
     double *a_h, *b_h, *pp_h, *pm_h;   /* n+1 entries, half node i+1/2 (last unused) */
+    double *sig_n, *kap_n, *sig_h, *kap_h;
 } or_axis;
+
+/* The four update coefficients of one axis at one field location. */
+typedef struct {
+    double a, b, pp, pm;
+} or_coef;
 
 static void or_axis_fill(or_axis* ax, int n, int nlo, int nhi, double delta, double dt,
                          const or_problem* p)
@@ -137,10 +150,13 @@ static void or_axis_fill(or_axis* ax, int n, int nlo, int nhi, double delta, dou
     size_t sz = (size_t)(n + 1) * sizeof(double);
     ax->a_n = malloc(sz); ax->b_n = malloc(sz); ax->pp_n = malloc(sz); ax->pm_n = malloc(sz);
     ax->a_h = malloc(sz); ax->b_h = malloc(sz); ax->pp_h = malloc(sz); ax->pm_h = malloc(sz);
+    ax->sig_n = malloc(sz); ax->kap_n = malloc(sz); ax->sig_h = malloc(sz); ax->kap_h = malloc(sz);
     for (int i = 0; i <= n; ++i) {
         for (int half = 0; half < 2; ++half) {
             double s, k;
             or_profile((double)i + 0.5 * half, n, nlo, nhi, delta, p, &s, &k);
+            if (half) { ax->sig_h[i] = s; ax->kap_h[i] = k; }
+            else      { ax->sig_n[i] = s; ax->kap_n[i] = k; }
             double pp = 2.0 * OR_EPS0 * k + s * dt;
             double pm = 2.0 * OR_EPS0 * k - s * dt;
             double a = pm / pp;
@@ -155,6 +171,28 @@ static void or_axis_free(or_axis* ax)
 {
     free(ax->a_n); free(ax->b_n); free(ax->pp_n); free(ax->pm_n);
     free(ax->a_h); free(ax->b_h); free(ax->pp_h); free(ax->pm_h);
+    free(ax->sig_n); free(ax->kap_n); free(ax->sig_h); free(ax->kap_h);
+}
+
+/* Coefficients of axis ax at index i (half: at i + 1/2) seen from a field
+ * location whose relative permittivity is eps_rw: Eq. 2 divides sigma by eps_rw
+ * (the same s-bar enters mu, so H and B use it too).  eps_rw == 1 is the table. */
+static inline __attribute__((always_inline)) or_coef or_at(const or_axis* ax, int i, int half,
+                                                         double eps_rw, double dt)
+{
+    or_coef c;
+    if (eps_rw == 1.0) {
+        if (half) { c.a = ax->a_h[i]; c.b = ax->b_h[i]; c.pp = ax->pp_h[i]; c.pm = ax->pm_h[i]; }
+        else      { c.a = ax->a_n[i]; c.b = ax->b_n[i]; c.pp = ax->pp_n[i]; c.pm = ax->pm_n[i]; }
+        return c;
+    }
+    const double s = (half ? ax->sig_h[i] : ax->sig_n[i]) / eps_rw;
+    const double k = half ? ax->kap_h[i] : ax->kap_n[i];
+    c.pp = 2.0 * OR_EPS0 * k + s * dt;
+    c.pm = 2.0 * OR_EPS0 * k - s * dt;
+    c.a = c.pm / c.pp;
+    c.b = 2.0 * OR_EPS0 * dt / c.pp;
+    return c;
 }
 
 /* Source waveform (Results section, Eq. 8 and the workload's plain Gaussian). */
@@ -204,43 +242,55 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i <= nx; ++i) {
-                    /* Hx(i, j+1/2, k+1/2) */
+                    /* Hx(i, j+1/2, k+1/2); eps_rw: the two cells sharing its x face */
                     size_t c = IX(i, j, k);
+                    const double ew = p->pml_eps_rw ?
+                        0.5 * ((double)er[CELL(i > 0 ? i - 1 : 0, j, k)] +
+                               (double)er[CELL(i < nx ? i : nx - 1, j, k)]) : 1.0;
+                    const or_coef cx = or_at(&X, i, 0, ew, dt), cy = or_at(&Y, j, 1, ew, dt),
+                                  cz = or_at(&Z, k, 1, ew, dt);
                     double curl = (ez[IX(i, j + 1, k)] - ez[c]) * rdy
                                 - (ey[IX(i, j, k + 1)] - ey[c]) * rdz;
                     double bo = Bx[c];
-                    double bn = Y.a_h[j] * bo - Y.b_h[j] * curl;
+                    double bn = cy.a * bo - cy.b * curl;
                     Bx[c] = bn;
-                    hx[c] = Z.a_h[k] * hx[c]
-                          + (X.pp_n[i] * bn - X.pm_n[i] * bo) / (OR_MU0 * Z.pp_h[k]);
+                    hx[c] = cz.a * hx[c] + (cx.pp * bn - cx.pm * bo) / (OR_MU0 * cz.pp);
                 }
 #pragma omp parallel for schedule(static)
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j <= ny; ++j)
                 for (int i = 0; i < nx; ++i) {
-                    /* Hy(i+1/2, j, k+1/2) */
+                    /* Hy(i+1/2, j, k+1/2); eps_rw: the two cells sharing its y face */
                     size_t c = IX(i, j, k);
+                    const double ew = p->pml_eps_rw ?
+                        0.5 * ((double)er[CELL(i, j > 0 ? j - 1 : 0, k)] +
+                               (double)er[CELL(i, j < ny ? j : ny - 1, k)]) : 1.0;
+                    const or_coef cx = or_at(&X, i, 1, ew, dt), cy = or_at(&Y, j, 0, ew, dt),
+                                  cz = or_at(&Z, k, 1, ew, dt);
                     double curl = (ex[IX(i, j, k + 1)] - ex[c]) * rdz
                                 - (ez[IX(i + 1, j, k)] - ez[c]) * rdx;
                     double bo = By[c];
-                    double bn = Z.a_h[k] * bo - Z.b_h[k] * curl;
+                    double bn = cz.a * bo - cz.b * curl;
                     By[c] = bn;
-                    hy[c] = X.a_h[i] * hy[c]
-                          + (Y.pp_n[j] * bn - Y.pm_n[j] * bo) / (OR_MU0 * X.pp_h[i]);
+                    hy[c] = cx.a * hy[c] + (cy.pp * bn - cy.pm * bo) / (OR_MU0 * cx.pp);
                 }
 #pragma omp parallel for schedule(static)
         for (int k = 0; k <= nz; ++k)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
-                    /* Hz(i+1/2, j+1/2, k) */
+                    /* Hz(i+1/2, j+1/2, k); eps_rw: the two cells sharing its z face */
                     size_t c = IX(i, j, k);
+                    const double ew = p->pml_eps_rw ?
+                        0.5 * ((double)er[CELL(i, j, k > 0 ? k - 1 : 0)] +
+                               (double)er[CELL(i, j, k < nz ? k : nz - 1)]) : 1.0;
+                    const or_coef cx = or_at(&X, i, 1, ew, dt), cy = or_at(&Y, j, 1, ew, dt),
+                                  cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (ey[IX(i + 1, j, k)] - ey[c]) * rdx
                                 - (ex[IX(i, j + 1, k)] - ex[c]) * rdy;
                     double bo = Bz[c];
-                    double bn = X.a_h[i] * bo - X.b_h[i] * curl;
+                    double bn = cx.a * bo - cx.b * curl;
                     Bz[c] = bn;
-                    hz[c] = Y.a_h[j] * hz[c]
-                          + (Z.pp_n[k] * bn - Z.pm_n[k] * bo) / (OR_MU0 * Y.pp_h[j]);
+                    hz[c] = cy.a * hz[c] + (cz.pp * bn - cz.pm * bo) / (OR_MU0 * cy.pp);
                 }
 
         /* ---- D then E at n+1 from H at n+1/2 ---- */
@@ -252,16 +302,19 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     /* Ex(i+1/2, j, k) */
                     size_t c = IX(i, j, k);
                     if (pec[c] & 1) { ex[c] = 0.0; continue; }
-                    double eps = OR_EPS0 * 0.25 *
+                    const double er_e = 0.25 *
                         ((double)er[CELL(i, j - 1, k - 1)] + (double)er[CELL(i, j, k - 1)] +
                          (double)er[CELL(i, j - 1, k)] + (double)er[CELL(i, j, k)]);
+                    const double eps = OR_EPS0 * er_e;
+                    const double ew = p->pml_eps_rw ? er_e : 1.0;
+                    const or_coef cx = or_at(&X, i, 1, ew, dt), cy = or_at(&Y, j, 0, ew, dt),
+                                  cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hz[c] - hz[IX(i, j - 1, k)]) * rdy
                                 - (hy[c] - hy[IX(i, j, k - 1)]) * rdz;
                     double d_o = Dx[c];
-                    double d_n = Y.a_n[j] * d_o + Y.b_n[j] * curl;
+                    double d_n = cy.a * d_o + cy.b * curl;
                     Dx[c] = d_n;
-                    ex[c] = Z.a_n[k] * ex[c]
-                          + (X.pp_h[i] * d_n - X.pm_h[i] * d_o) / (eps * Z.pp_n[k]);
+                    ex[c] = cz.a * ex[c] + (cx.pp * d_n - cx.pm * d_o) / (eps * cz.pp);
                 }
 #pragma omp parallel for schedule(static)
         for (int k = 1; k < nz; ++k)
@@ -270,16 +323,19 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     /* Ey(i, j+1/2, k) */
                     size_t c = IX(i, j, k);
                     if (pec[c] & 2) { ey[c] = 0.0; continue; }
-                    double eps = OR_EPS0 * 0.25 *
+                    const double er_e = 0.25 *
                         ((double)er[CELL(i - 1, j, k - 1)] + (double)er[CELL(i, j, k - 1)] +
                          (double)er[CELL(i - 1, j, k)] + (double)er[CELL(i, j, k)]);
+                    const double eps = OR_EPS0 * er_e;
+                    const double ew = p->pml_eps_rw ? er_e : 1.0;
+                    const or_coef cx = or_at(&X, i, 0, ew, dt), cy = or_at(&Y, j, 1, ew, dt),
+                                  cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hx[c] - hx[IX(i, j, k - 1)]) * rdz
                                 - (hz[c] - hz[IX(i - 1, j, k)]) * rdx;
                     double d_o = Dy[c];
-                    double d_n = Z.a_n[k] * d_o + Z.b_n[k] * curl;
+                    double d_n = cz.a * d_o + cz.b * curl;
                     Dy[c] = d_n;
-                    ey[c] = X.a_n[i] * ey[c]
-                          + (Y.pp_h[j] * d_n - Y.pm_h[j] * d_o) / (eps * X.pp_n[i]);
+                    ey[c] = cx.a * ey[c] + (cy.pp * d_n - cy.pm * d_o) / (eps * cx.pp);
                 }
 #pragma omp parallel for schedule(static)
         for (int k = 0; k < nz; ++k)
@@ -288,9 +344,11 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                     /* Ez(i, j, k+1/2) */
                     size_t c = IX(i, j, k);
                     if (pec[c] & 4) { ez[c] = 0.0; continue; }
-                    double eps = OR_EPS0 * 0.25 *
+                    const double er_e = 0.25 *
                         ((double)er[CELL(i - 1, j - 1, k)] + (double)er[CELL(i, j - 1, k)] +
                          (double)er[CELL(i - 1, j, k)] + (double)er[CELL(i, j, k)]);
+                    const double eps = OR_EPS0 * er_e;
+                    const double ew = p->pml_eps_rw ? er_e : 1.0;
                     double J = 0.0, g_l = 0.0;
                     for (int q = 0; q < p->nsrc; ++q)
                         if (p->src_ijk[3 * q] == i && p->src_ijk[3 * q + 1] == j &&
@@ -319,11 +377,12 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                         ez[c] = e_n;
                         continue;
                     }
+                    const or_coef cx = or_at(&X, i, 0, ew, dt), cy = or_at(&Y, j, 0, ew, dt),
+                                  cz = or_at(&Z, k, 1, ew, dt);
                     double d_o = Dz[c];
-                    double d_n = X.a_n[i] * d_o + X.b_n[i] * curl;
+                    double d_n = cx.a * d_o + cx.b * curl;
                     Dz[c] = d_n;
-                    ez[c] = Y.a_n[j] * ez[c]
-                          + (Z.pp_h[k] * d_n - Z.pm_h[k] * d_o) / (eps * Y.pp_n[j]);
+                    ez[c] = cy.a * ez[c] + (cz.pp * d_n - cz.pm * d_o) / (eps * cy.pp);
                 }
 
         /* ---- probes and the running DFT at t = (n+1) dt ---- */

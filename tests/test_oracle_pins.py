@@ -8,6 +8,7 @@
 * P10 the probe FFT against a direct DFT
 * P11 resistive voltage source: discrete energy balance, R -> infinity limits
 * P12 plane-wide DFT: closed form on a cavity eigenmode, agreement with the probe DFT
+* P13 Eq. 2's eps_rw: uniform-medium equivalence, no-op in air, absorption in dielectric
 * Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
 """
 import numpy as np
@@ -531,3 +532,82 @@ def test_p12_plane_dft_equals_probe_dft_on_its_nodes(oracle_mod):
     h1 = oracle_mod.run(b, nsteps=30)
     h2 = oracle_mod.run(b, nsteps=40, state=h1.state, plane_dft=h1.plane_dft)
     assert np.allclose(h2.plane_dft, r.plane_dft, rtol=0, atol=1e-12 * np.abs(r.plane_dft).max())
+
+
+# ---------------------------------------------------------------------------
+# P13  Eq. 2's eps_rw: each PML sigma divided by the relative permittivity at
+# the field location (E, D: the edge; H, B: the face)
+# ---------------------------------------------------------------------------
+
+def _pml_box(eps_r, seed, n=(14, 12, 10), npml=3):
+    nx, ny, nz = n
+    eps, mask = boardgen.air(nx, ny, nz)
+    eps[:] = np.float32(eps_r)
+    return boardgen.Board(f"pmlbox{seed}", nx, ny, nz, 1e-3, 0.8e-3, 0.5e-3, eps, mask,
+                          npml=(npml, npml + 1, npml, npml - 1, npml, npml), steps=40)
+
+
+def test_p13_eps_rw_in_a_uniform_medium_is_sigma_over_eps_r(oracle_mod):
+    """In a medium of uniform eps_r every location sees eps_rw = eps_r, so Eq. 2
+    equals eps_rw = 1 with every sigma divided by eps_r, i.e. sigma_max / eps_r,
+    i.e. a design reflection R^(1/eps_r).  A dropped, squared or inverted eps_rw,
+    or one applied to E but not to H, fails this."""
+    er = 4.0
+    a = _pml_box(er, 1)
+    a.pml_eps_rw = True
+    b = _pml_box(er, 1)
+    b.pml_R = a.pml_R ** (1.0 / er)
+    st_a = _random_state(oracle_mod, a, 3)
+    st_b = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st_a.items()}
+    oracle_mod.run(a, state=st_a)
+    oracle_mod.run(b, state=st_b)
+    for n in oracle_mod.FIELD_NAMES:
+        assert rel_max(st_a[n], st_b[n]) < 1e-12, n
+    # and the scaling is not a no-op here
+    c = _pml_box(er, 1)
+    st_c = _random_state(oracle_mod, c, 3)
+    oracle_mod.run(c, state=st_c)
+    assert rel_max(st_c["ddx"], st_a["ddx"]) > 1e-3
+
+
+def test_p13_eps_rw_is_a_no_op_where_the_pml_is_air(oracle_mod):
+    b = boardgen.random_tiny(40, nx=16, ny=14, nz=12, npml=2, steps=30)
+    p = b.npml
+    b.eps_r_cell[:] = 1.0
+    b.eps_r_cell[p[4] + 1:b.nz - p[5] - 1, p[2] + 1:b.ny - p[3] - 1, p[0] + 1:b.nx - p[1] - 1] = 4.4
+    r0 = oracle_mod.run(b)
+    b.pml_eps_rw = True
+    r1 = oracle_mod.run(b)
+    for n in oracle_mod.FIELD_NAMES:
+        assert np.array_equal(r0.state[n], r1.state[n]), n
+    assert np.array_equal(r0.probes, r1.probes)
+
+
+@pytest.mark.slow
+def test_p13_eps_rw_pml_absorbs_in_dielectric(oracle_mod):
+    """A dielectric (eps_r 4.4) filling the whole domain, PML included: with Eq. 2's
+    eps_rw the reflection seen two cells in front of the PML, against the same
+    geometry in a box large enough to show none, stays below -40 dB (-42.5 dB);
+    with eps_rw = 1 the effective grading is eps_r times steeper and the same
+    layer reflects far more (-31 dB)."""
+    d, er, npml, half_small, half_big = 1e-3, 4.4, 10, 12, 40
+    wave = (boardgen.DGAUSS, 1e6, 40e-12, 10e-12)
+
+    def box(half, rw):
+        n = 2 * half + 2 * npml
+        eps, mask = boardgen.air(n, n, n)
+        eps[:] = np.float32(er)
+        c = n // 2
+        b = boardgen.Board(f"pmldiel{half}", n, n, n, d, d, d, eps, mask, npml=(npml,) * 6,
+                           steps=300, pml_eps_rw=rw)
+        b.sources = [boardgen.Source(c, c, c, *wave)]
+        b.probes = [(c - half_small + 2, c, c)]
+        return b
+
+    def reflection(rw):
+        e = oracle_mod.run(box(half_small, rw), threads=8).probes[0]
+        e_ref = oracle_mod.run(box(half_big, rw), threads=8).probes[0]
+        return 20 * np.log10(np.abs(e - e_ref).max() / np.abs(e_ref).max())
+
+    assert reflection(True) < -40.0
+    assert reflection(False) > -35.0
