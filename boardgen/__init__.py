@@ -371,6 +371,38 @@ def table1_board(steps: int = 30000, air_cells: int = 6, pml_cells: int = 8,
     return b
 
 
+def fig3_board(steps: int = 1000, pml_xy: int = 8, air_z: int = 6, pml_z: int = 8,
+               eps_rw: bool = True) -> Board:
+    """The paper's Fig. 3 case: the 100 x 60 x 0.8 mm board (2 / 2 / 0.4 mm cells,
+    eps_r 4.0 as in Table 1) whose edges run into the UPML: the dielectric and both
+    PEC planes continue through the x/y PML slabs to the outer wall, with air and
+    PML above and below.  dt = 1 ps; the DGAUSS current source (1 A/mm^2, t0 =
+    100 ps, tau = 50 ps) sits at the board centre on the first Ez row above the
+    ground plane, with ground-row Ez probes at the centre offset by one cell, at
+    10 mm and 20 mm along x, and one cell before the x PML.  eps_rw selects
+    Eq. 2's sigma / eps_rw in the PML (the dielectric reaches it here)."""
+    bx, by, nd = 50, 30, 2
+    nx, ny = bx + 2 * pml_xy, by + 2 * pml_xy
+    nz = nd + 2 * air_z + 2 * pml_z
+    eps, mask = air(nx, ny, nz)
+    kg = pml_z + air_z
+    kt = kg + nd
+    fill_box(eps, 0, nx, 0, ny, kg, kt, 4.0)
+    pec_sheet(mask, kg, 0, nx, 0, ny)
+    pec_sheet(mask, kt, 0, nx, 0, ny)
+    b = Board(name="fig3-100x60mm", nx=nx, ny=ny, nz=nz, dx=2e-3, dy=2e-3, dz=0.4e-3,
+              eps_r_cell=eps, pec_edge_mask=mask,
+              npml=(pml_xy, pml_xy, pml_xy, pml_xy, pml_z, pml_z), pml_eps_rw=eps_rw)
+    b.dt = 1e-12
+    ci, cj = nx // 2, ny // 2
+    b.sources = [Source(ci, cj, kg, DGAUSS, 1.0e6, 100e-12, 50e-12)]
+    b.probes = [(ci + 1, cj, kg), (ci + 5, cj, kg), (ci + 10, cj, kg), (nx - pml_xy - 1, cj, kg)]
+    b.steps = steps
+    b.meta = dict(layout=dict(kg=kg, kt=kt, ci=ci, cj=cj))
+    b.check()
+    return b
+
+
 def zconv_board(n_diel: int, steps: int = 4000, n_diel_max: int = 15, air_xy: int = 6,
                 pml: int = 8) -> Board:
     """The z-convergence study of the Results section: the Table 1 board

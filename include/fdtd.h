@@ -89,6 +89,7 @@ typedef struct {
     int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
     int32_t plane_k;             /* plane of the plane DFT, -1 if none */
     int32_t plane_nf;            /* its number of frequencies */
+    int32_t eps_rw_passes;       /* 1: steps run the eps_rw passes (see fdtd_set_pml_eps_rw) */
 } fdtd_info;
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
@@ -152,6 +153,19 @@ int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id);
  * A[p][q] = sum_s e_p[s] exp(-i 2 pi f_q (s+1) dt) dt.  f_hz (host, nf values,
  * each >= 0 and finite), 1 <= nf <= 4096.  ESTATE after the first step. */
 int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
+
+/* Eq. 2's eps_rw (Model section): with on != 0 every PML sigma_w in
+ * s_w = kappa_w + sigma_w / (j w eps0 eps_rw) is divided by the relative
+ * permittivity at the field location: the edge mean of the touching cells for
+ * E and D, the mean of the two cells sharing the face (one on the outer wall)
+ * for H and B, since Eq. 1 puts the same s-bar on mu.  Off (the default),
+ * eps_rw = 1, which is the same wherever the PML holds air (eps_r = 1).  When it
+ * is on and some PML location has eps_r != 1 (a board running into the PML),
+ * steps run two per-node passes (H then E, coefficients rebuilt from kappa and
+ * sigma / eps_rw) instead of the tiled field kernels; fdtd_info.eps_rw_passes
+ * reports it, tile shapes are then ignored, and fdtd_step_many steps such handles
+ * on their own streams.  ESTATE after the first step. */
+int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);
 
 /* Plane DFT: the running DFT of Ez(i, j, k+1/2) over every node of the node plane
  * k (0 <= k < nz; the ground-plane field of the Results section, Figs. 3-5, in the

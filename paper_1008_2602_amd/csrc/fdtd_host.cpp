@@ -30,6 +30,8 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
 int field_step2_occupancy(int tile_y, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
+hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int rel, int flip,
+                           bool wide, hipStream_t st);
 hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
                              double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
                              double* re, double* im, hipStream_t st);
@@ -75,15 +77,19 @@ struct VoltageProbeH {
     int first, count;   // Ez probes first .. first+count-1, one per z cell
 };
 
+// a class: the E edges' 1/eps_r, the flags and (eps_rw passes only) the H faces' 1/eps_r
 struct ClassKey {
-    uint32_t a, b, c, f;
-    bool operator==(const ClassKey& o) const { return a == o.a && b == o.b && c == o.c && f == o.f; }
+    uint32_t a, b, c, f, hx, hy, hz;
+    bool operator==(const ClassKey& o) const
+    {
+        return a == o.a && b == o.b && c == o.c && f == o.f && hx == o.hx && hy == o.hy && hz == o.hz;
+    }
 };
 struct ClassKeyHash {
     size_t operator()(const ClassKey& k) const
     {
         uint64_t h = 1469598103934665603ull;
-        for (uint32_t v : {k.a, k.b, k.c, k.f}) {
+        for (uint32_t v : {k.a, k.b, k.c, k.f, k.hx, k.hy, k.hz}) {
             h ^= v;
             h *= 1099511628211ull;
         }
@@ -119,6 +125,7 @@ struct fdtd_grid {
     float* coef[3] = {};
     void* cls = nullptr;
     ClassEntry* ctab = nullptr;
+    float* hface = nullptr;
     int32_t* src_node = nullptr;
     float* src_j = nullptr;
     float* src_beta = nullptr;
@@ -152,6 +159,8 @@ struct fdtd_grid {
     std::vector<VoltageProbeH> vprobes;
     std::vector<double> freqs;
     int plane_k = -1;               // plane-DFT node plane, -1: none
+    bool pml_eps_rw = false;        // Eq. 2's eps_rw requested
+    bool eps_pass = false;          // ... and some PML location has eps_r != 1: per-node passes
     std::vector<double> plane_freqs;
     int n_classes = 0;
     bool wide = false;
@@ -399,7 +408,7 @@ std::vector<float> coef_table(const fdtd_grid_desc& d, int axis, double dt)
             profile(d, i + 0.5 * half, n, nlo, nhi, delta, &s, &k);
             const double q = s * dt / kEps0;
             const double ph = k + 0.5 * q;
-            const double v[kNumCoef] = {-q / ph, (k - 0.5 * q) / ph, 1.0 / ph, ph, q};
+            const double v[kNumCoef] = {-q / ph, (k - 0.5 * q) / ph, 1.0 / ph, ph, q, k};
             for (int c = 0; c < kNumCoef; ++c)
                 t[((size_t)c * 2 + half) * (n + 1) + i] = (float)v[c];
         }
@@ -492,8 +501,13 @@ int finalize(fdtd_grid* g)
     auto cell = [&](int i, int j, int k) -> double {
         return (double)er[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
     };
-    ClassKey last{~0u, ~0u, ~0u, ~0u};
+    ClassKey last{~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u};
     uint32_t last_id = 0;
+    // eps_rw passes: 1/eps_r at the H faces of each class (two cells share a face;
+    // one on the outer wall), and whether any PML location has eps_r != 1
+    std::vector<float> hface;
+    auto in_slab = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
+    g->eps_pass = false;
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
@@ -519,7 +533,22 @@ int finalize(fdtd_grid* g)
                 if (mark[n] & 1) fl |= kSrcEz;
                 if (mark[n] & 2) fl |= kPrbEz;
                 if (k == g->plane_k) fl |= kPlnEz;
-                const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl};
+                float fx = 1.f, fy = 1.f, fz = 1.f;
+                if (g->pml_eps_rw) {
+                    if (j < ny && k < nz)
+                        fx = (float)(2.0 / (cell(i > 0 ? i - 1 : 0, j, k) + cell(i < nx ? i : nx - 1, j, k)));
+                    if (i < nx && k < nz)
+                        fy = (float)(2.0 / (cell(i, j > 0 ? j - 1 : 0, k) + cell(i, j < ny ? j : ny - 1, k)));
+                    if (i < nx && j < ny)
+                        fz = (float)(2.0 / (cell(i, j, k > 0 ? k - 1 : 0) + cell(i, j, k < nz ? k : nz - 1)));
+                    const bool slab = in_slab(i, nx, d.npml[0], d.npml[1]) ||
+                                      in_slab(j, ny, d.npml[2], d.npml[3]) ||
+                                      in_slab(k, nz, d.npml[4], d.npml[5]);
+                    if (slab && (((fl & kUpdEx) && ix != 1.f) || ((fl & kUpdEy) && iy != 1.f) ||
+                                 ((fl & kUpdEz) && iz != 1.f) || fx != 1.f || fy != 1.f || fz != 1.f))
+                        g->eps_pass = true;
+                }
+                const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz)};
                 uint32_t id;
                 if (key == last) {
                     id = last_id;
@@ -533,6 +562,7 @@ int finalize(fdtd_grid* g)
                         id = (uint32_t)table.size();
                         map.emplace(key, id);
                         table.push_back(ClassEntry{ix, iy, iz, fl});
+                        hface.insert(hface.end(), {fx, fy, fz});
                     } else {
                         id = it->second;
                     }
@@ -561,6 +591,12 @@ int finalize(fdtd_grid* g)
     if (!g->ctab) return fail(FDTD_ENOMEM, "class table allocation failed");
     HIP_OR_FAIL(hipMemcpyAsync(g->ctab, table.data(), table.size() * sizeof(ClassEntry),
                                hipMemcpyHostToDevice, st));
+    if (g->eps_pass) {
+        g->hface = (float*)dev_alloc(g, hface.size() * 4);
+        if (!g->hface) return fail(FDTD_ENOMEM, "face table allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->hface, hface.data(), hface.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(st));   // table and hface are locals
 
     // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt.  A resistive
     // voltage source (R > 0) carries its Norton current c0 dt eta0 V_s / (R dx dy)
@@ -634,6 +670,7 @@ int finalize(fdtd_grid* g)
     }
     b.cls = g->cls;
     b.ctab = g->ctab;
+    b.hface = g->hface;
     b.src_node = g->src_node;
     b.src_j = g->src_j;
     b.src_beta = g->src_beta;
@@ -910,6 +947,14 @@ int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id)
     return FDTD_OK;
 }
 
+int fdtd_set_pml_eps_rw(fdtd_grid* g, int on)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "eps_rw is fixed after the first step");
+    g->pml_eps_rw = on != 0;
+    return FDTD_OK;
+}
+
 int fdtd_set_plane_dft(fdtd_grid* g, int k, const double* f_hz, int nf)
 {
     if (int e = check_grid(g)) return e;
@@ -1037,6 +1082,21 @@ static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
 // one single step when n is odd); returns the launch count through *launches.
 static int enqueue_steps(fdtd_grid* g, int64_t n, int64_t* launches)
 {
+    if (g->eps_pass) {
+        // eps_rw boards: one H pass and one E pass per step (one buffer flip)
+        for (int64_t s = 0; s < n; ++s) {
+            if (g->timing)
+                if (int e = record_event(g)) return e;
+            HIP_OR_FAIL(launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, (int)s, (int)(s & 1),
+                                        g->wide, g->stream));
+            if (g->timing) {
+                if (int e = record_event(g)) return e;
+                ++g->timed_launches;
+            }
+        }
+        *launches = n;
+        return FDTD_OK;
+    }
     const int per = g->tile_steps;
     int64_t l = 0, s = 0;
     for (; s + per <= n; s += per, ++l)
@@ -1059,10 +1119,13 @@ static void build_graph(fdtd_grid* g)
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
     bool ok = true;
-    const int per = g->tile_steps, nl = kGraphChunk / per;
+    const int per = g->eps_pass ? 1 : g->tile_steps, nl = kGraphChunk / per;
     for (int l = 0; l < nl && ok; ++l)
-        ok = launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev, g->ntiles, l * per,
-                         l & 1, g->wide, g->plane_k >= 0, g->stream) == hipSuccess;
+        ok = (g->eps_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, l, l & 1, g->wide,
+                                            g->stream)
+                          : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
+                                        g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
+                                        g->stream)) == hipSuccess;
     if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, nl, g->stream) == hipSuccess;
     if (ok) ok = fold_plane(g, -kGraphChunk, 0, g->stream) == FDTD_OK;
     const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
@@ -1090,7 +1153,7 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
         if (g->graph_exec) {
             for (; done + kGraphChunk <= n; done += kGraphChunk) {
                 HIP_OR_FAIL(hipGraphLaunch(g->graph_exec, g->stream));
-                launches += kGraphChunk / g->tile_steps;
+                launches += kGraphChunk / (g->eps_pass ? 1 : g->tile_steps);
             }
         }
     }
@@ -1137,6 +1200,22 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     for (int h = 0; h < ng; ++h)
         if (int e = finalize(gs[h])) return e;
+    // boards on the eps_rw passes step alone (on their own streams); the rest
+    // share the batched launches
+    std::vector<fdtd_grid*> fused;
+    std::vector<int64_t> nfused;
+    for (int h = 0; h < ng; ++h) {
+        if (gs[h]->eps_pass) {
+            if (int e = fdtd_step_n(gs[h], n[h])) return e;
+        } else {
+            fused.push_back(gs[h]);
+            nfused.push_back(n[h]);
+        }
+    }
+    if (fused.size() < (size_t)ng) {
+        if (fused.empty()) return FDTD_OK;
+        return fdtd_step_many(fused.data(), (int)fused.size(), nfused.data());
+    }
     bool planes = false;
     for (int h = 0; h < ng; ++h) planes |= gs[h]->plane_k >= 0;
     if (!planes) return step_many_round(gs, ng, n);
@@ -1622,6 +1701,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->tile_steps = g->tile_steps;
     out->plane_k = g->plane_k;
     out->plane_nf = (int32_t)g->plane_freqs.size();
+    out->eps_rw_passes = g->eps_pass ? 1 : 0;
     return FDTD_OK;
 }
 

@@ -35,8 +35,9 @@ static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly o
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;
 
-// per-axis coefficient table: 5 quantities x {node, half node} x (n+1) entries
-enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kNumCoef = 5 };
+// per-axis coefficient table: 6 quantities x {node, half node} x (n+1) entries
+// (kappa is read only by the eps_rw passes, which rebuild the others from it)
+enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kKappa = 5, kNumCoef = 6 };
 
 // class flags (per node): which E components are stepped, and source/probe marks
 // (kPlnEz: the node lies on the plane-DFT plane, its Ez goes to the sample ring)
@@ -57,6 +58,7 @@ struct BoardDev {
     float* d[2][3];
     const void* cls;             // uint8_t or uint16_t per node
     const ClassEntry* ctab;
+    const float* hface;          // eps_rw passes: per class, 1/eps_r at the Hx, Hy, Hz faces
     const float* coef[3];        // per axis: [kind][node/half][n+1]
     const int32_t* src_node;     // node index of each source's Ez edge
     const float* src_j;          // [nsrc][max_steps] Js samples

@@ -1,0 +1,244 @@
+// Leapfrog step with Eq. 2's eps_rw for boards whose dielectric reaches into a
+// PML slab: every sigma_w in s_w = kappa_w + sigma_w / (j w eps0 eps_rw) is
+// divided by the relative permittivity at the field location, so the update
+// coefficients of a PML node depend on its material as well as its position.
+// Two plain per-node passes (B then H, D then E) recompute each axis's five
+// coefficients from kappa and q / eps_rw; they share the fused kernels' layout,
+// buffers, class flags, sources, probes and plane ring, and run only for those
+// boards (all other boards take the fused field kernels).
+#include "fdtd_device.h"
+#include "fdtd_internal.h"
+
+namespace fdtd {
+
+namespace {
+
+struct Sc {
+    float cam1, ca, rp, ph, q;
+};
+
+// Coefficients of one axis at table index idx (node or half node) for a field
+// location of inverse relative permittivity inv_eps (q scaled by 1/eps_rw).
+__device__ __forceinline__ Sc sc_at(cgfloat* tab, int n1, int half, int idx, float inv_eps)
+{
+    const float q = tab[(kQ * 2 + half) * n1 + idx] * inv_eps;
+    const float kap = tab[(kKappa * 2 + half) * n1 + idx];
+    Sc s;
+    s.q = q;
+    s.ph = fmaf(0.5f, q, kap);
+    s.rp = 1.0f / s.ph;
+    s.ca = fmaf(-0.5f, q, kap) * s.rp;
+    s.cam1 = -q * s.rp;
+    return s;
+}
+
+struct NodeCtx {
+    int i, j, k, nx, ny, nz, sy, sz;
+    uint32_t nb;         // byte offset of the node
+    bool px, py, pz;     // node inside the x / y / z PML slab (D, B kept)
+    int par;
+};
+
+__device__ __forceinline__ bool node_ctx(const BoardDev& B, int flip, NodeCtx& c)
+{
+    c.i = blockIdx.x * blockDim.x + threadIdx.x;
+    c.j = blockIdx.y * blockDim.y + threadIdx.y;
+    c.k = blockIdx.z;
+    c.nx = B.nx;
+    c.ny = B.ny;
+    c.nz = B.nz;
+    if (c.i > c.nx || c.j > c.ny || c.k > c.nz) return false;
+    c.sy = B.pitch;
+    c.sz = B.pitch * (c.ny + 1);
+    c.nb = (uint32_t)(c.i + c.j * c.sy + c.k * c.sz) * 4u;
+    c.px = (c.i < B.pml[0]) || (B.pml[1] > 0 && c.i >= c.nx - B.pml[1]);
+    c.py = (c.j < B.pml[2]) || (B.pml[3] > 0 && c.j >= c.ny - B.pml[3]);
+    c.pz = (c.k < B.pml[4]) || (B.pml[5] > 0 && c.k >= c.nz - B.pml[5]);
+    c.par = (int)((B.step[1] + flip) & 1);
+    return true;
+}
+
+template <typename CT>
+__device__ __forceinline__ int class_of(const BoardDev& B, uint32_t nb)
+{
+    return (int)ld_at_t<CT>(B.cls, sizeof(CT) == 1 ? nb >> 2 : nb >> 1);
+}
+
+}  // namespace
+
+// B then H of every node from E at step n (buffer par) into buffer par ^ 1.
+template <typename CT>
+__global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ board, int flip)
+{
+    const BoardDev& B = *board;
+    NodeCtx c;
+    if (!node_ctx(B, flip, c)) return;
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride, nb = c.nb;
+    const uint32_t dyb = (uint32_t)c.sy * 4u, dzb = (uint32_t)c.sz * 4u;
+    const float* gE = B.f[c.par][0];
+    const float* gH = B.f[c.par][3];
+    const float* gB = B.f[c.par][6];
+    float* dH = B.f[c.par ^ 1][3];
+    float* dB = B.f[c.par ^ 1][6];
+    cgfloat* cx = (cgfloat*)B.coef[0];
+    cgfloat* cy = (cgfloat*)B.coef[1];
+    cgfloat* cz = (cgfloat*)B.coef[2];
+    const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
+    const int id = class_of<CT>(B, nb);
+    cgfloat* hf = (cgfloat*)B.hface + 3 * id;   // inverse eps_r at the Hx, Hy, Hz faces
+    const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
+    const int i = c.i, j = c.j, k = c.k;
+
+    // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i
+    float hx = 0.f;
+    if (j < c.ny && k < c.nz) {
+        const float ezo = ld_at(gE, nb + cs2), eyo = ld_at(gE, nb + cs);
+        const float cxe = (ld_at(gE, nb + dyb + cs2) - ezo) * crdy - (ld_at(gE, nb + dzb + cs) - eyo) * crdz;
+        const float inv = hf[0];
+        const Sc Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 0, i, inv);
+        const bool keep = c.px || c.py;
+        const float bo = keep ? ld_at(gB, nb) : 0.f;
+        const float db = fmaf(Y.cam1, bo, -Y.rp * cxe);
+        hx = fmaf(Z.ca, ld_at(gH, nb), Z.rp * fmaf(X.ph, db, X.q * bo));
+        if (keep) st_at(dB, nb, bo + db);
+    }
+    st_at(dH, nb, hx);
+    // Hy(i+1/2, j, k+1/2): By with z at k+1/2; Hy with x at i+1/2, y at j
+    float hy = 0.f;
+    if (i < c.nx && k < c.nz) {
+        const float exo = ld_at(gE, nb), ezo = ld_at(gE, nb + cs2);
+        const float cye = (ld_at(gE, nb + dzb) - exo) * crdz - (ld_at(gE, nb + 4u + cs2) - ezo) * crdx;
+        const float inv = hf[1];
+        const Sc Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 0, j, inv);
+        const bool keep = c.py || c.pz;
+        const float bo = keep ? ld_at(gB, nb + cs) : 0.f;
+        const float db = fmaf(Z.cam1, bo, -Z.rp * cye);
+        hy = fmaf(X.ca, ld_at(gH, nb + cs), X.rp * fmaf(Y.ph, db, Y.q * bo));
+        if (keep) st_at(dB, nb + cs, bo + db);
+    }
+    st_at(dH, nb + cs, hy);
+    // Hz(i+1/2, j+1/2, k): Bz with x at i+1/2; Hz with y at j+1/2, z at k
+    float hz = 0.f;
+    if (i < c.nx && j < c.ny) {
+        const float exo = ld_at(gE, nb), eyo = ld_at(gE, nb + cs);
+        const float cze = (ld_at(gE, nb + 4u + cs) - eyo) * crdx - (ld_at(gE, nb + dyb) - exo) * crdy;
+        const float inv = hf[2];
+        const Sc X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 0, k, inv);
+        const bool keep = c.pz || c.px;
+        const float bo = keep ? ld_at(gB, nb + cs2) : 0.f;
+        const float db = fmaf(X.cam1, bo, -X.rp * cze);
+        hz = fmaf(Y.ca, ld_at(gH, nb + cs2), Y.rp * fmaf(Z.ph, db, Z.q * bo));
+        if (keep) st_at(dB, nb + cs2, bo + db);
+    }
+    st_at(dH, nb + cs2, hz);
+}
+
+// D then E of every node from H at n+1/2 (buffer par ^ 1, written by the H
+// pass) and E, D at n (buffer par) into buffer par ^ 1, with the sources,
+// probes, plane ring and watchdog of the fused kernels.
+template <typename CT>
+__global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ board, int rel, int flip)
+{
+    const BoardDev& B = *board;
+    NodeCtx c;
+    if (!node_ctx(B, flip, c)) return;
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride, nb = c.nb;
+    const uint32_t dyb = (uint32_t)c.sy * 4u, dzb = (uint32_t)c.sz * 4u;
+    const float* gE = B.f[c.par][0];
+    const float* gD = B.d[c.par][0];
+    const float* nH = B.f[c.par ^ 1][3];
+    float* dE = B.f[c.par ^ 1][0];
+    float* dD = B.d[c.par ^ 1][0];
+    cgfloat* cx = (cgfloat*)B.coef[0];
+    cgfloat* cy = (cgfloat*)B.coef[1];
+    cgfloat* cz = (cgfloat*)B.coef[2];
+    const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
+    const int id = class_of<CT>(B, nb);
+    const __attribute__((address_space(1))) ClassEntry* ctab =
+        (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
+    const float inv_x = ctab[id].inv_x, inv_y = ctab[id].inv_y, inv_z = ctab[id].inv_z;
+    const uint32_t flags = ctab[id].flags;
+    const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
+    const int i = c.i, j = c.j, k = c.k;
+    const int64_t step = B.step[0] + rel;
+    const int64_t ms = B.max_steps;
+
+    const bool kx = c.px || c.py, ky = c.py || c.pz, kz = c.pz || c.px;   // D kept
+    const float dxo = kx ? ld_at(gD, nb) : 0.f;
+    const float dyo = ky ? ld_at(gD, nb + cs) : 0.f;
+    const float dzo = kz ? ld_at(gD, nb + cs2) : 0.f;
+    float exn = 0.f, eyn = 0.f, ezn = 0.f, ddx = 0.f, ddy = 0.f, ddz = 0.f;
+    // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
+    if (flags & kUpdEx) {
+        const float chx = (ld_at(nH, nb + cs2) - ld_at(nH, nb - dyb + cs2)) * crdy -
+                          (ld_at(nH, nb + cs) - ld_at(nH, nb - dzb + cs)) * crdz;
+        const Sc Y = sc_at(cy, ny1, 0, j, inv_x), Z = sc_at(cz, nz1, 0, k, inv_x), X = sc_at(cx, nx1, 1, i, inv_x);
+        ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
+        exn = fmaf(Z.ca, ld_at(gE, nb), Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
+    }
+    // Ey(i, j+1/2, k): Dy with z at k; Ey with x at i, y at j+1/2
+    if (flags & kUpdEy) {
+        const float chy = (ld_at(nH, nb) - ld_at(nH, nb - dzb)) * crdz -
+                          (ld_at(nH, nb + cs2) - ld_at(nH, nb - 4u + cs2)) * crdx;
+        const Sc Z = sc_at(cz, nz1, 0, k, inv_y), X = sc_at(cx, nx1, 0, i, inv_y), Y = sc_at(cy, ny1, 1, j, inv_y);
+        ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
+        eyn = fmaf(X.ca, ld_at(gE, nb + cs), X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
+    }
+    // Ez(i, j, k+1/2): Dz with x at i; Ez with y at j, z at k+1/2
+    if (flags & kUpdEz) {
+        float chz = (ld_at(nH, nb + cs) - ld_at(nH, nb - 4u + cs)) * crdx -
+                    (ld_at(nH, nb) - ld_at(nH, nb - dyb)) * crdy;
+        float bs = 0.f;
+        if (flags & kSrcEz) {
+            const int node = (int)(nb >> 2);
+            const __attribute__((address_space(1))) int32_t* sn =
+                (const __attribute__((address_space(1))) int32_t*)B.src_node;
+            float js = 0.f;
+            for (int q = 0; q < B.nsrc; ++q)
+                if (sn[q] == node) {
+                    js += B.src_j[q * ms + step];
+                    bs += B.src_beta[q];
+                }
+            chz -= js;
+        }
+        const Sc X = sc_at(cx, nx1, 0, i, inv_z), Y = sc_at(cy, ny1, 0, j, inv_z), Z = sc_at(cz, nz1, 1, k, inv_z);
+        const float ezo = ld_at(gE, nb + cs2);
+        ddz = fmaf(X.cam1, dzo, X.rp * chz);
+        ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
+        if (bs != 0.0f) ezn = resistive_ez(ezo, chz, inv_z, bs);
+    }
+    st_at(dE, nb, exn);
+    st_at(dE, nb + cs, eyn);
+    st_at(dE, nb + cs2, ezn);
+    if (kx) st_at(dD, nb, dxo + ddx);
+    if (ky) st_at(dD, nb + cs, dyo + ddy);
+    if (kz) st_at(dD, nb + cs2, dzo + ddz);
+    if (flags & kPrbEz) {
+        const int node = (int)(nb >> 2);
+        const __attribute__((address_space(1))) int32_t* pn =
+            (const __attribute__((address_space(1))) int32_t*)B.prb_node;
+        gfloat* ps = (gfloat*)B.prb_series;
+        for (int q = 0; q < B.nprb; ++q)
+            if (pn[q] == node) ps[q * ms + step] = ezn;
+    }
+    if (flags & kPlnEz)
+        st_at(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * dzb + (nb - (uint32_t)k * dzb), ezn);
+    if (!isfinite(exn + eyn + ezn)) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
+}
+
+hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int rel, int flip,
+                           bool wide, hipStream_t st)
+{
+    const dim3 block(64, 4);
+    const dim3 grid((unsigned)((nx + 1 + 63) / 64), (unsigned)((ny + 1 + 3) / 4), (unsigned)(nz + 1));
+    if (wide) {
+        hipLaunchKernelGGL(eps_h_pass<uint16_t>, grid, block, 0, st, board, flip);
+        hipLaunchKernelGGL(eps_e_pass<uint16_t>, grid, block, 0, st, board, rel, flip);
+    } else {
+        hipLaunchKernelGGL(eps_h_pass<uint8_t>, grid, block, 0, st, board, flip);
+        hipLaunchKernelGGL(eps_e_pass<uint8_t>, grid, block, 0, st, board, rel, flip);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdtd

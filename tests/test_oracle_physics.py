@@ -228,3 +228,26 @@ def test_x2_z_convergence_of_the_plane_field(oracle_mod):
         assert m[1][0][p] > m[2][0][p] > m[4][0][p]
     assert m[2][0].max() < 5e-3
     assert m[2][1][2] < 1e-3          # far-corner peak
+
+
+def test_p14_fig3_board_into_upml_decays_fig4_air_gap_rings(oracle_mod):
+    """Results section, Figs. 3 and 4: with the board's edges running into the UPML
+    (dielectric and planes through the PML, Eq. 2's eps_rw) the ground-plane wave
+    leaves the board and has all but died by about 600 ps (every probe below 5 %
+    of its peak after 600 ps); with an air layer between board and UPML the wave
+    reflects at the dielectric/air edge and the resonance persists (every probe
+    still above 40 % of its peak after 600 ps)."""
+    b3 = boardgen.fig3_board(steps=1000)
+    r3 = oracle_mod.run(b3, threads=8)
+    b4, lay = boardgen.plane_stack("fig4", (50, 30), 2, 6, 8, 6, 6, 8, 2e-3, 2e-3, 0.4e-3, 4.0)
+    b4.dt = 1e-12
+    ci, cj, kg = (lay["bi0"] + lay["bi1"]) // 2, (lay["bj0"] + lay["bj1"]) // 2, lay["kg"]
+    b4.sources = [boardgen.Source(ci, cj, kg, boardgen.DGAUSS, 1e6, 100e-12, 50e-12)]
+    b4.probes = [(ci + 1, cj, kg), (ci + 5, cj, kg), (ci + 10, cj, kg), (lay["bi1"] - 1, cj, kg)]
+    r4 = oracle_mod.run(b4, nsteps=1000, threads=8)
+    t = (np.arange(1000) + 1) * 1e-12
+    late = t > 600e-12
+    for p in range(4):
+        e3, e4 = r3.probes[p], r4.probes[p]
+        assert np.abs(e3[late]).max() < 0.05 * np.abs(e3).max(), p
+        assert np.abs(e4[late]).max() > 0.4 * np.abs(e4).max(), p
