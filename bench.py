@@ -19,6 +19,8 @@ Beside it, the same line carries
     short; the number is stated in the output;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
+  * "eps_rw": Eq. 2's eps_rw passes on the large board run into the PML, and
+    the paper's Fig. 3 board;
   * "zconv": the z-convergence study (1..15 cells across the dielectric) as
     one batched call;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
@@ -26,10 +28,11 @@ Beside it, the same line carries
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1|plane|zconv]
+                  [--only single|batch|serve|table1|plane|zconv|eps]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -163,6 +166,54 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
         "fold_bytes_per_launch": int(plane_nodes * (32 * 4 + nf * 32)),
         "ring_store_bytes_per_step": int(plane_nodes * 4),
     }
+
+
+def run_eps(F, torch, K=200, W=10):
+    """Eq. 2's eps_rw passes.  (1) The large board with its eps_r 4.2 slab run
+    through the x/y PML to the outer wall (1048x792x88), eps_rw on: the per-node
+    H and E passes, against the fused kernels on the same board with eps_rw = 1;
+    (2) the paper's Fig. 3 board (100x60x0.8 mm running into the UPML), 1000 steps
+    of 1 ps."""
+    import boardgen
+    from paper_1008_2602_amd import tune
+    b = boardgen.large_board(steps=W + K)
+    kg, kt = b.meta["layout"]["kg"], b.meta["layout"]["kt"]
+    b.eps_r_cell[kg:kt, :, :] = 4.2
+    b.sources, b.probes, b.dft_freqs = b.sources, b.probes[:4], None
+    out = {}
+    for rw in (True, False):
+        bb = dataclasses.replace(b, pml_eps_rw=rw)
+        tile = tune.tune_board(bb) if not rw else None
+        g, _ = F.grid_from_board(bb, max_steps=W + K, tile=tile)
+        F.fdtd_step_n(g, W)
+        F.fdtd_synchronize(g)
+        t0 = time.perf_counter()
+        F.fdtd_step_n(g, K)
+        F.fdtd_synchronize(g)
+        wall = time.perf_counter() - t0
+        info = F.fdtd_get_info(g)
+        F.fdtd_destroy_grid(g)
+        assert info.eps_rw_passes == (1 if rw else 0)
+        out["eps_rw" if rw else "fused_eps_rw_1"] = {
+            "ms_per_step": round(wall / K * 1e3, 4),
+            "gcell_updates_per_s": round(b.cells * K / wall / 1e9, 3),
+            "hbm_frac_algorithmic": round(info.step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
+        }
+    f3 = boardgen.fig3_board(steps=1000)
+    g, _ = F.grid_from_board(f3, max_steps=f3.steps)
+    F.fdtd_step_n(g, 0)
+    F.fdtd_synchronize(g)
+    t0 = time.perf_counter()
+    F.fdtd_step_n(g, f3.steps)
+    F.fdtd_synchronize(g)
+    wall = time.perf_counter() - t0
+    F.fdtd_destroy_grid(g)
+    out["fig3"] = {"cells": f3.cells, "steps": f3.steps, "wall_s": round(wall, 4),
+                   "gcell_updates_per_s": round(f3.cells * f3.steps / wall / 1e9, 3)}
+    out["workload"] = ("large board 1048x792x88 with its eps_r 4.2 slab through the x/y PML "
+                       "(eps_rw passes vs the fused kernels at eps_rw = 1); Fig. 3 board "
+                       f"{f3.nx}x{f3.ny}x{f3.nz} running into the UPML, 1000 steps")
+    return out
 
 
 def run_zconv(F, torch, steps=4000):
@@ -371,8 +422,8 @@ def main():
     ap.add_argument("--tile", default="",
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
-    ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv"],
-                    default=None)
+    ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
+                                       "eps"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -457,6 +508,8 @@ def main():
             _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
+    if args.only in (None, "eps"):
+        out["eps_rw"] = run_eps(F, torch)
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
     if args.only in (None, "table1"):

@@ -2,10 +2,13 @@
 // PML slab: every sigma_w in s_w = kappa_w + sigma_w / (j w eps0 eps_rw) is
 // divided by the relative permittivity at the field location, so the update
 // coefficients of a PML node depend on its material as well as its position.
-// Two plain per-node passes (B then H, D then E) recompute each axis's five
-// coefficients from kappa and q / eps_rw; they share the fused kernels' layout,
-// buffers, class flags, sources, probes and plane ring, and run only for those
-// boards (all other boards take the fused field kernels).
+// Two plain passes (B then H, D then E; one thread per (i, j) column marching
+// up in z) recompute each axis's five coefficients from kappa and q / eps_rw;
+// they share the fused kernels' layout, buffers, class flags, sources, probes
+// and plane ring, and run only for those boards (all other boards take the
+// fused field kernels).
+#include <algorithm>
+
 #include "fdtd_device.h"
 #include "fdtd_internal.h"
 
@@ -32,30 +35,35 @@ __device__ __forceinline__ Sc sc_at(cgfloat* tab, int n1, int half, int idx, flo
     return s;
 }
 
-struct NodeCtx {
-    int i, j, k, nx, ny, nz, sy, sz;
-    uint32_t nb;         // byte offset of the node
-    bool px, py, pz;     // node inside the x / y / z PML slab (D, B kept)
+struct ColCtx {
+    int i, j, nx, ny, nz, sy, sz, k0, k1;   // planes k0 .. k1-1
+    uint32_t nb0;        // byte offset of node (i, j, 0)
+    bool px, py;         // column inside the x / y PML slab
     int par;
 };
 
-__device__ __forceinline__ bool node_ctx(const BoardDev& B, int flip, NodeCtx& c)
+// One thread per (i, j) column and z chunk of zl planes, marching up in z.
+__device__ __forceinline__ bool col_ctx(const BoardDev& B, int flip, ColCtx& c)
 {
     c.i = blockIdx.x * blockDim.x + threadIdx.x;
     c.j = blockIdx.y * blockDim.y + threadIdx.y;
-    c.k = blockIdx.z;
     c.nx = B.nx;
     c.ny = B.ny;
     c.nz = B.nz;
-    if (c.i > c.nx || c.j > c.ny || c.k > c.nz) return false;
+    if (c.i > c.nx || c.j > c.ny) return false;
     c.sy = B.pitch;
     c.sz = B.pitch * (c.ny + 1);
-    c.nb = (uint32_t)(c.i + c.j * c.sy + c.k * c.sz) * 4u;
+    c.nb0 = (uint32_t)(c.i + c.j * c.sy) * 4u;
     c.px = (c.i < B.pml[0]) || (B.pml[1] > 0 && c.i >= c.nx - B.pml[1]);
     c.py = (c.j < B.pml[2]) || (B.pml[3] > 0 && c.j >= c.ny - B.pml[3]);
-    c.pz = (c.k < B.pml[4]) || (B.pml[5] > 0 && c.k >= c.nz - B.pml[5]);
     c.par = (int)((B.step[1] + flip) & 1);
     return true;
+}
+
+__device__ __forceinline__ void col_chunk(int zl, ColCtx& c)
+{
+    c.k0 = blockIdx.z * zl;
+    c.k1 = min(c.k0 + zl, c.nz + 1);
 }
 
 template <typename CT>
@@ -67,13 +75,15 @@ __device__ __forceinline__ int class_of(const BoardDev& B, uint32_t nb)
 }  // namespace
 
 // B then H of every node from E at step n (buffer par) into buffer par ^ 1.
+// E_x, E_y of plane k+1 carry over as plane k of the next iteration.
 template <typename CT>
-__global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ board, int flip)
+__global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ board, int flip, int zl)
 {
     const BoardDev& B = *board;
-    NodeCtx c;
-    if (!node_ctx(B, flip, c)) return;
-    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride, nb = c.nb;
+    ColCtx c;
+    if (!col_ctx(B, flip, c)) return;
+    col_chunk(zl, c);
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride;
     const uint32_t dyb = (uint32_t)c.sy * 4u, dzb = (uint32_t)c.sz * 4u;
     const float* gE = B.f[c.par][0];
     const float* gH = B.f[c.par][3];
@@ -84,65 +94,78 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
     cgfloat* cy = (cgfloat*)B.coef[1];
     cgfloat* cz = (cgfloat*)B.coef[2];
     const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
-    const int id = class_of<CT>(B, nb);
-    cgfloat* hf = (cgfloat*)B.hface + 3 * id;   // inverse eps_r at the Hx, Hy, Hz faces
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
-    const int i = c.i, j = c.j, k = c.k;
-
-    // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i
-    float hx = 0.f;
-    if (j < c.ny && k < c.nz) {
-        const float ezo = ld_at(gE, nb + cs2), eyo = ld_at(gE, nb + cs);
-        const float cxe = (ld_at(gE, nb + dyb + cs2) - ezo) * crdy - (ld_at(gE, nb + dzb + cs) - eyo) * crdz;
-        const float inv = hf[0];
-        const Sc Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 0, i, inv);
-        const bool keep = c.px || c.py;
-        const float bo = keep ? ld_at(gB, nb) : 0.f;
-        const float db = fmaf(Y.cam1, bo, -Y.rp * cxe);
-        hx = fmaf(Z.ca, ld_at(gH, nb), Z.rp * fmaf(X.ph, db, X.q * bo));
-        if (keep) st_at(dB, nb, bo + db);
+    const int i = c.i, j = c.j;
+    const bool hasx = j < c.ny, hasy = i < c.nx, hasz = i < c.nx && j < c.ny;
+    float exo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb), eyo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb + cs);
+    for (int k = c.k0; k < c.k1; ++k) {
+        const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
+        const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
+        const float ezo = ld_at(gE, nb + cs2);
+        float exu = 0.f, eyu = 0.f;
+        if (k < c.nz) {
+            exu = ld_at(gE, nb + dzb);
+            eyu = ld_at(gE, nb + dzb + cs);
+        }
+        const int id = class_of<CT>(B, nb);
+        cgfloat* hf = (cgfloat*)B.hface + 3 * id;   // inverse eps_r at the Hx, Hy, Hz faces
+        // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i
+        float hx = 0.f;
+        if (hasx && k < c.nz) {
+            const float cxe = (ld_at(gE, nb + dyb + cs2) - ezo) * crdy - (eyu - eyo) * crdz;
+            const float inv = hf[0];
+            const Sc Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 0, i, inv);
+            const bool keep = c.px || c.py;
+            const float bo = keep ? ld_at(gB, nb) : 0.f;
+            const float db = fmaf(Y.cam1, bo, -Y.rp * cxe);
+            hx = fmaf(Z.ca, ld_at(gH, nb), Z.rp * fmaf(X.ph, db, X.q * bo));
+            if (keep) st_at(dB, nb, bo + db);
+        }
+        st_at(dH, nb, hx);
+        // Hy(i+1/2, j, k+1/2): By with z at k+1/2; Hy with x at i+1/2, y at j
+        float hy = 0.f;
+        if (hasy && k < c.nz) {
+            const float cye = (exu - exo) * crdz - (ld_at(gE, nb + 4u + cs2) - ezo) * crdx;
+            const float inv = hf[1];
+            const Sc Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 0, j, inv);
+            const bool keep = c.py || pz;
+            const float bo = keep ? ld_at(gB, nb + cs) : 0.f;
+            const float db = fmaf(Z.cam1, bo, -Z.rp * cye);
+            hy = fmaf(X.ca, ld_at(gH, nb + cs), X.rp * fmaf(Y.ph, db, Y.q * bo));
+            if (keep) st_at(dB, nb + cs, bo + db);
+        }
+        st_at(dH, nb + cs, hy);
+        // Hz(i+1/2, j+1/2, k): Bz with x at i+1/2; Hz with y at j+1/2, z at k
+        float hz = 0.f;
+        if (hasz) {
+            const float cze = (ld_at(gE, nb + 4u + cs) - eyo) * crdx - (ld_at(gE, nb + dyb) - exo) * crdy;
+            const float inv = hf[2];
+            const Sc X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 0, k, inv);
+            const bool keep = pz || c.px;
+            const float bo = keep ? ld_at(gB, nb + cs2) : 0.f;
+            const float db = fmaf(X.cam1, bo, -X.rp * cze);
+            hz = fmaf(Y.ca, ld_at(gH, nb + cs2), Y.rp * fmaf(Z.ph, db, Z.q * bo));
+            if (keep) st_at(dB, nb + cs2, bo + db);
+        }
+        st_at(dH, nb + cs2, hz);
+        exo = exu;
+        eyo = eyu;
     }
-    st_at(dH, nb, hx);
-    // Hy(i+1/2, j, k+1/2): By with z at k+1/2; Hy with x at i+1/2, y at j
-    float hy = 0.f;
-    if (i < c.nx && k < c.nz) {
-        const float exo = ld_at(gE, nb), ezo = ld_at(gE, nb + cs2);
-        const float cye = (ld_at(gE, nb + dzb) - exo) * crdz - (ld_at(gE, nb + 4u + cs2) - ezo) * crdx;
-        const float inv = hf[1];
-        const Sc Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 0, j, inv);
-        const bool keep = c.py || c.pz;
-        const float bo = keep ? ld_at(gB, nb + cs) : 0.f;
-        const float db = fmaf(Z.cam1, bo, -Z.rp * cye);
-        hy = fmaf(X.ca, ld_at(gH, nb + cs), X.rp * fmaf(Y.ph, db, Y.q * bo));
-        if (keep) st_at(dB, nb + cs, bo + db);
-    }
-    st_at(dH, nb + cs, hy);
-    // Hz(i+1/2, j+1/2, k): Bz with x at i+1/2; Hz with y at j+1/2, z at k
-    float hz = 0.f;
-    if (i < c.nx && j < c.ny) {
-        const float exo = ld_at(gE, nb), eyo = ld_at(gE, nb + cs);
-        const float cze = (ld_at(gE, nb + 4u + cs) - eyo) * crdx - (ld_at(gE, nb + dyb) - exo) * crdy;
-        const float inv = hf[2];
-        const Sc X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 0, k, inv);
-        const bool keep = c.pz || c.px;
-        const float bo = keep ? ld_at(gB, nb + cs2) : 0.f;
-        const float db = fmaf(X.cam1, bo, -X.rp * cze);
-        hz = fmaf(Y.ca, ld_at(gH, nb + cs2), Y.rp * fmaf(Z.ph, db, Z.q * bo));
-        if (keep) st_at(dB, nb + cs2, bo + db);
-    }
-    st_at(dH, nb + cs2, hz);
 }
 
 // D then E of every node from H at n+1/2 (buffer par ^ 1, written by the H
 // pass) and E, D at n (buffer par) into buffer par ^ 1, with the sources,
-// probes, plane ring and watchdog of the fused kernels.
+// probes, plane ring and watchdog of the fused kernels.  H_x, H_y of plane k
+// carry over as plane k-1 of the next iteration.
 template <typename CT>
-__global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ board, int rel, int flip)
+__global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ board, int rel, int flip,
+                                                  int zl)
 {
     const BoardDev& B = *board;
-    NodeCtx c;
-    if (!node_ctx(B, flip, c)) return;
-    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride, nb = c.nb;
+    ColCtx c;
+    if (!col_ctx(B, flip, c)) return;
+    col_chunk(zl, c);
+    const uint32_t cs = B.cstride, cs2 = 2u * B.cstride;
     const uint32_t dyb = (uint32_t)c.sy * 4u, dzb = (uint32_t)c.sz * 4u;
     const float* gE = B.f[c.par][0];
     const float* gD = B.d[c.par][0];
@@ -153,90 +176,105 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
     cgfloat* cy = (cgfloat*)B.coef[1];
     cgfloat* cz = (cgfloat*)B.coef[2];
     const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
-    const int id = class_of<CT>(B, nb);
     const __attribute__((address_space(1))) ClassEntry* ctab =
         (const __attribute__((address_space(1))) ClassEntry*)B.ctab;
-    const float inv_x = ctab[id].inv_x, inv_y = ctab[id].inv_y, inv_z = ctab[id].inv_z;
-    const uint32_t flags = ctab[id].flags;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
-    const int i = c.i, j = c.j, k = c.k;
+    const int i = c.i, j = c.j;
     const int64_t step = B.step[0] + rel;
     const int64_t ms = B.max_steps;
-
-    const bool kx = c.px || c.py, ky = c.py || c.pz, kz = c.pz || c.px;   // D kept
-    const float dxo = kx ? ld_at(gD, nb) : 0.f;
-    const float dyo = ky ? ld_at(gD, nb + cs) : 0.f;
-    const float dzo = kz ? ld_at(gD, nb + cs2) : 0.f;
-    float exn = 0.f, eyn = 0.f, ezn = 0.f, ddx = 0.f, ddy = 0.f, ddz = 0.f;
-    // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
-    if (flags & kUpdEx) {
-        const float chx = (ld_at(nH, nb + cs2) - ld_at(nH, nb - dyb + cs2)) * crdy -
-                          (ld_at(nH, nb + cs) - ld_at(nH, nb - dzb + cs)) * crdz;
-        const Sc Y = sc_at(cy, ny1, 0, j, inv_x), Z = sc_at(cz, nz1, 0, k, inv_x), X = sc_at(cx, nx1, 1, i, inv_x);
-        ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
-        exn = fmaf(Z.ca, ld_at(gE, nb), Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
-    }
-    // Ey(i, j+1/2, k): Dy with z at k; Ey with x at i, y at j+1/2
-    if (flags & kUpdEy) {
-        const float chy = (ld_at(nH, nb) - ld_at(nH, nb - dzb)) * crdz -
-                          (ld_at(nH, nb + cs2) - ld_at(nH, nb - 4u + cs2)) * crdx;
-        const Sc Z = sc_at(cz, nz1, 0, k, inv_y), X = sc_at(cx, nx1, 0, i, inv_y), Y = sc_at(cy, ny1, 1, j, inv_y);
-        ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
-        eyn = fmaf(X.ca, ld_at(gE, nb + cs), X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
-    }
-    // Ez(i, j, k+1/2): Dz with x at i; Ez with y at j, z at k+1/2
-    if (flags & kUpdEz) {
-        float chz = (ld_at(nH, nb + cs) - ld_at(nH, nb - 4u + cs)) * crdx -
-                    (ld_at(nH, nb) - ld_at(nH, nb - dyb)) * crdy;
-        float bs = 0.f;
-        if (flags & kSrcEz) {
-            const int node = (int)(nb >> 2);
-            const __attribute__((address_space(1))) int32_t* sn =
-                (const __attribute__((address_space(1))) int32_t*)B.src_node;
-            float js = 0.f;
-            for (int q = 0; q < B.nsrc; ++q)
-                if (sn[q] == node) {
-                    js += B.src_j[q * ms + step];
-                    bs += B.src_beta[q];
-                }
-            chz -= js;
+    bool bad = false;
+    // H_x, H_y of plane k-1
+    float hxm = c.k0 > 0 ? ld_at(nH, c.nb0 + (uint32_t)(c.k0 - 1) * dzb) : 0.f;
+    float hym = c.k0 > 0 ? ld_at(nH, c.nb0 + (uint32_t)(c.k0 - 1) * dzb + cs) : 0.f;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
+        const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
+        const int id = class_of<CT>(B, nb);
+        const float inv_x = ctab[id].inv_x, inv_y = ctab[id].inv_y, inv_z = ctab[id].inv_z;
+        const uint32_t flags = ctab[id].flags;
+        const float hx = ld_at(nH, nb), hy = ld_at(nH, nb + cs), hz = ld_at(nH, nb + cs2);
+        const bool kx = c.px || c.py, ky = c.py || pz, kz = pz || c.px;   // D kept
+        const float dxo = kx ? ld_at(gD, nb) : 0.f;
+        const float dyo = ky ? ld_at(gD, nb + cs) : 0.f;
+        const float dzo = kz ? ld_at(gD, nb + cs2) : 0.f;
+        float exn = 0.f, eyn = 0.f, ezn = 0.f, ddx = 0.f, ddy = 0.f, ddz = 0.f;
+        // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
+        if (flags & kUpdEx) {
+            const float chx = (hz - ld_at(nH, nb - dyb + cs2)) * crdy - (hy - hym) * crdz;
+            const Sc Y = sc_at(cy, ny1, 0, j, inv_x), Z = sc_at(cz, nz1, 0, k, inv_x), X = sc_at(cx, nx1, 1, i, inv_x);
+            ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
+            exn = fmaf(Z.ca, ld_at(gE, nb), Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
         }
-        const Sc X = sc_at(cx, nx1, 0, i, inv_z), Y = sc_at(cy, ny1, 0, j, inv_z), Z = sc_at(cz, nz1, 1, k, inv_z);
-        const float ezo = ld_at(gE, nb + cs2);
-        ddz = fmaf(X.cam1, dzo, X.rp * chz);
-        ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
-        if (bs != 0.0f) ezn = resistive_ez(ezo, chz, inv_z, bs);
+        // Ey(i, j+1/2, k): Dy with z at k; Ey with x at i, y at j+1/2
+        if (flags & kUpdEy) {
+            const float chy = (hx - hxm) * crdz - (hz - ld_at(nH, nb - 4u + cs2)) * crdx;
+            const Sc Z = sc_at(cz, nz1, 0, k, inv_y), X = sc_at(cx, nx1, 0, i, inv_y), Y = sc_at(cy, ny1, 1, j, inv_y);
+            ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
+            eyn = fmaf(X.ca, ld_at(gE, nb + cs), X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
+        }
+        // Ez(i, j, k+1/2): Dz with x at i; Ez with y at j, z at k+1/2
+        if (flags & kUpdEz) {
+            float chz = (hy - ld_at(nH, nb - 4u + cs)) * crdx - (hx - ld_at(nH, nb - dyb)) * crdy;
+            float bs = 0.f;
+            if (flags & kSrcEz) {
+                const int node = (int)(nb >> 2);
+                const __attribute__((address_space(1))) int32_t* sn =
+                    (const __attribute__((address_space(1))) int32_t*)B.src_node;
+                cgfloat* sj = (cgfloat*)B.src_j;
+                cgfloat* sb = (cgfloat*)B.src_beta;
+                float js = 0.f;
+                for (int q = 0; q < B.nsrc; ++q)
+                    if (sn[q] == node) {
+                        js += sj[q * ms + step];
+                        bs += sb[q];
+                    }
+                chz -= js;
+            }
+            const Sc X = sc_at(cx, nx1, 0, i, inv_z), Y = sc_at(cy, ny1, 0, j, inv_z), Z = sc_at(cz, nz1, 1, k, inv_z);
+            const float ezo = ld_at(gE, nb + cs2);
+            ddz = fmaf(X.cam1, dzo, X.rp * chz);
+            ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
+            if (bs != 0.0f) ezn = resistive_ez(ezo, chz, inv_z, bs);
+        }
+        st_at(dE, nb, exn);
+        st_at(dE, nb + cs, eyn);
+        st_at(dE, nb + cs2, ezn);
+        if (kx) st_at(dD, nb, dxo + ddx);
+        if (ky) st_at(dD, nb + cs, dyo + ddy);
+        if (kz) st_at(dD, nb + cs2, dzo + ddz);
+        if (flags & kPrbEz) {
+            const int node = (int)(nb >> 2);
+            const __attribute__((address_space(1))) int32_t* pn =
+                (const __attribute__((address_space(1))) int32_t*)B.prb_node;
+            gfloat* ps = (gfloat*)B.prb_series;
+            for (int q = 0; q < B.nprb; ++q)
+                if (pn[q] == node) ps[q * ms + step] = ezn;
+        }
+        if (flags & kPlnEz)
+            st_at(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * dzb + c.nb0, ezn);
+        bad |= !isfinite(exn + eyn + ezn);
+        hxm = hx;
+        hym = hy;
     }
-    st_at(dE, nb, exn);
-    st_at(dE, nb + cs, eyn);
-    st_at(dE, nb + cs2, ezn);
-    if (kx) st_at(dD, nb, dxo + ddx);
-    if (ky) st_at(dD, nb + cs, dyo + ddy);
-    if (kz) st_at(dD, nb + cs2, dzo + ddz);
-    if (flags & kPrbEz) {
-        const int node = (int)(nb >> 2);
-        const __attribute__((address_space(1))) int32_t* pn =
-            (const __attribute__((address_space(1))) int32_t*)B.prb_node;
-        gfloat* ps = (gfloat*)B.prb_series;
-        for (int q = 0; q < B.nprb; ++q)
-            if (pn[q] == node) ps[q * ms + step] = ezn;
-    }
-    if (flags & kPlnEz)
-        st_at(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * dzb + (nb - (uint32_t)k * dzb), ezn);
-    if (!isfinite(exn + eyn + ezn)) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
+    if (bad) *(__attribute__((address_space(1))) int32_t*)B.bad = 1;
 }
 
 hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int rel, int flip,
                            bool wide, hipStream_t st)
 {
+    // z chunks of up to 8 planes (a plane carried in registers saves a z
+    // neighbour load), shorter when the columns alone leave the GPU idle
     const dim3 block(64, 4);
-    const dim3 grid((unsigned)((nx + 1 + 63) / 64), (unsigned)((ny + 1 + 3) / 4), (unsigned)(nz + 1));
+    const int64_t bxy = (int64_t)((nx + 1 + 63) / 64) * ((ny + 1 + 3) / 4);
+    const int zl = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(nz + 1) * bxy / 2048));
+    const dim3 grid((unsigned)((nx + 1 + 63) / 64), (unsigned)((ny + 1 + 3) / 4),
+                    (unsigned)((nz + 1 + zl - 1) / zl));
     if (wide) {
-        hipLaunchKernelGGL(eps_h_pass<uint16_t>, grid, block, 0, st, board, flip);
-        hipLaunchKernelGGL(eps_e_pass<uint16_t>, grid, block, 0, st, board, rel, flip);
+        hipLaunchKernelGGL(eps_h_pass<uint16_t>, grid, block, 0, st, board, flip, zl);
+        hipLaunchKernelGGL(eps_e_pass<uint16_t>, grid, block, 0, st, board, rel, flip, zl);
     } else {
-        hipLaunchKernelGGL(eps_h_pass<uint8_t>, grid, block, 0, st, board, flip);
-        hipLaunchKernelGGL(eps_e_pass<uint8_t>, grid, block, 0, st, board, rel, flip);
+        hipLaunchKernelGGL(eps_h_pass<uint8_t>, grid, block, 0, st, board, flip, zl);
+        hipLaunchKernelGGL(eps_e_pass<uint8_t>, grid, block, 0, st, board, rel, flip, zl);
     }
     return hipGetLastError();
 }
