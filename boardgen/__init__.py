@@ -76,6 +76,8 @@ class Board:
     # Eq. 2's eps_rw: True divides each PML sigma by the relative permittivity at
     # the field location; False takes eps_rw = 1 (the same wherever the PML is air)
     pml_eps_rw: bool = False
+    # conductivity per cell in S/m (lossy dielectric), None = lossless; zero in PML slabs
+    sigma_cell: Optional[np.ndarray] = None
     sources: List[Source] = field(default_factory=list)
     probes: List[Tuple[int, int, int]] = field(default_factory=list)
     steps: int = 1000

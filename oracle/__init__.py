@@ -49,7 +49,7 @@ class _Problem(C.Structure):
                 ("dt", C.c_double), ("courant", C.c_double),
                 ("npml", C.c_int32 * 6),
                 ("pml_m", C.c_double), ("pml_R", C.c_double), ("pml_kappa_max", C.c_double),
-                ("eps_r_cell", C.c_void_p), ("pec_mask", C.c_void_p),
+                ("eps_r_cell", C.c_void_p), ("sigma_cell", C.c_void_p), ("pec_mask", C.c_void_p),
                 ("nsrc", C.c_int32), ("src_ijk", C.c_void_p), ("src_wave", C.c_void_p),
                 ("src_J0", C.c_void_p), ("src_t0", C.c_void_p), ("src_sigma", C.c_void_p),
                 ("src_R", C.c_void_p),
@@ -110,6 +110,14 @@ class Problem:
         b = board
         self.board = b
         self.eps = np.ascontiguousarray(b.eps_r_cell, dtype=np.float32)
+        sig = getattr(b, "sigma_cell", None)
+        self.sigma = None if sig is None else np.ascontiguousarray(sig, dtype=np.float32)
+        if self.sigma is not None:
+            assert self.sigma.shape == self.eps.shape and np.all(self.sigma >= 0)
+            p_ = b.npml
+            inner = np.zeros_like(self.sigma, dtype=bool)
+            inner[p_[4]:b.nz - p_[5], p_[2]:b.ny - p_[3], p_[0]:b.nx - p_[1]] = True
+            assert not np.any(self.sigma[~inner]), "conductivity only outside the PML slabs"
         self.pec = np.ascontiguousarray(b.pec_edge_mask, dtype=np.uint8)
         ns = len(b.sources)
         self.src_ijk = np.array([[s.i, s.j, s.k] for s in b.sources], np.int32).reshape(ns, 3)
@@ -139,6 +147,7 @@ class Problem:
         p.npml = (C.c_int32 * 6)(*b.npml)
         p.pml_m, p.pml_R, p.pml_kappa_max = b.pml_m, b.pml_R, b.pml_kappa_max
         p.eps_r_cell = self.eps.ctypes.data
+        p.sigma_cell = None if self.sigma is None else self.sigma.ctypes.data
         p.pec_mask = self.pec.ctypes.data
         p.nsrc = ns
         p.src_ijk = self.src_ijk.ctypes.data

@@ -26,6 +26,10 @@
  *     and B (Eq. 1 puts the same s-bar on mu); otherwise eps_rw = 1;
  *   - the power and ground planes zero the tangential Ex, Ey on their edges;
  *   - a current source enters the D_z update as -J_z at the half step;
+ *   - a lossy dielectric (the Results section notes the lossless model overstates
+ *     how long the ringing lasts): conductivity sigma_c per cell, the edge mean of
+ *     the touching cells, with eps dE/dt + sigma_c Ebar = curl H - J and Ebar the
+ *     mean of E^n and E^{n+1}, solved for E^{n+1} (interior edges only);
  *   - a resistive voltage source (Results section, the Table 1 run, built with
  *     semi-explicit update coefficients) is a lumped element on one E_z edge of
  *     the interior: an EMF V_s that raises node k+1 over node k, in series with
@@ -66,6 +70,7 @@ typedef struct {
     int32_t npml[6];           /* -x +x -y +y -z +z */
     double pml_m, pml_R, pml_kappa_max;
     const float* eps_r_cell;   /* nz*ny*nx, x fastest */
+    const float* sigma_cell;   /* NULL or nz*ny*nx conductivity in S/m, zero in PML slabs */
     const uint8_t* pec_mask;   /* (nz+1)(ny+1)(nx+1), bit0 Ex bit1 Ey bit2 Ez */
     int32_t nsrc;
     const int32_t* src_ijk;    /* 3*nsrc */
@@ -195,6 +200,17 @@ static inline __attribute__((always_inline)) or_coef or_at(const or_axis* ax, in
     return c;
 }
 
+/* An interior edge (kappa 1, PML sigma 0, so D = eps E and the D update is
+ * D += dt (curl - J)) carrying a conduction current g Ebar, Ebar the mean of E^n
+ * and E^{n+1}: eps (E' - E)/dt = curl - g (E' + E)/2, solved for E'. */
+static void or_lossy(double* e, double* d, double curl, double g, double eps, double dt)
+{
+    const double beta = 0.5 * dt * g / eps;
+    const double e_n = ((1.0 - beta) * *e + dt / eps * curl) / (1.0 + beta);
+    *d += eps * (e_n - *e);
+    *e = e_n;
+}
+
 /* Source waveform (Results section, Eq. 8 and the workload's plain Gaussian). */
 double or_waveform(int wave, double J0, double t0, double sigma, double t)
 {
@@ -311,6 +327,13 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                                   cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hz[c] - hz[IX(i, j - 1, k)]) * rdy
                                 - (hy[c] - hy[IX(i, j, k - 1)]) * rdz;
+                    const double sg = !p->sigma_cell ? 0.0 : 0.25 *
+                        ((double)p->sigma_cell[CELL(i, j - 1, k - 1)] + (double)p->sigma_cell[CELL(i, j, k - 1)] +
+                         (double)p->sigma_cell[CELL(i, j - 1, k)] + (double)p->sigma_cell[CELL(i, j, k)]);
+                    if (sg != 0.0) {
+                        or_lossy(&ex[c], &Dx[c], curl, sg, eps, dt);
+                        continue;
+                    }
                     double d_o = Dx[c];
                     double d_n = cy.a * d_o + cy.b * curl;
                     Dx[c] = d_n;
@@ -332,6 +355,13 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                                   cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hx[c] - hx[IX(i, j, k - 1)]) * rdz
                                 - (hz[c] - hz[IX(i - 1, j, k)]) * rdx;
+                    const double sg = !p->sigma_cell ? 0.0 : 0.25 *
+                        ((double)p->sigma_cell[CELL(i - 1, j, k - 1)] + (double)p->sigma_cell[CELL(i, j, k - 1)] +
+                         (double)p->sigma_cell[CELL(i - 1, j, k)] + (double)p->sigma_cell[CELL(i, j, k)]);
+                    if (sg != 0.0) {
+                        or_lossy(&ey[c], &Dy[c], curl, sg, eps, dt);
+                        continue;
+                    }
                     double d_o = Dy[c];
                     double d_n = cz.a * d_o + cz.b * curl;
                     Dy[c] = d_n;
@@ -365,16 +395,14 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                         }
                     double curl = (hy[c] - hy[IX(i - 1, j, k)]) * rdx
                                 - (hx[c] - hx[IX(i, j - 1, k)]) * rdy - J;
-                    if (g_l != 0.0) {
-                        /* resistive source on an interior edge (kappa 1, sigma 0, so
-                         * D = eps E and the D update is D += dt (curl - J_branch)):
-                         * eps (E' - E)/dt = curl - g_l (E' + E)/2, solved for E'
-                         * (curl already holds -V_s/(R dx dy)) */
-                        const double beta = 0.5 * dt * g_l / eps;
-                        const double e_n = ((1.0 - beta) * ez[c] + dt / eps * curl) /
-                                           (1.0 + beta);
-                        Dz[c] += eps * (e_n - ez[c]);
-                        ez[c] = e_n;
+                    const double sg = !p->sigma_cell ? 0.0 : 0.25 *
+                        ((double)p->sigma_cell[CELL(i - 1, j - 1, k)] + (double)p->sigma_cell[CELL(i, j - 1, k)] +
+                         (double)p->sigma_cell[CELL(i - 1, j, k)] + (double)p->sigma_cell[CELL(i, j, k)]);
+                    if (g_l + sg != 0.0) {
+                        /* resistive source and/or lossy dielectric on an interior edge:
+                         * the lumped conductance g_l (curl already holds -V_s/(R dx dy))
+                         * adds to the medium's sigma_c */
+                        or_lossy(&ez[c], &Dz[c], curl, g_l + sg, eps, dt);
                         continue;
                     }
                     const or_coef cx = or_at(&X, i, 0, ew, dt), cy = or_at(&Y, j, 0, ew, dt),

@@ -9,6 +9,7 @@
 * P11 resistive voltage source: discrete energy balance, R -> infinity limits
 * P12 plane-wide DFT: closed form on a cavity eigenmode, agreement with the probe DFT
 * P13 Eq. 2's eps_rw: uniform-medium equivalence, no-op in air, absorption in dielectric
+* P15 lossy dielectric: closed-form recurrence of a lossy cavity eigenmode
 * Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
 """
 import numpy as np
@@ -611,3 +612,50 @@ def test_p13_eps_rw_pml_absorbs_in_dielectric(oracle_mod):
 
     assert reflection(True) < -40.0
     assert reflection(False) > -35.0
+
+
+# ---------------------------------------------------------------------------
+# P15  lossy dielectric: conduction current sigma_c Ebar, solved for E^{n+1}
+# ---------------------------------------------------------------------------
+
+def test_p15_lossy_cavity_eigenmode_recurrence(oracle_mod):
+    """A TM_pq0 eigenmode of a PEC box filled with a uniformly lossy dielectric
+    keeps its shape S(i, j); its amplitude obeys, in closed form,
+    (1 + beta) u_{n+1} - (2 - s2) u_n + (1 - beta) u_{n-1} = 0 with
+    beta = sigma dt / (2 eps) and s2 = (c dt)^2 lambda, so it decays by
+    sqrt((1 - beta) / (1 + beta)) per step.  An explicit loss term (sigma E^n) or
+    a dropped factor 1/2 gives another recurrence and fails."""
+    nx, ny, nz, er = 12, 9, 3, 2.2
+    dx, dy, dz = 1e-3, 1.3e-3, 0.5e-3
+    b = boardgen.cavity_box(nx, ny, nz, dx, dy, dz, er, steps=1)
+    sigma = 0.05
+    b.sigma_cell = np.full(b.eps_r_cell.shape, sigma, np.float32)
+    dt = oracle_mod.time_step(b)
+    p, q, A = 2, 1, 3.0
+    ii, jj = np.arange(nx + 1), np.arange(ny + 1)
+    S = np.outer(np.sin(q * np.pi * jj / ny), np.sin(p * np.pi * ii / nx))
+    st = oracle_mod.new_state(b)
+    st["ez"][:nz] = A * S[None]
+    ez0 = A * S
+    st["hx"][:nz, :ny, :] = dt / (2 * MU0) * ((ez0[1:, :] - ez0[:-1, :]) / dy)[None]
+    st["hy"][:nz, :, :nx] = dt / (2 * MU0) * (-(ez0[:, 1:] - ez0[:, :-1]) / dx)[None]
+    u = [A]
+    for _ in range(300):
+        oracle_mod.run(b, nsteps=1, state=st)
+        plane = st["ez"][1]
+        un = float(np.sum(plane * S) / np.sum(S * S))
+        assert np.abs(plane - un * S).max() <= 1e-12 * A       # the shape is kept
+        u.append(un)
+    u = np.array(u)
+    eps = EPS0 * float(np.float32(er))
+    beta = float(np.float32(sigma)) * dt / (2 * eps)
+    lam = 4 * np.sin(p * np.pi / (2 * nx)) ** 2 / dx ** 2 + 4 * np.sin(q * np.pi / (2 * ny)) ** 2 / dy ** 2
+    s2 = dt ** 2 * lam / (MU0 * eps)
+    res = (1 + beta) * u[2:] - (2 - s2) * u[1:-1] + (1 - beta) * u[:-2]
+    assert np.abs(res).max() <= 1e-11 * A
+    assert abs(u[1] - ((1 - beta) - s2 / 2) / (1 + beta) * u[0]) <= 1e-12 * A
+    assert beta > 1e-3 and abs(u[-1]) < 0.7 * A                  # the loss is visible
+    explicit = u[2:] - (2 - s2 - 2 * beta) * u[1:-1] + (1 - 2 * beta) * u[:-2]
+    half = (1 + beta / 2) * u[2:] - (2 - s2) * u[1:-1] + (1 - beta / 2) * u[:-2]
+    assert np.abs(explicit).max() > 1e3 * np.abs(res).max()
+    assert np.abs(half).max() > 1e3 * np.abs(res).max()
