@@ -434,6 +434,21 @@ def zconv_board(n_diel: int, steps: int = 4000, n_diel_max: int = 15, air_xy: in
     return b
 
 
+def lossy_dielectric(board: Board, tan_delta: float, f_ref: float = 5e9) -> Board:
+    """Give the board's dielectric (cells with eps_r > 1) a loss tangent tan_delta
+    at f_ref: conductivity sigma = 2 pi f_ref eps0 eps_r tan_delta per cell, cells
+    in the PML slabs left lossless."""
+    eps0 = 8.854187817620389e-12
+    sig = np.where(board.eps_r_cell > 1.0,
+                   2 * np.pi * f_ref * eps0 * board.eps_r_cell * tan_delta, 0.0).astype(np.float32)
+    p = board.npml
+    inner = np.zeros(sig.shape, bool)
+    inner[p[4]:board.nz - p[5], p[2]:board.ny - p[3], p[0]:board.nx - p[1]] = True
+    sig[~inner] = 0.0
+    board.sigma_cell = sig
+    return board
+
+
 def random_tiny(seed: int, nx: int = 10, ny: int = 9, nz: int = 8, npml: int = 2,
                 steps: int = 40) -> Board:
     """A tiny board with every feature: PML on all faces (may differ per face),

@@ -89,7 +89,7 @@ typedef struct {
     int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
     int32_t plane_k;             /* plane of the plane DFT, -1 if none */
     int32_t plane_nf;            /* its number of frequencies */
-    int32_t eps_rw_passes;       /* 1: steps run the eps_rw passes (see fdtd_set_pml_eps_rw) */
+    int32_t node_passes;         /* 1: steps run the node passes (fdtd_set_pml_eps_rw, fdtd_set_conductivity) */
 } fdtd_info;
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
@@ -161,11 +161,23 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
  * for H and B, since Eq. 1 puts the same s-bar on mu.  Off (the default),
  * eps_rw = 1, which is the same wherever the PML holds air (eps_r = 1).  When it
  * is on and some PML location has eps_r != 1 (a board running into the PML),
- * steps run two per-node passes (H then E, coefficients rebuilt from kappa and
- * sigma / eps_rw) instead of the tiled field kernels; fdtd_info.eps_rw_passes
- * reports it, tile shapes are then ignored, and fdtd_step_many steps such handles
- * on their own streams.  ESTATE after the first step. */
+ * steps run the node passes (two per-node passes, H then E, coefficients rebuilt
+ * from kappa and sigma / eps_rw) instead of the tiled field kernels;
+ * fdtd_info.node_passes reports it, tile shapes are then ignored, and
+ * fdtd_step_many steps such handles on their own streams.  ESTATE after the
+ * first step. */
 int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);
+
+/* Lossy dielectric (the Results section notes the lossless model overstates how
+ * long the resonances last): sigma_cell (host, nx*ny*nz floats, x fastest, S/m,
+ * each finite and >= 0, NULL = lossless) is the conductivity of every cell; each
+ * E edge takes the mean of the touching cells and carries the conduction
+ * current sigma_c Ebar (Ebar the mean of E^n and E^{n+1}), solved for E^{n+1}
+ * as for a resistive source, whose lumped conductance it adds to.  Cells in a
+ * PML slab must be lossless (EINVAL otherwise).  A board with any conductive
+ * edge steps with the node passes (see fdtd_set_pml_eps_rw).  ESTATE after the
+ * first step. */
+int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell);
 
 /* Plane DFT: the running DFT of Ez(i, j, k+1/2) over every node of the node plane
  * k (0 <= k < nz; the ground-plane field of the Results section, Figs. 3-5, in the

@@ -31,17 +31,18 @@ __device__ __forceinline__ T ld_at_t(const void* base, uint32_t off)
     return *(const __attribute__((address_space(1))) T*)((const gbyte*)base + off);
 }
 
-// Ez^{n+1} on the edge of a resistive voltage source (Results section, the
-// Table 1 run): EMF V_s in series with R across the edge, outside every PML (so
-// the edge's kappa is 1 and its sigma 0, and D never enters).  In the scaled
-// units the branch current is beta (E^n + E^{n+1}) + js, beta = c0 dt eta0 dz /
-// (2 R dx dy) and js its Norton part, already subtracted in chz; with b =
-// beta / eps_r the update (E' - E) / inv_eps_r = chz - beta (E + E') solved for E'
-// is ((1 - b) E + inv_eps_r chz) / (1 + b).
-__device__ __forceinline__ float resistive_ez(float e_old, float chz, float inv_eps, float beta)
+// E^{n+1} of an interior edge that carries a conduction current (a resistive
+// voltage source's lumped conductance, Results section, the Table 1 run; or a
+// lossy dielectric).  Outside every PML (kappa 1, sigma 0, D never enters) and
+// in the scaled units the current is beta (E^n + E^{n+1}) plus any Norton part,
+// already subtracted in ch; with b = beta / eps_r the update
+// (E' - E) / inv_eps_r = ch - beta (E + E') solved for E' is
+// ((1 - b) E + inv_eps_r ch) / (1 + b).  beta = c0 dt eta0 dz / (2 R dx dy) for
+// a resistor, sigma_c dt / (2 eps0) for a conductivity.
+__device__ __forceinline__ float conductive_e(float e_old, float ch, float inv_eps, float beta)
 {
     const float b = inv_eps * beta;
-    return (fmaf(-b, e_old, e_old) + inv_eps * chz) / (1.0f + b);
+    return (fmaf(-b, e_old, e_old) + inv_eps * ch) / (1.0f + b);
 }
 
 // Hardware dispatches block b to XCD b % 8.  Map blocks so that each XCD walks

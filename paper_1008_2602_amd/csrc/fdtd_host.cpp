@@ -77,19 +77,21 @@ struct VoltageProbeH {
     int first, count;   // Ez probes first .. first+count-1, one per z cell
 };
 
-// a class: the E edges' 1/eps_r, the flags and (eps_rw passes only) the H faces' 1/eps_r
+// a class: the E edges' 1/eps_r, the flags and (node passes only) the H faces'
+// 1/eps_r and the E edges' conduction coefficients
 struct ClassKey {
-    uint32_t a, b, c, f, hx, hy, hz;
+    uint32_t a, b, c, f, hx, hy, hz, lx, ly, lz;
     bool operator==(const ClassKey& o) const
     {
-        return a == o.a && b == o.b && c == o.c && f == o.f && hx == o.hx && hy == o.hy && hz == o.hz;
+        return a == o.a && b == o.b && c == o.c && f == o.f && hx == o.hx && hy == o.hy &&
+               hz == o.hz && lx == o.lx && ly == o.ly && lz == o.lz;
     }
 };
 struct ClassKeyHash {
     size_t operator()(const ClassKey& k) const
     {
         uint64_t h = 1469598103934665603ull;
-        for (uint32_t v : {k.a, k.b, k.c, k.f, k.hx, k.hy, k.hz}) {
+        for (uint32_t v : {k.a, k.b, k.c, k.f, k.hx, k.hy, k.hz, k.lx, k.ly, k.lz}) {
             h ^= v;
             h *= 1099511628211ull;
         }
@@ -125,7 +127,7 @@ struct fdtd_grid {
     float* coef[3] = {};
     void* cls = nullptr;
     ClassEntry* ctab = nullptr;
-    float* hface = nullptr;
+    float* node_aux = nullptr;
     int32_t* src_node = nullptr;
     float* src_j = nullptr;
     float* src_beta = nullptr;
@@ -152,6 +154,7 @@ struct fdtd_grid {
 
     // host-side set-up
     std::vector<float> eps;
+    std::vector<float> sigma;       // conductivity per cell (S/m), empty: lossless
     std::vector<uint8_t> pec;
     bool have_materials = false;
     std::vector<SourceH> sources;
@@ -160,7 +163,7 @@ struct fdtd_grid {
     std::vector<double> freqs;
     int plane_k = -1;               // plane-DFT node plane, -1: none
     bool pml_eps_rw = false;        // Eq. 2's eps_rw requested
-    bool eps_pass = false;          // ... and some PML location has eps_r != 1: per-node passes
+    bool node_pass = false;         // steps run the node passes (eps_rw in a dielectric PML, or loss)
     std::vector<double> plane_freqs;
     int n_classes = 0;
     bool wide = false;
@@ -501,13 +504,19 @@ int finalize(fdtd_grid* g)
     auto cell = [&](int i, int j, int k) -> double {
         return (double)er[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
     };
-    ClassKey last{~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u};
+    ClassKey last{~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u};
     uint32_t last_id = 0;
-    // eps_rw passes: 1/eps_r at the H faces of each class (two cells share a face;
-    // one on the outer wall), and whether any PML location has eps_r != 1
-    std::vector<float> hface;
+    // node passes: 1/eps_r at the H faces of each class (two cells share a face;
+    // one on the outer wall) and the edges' conduction, and whether any PML
+    // location has eps_r != 1 (with eps_rw) or any edge conducts
+    std::vector<float> node_aux;
+    const bool lossy = !g->sigma.empty();
+    auto sig = [&](int i, int j, int k) -> double {
+        return (double)g->sigma[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
+    };
+    const double lscale = g->dt / (2.0 * kEps0);   // sigma_c -> sigma_c dt / (2 eps0)
     auto in_slab = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
-    g->eps_pass = false;
+    g->node_pass = false;
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
@@ -546,9 +555,23 @@ int finalize(fdtd_grid* g)
                                       in_slab(k, nz, d.npml[4], d.npml[5]);
                     if (slab && (((fl & kUpdEx) && ix != 1.f) || ((fl & kUpdEy) && iy != 1.f) ||
                                  ((fl & kUpdEz) && iz != 1.f) || fx != 1.f || fy != 1.f || fz != 1.f))
-                        g->eps_pass = true;
+                        g->node_pass = true;
                 }
-                const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz)};
+                float lx = 0.f, ly = 0.f, lz = 0.f;
+                if (lossy) {
+                    if (fl & kUpdEx)
+                        lx = (float)(lscale * 0.25 * (sig(i, j - 1, k - 1) + sig(i, j, k - 1) +
+                                                      sig(i, j - 1, k) + sig(i, j, k)));
+                    if (fl & kUpdEy)
+                        ly = (float)(lscale * 0.25 * (sig(i - 1, j, k - 1) + sig(i, j, k - 1) +
+                                                      sig(i - 1, j, k) + sig(i, j, k)));
+                    if (fl & kUpdEz)
+                        lz = (float)(lscale * 0.25 * (sig(i - 1, j - 1, k) + sig(i, j - 1, k) +
+                                                      sig(i - 1, j, k) + sig(i, j, k)));
+                    if (lx != 0.f || ly != 0.f || lz != 0.f) g->node_pass = true;
+                }
+                const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz),
+                                   fbits(lx), fbits(ly), fbits(lz)};
                 uint32_t id;
                 if (key == last) {
                     id = last_id;
@@ -562,7 +585,7 @@ int finalize(fdtd_grid* g)
                         id = (uint32_t)table.size();
                         map.emplace(key, id);
                         table.push_back(ClassEntry{ix, iy, iz, fl});
-                        hface.insert(hface.end(), {fx, fy, fz});
+                        node_aux.insert(node_aux.end(), {fx, fy, fz, lx, ly, lz});
                     } else {
                         id = it->second;
                     }
@@ -591,12 +614,12 @@ int finalize(fdtd_grid* g)
     if (!g->ctab) return fail(FDTD_ENOMEM, "class table allocation failed");
     HIP_OR_FAIL(hipMemcpyAsync(g->ctab, table.data(), table.size() * sizeof(ClassEntry),
                                hipMemcpyHostToDevice, st));
-    if (g->eps_pass) {
-        g->hface = (float*)dev_alloc(g, hface.size() * 4);
-        if (!g->hface) return fail(FDTD_ENOMEM, "face table allocation failed");
-        HIP_OR_FAIL(hipMemcpyAsync(g->hface, hface.data(), hface.size() * 4, hipMemcpyHostToDevice, st));
+    if (g->node_pass) {
+        g->node_aux = (float*)dev_alloc(g, node_aux.size() * 4);
+        if (!g->node_aux) return fail(FDTD_ENOMEM, "face table allocation failed");
+        HIP_OR_FAIL(hipMemcpyAsync(g->node_aux, node_aux.data(), node_aux.size() * 4, hipMemcpyHostToDevice, st));
     }
-    HIP_OR_FAIL(hipStreamSynchronize(st));   // table and hface are locals
+    HIP_OR_FAIL(hipStreamSynchronize(st));   // table and node_aux are locals
 
     // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt.  A resistive
     // voltage source (R > 0) carries its Norton current c0 dt eta0 V_s / (R dx dy)
@@ -670,7 +693,7 @@ int finalize(fdtd_grid* g)
     }
     b.cls = g->cls;
     b.ctab = g->ctab;
-    b.hface = g->hface;
+    b.node_aux = g->node_aux;
     b.src_node = g->src_node;
     b.src_j = g->src_j;
     b.src_beta = g->src_beta;
@@ -692,6 +715,7 @@ int finalize(fdtd_grid* g)
     b.crd_y = (float)(kC0 * g->dt / d.dy);
     b.crd_z = (float)(kC0 * g->dt / d.dz);
     b.plane_ring = g->plane_ring;
+    b.eps_rw = g->pml_eps_rw ? 1 : 0;
     g->board_dev = (BoardDev*)dev_alloc(g, sizeof(BoardDev));
     if (!g->board_dev) return fail(FDTD_ENOMEM, "descriptor allocation failed");
     if (int e = upload_tiles(g)) return e;
@@ -947,6 +971,36 @@ int fdtd_add_voltage_probe(fdtd_grid* g, int i, int j, int k0, int k1, int* id)
     return FDTD_OK;
 }
 
+int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "the conductivity is fixed after the first step");
+    const fdtd_grid_desc& d = g->d;
+    if (!sigma_cell) {
+        g->sigma.clear();
+        return FDTD_OK;
+    }
+    const int* p = d.npml;
+    bool any = false;
+    for (int k = 0; k < d.nz; ++k)
+        for (int j = 0; j < d.ny; ++j)
+            for (int i = 0; i < d.nx; ++i) {
+                const float v = sigma_cell[(size_t)i + (size_t)d.nx * ((size_t)j + (size_t)d.ny * k)];
+                if (!(v >= 0.f) || !std::isfinite(v))
+                    return fail(FDTD_EINVAL, "conductivity of cell (%d,%d,%d) is negative or not finite", i, j, k);
+                const bool slab = i < p[0] || i >= d.nx - p[1] || j < p[2] || j >= d.ny - p[3] ||
+                                  k < p[4] || k >= d.nz - p[5];
+                if (v != 0.f && slab)
+                    return fail(FDTD_EINVAL, "conductive cell (%d,%d,%d) lies in a PML slab", i, j, k);
+                any |= v != 0.f;
+            }
+    if (any)
+        g->sigma.assign(sigma_cell, sigma_cell + (size_t)d.nx * d.ny * d.nz);
+    else
+        g->sigma.clear();
+    return FDTD_OK;
+}
+
 int fdtd_set_pml_eps_rw(fdtd_grid* g, int on)
 {
     if (int e = check_grid(g)) return e;
@@ -1082,7 +1136,7 @@ static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
 // one single step when n is odd); returns the launch count through *launches.
 static int enqueue_steps(fdtd_grid* g, int64_t n, int64_t* launches)
 {
-    if (g->eps_pass) {
+    if (g->node_pass) {
         // eps_rw boards: one H pass and one E pass per step (one buffer flip)
         for (int64_t s = 0; s < n; ++s) {
             if (g->timing)
@@ -1119,9 +1173,9 @@ static void build_graph(fdtd_grid* g)
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
     bool ok = true;
-    const int per = g->eps_pass ? 1 : g->tile_steps, nl = kGraphChunk / per;
+    const int per = g->node_pass ? 1 : g->tile_steps, nl = kGraphChunk / per;
     for (int l = 0; l < nl && ok; ++l)
-        ok = (g->eps_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, l, l & 1, g->wide,
+        ok = (g->node_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, l, l & 1, g->wide,
                                             g->stream)
                           : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
                                         g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
@@ -1153,7 +1207,7 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
         if (g->graph_exec) {
             for (; done + kGraphChunk <= n; done += kGraphChunk) {
                 HIP_OR_FAIL(hipGraphLaunch(g->graph_exec, g->stream));
-                launches += kGraphChunk / (g->eps_pass ? 1 : g->tile_steps);
+                launches += kGraphChunk / (g->node_pass ? 1 : g->tile_steps);
             }
         }
     }
@@ -1205,7 +1259,7 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     std::vector<fdtd_grid*> fused;
     std::vector<int64_t> nfused;
     for (int h = 0; h < ng; ++h) {
-        if (gs[h]->eps_pass) {
+        if (gs[h]->node_pass) {
             if (int e = fdtd_step_n(gs[h], n[h])) return e;
         } else {
             fused.push_back(gs[h]);
@@ -1701,7 +1755,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->tile_steps = g->tile_steps;
     out->plane_k = g->plane_k;
     out->plane_nf = (int32_t)g->plane_freqs.size();
-    out->eps_rw_passes = g->eps_pass ? 1 : 0;
+    out->node_passes = g->node_pass ? 1 : 0;
     return FDTD_OK;
 }
 

@@ -58,7 +58,10 @@ struct BoardDev {
     float* d[2][3];
     const void* cls;             // uint8_t or uint16_t per node
     const ClassEntry* ctab;
-    const float* hface;          // eps_rw passes: per class, 1/eps_r at the Hx, Hy, Hz faces
+    // node passes (eps_rw, lossy dielectric), 6 floats per class: 1/eps_r at the
+    // Hx, Hy, Hz faces, then the conduction coefficient sigma_c dt / (2 eps0) of
+    // the Ex, Ey, Ez edges
+    const float* node_aux;
     const float* coef[3];        // per axis: [kind][node/half][n+1]
     const int32_t* src_node;     // node index of each source's Ez edge
     const float* src_j;          // [nsrc][max_steps] Js samples
@@ -82,6 +85,8 @@ struct BoardDev {
     // plane DFT: Ez of the nodes flagged kPlnEz goes to slot (step mod kPlaneRing)
     // of the ring, each slot one node plane of the field layout
     float* plane_ring;
+    // node passes: 1 when Eq. 2's eps_rw scales the PML sigma (else eps_rw = 1)
+    int32_t eps_rw;
 };
 
 // One work item of the field kernel: tile (tx, ty) of a board, planes kb..ke-1.

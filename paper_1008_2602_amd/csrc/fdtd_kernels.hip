@@ -256,7 +256,7 @@ __global__ __launch_bounds__(TX* TY + 64) void field_step(const BoardDev* __rest
                     const float chs = chz - js;
                     ddz = fmaf(x_cam1_n, o.dz, x_rp_n * chs);
                     ezn = fmaf(y_ca_n, ezo, y_rp_n * (ce.inv_z * fmaf(z_ph_h, ddz, z_q_h * o.dz)));
-                    if (bs != 0.0f) ezn = resistive_ez(ezo, chs, ce.inv_z, bs);
+                    if (bs != 0.0f) ezn = conductive_e(ezo, chs, ce.inv_z, bs);
                 }
                 exn = (ce.flags & kUpdEx) ? exn : 0.0f;
                 eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;

@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __r
         const float chs = chz - js;
         ddz = fmaf(X.cam1_n, d_old, X.rp_n * chs);
         ezn = fmaf(Y.ca_n, e_old, Y.rp_n * (inv_z * fmaf(Zc.ph_h, ddz, Zc.q_h * d_old)));
-        if (bs != 0.0f) ezn = resistive_ez(e_old, chs, inv_z, bs);
+        if (bs != 0.0f) ezn = conductive_e(e_old, chs, inv_z, bs);
     };
     auto record_probe = [&](int node, int64_t s, float ez) {
         const __attribute__((address_space(1))) int32_t* pn =

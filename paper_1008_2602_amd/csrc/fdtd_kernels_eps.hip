@@ -1,7 +1,9 @@
-// Leapfrog step with Eq. 2's eps_rw for boards whose dielectric reaches into a
-// PML slab: every sigma_w in s_w = kappa_w + sigma_w / (j w eps0 eps_rw) is
-// divided by the relative permittivity at the field location, so the update
-// coefficients of a PML node depend on its material as well as its position.
+// Leapfrog step for boards the tiled kernels do not cover: Eq. 2's eps_rw with a
+// dielectric reaching into a PML slab (every sigma_w in s_w = kappa_w + sigma_w /
+// (j w eps0 eps_rw) divided by the relative permittivity at the field location,
+// so the update coefficients of a PML node depend on its material as well as
+// its position), and lossy dielectrics (a conduction current sigma_c Ebar on
+// interior edges, solved for E^{n+1} like a resistive source's).
 // Two plain passes (B then H, D then E; one thread per (i, j) column marching
 // up in z) recompute each axis's five coefficients from kappa and q / eps_rw;
 // they share the fused kernels' layout, buffers, class flags, sources, probes
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
             eyu = ld_at(gE, nb + dzb + cs);
         }
         const int id = class_of<CT>(B, nb);
-        cgfloat* hf = (cgfloat*)B.hface + 3 * id;   // inverse eps_r at the Hx, Hy, Hz faces
+        cgfloat* hf = (cgfloat*)B.node_aux + 6 * id;   // inverse eps_r at the Hx, Hy, Hz faces
         // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i
         float hx = 0.f;
         if (hasx && k < c.nz) {
@@ -192,6 +194,10 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         const int id = class_of<CT>(B, nb);
         const float inv_x = ctab[id].inv_x, inv_y = ctab[id].inv_y, inv_z = ctab[id].inv_z;
         const uint32_t flags = ctab[id].flags;
+        cgfloat* loss = (cgfloat*)B.node_aux + 6 * id + 3;   // conduction of the Ex, Ey, Ez edges
+        // the PML sigma seen by each edge: / eps_r with Eq. 2's eps_rw, else as is
+        const float wx = B.eps_rw ? inv_x : 1.0f, wy = B.eps_rw ? inv_y : 1.0f,
+                    wz = B.eps_rw ? inv_z : 1.0f;
         const float hx = ld_at(nH, nb), hy = ld_at(nH, nb + cs), hz = ld_at(nH, nb + cs2);
         const bool kx = c.px || c.py, ky = c.py || pz, kz = pz || c.px;   // D kept
         const float dxo = kx ? ld_at(gD, nb) : 0.f;
@@ -201,16 +207,26 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
         if (flags & kUpdEx) {
             const float chx = (hz - ld_at(nH, nb - dyb + cs2)) * crdy - (hy - hym) * crdz;
-            const Sc Y = sc_at(cy, ny1, 0, j, inv_x), Z = sc_at(cz, nz1, 0, k, inv_x), X = sc_at(cx, nx1, 1, i, inv_x);
+            const Sc Y = sc_at(cy, ny1, 0, j, wx), Z = sc_at(cz, nz1, 0, k, wx), X = sc_at(cx, nx1, 1, i, wx);
             ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
-            exn = fmaf(Z.ca, ld_at(gE, nb), Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
+            const float exo = ld_at(gE, nb), lx = loss[0];
+            exn = fmaf(Z.ca, exo, Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
+            if (lx != 0.0f) {   // lossy interior edge; D (kept on a PML interface) gains eps_r (E' - E)
+                exn = conductive_e(exo, chx, inv_x, lx);
+                ddx = chx - lx * (exn + exo);
+            }
         }
         // Ey(i, j+1/2, k): Dy with z at k; Ey with x at i, y at j+1/2
         if (flags & kUpdEy) {
             const float chy = (hx - hxm) * crdz - (hz - ld_at(nH, nb - 4u + cs2)) * crdx;
-            const Sc Z = sc_at(cz, nz1, 0, k, inv_y), X = sc_at(cx, nx1, 0, i, inv_y), Y = sc_at(cy, ny1, 1, j, inv_y);
+            const Sc Z = sc_at(cz, nz1, 0, k, wy), X = sc_at(cx, nx1, 0, i, wy), Y = sc_at(cy, ny1, 1, j, wy);
             ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
-            eyn = fmaf(X.ca, ld_at(gE, nb + cs), X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
+            const float eyo = ld_at(gE, nb + cs), ly = loss[1];
+            eyn = fmaf(X.ca, eyo, X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
+            if (ly != 0.0f) {
+                eyn = conductive_e(eyo, chy, inv_y, ly);
+                ddy = chy - ly * (eyn + eyo);
+            }
         }
         // Ez(i, j, k+1/2): Dz with x at i; Ez with y at j, z at k+1/2
         if (flags & kUpdEz) {
@@ -230,11 +246,15 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
                     }
                 chz -= js;
             }
-            const Sc X = sc_at(cx, nx1, 0, i, inv_z), Y = sc_at(cy, ny1, 0, j, inv_z), Z = sc_at(cz, nz1, 1, k, inv_z);
+            const Sc X = sc_at(cx, nx1, 0, i, wz), Y = sc_at(cy, ny1, 0, j, wz), Z = sc_at(cz, nz1, 1, k, wz);
             const float ezo = ld_at(gE, nb + cs2);
             ddz = fmaf(X.cam1, dzo, X.rp * chz);
             ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
-            if (bs != 0.0f) ezn = resistive_ez(ezo, chz, inv_z, bs);
+            bs += loss[2];   // a resistive source's lumped conductance adds to the medium's
+            if (bs != 0.0f) {
+                ezn = conductive_e(ezo, chz, inv_z, bs);
+                ddz = chz - bs * (ezn + ezo);
+            }
         }
         st_at(dE, nb, exn);
         st_at(dE, nb + cs, eyn);

@@ -63,7 +63,7 @@ class fdtd_info(C.Structure):
                 ("n_sources", C.c_int32), ("n_probes", C.c_int32), ("n_freqs", C.c_int32),
                 ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("tile_steps", C.c_int32), ("plane_k", C.c_int32), ("plane_nf", C.c_int32),
-                ("eps_rw_passes", C.c_int32)]
+                ("node_passes", C.c_int32)]
 
 
 class FdtdError(RuntimeError):
@@ -88,6 +88,7 @@ _sigs = {
     "fdtd_set_dft_freqs": ([_P, _P, C.c_int], C.c_int),
     "fdtd_set_plane_dft": ([_P, C.c_int, _P, C.c_int], C.c_int),
     "fdtd_set_pml_eps_rw": ([_P, C.c_int], C.c_int),
+    "fdtd_set_conductivity": ([_P, _P], C.c_int),
     "fdtd_get_plane_dft": ([_P, _P, _P], C.c_int),
     "fdtd_get_plane": ([_P, C.c_int, C.c_int, _P], C.c_int),
     "fdtd_step_n": ([_P, C.c_int64], C.c_int),
@@ -235,6 +236,11 @@ def fdtd_add_voltage_probe(g, i, j, k0, k1) -> int:
 def fdtd_set_dft_freqs(g, f_hz: Sequence[float]):
     f = np.ascontiguousarray(f_hz, dtype=np.float64)
     _check(_lib.fdtd_set_dft_freqs(g, _ptr(f), len(f)))
+
+
+def fdtd_set_conductivity(g, sigma_cell: Optional[np.ndarray]):
+    sig = None if sigma_cell is None else np.ascontiguousarray(sigma_cell, dtype=np.float32)
+    _check(_lib.fdtd_set_conductivity(g, _ptr(sig)))
 
 
 def fdtd_set_pml_eps_rw(g, on: bool):
@@ -403,6 +409,8 @@ def grid_from_board(board, max_steps: Optional[int] = None, hip_stream=None,
         fdtd_set_materials(g, b.eps_r_cell, b.pec_edge_mask)
         if getattr(b, "pml_eps_rw", False):
             fdtd_set_pml_eps_rw(g, True)
+        if getattr(b, "sigma_cell", None) is not None:
+            fdtd_set_conductivity(g, b.sigma_cell)
         for s in b.sources:
             if getattr(s, "R", 0.0) > 0.0:
                 fdtd_add_voltage_source(g, s.i, s.j, s.k, s.waveform, s.J0, s.t0, s.sigma, s.R)

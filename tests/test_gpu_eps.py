@@ -67,7 +67,7 @@ def test_eps_rw_from_zero_against_oracle(F, oracle_mod, seed):
     announce(f"eps_rw board seed={seed} {b.nx}x{b.ny}x{b.nz}")
     ref = oracle_mod.run(b)
     info, probes, plane, fields = run(F, b)
-    assert info.eps_rw_passes == 1
+    assert info.node_passes == 1
     for p in range(len(b.probes)):
         if np.abs(ref.probes[p]).max() > 0:
             assert rel_l2(probes[p], ref.probes[p]) <= 1e-4, p
@@ -101,7 +101,7 @@ def test_eps_rw_random_state_few_steps(F, oracle_mod, shape, npml):
             F.fdtd_set_field(g, c, init[n].astype(np.float32))
         F.fdtd_step_n(g, b.steps)
         F.fdtd_synchronize(g)
-        assert F.fdtd_get_info(g).eps_rw_passes == 1
+        assert F.fdtd_get_info(g).node_passes == 1
         fields = gpu_fields(F, g, b)
     finally:
         F.fdtd_destroy_grid(g)
@@ -149,7 +149,7 @@ def test_eps_rw_with_the_pml_in_air_is_the_fused_path(F):
     b = boardgen.small_board(steps=60)
     on = run(F, dataclasses.replace(b, pml_eps_rw=True))
     off = run(F, b)
-    assert on[0].eps_rw_passes == 0
+    assert on[0].node_passes == 0
     assert np.array_equal(on[1], off[1])
     for n in FIELDS:
         assert np.array_equal(on[3][n], off[3][n]), n
@@ -164,7 +164,7 @@ def test_fig3_board_into_upml_against_oracle(F, oracle_mod):
     ref = oracle_mod.run(b, threads=16)
     announce("fig3 board: gpu")
     info, probes, _, _ = run(F, b)
-    assert info.eps_rw_passes == 1
+    assert info.node_passes == 1
     t = (np.arange(b.steps) + 1) * 1e-12
     for p in range(len(b.probes)):
         assert rel_l2(probes[p], ref.probes[p]) <= 1e-4, p

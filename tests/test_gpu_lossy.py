@@ -1,0 +1,126 @@
+"""Lossy dielectrics on the HIP path (the node passes), against the FP64 oracle:
+probes within 1e-4 (relative L2), all 12 arrays within 2e-5 after a few steps
+from arbitrary states, a resistive source on a lossy edge (the two conductances
+add), and the argument checks."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import boardgen
+from _util import rel_l2
+from test_gpu_parity import FIELDS, announce, compare_fields, gpu_fields, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1008_2602_amd import fdtd
+    return fdtd
+
+
+def lossy_board(seed, steps, nx=28, ny=20, nz=13):
+    b = boardgen.random_tiny(seed, nx=nx, ny=ny, nz=nz, npml=3, steps=steps)
+    rng = np.random.default_rng(seed + 11)
+    p = b.npml
+    sig = np.zeros(b.eps_r_cell.shape, np.float32)
+    inner = (slice(p[4], nz - p[5]), slice(p[2], ny - p[3]), slice(p[0], nx - p[1]))
+    sig[inner] = rng.choice([0.0, 0.02, 0.5, 3.0], size=sig[inner].shape).astype(np.float32)
+    b.sigma_cell = sig
+    i, j, k = (p[0] + nx - p[1]) // 2, (p[2] + ny - p[3]) // 2, (p[4] + nz - p[5]) // 2
+    while b.pec_edge_mask[k, j, i] & 4 or any((s.i, s.j, s.k) == (i, j, k) for s in b.sources):
+        i += 1
+    b.sources.append(boardgen.Source(i, j, k, boardgen.GAUSS, 3.0, 12e-12, 4e-12, R=15.0))
+    b.probes.append((i, j, k))
+    return b
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lossy_from_zero_against_oracle(F, oracle_mod, seed):
+    b = lossy_board(seed, steps=71)
+    announce(f"lossy board seed={seed}")
+    ref = oracle_mod.run(b)
+    g, ids = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        assert F.fdtd_get_info(g).node_passes == 1
+        probes = np.stack([F.fdtd_get_probe(g, p, b.steps) for p in ids])
+        fields = gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+    for p in range(len(b.probes)):
+        if np.abs(ref.probes[p]).max() > 0:
+            assert rel_l2(probes[p], ref.probes[p]) <= 1e-4, p
+    compare_fields(ref.state, fields, b, 2e-5)
+    # the loss matters here
+    ref0 = oracle_mod.run(dataclasses.replace(b, sigma_cell=None))
+    assert rel_l2(ref0.probes[-1], ref.probes[-1]) > 1e-2
+
+
+@pytest.mark.parametrize("eps_rw", [False, True])
+def test_lossy_random_state_few_steps(F, oracle_mod, eps_rw):
+    b = lossy_board(3, steps=5)
+    b.sources = []
+    b.pml_eps_rw = eps_rw
+    st = random_state(oracle_mod, b, seed=9)
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"lossy random state eps_rw={eps_rw}")
+    ref = oracle_mod.run(b, state=st)
+    g, _ = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        for c, n in enumerate(FIELDS):
+            F.fdtd_set_field(g, c, init[n].astype(np.float32))
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        fields = gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+    compare_fields(ref.state, fields, b, 2e-5)
+
+
+def test_lossy_table1_board_against_oracle(F, oracle_mod):
+    """The Table 1 board with a loss tangent of 0.02 at 5 GHz in its dielectric,
+    10000 steps: probe and the faster decay against the oracle."""
+    b = boardgen.lossy_dielectric(boardgen.table1_board(steps=10000, source="resistive"), 0.02)
+    announce("lossy table1: oracle")
+    ref = oracle_mod.run(b, threads=16).probes[0]
+    g, ids = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        e = F.fdtd_get_probe(g, ids[0], b.steps).astype(np.float64)
+    finally:
+        F.fdtd_destroy_grid(g)
+    assert rel_l2(e, ref) <= 1e-4
+    assert np.sqrt(np.mean(e[8000:] ** 2)) < 0.1 * np.sqrt(np.mean(e[:2000] ** 2))
+
+
+def test_conductivity_argument_errors(F):
+    b = boardgen.random_tiny(5, nx=16, ny=14, nz=12, npml=2, steps=3)
+    g, _ = F.grid_from_board(b, max_steps=3)
+    try:
+        sig = np.zeros(b.eps_r_cell.shape, np.float32)
+        bad_pml = sig.copy()
+        bad_pml[0, 5, 5] = 1.0
+        with pytest.raises(F.FdtdError) as ei:
+            F.fdtd_set_conductivity(g, bad_pml)
+        assert ei.value.code == F.FDTD_EINVAL and "PML" in str(ei.value)
+        for v in (-1.0, np.nan, np.inf):
+            x = sig.copy()
+            x[6, 6, 6] = v
+            with pytest.raises(F.FdtdError) as ei:
+                F.fdtd_set_conductivity(g, x)
+            assert ei.value.code == F.FDTD_EINVAL
+        F.fdtd_set_conductivity(g, sig)          # all zero: lossless, fused kernels
+        F.fdtd_step_n(g, 1)
+        assert F.fdtd_get_info(g).node_passes == 0
+        with pytest.raises(F.FdtdError) as ei:
+            F.fdtd_set_conductivity(g, sig)
+        assert ei.value.code == F.FDTD_ESTATE
+    finally:
+        F.fdtd_destroy_grid(g)

@@ -251,3 +251,17 @@ def test_p14_fig3_board_into_upml_decays_fig4_air_gap_rings(oracle_mod):
         e3, e4 = r3.probes[p], r4.probes[p]
         assert np.abs(e3[late]).max() < 0.05 * np.abs(e3).max(), p
         assert np.abs(e4[late]).max() > 0.4 * np.abs(e4).max(), p
+
+
+@pytest.mark.slow
+def test_p16_lossy_dielectric_shortens_the_ringing(oracle_mod):
+    """Results section: the lossless model overstates how long the board rings.
+    On the Table 1 board (resistive corner source, opposite-corner probe) a loss
+    tangent of 0.02 at 5 GHz makes the probe's rms over steps 8000-10000 fall to
+    under a fifth of the lossless board's ratio to its first 2000 steps."""
+    def ratio(b):
+        e = oracle_mod.run(b, threads=8).probes[0]
+        return np.sqrt(np.mean(e[8000:] ** 2)) / np.sqrt(np.mean(e[:2000] ** 2))
+    r0 = ratio(boardgen.table1_board(steps=10000, source="resistive"))
+    r1 = ratio(boardgen.lossy_dielectric(boardgen.table1_board(steps=10000, source="resistive"), 0.02))
+    assert r0 > 0.3 and r1 < 0.2 * r0
