@@ -19,8 +19,8 @@ Beside it, the same line carries
     short; the number is stated in the output;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
-  * "eps_rw": Eq. 2's eps_rw passes on the large board run into the PML, and
-    the paper's Fig. 3 board;
+  * "node_passes": Eq. 2's eps_rw passes on the large board run into the PML,
+    the paper's Fig. 3 board and a lossy Table 1 run;
   * "zconv": the z-convergence study (1..15 cells across the dielectric) as
     one batched call;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
@@ -169,11 +169,11 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
 
 
 def run_eps(F, torch, K=200, W=10):
-    """Eq. 2's eps_rw passes.  (1) The large board with its eps_r 4.2 slab run
-    through the x/y PML to the outer wall (1048x792x88), eps_rw on: the per-node
-    H and E passes, against the fused kernels on the same board with eps_rw = 1;
-    (2) the paper's Fig. 3 board (100x60x0.8 mm running into the UPML), 1000 steps
-    of 1 ps."""
+    """The node passes (Eq. 2's eps_rw, lossy dielectrics).  (1) The large board
+    with its eps_r 4.2 slab run through the x/y PML to the outer wall
+    (1048x792x88), eps_rw on, against the fused kernels on the same board with
+    eps_rw = 1; (2) the paper's Fig. 3 board (100x60x0.8 mm running into the
+    UPML), 1000 steps of 1 ps; (3) the Table 1 run with a lossy dielectric."""
     import boardgen
     from paper_1008_2602_amd import tune
     b = boardgen.large_board(steps=W + K)
@@ -193,7 +193,7 @@ def run_eps(F, torch, K=200, W=10):
         wall = time.perf_counter() - t0
         info = F.fdtd_get_info(g)
         F.fdtd_destroy_grid(g)
-        assert info.eps_rw_passes == (1 if rw else 0)
+        assert info.node_passes == (1 if rw else 0)
         out["eps_rw" if rw else "fused_eps_rw_1"] = {
             "ms_per_step": round(wall / K * 1e3, 4),
             "gcell_updates_per_s": round(b.cells * K / wall / 1e9, 3),
@@ -210,9 +210,23 @@ def run_eps(F, torch, K=200, W=10):
     F.fdtd_destroy_grid(g)
     out["fig3"] = {"cells": f3.cells, "steps": f3.steps, "wall_s": round(wall, 4),
                    "gcell_updates_per_s": round(f3.cells * f3.steps / wall / 1e9, 3)}
-    out["workload"] = ("large board 1048x792x88 with its eps_r 4.2 slab through the x/y PML "
-                       "(eps_rw passes vs the fused kernels at eps_rw = 1); Fig. 3 board "
-                       f"{f3.nx}x{f3.ny}x{f3.nz} running into the UPML, 1000 steps")
+    # the Table 1 run with a lossy dielectric (loss tangent 0.02 at 5 GHz)
+    t1 = boardgen.lossy_dielectric(boardgen.table1_board(steps=30000, source="resistive"), 0.02)
+    g, _ = F.grid_from_board(t1, max_steps=t1.steps)
+    F.fdtd_step_n(g, 0)
+    F.fdtd_synchronize(g)
+    t0 = time.perf_counter()
+    F.fdtd_step_n(g, t1.steps)
+    F.fdtd_synchronize(g)
+    wall = time.perf_counter() - t0
+    assert F.fdtd_get_info(g).node_passes == 1
+    F.fdtd_destroy_grid(g)
+    out["lossy_table1"] = {"cells": t1.cells, "steps": t1.steps, "wall_s": round(wall, 4),
+                           "gcell_updates_per_s": round(t1.cells * t1.steps / wall / 1e9, 3)}
+    out["workload"] = ("node passes: large board 1048x792x88 with its eps_r 4.2 slab through the "
+                       "x/y PML (eps_rw passes vs the fused kernels at eps_rw = 1); Fig. 3 board "
+                       f"{f3.nx}x{f3.ny}x{f3.nz} running into the UPML, 1000 steps; the Table 1 "
+                       "run with a loss tangent of 0.02, 30000 steps")
     return out
 
 
@@ -509,7 +523,7 @@ def main():
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
     if args.only in (None, "eps"):
-        out["eps_rw"] = run_eps(F, torch)
+        out["node_passes"] = run_eps(F, torch)
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
     if args.only in (None, "table1"):
