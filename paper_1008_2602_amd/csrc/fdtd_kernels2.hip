@@ -39,7 +39,8 @@ struct AxisCoef {
 };
 
 template <int TY, typename CT, bool PL>
-__global__ __launch_bounds__(64 * TY + 128) void field_step2(const BoardDev* __restrict__ boards,
+__global__ __launch_bounds__(64 * TY + 128)
+__attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const BoardDev* __restrict__ boards,
                                                              const TileRef* __restrict__ tiles,
                                                              int rel, int flip)
 {
@@ -440,9 +441,10 @@ struct Shape2 {
     int tx, ty;
 };
 // 64*TY + 128 threads.  TY = 14 and 12 run four waves per SIMD (128 VGPRs, a few
-// spilled); TY <= 10 runs three (the kernel's 131 VGPRs fit).  Taller tiles
-// recompute fewer halo rows per owned row.
-static const Shape2 kShapes2[] = {{64, 14}, {64, 12}, {64, 10}, {64, 9}, {64, 8}};
+// spilled); 10, 9 and 8 run three (the kernel's 131 VGPRs fit); TY = 6 is held to
+// 128 VGPRs so that two of its 512-thread blocks share a compute unit.  Taller
+// tiles recompute fewer halo rows per owned row.
+static const Shape2 kShapes2[] = {{64, 14}, {64, 12}, {64, 10}, {64, 9}, {64, 8}, {64, 6}};
 static const int kNumShapes2 = sizeof(kShapes2) / sizeof(kShapes2[0]);
 
 int num_shapes2() { return kNumShapes2; }
@@ -496,6 +498,7 @@ int field_step2_occupancy(int tile_y, bool wide)
         case 10: return occupancy2_t<10>(wide);
         case 9: return occupancy2_t<9>(wide);
         case 8: return occupancy2_t<8>(wide);
+        case 6: return occupancy2_t<6>(wide);
         default: return 1;
     }
 }
@@ -509,6 +512,7 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
         case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, plane, st);
         case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, plane, st);
         case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 6: return launch2_t<6>(boards, tiles, ntiles, rel, flip, wide, plane, st);
         default: return hipErrorInvalidValue;
     }
 }
