@@ -616,7 +616,7 @@ int finalize(fdtd_grid* g)
                                hipMemcpyHostToDevice, st));
     if (g->node_pass) {
         g->node_aux = (float*)dev_alloc(g, node_aux.size() * 4);
-        if (!g->node_aux) return fail(FDTD_ENOMEM, "face table allocation failed");
+        if (!g->node_aux) return fail(FDTD_ENOMEM, "node table allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->node_aux, node_aux.data(), node_aux.size() * 4, hipMemcpyHostToDevice, st));
     }
     HIP_OR_FAIL(hipStreamSynchronize(st));   // table and node_aux are locals
@@ -1254,7 +1254,7 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     for (int h = 0; h < ng; ++h)
         if (int e = finalize(gs[h])) return e;
-    // boards on the eps_rw passes step alone (on their own streams); the rest
+    // boards on the node passes step alone (on their own streams); the rest
     // share the batched launches
     std::vector<fdtd_grid*> fused;
     std::vector<int64_t> nfused;

@@ -36,7 +36,7 @@ static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly o
 constexpr int64_t kGuard = 64;
 
 // per-axis coefficient table: 6 quantities x {node, half node} x (n+1) entries
-// (kappa is read only by the eps_rw passes, which rebuild the others from it)
+// (kappa is read only by the node passes, which rebuild the others from it)
 enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kKappa = 5, kNumCoef = 6 };
 
 // class flags (per node): which E components are stepped, and source/probe marks
