@@ -23,12 +23,15 @@ Beside it, the same line carries
     the paper's Fig. 3 board and a lossy Table 1 run;
   * "zconv": the z-convergence study (1..15 cells across the dielectric) as
     one batched call;
+  * "shard": the large board cut into 8 y-slabs of 1048x99x88 cells (one
+    rank's share of a slab decomposition, halo stubbed), every slab timed on
+    its own;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
     one solve, and a 64-board sweep of its source resistance, with the oracle's
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1|plane|zconv|eps]
+                  [--only single|batch|serve|table1|plane|zconv|eps|shard]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -267,6 +270,54 @@ def run_zconv(F, torch, steps=4000):
     }
 
 
+def run_shard(F, torch, K=400, W=20, nranks=8):
+    """The field kernel at one rank's share of the large board slab-decomposed
+    along y (8 slabs of 1048x99x88 cells; the cut faces carry no PML and, with no
+    exchange, act as PEC walls: the halo is stubbed).  Each slab is timed on its
+    own; a decomposed step would take the slowest slab's time plus the exchange,
+    which is not built.  Reports per-slab ms per step and the HBM fraction of the
+    slowest slab's launches on their algorithmic bytes."""
+    import numpy as np
+    import boardgen
+    from paper_1008_2602_amd import tune
+    per = []
+    for rank in range(nranks):
+        board = boardgen.large_board_shard(rank, nranks)
+        tile = tune.tune_board(board)
+        g, ids = F.grid_from_board(board, max_steps=W + K, tile=tile)
+        F.fdtd_step_n(g, W)
+        F.fdtd_synchronize(g)
+        F.fdtd_set_timing(g, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fdtd_step_n(g, K)
+        F.fdtd_synchronize(g)
+        wall = time.perf_counter() - t0
+        kern_ms, launches = F.fdtd_get_timing(g)
+        info = F.fdtd_get_info(g)
+        probe = F.fdtd_get_probe(g, ids[0], W + K) if ids else np.zeros(1)
+        F.fdtd_destroy_grid(g)
+        assert np.all(np.isfinite(probe))
+        launch_s = kern_ms / 1e3 / launches
+        per.append({"rank": rank, "tile": "x".join(str(v) for v in tile),
+                    "ms_per_step": wall / K * 1e3, "launch_s": launch_s,
+                    "launch_bytes": info.step_bytes * K / launches, "cells": board.cells})
+    slow = max(per, key=lambda r: r["ms_per_step"])
+    achieved = slow["launch_bytes"] / slow["launch_s"] / 1e9
+    return {
+        "workload": f"large board split into {nranks} y-slabs of 1048x{792 // nranks}x88 cells "
+                    "(cut faces without PML, halo stubbed), each slab stepped alone",
+        "cells_per_slab": slow["cells"],
+        "steps": K,
+        "tiles": sorted({r["tile"] for r in per}),
+        "ms_per_step": [round(r["ms_per_step"], 4) for r in per],
+        "ms_per_step_slowest": round(slow["ms_per_step"], 4),
+        "gcell_updates_per_s_slowest": round(slow["cells"] / slow["ms_per_step"] / 1e6, 3),
+        "roofline_frac_slowest": round(achieved / HBM_PEAK_GBS, 4),
+        "avg_launch_ms_slowest": round(slow["launch_s"] * 1e3, 4),
+    }
+
+
 def run_batch(F, torch, K, W):
     """The 64-board variant batch, all boards advanced by K steps together."""
     import boardgen
@@ -437,7 +488,7 @@ def main():
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
     ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
-                                       "eps"], default=None)
+                                       "eps", "shard"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -526,6 +577,8 @@ def main():
         out["node_passes"] = run_eps(F, torch)
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
+    if args.only in (None, "shard"):
+        out["shard"] = run_shard(F, torch)
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:

@@ -278,6 +278,48 @@ def large_board(seed: int = 1003, steps: int = 10000) -> Board:
     return b
 
 
+def y_slab(board: Board, j0: int, j1: int) -> Board:
+    """Cells j0 <= j < j1 of ``board`` as a board of its own: the y-slab that one
+    rank of a slab decomposition along y would own.  A cut face (j0 > 0 or
+    j1 < ny) gets no PML; with no halo exchanged it is an outer PEC wall, so
+    the slab is the rank's share with its halo stubbed to zero.  Sources and
+    probes strictly between the cut faces are kept (on a face an Ez edge is
+    tangential and stays zero)."""
+    assert 0 <= j0 < j1 <= board.ny
+    npml = list(board.npml)
+    if j0 > 0:
+        npml[2] = 0
+    if j1 < board.ny:
+        npml[3] = 0
+    assert npml[2] + npml[3] < j1 - j0
+    def keep(j):
+        return (j > j0 or j0 == 0) and (j < j1 or j1 == board.ny)
+
+    b = dataclasses.replace(
+        board, name=f"{board.name}-y{j0}-{j1}", ny=j1 - j0,
+        eps_r_cell=np.ascontiguousarray(board.eps_r_cell[:, j0:j1, :]),
+        pec_edge_mask=np.ascontiguousarray(board.pec_edge_mask[:, j0:j1 + 1, :]),
+        sigma_cell=(None if board.sigma_cell is None
+                    else np.ascontiguousarray(board.sigma_cell[:, j0:j1, :])),
+        npml=tuple(npml),
+        sources=[dataclasses.replace(s, j=s.j - j0) for s in board.sources if keep(s.j)],
+        probes=[(i, j - j0, k) for (i, j, k) in board.probes if keep(j)],
+        plane_dft=board.plane_dft,
+        meta=dict(board.meta, slab=(j0, j1)))
+    b.check()
+    return b
+
+
+def large_board_shard(rank: int, nranks: int = 8, seed: int = 1003, steps: int = 10000) -> Board:
+    """Rank ``rank``'s share of the large board split into ``nranks`` equal y-slabs
+    (792 / 8 = 99 cells each: grid 1048 x 99 x 88), halo stubbed (see y_slab).
+    Only the first and last slab keep a y-PML face."""
+    full = large_board(seed, steps)
+    assert full.ny % nranks == 0 and 0 <= rank < nranks
+    h = full.ny // nranks
+    return y_slab(full, rank * h, (rank + 1) * h)
+
+
 def variant_board(rng: np.random.Generator, idx: int, steps: int = 8000,
                   n_xy: Optional[Tuple[int, int]] = None,
                   nz: Optional[int] = None) -> Board:

@@ -81,7 +81,9 @@ typedef struct {
     int64_t max_steps;
     int64_t cells;               /* nx*ny*nz (the unit of "cell-updates") */
     int64_t nodes;               /* (nx+1)(ny+1)(nz+1) */
-    int64_t step_bytes;          /* algorithmic HBM bytes one step of the field kernel must move */
+    int64_t step_bytes;          /* algorithmic HBM bytes one step of the field kernel must move:
+                                    E, H read and written and the class read per cell,
+                                    each kept D/B component read and written */
     int64_t device_bytes;        /* device memory held by the handle */
     int32_t n_sources, n_probes, n_freqs;
     int32_t n_classes;           /* distinct per-node material classes after finalisation */
@@ -245,7 +247,10 @@ int fdtd_get_plane_dft(fdtd_grid* g, double* re, double* im);
  * are the UPML auxiliaries of Eq. 4 (zero where the layout keeps none: the
  * library stores D/B only where a PML loss acts on them).  set is allowed before
  * the first step or between steps; it replaces the state at the current step.
- * Synchronises. */
+ * set stores zero for entries outside the state: a component that does not
+ * exist at the node (Ex at i = nx, ...), E tangential to the outer PEC wall, and
+ * H (and B) on the outer wall normal to itself (Hx at i = 0 or nx, ...), which
+ * touches only such E and so never changes.  Synchronises. */
 int fdtd_get_field(fdtd_grid* g, int comp, float* out);
 int fdtd_set_field(fdtd_grid* g, int comp, const float* in);
 

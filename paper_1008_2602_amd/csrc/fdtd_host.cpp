@@ -264,11 +264,16 @@ int owned_rows(int ty, int steps) { return steps == 2 ? ty - 3 : ty - 1; }
 // The one-step shape that takes the odd step of a two-step shape.
 constexpr int kOddX = 64, kOddY = 15;
 
-// Tiles of a shape: tx aligned columns and `rows` owned rows each
+// Tiles of a shape: tx aligned columns and `rows` owned rows each.  The tiles
+// cover node columns 0..nx-1 and rows 0..ny-1 (and the kernels step planes
+// 0..nz-1): a node on the far wall (i = nx, j = ny or k = nz) carries only
+// components that are tangential E on the wall (held at zero), H normal to the
+// wall (which touches nothing but such E, so it stays zero) or components that
+// do not exist, so nothing there is ever stepped.
 void tile_counts(int nx, int ny, int tx, int rows, int* cx, int* cy)
 {
-    *cx = (nx + 1 + tx - 1) / tx;
-    *cy = (ny + 1 + rows - 1) / rows;
+    *cx = (nx + tx - 1) / tx;
+    *cy = (ny + rows - 1) / rows;
 }
 
 // One launch of the field kernel of a shape (one or two steps per pass); plane:
@@ -348,13 +353,13 @@ void build_work(const std::vector<TileRef>& tiles, int slots_per_xcd, std::vecto
     }
 }
 
-// Whole tiles of board b (row-major), all planes.
+// Whole tiles of board b (row-major), planes 0..nz-1.
 void board_tiles(int b, int nx, int ny, int nz, int tx, int rows, std::vector<TileRef>& out)
 {
     int cx, cy;
     tile_counts(nx, ny, tx, rows, &cx, &cy);
     for (int y = 0; y < cy; ++y)
-        for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz + 1});
+        for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz});
 }
 
 int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide)
@@ -444,8 +449,9 @@ int64_t dev_index(const fdtd_grid* g, int i, int j, int k)
 }
 
 // Count the bytes one field step must move with this layout: E and H read and
-// written once per node, the class byte(s) once, and each stored D/B component
-// read and written once where its PML predicate holds.
+// written once per stepped node (i < nx, j < ny, k < nz: one per cell), the
+// class byte(s) once, and each stored D/B component read and written once where
+// its PML predicate holds.
 int64_t count_step_bytes(const fdtd_grid* g)
 {
     const fdtd_grid_desc& d = g->d;
@@ -453,10 +459,10 @@ int64_t count_step_bytes(const fdtd_grid* g)
         return idx < lo || (hi > 0 && idx >= n - hi);
     };
     int64_t px = 0, py = 0, pz = 0;
-    for (int i = 0; i <= d.nx; ++i) px += in_pml(i, d.nx, d.npml[0], d.npml[1]);
-    for (int j = 0; j <= d.ny; ++j) py += in_pml(j, d.ny, d.npml[2], d.npml[3]);
-    for (int k = 0; k <= d.nz; ++k) pz += in_pml(k, d.nz, d.npml[4], d.npml[5]);
-    const int64_t X = d.nx + 1, Y = d.ny + 1, Z = d.nz + 1;
+    for (int i = 0; i < d.nx; ++i) px += in_pml(i, d.nx, d.npml[0], d.npml[1]);
+    for (int j = 0; j < d.ny; ++j) py += in_pml(j, d.ny, d.npml[2], d.npml[3]);
+    for (int k = 0; k < d.nz; ++k) pz += in_pml(k, d.nz, d.npml[4], d.npml[5]);
+    const int64_t X = d.nx, Y = d.ny, Z = d.nz;
     // nodes where (a or b) holds, a/b independent predicates on two axes
     auto either = [](int64_t pa, int64_t na, int64_t pb, int64_t nb, int64_t other) {
         return (pa * nb + na * pb - pa * pb) * other;
@@ -465,7 +471,7 @@ int64_t count_step_bytes(const fdtd_grid* g)
     const int64_t aux_y = either(py, Y, pz, Z, X);  // Dy, By: y or z PML
     const int64_t aux_z = either(pz, Z, px, X, Y);  // Dz, Bz: z or x PML
     const int64_t cls_bytes = g->wide ? 2 : 1;
-    return g->nodes * (24 + 24 + cls_bytes) + (aux_x + aux_y + aux_z) * 2 * 8;
+    return X * Y * Z * (24 + 24 + cls_bytes) + (aux_x + aux_y + aux_z) * 2 * 8;
 }
 
 }  // namespace
@@ -1623,12 +1629,29 @@ int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
     // auxiliaries exist only where their PML predicate holds
     auto in_pml = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
     const int axis = comp >= FDTD_DX ? (comp - FDTD_DX) % 3 : -1;
+    // E-like components (E, D) and H-like ones (H, B) by axis
+    const bool e_like = comp <= FDTD_EZ || (comp >= FDTD_DX && comp <= FDTD_DZ);
+    const int u = comp % 3;
+    const int n3[3] = {d.nx, d.ny, d.nz};
     for (int k = 0; k <= d.nz; ++k)
         for (int j = 0; j <= d.ny; ++j)
             for (int i = 0; i <= d.nx; ++i) {
                 const int64_t n = node_index(g, i, j, k);
+                // state entries only: an E edge exists for index < n along its own
+                // axis and is tangential to the wall (held at zero) at 0 or n along
+                // the others; an H face exists for index < n along the other two
+                // axes and, on the wall normal to it (0 or n along its own axis),
+                // touches only such E edges, so it carries nothing either
+                const int q[3] = {i, j, k};
                 bool keep = true;
-                if (axis >= 0) {
+                for (int a = 0; a < 3; ++a) {
+                    const bool own = a == u;
+                    if (e_like ? own : !own)
+                        keep &= q[a] < n3[a];
+                    else
+                        keep &= q[a] > 0 && q[a] < n3[a];
+                }
+                if (keep && axis >= 0) {
                     const bool px = in_pml(i, d.nx, d.npml[0], d.npml[1]);
                     const bool py = in_pml(j, d.ny, d.npml[2], d.npml[3]);
                     const bool pz = in_pml(k, d.nz, d.npml[4], d.npml[5]);

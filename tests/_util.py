@@ -4,7 +4,8 @@ import numpy as np
 
 def live_masks(board):
     """Boolean masks of the entries each oracle array actually carries: E edges
-    that are updated (not on the outer wall, not PEC) and H faces that exist."""
+    that are updated (not on the outer wall, not PEC) and H faces that exist and
+    do not lie on the outer wall normal to themselves."""
     nx, ny, nz = board.nx, board.ny, board.nz
     kk = np.arange(nz + 1)[:, None, None]
     jj = np.arange(ny + 1)[None, :, None]
@@ -15,9 +16,11 @@ def live_masks(board):
     m["ex"] = (ii < nx) & (jj >= 1) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 1) == 0)
     m["ey"] = (ii >= 1) & (ii < nx) & (jj < ny) & (kk >= 1) & (kk < nz) & ((pec & 2) == 0)
     m["ez"] = (ii >= 1) & (ii < nx) & (jj >= 1) & (jj < ny) & (kk < nz) & ((pec & 4) == 0)
-    m["hx"] = np.broadcast_to((jj < ny) & (kk < nz), shp)
-    m["hy"] = np.broadcast_to((ii < nx) & (kk < nz), shp)
-    m["hz"] = np.broadcast_to((ii < nx) & (jj < ny), shp)
+    # an H face on the outer wall normal to it (Hx at i = 0 or nx, ...) touches only
+    # E edges tangential to that wall, which stay zero: it carries nothing
+    m["hx"] = (ii >= 1) & (ii < nx) & (jj < ny) & (kk < nz)
+    m["hy"] = (jj >= 1) & (jj < ny) & (ii < nx) & (kk < nz)
+    m["hz"] = (kk >= 1) & (kk < nz) & (ii < nx) & (jj < ny)
     for a, f in (("ddx", "ex"), ("ddy", "ey"), ("ddz", "ez"),
                  ("bbx", "hx"), ("bby", "hy"), ("bbz", "hz")):
         m[a] = m[f]

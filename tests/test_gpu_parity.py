@@ -332,7 +332,7 @@ def test_info_and_state_errors(F):
         F.fdtd_add_probe(g, 5, 5, 5)      # after the first step
     assert ei.value.code == F.FDTD_ESTATE
     info = F.fdtd_get_info(g)
-    assert info.step == 10 and info.step_bytes > 48 * info.nodes
+    assert info.step == 10 and info.step_bytes >= 49 * info.cells
     F.fdtd_destroy_grid(g)
 
 

@@ -5,6 +5,10 @@
 * P9  the wavefront reaches the board's y edge after ~300 ps (Results, Fig. 4 text)
 * Eq. 9 with eps_r = 4.0 reproduces Table 1's predicted column
 * P6  the Table 1 board's FDTD peaks against the paper's modelled column (loose)
+* X3  a y-slab with its halo stubbed evolves bitwise like the whole board away
+      from its cut faces (the locality a slab decomposition relies on)
+* X4  H faces on the outer wall normal to themselves touch nothing: the state
+      without them evolves bitwise as with them
 """
 import os
 
@@ -265,3 +269,69 @@ def test_p16_lossy_dielectric_shortens_the_ringing(oracle_mod):
     r0 = ratio(boardgen.table1_board(steps=10000, source="resistive"))
     r1 = ratio(boardgen.lossy_dielectric(boardgen.table1_board(steps=10000, source="resistive"), 0.02))
     assert r0 > 0.3 and r1 < 0.2 * r0
+
+
+def test_x3_y_slab_locality(oracle_mod):
+    """Yee's stencil reaches one cell per half-step pair, so after s steps from the
+    same state a y-slab of a board (cut faces without PML, held at zero) and the
+    whole board agree bitwise on every row more than s + 1 cells from a cut face,
+    and differ next to it.  Slabs with and without the board's own y-PML faces."""
+    from _util import live_masks
+    steps = 6
+    b = boardgen.small_board(steps=steps)
+    b.sources, b.probes, b.dft_freqs = [], [], None
+    rng = np.random.default_rng(31)
+    st = oracle_mod.new_state(b)
+    m = live_masks(b)
+    for n in oracle_mod.FIELD_NAMES:
+        st[n][...] = rng.standard_normal(st[n].shape) * m[n]
+    init = {n: st[n].copy() for n in oracle_mod.FIELD_NAMES}
+    whole = oracle_mod.run(b, state=st, threads=8).state
+    margin = steps + 2
+    for j0, j1 in ((0, 30), (30, 50), (50, b.ny)):
+        sl = boardgen.y_slab(b, j0, j1)
+        ms = live_masks(sl)
+        ss = oracle_mod.new_state(sl)
+        for n in oracle_mod.FIELD_NAMES:
+            ss[n][...] = init[n][:, j0:j1 + 1, :] * ms[n]
+        part = oracle_mod.run(sl, state=ss, threads=8).state
+        lo = margin if j0 > 0 else 0
+        hi = (j1 - j0) - margin if j1 < b.ny else j1 - j0
+        for n in oracle_mod.FIELD_NAMES:
+            assert np.array_equal(part[n][:, lo:hi + 1, :], whole[n][:, j0 + lo:j0 + hi + 1, :]), (j0, n)
+        cut = 0 if j0 > 0 else j1 - j0 - 1
+        assert not np.array_equal(part["hz"][:, cut, :], whole["hz"][:, j0 + cut, :])
+
+
+def test_x4_wall_normal_h_is_decoupled(oracle_mod):
+    """Hx on the x walls (and Hy, Hz likewise) sits between E edges tangential to
+    the wall, which stay zero, so it neither feeds nor is fed by the rest of the
+    state.  Random values there (and in their B) change no other entry after many
+    steps, and from zero they stay zero; PML on some faces, none on others."""
+    from _util import live_masks
+    b = boardgen.random_tiny(5, nx=12, ny=11, nz=9, npml=2, steps=25)
+    b.npml = (2, 0, 3, 2, 0, 2)
+    rng = np.random.default_rng(8)
+    m = live_masks(b)
+    nx, ny, nz = b.nx, b.ny, b.nz
+    kk = np.arange(nz + 1)[:, None, None]
+    jj = np.arange(ny + 1)[None, :, None]
+    ii = np.arange(nx + 1)[None, None, :]
+    wall = {"hx": ((ii == 0) | (ii == nx)) & (jj < ny) & (kk < nz),
+            "hy": ((jj == 0) | (jj == ny)) & (ii < nx) & (kk < nz),
+            "hz": ((kk == 0) | (kk == nz)) & (ii < nx) & (jj < ny)}
+    wall.update({"bb" + n[1]: v for n, v in list(wall.items())})
+    base = oracle_mod.new_state(b)
+    for n in oracle_mod.FIELD_NAMES:
+        base[n][...] = rng.standard_normal(base[n].shape) * m[n]
+    noisy = {n: base[n].copy() for n in oracle_mod.FIELD_NAMES}
+    noisy["step"] = 0
+    for n, w in wall.items():
+        assert not (w & m[n]).any()
+        noisy[n][w] = rng.standard_normal(int(w.sum()))
+    a = oracle_mod.run(b, state=base).state
+    c = oracle_mod.run(b, state=noisy).state
+    for n in oracle_mod.FIELD_NAMES:
+        w = wall.get(n, np.zeros(a[n].shape, bool))
+        assert np.array_equal(a[n][~w], c[n][~w]), n
+        assert not a[n][w].any(), n
