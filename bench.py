@@ -498,8 +498,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one MI355X: this build has no multi-GPU path "
-              "(boards shard whole across GPUs by design; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one MI355X: the library has no multi-GPU path "
+              "(boards shard whole across GPUs by design).", file=sys.stderr)
         sys.exit(2)
 
     import torch
