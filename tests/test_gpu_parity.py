@@ -167,6 +167,64 @@ def test_random_state_few_steps(F, orc, shape, npml, tile):
     compare_fields(ref.state, fields, b, 2e-5)
 
 
+@pytest.mark.parametrize("shape,npml", [((64, 22, 5), (2, 2, 2, 2, 1, 1)),
+                                        ((128, 14, 4), (1, 1, 1, 1, 1, 1)),
+                                        ((2, 2, 2), (0, 0, 0, 0, 0, 0)),
+                                        ((2, 9, 3), (0, 0, 1, 1, 0, 0)),
+                                        ((65, 2, 2), (1, 1, 0, 0, 0, 0))])
+@pytest.mark.parametrize("tile", [None, TWO_STEP, (64, 15, 1)])
+def test_exact_tile_multiples_and_degenerate_shapes(F, orc, shape, npml, tile):
+    """Grids whose cells fill the tiles exactly (nx a multiple of 64, ny of the
+    owned rows: 11 for 64x14x2, 7 for 64x10x2, 14 for 64x15x1), so that the far
+    wall's nodes fall outside every tile, and grids of the smallest size the
+    library takes (two cells) in a direction.
+    Three or four steps from an arbitrary state with sources, against the oracle."""
+    nx, ny, nz = shape
+    eps, mask = boardgen.air(nx, ny, nz)
+    rng = np.random.default_rng(nx * 7 + ny * 3 + nz)
+    eps[:] = rng.choice([1.0, 3.3], size=eps.shape).astype(np.float32)
+    b = boardgen.Board(f"edge{nx}x{ny}x{nz}", nx, ny, nz, 0.5e-3, 0.6e-3, 0.3e-3, eps, mask,
+                       npml=npml, steps=3 if tile == (64, 15, 1) else 4)
+    b.sources = [boardgen.Source(nx // 2, ny // 2, nz // 2, boardgen.GAUSS, 1e6, 0.0, 1e-12)]
+    b.probes = [(nx // 2, ny // 2, nz // 2), (nx - 1, ny - 1, nz - 1)]
+    st = random_state(orc, b, seed=nx + 2 * ny + 5 * nz)
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"exact multiples / degenerate {shape} npml={npml} tile={tile}")
+    ref = orc.run(b, state=st)
+    probes, fields, _, _ = gpu_run(F, b, init=init, tile=tile)
+    compare_fields(ref.state, fields, b, 2e-5)
+    assert rel_l2(probes, ref.probes) <= 2e-5
+
+
+def test_set_field_keeps_only_state_entries(F):
+    """Entries outside the state (components that do not exist at a node, E
+    tangential to the outer wall, H normal to the wall on it) are stored as zero,
+    and a step leaves them zero."""
+    b = boardgen.random_tiny(3, nx=70, ny=12, nz=6, npml=1, steps=2)
+    shp = (b.nz + 1, b.ny + 1, b.nx + 1)
+    m = live_masks(b)
+    am = aux_masks(b)
+    axis = {"ddx": "x", "ddy": "y", "ddz": "z", "bbx": "x", "bby": "y", "bbz": "z"}
+    announce("set_field outside the state")
+    g, _ = F.grid_from_board(b, max_steps=4)
+    try:
+        rng = np.random.default_rng(5)
+        for c, n in enumerate(FIELDS):
+            F.fdtd_set_field(g, c, rng.standard_normal(shp).astype(np.float32))
+        for step in range(2):
+            for c, n in enumerate(FIELDS):
+                got = F.fdtd_get_field(g, c, shp)
+                keep = m[n] & am[axis[n]] if n in axis else m[n].copy()
+                if n in ("ex", "ey", "ez", "ddx", "ddy", "ddz"):
+                    keep |= (b.pec_edge_mask & {"x": 1, "y": 2, "z": 4}[n[-1]]) != 0   # PEC edges: caller's business
+                assert not got[~keep].any(), (step, n)
+                if step == 0:
+                    assert got[keep & m[n]].any(), n
+            F.fdtd_step_n(g, 1)
+    finally:
+        F.fdtd_destroy_grid(g)
+
+
 def test_small_board_full_run_parity(F, orc):
     b = boardgen.small_board()
     announce(f"small board full {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
