@@ -303,22 +303,22 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         const bool okk = ib && k <= nz;
         const bool pz = in_pz(k);
         float h1x = 0.f, h1y = 0.f, h1z = 0.f, b1x = 0.f, b1y = 0.f, b1z = 0.f;
+        if (rH1 && okk) {
+            const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
+            const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
+            const float dbx = fmaf(Y.cam1_h, o.bx, -Y.rp_h * cxe);
+            h1x = fmaf(Zk.ca_h, o.hx, Zk.rp_h * fmaf(X.ph_n, dbx, X.q_n * o.bx));
+            const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
+            const float dby = fmaf(Zk.cam1_h, o.by, -Zk.rp_h * cye);
+            h1y = fmaf(X.ca_h, o.hy, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * o.by));
+            const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
+            const float dbz = fmaf(X.cam1_h, o.bz, -X.rp_h * cze);
+            h1z = fmaf(Y.ca_h, o.hz, Y.rp_h * fmaf(Zk.ph_n, dbz, Zk.q_n * o.bz));
+            b1x = (px || py) ? o.bx + dbx : 0.f;
+            b1y = (py || pz) ? o.by + dby : 0.f;
+            b1z = (pz || px) ? o.bz + dbz : 0.f;
+        }
         if (rH1) {
-            if (okk) {
-                const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
-                const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
-                const float dbx = fmaf(Y.cam1_h, o.bx, -Y.rp_h * cxe);
-                h1x = fmaf(Zk.ca_h, o.hx, Zk.rp_h * fmaf(X.ph_n, dbx, X.q_n * o.bx));
-                const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
-                const float dby = fmaf(Zk.cam1_h, o.by, -Zk.rp_h * cye);
-                h1y = fmaf(X.ca_h, o.hy, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * o.by));
-                const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
-                const float dbz = fmaf(X.cam1_h, o.bz, -X.rp_h * cze);
-                h1z = fmaf(Y.ca_h, o.hz, Y.rp_h * fmaf(Zk.ph_n, dbz, Zk.q_n * o.bz));
-                b1x = (px || py) ? o.bx + dbx : 0.f;
-                b1y = (py || pz) ? o.by + dby : 0.f;
-                b1z = (pz || px) ? o.bz + dbz : 0.f;
-            }
             sH1x[r][c] = h1x;
             sH1y[r][c] = h1y;
             sH1z[r][c] = h1z;
@@ -328,30 +328,30 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         // ---- E1 of plane k: D then E, step n -> n+1
         float e1x = 0.f, e1y = 0.f, e1z = 0.f, d1x = 0.f, d1y = 0.f, d1z = 0.f;
         const int e = cur;   // E1 plane slot of plane k (plane k-1 is in e ^ 1)
+        if (rE1 && okk) {
+            const ClassEntry ce = class_entry(o.c);
+            const int node = (int)(node0b >> 2) + k * sz;   // node index (source/probe match)
+            const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
+            const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
+            const float ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
+            float exn = fmaf(Zk.ca_n, exo, Zk.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * o.dx)));
+            const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
+            const float ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
+            float eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
+            const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
+            float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
+            float ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
+            if (ce.flags & kSrcEz) source_ez(node, step, chz, ezo, o.dz, ce.inv_z, Zk, ddz, ezn);
+            e1x = (ce.flags & kUpdEx) ? exn : 0.0f;
+            e1y = (ce.flags & kUpdEy) ? eyn : 0.0f;
+            e1z = (ce.flags & kUpdEz) ? ezn : 0.0f;
+            d1x = ((px || py) && (ce.flags & kUpdEx)) ? o.dx + ddx : o.dx;
+            d1y = ((py || pz) && (ce.flags & kUpdEy)) ? o.dy + ddy : o.dy;
+            d1z = ((pz || px) && (ce.flags & kUpdEz)) ? o.dz + ddz : o.dz;
+            if (own && k >= kb && k < ke && (ce.flags & kPrbEz)) record_probe(node, step, e1z);
+            if (PL && own && k >= kb && k < ke && (ce.flags & kPlnEz)) plane_sample(0, e1z);
+        }
         if (rE1) {
-            if (okk) {
-                const ClassEntry ce = class_entry(o.c);
-                const int node = (int)(node0b >> 2) + k * sz;   // node index (source/probe match)
-                const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
-                const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
-                const float ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
-                float exn = fmaf(Zk.ca_n, exo, Zk.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * o.dx)));
-                const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
-                const float ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
-                float eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
-                const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
-                float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
-                float ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
-                if (ce.flags & kSrcEz) source_ez(node, step, chz, ezo, o.dz, ce.inv_z, Zk, ddz, ezn);
-                e1x = (ce.flags & kUpdEx) ? exn : 0.0f;
-                e1y = (ce.flags & kUpdEy) ? eyn : 0.0f;
-                e1z = (ce.flags & kUpdEz) ? ezn : 0.0f;
-                d1x = ((px || py) && (ce.flags & kUpdEx)) ? o.dx + ddx : o.dx;
-                d1y = ((py || pz) && (ce.flags & kUpdEy)) ? o.dy + ddy : o.dy;
-                d1z = ((pz || px) && (ce.flags & kUpdEz)) ? o.dz + ddz : o.dz;
-                if (own && k >= kb && k < ke && (ce.flags & kPrbEz)) record_probe(node, step, e1z);
-                if (PL && own && k >= kb && k < ke && (ce.flags & kPlnEz)) plane_sample(0, e1z);
-            }
             sE1x[e][r][c] = e1x;
             sE1y[e][r][c] = e1y;
             sE1z[e][r][c] = e1z;
@@ -364,29 +364,29 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         const AxisCoef Zm = z_coef(m);
         const bool pzm = in_pz(m);
         float h2x = 0.f, h2y = 0.f, h2z = 0.f;
-        if (rH2) {
-            if (okm) {
-                const int pe = e ^ 1;
-                const float exo = sE1x[pe][r][c], eyo = sE1y[pe][r][c], ezo = sE1z[pe][r][c];
-                const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
-                const float dbx = fmaf(Y.cam1_h, p_b1x, -Y.rp_h * cxe);
-                h2x = fmaf(Zm.ca_h, p_h1x, Zm.rp_h * fmaf(X.ph_n, dbx, X.q_n * p_b1x));
-                const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
-                const float dby = fmaf(Zm.cam1_h, p_b1y, -Zm.rp_h * cye);
-                h2y = fmaf(X.ca_h, p_h1y, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * p_b1y));
-                const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
-                const float dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
-                h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
-                if (own && livem) {
-                    const uint32_t nb = node0b + (uint32_t)m * szb;
-                    st_at(dH, nb, h2x);
-                    st_at(dH, nb + cs, h2y);
-                    st_at(dH, nb + cs2, h2z);
-                    if (px || py) st_at(dB, nb, p_b1x + dbx);
-                    if (py || pzm) st_at(dB, nb + cs, p_b1y + dby);
-                    if (pzm || px) st_at(dB, nb + cs2, p_b1z + dbz);
-                }
+        if (rH2 && okm) {
+            const int pe = e ^ 1;
+            const float exo = sE1x[pe][r][c], eyo = sE1y[pe][r][c], ezo = sE1z[pe][r][c];
+            const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
+            const float dbx = fmaf(Y.cam1_h, p_b1x, -Y.rp_h * cxe);
+            h2x = fmaf(Zm.ca_h, p_h1x, Zm.rp_h * fmaf(X.ph_n, dbx, X.q_n * p_b1x));
+            const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
+            const float dby = fmaf(Zm.cam1_h, p_b1y, -Zm.rp_h * cye);
+            h2y = fmaf(X.ca_h, p_h1y, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * p_b1y));
+            const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
+            const float dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
+            h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
+            if (own && livem) {
+                const uint32_t nb = node0b + (uint32_t)m * szb;
+                st_at(dH, nb, h2x);
+                st_at(dH, nb + cs, h2y);
+                st_at(dH, nb + cs2, h2z);
+                if (px || py) st_at(dB, nb, p_b1x + dbx);
+                if (py || pzm) st_at(dB, nb + cs, p_b1y + dby);
+                if (pzm || px) st_at(dB, nb + cs2, p_b1z + dbz);
             }
+        }
+        if (rH2) {
             sH2x[r][c] = h2x;
             sH2y[r][c] = h2y;
             sH2z[r][c] = h2z;
