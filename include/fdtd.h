@@ -214,8 +214,10 @@ int fdtd_step_many(fdtd_grid* const* g, int ng, const int64_t* n);
 
 /* Upper bound of the device memory (bytes) fdtd_create_grid with this
  * descriptor, plus the given numbers of sources, probes and DFT frequencies, can
- * allocate over the handle's life (for admission by HBM footprint).  Negative
- * FDTD_EINVAL on a bad descriptor. */
+ * allocate over the handle's life (for admission by HBM footprint).  A plane DFT
+ * (fdtd_set_plane_dft) comes on top: 128 B + 16 B per frequency for each padded
+ * node of one plane, plus 520 B per frequency.  Negative FDTD_EINVAL on a bad
+ * descriptor. */
 int64_t fdtd_estimate_bytes(const fdtd_grid_desc* desc, int n_sources, int n_probes, int n_freqs);
 
 /* Spectrum of probe `id` over the steps run so far (Results section, Fig. 5):

@@ -34,7 +34,7 @@ hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int re
                            bool wide, hipStream_t st);
 hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
                              double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
-                             double* re, double* im, hipStream_t st);
+                             double* tw, double* re, double* im, hipStream_t st);
 hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
                       double dt, int64_t s0, int64_t s1, double* re, double* im, hipStream_t st);
 hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
@@ -138,6 +138,7 @@ struct fdtd_grid {
     double* dft_im = nullptr;
     float* plane_ring = nullptr;    // kPlaneRing slots of one padded plane
     double* plane_f = nullptr;
+    double* plane_tw = nullptr;     // [nf][kPlaneRing] (cos, -sin) * dt of one fold
     double* plane_re = nullptr;     // [nf][ny+1][pitch]
     double* plane_im = nullptr;
     int64_t* step_dev = nullptr;
@@ -677,9 +678,10 @@ int finalize(fdtd_grid* g)
         const int pf = (int)g->plane_freqs.size();
         g->plane_ring = (float*)dev_alloc(g, (size_t)kPlaneRing * pn * 4);
         g->plane_f = (double*)dev_alloc(g, (size_t)pf * 8);
+        g->plane_tw = (double*)dev_alloc(g, (size_t)pf * kPlaneRing * 16);
         g->plane_re = (double*)dev_alloc(g, (size_t)pf * pn * 8);
         g->plane_im = (double*)dev_alloc(g, (size_t)pf * pn * 8);
-        if (!g->plane_ring || !g->plane_f || !g->plane_re || !g->plane_im)
+        if (!g->plane_ring || !g->plane_f || !g->plane_tw || !g->plane_re || !g->plane_im)
             return fail(FDTD_ENOMEM, "plane DFT allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->plane_f, g->plane_freqs.data(), (size_t)pf * 8,
                                    hipMemcpyHostToDevice, st));
@@ -1115,7 +1117,7 @@ static int fold_plane(fdtd_grid* g, int64_t rel_from, int64_t rel_to, hipStream_
     if (g->plane_k < 0) return FDTD_OK;
     HIP_OR_FAIL(launch_plane_fold(g->plane_ring, g->pitch * (g->d.ny + 1), g->plane_f,
                                   (int)g->plane_freqs.size(), g->dt, g->step_dev, rel_from, rel_to,
-                                  g->plane_re, g->plane_im, st));
+                                  g->plane_tw, g->plane_re, g->plane_im, st));
     return FDTD_OK;
 }
 
@@ -1447,6 +1449,7 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* d, int n_sources, int n_probes
     int64_t t = 8 * r(3 * component_stride(nodes));                             // fields
     t += r(2 * (nodes + kGuard));                                               // class map (upper bound)
     t += r(65535 * (int64_t)sizeof(ClassEntry));                                // class table (upper bound)
+    t += r(65535 * 6 * 4);                                                      // node-pass class data (upper bound)
     t += r((int64_t)kNumCoef * 2 * (d->nx + 1) * 4) + r((int64_t)kNumCoef * 2 * (d->ny + 1) * 4) +
          r((int64_t)kNumCoef * 2 * (d->nz + 1) * 4);                            // coefficients
     t += 2 * r(4 * (int64_t)n_sources) + r(4 * (int64_t)n_sources * d->max_steps);   // sources

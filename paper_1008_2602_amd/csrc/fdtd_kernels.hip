@@ -436,58 +436,67 @@ __global__ void dft_accumulate(const float* __restrict__ series, int64_t max_ste
     im[p * nf + q] += ai * dt;
 }
 
-// Fold the ring samples of steps [s0, s1) (s1 - s0 <= kPlaneRing; s0, s1 are
+// Twiddles of one fold: tw[f][q] = (cos, -sin)(2 pi f (s0 + q + 1) dt) * dt for
+// the steps s0 + q of the fold (s0 = device step counter + rel_from), computed
+// once per fold so that the fold reads them as wave-uniform scalar loads.
+__global__ __launch_bounds__(256) void plane_twiddle(const double* __restrict__ freqs, int nf,
+                                                     double dt, const int64_t* __restrict__ step,
+                                                     int64_t rel_from, int n, double* __restrict__ tw)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * kPlaneRing) return;
+    const int f = t / kPlaneRing, q = t % kPlaneRing;
+    double cs = 0.0, sn = 0.0;
+    if (q < n) {
+        double turns = freqs[f] * dt * (double)(step[0] + rel_from + q + 1);
+        turns -= floor(turns);
+        sincospi(2.0 * turns, &sn, &cs);
+    }
+    tw[2 * t] = cs * dt;
+    tw[2 * t + 1] = -sn * dt;
+}
+
+// Fold the ring samples of steps [s0, s1) (s1 - s0 = n <= kPlaneRing; s0, s1 are
 // the device step counter plus rel_from, rel_to) into the plane accumulators:
 // A_f(node) += e_s(node) exp(-i 2 pi f (s+1) dt) dt for each s in order, the
 // probe DFT's definition applied to every node of the plane.  Every sample is
 // added to the accumulator on its own, so the result does not depend on how the
 // steps were grouped into folds.  One thread per node (padded row layout); the
-// twiddles (times dt) of kPlaneFreqs frequencies at a time sit in LDS.
-constexpr int kPlaneFreqs = 8;
+// twiddles come from plane_twiddle's table through the scalar cache.
 __global__ __launch_bounds__(256) void plane_fold(const float* __restrict__ ring, int64_t plane_nodes,
-                                                  const double* __restrict__ freqs, int nf, double dt,
-                                                  const int64_t* __restrict__ step, int64_t rel_from,
-                                                  int64_t rel_to, double* __restrict__ re,
-                                                  double* __restrict__ im)
+                                                  int nf, const int64_t* __restrict__ step,
+                                                  int64_t rel_from, int n,
+                                                  const double* __restrict__ tw,
+                                                  double* __restrict__ re, double* __restrict__ im)
 {
-    static_assert(kPlaneFreqs * kPlaneRing == 256, "one twiddle per thread");
-    __shared__ double tc[kPlaneFreqs][kPlaneRing], ts[kPlaneFreqs][kPlaneRing];
     const int64_t s0 = step[0] + rel_from;
-    const int n = (int)(rel_to - rel_from);
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool ok = node < plane_nodes;
+    if (node >= plane_nodes) return;
     float e[kPlaneRing];
 #pragma unroll
     for (int q = 0; q < kPlaneRing; ++q)
-        e[q] = (ok && q < n) ? ring[(int64_t)((s0 + q) & (kPlaneRing - 1)) * plane_nodes + node] : 0.0f;
-    const int tf = threadIdx.x / kPlaneRing, tq = threadIdx.x % kPlaneRing;
-    for (int f0 = 0; f0 < nf; f0 += kPlaneFreqs) {
-        if (f0 + tf < nf && tq < n) {
-            double turns = freqs[f0 + tf] * dt * (double)(s0 + tq + 1);
-            turns -= floor(turns);
-            double sn, cs;
-            sincospi(2.0 * turns, &sn, &cs);
-            tc[tf][tq] = cs * dt;
-            ts[tf][tq] = -sn * dt;
+        e[q] = q < n ? ring[(int64_t)((s0 + q) & (kPlaneRing - 1)) * plane_nodes + node] : 0.0f;
+    // the next frequency's accumulators are loaded while this one's are summed
+    double ar = re[node], ai = im[node];
+    for (int f = 0; f < nf; ++f) {
+        const int64_t a = (int64_t)f * plane_nodes + node;
+        double nr = 0.0, ni = 0.0;
+        if (f + 1 < nf) {
+            nr = re[a + plane_nodes];
+            ni = im[a + plane_nodes];
         }
-        __syncthreads();
-        if (ok) {
-            const int fe = min(kPlaneFreqs, nf - f0);
-            for (int fl = 0; fl < fe; ++fl) {
-                const int64_t a = (int64_t)(f0 + fl) * plane_nodes + node;
-                double ar = re[a], ai = im[a];
+        const double* w = tw + 2 * kPlaneRing * f;
+        // slots q >= n hold e = 0 and zero twiddles: those terms add exact zeros
 #pragma unroll
-                for (int q = 0; q < kPlaneRing; ++q)
-                    if (q < n) {
-                        const double v = (double)e[q];
-                        ar = fma(v, tc[fl][q], ar);
-                        ai = fma(v, ts[fl][q], ai);
-                    }
-                re[a] = ar;
-                im[a] = ai;
-            }
+        for (int q = 0; q < kPlaneRing; ++q) {
+            const double v = (double)e[q];
+            ar = fma(v, w[2 * q], ar);
+            ai = fma(v, w[2 * q + 1], ai);
         }
-        __syncthreads();
+        re[a] = ar;
+        im[a] = ai;
+        ar = nr;
+        ai = ni;
     }
 }
 
@@ -615,12 +624,17 @@ hipError_t launch_dft(const float* series, int64_t max_steps, const double* freq
 
 hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
                              double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
-                             double* re, double* im, hipStream_t st)
+                             double* tw, double* re, double* im, hipStream_t st)
 {
     if (nf <= 0 || rel_to <= rel_from) return hipSuccess;
     if (rel_to - rel_from > kPlaneRing) return hipErrorInvalidValue;
+    const int n = (int)(rel_to - rel_from);
+    hipLaunchKernelGGL(plane_twiddle, dim3((unsigned)((nf * kPlaneRing + 255) / 256)), dim3(256), 0,
+                       st, freqs, nf, dt, step, rel_from, n, tw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(plane_fold, dim3((unsigned)((plane_nodes + 255) / 256)), dim3(256), 0, st,
-                       ring, plane_nodes, freqs, nf, dt, step, rel_from, rel_to, re, im);
+                       ring, plane_nodes, nf, step, rel_from, n, (const double*)tw, re, im);
     return hipGetLastError();
 }
 
