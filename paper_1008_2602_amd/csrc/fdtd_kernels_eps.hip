@@ -44,7 +44,13 @@ struct ColCtx {
     int par;
 };
 
-// One thread per (i, j) column and z chunk of zl planes, marching up in z.
+// One thread per (i, j) column and z chunk of zl planes, marching up in z.  Only
+// nodes with i < nx, j < ny, k < nz are stepped: a node on the far wall holds
+// only E tangential to the wall, H normal to it (which touches only such E) or
+// components that do not exist, all zero.  Every neighbour a stepped node reads
+// at +1 is then inside the arrays; the E pass clamps those at -1 to the node
+// itself on the low walls (the components that read them are tangential there,
+// held at zero), so its loads need no branch.
 __device__ __forceinline__ bool col_ctx(const BoardDev& B, int flip, ColCtx& c)
 {
     c.i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,7 +58,7 @@ __device__ __forceinline__ bool col_ctx(const BoardDev& B, int flip, ColCtx& c)
     c.nx = B.nx;
     c.ny = B.ny;
     c.nz = B.nz;
-    if (c.i > c.nx || c.j > c.ny) return false;
+    if (c.i >= c.nx || c.j >= c.ny) return false;
     c.sy = B.pitch;
     c.sz = B.pitch * (c.ny + 1);
     c.nb0 = (uint32_t)(c.i + c.j * c.sy) * 4u;
@@ -65,7 +71,7 @@ __device__ __forceinline__ bool col_ctx(const BoardDev& B, int flip, ColCtx& c)
 __device__ __forceinline__ void col_chunk(int zl, ColCtx& c)
 {
     c.k0 = blockIdx.z * zl;
-    c.k1 = min(c.k0 + zl, c.nz + 1);
+    c.k1 = min(c.k0 + zl, c.nz);
 }
 
 template <typename CT>
@@ -98,22 +104,20 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
     const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
     const int i = c.i, j = c.j;
-    const bool hasx = j < c.ny, hasy = i < c.nx, hasz = i < c.nx && j < c.ny;
     float exo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb), eyo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb + cs);
     for (int k = c.k0; k < c.k1; ++k) {
         const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
         const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
         const float ezo = ld_at(gE, nb + cs2);
-        float exu = 0.f, eyu = 0.f;
-        if (k < c.nz) {
-            exu = ld_at(gE, nb + dzb);
-            eyu = ld_at(gE, nb + dzb + cs);
-        }
+        const float exu = ld_at(gE, nb + dzb), eyu = ld_at(gE, nb + dzb + cs);
         const int id = class_of<CT>(B, nb);
         cgfloat* hf = (cgfloat*)B.node_aux + 6 * id;   // inverse eps_r at the Hx, Hy, Hz faces
-        // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i
-        float hx = 0.f;
-        if (hasx && k < c.nz) {
+        // Hx(i, j+1/2, k+1/2): Bx with y at j+1/2; Hx with z at k+1/2, x at i.  B is
+        // read only where a PML keeps it: the branch also keeps each component's
+        // loads next to their use, which holds the register count (and so the
+        // occupancy) of this streaming pass up
+        float hx;
+        {
             const float cxe = (ld_at(gE, nb + dyb + cs2) - ezo) * crdy - (eyu - eyo) * crdz;
             const float inv = hf[0];
             const Sc Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 0, i, inv);
@@ -125,8 +129,8 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
         }
         st_at(dH, nb, hx);
         // Hy(i+1/2, j, k+1/2): By with z at k+1/2; Hy with x at i+1/2, y at j
-        float hy = 0.f;
-        if (hasy && k < c.nz) {
+        float hy;
+        {
             const float cye = (exu - exo) * crdz - (ld_at(gE, nb + 4u + cs2) - ezo) * crdx;
             const float inv = hf[1];
             const Sc Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 0, j, inv);
@@ -138,8 +142,8 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
         }
         st_at(dH, nb + cs, hy);
         // Hz(i+1/2, j+1/2, k): Bz with x at i+1/2; Hz with y at j+1/2, z at k
-        float hz = 0.f;
-        if (hasz) {
+        float hz;
+        {
             const float cze = (ld_at(gE, nb + 4u + cs) - eyo) * crdx - (ld_at(gE, nb + dyb) - exo) * crdy;
             const float inv = hf[2];
             const Sc X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 0, k, inv);
@@ -188,6 +192,8 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
     // H_x, H_y of plane k-1
     float hxm = c.k0 > 0 ? ld_at(nH, c.nb0 + (uint32_t)(c.k0 - 1) * dzb) : 0.f;
     float hym = c.k0 > 0 ? ld_at(nH, c.nb0 + (uint32_t)(c.k0 - 1) * dzb + cs) : 0.f;
+    // byte steps to the -x and -y neighbours, 0 on the low walls (see col_ctx)
+    const uint32_t mxb = i > 0 ? 4u : 0u, myb = j > 0 ? dyb : 0u;
     for (int k = c.k0; k < c.k1; ++k) {
         const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
         const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
@@ -199,69 +205,77 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         const float wx = B.eps_rw ? inv_x : 1.0f, wy = B.eps_rw ? inv_y : 1.0f,
                     wz = B.eps_rw ? inv_z : 1.0f;
         const float hx = ld_at(nH, nb), hy = ld_at(nH, nb + cs), hz = ld_at(nH, nb + cs2);
-        const bool kx = c.px || c.py, ky = c.py || pz, kz = pz || c.px;   // D kept
-        const float dxo = kx ? ld_at(gD, nb) : 0.f;
-        const float dyo = ky ? ld_at(gD, nb + cs) : 0.f;
-        const float dzo = kz ? ld_at(gD, nb + cs2) : 0.f;
-        float exn = 0.f, eyn = 0.f, ezn = 0.f, ddx = 0.f, ddy = 0.f, ddz = 0.f;
+        const float hzj = ld_at(nH, nb - myb + cs2), hzi = ld_at(nH, nb - mxb + cs2);
+        const float hyi = ld_at(nH, nb - mxb + cs), hxj = ld_at(nH, nb - myb);
+        const float exo = ld_at(gE, nb), eyo = ld_at(gE, nb + cs), ezo = ld_at(gE, nb + cs2);
+        // D where a PML keeps it (elsewhere the arrays hold zeros)
+        const bool kx = c.px || c.py, ky = c.py || pz, kz = pz || c.px;
+        const float dxl = ld_at(gD, nb), dyl = ld_at(gD, nb + cs), dzl = ld_at(gD, nb + cs2);
+        const float dxo = kx ? dxl : 0.f, dyo = ky ? dyl : 0.f, dzo = kz ? dzl : 0.f;
+        const float lx = loss[0], ly = loss[1], lz = loss[2];
         // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
-        if (flags & kUpdEx) {
-            const float chx = (hz - ld_at(nH, nb - dyb + cs2)) * crdy - (hy - hym) * crdz;
+        const float chx = (hz - hzj) * crdy - (hy - hym) * crdz;
+        float ddx, exn;
+        {
             const Sc Y = sc_at(cy, ny1, 0, j, wx), Z = sc_at(cz, nz1, 0, k, wx), X = sc_at(cx, nx1, 1, i, wx);
             ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
-            const float exo = ld_at(gE, nb), lx = loss[0];
             exn = fmaf(Z.ca, exo, Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
-            if (lx != 0.0f) {   // lossy interior edge; D (kept on a PML interface) gains eps_r (E' - E)
-                exn = conductive_e(exo, chx, inv_x, lx);
-                ddx = chx - lx * (exn + exo);
-            }
+        }
+        if (lx != 0.0f) {   // lossy interior edge; D (kept on a PML interface) gains eps_r (E' - E)
+            exn = conductive_e(exo, chx, inv_x, lx);
+            ddx = chx - lx * (exn + exo);
         }
         // Ey(i, j+1/2, k): Dy with z at k; Ey with x at i, y at j+1/2
-        if (flags & kUpdEy) {
-            const float chy = (hx - hxm) * crdz - (hz - ld_at(nH, nb - 4u + cs2)) * crdx;
+        const float chy = (hx - hxm) * crdz - (hz - hzi) * crdx;
+        float ddy, eyn;
+        {
             const Sc Z = sc_at(cz, nz1, 0, k, wy), X = sc_at(cx, nx1, 0, i, wy), Y = sc_at(cy, ny1, 1, j, wy);
             ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
-            const float eyo = ld_at(gE, nb + cs), ly = loss[1];
             eyn = fmaf(X.ca, eyo, X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
-            if (ly != 0.0f) {
-                eyn = conductive_e(eyo, chy, inv_y, ly);
-                ddy = chy - ly * (eyn + eyo);
-            }
+        }
+        if (ly != 0.0f) {
+            eyn = conductive_e(eyo, chy, inv_y, ly);
+            ddy = chy - ly * (eyn + eyo);
         }
         // Ez(i, j, k+1/2): Dz with x at i; Ez with y at j, z at k+1/2
-        if (flags & kUpdEz) {
-            float chz = (hy - ld_at(nH, nb - 4u + cs)) * crdx - (hx - ld_at(nH, nb - dyb)) * crdy;
-            float bs = 0.f;
-            if (flags & kSrcEz) {
-                const int node = (int)(nb >> 2);
-                const __attribute__((address_space(1))) int32_t* sn =
-                    (const __attribute__((address_space(1))) int32_t*)B.src_node;
-                cgfloat* sj = (cgfloat*)B.src_j;
-                cgfloat* sb = (cgfloat*)B.src_beta;
-                float js = 0.f;
-                for (int q = 0; q < B.nsrc; ++q)
-                    if (sn[q] == node) {
-                        js += sj[q * ms + step];
-                        bs += sb[q];
-                    }
-                chz -= js;
-            }
+        float chz = (hy - hyi) * crdx - (hx - hxj) * crdy;
+        float bs = 0.f;
+        if (flags & kSrcEz) {
+            const int node = (int)(nb >> 2);
+            const __attribute__((address_space(1))) int32_t* sn =
+                (const __attribute__((address_space(1))) int32_t*)B.src_node;
+            cgfloat* sj = (cgfloat*)B.src_j;
+            cgfloat* sb = (cgfloat*)B.src_beta;
+            float js = 0.f;
+            for (int q = 0; q < B.nsrc; ++q)
+                if (sn[q] == node) {
+                    js += sj[q * ms + step];
+                    bs += sb[q];
+                }
+            chz -= js;
+        }
+        float ddz, ezn;
+        {
             const Sc X = sc_at(cx, nx1, 0, i, wz), Y = sc_at(cy, ny1, 0, j, wz), Z = sc_at(cz, nz1, 1, k, wz);
-            const float ezo = ld_at(gE, nb + cs2);
             ddz = fmaf(X.cam1, dzo, X.rp * chz);
             ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
-            bs += loss[2];   // a resistive source's lumped conductance adds to the medium's
-            if (bs != 0.0f) {
-                ezn = conductive_e(ezo, chz, inv_z, bs);
-                ddz = chz - bs * (ezn + ezo);
-            }
         }
+        bs += lz;   // a resistive source's lumped conductance adds to the medium's
+        if (bs != 0.0f) {
+            ezn = conductive_e(ezo, chz, inv_z, bs);
+            ddz = chz - bs * (ezn + ezo);
+        }
+        // components on the outer wall or on PEC stay zero and keep their D
+        const bool ux = flags & kUpdEx, uy = flags & kUpdEy, uz = flags & kUpdEz;
+        exn = ux ? exn : 0.f;
+        eyn = uy ? eyn : 0.f;
+        ezn = uz ? ezn : 0.f;
         st_at(dE, nb, exn);
         st_at(dE, nb + cs, eyn);
         st_at(dE, nb + cs2, ezn);
-        if (kx) st_at(dD, nb, dxo + ddx);
-        if (ky) st_at(dD, nb + cs, dyo + ddy);
-        if (kz) st_at(dD, nb + cs2, dzo + ddz);
+        if (kx) st_at(dD, nb, ux ? dxo + ddx : dxo);
+        if (ky) st_at(dD, nb + cs, uy ? dyo + ddy : dyo);
+        if (kz) st_at(dD, nb + cs2, uz ? dzo + ddz : dzo);
         if (flags & kPrbEz) {
             const int node = (int)(nb >> 2);
             const __attribute__((address_space(1))) int32_t* pn =
@@ -285,10 +299,9 @@ hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int re
     // z chunks of up to 8 planes (a plane carried in registers saves a z
     // neighbour load), shorter when the columns alone leave the GPU idle
     const dim3 block(64, 4);
-    const int64_t bxy = (int64_t)((nx + 1 + 63) / 64) * ((ny + 1 + 3) / 4);
-    const int zl = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(nz + 1) * bxy / 2048));
-    const dim3 grid((unsigned)((nx + 1 + 63) / 64), (unsigned)((ny + 1 + 3) / 4),
-                    (unsigned)((nz + 1 + zl - 1) / zl));
+    const int64_t bxy = (int64_t)((nx + 63) / 64) * ((ny + 3) / 4);
+    const int zl = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)nz * bxy / 2048));
+    const dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)((nz + zl - 1) / zl));
     if (wide) {
         hipLaunchKernelGGL(eps_h_pass<uint16_t>, grid, block, 0, st, board, flip, zl);
         hipLaunchKernelGGL(eps_e_pass<uint16_t>, grid, block, 0, st, board, rel, flip, zl);
