@@ -31,7 +31,7 @@ Beside it, the same line carries
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1|plane|zconv|eps|shard]
+                  [--only single|batch|serve|table1|plane|zconv|eps|eps_large|shard]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -171,12 +171,13 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
     }
 
 
-def run_eps(F, torch, K=200, W=10):
+def run_eps(F, torch, K=200, W=10, large_only=False):
     """The node passes (Eq. 2's eps_rw, lossy dielectrics).  (1) The large board
     with its eps_r 4.2 slab run through the x/y PML to the outer wall
     (1048x792x88), eps_rw on, against the fused kernels on the same board with
     eps_rw = 1; (2) the paper's Fig. 3 board (100x60x0.8 mm running into the
-    UPML), 1000 steps of 1 ps; (3) the Table 1 run with a lossy dielectric."""
+    UPML), 1000 steps of 1 ps; (3) the Table 1 run with a lossy dielectric.
+    large_only: (1) alone."""
     import boardgen
     from paper_1008_2602_amd import tune
     b = boardgen.large_board(steps=W + K)
@@ -202,6 +203,8 @@ def run_eps(F, torch, K=200, W=10):
             "gcell_updates_per_s": round(b.cells * K / wall / 1e9, 3),
             "hbm_frac_algorithmic": round(info.step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         }
+    if large_only:
+        return out
     f3 = boardgen.fig3_board(steps=1000)
     g, _ = F.grid_from_board(f3, max_steps=f3.steps)
     F.fdtd_step_n(g, 0)
@@ -488,7 +491,7 @@ def main():
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
     ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
-                                       "eps", "shard"], default=None)
+                                       "eps", "eps_large", "shard"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -573,8 +576,8 @@ def main():
             _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
-    if args.only in (None, "eps"):
-        out["node_passes"] = run_eps(F, torch)
+    if args.only in (None, "eps", "eps_large"):
+        out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large")
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
     if args.only in (None, "shard"):
