@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
     float hym = c.k0 > 0 ? ld_at(nH, c.nb0 + (uint32_t)(c.k0 - 1) * dzb + cs) : 0.f;
     // byte steps to the -x and -y neighbours, 0 on the low walls (see col_ctx)
     const uint32_t mxb = i > 0 ? 4u : 0u, myb = j > 0 ? dyb : 0u;
+    const uint32_t guardb = dzb * (uint32_t)(c.nz + 1);   // first guard word of each array
     for (int k = c.k0; k < c.k1; ++k) {
         const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
         const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
@@ -208,10 +209,11 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         const float hzj = ld_at(nH, nb - myb + cs2), hzi = ld_at(nH, nb - mxb + cs2);
         const float hyi = ld_at(nH, nb - mxb + cs), hxj = ld_at(nH, nb - myb);
         const float exo = ld_at(gE, nb), eyo = ld_at(gE, nb + cs), ezo = ld_at(gE, nb + cs2);
-        // D where a PML keeps it (elsewhere the arrays hold zeros)
+        // D where a PML keeps it; elsewhere the load reads the zero guard words
+        // after the array (one cache line for the whole wave, no HBM traffic)
         const bool kx = c.px || c.py, ky = c.py || pz, kz = pz || c.px;
-        const float dxl = ld_at(gD, nb), dyl = ld_at(gD, nb + cs), dzl = ld_at(gD, nb + cs2);
-        const float dxo = kx ? dxl : 0.f, dyo = ky ? dyl : 0.f, dzo = kz ? dzl : 0.f;
+        const float dxo = ld_at(gD, kx ? nb : guardb), dyo = ld_at(gD, (ky ? nb : guardb) + cs),
+                    dzo = ld_at(gD, (kz ? nb : guardb) + cs2);
         const float lx = loss[0], ly = loss[1], lz = loss[2];
         // Ex(i+1/2, j, k): Dx with y at j; Ex with z at k, x at i+1/2
         const float chx = (hz - hzj) * crdy - (hy - hym) * crdz;
