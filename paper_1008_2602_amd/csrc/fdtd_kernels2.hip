@@ -62,8 +62,9 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     __shared__ float sH2z[TY][SC];
     constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
     __shared__ ClassEntry sTab[kLdsClasses];
-    // z coefficients of planes k (slot k&1) and k-1, staged by the last wave
-    __shared__ float sZ[2][10];
+    // z coefficients of plane p in slot p & 3 (planes k-1, k and k+1 are live at
+    // once), staged by the last wave
+    __shared__ float sZ[4][10];
 
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (t.board < 0) return;   // idle entry padding an XCD's list
@@ -157,7 +158,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     };
     // z coefficients from the LDS ring (entry kind*2 + half of the table)
     auto z_coef = [&](int k) {
-        const float* z = sZ[k & 1];
+        const float* z = sZ[k & 3];
         AxisCoef a;
         a.cam1_n = z[kCam1 * 2 + 0];
         a.ca_n = z[kCa * 2 + 0];
@@ -271,12 +272,22 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         st_at(B.plane_ring, (uint32_t)(now & (kPlaneRing - 1)) * szb + node0b, ez);
     };
 
-    // staging of the first plane
+    // staging of the first front plane: E_x, E_y of planes k0 (slot 0) and k0+1
+    // (slot 1), E_z of plane k0.  Stage p (E_x, E_y of plane p+1, E_z of plane p)
+    // is loaded two front planes before it is written.
     sE0x[0][r][c] = ld_at(gE, at_plane(k0));
     sE0y[0][r][c] = ld_at(gE, at_plane(k0) + cs);
-    Stage s0 = load_stage(k0), s1 = load_stage(k0 + 1);
+    {
+        const Stage t = load_stage(k0);
+        sE0x[1][r][c] = t.ex;
+        sE0y[1][r][c] = t.ey;
+        sE0z[r][c] = t.ez;
+        if (z_lane) sZ[k0 & 3][lane] = t.z;
+    }
+    Stage s0 = load_stage(k0 + 1), s1 = load_stage(k0 + 2);
     Col cA, cB;
     load_col(k0, cA);
+    __syncthreads();
 
     // carried from the previous front plane (k-1): H1, B1, own E1, D1 and class;
     // H2 of plane k-2
@@ -286,17 +297,12 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     float p_h2x = 0.f, p_h2y = 0.f;
     bool bad = false;
 
+    // st holds stage k+1 on entry: it is written once E1 of plane k has read plane
+    // k's E^n, so the staging needs no barrier of its own (three per plane)
     auto plane_step = [&](int k, Stage& st, const Col& o, Col& nxt_col) {
         const int cur = (k - k0) & 1, nxt = cur ^ 1;
         const int m = k - 1;   // plane of the second step
-        // ---- stage E^n
-        sE0x[nxt][r][c] = st.ex;
-        sE0y[nxt][r][c] = st.ey;
-        sE0z[r][c] = st.ez;
-        if (z_lane) sZ[k & 1][lane] = st.z;
-        st = load_stage(k + 2);
         load_col(k + 1, nxt_col);
-        __syncthreads();
         const AxisCoef Zk = z_coef(k);
 
         // ---- H1 of plane k: B then H, step n -> n+1/2
@@ -391,6 +397,12 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
             sH2y[r][c] = h2y;
             sH2z[r][c] = h2z;
         }
+        // ---- stage k+1: E_x, E_y of plane k+2 into plane k's slot, E_z of plane k+1
+        sE0x[cur][r][c] = st.ex;
+        sE0y[cur][r][c] = st.ey;
+        sE0z[r][c] = st.ez;
+        if (z_lane) sZ[(k + 1) & 3][lane] = st.z;
+        st = load_stage(k + 3);
         __syncthreads();
 
         // ---- E2 of plane m on the owned patch: D then E, step n+1 -> n+2
