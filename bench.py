@@ -39,6 +39,7 @@ import dataclasses
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,11 +53,25 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1008_2602_amd", "csrc", f)
                             "fdtd_internal.h", "fdtd_host.cpp")]
 
 
-def kernel_hash() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed: what the
+    compiler sees, so that editing a comment does not void the counters."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_hash(read=None) -> str:
+    """Hash of the field-kernel sources' code (comments and layout ignored).
+    read(path) -> text, default: the working tree."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(p, encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(p)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

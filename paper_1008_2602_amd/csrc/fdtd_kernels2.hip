@@ -15,10 +15,12 @@
 // with W = 64 aligned columns and Hh = TY-3 owned rows.  TY row waves cover
 // columns i0..i0+63 of the H1 rows; helper wave A takes the three halo columns
 // (i0-2, i0-1, i0+W) and stages column i0+W+1, helper wave B stages the row
-// above.  Per front plane k the block
-//   1. stages E^n of planes k+1 (Ex, Ey) and k (Ez) in LDS,
-//   2. computes H1 of plane k, then E1 of plane k (from H1 of planes k and k-1),
-//   3. computes H2 of plane k-1 (from E1 of planes k-1 and k, both in LDS),
+// above.  Per front plane k the block, with a barrier after each of 1-3,
+//   1. computes H1 of plane k from E^n of planes k and k+1 (staged in LDS),
+//   2. computes E1 of plane k (from H1 of planes k and k-1),
+//   3. computes H2 of plane k-1 (from E1 of planes k-1 and k, both in LDS) and
+//      stages E^n for the next front plane (Ex, Ey of plane k+2 into plane k's
+//      slot, Ez of plane k+1),
 //   4. computes E2 of plane k-1 on the owned patch and stores E2, H2 and the
 //      kept D/B of step n+2.
 // Every per-node update is written with exactly the expressions of the one-step
