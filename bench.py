@@ -26,12 +26,14 @@ Beside it, the same line carries
   * "shard": the large board cut into 8 y-slabs of 1048x99x88 cells (one
     rank's share of a slab decomposition, halo stubbed), every slab timed on
     its own;
+  * "realistic": the 444x364x60 realistic board's full 20000-step solve with
+    its 16 probe spectra, one board at a time;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
     one solve, and a 64-board sweep of its source resistance, with the oracle's
     time for the same whole run beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--only single|batch|serve|table1|plane|zconv|eps|eps_large|shard]
+                  [--only single|batch|serve|table1|plane|zconv|eps|eps_large|shard|realistic]
   python bench.py --copy-calibration      # plain device copy for PMC scaling
 """
 import argparse
@@ -336,6 +338,36 @@ def run_shard(F, torch, K=400, W=20, nranks=8):
     }
 
 
+def run_realistic(F, torch):
+    """The realistic board (444x364x60 cells, 16 probes) as one plain solve: its
+    full 20000 steps and the 16 probe spectra, one board at a time."""
+    import numpy as np
+    import boardgen
+    from paper_1008_2602_amd import tune
+    b = boardgen.realistic_board()
+    tile = tune.tune_board(b)
+    g, ids = F.grid_from_board(b, max_steps=b.steps, tile=tile)
+    F.fdtd_step_n(g, 0)                  # set-up (tables, work lists) outside the timing
+    F.fdtd_synchronize(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fdtd_step_n(g, b.steps)
+    n_fft = 1
+    while n_fft < b.steps:
+        n_fft *= 2
+    spec = [F.fdtd_probe_fft(g, p, n_fft) for p in ids]
+    wall = time.perf_counter() - t0
+    F.fdtd_destroy_grid(g)
+    assert all(np.all(np.isfinite(x)) for x in spec)
+    return {
+        "workload": f"realistic board {b.nx}x{b.ny}x{b.nz} cells (200x160 mm, 1.6 mm FR4), "
+                    f"{b.steps} steps, {len(ids)} probe spectra, one plain solve",
+        "tile": "x".join(str(v) for v in tile),
+        "wall_s": round(wall, 3),
+        "gcell_updates_per_s": round(b.cells * b.steps / wall / 1e9, 3),
+    }
+
+
 def run_batch(F, torch, K, W):
     """The 64-board variant batch, all boards advanced by K steps together."""
     import boardgen
@@ -506,7 +538,7 @@ def main():
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
     ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
-                                       "eps", "eps_large", "shard"], default=None)
+                                       "eps", "eps_large", "shard", "realistic"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -597,6 +629,8 @@ def main():
         out["zconv"] = run_zconv(F, torch)
     if args.only in (None, "shard"):
         out["shard"] = run_shard(F, torch)
+    if args.only in (None, "realistic"):
+        out["realistic"] = run_realistic(F, torch)
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:

@@ -5,6 +5,7 @@ bins (within one bin) for full runs; whole-array relative L2 <= 2e-5 for short
 runs from arbitrary states (FP32 arithmetic over a few steps); batched, resumed
 and re-tiled runs are bitwise equal to the plain run.
 """
+import os
 import sys
 
 import numpy as np
@@ -241,6 +242,35 @@ def test_small_board_full_run_parity(F, orc):
         pg = orc.find_peaks(Xg, f, f_min=0.5e9)
         assert len(pr) == len(pg)
         assert np.all(np.abs(pr - pg) <= 1.0 / (b.steps * ref.dt))
+
+
+GOLDEN_REALISTIC = os.path.join(os.path.dirname(__file__), "golden", "realistic_board_probes.npz")
+
+
+def test_realistic_board_full_run(F, orc):
+    """The realistic board (444x364x60 cells, 16 probes) over its full 20000
+    steps against the FP64 oracle's run stored by
+    tests/golden/make_realistic_probes.py: per probe relative L2 <= 1e-4 on
+    every 4th sample, and the spectral peaks of the full-resolution series
+    within one bin of the oracle's."""
+    d = np.load(GOLDEN_REALISTIC)
+    b = boardgen.realistic_board()
+    assert int(d["steps"]) == b.steps
+    announce(f"realistic board full run {b.nx}x{b.ny}x{b.nz} steps={b.steps}")
+    probes, _, _, info = gpu_run(F, b)
+    assert abs(info.dt - float(d["dt"])) <= 1e-12 * float(d["dt"])
+    dec = int(d["decimate"])
+    n_fft = int(d["n_fft"])
+    f = orc.bin_freqs(n_fft, float(d["dt"]))
+    bin_hz = 1.0 / (b.steps * float(d["dt"]))
+    for p in range(len(b.probes)):
+        e = rel_l2(probes[p][::dec], d["series"][p])
+        assert e <= 1e-4, (p, e)
+        ref = d["peaks_hz"][p]
+        ref = ref[~np.isnan(ref)]
+        got = orc.find_peaks(np.abs(orc.probe_fft(probes[p].astype(np.float64), n_fft)), f, f_min=0.5e9)
+        assert len(got) == len(ref), (p, got, ref)
+        assert np.all(np.abs(got - ref) <= bin_hz), (p, got, ref)
 
 
 def _bench_tile(board):
