@@ -16,8 +16,8 @@
  *     sigma = 0, kappa = 1 outside it, so one update runs everywhere;
  *   - D is introduced by Dx = eps sz/sx Ex, Dy = eps sx/sy Ey, Dz = eps sy/sz Ez;
  *     curl H = d/dt(kappa D) + sigma D/eps0 row by row (Eq. 4, last row read as
- *     the z component); D is stepped first, E follows from D ("two step
- *     process"), and likewise B then H using the same s (mu2 = mu1 s in Eq. 1);
+ *     the z component); D is stepped first and E follows from D, and
+ *     likewise B then H using the same s (mu2 = mu1 s in Eq. 1);
  *   - sigma and kappa are graded polynomially from the PML interface to the
  *     outer PEC wall (Eq. 5, read as (depth/d)^m);
  *   - with pml_eps_rw set, Eq. 2's s_w = kappa_w + sigma_w / (j w eps0 eps_rw)
