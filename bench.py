@@ -16,7 +16,9 @@ Beside it, the same line carries
     into 85 % of free HBM, advanced in 500-step chunks, each finished solve
     read back with its probe spectra; p50/p99 latency and throughput.  The step
     count per solve is reduced (default 1000 instead of 8000) so the run stays
-    short; the number is stated in the output;
+    short; the number is stated in the output.  Unless --no-cpu-baseline, the
+    oracle re-runs the smallest served solve and the largest probe relative L2
+    is reported beside the latencies;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
   * "node_passes": Eq. 2's eps_rw passes on the large board run into the PML,
@@ -515,7 +517,7 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
     res = srv.run(requests)
     wall = time.perf_counter() - t0
     s = summarize(res, wall_s=wall)
-    return {
+    out = {
         "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x measured "
                     f"capacity) of board variants, 5% 800x800x64, {steps} steps each, "
                     f"500-step chunks, probe FFT per solve",
@@ -527,6 +529,26 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
         "peak_resident": srv.peak_resident,
         "budget_gb": round(budget / 1e9, 1),
     }
+    return out, res, requests
+
+
+def served_oracle_check(results, requests):
+    """The CPU leg beside the served numbers: the oracle re-runs the smallest
+    served solve, and the served probe series are compared with it (largest
+    relative L2 over the solve's probes)."""
+    import numpy as np
+    import oracle
+    by_rid = {r.rid: r for r in requests}
+    pick = min(results, key=lambda r: r.cells)
+    req = by_rid[pick.rid]
+    t0 = time.perf_counter()
+    ref = oracle.run(req.board, nsteps=req.n_steps, threads=None)
+    cpu_s = time.perf_counter() - t0
+    errs = [float(np.linalg.norm(pick.probes[p].astype(np.float64) - ref.probes[p])
+                  / np.linalg.norm(ref.probes[p])) for p in range(len(ref.probes))]
+    return {"rid": pick.rid, "cells": pick.cells, "steps": req.n_steps,
+            "max_probe_rel_l2": float(f"{max(errs):.3g}"), "oracle_s": round(cpu_s, 2),
+            "cores": oracle.num_threads()}
 
 
 def main():
@@ -615,8 +637,10 @@ def main():
         if args.only != "serve":
             out["batched"] = batch
         if args.only in (None, "serve"):
-            out["served"] = run_serve(F, torch, batch["value"], mean_cells,
-                                      args.serve_requests, args.serve_steps)
+            out["served"], served_res, served_req = run_serve(F, torch, batch["value"], mean_cells,
+                                                              args.serve_requests, args.serve_steps)
+            if not args.no_cpu_baseline:
+                out["served"]["oracle_check"] = served_oracle_check(served_res, served_req)
     if args.only in (None, "plane"):
         plain = out.get("ms_per_step")
         if plain is None:
