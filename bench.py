@@ -28,8 +28,9 @@ Beside it, the same line carries
   * "shard": the large board cut into 8 y-slabs of 1048x99x88 cells (one
     rank's share of a slab decomposition, halo stubbed), every slab timed on
     its own;
-  * "realistic": the 444x364x60 realistic board's full 20000-step solve with
-    its 16 probe spectra, one board at a time;
+  * "realistic", "small": the 444x364x60 realistic board's full 20000-step
+    solve with its 16 probe spectra, and the 80x72x37 small board's 3000-step
+    solve (beside the oracle's whole run of it), one board at a time;
   * "table1": the paper's own Table 1 run (resistive source, 30000 steps) as
     one solve, and a 64-board sweep of its source resistance, with the oracle's
     time for the same whole run beside it.
@@ -340,13 +341,14 @@ def run_shard(F, torch, K=400, W=20, nranks=8):
     }
 
 
-def run_realistic(F, torch):
+def run_realistic(F, torch, which="realistic"):
     """The realistic board (444x364x60 cells, 16 probes) as one plain solve: its
-    full 20000 steps and the 16 probe spectra, one board at a time."""
+    full 20000 steps and the 16 probe spectra, one board at a time; with
+    which="small", the small board (80x72x37, 3000 steps, 4 probes) likewise."""
     import numpy as np
     import boardgen
     from paper_1008_2602_amd import tune
-    b = boardgen.realistic_board()
+    b = boardgen.realistic_board() if which == "realistic" else boardgen.small_board()
     tile = tune.tune_board(b)
     g, ids = F.grid_from_board(b, max_steps=b.steps, tile=tile)
     F.fdtd_step_n(g, 0)                  # set-up (tables, work lists) outside the timing
@@ -362,12 +364,12 @@ def run_realistic(F, torch):
     F.fdtd_destroy_grid(g)
     assert all(np.all(np.isfinite(x)) for x in spec)
     return {
-        "workload": f"realistic board {b.nx}x{b.ny}x{b.nz} cells (200x160 mm, 1.6 mm FR4), "
+        "workload": f"{which} board {b.nx}x{b.ny}x{b.nz} cells, "
                     f"{b.steps} steps, {len(ids)} probe spectra, one plain solve",
         "tile": "x".join(str(v) for v in tile),
         "wall_s": round(wall, 3),
         "gcell_updates_per_s": round(b.cells * b.steps / wall / 1e9, 3),
-    }
+    }, b
 
 
 def run_batch(F, torch, K, W):
@@ -481,7 +483,8 @@ def run_table1(F, torch, n_sweep=64, kernel_steps=200):
 
 
 def table1_cpu(board):
-    """The oracle's whole Table 1 run (it is small enough to run in full)."""
+    """The oracle's whole run of a board small enough to run in full (the Table 1
+    board, the small board)."""
     import oracle
     t0 = time.perf_counter()
     oracle.run(board, threads=None)
@@ -654,7 +657,10 @@ def main():
     if args.only in (None, "shard"):
         out["shard"] = run_shard(F, torch)
     if args.only in (None, "realistic"):
-        out["realistic"] = run_realistic(F, torch)
+        out["realistic"], _ = run_realistic(F, torch)
+        out["small"], small_board = run_realistic(F, torch, "small")
+        if not args.no_cpu_baseline:
+            out["small"]["cpu_baseline"] = table1_cpu(small_board)
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:
