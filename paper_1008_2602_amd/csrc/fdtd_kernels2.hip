@@ -224,17 +224,31 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     };
     // every load is issued on every path (absent operands read the zero guard
     // words), so the wait counts stay exact
-    auto load_col = [&](int p, Col& o) {
+    // The next plane's column operands are issued in two groups so that the
+    // vector memory pipe is not flooded at one point of the plane: H (read by
+    // H1) at the top of the plane, and B (H1), the class and D (E1) once H1 is
+    // done; the staging loads follow the H2 phase.
+    auto load_col_h = [&](int p, Col& o) {
         const uint32_t n = node0b + (uint32_t)p * szb;
         const bool pz = in_pz(p);
-        const bool okh = rH1 && ib && p <= nz, oke = rE1 && ib && p <= nz;
+        const bool okh = rH1 && ib && p <= nz;
         const uint32_t nh = okh ? n : guardb;
         o.hx = ld_at(gH, nh);
         o.hy = ld_at(gH, nh + cs);
         o.hz = ld_at(gH, nh + cs2);
+    };
+    auto load_col_b = [&](int p, Col& o) {
+        const uint32_t n = node0b + (uint32_t)p * szb;
+        const bool pz = in_pz(p);
+        const bool okh = rH1 && ib && p <= nz;
         o.bx = ld_at(gB, okh && (px || py) ? n : guardb);
         o.by = ld_at(gB, (okh && (py || pz) ? n : guardb) + cs);
         o.bz = ld_at(gB, (okh && (pz || px) ? n : guardb) + cs2);
+    };
+    auto load_col_cd = [&](int p, Col& o) {
+        const uint32_t n = node0b + (uint32_t)p * szb;
+        const bool pz = in_pz(p);
+        const bool oke = rE1 && ib && p <= nz;
         const uint32_t ne = oke ? n : guardb;
         o.c = ld_at_t<CT>(cls, sizeof(CT) == 1 ? ne >> 2 : ne >> 1);
         o.dx = ld_at(gD, oke && (px || py) ? n : guardb);
@@ -291,7 +305,9 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     }
     Stage s0 = load_stage(k0 + 1), s1 = load_stage(k0 + 2);
     Col cA, cB;
-    load_col(k0, cA);
+    load_col_h(k0, cA);
+    load_col_b(k0, cA);
+    load_col_cd(k0, cA);
     __syncthreads();
 
     // carried from the previous front plane (k-1): H1, B1, own E1, D1 and class;
@@ -307,7 +323,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     auto plane_step = [&](int k, Stage& st, const Col& o, Col& nxt_col) {
         const int cur = (k - k0) & 1, nxt = cur ^ 1;
         const int m = k - 1;   // plane of the second step
-        load_col(k + 1, nxt_col);
+        load_col_h(k + 1, nxt_col);
         const AxisCoef Zk = z_coef(k);
 
         // ---- H1 of plane k: B then H, step n -> n+1/2
@@ -336,6 +352,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         }
         __syncthreads();
 
+        load_col_b(k + 1, nxt_col);
+        load_col_cd(k + 1, nxt_col);
         // ---- E1 of plane k: D then E, step n -> n+1
         float e1x = 0.f, e1y = 0.f, e1z = 0.f, d1x = 0.f, d1y = 0.f, d1z = 0.f;
         const int e = cur;   // E1 plane slot of plane k (plane k-1 is in e ^ 1)
@@ -407,8 +425,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         sE0y[cur][r][c] = st.ey;
         sE0z[r][c] = st.ez;
         if (z_lane) sZ[(k + 1) & 3][lane] = st.z;
-        st = load_stage(k + 3);
         __syncthreads();
+        st = load_stage(k + 3);
 
         // ---- E2 of plane m on the owned patch: D then E, step n+1 -> n+2
         if (own && livem) {
