@@ -230,7 +230,6 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     // done; the staging loads follow the H2 phase.
     auto load_col_h = [&](int p, Col& o) {
         const uint32_t n = node0b + (uint32_t)p * szb;
-        const bool pz = in_pz(p);
         const bool okh = rH1 && ib && p <= nz;
         const uint32_t nh = okh ? n : guardb;
         o.hx = ld_at(gH, nh);
