@@ -329,6 +329,28 @@ def test_large_board_full_size_random_state(F, orc):
     compare_fields(ref.state, fields, b, 2e-5)
 
 
+def test_large_board_full_length_is_stable(F):
+    """The large-board workload over its whole 10000 steps (2.7 ns) in the
+    benchmark's tile: the watchdog stays quiet, every probe series and DFT value is
+    finite, the probes see the pulses, and nothing grows: the swing of every
+    probe over the last quarter of the run stays below the largest swing of the
+    first half, which holds the pulses (the plane pair rings for a long time and
+    keeps the static field the Gaussian sources leave, so the field need not decay
+    monotonically)."""
+    b = boardgen.large_board()
+    tile = _bench_tile(b)
+    announce(f"large board full length {b.steps} steps tile={tile}")
+    probes, _, dft, info = gpu_run(F, b, tile=tile)
+    assert info.step == b.steps
+    assert np.all(np.isfinite(probes)) and np.all(np.isfinite(dft))
+    peak = np.abs(probes).max()
+    assert peak > 0
+    n = b.steps
+    late = np.ptp(probes[:, 3 * n // 4:], axis=1).max()
+    early = np.ptp(probes[:, :n // 2], axis=1).max()
+    assert late < early, (late, early)
+
+
 def test_tile_shapes_bitwise(F):
     """Every shape, one- and two-step (an odd count ends on one single step),
     gives the same bits as the first."""
