@@ -14,9 +14,9 @@ Beside it, the same line carries
   * "served": seeded Poisson arrivals of board variants (5 % large 800x800x64
     boards) at 0.7x the measured batched capacity, admitted by device footprint
     into 85 % of free HBM, advanced in 500-step chunks, each finished solve
-    read back with its probe spectra; p50/p99 latency and throughput.  The step
-    count per solve is reduced (default 1000 instead of 8000) so the run stays
-    short; the number is stated in the output.  Unless --no-cpu-baseline, the
+    read back with its probe spectra; p50/p99 latency and throughput.  Each solve
+    is 8000 steps; the number of requests is reduced (default 24) so the run
+    stays short; both are stated in the output.  Unless --no-cpu-baseline, the
     oracle re-runs the smallest served solve and the largest probe relative L2
     is reported beside the latencies;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
@@ -566,7 +566,7 @@ def main():
                                        "eps", "eps_large", "shard", "realistic"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-steps", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
