@@ -474,10 +474,11 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
 struct Shape2 {
     int tx, ty;
 };
-// 64*TY + 128 threads.  TY = 14 and 12 run four waves per SIMD (128 VGPRs, a few
-// spilled); 10, 9 and 8 run three (the kernel's 131 VGPRs fit); TY = 6 is held to
-// 128 VGPRs so that two of its 512-thread blocks share a compute unit.  Taller
-// tiles recompute fewer halo rows per owned row.
+// 64*TY + 128 threads.  TY = 14 and 12 run four waves per SIMD (128 VGPRs, two
+// values spilled, four in the plane-DFT variant); 10, 9 and 8 run three (the
+// kernel's 129-131 VGPRs fit); TY = 6 is held to 128 VGPRs so that two of its
+// 512-thread blocks share a compute unit.  Taller tiles recompute fewer halo rows
+// per owned row.
 static const Shape2 kShapes2[] = {{64, 14}, {64, 12}, {64, 10}, {64, 9}, {64, 8}, {64, 6}};
 static const int kNumShapes2 = sizeof(kShapes2) / sizeof(kShapes2[0]);
 
