@@ -77,9 +77,10 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int i0 = t.tx * W, j0 = t.ty * (TY - 3);
-    // the row waves that run all four updates of a plane set each phase's length;
-    // they issue first (the halo rows and the helper waves have less to do)
-    if (wave >= 2 && wave <= TY - 2) __builtin_amdgcn_s_setprio(1);
+    // the row waves that run the second step's H (rows 1 .. TY-2; from row 2 on
+    // also its E) set each phase's length: they issue first (the outer halo rows
+    // and the helper waves have less to do)
+    if (wave >= 1 && wave <= TY - 2) __builtin_amdgcn_s_setprio(1);
 
     // ---- lane roles: LDS position (r, c) and which stages it computes
     int r, c;
