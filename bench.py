@@ -402,6 +402,7 @@ def run_batch(F, torch, K, W):
         "ms_per_step": round(wall / K * 1e3, 4),
         "tile": "x".join(str(v) for v in tile),
         "hbm_frac_algorithmic": round(step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_step": int(step_bytes),
     }, cells / len(boards)
 
 
