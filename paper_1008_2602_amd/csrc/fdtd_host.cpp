@@ -324,7 +324,10 @@ void build_work(const std::vector<TileRef>& tiles, int slots_per_xcd, std::vecto
             for (size_t q = n - m; q < n; ++q) pbar += whole[q].ke - whole[q].kb;
             pbar /= (double)m;
             double best = pbar;
-            for (int cand = 2; cand <= 8 && pbar / cand >= 3.0; ++cand) {
+            // up to 16 pieces of at least two planes: small boards (a few tiles,
+            // 30-plane columns) are latency bound, and shorter pieces cut the
+            // planes each block walks in sequence
+            for (int cand = 2; cand <= 16 && pbar / cand >= 2.0; ++cand) {
                 const double rounds = std::ceil((double)(m * cand) / (double)C);
                 const double cost = rounds * (pbar / cand + 1.0);
                 if (cost < 0.97 * best) {
