@@ -223,19 +223,22 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         s.z = czp[zent * nz1 + min(p, nz)];       // every lane loads one (exact wait counts)
         return s;
     };
-    // every load is issued on every path (absent operands read the zero guard
-    // words), so the wait counts stay exact
-    // The next plane's column operands are issued in two groups so that the
-    // vector memory pipe is not flooded at one point of the plane: H (read by
-    // H1) at the top of the plane, and B (H1), the class and D (E1) once H1 is
-    // done; the staging loads follow the H2 phase.
+    // Every load is issued on every path (absent operands read the zero guard
+    // words), so the wait counts stay exact.  The next plane's column operands are issued in two groups so that the
+    // vector memory pipe is not flooded at one point of the plane: H_x and H_y
+    // (read by H1) at the top of the plane; H_z, B (H1), the class and D (E1) once
+    // H1 is done; the staging loads follow the H2 phase.
     auto load_col_h = [&](int p, Col& o) {
         const uint32_t n = node0b + (uint32_t)p * szb;
         const bool okh = rH1 && ib && p <= nz;
         const uint32_t nh = okh ? n : guardb;
         o.hx = ld_at(gH, nh);
         o.hy = ld_at(gH, nh + cs);
-        o.hz = ld_at(gH, nh + cs2);
+    };
+    auto load_col_hz = [&](int p, Col& o) {
+        const uint32_t n = node0b + (uint32_t)p * szb;
+        const bool okh = rH1 && ib && p <= nz;
+        o.hz = ld_at(gH, (okh ? n : guardb) + cs2);
     };
     auto load_col_b = [&](int p, Col& o) {
         const uint32_t n = node0b + (uint32_t)p * szb;
@@ -306,6 +309,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     Stage s0 = load_stage(k0 + 1), s1 = load_stage(k0 + 2);
     Col cA, cB;
     load_col_h(k0, cA);
+    load_col_hz(k0, cA);
     load_col_b(k0, cA);
     load_col_cd(k0, cA);
     __syncthreads();
@@ -352,6 +356,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         }
         __syncthreads();
 
+        load_col_hz(k + 1, nxt_col);
         load_col_b(k + 1, nxt_col);
         load_col_cd(k + 1, nxt_col);
         // ---- E1 of plane k: D then E, step n -> n+1
