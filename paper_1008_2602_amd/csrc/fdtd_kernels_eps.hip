@@ -22,12 +22,21 @@ struct Sc {
     float cam1, ca, rp, ph, q;
 };
 
-// Coefficients of one axis at table index idx (node or half node) for a field
-// location of inverse relative permittivity inv_eps (q scaled by 1/eps_rw).
-__device__ __forceinline__ Sc sc_at(cgfloat* tab, int n1, int half, int idx, float inv_eps)
+// q and kappa of one axis at one table index (node or half node)
+struct Qk {
+    float q, kap;
+};
+__device__ __forceinline__ Qk qk_at(cgfloat* tab, int n1, int half, int idx)
 {
-    const float q = tab[(kQ * 2 + half) * n1 + idx] * inv_eps;
-    const float kap = tab[(kKappa * 2 + half) * n1 + idx];
+    return Qk{tab[(kQ * 2 + half) * n1 + idx], tab[(kKappa * 2 + half) * n1 + idx]};
+}
+
+// Coefficients of one axis from its q and kappa for a field location of inverse
+// relative permittivity inv_eps (q scaled by 1/eps_rw).
+__device__ __forceinline__ Sc sc_of(Qk t, float inv_eps)
+{
+    const float q = t.q * inv_eps;
+    const float kap = t.kap;
     Sc s;
     s.q = q;
     s.ph = fmaf(0.5f, q, kap);
@@ -104,10 +113,15 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
     const int nx1 = c.nx + 1, ny1 = c.ny + 1, nz1 = c.nz + 1;
     const float crdx = B.crd_x, crdy = B.crd_y, crdz = B.crd_z;
     const int i = c.i, j = c.j;
+    // the x and y tables at the column, read once (the stores below may alias
+    // them as far as the compiler knows, so it would reload them every plane)
+    const Qk x0 = qk_at(cx, nx1, 0, i), x1 = qk_at(cx, nx1, 1, i);
+    const Qk y0 = qk_at(cy, ny1, 0, j), y1 = qk_at(cy, ny1, 1, j);
     float exo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb), eyo = ld_at(gE, c.nb0 + (uint32_t)c.k0 * dzb + cs);
     for (int k = c.k0; k < c.k1; ++k) {
         const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
         const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
+        const Qk z0 = qk_at(cz, nz1, 0, k), z1 = qk_at(cz, nz1, 1, k);
         const float ezo = ld_at(gE, nb + cs2);
         const float exu = ld_at(gE, nb + dzb), eyu = ld_at(gE, nb + dzb + cs);
         const int id = class_of<CT>(B, nb);
@@ -120,7 +134,7 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
         {
             const float cxe = (ld_at(gE, nb + dyb + cs2) - ezo) * crdy - (eyu - eyo) * crdz;
             const float inv = hf[0];
-            const Sc Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 0, i, inv);
+            const Sc Y = sc_of(y1, inv), Z = sc_of(z1, inv), X = sc_of(x0, inv);
             const bool keep = c.px || c.py;
             const float bo = keep ? ld_at(gB, nb) : 0.f;
             const float db = fmaf(Y.cam1, bo, -Y.rp * cxe);
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
         {
             const float cye = (exu - exo) * crdz - (ld_at(gE, nb + 4u + cs2) - ezo) * crdx;
             const float inv = hf[1];
-            const Sc Z = sc_at(cz, nz1, 1, k, inv), X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 0, j, inv);
+            const Sc Z = sc_of(z1, inv), X = sc_of(x1, inv), Y = sc_of(y0, inv);
             const bool keep = c.py || pz;
             const float bo = keep ? ld_at(gB, nb + cs) : 0.f;
             const float db = fmaf(Z.cam1, bo, -Z.rp * cye);
@@ -146,7 +160,7 @@ __global__ __launch_bounds__(256) void eps_h_pass(const BoardDev* __restrict__ b
         {
             const float cze = (ld_at(gE, nb + 4u + cs) - eyo) * crdx - (ld_at(gE, nb + dyb) - exo) * crdy;
             const float inv = hf[2];
-            const Sc X = sc_at(cx, nx1, 1, i, inv), Y = sc_at(cy, ny1, 1, j, inv), Z = sc_at(cz, nz1, 0, k, inv);
+            const Sc X = sc_of(x1, inv), Y = sc_of(y1, inv), Z = sc_of(z0, inv);
             const bool keep = pz || c.px;
             const float bo = keep ? ld_at(gB, nb + cs2) : 0.f;
             const float db = fmaf(X.cam1, bo, -X.rp * cze);
@@ -195,9 +209,13 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
     // byte steps to the -x and -y neighbours, 0 on the low walls (see col_ctx)
     const uint32_t mxb = i > 0 ? 4u : 0u, myb = j > 0 ? dyb : 0u;
     const uint32_t guardb = dzb * (uint32_t)(c.nz + 1);   // first guard word of each array
+    // the x and y tables at the column, read once (as in the H pass)
+    const Qk x0 = qk_at(cx, nx1, 0, i), x1 = qk_at(cx, nx1, 1, i);
+    const Qk y0 = qk_at(cy, ny1, 0, j), y1 = qk_at(cy, ny1, 1, j);
     for (int k = c.k0; k < c.k1; ++k) {
         const uint32_t nb = c.nb0 + (uint32_t)k * dzb;
         const bool pz = (k < B.pml[4]) || (B.pml[5] > 0 && k >= c.nz - B.pml[5]);
+        const Qk z0 = qk_at(cz, nz1, 0, k), z1 = qk_at(cz, nz1, 1, k);
         const int id = class_of<CT>(B, nb);
         const float inv_x = ctab[id].inv_x, inv_y = ctab[id].inv_y, inv_z = ctab[id].inv_z;
         const uint32_t flags = ctab[id].flags;
@@ -219,7 +237,7 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         const float chx = (hz - hzj) * crdy - (hy - hym) * crdz;
         float ddx, exn;
         {
-            const Sc Y = sc_at(cy, ny1, 0, j, wx), Z = sc_at(cz, nz1, 0, k, wx), X = sc_at(cx, nx1, 1, i, wx);
+            const Sc Y = sc_of(y0, wx), Z = sc_of(z0, wx), X = sc_of(x1, wx);
             ddx = fmaf(Y.cam1, dxo, Y.rp * chx);
             exn = fmaf(Z.ca, exo, Z.rp * (inv_x * fmaf(X.ph, ddx, X.q * dxo)));
         }
@@ -231,7 +249,7 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         const float chy = (hx - hxm) * crdz - (hz - hzi) * crdx;
         float ddy, eyn;
         {
-            const Sc Z = sc_at(cz, nz1, 0, k, wy), X = sc_at(cx, nx1, 0, i, wy), Y = sc_at(cy, ny1, 1, j, wy);
+            const Sc Z = sc_of(z0, wy), X = sc_of(x0, wy), Y = sc_of(y1, wy);
             ddy = fmaf(Z.cam1, dyo, Z.rp * chy);
             eyn = fmaf(X.ca, eyo, X.rp * (inv_y * fmaf(Y.ph, ddy, Y.q * dyo)));
         }
@@ -258,7 +276,7 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
         }
         float ddz, ezn;
         {
-            const Sc X = sc_at(cx, nx1, 0, i, wz), Y = sc_at(cy, ny1, 0, j, wz), Z = sc_at(cz, nz1, 1, k, wz);
+            const Sc X = sc_of(x0, wz), Y = sc_of(y0, wz), Z = sc_of(z1, wz);
             ddz = fmaf(X.cam1, dzo, X.rp * chz);
             ezn = fmaf(Y.ca, ezo, Y.rp * (inv_z * fmaf(Z.ph, ddz, Z.q * dzo)));
         }
