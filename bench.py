@@ -103,24 +103,66 @@ def copy_calibration(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_each_way": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(board, budget_s=20.0):
-    """The FP64 oracle, as it stands, on this host's cores: a bounded number of
-    steps of the same board (one untimed step touches the memory, two more
-    calibrate the per-step time), in Gcell-updates/s."""
+def host_cpu():
+    """CPU model and logical core count of this host (the oracle's machine)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model or "unknown", "logical_cpus": os.cpu_count()}
+
+
+def _oracle_rate(board, threads, budget_s, max_steps=400):
+    """Gcell-updates/s of the oracle on ``board`` with ``threads`` threads: one
+    untimed step touches the memory, two more calibrate the per-step time, then
+    about budget_s seconds of steps are timed.  Returns (rate, steps, seconds)."""
     import oracle
+    oracle.set_threads(threads)
     st = oracle.new_state(board)
     oracle.run(board, nsteps=1, state=st)
     t0 = time.perf_counter()
     oracle.run(board, nsteps=2, state=st)
     per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(400, budget_s / max(per, 1e-6))))
+    n = int(max(2, min(max_steps, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     oracle.run(board, nsteps=n, state=st)
     dt = time.perf_counter() - t0
-    return {"value": round(board.cells * n / dt / 1e9, 4), "unit": "Gcell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} steps of the full {board.nx}x{board.ny}x{board.nz} board after 3 "
-                      f"calibration steps ({dt:.1f} s; FP64, unified D/B storage)"}
+    return board.cells * n / dt / 1e9, n, dt
+
+
+def cpu_baseline(board, budget_s=20.0, single_budget_s=8.0):
+    """The FP64 oracle, as it stands, on this host's cores: a bounded number of
+    steps of the same board, in Gcell-updates/s, with all host threads and with
+    one thread."""
+    import oracle
+    threads = oracle.num_threads()        # OpenMP's default: every host thread it may use
+    rate, n, dt = _oracle_rate(board, threads, budget_s)
+    cores = oracle.num_threads()
+    rate1, n1, dt1 = _oracle_rate(board, 1, single_budget_s)
+    oracle.set_threads(threads)
+    out = {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} steps of the full {board.nx}x{board.ny}x{board.nz} board after 3 "
+                     f"calibration steps ({dt:.1f} s; FP64, unified D/B storage)",
+           "single_thread": {"value": round(rate1, 5), "unit": "Gcell-updates/s", "cores": 1,
+                             "sample": f"{n1} steps of the same board ({dt1:.1f} s)"}}
+    out.update(host_cpu())
+    return out
+
+
+def sec8d_step_bytes(info):
+    """Algorithmic bytes of one step by the survey's count for the split layout:
+    per cell 72 B (separate H and E passes: E, H read and H written, then H, E
+    read and E written, FP32) plus the class index, plus 8 B (read and write) for
+    every kept D/B component.  The kept D/B bytes are the library's own count
+    (its step_bytes minus the 48 B of E and H and the class per cell)."""
+    cls = 2 if info.n_classes > 256 else 1
+    aux = info.step_bytes - info.cells * (48 + cls)
+    return info.cells * (72 + cls) + aux
 
 
 def run_single(F, torch, K, W, tile):
@@ -221,7 +263,8 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
         out["eps_rw" if rw else "fused_eps_rw_1"] = {
             "ms_per_step": round(wall / K * 1e3, 4),
             "gcell_updates_per_s": round(b.cells * K / wall / 1e9, 3),
-            "hbm_frac_algorithmic": round(info.step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
+            # the survey's algorithmic bytes (two passes per step, as these are)
+            "hbm_frac_algorithmic": round(sec8d_step_bytes(info) * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         }
     if large_only:
         return out
@@ -324,7 +367,7 @@ def run_shard(F, torch, K=400, W=20, nranks=8):
         launch_s = kern_ms / 1e3 / launches
         per.append({"rank": rank, "tile": "x".join(str(v) for v in tile),
                     "ms_per_step": wall / K * 1e3, "launch_s": launch_s,
-                    "launch_bytes": info.step_bytes * K / launches, "cells": board.cells})
+                    "launch_bytes": sec8d_step_bytes(info) * K / launches, "cells": board.cells})
     slow = max(per, key=lambda r: r["ms_per_step"])
     achieved = slow["launch_bytes"] / slow["launch_s"] / 1e9
     return {
@@ -336,7 +379,7 @@ def run_shard(F, torch, K=400, W=20, nranks=8):
         "ms_per_step": [round(r["ms_per_step"], 4) for r in per],
         "ms_per_step_slowest": round(slow["ms_per_step"], 4),
         "gcell_updates_per_s_slowest": round(slow["cells"] / slow["ms_per_step"] / 1e6, 3),
-        "roofline_frac_slowest": round(achieved / HBM_PEAK_GBS, 4),
+        "frac_effective_slowest": round(achieved / HBM_PEAK_GBS, 4),
         "avg_launch_ms_slowest": round(slow["launch_s"] * 1e3, 4),
     }
 
@@ -388,7 +431,9 @@ def run_batch(F, torch, K, W):
     F.fdtd_step_many(gs, [K] * len(gs))
     F.fdtd_synchronize(gs[0])
     wall = time.perf_counter() - t0
-    step_bytes = sum(F.fdtd_get_info(g).step_bytes for g in gs)
+    infos = [F.fdtd_get_info(g) for g in gs]
+    step_bytes = sum(sec8d_step_bytes(i) for i in infos)
+    fused_bytes = sum(i.step_bytes for i in infos)
     for g in gs:
         F.fdtd_destroy_grid(g)
     cells = sum(b.cells for b in boards)
@@ -401,8 +446,10 @@ def run_batch(F, torch, K, W):
         "steps": K,
         "ms_per_step": round(wall / K * 1e3, 4),
         "tile": "x".join(str(v) for v in tile),
-        "hbm_frac_algorithmic": round(step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
+        # on the survey's algorithmic bytes; effective (two steps per pass)
+        "frac_effective": round(step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_step": int(step_bytes),
+        "frac_on_fused_bytes": round(fused_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
     }, cells / len(boards)
 
 
@@ -442,7 +489,7 @@ def run_table1(F, torch, n_sweep=64, kernel_steps=200):
     info = F.fdtd_get_info(g)
     F.fdtd_destroy_grid(g)
     per_launch_s = kern_ms / 1e3 / launches
-    launch_bytes = info.step_bytes * kernel_steps / launches
+    launch_bytes = sec8d_step_bytes(info) * kernel_steps / launches
 
     boards = []
     for r in np.geomspace(1.0, 1000.0, n_sweep):
@@ -472,7 +519,7 @@ def run_table1(F, torch, n_sweep=64, kernel_steps=200):
         "ms_per_step": round(wall / N * 1e3, 5),
         "gcell_updates_per_s": round(b.cells * N / wall / 1e9, 3),
         "kernel_avg_launch_us": round(per_launch_s * 1e6, 2),
-        "kernel_hbm_frac_algorithmic": round(launch_bytes / per_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_frac_effective": round(launch_bytes / per_launch_s / 1e9 / HBM_PEAK_GBS, 4),
         "r_sweep": {
             "boards": len(boards),
             "R_ohm": [1.0, 1000.0],
@@ -493,6 +540,18 @@ def table1_cpu(board):
     return {"value": round(board.cells * board.steps / dt / 1e9, 4),
             "unit": "Gcell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"the whole {board.steps}-step run ({dt:.1f} s; FP64)"}
+
+
+def sampled_cpu(board, budget_s=15.0):
+    """The oracle on a bounded sample of a board's steps (all host threads), with
+    the whole run's time extrapolated from it."""
+    import oracle
+    rate, n, dt = _oracle_rate(board, oracle.num_threads(), budget_s)
+    return {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} of the {board.steps} steps ({dt:.1f} s; FP64); the whole run "
+                      f"would take about {board.cells * board.steps / rate / 1e9:.0f} s "
+                      f"(extrapolated)"}
 
 
 def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
@@ -529,6 +588,8 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
         "p99_latency_s": round(s["p99_latency_s"], 4),
         "solves_per_s": round(s["solves_per_s"], 4),
         "gcell_updates_per_s": round(s["gcell_updates_per_s"], 3),
+        "requests": n_requests,
+        "large_boards": sum(1 for r in requests if (r.board.nx, r.board.ny) == (800, 800)),
         "completed": s["completed"],
         "peak_resident": srv.peak_resident,
         "budget_gb": round(budget / 1e9, 1),
@@ -596,8 +657,10 @@ def main():
         per_launch_s = kern_ms / 1e3 / launches
         steps_per_launch = K / launches          # 2 for a two-step shape (K even)
         traffic = measured_traffic()
-        launch_bytes = info.step_bytes * steps_per_launch
+        sec8d_step = sec8d_step_bytes(info)
+        launch_bytes = sec8d_step * steps_per_launch
         achieved = launch_bytes / per_launch_s / 1e9
+        fused_launch_bytes = info.step_bytes * steps_per_launch
         out.update({
             "metric": "Gcell-updates/s + % HBM roofline (1 GPU); served solves p50/p99 latency",
             "value": round(cells * K / wall / 1e9, 3),
@@ -621,19 +684,32 @@ def main():
             },
             "roofline": {
                 "bound": "hbm",
+                # algorithmic bytes: the survey's per cell-update count for the
+                # layout used (D/B kept only where a PML loss acts): 72 B of E and H
+                # for separate H and E passes, the class byte(s), 8 B per kept D/B
+                # component, times the steps one launch advances
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
+                # above 1 is possible: the kernel keeps step n+1 on chip, so it moves
+                # fewer bytes than two separate steps of the survey's count
+                "frac_kind": "effective (temporally blocked: two steps per pass)",
                 "traffic": traffic,
-                # HBM rate actually moved (PMC bytes / launch time); a two-step pass
-                # moves far less than twice the one-step bytes
+                # HBM bytes actually moved (PMC) over the launch time, against the peak
                 "measured_hbm_gbs": (round(traffic / per_launch_s / 1e9, 1)
                                      if traffic is not None else None),
+                "hbm_frac_measured": (round(traffic / per_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic is not None else None),
                 "kernel": "field_step2" if info.tile_steps == 2 else "field_step",
                 "steps_per_launch": steps_per_launch,
+                "bytes_per_cell_update": round(sec8d_step / cells, 2),
                 "algorithmic_bytes_per_launch": int(launch_bytes),
                 "avg_launch_ms": round(per_launch_s * 1e3, 4),
+                # the library's own count (one fused pass per step: E and H read and
+                # written once, class, kept D/B), and the fraction on it
+                "fused_bytes_per_cell_update": round(info.step_bytes / cells, 2),
+                "frac_on_fused_bytes": round(fused_launch_bytes / per_launch_s / 1e9 / HBM_PEAK_GBS, 4),
             },
         })
     if args.only in (None, "batch", "serve"):
@@ -658,7 +734,9 @@ def main():
     if args.only in (None, "shard"):
         out["shard"] = run_shard(F, torch)
     if args.only in (None, "realistic"):
-        out["realistic"], _ = run_realistic(F, torch)
+        out["realistic"], real_board = run_realistic(F, torch)
+        if not args.no_cpu_baseline:
+            out["realistic"]["cpu_baseline"] = sampled_cpu(real_board)
         out["small"], small_board = run_realistic(F, torch, "small")
         if not args.no_cpu_baseline:
             out["small"]["cpu_baseline"] = table1_cpu(small_board)

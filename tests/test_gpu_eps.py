@@ -108,6 +108,51 @@ def test_eps_rw_random_state_few_steps(F, oracle_mod, shape, npml):
     compare_fields(ref.state, fields, b, 2e-5)
 
 
+@pytest.mark.parametrize("shape,lossy", [((256, 128, 48), True), ((512, 256, 48), False)])
+def test_node_pass_z_chunks_random_state(F, oracle_mod, shape, lossy):
+    """Boards with enough columns that the node passes cut z into chunks that
+    carry the previous plane in registers: 3 planes per chunk on the first board
+    (4 x 32 column blocks), 12 on the second (8 x 64), as on the large benchmark
+    board; the chunk seams (k0 > 0) lie at every third or twelfth plane.  Random
+    eps_r in every cell (PML included), a PEC sheet, eps_rw on (and on the first
+    board a lossy interior): three steps from an arbitrary state against the
+    oracle, every array, element and region (each plane on its own)."""
+    nx, ny, nz = shape
+    eps, mask = boardgen.air(nx, ny, nz)
+    rng = np.random.default_rng(nx + nz)
+    eps[:] = rng.choice([1.0, 2.2, 4.4], size=eps.shape).astype(np.float32)
+    boardgen.pec_sheet(mask, nz // 2, 0, nx // 2, 1, ny - 1)
+    npml = (5, 4, 6, 3, 4, 5)
+    b = boardgen.Board(f"epschunk{nx}", nx, ny, nz, 0.5e-3, 0.6e-3, 0.2e-3, eps, mask,
+                       npml=npml, steps=3, pml_eps_rw=True)
+    if lossy:
+        sig = rng.uniform(0.0, 2.0, size=eps.shape).astype(np.float32)
+        sig[:npml[4]] = 0.0
+        sig[nz - npml[5]:] = 0.0
+        sig[:, :npml[2]] = 0.0
+        sig[:, ny - npml[3]:] = 0.0
+        sig[:, :, :npml[0]] = 0.0
+        sig[:, :, nx - npml[1]:] = 0.0
+        b.sigma_cell = sig
+    st = random_state(oracle_mod, b, seed=nx + ny)
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"node-pass z chunks {shape} lossy={lossy}")
+    ref = oracle_mod.run(b, state=st, threads=16)
+    g, _ = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        for c, n in enumerate(FIELDS):
+            F.fdtd_set_field(g, c, init[n].astype(np.float32))
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        assert F.fdtd_get_info(g).node_passes == 1
+        fields = gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+    rep = compare_fields(ref.state, fields, b, 2e-5)
+    for n, (whole, elem, reg, where) in rep.items():
+        print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
+
+
 def test_eps_rw_bitwise_across_calls_graphs_checkpoints_and_batches(F):
     b = eps_board(3, steps=75)
     ref = run(F, b)

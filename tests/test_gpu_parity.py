@@ -1,8 +1,11 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 oracle.
 
 Tolerances: probe series relative L2 <= 1e-4 per probe and identical FFT peak
-bins (within one bin) for full runs; whole-array relative L2 <= 2e-5 for short
-runs from arbitrary states (FP32 arithmetic over a few steps); batched, resumed
+bins (within one bin) for full runs; the DFT within 1e-4 per probe; for short
+runs from arbitrary states (FP32 arithmetic over a few steps) every array
+within a relative L2 of 2e-5, every element within 1e-5 of the array's largest
+value and every region (PML faces, edges and corners, each node plane, row and
+column, the PEC sheet rims) within 4e-5 (tests/_compare.py); batched, resumed
 and re-tiled runs are bitwise equal to the plain run.
 """
 import os
@@ -12,11 +15,11 @@ import numpy as np
 import pytest
 
 import boardgen
+from _compare import FIELDS, aux_masks, compare_fields  # noqa: F401  (re-exported to the other GPU tests)
 from _util import live_masks, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("ex", "ey", "ez", "hx", "hy", "hz", "ddx", "ddy", "ddz", "bbx", "bby", "bbz")
 TWO_STEP = (64, 10, 2)   # a two-steps-per-pass shape other than the default 64x14x2
 
 
@@ -37,22 +40,6 @@ def F():
 @pytest.fixture(scope="module")
 def orc(oracle_mod):
     return oracle_mod
-
-
-def aux_masks(board):
-    """Where the library keeps D/B: the component's own or cyclic-next axis is in
-    a PML slab (elsewhere those auxiliaries never influence E or H)."""
-    nx, ny, nz = board.nx, board.ny, board.nz
-    p = board.npml
-    px = np.array([(i < p[0]) or (p[1] > 0 and i >= nx - p[1]) for i in range(nx + 1)])
-    py = np.array([(j < p[2]) or (p[3] > 0 and j >= ny - p[3]) for j in range(ny + 1)])
-    pz = np.array([(k < p[4]) or (p[5] > 0 and k >= nz - p[5]) for k in range(nz + 1)])
-    X = px[None, None, :]
-    Y = py[None, :, None]
-    Z = pz[:, None, None]
-    shp = (nz + 1, ny + 1, nx + 1)
-    return {"x": np.broadcast_to(X | Y, shp), "y": np.broadcast_to(Y | Z, shp),
-            "z": np.broadcast_to(Z | X, shp)}
 
 
 def gpu_fields(F, g, board):
@@ -98,35 +85,6 @@ def random_state(orc, board, seed, scale_h=376.73):
         else:                                                   # both sides see FP32 inputs
             st[n][...] = (v.astype(np.float64) * scale).astype(np.float32)
     return st
-
-
-# SI value -> E-like units (V/m): H by eta0, D by 1/eps0, B by c0
-_EPS0 = 8.854187817620389e-12
-_MU0 = 4e-7 * np.pi
-_TO_E_UNITS = {"e": 1.0, "h": np.sqrt(_MU0 / _EPS0), "d": 1.0 / _EPS0, "b": 1.0 / np.sqrt(_MU0 * _EPS0)}
-
-
-def compare_fields(ref, got, board, tol, floor_rel=None):
-    """Relative L2 of every array against the oracle.  With ``floor_rel`` the
-    denominator is at least floor_rel times the norm of the whole E field (in
-    each array's own units): an array that the pulse has only reached through
-    the stencil's far tail (values many decades below the field, flushed or
-    lost in FP32) is then held to an absolute bound instead of a relative one."""
-    am = aux_masks(board)
-    axis = {"ddx": "x", "ddy": "y", "ddz": "z", "bbx": "x", "bby": "y", "bbz": "z"}
-    e_norm = float(np.sqrt(sum(np.linalg.norm(ref[n]) ** 2 for n in ("ex", "ey", "ez"))))
-    for n in FIELDS:
-        r = ref[n]
-        if n in axis:
-            r = np.where(am[axis[n]], r, 0.0)
-        if np.abs(r).max() == 0:
-            assert np.abs(got[n]).max() == 0, n
-            continue
-        den = float(np.linalg.norm(r))
-        if floor_rel is not None:
-            den = max(den, floor_rel * e_norm / _TO_E_UNITS[n[0]])
-        e = float(np.linalg.norm(got[n] - r)) / den
-        assert e <= tol, (n, e)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
@@ -306,8 +264,17 @@ def test_large_board_full_size_from_zero(F, orc):
         else:                                   # ahead of the front: tiny on both sides
             assert np.abs(probes[p] - r).max() <= 1e-4 * peak, p
     assert checked >= 4
-    compare_fields(ref.state, fields, b, 1e-4, floor_rel=1e-6)
-    assert rel_l2(dft, ref.dft) <= 1e-4
+    rep = compare_fields(ref.state, fields, b, 1e-4, floor_rel=1e-6)
+    for n, (whole, elem, reg, where) in rep.items():
+        print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
+    # the DFT per probe (256 frequencies each): within 1e-4 where the pulse arrived
+    dmax = np.abs(ref.dft).max()
+    for p in range(len(b.probes)):
+        if np.abs(ref.probes[p]).max() > 1e-6 * peak:
+            e = rel_l2(dft[p], ref.dft[p])
+            assert e <= 1e-4, (p, e)
+        else:
+            assert np.abs(dft[p] - ref.dft[p]).max() <= 1e-4 * dmax, p
 
 
 def test_large_board_full_size_random_state(F, orc):
@@ -326,7 +293,9 @@ def test_large_board_full_size_random_state(F, orc):
     _, fields, _, _ = gpu_run(F, b, init=init, tile=tile)
     del init
     announce("large board full size random state: compare")
-    compare_fields(ref.state, fields, b, 2e-5)
+    rep = compare_fields(ref.state, fields, b, 2e-5)
+    for n, (whole, elem, reg, where) in rep.items():
+        print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
 
 
 def test_large_board_full_length_is_stable(F):
