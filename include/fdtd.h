@@ -227,6 +227,19 @@ int64_t fdtd_estimate_bytes(const fdtd_grid_desc* desc, int n_sources, int n_pro
  * doubles each.  Synchronises. */
 int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im);
 
+/* fdtd_probe_fft without any allocation, for callers that cannot allocate
+ * device memory (code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same spectrum, bit for bit, with the
+ * same arguments and errors, computed in a fixed device scratch array of the
+ * library (32 MiB, held on every device the library runs on until the process
+ * ends) instead of temporary buffers.  n_fft <= 2^20 (EINVAL beyond, with a
+ * message naming fdtd_probe_fft).  Every call on a device shares that device's
+ * scratch: calls that overlap on one device (from several threads, or on
+ * several streams) race; calls that follow one another do not, since each
+ * synchronises its handle's stream before returning.  Before the first step
+ * (nothing finalised) the spectrum is all zeros.  Synchronises. */
+int fdtd_probe_fft_noalloc(fdtd_grid* g, int id, int n_fft, double* re, double* im);
+
 /* Copy the first n samples (n <= completed steps) of probe `id` into out (host,
  * n floats).  Synchronises. */
 int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n);

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["fdtd_kernels.hip", "fdtd_kernels2.hip", "fdtd_kernels_eps.hip", "fdtd_host.cpp"]
+SOURCES = ["fdtd_kernels.hip", "fdtd_kernels2.hip", "fdtd_kernels_eps.hip", "fdtd_noalloc.hip",
+           "fdtd_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -40,6 +40,9 @@ hipError_t launch_dft(const float* series, int64_t max_steps, const double* freq
 hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
                       double2** result, hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
+// fdtd_noalloc.hip
+hipError_t noalloc_scratch(int device, void** out);
+hipError_t launch_fft_split(const double2* x, int nbins, double* out, hipStream_t st);
 }  // namespace fdtd
 
 using namespace fdtd;
@@ -829,6 +832,15 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
         delete g;
         return fail(FDTD_EDEVICE, "no HIP device");
     }
+    // the allocation-free probe spectrum's fixed scratch: its address on this
+    // device is looked up once per device, here, with the device current
+    {
+        void* s = nullptr;
+        if (noalloc_scratch(g->device, &s) != hipSuccess) {
+            delete g;
+            return fail(FDTD_EDEVICE, "device scratch lookup failed");
+        }
+    }
     if (d.hip_stream) {
         g->stream = (hipStream_t)d.hip_stream;
     } else {
@@ -1574,6 +1586,41 @@ int fdtd_probe_fft(fdtd_grid* g, int id, int n_fft, double* re, double* im)
         re[k] = h[k].x;
         im[k] = h[k].y;
     }
+    return check_bad(g);
+}
+
+int fdtd_probe_fft_noalloc(fdtd_grid* g, int id, int n_fft, double* re, double* im)
+{
+    if (int e = check_grid(g)) return e;
+    if (id < 0 || id >= (int)g->probes.size()) return fail(FDTD_EINVAL, "no probe %d", id);
+    if (n_fft < 2 || (n_fft & (n_fft - 1)) || n_fft < g->step)
+        return fail(FDTD_EINVAL, "n_fft %d must be a power of two >= the step count %lld", n_fft,
+                    (long long)g->step);
+    if (n_fft > kNoAllocFftMax)
+        return fail(FDTD_EINVAL,
+                    "n_fft %d exceeds the allocation-free maximum %d (use fdtd_probe_fft)", n_fft,
+                    kNoAllocFftMax);
+    if (!re || !im) return fail(FDTD_EINVAL, "null output");
+    const int nbins = n_fft / 2 + 1;
+    if (!g->finalized) {
+        // nothing stepped yet (set-up, which allocates, has not run): no samples
+        std::fill(re, re + nbins, 0.0);
+        std::fill(im, im + nbins, 0.0);
+        return FDTD_OK;
+    }
+    void* s = nullptr;
+    HIP_OR_FAIL(noalloc_scratch(g->device, &s));
+    double2* a = (double2*)s;
+    double2* b = a + kNoAllocFftMax;
+    double2* res = nullptr;
+    HIP_OR_FAIL(launch_fft(g->prb_series + (size_t)id * g->d.max_steps, g->step, n_fft, a, b,
+                           &res, g->stream));
+    // the buffer the last pass did not write holds the split bins
+    double* split = (double*)(res == a ? b : a);
+    HIP_OR_FAIL(launch_fft_split(res, nbins, split, g->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(re, split, (size_t)nbins * 8, hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(im, split + nbins, (size_t)nbins * 8, hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     return check_bad(g);
 }
 

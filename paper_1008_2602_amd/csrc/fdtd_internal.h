@@ -32,6 +32,10 @@ constexpr int kGraphChunk = 32;
 constexpr int kPlaneRing = 32;
 static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly once");
 
+// largest transform of the allocation-free probe spectrum: its two FP64 complex
+// ping-pong buffers (32 B per point, 32 MiB) sit in a fixed device array
+constexpr int kNoAllocFftMax = 1 << 20;
+
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;
 

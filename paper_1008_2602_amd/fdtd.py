@@ -94,6 +94,7 @@ _sigs = {
     "fdtd_step_n": ([_P, C.c_int64], C.c_int),
     "fdtd_step_many": ([_P, C.c_int, _P], C.c_int),
     "fdtd_probe_fft": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
+    "fdtd_probe_fft_noalloc": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
     "fdtd_get_probe": ([_P, C.c_int, _P, C.c_int64], C.c_int),
     "fdtd_get_dft": ([_P, C.c_int, _P, _P], C.c_int),
     "fdtd_get_field": ([_P, C.c_int, _P], C.c_int),
@@ -281,6 +282,13 @@ def fdtd_probe_fft(g, pid: int, n_fft: int) -> np.ndarray:
     re = np.zeros(n_fft // 2 + 1)
     im = np.zeros(n_fft // 2 + 1)
     _check(_lib.fdtd_probe_fft(g, int(pid), int(n_fft), _ptr(re), _ptr(im)))
+    return re + 1j * im
+
+
+def fdtd_probe_fft_noalloc(g, pid: int, n_fft: int) -> np.ndarray:
+    re = np.zeros(n_fft // 2 + 1)
+    im = np.zeros(n_fft // 2 + 1)
+    _check(_lib.fdtd_probe_fft_noalloc(g, int(pid), int(n_fft), _ptr(re), _ptr(im)))
     return re + 1j * im
 
 
