@@ -56,7 +56,8 @@ class _Problem(C.Structure):
                 ("nprobe", C.c_int32), ("probe_ijk", C.c_void_p),
                 ("nfreq", C.c_int32), ("freqs", C.c_void_p),
                 ("pml_eps_rw", C.c_int32),
-                ("plane_k", C.c_int32), ("nplane_freq", C.c_int32), ("plane_freqs", C.c_void_p)]
+                ("plane_k", C.c_int32), ("nplane_freq", C.c_int32), ("plane_freqs", C.c_void_p),
+                ("sheet_R", C.c_double)]
 
 
 class _State(C.Structure):
@@ -119,6 +120,20 @@ class Problem:
             inner[p_[4]:b.nz - p_[5], p_[2]:b.ny - p_[3], p_[0]:b.nx - p_[1]] = True
             assert not np.any(self.sigma[~inner]), "conductivity only outside the PML slabs"
         self.pec = np.ascontiguousarray(b.pec_edge_mask, dtype=np.uint8)
+        self.sheet_R = float(getattr(b, "sheet_R", 0.0) or 0.0)
+        assert self.sheet_R >= 0.0 and np.isfinite(self.sheet_R)
+        if self.sheet_R > 0.0:
+            # sheet edges conduct like a lossy dielectric: only where every cell
+            # touching them lies outside the PML slabs (edges on the outer wall are
+            # never stepped and do not count)
+            p_ = b.npml
+            for bit, lo_i, lo_j in ((1, p_[0], p_[2] + 1), (2, p_[0] + 1, p_[2])):
+                kk, jj, ii = np.nonzero(self.pec & bit)
+                wall = ((kk == 0) | (kk == b.nz) | (ii == b.nx) | (jj == b.ny) |
+                        ((jj == 0) if bit == 1 else (ii == 0)))
+                ok = ((ii >= lo_i) & (ii < b.nx - p_[1]) & (jj >= lo_j) & (jj < b.ny - p_[3]) &
+                      (kk > p_[4]) & (kk < b.nz - p_[5]))
+                assert np.all(ok | wall), "resistive sheets only outside the PML slabs"
         ns = len(b.sources)
         self.src_ijk = np.array([[s.i, s.j, s.k] for s in b.sources], np.int32).reshape(ns, 3)
         self.src_wave = np.array([s.waveform for s in b.sources], np.int32)
@@ -164,6 +179,7 @@ class Problem:
         p.plane_k = self.plane_k
         p.nplane_freq = len(self.plane_freqs)
         p.plane_freqs = self.plane_freqs.ctypes.data
+        p.sheet_R = self.sheet_R
         self.c = p
 
     @property

@@ -30,6 +30,13 @@
  *     how long the ringing lasts): conductivity sigma_c per cell, the edge mean of
  *     the touching cells, with eps dE/dt + sigma_c Ebar = curl H - J and Ebar the
  *     mean of E^n and E^{n+1}, solved for E^{n+1} (interior edges only);
+ *   - conductor loss (the Results section names the perfect conductors, with the
+ *     lossless dielectric, as why the ringing lasts too long): with sheet_R > 0
+ *     every PEC-marked Ex/Ey edge is a thin resistive sheet of surface
+ *     resistance sheet_R (ohms per square) instead of a perfect conductor.  Its
+ *     sheet current density K = Ebar / sheet_R (A/m) flows within the edge's
+ *     dual cell, of height dz, so the edge carries the volume conductivity
+ *     1 / (sheet_R dz), added to any dielectric loss and stepped like it;
  *   - a resistive voltage source (Results section, the Table 1 run, built with
  *     semi-explicit update coefficients) is a lumped element on one E_z edge of
  *     the interior: an EMF V_s that raises node k+1 over node k, in series with
@@ -89,6 +96,8 @@ typedef struct {
     int32_t plane_k;           /* >= 0: running DFT of Ez(i, j, plane_k+1/2) over the plane */
     int32_t nplane_freq;
     const double* plane_freqs; /* Hz */
+    double sheet_R;            /* > 0: PEC-marked Ex/Ey edges are resistive sheets of this
+                                  surface resistance (ohm per square); 0: perfect conductors */
 } or_problem;
 
 typedef struct {
@@ -317,7 +326,9 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                 for (int i = 0; i < nx; ++i) {
                     /* Ex(i+1/2, j, k) */
                     size_t c = IX(i, j, k);
-                    if (pec[c] & 1) { ex[c] = 0.0; continue; }
+                    if ((pec[c] & 1) && !(p->sheet_R > 0.0)) { ex[c] = 0.0; continue; }
+                    /* a resistive sheet's edge: sheet conductance over the dual cell height */
+                    const double g_sh = (pec[c] & 1) ? 1.0 / (p->sheet_R * p->dz) : 0.0;
                     const double er_e = 0.25 *
                         ((double)er[CELL(i, j - 1, k - 1)] + (double)er[CELL(i, j, k - 1)] +
                          (double)er[CELL(i, j - 1, k)] + (double)er[CELL(i, j, k)]);
@@ -327,9 +338,9 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                                   cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hz[c] - hz[IX(i, j - 1, k)]) * rdy
                                 - (hy[c] - hy[IX(i, j, k - 1)]) * rdz;
-                    const double sg = !p->sigma_cell ? 0.0 : 0.25 *
+                    const double sg = g_sh + (!p->sigma_cell ? 0.0 : 0.25 *
                         ((double)p->sigma_cell[CELL(i, j - 1, k - 1)] + (double)p->sigma_cell[CELL(i, j, k - 1)] +
-                         (double)p->sigma_cell[CELL(i, j - 1, k)] + (double)p->sigma_cell[CELL(i, j, k)]);
+                         (double)p->sigma_cell[CELL(i, j - 1, k)] + (double)p->sigma_cell[CELL(i, j, k)]));
                     if (sg != 0.0) {
                         or_lossy(&ex[c], &Dx[c], curl, sg, eps, dt);
                         continue;
@@ -345,7 +356,8 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                 for (int i = 1; i < nx; ++i) {
                     /* Ey(i, j+1/2, k) */
                     size_t c = IX(i, j, k);
-                    if (pec[c] & 2) { ey[c] = 0.0; continue; }
+                    if ((pec[c] & 2) && !(p->sheet_R > 0.0)) { ey[c] = 0.0; continue; }
+                    const double g_sh = (pec[c] & 2) ? 1.0 / (p->sheet_R * p->dz) : 0.0;
                     const double er_e = 0.25 *
                         ((double)er[CELL(i - 1, j, k - 1)] + (double)er[CELL(i, j, k - 1)] +
                          (double)er[CELL(i - 1, j, k)] + (double)er[CELL(i, j, k)]);
@@ -355,9 +367,9 @@ int or_run(const or_problem* p, or_state* st, int64_t nsteps,
                                   cz = or_at(&Z, k, 0, ew, dt);
                     double curl = (hx[c] - hx[IX(i, j, k - 1)]) * rdz
                                 - (hz[c] - hz[IX(i - 1, j, k)]) * rdx;
-                    const double sg = !p->sigma_cell ? 0.0 : 0.25 *
+                    const double sg = g_sh + (!p->sigma_cell ? 0.0 : 0.25 *
                         ((double)p->sigma_cell[CELL(i - 1, j, k - 1)] + (double)p->sigma_cell[CELL(i, j, k - 1)] +
-                         (double)p->sigma_cell[CELL(i - 1, j, k)] + (double)p->sigma_cell[CELL(i, j, k)]);
+                         (double)p->sigma_cell[CELL(i - 1, j, k)] + (double)p->sigma_cell[CELL(i, j, k)]));
                     if (sg != 0.0) {
                         or_lossy(&ey[c], &Dy[c], curl, sg, eps, dt);
                         continue;

@@ -10,6 +10,8 @@
 * P12 plane-wide DFT: closed form on a cavity eigenmode, agreement with the probe DFT
 * P13 Eq. 2's eps_rw: uniform-medium equivalence, no-op in air, absorption in dielectric
 * P15 lossy dielectric: closed-form recurrence of a lossy cavity eigenmode
+* P17 conductor loss (resistive sheets): discrete energy balance, the closed-form
+      decay of a parallel-plate resonator, the R_s -> 0 and R_s -> infinity limits
 * Eq. 5 / Eq. 7 hand values (sigma_max, CFL step of the paper's grid)
 """
 import numpy as np
@@ -659,3 +661,149 @@ def test_p15_lossy_cavity_eigenmode_recurrence(oracle_mod):
     half = (1 + beta / 2) * u[2:] - (2 - s2) * u[1:-1] + (1 - beta / 2) * u[:-2]
     assert np.abs(explicit).max() > 1e3 * np.abs(res).max()
     assert np.abs(half).max() > 1e3 * np.abs(res).max()
+
+
+# ---------------------------------------------------------------------------
+# P17  conductor loss: the PEC sheets as thin resistive sheets of surface
+# resistance R_s (sheet current Ebar / R_s within the edge's dual cell)
+# ---------------------------------------------------------------------------
+
+def _sheet_masks(b):
+    """Live masks with the sheet edges counted as ordinary (stepped) edges."""
+    import dataclasses
+    open_b = dataclasses.replace(b, pec_edge_mask=(b.pec_edge_mask & 4).astype(np.uint8))
+    return live_masks(open_b)
+
+
+def _sheet_energy(b, e_now, h_a, h_b, eps, m):
+    V = b.dx * b.dy * b.dz
+    w = 0.0
+    for e in ("ex", "ey", "ez"):
+        w += 0.5 * np.sum(eps[e][m[e]] * e_now[e][m[e]] ** 2) * V
+    for h in ("hx", "hy", "hz"):
+        w += 0.5 * MU0 * np.sum(h_a[h][m[h]] * h_b[h][m[h]]) * V
+    return w
+
+
+def test_p17_sheet_energy_balance(oracle_mod):
+    """Undriven, from an arbitrary state: the discrete energy falls each step by
+    exactly the power the sheets dissipate, dt * sum over sheet edges of
+    Ebar^2 / R_s * dx dy (the sheet area one edge carries; Ebar the mean of E^n
+    and E^{n+1}).  A loss taken at E^n (explicit) or spread over dx instead of dz
+    breaks the balance."""
+    b = _inhomogeneous_box(31, nx=14, ny=11, nz=9)
+    b.sheet_R = 0.7
+    dt = oracle_mod.time_step(b)
+    eps = bruteforce.Stepper(b, dt).eps
+    m = _sheet_masks(b)
+    st = _random_state(oracle_mod, b, 31, aux=False)
+    sheet = {"ex": (b.pec_edge_mask & 1) != 0, "ey": (b.pec_edge_mask & 2) != 0}
+    for e in ("ex", "ey"):
+        st[e] = np.where(m[e], st[e] + 0.0, 0.0)
+        st[e][sheet[e] & m[e]] *= 20.0          # large start values on the sheet
+    states = [_snap(st)]
+    for _ in range(120):
+        oracle_mod.run(b, nsteps=1, state=st)
+        states.append(_snap(st))
+    W = np.array([_sheet_energy(b, states[n][0], states[n][1], states[n + 1][1], eps, m)
+                  for n in range(len(states) - 1)])
+    dW = W[1:] - W[:-1]
+
+    def loss(ebar_of, area):
+        out = np.zeros(len(dW))
+        for n in range(len(dW)):
+            for e in ("ex", "ey"):
+                sel = sheet[e] & m[e]
+                out[n] += dt * np.sum(ebar_of(n, e)[sel] ** 2) / b.sheet_R * area
+        return out
+
+    ebar = lambda n, e: 0.5 * (states[n][0][e] + states[n + 1][0][e])
+    res = dW + loss(ebar, b.dx * b.dy)
+    assert np.all(dW <= 1e-13 * W[0]) and -dW.sum() > 1e-2 * W[0]
+    assert np.abs(res).max() < 1e-11 * W[0]
+    explicit = dW + loss(lambda n, e: states[n][0][e], b.dx * b.dy)
+    wrong_h = dW + loss(ebar, b.dy * b.dz)
+    assert np.abs(explicit).max() > 1e3 * np.abs(res).max()
+    assert np.abs(wrong_h).max() > 1e3 * np.abs(res).max()
+
+
+def _plate_cavity(sheet_R, nx=20, ny=16, k0=2, k1=6, nz=8, dx=1e-3, dz=0.25e-3, eps_r=1.0,
+                  backing_sigma=20.0):
+    """PEC box with two full resistive sheets at planes k0 < k1: a parallel-plate
+    resonator between them.  The layers outside the sheets are a strongly lossy
+    dielectric (backing_sigma S/m), so that what leaks through a sheet is absorbed
+    there: an air layer would be a resonator with the same TM_mn0 frequencies as
+    the inner one and would trade energy with it."""
+    b = boardgen.cavity_box(nx, ny, nz, dx, dx, dz, eps_r, steps=1)
+    boardgen.pec_sheet(b.pec_edge_mask, k0, 0, nx, 0, ny)
+    boardgen.pec_sheet(b.pec_edge_mask, k1, 0, nx, 0, ny)
+    b.sheet_R = sheet_R
+    sig = np.zeros(b.eps_r_cell.shape, np.float32)
+    sig[:k0] = backing_sigma
+    sig[k1:] = backing_sigma
+    b.sigma_cell = sig
+    return b
+
+
+def _plate_mode_energy(oracle_mod, b, k0, k1, nsteps, p=1, q=1):
+    """Start the TM_pq0 mode of the plate pair consistently (Ez = S between the
+    plates, H at -1/2 from one half step of Faraday's law) and return the
+    discrete energy of the whole box at every step, and dt."""
+    nx, ny = b.nx, b.ny
+    dt = oracle_mod.time_step(b)
+    ii, jj = np.arange(nx + 1), np.arange(ny + 1)
+    S = np.outer(np.sin(q * np.pi * jj / ny), np.sin(p * np.pi * ii / nx))
+    st = oracle_mod.new_state(b)
+    st["ez"][k0:k1] = S[None]
+    st["hx"][k0:k1, :ny, :] = dt / (2 * MU0) * ((S[1:, :] - S[:-1, :]) / b.dy)[None]
+    st["hy"][k0:k1, :, :nx] = dt / (2 * MU0) * (-(S[:, 1:] - S[:, :-1]) / b.dx)[None]
+    eps = bruteforce.Stepper(b, dt).eps
+    m = _sheet_masks(b)
+    prev = _snap(st)
+    W = []
+    for _ in range(nsteps):
+        oracle_mod.run(b, nsteps=1, state=st)
+        cur = _snap(st)
+        W.append(_sheet_energy(b, prev[0], prev[1], cur[1], eps, m))
+        prev = cur
+    return np.array(W), dt
+
+
+def test_p17_plate_pair_decay_closed_form(oracle_mod):
+    """A TM_110 mode between two plates of surface resistance R_s, h apart,
+    loses energy at the rate of the textbook surface-resistance loss of a
+    parallel-plate resonator: P = R_s |H_t|^2 per plate area against the stored
+    mu0 |H|^2 h / 2, so the energy decays as exp(-2 R_s t / (mu0 h)) for every
+    TM_mn0 mode.  Fitted over 3000 steps (about 28 periods) for two R_s, within
+    1.5 % (measured 0.1-0.7 %: the sheet leaks a fraction of order R_s / eta0 into
+    the backing, and the grid's dispersion shifts the mode)."""
+    k0, k1, dz = 2, 6, 0.25e-3
+    h = (k1 - k0) * dz
+    for R_s in (0.5, 1.5):
+        b = _plate_cavity(R_s, k0=k0, k1=k1, dz=dz)
+        W, dt = _plate_mode_energy(oracle_mod, b, k0, k1, 3000)
+        t = (np.arange(len(W)) + 1) * dt
+        slope = np.polyfit(t, np.log(W), 1)[0]
+        alpha = R_s / (MU0 * h)
+        print(f"R_s {R_s}: fitted {-slope / 2:.4e} /s, closed form {alpha:.4e} /s")
+        assert abs(-slope / 2 / alpha - 1.0) < 0.015, (R_s, -slope / 2, alpha)
+        assert W[-1] < 0.5 * W[0]
+
+
+def test_p17_sheet_limits(oracle_mod):
+    """R_s -> 0 is the perfect conductor and R_s -> infinity no sheet at all, on
+    a board with a source, from zero, to 1e-10 of the field."""
+    base = _inhomogeneous_box(33, nx=14, ny=11, nz=9)
+    base.sources = [boardgen.Source(6, 5, 2, boardgen.GAUSS, 1e6, 20e-12, 6e-12)]
+    base.steps = 150
+    import dataclasses
+    pec = oracle_mod.run(base).state
+    tiny = oracle_mod.run(dataclasses.replace(base, sheet_R=1e-12)).state
+    none = oracle_mod.run(dataclasses.replace(
+        base, pec_edge_mask=(base.pec_edge_mask & 4).astype(np.uint8))).state
+    huge = oracle_mod.run(dataclasses.replace(base, sheet_R=1e30)).state
+    for n in ("ex", "ey", "ez", "hx", "hy", "hz"):
+        scale = np.abs(pec[n]).max()
+        assert np.abs(tiny[n] - pec[n]).max() <= 1e-10 * scale, n
+        assert np.abs(huge[n] - none[n]).max() <= 1e-10 * np.abs(none[n]).max(), n
+    assert np.abs(none["ez"] - pec["ez"]).max() > 1e-3 * np.abs(pec["ez"]).max()
