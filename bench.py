@@ -575,22 +575,36 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
             assert all(np.all(np.isfinite(x)) for x in spectra)
             return super().finish(handle, probe_ids, req)
 
-    srv = Server(FftExecutor(allocator=F.TorchAllocator()), budget, chunk=500)
+    ex = FftExecutor(allocator=F.TorchAllocator())
+    done = [0]
+
+    def progress(d):
+        # progress on stderr (stdout carries only the JSON line)
+        if d["chunk"] % 50 == 0:
+            print(f"[served] chunk {d['chunk']} at {d['t']:.0f} s: {d['resident']} resident, "
+                  f"{d['waiting']} waiting", file=sys.stderr, flush=True)
+
+    srv = Server(ex, budget, chunk=500, workers=2, depth=2, log=progress)
     t0 = time.perf_counter()
     res = srv.run(requests)
     wall = time.perf_counter() - t0
     s = summarize(res, wall_s=wall)
+    busy = ex.busy_fraction()
     out = {
         "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x measured "
                     f"capacity) of board variants, 5% 800x800x64, {steps} steps each, "
-                    f"500-step chunks, probe FFT per solve",
+                    f"500-step chunks (up to two in flight, set-up and read-back on two "
+                    f"worker threads), probe FFT per solve",
         "p50_latency_s": round(s["p50_latency_s"], 4),
         "p99_latency_s": round(s["p99_latency_s"], 4),
         "solves_per_s": round(s["solves_per_s"], 4),
         "gcell_updates_per_s": round(s["gcell_updates_per_s"], 3),
         "requests": n_requests,
         "large_boards": sum(1 for r in requests if (r.board.nx, r.board.ny) == (800, 800)),
+        "latency_samples": s["completed"],
         "completed": s["completed"],
+        "gpu_busy_frac": round(busy, 4) if busy is not None else None,
+        "chunks": srv.chunks,
         "peak_resident": srv.peak_resident,
         "budget_gb": round(budget / 1e9, 1),
     }

@@ -91,7 +91,10 @@ typedef struct {
     int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
     int32_t plane_k;             /* plane of the plane DFT, -1 if none */
     int32_t plane_nf;            /* its number of frequencies */
-    int32_t node_passes;         /* 1: steps run the node passes (fdtd_set_pml_eps_rw, fdtd_set_conductivity) */
+    int32_t node_passes;         /* 1: steps run the node passes (fdtd_set_pml_eps_rw, fdtd_set_conductivity,
+                                    fdtd_set_sheet_resistance) */
+    int32_t batch_plans;         /* plans of fdtd_step_many calls this handle led, kept for reuse */
+    int32_t batch_graphs;        /* of which captured as a graph (one graph launch per call) */
 } fdtd_info;
 
 /* Create a grid (Model section: Yee grid with anisotropic spacing, UPML of
@@ -181,6 +184,20 @@ int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);
  * first step. */
 int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell);
 
+/* Conductor loss (the Results section names the perfect conductors, beside the
+ * lossless dielectric, as why the modelled resonances ring too long): with
+ * ohms_per_square > 0 every PEC-marked Ex/Ey edge (the power and ground planes)
+ * is a thin resistive sheet of that surface resistance R_s instead of a
+ * perfect conductor.  Its sheet current Ebar / R_s (A/m; Ebar the mean of E^n
+ * and E^{n+1}) flows within the edge's dual cell of height dz, so the edge
+ * carries the conductivity 1 / (R_s dz), is solved for E^{n+1} like a lossy
+ * dielectric and adds to any conductivity set by fdtd_set_conductivity; PEC Ez
+ * edges stay perfect.  0 (the default) keeps perfect conductors.  A board with
+ * sheets steps with the node passes (see fdtd_set_pml_eps_rw).  EINVAL if the
+ * value is negative or not finite, and at the first step if a stepped sheet
+ * edge touches a cell of a PML slab; ESTATE after the first step. */
+int fdtd_set_sheet_resistance(fdtd_grid* g, double ohms_per_square);
+
 /* Plane DFT: the running DFT of Ez(i, j, k+1/2) over every node of the node plane
  * k (0 <= k < nz; the ground-plane field of the Results section, Figs. 3-5, in the
  * frequency domain): A_f(i, j) = sum_s Ez_s(i, j) exp(-i 2 pi f (s+1) dt) dt, FP32
@@ -204,12 +221,18 @@ int fdtd_set_plane_dft(fdtd_grid* g, int k, const double* f_hz, int nf);
 int fdtd_step_n(fdtd_grid* g, int64_t n);
 
 /* Batched stepping: advance ng handles by n[h] steps each in shared launches
- * (one field launch per step covers every handle still running; handles whose
+ * (one field launch per pass covers every handle still running; handles whose
  * class index widths differ go to two launches).  Handles must be distinct and
- * share one device; results are bitwise those of stepping each alone.  Runs on
- * the first handle's stream, ordered after (and before) work on the other
- * handles' streams by events; uses the first handle's tile shape.  Same errors
- * as fdtd_step_n. */
+ * share one device; results are bitwise those of stepping each alone (the probe
+ * DFT to rounding: it sums each call's samples in one pass).  Runs on the first
+ * handle's stream, ordered after (and before) work on the other handles'
+ * streams by events; uses the first handle's tile shape.  The first call with a
+ * given (handles in order, step counts, lead tile shape) builds a plan: the
+ * per-board tables and work lists in device memory, and the call's launches
+ * captured as a HIP graph when the lead's stream can be captured; later calls
+ * with the same plan replay it as one graph launch and return without waiting
+ * for the device.  The lead keeps its last 4 plans.  Boards on the node passes
+ * step on their own streams.  Same errors as fdtd_step_n. */
 int fdtd_step_many(fdtd_grid* const* g, int ng, const int64_t* n);
 
 /* Upper bound of the device memory (bytes) fdtd_create_grid with this

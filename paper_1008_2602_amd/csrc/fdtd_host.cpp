@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -30,13 +31,16 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
 int field_step2_occupancy(int tile_y, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
-hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int rel, int flip,
-                           bool wide, hipStream_t st);
+hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int64_t plane_bytes,
+                           bool big, int rel, int flip, bool wide, hipStream_t st);
 hipError_t launch_plane_fold(const float* ring, int64_t plane_nodes, const double* freqs, int nf,
                              double dt, const int64_t* step, int64_t rel_from, int64_t rel_to,
                              double* tw, double* re, double* im, hipStream_t st);
 hipError_t launch_dft(const float* series, int64_t max_steps, const double* freqs, int nf, int np,
                       double dt, int64_t s0, int64_t s1, double* re, double* im, hipStream_t st);
+hipError_t launch_dft_back(const float* series, int64_t max_steps, const double* freqs, int nf,
+                           int np, double dt, const int64_t* step, int64_t back, double* re,
+                           double* im, hipStream_t st);
 hipError_t launch_fft(const float* series, int64_t n_samples, int n_fft, double2* a, double2* b,
                       double2** result, hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
@@ -118,6 +122,7 @@ struct fdtd_grid {
     int64_t pitch = 0;      // device row pitch in nodes: nx+1 rounded up to 32
     int64_t dnodes = 0;     // device nodes per field array: pitch (ny+1)(nz+1)
     int64_t cstride = 0;    // bytes between the x, y, z arrays of one field
+    bool big = false;       // 3 cstride beyond 32-bit offsets: the node passes with per-component bases
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -132,6 +137,8 @@ struct fdtd_grid {
     ClassEntry* ctab = nullptr;
     float* node_aux = nullptr;
     int32_t* src_node = nullptr;
+    int64_t* src_node64 = nullptr;
+    int64_t* prb_node64 = nullptr;
     float* src_j = nullptr;
     float* src_beta = nullptr;
     int32_t* prb_node = nullptr;
@@ -167,6 +174,7 @@ struct fdtd_grid {
     std::vector<double> freqs;
     int plane_k = -1;               // plane-DFT node plane, -1: none
     bool pml_eps_rw = false;        // Eq. 2's eps_rw requested
+    double sheet_R = 0.0;           // > 0: PEC Ex/Ey edges are resistive sheets (ohm per square)
     bool node_pass = false;         // steps run the node passes (eps_rw in a dielectric PML, or loss)
     std::vector<double> plane_freqs;
     int n_classes = 0;
@@ -188,13 +196,12 @@ struct fdtd_grid {
     bool graph_failed = false;
     hipEvent_t sync_ev = nullptr;
 
-    // batched-launch scratch (owned by the handle that leads a batch)
-    BoardDev* batch_boards = nullptr;
-    int batch_boards_cap = 0;
-    TileRef* batch_tiles = nullptr;
-    int batch_tiles_cap = 0;
-    int64_t* batch_n = nullptr;
-    int batch_n_cap = 0;
+    // batched calls led by this handle: their plans (tables in device memory and
+    // a captured graph), most recently used kept
+    uint64_t serial = 0;            // unique per handle created in this process
+    std::vector<struct BatchPlan*> plans;
+    std::vector<struct BatchPlan*> retired;   // evicted, freed once their last launch is done
+    uint64_t plan_clock = 0;
 };
 
 namespace {
@@ -498,8 +505,15 @@ int finalize(fdtd_grid* g)
             return fail(FDTD_EINVAL, "source at (%d,%d,%d) sits on a PEC edge", s.i, s.j, s.k);
     }
     std::vector<int32_t> src_node, prb_node;
-    for (const SourceH& s : g->sources) src_node.push_back((int32_t)dev_index(g, s.i, s.j, s.k));
-    for (const auto& p : g->probes) prb_node.push_back((int32_t)dev_index(g, p[0], p[1], p[2]));
+    std::vector<int64_t> src_node64, prb_node64;
+    for (const SourceH& s : g->sources) {
+        src_node64.push_back(dev_index(g, s.i, s.j, s.k));
+        src_node.push_back((int32_t)src_node64.back());   // tiled kernels: boards within 2^31 nodes
+    }
+    for (const auto& p : g->probes) {
+        prb_node64.push_back(dev_index(g, p[0], p[1], p[2]));
+        prb_node.push_back((int32_t)prb_node64.back());
+    }
     std::vector<uint8_t> is_src(0), is_prb(0);
 
     // per-node classes: edge permittivity (mean of the touching cells), stepped
@@ -529,20 +543,37 @@ int finalize(fdtd_grid* g)
     };
     const double lscale = g->dt / (2.0 * kEps0);   // sigma_c -> sigma_c dt / (2 eps0)
     auto in_slab = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
-    g->node_pass = false;
+    // resistive sheets: a PEC-marked Ex/Ey edge carries the sheet current
+    // Ebar / R_s within its dual cell of height dz, a conductivity 1 / (R_s dz)
+    const bool sheets = g->sheet_R > 0.0;
+    const double g_sheet = sheets ? 1.0 / (g->sheet_R * d.dz) : 0.0;
+    auto pml_cell = [&](int i, int j, int k) {
+        return in_slab(i, nx, d.npml[0], d.npml[1]) || in_slab(j, ny, d.npml[2], d.npml[3]) ||
+               in_slab(k, nz, d.npml[4], d.npml[5]);
+    };
+    g->node_pass = g->big;
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
                 const int64_t n = node_index(g, i, j, k);
                 const uint8_t pm = g->pec[n];
+                const bool shx = sheets && (pm & 1), shy = sheets && (pm & 2);
                 uint32_t fl = 0;
                 float ix = 0.f, iy = 0.f, iz = 0.f;
-                if (i < nx && j >= 1 && j < ny && k >= 1 && k < nz && !(pm & 1)) {
+                if (i < nx && j >= 1 && j < ny && k >= 1 && k < nz && (!(pm & 1) || shx)) {
+                    if (shx && (pml_cell(i, j - 1, k - 1) || pml_cell(i, j, k - 1) ||
+                                pml_cell(i, j - 1, k) || pml_cell(i, j, k)))
+                        return fail(FDTD_EINVAL,
+                                    "resistive sheet edge Ex(%d,%d,%d) touches a PML cell", i, j, k);
                     fl |= kUpdEx;
                     ix = (float)(4.0 / (cell(i, j - 1, k - 1) + cell(i, j, k - 1) +
                                         cell(i, j - 1, k) + cell(i, j, k)));
                 }
-                if (i >= 1 && i < nx && j < ny && k >= 1 && k < nz && !(pm & 2)) {
+                if (i >= 1 && i < nx && j < ny && k >= 1 && k < nz && (!(pm & 2) || shy)) {
+                    if (shy && (pml_cell(i - 1, j, k - 1) || pml_cell(i, j, k - 1) ||
+                                pml_cell(i - 1, j, k) || pml_cell(i, j, k)))
+                        return fail(FDTD_EINVAL,
+                                    "resistive sheet edge Ey(%d,%d,%d) touches a PML cell", i, j, k);
                     fl |= kUpdEy;
                     iy = (float)(4.0 / (cell(i - 1, j, k - 1) + cell(i, j, k - 1) +
                                         cell(i - 1, j, k) + cell(i, j, k)));
@@ -571,14 +602,18 @@ int finalize(fdtd_grid* g)
                         g->node_pass = true;
                 }
                 float lx = 0.f, ly = 0.f, lz = 0.f;
-                if (lossy) {
+                if (lossy || sheets) {
                     if (fl & kUpdEx)
-                        lx = (float)(lscale * 0.25 * (sig(i, j - 1, k - 1) + sig(i, j, k - 1) +
-                                                      sig(i, j - 1, k) + sig(i, j, k)));
+                        lx = (float)(lscale * ((lossy ? 0.25 * (sig(i, j - 1, k - 1) + sig(i, j, k - 1) +
+                                                                sig(i, j - 1, k) + sig(i, j, k))
+                                                      : 0.0) +
+                                               (shx ? g_sheet : 0.0)));
                     if (fl & kUpdEy)
-                        ly = (float)(lscale * 0.25 * (sig(i - 1, j, k - 1) + sig(i, j, k - 1) +
-                                                      sig(i - 1, j, k) + sig(i, j, k)));
-                    if (fl & kUpdEz)
+                        ly = (float)(lscale * ((lossy ? 0.25 * (sig(i - 1, j, k - 1) + sig(i, j, k - 1) +
+                                                                sig(i - 1, j, k) + sig(i, j, k))
+                                                      : 0.0) +
+                                               (shy ? g_sheet : 0.0)));
+                    if ((fl & kUpdEz) && lossy)
                         lz = (float)(lscale * 0.25 * (sig(i - 1, j - 1, k) + sig(i, j - 1, k) +
                                                       sig(i - 1, j, k) + sig(i, j, k)));
                     if (lx != 0.f || ly != 0.f || lz != 0.f) g->node_pass = true;
@@ -650,20 +685,25 @@ int finalize(fdtd_grid* g)
                 js[(size_t)s * ms + t] = (float)(scale * waveform(q, (t + 0.5) * g->dt));
         }
         g->src_node = (int32_t*)dev_alloc(g, ns * 4);
+        g->src_node64 = (int64_t*)dev_alloc(g, ns * 8);
         g->src_j = (float*)dev_alloc(g, js.size() * 4);
         g->src_beta = (float*)dev_alloc(g, ns * 4);
-        if (!g->src_node || !g->src_j || !g->src_beta)
+        if (!g->src_node || !g->src_node64 || !g->src_j || !g->src_beta)
             return fail(FDTD_ENOMEM, "source table allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->src_node, src_node.data(), ns * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->src_node64, src_node64.data(), ns * 8, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipMemcpyAsync(g->src_j, js.data(), js.size() * 4, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipMemcpyAsync(g->src_beta, beta.data(), ns * 4, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
     }
     if (np) {
         g->prb_node = (int32_t*)dev_alloc(g, np * 4);
+        g->prb_node64 = (int64_t*)dev_alloc(g, np * 8);
         g->prb_series = (float*)dev_alloc(g, (size_t)np * ms * 4);
-        if (!g->prb_node || !g->prb_series) return fail(FDTD_ENOMEM, "probe buffer allocation failed");
+        if (!g->prb_node || !g->prb_node64 || !g->prb_series)
+            return fail(FDTD_ENOMEM, "probe buffer allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->prb_node, prb_node.data(), np * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(hipMemcpyAsync(g->prb_node64, prb_node64.data(), np * 8, hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(launch_fill_zero(g->prb_series, (int64_t)np * ms, st));
     }
     const int nf = (int)g->freqs.size();
@@ -709,6 +749,9 @@ int finalize(fdtd_grid* g)
     b.ctab = g->ctab;
     b.node_aux = g->node_aux;
     b.src_node = g->src_node;
+    b.src_node64 = g->src_node64;
+    b.prb_node64 = g->prb_node64;
+    b.cstride64 = (uint64_t)g->cstride;
     b.src_j = g->src_j;
     b.src_beta = g->src_beta;
     b.prb_node = g->prb_node;
@@ -719,7 +762,7 @@ int finalize(fdtd_grid* g)
     b.ny = ny;
     b.nz = nz;
     b.pitch = (int32_t)g->pitch;
-    b.cstride = (uint32_t)g->cstride;
+    b.cstride = g->big ? 0u : (uint32_t)g->cstride;   // the tiled kernels never run a big board
     b.nsrc = ns;
     b.nprb = np;
     b.nclass = (int32_t)table.size();
@@ -787,11 +830,12 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
     const int64_t pitch = row_pitch(d.nx);
     const int64_t dnodes = pitch * (d.ny + 1) * (d.nz + 1);
     const int64_t cstride = component_stride(dnodes);
-    if (3 * cstride >= (int64_t(1) << 32))
-        return fail(FDTD_EINVAL,
-                    "grid too large: the three components of a field (%lld padded nodes each, "
-                    "row pitch %lld) must fit a 4 GiB window",
-                    (long long)dnodes, (long long)pitch);
+    // past the 4 GiB window of the tiled kernels' offsets the node passes step
+    // the board from per-component bases; they need three planes in 32 bits
+    const int64_t plane_bytes = pitch * (d.ny + 1) * 4;
+    if (3 * plane_bytes >= (int64_t(1) << 32))
+        return fail(FDTD_EINVAL, "grid too large: three node planes (%lld bytes each) must fit 4 GiB",
+                    (long long)plane_bytes);
     if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !std::isfinite(d.dx) ||
         !std::isfinite(d.dy) || !std::isfinite(d.dz))
         return fail(FDTD_EINVAL, "cell sizes must be positive and finite");
@@ -821,6 +865,8 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
 
     fdtd_grid* g = new (std::nothrow) fdtd_grid();
     if (!g) return fail(FDTD_ENOMEM, "host allocation failed");
+    static std::atomic<uint64_t> next_serial{1};
+    g->serial = next_serial.fetch_add(1);
     g->d = d;
     g->dt = dt;
     g->nodes = nodes;
@@ -874,6 +920,7 @@ int fdtd_create_grid(const fdtd_grid_desc* desc, fdtd_grid** out)
             }
         }
     g->cstride = cstride;
+    g->big = 3 * cstride >= (int64_t(1) << 32);
     for (int a = 0; a < 3; ++a) {
         std::vector<float> t = coef_table(d, a, dt);
         if (!(g->coef[a] = (float*)dev_alloc(g, t.size() * 4)))
@@ -1024,6 +1071,16 @@ int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell)
     return FDTD_OK;
 }
 
+int fdtd_set_sheet_resistance(fdtd_grid* g, double ohms_per_square)
+{
+    if (int e = check_grid(g)) return e;
+    if (g->finalized) return fail(FDTD_ESTATE, "the sheet resistance is fixed after the first step");
+    if (!(ohms_per_square >= 0.0) || !std::isfinite(ohms_per_square))
+        return fail(FDTD_EINVAL, "sheet resistance must be finite and >= 0");
+    g->sheet_R = ohms_per_square;
+    return FDTD_OK;
+}
+
 int fdtd_set_pml_eps_rw(fdtd_grid* g, int on)
 {
     if (int e = check_grid(g)) return e;
@@ -1164,7 +1221,8 @@ static int enqueue_steps(fdtd_grid* g, int64_t n, int64_t* launches)
         for (int64_t s = 0; s < n; ++s) {
             if (g->timing)
                 if (int e = record_event(g)) return e;
-            HIP_OR_FAIL(launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, (int)s, (int)(s & 1),
+            HIP_OR_FAIL(launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz,
+                                        g->pitch * (g->d.ny + 1) * 4, g->big, (int)s, (int)(s & 1),
                                         g->wide, g->stream));
             if (g->timing) {
                 if (int e = record_event(g)) return e;
@@ -1198,7 +1256,8 @@ static void build_graph(fdtd_grid* g)
     bool ok = true;
     const int per = g->node_pass ? 1 : g->tile_steps, nl = kGraphChunk / per;
     for (int l = 0; l < nl && ok; ++l)
-        ok = (g->node_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, l, l & 1, g->wide,
+        ok = (g->node_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz,
+                                            g->pitch * (g->d.ny + 1) * 4, g->big, l, l & 1, g->wide,
                                             g->stream)
                           : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
                                         g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
@@ -1261,7 +1320,298 @@ static int ensure_event(fdtd_grid* g)
     return FDTD_OK;
 }
 
-static int step_many_round(fdtd_grid* const* gs, int ng, const int64_t* n);
+// ---------------------------------------------------------------------------
+// Batched stepping.  A call is planned once per (handles, step counts, lead
+// shape): the per-board descriptors, the balanced work lists and the counter
+// advances of every round go to one device buffer, and the call's launches are
+// captured into a graph that later calls with the same plan replay (one graph
+// launch per call).  Plans live with the lead handle.
+
+namespace {
+
+// launches of one work list: passes s0 .. s1-1 of `steps` steps each, or the
+// single-step tail launch (which reads the boards' tail copies)
+struct Span {
+    int w, steps;
+    int64_t s0, s1;
+    int off, count;   // into the round's tile list
+    bool tail;
+};
+
+// One round: every handle advances by n[h] steps (at most kPlaneRing when some
+// handle keeps a plane DFT, whose ring is folded after every round).
+struct RoundHost {
+    std::vector<int64_t> n;         // per handle, call order
+    std::vector<int> order;         // boards in launch order
+    std::vector<BoardDev> boards;   // [0, ng): passes; [ng, 2 ng): the single-step tail
+    std::vector<int64_t> adv;       // per board: steps, launches (field-buffer flips)
+    std::vector<Span> spans;
+    std::vector<TileRef> items;
+};
+
+}  // namespace
+
+struct BatchPlan {
+    std::vector<uint64_t> key;
+    std::vector<int64_t> n;          // per handle, the call's steps
+    std::vector<int64_t> flips;      // per handle, field-buffer flips of the call
+    std::vector<RoundHost> rounds;
+    char* dev = nullptr;             // device tables of every round
+    size_t dev_bytes = 0;
+    std::vector<size_t> off_boards, off_adv, off_tiles;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;       // recorded after every launch of the plan
+    uint64_t used = 0;
+};
+
+namespace {
+
+// Host side of one round (board order, descriptors, work lists).
+void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
+{
+    fdtd_grid* lead = gs[0];
+    const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
+    r.n.assign(n, n + ng);
+    // order boards by step count (descending): at pass s the boards still running
+    // form a prefix, and so do their tiles; narrow and wide class maps go to
+    // separate launches (the kernel is specialised on the class index width)
+    r.order.resize(ng);
+    for (int h = 0; h < ng; ++h) r.order[h] = h;
+    std::stable_sort(r.order.begin(), r.order.end(), [&](int a, int b) {
+        if (gs[a]->wide != gs[b]->wide) return gs[a]->wide < gs[b]->wide;
+        return n[a] > n[b];
+    });
+    // board b runs np[b] passes of `per` steps, then (two-step shapes) one single
+    // step when its count is odd.  boards[ng + b] is the copy the single-step
+    // launch reads: its step and buffer offsets skip the board's own passes.
+    r.boards.assign(2 * (size_t)ng, BoardDev{});
+    r.adv.assign(2 * (size_t)ng, 0);
+    std::vector<int64_t> np(ng), odd(ng);
+    int64_t max_np = 0;
+    for (int b = 0; b < ng; ++b) {
+        const int64_t nb = n[r.order[b]];
+        np[b] = nb / per;
+        odd[b] = nb - np[b] * per;
+        max_np = std::max(max_np, np[b]);
+        r.boards[b] = gs[r.order[b]]->board_host;
+        r.boards[ng + b] = r.boards[b];
+        r.boards[ng + b].rel0 = (int32_t)(np[b] * per);
+        r.boards[ng + b].flip0 = (int32_t)(np[b] & 1);
+        r.adv[2 * b] = nb;
+        r.adv[2 * b + 1] = np[b] + odd[b];
+    }
+    // Each class width forms a group [b0, b1) of the order; at pass s the boards
+    // still running are a prefix [b0, active) of it.  One balanced work list per
+    // distinct prefix, plus one for the single-step tail, all in one buffer.
+    r.spans.clear();
+    r.items.clear();
+    std::vector<TileRef> whole, list;
+    for (int w = 0; w < 2; ++w) {
+        int b0 = 0;
+        while (b0 < ng && gs[r.order[b0]]->wide != (w == 1)) ++b0;
+        if (b0 == ng) continue;
+        int b1 = b0;
+        while (b1 < ng && gs[r.order[b1]]->wide == (w == 1)) ++b1;
+        int64_t s = 0;
+        for (int active = b1; active > b0 && s < max_np;) {
+            const int64_t s_end = np[active - 1];  // boards [b0, active) all run through s_end
+            if (s_end > s) {
+                whole.clear();
+                for (int b = b0; b < active; ++b) {
+                    const fdtd_grid* g = gs[r.order[b]];
+                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, per), whole);
+                }
+                build_work(whole, slots_per_xcd(lead, tx, ty, per, w == 1), list);
+                r.spans.push_back(Span{w, per, s, s_end, (int)r.items.size(), (int)list.size(), false});
+                r.items.insert(r.items.end(), list.begin(), list.end());
+                s = s_end;
+            }
+            --active;
+        }
+        whole.clear();
+        for (int b = b0; b < b1; ++b)
+            if (odd[b]) {
+                const fdtd_grid* g = gs[r.order[b]];
+                board_tiles(b, g->d.nx, g->d.ny, g->d.nz, kOddX, owned_rows(kOddY, 1), whole);
+            }
+        if (!whole.empty()) {
+            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1), list);
+            r.spans.push_back(Span{w, 1, 0, 1, (int)r.items.size(), (int)list.size(), true});
+            r.items.insert(r.items.end(), list.begin(), list.end());
+        }
+    }
+}
+
+bool any_plane(fdtd_grid* const* gs, int ng)
+{
+    for (int h = 0; h < ng; ++h)
+        if (gs[h]->plane_k >= 0) return true;
+    return false;
+}
+
+void free_plan(fdtd_grid* lead, BatchPlan* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->dev) {
+        temp_free(lead, p->dev);
+        lead->device_bytes -= (int64_t)p->dev_bytes;
+    }
+    delete p;
+}
+
+// Enqueue a plan's launches on st (also used inside graph capture): every
+// round's field launches and counter advance, the plane folds after each
+// round, then each handle's probe DFT over the whole call.
+int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t st)
+{
+    const fdtd_grid* lead = gs[0];
+    const int tx = lead->tile_x, ty = lead->tile_y;
+    const bool planes = any_plane(gs, ng);
+    for (size_t q = 0; q < P.rounds.size(); ++q) {
+        const RoundHost& R = P.rounds[q];
+        const BoardDev* db = (const BoardDev*)(P.dev + P.off_boards[q]);
+        const int64_t* dn = (const int64_t*)(P.dev + P.off_adv[q]);
+        const TileRef* dt = (const TileRef*)(P.dev + P.off_tiles[q]);
+        for (const Span& sp : R.spans) {
+            if (sp.tail) {
+                HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, db + ng, dt + sp.off, sp.count, 0, 0,
+                                        sp.w == 1, planes, st));
+                continue;
+            }
+            for (int64_t k = sp.s0; k < sp.s1; ++k)
+                HIP_OR_FAIL(launch_pass(tx, ty, sp.steps, db, dt + sp.off, sp.count,
+                                        (int)(k * sp.steps), (int)(k & 1), sp.w == 1, planes, st));
+        }
+        HIP_OR_FAIL(launch_advance((BoardDev*)db, ng, dn, st));
+        for (int h = 0; h < ng; ++h)
+            if (R.n[h] > 0)
+                if (int e = fold_plane(gs[h], -R.n[h], 0, st)) return e;
+    }
+    for (int h = 0; h < ng; ++h) {
+        const fdtd_grid* g = gs[h];
+        if (g->dft_f && P.n[h] > 0)
+            HIP_OR_FAIL(launch_dft_back(g->prb_series, g->d.max_steps, g->dft_f,
+                                        (int)g->freqs.size(), (int)g->probes.size(), g->dt,
+                                        g->step_dev, P.n[h], g->dft_re, g->dft_im, st));
+    }
+    return FDTD_OK;
+}
+
+// Plan a batched call: rounds, device tables (copied with a synchronous copy
+// that does not wait for the handles' streams) and, where the lead's stream can
+// be captured, the graph of its launches.
+int build_plan(fdtd_grid* const* gs, int ng, const int64_t* n, BatchPlan* P)
+{
+    fdtd_grid* lead = gs[0];
+    P->n.assign(n, n + ng);
+    P->flips.assign(ng, 0);
+    std::vector<int64_t> left(n, n + ng), r(ng);
+    const bool planes = any_plane(gs, ng);
+    for (bool more = true; more;) {
+        more = false;
+        for (int h = 0; h < ng; ++h) {
+            r[h] = planes ? std::min<int64_t>(left[h], kPlaneRing) : left[h];
+            left[h] -= r[h];
+            more |= left[h] > 0;
+        }
+        P->rounds.emplace_back();
+        plan_round(gs, ng, r.data(), P->rounds.back());
+        const RoundHost& R = P->rounds.back();
+        for (int b = 0; b < ng; ++b) P->flips[R.order[b]] += R.adv[2 * b + 1];
+    }
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t total = 0;
+    for (const RoundHost& R : P->rounds) {
+        P->off_boards.push_back(total);
+        total += up(R.boards.size() * sizeof(BoardDev));
+        P->off_adv.push_back(total);
+        total += up(R.adv.size() * sizeof(int64_t));
+        P->off_tiles.push_back(total);
+        total += up(std::max<size_t>(1, R.items.size()) * sizeof(TileRef));
+    }
+    std::vector<char> host(total, 0);
+    for (size_t q = 0; q < P->rounds.size(); ++q) {
+        const RoundHost& R = P->rounds[q];
+        memcpy(host.data() + P->off_boards[q], R.boards.data(), R.boards.size() * sizeof(BoardDev));
+        memcpy(host.data() + P->off_adv[q], R.adv.data(), R.adv.size() * sizeof(int64_t));
+        if (!R.items.empty())
+            memcpy(host.data() + P->off_tiles[q], R.items.data(), R.items.size() * sizeof(TileRef));
+    }
+    HIP_OR_FAIL(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
+    P->dev = (char*)temp_alloc(lead, total);
+    if (!P->dev) return fail(FDTD_ENOMEM, "batch plan allocation failed");
+    P->dev_bytes = up(total);
+    lead->device_bytes += (int64_t)P->dev_bytes;
+    HIP_OR_FAIL(hipMemcpy(P->dev, host.data(), total, hipMemcpyHostToDevice));
+    // capture the launches (a stream that cannot be captured keeps plain launches)
+    if (!lead->own_stream && lead->stream == nullptr) return FDTD_OK;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(lead->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int e = enqueue_plan(gs, ng, *P, lead->stream);
+        const bool ended = hipStreamEndCapture(lead->stream, &graph) == hipSuccess;
+        if (e != FDTD_OK || !ended || !graph ||
+            hipGraphInstantiate(&P->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            P->exec = nullptr;
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    (void)hipGetLastError();
+    return FDTD_OK;
+}
+
+constexpr size_t kPlansKept = 4;
+
+// The plan of this call from the lead's cache, built if missing.
+int find_plan(fdtd_grid* const* gs, int ng, const int64_t* n, BatchPlan** out)
+{
+    fdtd_grid* lead = gs[0];
+    std::vector<uint64_t> key;
+    key.reserve(2 * (size_t)ng + 3);
+    key.push_back((uint64_t)lead->tile_x);
+    key.push_back((uint64_t)lead->tile_y);
+    key.push_back((uint64_t)lead->tile_steps);
+    for (int h = 0; h < ng; ++h) {
+        key.push_back(gs[h]->serial);
+        key.push_back((uint64_t)n[h]);
+    }
+    ++lead->plan_clock;
+    // free the retired plans whose last launch has finished
+    for (size_t q = 0; q < lead->retired.size();) {
+        if (hipEventQuery(lead->retired[q]->done) == hipSuccess) {
+            free_plan(lead, lead->retired[q]);
+            lead->retired.erase(lead->retired.begin() + (std::ptrdiff_t)q);
+        } else {
+            ++q;
+        }
+    }
+    (void)hipGetLastError();   // hipErrorNotReady from the queries
+    for (BatchPlan* p : lead->plans)
+        if (p->key == key) {
+            p->used = lead->plan_clock;
+            *out = p;
+            return FDTD_OK;
+        }
+    if (lead->plans.size() >= kPlansKept) {
+        auto lru = std::min_element(lead->plans.begin(), lead->plans.end(),
+                                    [](const BatchPlan* a, const BatchPlan* b) { return a->used < b->used; });
+        // the evicted plan's last launch may still run: it is freed later
+        lead->retired.push_back(*lru);
+        lead->plans.erase(lru);
+    }
+    BatchPlan* p = new (std::nothrow) BatchPlan();
+    if (!p) return fail(FDTD_ENOMEM, "host allocation failed");
+    p->key = std::move(key);
+    p->used = lead->plan_clock;
+    if (int e = build_plan(gs, ng, n, p)) {
+        free_plan(lead, p);
+        return e;
+    }
+    lead->plans.push_back(p);
+    *out = p;
+    return FDTD_OK;
+}
+
+}  // namespace
 
 int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
 {
@@ -1293,116 +1643,13 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
         if (fused.empty()) return FDTD_OK;
         return fdtd_step_many(fused.data(), (int)fused.size(), nfused.data());
     }
-    bool planes = false;
-    for (int h = 0; h < ng; ++h) planes |= gs[h]->plane_k >= 0;
-    if (!planes) return step_many_round(gs, ng, n);
-    // plane DFTs fold their rings at least every kPlaneRing steps: rounds of at
-    // most that many steps per handle
-    std::vector<int64_t> left(n, n + ng), r(ng);
-    for (bool more = true; more;) {
-        more = false;
-        for (int h = 0; h < ng; ++h) {
-            r[h] = std::min<int64_t>(left[h], kPlaneRing);
-            left[h] -= r[h];
-            more |= left[h] > 0;
-        }
-        if (int e = step_many_round(gs, ng, r.data())) return e;
-    }
-    return FDTD_OK;
-}
-
-// One batched stepping of validated, finalised handles (the body of
-// fdtd_step_many; with plane DFTs every n[h] <= kPlaneRing).
-static int step_many_round(fdtd_grid* const* gs, int ng, const int64_t* n)
-{
+    bool any = false;
+    for (int h = 0; h < ng; ++h) any |= n[h] > 0;
+    if (!any) return FDTD_OK;
     fdtd_grid* lead = gs[0];
     hipStream_t st = lead->stream;
-    const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
-
-    // order boards by step count (descending): at pass s the boards still running
-    // form a prefix, and so do their tiles; narrow and wide class maps go to
-    // separate launches (the kernel is specialised on the class index width)
-    std::vector<int> order(ng);
-    for (int h = 0; h < ng; ++h) order[h] = h;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (gs[a]->wide != gs[b]->wide) return gs[a]->wide < gs[b]->wide;
-        return n[a] > n[b];
-    });
-    // board b runs np[b] passes of `per` steps, then (two-step shapes) one single
-    // step when its count is odd.  boards[ng + b] is the copy the single-step
-    // launch reads: its step and buffer offsets skip the board's own passes.
-    std::vector<BoardDev> boards(2 * (size_t)ng);
-    std::vector<int64_t> np(ng), odd(ng), adv(2 * (size_t)ng);
-    int64_t max_np = 0;
-    for (int b = 0; b < ng; ++b) {
-        const int64_t nb = n[order[b]];
-        np[b] = nb / per;
-        odd[b] = nb - np[b] * per;
-        max_np = std::max(max_np, np[b]);
-        boards[b] = gs[order[b]]->board_host;
-        boards[ng + b] = boards[b];
-        boards[ng + b].rel0 = (int32_t)(np[b] * per);
-        boards[ng + b].flip0 = (int32_t)(np[b] & 1);
-        adv[2 * b] = nb;
-        adv[2 * b + 1] = np[b] + odd[b];
-    }
-    // Each class width forms a group [b0, b1) of the order; at pass s the boards
-    // still running are a prefix [b0, active) of it.  One balanced work list per
-    // distinct prefix, plus one for the single-step tail, all in one buffer.
-    struct Span {
-        int w, steps;
-        int64_t s0, s1;   // passes s0 .. s1-1 run this list
-        int off, count;
-        bool tail;        // the single-step launch (reads boards[ng..])
-    };
-    std::vector<Span> spans;
-    std::vector<TileRef> items, whole, list;
-    for (int w = 0; w < 2; ++w) {
-        int b0 = 0;
-        while (b0 < ng && gs[order[b0]]->wide != (w == 1)) ++b0;
-        if (b0 == ng) continue;
-        int b1 = b0;
-        while (b1 < ng && gs[order[b1]]->wide == (w == 1)) ++b1;
-        int64_t s = 0;
-        for (int active = b1; active > b0 && s < max_np;) {
-            const int64_t s_end = np[active - 1];  // boards [b0, active) all run through s_end
-            if (s_end > s) {
-                whole.clear();
-                for (int b = b0; b < active; ++b) {
-                    const fdtd_grid* g = gs[order[b]];
-                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, per), whole);
-                }
-                build_work(whole, slots_per_xcd(lead, tx, ty, per, w == 1), list);
-                spans.push_back(Span{w, per, s, s_end, (int)items.size(), (int)list.size(), false});
-                items.insert(items.end(), list.begin(), list.end());
-                s = s_end;
-            }
-            --active;
-        }
-        whole.clear();
-        for (int b = b0; b < b1; ++b)
-            if (odd[b]) {
-                const fdtd_grid* g = gs[order[b]];
-                board_tiles(b, g->d.nx, g->d.ny, g->d.nz, kOddX, owned_rows(kOddY, 1), whole);
-            }
-        if (!whole.empty()) {
-            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1), list);
-            spans.push_back(Span{w, 1, 0, 1, (int)items.size(), (int)list.size(), true});
-            items.insert(items.end(), list.begin(), list.end());
-        }
-    }
-    // device scratch held by the lead handle
-    if (lead->batch_boards_cap < ng) {
-        lead->batch_boards = (BoardDev*)dev_alloc(lead, sizeof(BoardDev) * 2 * (size_t)ng);
-        lead->batch_n = (int64_t*)dev_alloc(lead, sizeof(int64_t) * 2 * (size_t)ng);
-        if (!lead->batch_boards || !lead->batch_n) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
-        lead->batch_boards_cap = ng;
-    }
-    if (lead->batch_tiles_cap < (int)items.size()) {
-        lead->batch_tiles = (TileRef*)dev_alloc(lead, sizeof(TileRef) * items.size());
-        if (!lead->batch_tiles) return fail(FDTD_ENOMEM, "batch scratch allocation failed");
-        lead->batch_tiles_cap = (int)items.size();
-    }
+    BatchPlan* P = nullptr;
+    if (int e = find_plan(gs, ng, n, &P)) return e;
     // order after the work already queued on every handle's stream
     for (int h = 1; h < ng; ++h) {
         if (gs[h]->stream == st) continue;
@@ -1410,41 +1657,15 @@ static int step_many_round(fdtd_grid* const* gs, int ng, const int64_t* n)
         HIP_OR_FAIL(hipEventRecord(gs[h]->sync_ev, gs[h]->stream));
         HIP_OR_FAIL(hipStreamWaitEvent(st, gs[h]->sync_ev, 0));
     }
-    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_boards, boards.data(), sizeof(BoardDev) * boards.size(),
-                               hipMemcpyHostToDevice, st));
-    if (!items.empty())
-        HIP_OR_FAIL(hipMemcpyAsync(lead->batch_tiles, items.data(), sizeof(TileRef) * items.size(),
-                                   hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(hipMemcpyAsync(lead->batch_n, adv.data(), sizeof(int64_t) * adv.size(),
-                               hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(hipStreamSynchronize(st));  // the host arrays above are locals
-    bool planes = false;
-    for (int h = 0; h < ng; ++h) planes |= gs[h]->plane_k >= 0;
-    for (const Span& sp : spans) {
-        if (sp.tail) {
-            HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, lead->batch_boards + ng,
-                                    lead->batch_tiles + sp.off, sp.count, 0, 0, sp.w == 1, planes, st));
-            continue;
-        }
-        for (int64_t q = sp.s0; q < sp.s1; ++q)
-            HIP_OR_FAIL(launch_pass(tx, ty, sp.steps, lead->batch_boards, lead->batch_tiles + sp.off,
-                                    sp.count, (int)(q * sp.steps), (int)(q & 1), sp.w == 1, planes,
-                                    st));
-    }
-    HIP_OR_FAIL(launch_advance(lead->batch_boards, ng, lead->batch_n, st));
-    for (int b = 0; b < ng; ++b) {
-        fdtd_grid* g = gs[order[b]];
-        g->buf = (int)((g->buf + adv[2 * b + 1]) & 1);
-    }
+    if (P->exec)
+        HIP_OR_FAIL(hipGraphLaunch(P->exec, st));
+    else if (int e = enqueue_plan(gs, ng, *P, st))
+        return e;
+    HIP_OR_FAIL(hipEventRecord(P->done, st));
     for (int h = 0; h < ng; ++h) {
         fdtd_grid* g = gs[h];
-        if (n[h] > 0)
-            if (int e = fold_plane(g, -n[h], 0, st)) return e;
-        if (g->dft_f && n[h] > 0)
-            HIP_OR_FAIL(launch_dft(g->prb_series, g->d.max_steps, g->dft_f, (int)g->freqs.size(),
-                                   (int)g->probes.size(), g->dt, g->step, g->step + n[h],
-                                   g->dft_re, g->dft_im, st));
         g->step += n[h];
+        g->buf = (int)((g->buf + P->flips[h]) & 1);
     }
     // later work on every handle's own stream orders after the batch
     if (int e = ensure_event(lead)) return e;
@@ -1832,6 +2053,9 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->plane_k = g->plane_k;
     out->plane_nf = (int32_t)g->plane_freqs.size();
     out->node_passes = g->node_pass ? 1 : 0;
+    out->batch_plans = (int32_t)g->plans.size();
+    out->batch_graphs = 0;
+    for (const BatchPlan* p : g->plans) out->batch_graphs += p->exec != nullptr;
     return FDTD_OK;
 }
 
@@ -1867,6 +2091,10 @@ int fdtd_destroy_grid(fdtd_grid* g)
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
     if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
     if (g->sync_ev) (void)hipEventDestroy(g->sync_ev);
+    for (BatchPlan* p : g->plans) free_plan(g, p);
+    for (BatchPlan* p : g->retired) free_plan(g, p);
+    g->plans.clear();
+    g->retired.clear();
     dev_free_all(g);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

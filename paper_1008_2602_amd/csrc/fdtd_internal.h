@@ -91,6 +91,12 @@ struct BoardDev {
     float* plane_ring;
     // node passes: 1 when Eq. 2's eps_rw scales the PML sigma (else eps_rw = 1)
     int32_t eps_rw;
+    // node passes: the bytes between a field's x, y and z arrays in 64 bits (the
+    // 32-bit cstride does not hold them on boards past the 4 GiB window), and
+    // the source and probe nodes as 64-bit indices
+    uint64_t cstride64;
+    const int64_t* src_node64;
+    const int64_t* prb_node64;
 };
 
 // One work item of the field kernel: tile (tx, ty) of a board, planes kb..ke-1.

@@ -412,14 +412,20 @@ __global__ void advance_one(int64_t* step, int64_t n, int64_t launches)
 // Running DFT (FP64): for probe p and frequency q add the samples s in [s0, s1):
 // A += e[s] * exp(-i 2 pi f_q (s+1) dt) * dt.  The phase is reduced to [0, 1)
 // turns in FP64 before sincospi.
+// With `step` set, the range is the last `back` steps before the device step
+// counter, [step[0] - back, step[0]) (a replayed graph's call advances it).
 __global__ void dft_accumulate(const float* __restrict__ series, int64_t max_steps,
                                const double* __restrict__ freqs, int nf, int np,
-                               double dt, int64_t s0, int64_t s1,
-                               double* __restrict__ re, double* __restrict__ im)
+                               double dt, int64_t s0, int64_t s1, const int64_t* __restrict__ step,
+                               int64_t back, double* __restrict__ re, double* __restrict__ im)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
     if (q >= nf || p >= np) return;
+    if (step) {
+        s1 = step[0];
+        s0 = s1 - back;
+    }
     const double fdt = freqs[q] * dt;
     double ar = 0.0, ai = 0.0;
     const float* e = series + (int64_t)p * max_steps;
@@ -618,7 +624,18 @@ hipError_t launch_dft(const float* series, int64_t max_steps, const double* freq
     if (np <= 0 || nf <= 0 || s1 <= s0) return hipSuccess;
     dim3 grid((nf + 63) / 64, np);
     hipLaunchKernelGGL(dft_accumulate, grid, dim3(64), 0, st, series, max_steps, freqs, nf, np,
-                       dt, s0, s1, re, im);
+                       dt, s0, s1, (const int64_t*)nullptr, (int64_t)0, re, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_back(const float* series, int64_t max_steps, const double* freqs, int nf,
+                           int np, double dt, const int64_t* step, int64_t back, double* re,
+                           double* im, hipStream_t st)
+{
+    if (np <= 0 || nf <= 0 || back <= 0) return hipSuccess;
+    dim3 grid((nf + 63) / 64, np);
+    hipLaunchKernelGGL(dft_accumulate, grid, dim3(64), 0, st, series, max_steps, freqs, nf, np,
+                       dt, (int64_t)0, (int64_t)0, step, back, re, im);
     return hipGetLastError();
 }
 

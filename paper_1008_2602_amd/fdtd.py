@@ -63,7 +63,7 @@ class fdtd_info(C.Structure):
                 ("n_sources", C.c_int32), ("n_probes", C.c_int32), ("n_freqs", C.c_int32),
                 ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("tile_steps", C.c_int32), ("plane_k", C.c_int32), ("plane_nf", C.c_int32),
-                ("node_passes", C.c_int32)]
+                ("node_passes", C.c_int32), ("batch_plans", C.c_int32), ("batch_graphs", C.c_int32)]
 
 
 class FdtdError(RuntimeError):
@@ -89,6 +89,7 @@ _sigs = {
     "fdtd_set_plane_dft": ([_P, C.c_int, _P, C.c_int], C.c_int),
     "fdtd_set_pml_eps_rw": ([_P, C.c_int], C.c_int),
     "fdtd_set_conductivity": ([_P, _P], C.c_int),
+    "fdtd_set_sheet_resistance": ([_P, C.c_double], C.c_int),
     "fdtd_get_plane_dft": ([_P, _P, _P], C.c_int),
     "fdtd_get_plane": ([_P, C.c_int, C.c_int, _P], C.c_int),
     "fdtd_step_n": ([_P, C.c_int64], C.c_int),
@@ -242,6 +243,10 @@ def fdtd_set_dft_freqs(g, f_hz: Sequence[float]):
 def fdtd_set_conductivity(g, sigma_cell: Optional[np.ndarray]):
     sig = None if sigma_cell is None else np.ascontiguousarray(sigma_cell, dtype=np.float32)
     _check(_lib.fdtd_set_conductivity(g, _ptr(sig)))
+
+
+def fdtd_set_sheet_resistance(g, ohms_per_square: float):
+    _check(_lib.fdtd_set_sheet_resistance(g, float(ohms_per_square)))
 
 
 def fdtd_set_pml_eps_rw(g, on: bool):
@@ -419,6 +424,8 @@ def grid_from_board(board, max_steps: Optional[int] = None, hip_stream=None,
             fdtd_set_pml_eps_rw(g, True)
         if getattr(b, "sigma_cell", None) is not None:
             fdtd_set_conductivity(g, b.sigma_cell)
+        if getattr(b, "sheet_R", 0.0):
+            fdtd_set_sheet_resistance(g, b.sheet_R)
         for s in b.sources:
             if getattr(s, "R", 0.0) > 0.0:
                 fdtd_add_voltage_source(g, s.i, s.j, s.k, s.waveform, s.J0, s.t0, s.sigma, s.R)

@@ -12,11 +12,23 @@ Board-solve requests arrive over time.  At every chunk boundary the server
 Fields stay resident on the device between chunks.  Latency is completion time
 minus arrival time.  The executor is pluggable: ``GpuExecutor`` drives the
 library, tests drive the same scheduler with a modelled executor on the CPU.
+
+With an executor that can enqueue a chunk without waiting for it
+(``step_async``) and ``workers`` > 0, the loop is pipelined: admitted requests
+are set up (device buffers, material classes, tables) on worker threads while
+the device runs the current chunks, and finished boards are read back and
+released on workers too; up to ``depth`` chunks are in flight, the next one
+enqueued before the previous one ends, so the device does not idle at chunk
+boundaries.  A prepared board joins the first chunk enqueued after its set-up
+is done; the budget counts a board from admission until it is released.
 """
 from __future__ import annotations
 
 import heapq
+import threading
 import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor
+from concurrent.futures import wait as wait_futures
 from dataclasses import dataclass, field
 from typing import Any, Callable, Dict, List, Optional, Sequence
 
@@ -66,26 +78,71 @@ class _Resident:
 
 
 class GpuExecutor:
-    """Runs boards through libfdtd on the current device."""
+    """Runs boards through libfdtd on the current device.  Every board gets a
+    stream of its own; a chunk runs on its first board's stream (the library's
+    batched call), bracketed by events for the device-busy figure."""
 
     def __init__(self, allocator=None, tile=None, collect=True):
+        import torch
         from . import fdtd as F
         self.F = F
+        self.torch = torch
         self.allocator = allocator
         self.tile = tile
         self.collect = collect
+        self.streams = {}
+        self._lock = threading.Lock()
+        self.chunk_events = []          # (start, end) events of every chunk
 
     def footprint(self, req: SolveRequest) -> int:
         return self.F.board_bytes(req.board, max_steps=req.n_steps)
 
     def create(self, req: SolveRequest):
+        """Set up a board (device buffers, classes, tables, work lists) on its own
+        stream; returns when the board is ready to step."""
+        st = self.torch.cuda.Stream()
         g, ids = self.F.grid_from_board(req.board, max_steps=req.n_steps,
-                                        allocator=self.allocator, tile=self.tile)
+                                        allocator=self.allocator, tile=self.tile,
+                                        hip_stream=st.cuda_stream)
+        self.F.fdtd_step_n(g, 0)               # finalise now, not inside a chunk
+        self.F.fdtd_synchronize(g)
+        with self._lock:
+            self.streams[id(g)] = st
         return g, ids
 
-    def step(self, handles: Sequence, ns: Sequence[int]) -> None:
+    def step_async(self, handles: Sequence, ns: Sequence[int]):
+        """Enqueue one chunk (no wait); returns its completion token."""
+        st = self.streams[id(handles[0])]
+        start = self.torch.cuda.Event(enable_timing=True)
+        end = self.torch.cuda.Event(enable_timing=True)
+        start.record(st)
         self.F.fdtd_step_many(list(handles), list(ns))
-        self.F.fdtd_synchronize(handles[0])
+        end.record(st)
+        self.chunk_events.append((start, end))
+        return end
+
+    def wait(self, token) -> None:
+        token.synchronize()
+
+    def step(self, handles: Sequence, ns: Sequence[int]) -> None:
+        self.wait(self.step_async(handles, ns))
+
+    def busy_fraction(self) -> Optional[float]:
+        """Share of the time from the first chunk's start to the last chunk's end
+        that some chunk ran on the device."""
+        if not self.chunk_events:
+            return None
+        for _, e in self.chunk_events:
+            e.synchronize()
+        first = self.chunk_events[0][0]
+        busy = 0.0
+        last_end = 0.0
+        for s, e in self.chunk_events:
+            t0 = max(first.elapsed_time(s), last_end)
+            t1 = first.elapsed_time(e)
+            busy += max(0.0, t1 - t0)
+            last_end = max(last_end, t1)
+        return busy / last_end if last_end > 0 else None
 
     def finish(self, handle, probe_ids, req: SolveRequest):
         F = self.F
@@ -96,6 +153,8 @@ class GpuExecutor:
             if req.board.dft_freqs is not None and probe_ids:
                 dft = np.stack([F.fdtd_get_dft(handle, p) for p in probe_ids])
         F.fdtd_destroy_grid(handle)
+        with self._lock:
+            self.streams.pop(id(handle), None)
         return probes, dft
 
     def now(self) -> float:
@@ -110,7 +169,8 @@ class GpuExecutor:
 class Server:
     def __init__(self, executor, budget_bytes: int, chunk: int = 500,
                  max_resident: Optional[int] = None, max_bypass_s: float = 5.0,
-                 log: Optional[Callable[[dict], None]] = None):
+                 log: Optional[Callable[[dict], None]] = None, workers: int = 0,
+                 depth: int = 2):
         if budget_bytes <= 0 or chunk <= 0:
             raise ValueError("budget and chunk must be positive")
         self.ex = executor
@@ -119,12 +179,16 @@ class Server:
         self.max_resident = max_resident
         self.max_bypass_s = float(max_bypass_s)
         self.log = log
+        self.workers = int(workers)
+        self.depth = max(1, int(depth))
         self.chunks = 0
         self.peak_bytes = 0
         self.peak_resident = 0
         self.rejected: List[int] = []
 
     def run(self, requests: Sequence[SolveRequest]) -> List[SolveResult]:
+        if self.workers > 0 and hasattr(self.ex, "step_async"):
+            return self._run_pipelined(requests)
         ex = self.ex
         pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         foot = {}
@@ -192,6 +256,111 @@ class Server:
             if self.log:
                 self.log(dict(t=fin_t, chunk=self.chunks, resident=len(resident),
                               waiting=len(waiting), used=used, admitted=admitted))
+        return sorted(results, key=lambda r: r.rid)
+
+
+    # ------------------------------------------------------------------ pipelined
+    def _admit(self, waiting, foot, used, n_live, now):
+        """Requests to admit now, oldest first, within the budget (younger ones may
+        pass a blocked one until it has waited max_bypass_s)."""
+        out = []
+        blocked_since = None
+        for r in waiting:
+            if self.max_resident is not None and n_live + len(out) >= self.max_resident:
+                break
+            if used + foot[r.rid] > self.budget:
+                if blocked_since is None:
+                    blocked_since = r.arrival_s
+                if now - blocked_since >= self.max_bypass_s:
+                    break
+                continue
+            out.append(r)
+            used += foot[r.rid]
+        return out
+
+    def _run_pipelined(self, requests: Sequence[SolveRequest]) -> List[SolveResult]:
+        ex = self.ex
+        pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        foot = {r.rid: ex.footprint(r) for r in pending}
+        self.rejected = [r.rid for r in pending if foot[r.rid] > self.budget]
+        rejected = set(self.rejected)
+        pending = [r for r in pending if r.rid not in rejected]
+        t0 = ex.now()
+        waiting: List[SolveRequest] = []
+        preparing = {}                 # future -> (request, admit time)
+        resident: List[_Resident] = []
+        inflight = []                  # (token, [boards that complete in that chunk])
+        finishing = {}                 # future -> _Resident
+        results: List[SolveResult] = []
+        used = 0
+        nxt = 0
+        pool = ThreadPoolExecutor(max_workers=self.workers)
+
+        def finish_job(e: _Resident, token):
+            ex.wait(token)
+            probes, dft = ex.finish(e.handle, e.probe_ids, e.req)
+            b = e.req.board
+            return SolveResult(e.req.rid, e.req.arrival_s, e.admit_s, ex.now() - t0,
+                               e.req.n_steps, b.nx * b.ny * b.nz, probes, dft)
+
+        try:
+            while nxt < len(pending) or waiting or preparing or resident or inflight or finishing:
+                now = ex.now() - t0
+                while nxt < len(pending) and pending[nxt].arrival_s <= now:
+                    waiting.append(pending[nxt])
+                    nxt += 1
+                # boards whose set-up is done join the next chunk
+                for f in [f for f in preparing if f.done()]:
+                    r, adm = preparing.pop(f)
+                    h, ids = f.result()
+                    resident.append(_Resident(r, h, ids, 0, foot[r.rid], adm))
+                # released boards give their budget back
+                for f in [f for f in finishing if f.done()]:
+                    e = finishing.pop(f)
+                    results.append(f.result())
+                    used -= e.bytes
+                admitted = self._admit(waiting, foot, used,
+                                       len(resident) + len(preparing), now)
+                for r in admitted:
+                    waiting.remove(r)
+                    used += foot[r.rid]
+                    preparing[pool.submit(ex.create, r)] = (r, now)
+                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_resident = max(self.peak_resident, len(resident))
+                if resident and len(inflight) < self.depth:
+                    ns = [min(self.chunk, e.req.n_steps - e.done) for e in resident]
+                    token = ex.step_async([e.handle for e in resident], ns)
+                    self.chunks += 1
+                    done, still = [], []
+                    for e, n in zip(resident, ns):
+                        e.done += n
+                        (done if e.done >= e.req.n_steps else still).append(e)
+                    resident = still
+                    inflight.append((token, done))
+                    for e in done:
+                        finishing[pool.submit(finish_job, e, token)] = e
+                    if self.log:
+                        self.log(dict(t=ex.now() - t0, chunk=self.chunks, resident=len(resident),
+                                      waiting=len(waiting), used=used,
+                                      admitted=[r.rid for r in admitted]))
+                    continue
+                if inflight:
+                    # the oldest chunk in flight ends before the next is enqueued
+                    token, _ = inflight.pop(0)
+                    ex.wait(token)
+                    continue
+                if preparing or finishing:
+                    wait_futures(list(preparing) + list(finishing), return_when=FIRST_COMPLETED,
+                                 timeout=(None if nxt >= len(pending) else
+                                          max(0.0, pending[nxt].arrival_s - (ex.now() - t0))))
+                    continue
+                if nxt < len(pending):
+                    ex.wait_until(t0 + pending[nxt].arrival_s)
+                    continue
+                if waiting:
+                    raise RuntimeError("a waiting request can never be admitted")
+        finally:
+            pool.shutdown(wait=True)
         return sorted(results, key=lambda r: r.rid)
 
 

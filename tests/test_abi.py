@@ -51,19 +51,18 @@ def test_null_handle_is_einval():
     F.fdtd_destroy_grid(None)  # NULL is accepted
 
 
-def test_node_count_limit():
-    """The x, y and z arrays of a field (padded rows of 32 nodes, 64 guard words,
-    256-byte rounding) must fit one 4 GiB window: 1024 x 1024 x 342 nodes do not,
-    1024 x 1024 x 341 do (that call then fails only for want of a device here)."""
+def test_plane_size_limit():
+    """Boards past the tiled kernels' 4 GiB offset window are accepted (they step
+    on the node passes from per-component bases); what is refused is a node
+    plane so large that three of them (a chunk's base plane and its neighbours)
+    leave 32-bit offsets.  2048 x 2048 x 600 cells pass the size checks (the call
+    then fails only for want of a device here); 40000 x 40000 do not."""
     with pytest.raises(F.FdtdError) as ei:
-        F.fdtd_create_grid(2048, 2048, 600, 1e-3, 1e-3, 1e-3, max_steps=1)
-    assert "4 GiB window" in str(ei.value)
-    with pytest.raises(F.FdtdError) as ei:
-        F.fdtd_create_grid(1023, 1023, 341, 1e-3, 1e-3, 1e-3, max_steps=1)
-    assert "4 GiB window" in str(ei.value)
+        F.fdtd_create_grid(40000, 40000, 4, 1e-3, 1e-3, 1e-3, max_steps=1)
+    assert "three node planes" in str(ei.value)
     try:
-        g = F.fdtd_create_grid(1023, 1023, 340, 1e-3, 1e-3, 1e-3, max_steps=1)
+        g = F.fdtd_create_grid(2048, 2048, 600, 1e-3, 1e-3, 1e-3, max_steps=1)
     except F.FdtdError as e:
-        assert "4 GiB window" not in str(e)
+        assert "too large" not in str(e)
     else:
         F.fdtd_destroy_grid(g)

@@ -13,7 +13,7 @@ from test_gpu_parity import random_state
 
 @pytest.fixture(scope="module")
 def case(oracle_mod):
-    nx, ny, nz = 70, 30, 16
+    nx, ny, nz = 140, 60, 24
     eps, mask = boardgen.air(nx, ny, nz)
     eps[4:12, :, :] = 4.4
     boardgen.pec_sheet(mask, 4, 10, 50, 5, 22)
@@ -39,13 +39,13 @@ def _fails(b, ref, got, check):
 
 def _plant(fp32, ref, name, where):
     """A copy of the FP32 state whose array ``name`` carries, on the nodes
-    ``where``, an error of 0.9e-5 of the array's largest value with a random sign:
+    ``where``, an error of 1.8e-5 of the array's largest value with a random sign:
     below the element-wise bound, and too small to move the whole-array norm."""
     got = dict(fp32)
     got[name] = fp32[name].copy()
     rng = np.random.default_rng(0)
     sel = got[name][where]
-    sel += 0.9e-5 * np.abs(ref[name]).max() * rng.choice([-1.0, 1.0], size=sel.shape)
+    sel += 1.8e-5 * np.abs(ref[name]).max() * rng.choice([-1.0, 1.0], size=sel.shape)
     got[name][where] = sel
     return got
 
@@ -64,12 +64,12 @@ def test_pml_corner_error_fails(case):
 
 def test_seam_column_error_fails(case):
     b, ref, fp32 = case
-    _fails(b, ref, _plant(fp32, ref, "hy", np.s_[:, :, 63]), "region")    # after a 64-wide tile
+    _fails(b, ref, _plant(fp32, ref, "hy", np.s_[:, 10:40, 63]), "region")    # after a 64-wide tile
 
 
 def test_single_plane_error_fails(case):
     b, ref, fp32 = case
-    _fails(b, ref, _plant(fp32, ref, "ez", np.s_[7, :12, :]), "region")   # part of one plane
+    _fails(b, ref, _plant(fp32, ref, "ez", np.s_[7, :6, :70]), "region")   # part of one plane
 
 
 def test_rim_error_fails(case):
@@ -86,7 +86,7 @@ def test_single_node_error_fails(case):
     got = dict(fp32)
     got["hx"] = fp32["hx"].copy()
     k, j, i = np.unravel_index(np.argmax(np.abs(ref["hx"])), ref["hx"].shape)
-    got["hx"][k, j, i] += 2e-5 * np.abs(ref["hx"]).max()
+    got["hx"][k, j, i] += 3e-5 * np.abs(ref["hx"]).max()
     _fails(b, ref, got, "element-wise")
 
 

@@ -105,7 +105,7 @@ def test_eps_rw_random_state_few_steps(F, oracle_mod, shape, npml):
         fields = gpu_fields(F, g, b)
     finally:
         F.fdtd_destroy_grid(g)
-    compare_fields(ref.state, fields, b, 2e-5)
+    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
 
 @pytest.mark.parametrize("shape,lossy", [((256, 128, 48), True), ((512, 256, 48), False)])
@@ -114,19 +114,25 @@ def test_node_pass_z_chunks_random_state(F, oracle_mod, shape, lossy):
     carry the previous plane in registers: 3 planes per chunk on the first board
     (4 x 32 column blocks), 12 on the second (8 x 64), as on the large benchmark
     board; the chunk seams (k0 > 0) lie at every third or twelfth plane.  Random
-    eps_r in every cell (PML included), a PEC sheet, eps_rw on (and on the first
-    board a lossy interior): three steps from an arbitrary state against the
-    oracle, every array, element and region (each plane on its own)."""
+    eps_r in blocks everywhere (PML included), a PEC sheet, eps_rw on (and on the
+    first board a lossy interior, in other blocks): three steps from an arbitrary
+    state against the oracle, every array, element and region (each plane on
+    its own)."""
     nx, ny, nz = shape
     eps, mask = boardgen.air(nx, ny, nz)
     rng = np.random.default_rng(nx + nz)
-    eps[:] = rng.choice([1.0, 2.2, 4.4], size=eps.shape).astype(np.float32)
+    # random eps_r in blocks of 32 x 16 x 4 cells (random per cell would exceed
+    # the 65535 material classes on boards this size once the loss varies too)
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    blocks = rng.choice([1.0, 2.2, 4.4], size=(nz // 4 + 1, ny // 16 + 1, nx // 32 + 1))
+    eps[:] = blocks[kk // 4, jj // 16, ii // 32].astype(np.float32)
     boardgen.pec_sheet(mask, nz // 2, 0, nx // 2, 1, ny - 1)
     npml = (5, 4, 6, 3, 4, 5)
     b = boardgen.Board(f"epschunk{nx}", nx, ny, nz, 0.5e-3, 0.6e-3, 0.2e-3, eps, mask,
                        npml=npml, steps=3, pml_eps_rw=True)
     if lossy:
-        sig = rng.uniform(0.0, 2.0, size=eps.shape).astype(np.float32)
+        sblocks = rng.choice([0.0, 0.4, 2.0], size=(nz // 4 + 1, ny // 16 + 1, nx // 32 + 1))
+        sig = sblocks[(kk + 2) // 4, (jj + 8) // 16, (ii + 16) // 32].astype(np.float32)
         sig[:npml[4]] = 0.0
         sig[nz - npml[5]:] = 0.0
         sig[:, :npml[2]] = 0.0
@@ -148,7 +154,7 @@ def test_node_pass_z_chunks_random_state(F, oracle_mod, shape, lossy):
         fields = gpu_fields(F, g, b)
     finally:
         F.fdtd_destroy_grid(g)
-    rep = compare_fields(ref.state, fields, b, 2e-5)
+    rep = compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
     for n, (whole, elem, reg, where) in rep.items():
         print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
 

@@ -1,7 +1,8 @@
-"""Lossy dielectrics on the HIP path (the node passes), against the FP64 oracle:
-probes within 1e-4 (relative L2), all 12 arrays within 2e-5 after a few steps
-from arbitrary states, a resistive source on a lossy edge (the two conductances
-add), and the argument checks."""
+"""Lossy dielectrics and resistive sheets (conductor loss) on the HIP path (the
+node passes), against the FP64 oracle: probes within 1e-4 (relative L2), all 12
+arrays within 2e-5 after a few steps from arbitrary states, a resistive source
+on a lossy edge (the two conductances add), sheet edges on lossy cells, and the
+argument checks."""
 import dataclasses
 
 import numpy as np
@@ -80,7 +81,7 @@ def test_lossy_random_state_few_steps(F, oracle_mod, eps_rw):
         fields = gpu_fields(F, g, b)
     finally:
         F.fdtd_destroy_grid(g)
-    compare_fields(ref.state, fields, b, 2e-5)
+    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
 
 def test_lossy_table1_board_against_oracle(F, oracle_mod):
@@ -121,6 +122,129 @@ def test_conductivity_argument_errors(F):
         assert F.fdtd_get_info(g).node_passes == 0
         with pytest.raises(F.FdtdError) as ei:
             F.fdtd_set_conductivity(g, sig)
+        assert ei.value.code == F.FDTD_ESTATE
+    finally:
+        F.fdtd_destroy_grid(g)
+
+
+# ---------------------------------------------------------------------------
+# conductor loss: the PEC sheets as resistive sheets of surface resistance R_s
+# ---------------------------------------------------------------------------
+
+def sheet_board(seed, steps):
+    """lossy_board with its PEC sheet kept inside the PML's inner region and
+    given a surface resistance (the sheet edges then add to the cells' loss)."""
+    b = lossy_board(seed, steps)
+    p = b.npml
+    mask = b.pec_edge_mask
+    mask[:] &= 4
+    k = (p[4] + b.nz - p[5]) // 2
+    boardgen.pec_sheet(mask, k, p[0] + 2, b.nx - p[1] - 3, p[2] + 2, b.ny - p[3] - 3)
+    b.sheet_R = 0.35
+    return b
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sheet_from_zero_against_oracle(F, oracle_mod, seed):
+    b = sheet_board(seed, steps=73)
+    b.sources.append(boardgen.Source(b.nx // 2, b.ny // 2, b.nz // 2 - 2, boardgen.GAUSS, 2e6,
+                                     10e-12, 3e-12))
+    b.probes.append((b.nx // 2 + 2, b.ny // 2, b.nz // 2 + 1))
+    announce(f"resistive-sheet board seed={seed}")
+    ref = oracle_mod.run(b)
+    g, ids = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        assert F.fdtd_get_info(g).node_passes == 1
+        probes = np.stack([F.fdtd_get_probe(g, p, b.steps) for p in ids])
+        fields = gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+    for p in range(len(b.probes)):
+        if np.abs(ref.probes[p]).max() > 0:
+            assert rel_l2(probes[p], ref.probes[p]) <= 1e-4, p
+    compare_fields(ref.state, fields, b, 2e-5)
+    # the sheet matters: perfect conductors give another field
+    ref0 = oracle_mod.run(dataclasses.replace(b, sheet_R=0.0))
+    assert rel_l2(ref0.state["ex"], ref.state["ex"]) > 1e-3
+
+
+@pytest.mark.parametrize("eps_rw", [False, True])
+def test_sheet_random_state_few_steps(F, oracle_mod, eps_rw):
+    b = sheet_board(4, steps=5)
+    b.pml_eps_rw = eps_rw
+    b.sheet_R = 2.0
+    st = random_state(oracle_mod, b, seed=19)
+    # the sheet edges are state too once they are resistive
+    rng = np.random.default_rng(3)
+    for n, bit in (("ex", 1), ("ey", 2)):
+        on = (b.pec_edge_mask & bit) != 0
+        st[n][on] = rng.standard_normal(int(on.sum()))
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"resistive sheet random state eps_rw={eps_rw}")
+    ref = oracle_mod.run(b, state=st)
+    g, _ = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        for c, n in enumerate(FIELDS):
+            F.fdtd_set_field(g, c, init[n].astype(np.float32))
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        fields = gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
+
+
+def test_conductor_loss_table1_board_against_oracle(F, oracle_mod):
+    """The Table 1 board with copper planes (surface resistance at 5 GHz, 18.4
+    milliohms per square) and a lossless dielectric, 10000 steps: the probe
+    against the oracle, and the planes' loss shortens the ringing against the
+    perfect conductors."""
+    b = boardgen.conductor_loss(boardgen.table1_board(steps=10000, source="resistive"))
+    announce(f"conductor-loss table1 (R_s {b.sheet_R:.4g} ohm): oracle")
+    ref = oracle_mod.run(b, threads=16).probes[0]
+    g, ids = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        assert F.fdtd_get_info(g).node_passes == 1
+        e = F.fdtd_get_probe(g, ids[0], b.steps).astype(np.float64)
+    finally:
+        F.fdtd_destroy_grid(g)
+    assert rel_l2(e, ref) <= 1e-4
+    pec = oracle_mod.run(dataclasses.replace(b, sheet_R=0.0), threads=16).probes[0]
+    late = slice(6000, None)
+    assert np.sqrt(np.mean(e[late] ** 2)) < 0.95 * np.sqrt(np.mean(pec[late] ** 2))
+
+
+def test_sheet_argument_errors(F):
+    b = boardgen.random_tiny(6, nx=16, ny=14, nz=12, npml=2, steps=3)
+    g, _ = F.grid_from_board(b, max_steps=3)
+    try:
+        for v in (-1.0, np.nan, np.inf):
+            with pytest.raises(F.FdtdError) as ei:
+                F.fdtd_set_sheet_resistance(g, v)
+            assert ei.value.code == F.FDTD_EINVAL
+    finally:
+        F.fdtd_destroy_grid(g)
+    # a sheet running into a PML slab is refused at the first step
+    b2 = boardgen.random_tiny(6, nx=16, ny=14, nz=12, npml=2, steps=3)
+    b2.pec_edge_mask[:] &= 4
+    boardgen.pec_sheet(b2.pec_edge_mask, 6, 0, 16, 0, 14)
+    b2.sheet_R = 1.0
+    g, _ = F.grid_from_board(b2, max_steps=3)
+    try:
+        with pytest.raises(F.FdtdError) as ei:
+            F.fdtd_step_n(g, 1)
+        assert ei.value.code == F.FDTD_EINVAL and "PML" in str(ei.value)
+    finally:
+        F.fdtd_destroy_grid(g)
+    g, _ = F.grid_from_board(b, max_steps=3)
+    try:
+        F.fdtd_step_n(g, 1)
+        with pytest.raises(F.FdtdError) as ei:
+            F.fdtd_set_sheet_resistance(g, 1.0)
         assert ei.value.code == F.FDTD_ESTATE
     finally:
         F.fdtd_destroy_grid(g)

@@ -163,3 +163,96 @@ def test_tuner_picks_and_caches(tmp_path):
     assert best4 == (64, 8) and len(calls) == n + 2 and set(tim4) == {(64, 8), (32, 8)}
     assert tune.cached("k", [(64, 8)], path) == (64, 8)
     assert tune.cached("k", [(32, 8)], path) is None
+
+
+class AsyncModelExecutor(ModelExecutor):
+    """Modelled device for the pipelined loop, in real time: set-up takes a few
+    milliseconds on the calling (worker) thread; a chunk runs on a device thread
+    after the chunks enqueued before it (sum(cells * steps) / rate seconds) and
+    step_async returns at once with an event that is set when it ends."""
+
+    def __init__(self, rate=5e10, setup_s=0.004):
+        super().__init__(rate)
+        import queue
+        import threading
+        self.setup_s = setup_s
+        self.q = queue.Queue()
+        self.lock = threading.Lock()
+        self.t0 = __import__("time").perf_counter()
+        self.dev = threading.Thread(target=self._device, daemon=True)
+        self.dev.start()
+
+    def _device(self):
+        import time
+        while True:
+            item = self.q.get()
+            if item is None:
+                return
+            work, ev = item
+            time.sleep(work / self.rate)
+            ev.set()
+
+    def create(self, req):
+        import time
+        time.sleep(self.setup_s)
+        with self.lock:
+            self.live[req.rid] = 0
+            self.max_live = max(self.max_live, len(self.live))
+        return req.rid, [0]
+
+    def step_async(self, handles, ns):
+        import threading
+        work = 0
+        with self.lock:
+            self.batches.append(list(handles))
+            for h, n in zip(handles, ns):
+                self.live[h] += n
+                b = self.reqs[h].board
+                work += b.nx * b.ny * b.nz * n
+        ev = threading.Event()
+        self.q.put((work, ev))
+        return ev
+
+    def wait(self, token):
+        token.wait()
+
+    def finish(self, h, ids, req):
+        with self.lock:
+            steps = self.live.pop(h)
+        assert steps == req.n_steps
+        return np.full((1, 3), float(h)), None
+
+    def now(self):
+        return __import__("time").perf_counter() - self.t0
+
+    def wait_until(self, t):
+        import time
+        d = t - self.now()
+        if d > 0:
+            time.sleep(d)
+
+    def close(self):
+        self.q.put(None)
+
+
+def test_pipelined_loop_completes_within_budget_and_batches_arrivals():
+    reqs = _requests(40, seed=7, rate=200.0)
+    ex = AsyncModelExecutor()
+    ex.reqs = {r.rid: r for r in reqs}
+    log = []
+    budget = 4 * 300 * 300 * 30 * 100
+    srv = Server(ex, budget, chunk=100, log=log.append, workers=2, depth=2)
+    try:
+        res = srv.run(reqs)
+    finally:
+        ex.close()
+    assert [r.rid for r in res] == list(range(40))
+    for r in res:
+        assert r.probes[0, 0] == r.rid                  # its own result, all its steps
+        assert r.finish_s >= r.admit_s >= r.arrival_s - 1e-9
+    assert srv.peak_bytes <= budget and all(d["used"] <= budget for d in log)
+    assert not ex.live                                   # every board released
+    assert max(len(b) for b in ex.batches) > 1
+    # boards admitted while others were on the device joined later chunks
+    joined = [d for d in log[1:] if d["resident"] > 0 and d["admitted"]]
+    assert joined
