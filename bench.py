@@ -21,8 +21,10 @@ Beside it, the same line carries
     is reported beside the latencies;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
-  * "node_passes": Eq. 2's eps_rw passes on the large board run into the PML,
-    the paper's Fig. 3 board and a lossy Table 1 run;
+  * "node_passes": boards in the node passes' arithmetic: the large board run
+    into the PML with Eq. 2's eps_rw (material two-step kernel and node passes
+    alone), the large board lossy with copper planes, the paper's Fig. 3 board
+    and a lossy Table 1 run;
   * "zconv": the z-convergence study (1..15 cells across the dielectric) as
     one batched call;
   * "shard": the large board cut into 8 y-slabs of 1048x99x88 cells (one
@@ -105,16 +107,20 @@ def copy_calibration(nbytes=1 << 30, reps=5):
 
 def host_cpu():
     """CPU model and logical core count of this host (the oracle's machine)."""
-    model = ""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                if ":" in line:
+                    k, v = (x.strip() for x in line.split(":", 1))
+                    if k in ("model name", "cpu family", "model") and k not in info:
+                        info[k] = v
     except OSError:
         pass
-    return {"cpu_model": model or "unknown", "logical_cpus": os.cpu_count()}
+    model = info.get("model name", "unknown")
+    if "cpu family" in info:
+        model += f" (family {info['cpu family']}, model {info.get('model', '?')})"
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def _oracle_rate(board, threads, budget_s, max_steps=400):
@@ -234,22 +240,31 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
 
 
 def run_eps(F, torch, K=200, W=10, large_only=False):
-    """The node passes (Eq. 2's eps_rw, lossy dielectrics).  (1) The large board
-    with its eps_r 4.2 slab run through the x/y PML to the outer wall
-    (1048x792x88), eps_rw on, against the fused kernels on the same board with
-    eps_rw = 1; (2) the paper's Fig. 3 board (100x60x0.8 mm running into the
-    UPML), 1000 steps of 1 ps; (3) the Table 1 run with a lossy dielectric.
-    large_only: (1) alone."""
+    """Boards in the node passes' arithmetic (Eq. 2's eps_rw, lossy dielectrics,
+    resistive sheets).  (1) The large board with its eps_r 4.2 slab run through
+    the x/y PML to the outer wall (1048x792x88), eps_rw on: pairs of steps on the
+    material two-step kernel (the default), and every step on the node passes,
+    against the fused kernels on the same board with eps_rw = 1; (2) the large
+    board with a lossy dielectric (loss tangent 0.02 at 5 GHz) and copper planes
+    (resistive sheets, 18.4 milliohm per square); (3) the paper's Fig. 3 board
+    (100x60x0.8 mm running into the UPML), 1000 steps of 1 ps; (4) the Table 1 run
+    with a lossy dielectric.  large_only: (1) and (2) alone."""
     import boardgen
     from paper_1008_2602_amd import tune
     b = boardgen.large_board(steps=W + K)
     kg, kt = b.meta["layout"]["kg"], b.meta["layout"]["kt"]
     b.eps_r_cell[kg:kt, :, :] = 4.2
     b.sources, b.probes, b.dft_freqs = b.sources, b.probes[:4], None
+    lossy = boardgen.conductor_loss(boardgen.lossy_dielectric(boardgen.large_board(steps=W + K), 0.02))
+    lossy.probes, lossy.dft_freqs = lossy.probes[:4], None
     out = {}
-    for rw in (True, False):
-        bb = dataclasses.replace(b, pml_eps_rw=rw)
-        tile = tune.tune_board(bb) if not rw else None
+    cases = (("eps_rw", dataclasses.replace(b, pml_eps_rw=True), None, 1),
+             ("eps_rw_node_passes", dataclasses.replace(b, pml_eps_rw=True), (64, 8, 1), 0),
+             ("fused_eps_rw_1", b, "tune", -1),
+             ("lossy_copper", lossy, None, 1))
+    for name, bb, tile, mat in cases:
+        if tile == "tune":
+            tile = tune.tune_board(bb)
         g, _ = F.grid_from_board(bb, max_steps=W + K, tile=tile)
         F.fdtd_step_n(g, W)
         F.fdtd_synchronize(g)
@@ -259,11 +274,13 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
         wall = time.perf_counter() - t0
         info = F.fdtd_get_info(g)
         F.fdtd_destroy_grid(g)
-        assert info.node_passes == (1 if rw else 0)
-        out["eps_rw" if rw else "fused_eps_rw_1"] = {
+        assert info.node_passes == (1 if mat >= 0 else 0) and info.material_two_step == max(mat, 0)
+        out[name] = {
+            "kernel": ("material two-step (odd steps on the node passes)" if mat == 1 else
+                       "node passes" if mat == 0 else f"fused {info.tile_x}x{info.tile_y}x{info.tile_steps}"),
             "ms_per_step": round(wall / K * 1e3, 4),
-            "gcell_updates_per_s": round(b.cells * K / wall / 1e9, 3),
-            # the survey's algorithmic bytes (two passes per step, as these are)
+            "gcell_updates_per_s": round(bb.cells * K / wall / 1e9, 3),
+            # the survey's algorithmic bytes of a step of this board
             "hbm_frac_algorithmic": round(sec8d_step_bytes(info) * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         }
     if large_only:
@@ -292,8 +309,10 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
     F.fdtd_destroy_grid(g)
     out["lossy_table1"] = {"cells": t1.cells, "steps": t1.steps, "wall_s": round(wall, 4),
                            "gcell_updates_per_s": round(t1.cells * t1.steps / wall / 1e9, 3)}
-    out["workload"] = ("node passes: large board 1048x792x88 with its eps_r 4.2 slab through the "
-                       "x/y PML (eps_rw passes vs the fused kernels at eps_rw = 1); Fig. 3 board "
+    out["workload"] = ("material boards: large board 1048x792x88 with its eps_r 4.2 slab through the "
+                       "x/y PML (eps_rw on: the material two-step kernel and the node passes, vs "
+                       "the fused kernels at eps_rw = 1); the large board lossy (tan d 0.02) with "
+                       "copper planes; Fig. 3 board "
                        f"{f3.nx}x{f3.ny}x{f3.nz} running into the UPML, 1000 steps; the Table 1 "
                        "run with a loss tangent of 0.02, 30000 steps")
     return out
@@ -554,15 +573,19 @@ def sampled_cpu(board, budget_s=15.0):
                       f"(extrapolated)"}
 
 
-def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
+def run_serve(F, torch, capacity_gcells, n_requests, steps):
     import numpy as np
     import boardgen
     from paper_1008_2602_amd.serve import GpuExecutor, Server, summarize
+    # the request stream at unit rate (arrival times scale with 1/rate; the boards
+    # do not depend on it), then the rate that offers 0.7x the measured batched
+    # capacity for this stream's own mean board (the large boards included)
+    reqs = boardgen.served_requests(1.0, n_requests=n_requests, steps=steps)
+    mean_cells = float(np.mean([r.board.cells for r in reqs]))
     capacity = capacity_gcells * 1e9 / (mean_cells * steps)           # boards per second
     rate = 0.7 * capacity
-    reqs = boardgen.served_requests(rate, n_requests=n_requests, steps=steps)
     from paper_1008_2602_amd.serve import SolveRequest
-    requests = [SolveRequest(r.rid, r.arrival_s, r.board) for r in reqs]
+    requests = [SolveRequest(r.rid, r.arrival_s / rate, r.board) for r in reqs]
     free, _total = torch.cuda.mem_get_info()
     budget = int(0.85 * free)
 
@@ -575,8 +598,11 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
             assert all(np.all(np.isfinite(x)) for x in spectra)
             return super().finish(handle, probe_ids, req)
 
-    ex = FftExecutor(allocator=F.TorchAllocator())
-    done = [0]
+    # the batched shape tuned on the first 64 requests' boards (the mix the
+    # chunks will hold), then used by every served handle
+    from paper_1008_2602_amd import tune
+    tile = tune.tune_batch([r.board for r in requests[:64]])
+    ex = FftExecutor(allocator=F.TorchAllocator(), tile=tile)
 
     def progress(d):
         # progress on stderr (stdout carries only the JSON line)
@@ -590,9 +616,11 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
     wall = time.perf_counter() - t0
     s = summarize(res, wall_s=wall)
     busy = ex.busy_fraction()
+    ex.close()
     out = {
-        "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x measured "
-                    f"capacity) of board variants, 5% 800x800x64, {steps} steps each, "
+        "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x the measured "
+                    f"batched capacity for the stream's mean board of {mean_cells / 1e6:.2f} M "
+                    f"cells) of board variants, 5% 800x800x64, {steps} steps each, "
                     f"500-step chunks (up to two in flight, set-up and read-back on two "
                     f"worker threads), probe FFT per solve",
         "p50_latency_s": round(s["p50_latency_s"], 4),
@@ -605,6 +633,7 @@ def run_serve(F, torch, capacity_gcells, mean_cells, n_requests, steps):
         "completed": s["completed"],
         "gpu_busy_frac": round(busy, 4) if busy is not None else None,
         "chunks": srv.chunks,
+        "tile": "x".join(str(v) for v in tile),
         "peak_resident": srv.peak_resident,
         "budget_gb": round(budget / 1e9, 1),
     }
@@ -631,6 +660,8 @@ def served_oracle_check(results, requests):
 
 
 def main():
+    import faulthandler
+    faulthandler.enable()            # a native crash prints every thread's Python stack
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
@@ -665,6 +696,13 @@ def main():
     K, W = int(args.steps), int(args.warmup)
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     out = {}
+    clock = [time.perf_counter()]
+
+    def section(name):
+        # progress and the time of each part on stderr (stdout carries only the JSON line)
+        now = time.perf_counter()
+        print(f"[bench] {name}: {now - clock[0]:.1f} s", file=sys.stderr, flush=True)
+        clock[0] = now
     if args.only in (None, "single"):
         board, tile, info, wall, kern_ms, launches = run_single(F, torch, K, W, tile)
         cells = board.cells
@@ -726,27 +764,35 @@ def main():
                 "frac_on_fused_bytes": round(fused_launch_bytes / per_launch_s / 1e9 / HBM_PEAK_GBS, 4),
             },
         })
+        section("single")
     if args.only in (None, "batch", "serve"):
-        batch, mean_cells = run_batch(F, torch, args.batch_steps, 5)
+        batch, _ = run_batch(F, torch, args.batch_steps, 5)
         if args.only != "serve":
             out["batched"] = batch
+        section("batched")
         if args.only in (None, "serve"):
-            out["served"], served_res, served_req = run_serve(F, torch, batch["value"], mean_cells,
+            out["served"], served_res, served_req = run_serve(F, torch, batch["value"],
                                                               args.serve_requests, args.serve_steps)
+            section("served")
             if not args.no_cpu_baseline:
                 out["served"]["oracle_check"] = served_oracle_check(served_res, served_req)
+                section("served oracle check")
     if args.only in (None, "plane"):
         plain = out.get("ms_per_step")
         if plain is None:
             _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
+        section("plane_dft")
     if args.only in (None, "eps", "eps_large"):
         out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large")
+        section("node_passes")
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
+        section("zconv")
     if args.only in (None, "shard"):
         out["shard"] = run_shard(F, torch)
+        section("shard")
     if args.only in (None, "realistic"):
         out["realistic"], real_board = run_realistic(F, torch)
         if not args.no_cpu_baseline:
@@ -754,13 +800,16 @@ def main():
         out["small"], small_board = run_realistic(F, torch, "small")
         if not args.no_cpu_baseline:
             out["small"]["cpu_baseline"] = table1_cpu(small_board)
+        section("realistic and small")
     if args.only in (None, "table1"):
         out["table1"], t1_board = run_table1(F, torch)
         if not args.no_cpu_baseline:
             out["table1"]["cpu_baseline"] = table1_cpu(t1_board)
+        section("table1")
     if args.only in (None, "single") and not args.no_cpu_baseline:
         import boardgen
         out["cpu_baseline"] = cpu_baseline(boardgen.large_board())
+        section("cpu_baseline")
     print(json.dumps(out), flush=True)
 
 

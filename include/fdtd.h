@@ -91,8 +91,9 @@ typedef struct {
     int32_t tile_steps;          /* leapfrog steps per pass of that shape (1 or 2) */
     int32_t plane_k;             /* plane of the plane DFT, -1 if none */
     int32_t plane_nf;            /* its number of frequencies */
-    int32_t node_passes;         /* 1: steps run the node passes (fdtd_set_pml_eps_rw, fdtd_set_conductivity,
-                                    fdtd_set_sheet_resistance) */
+    int32_t node_passes;         /* 1: steps run the node passes' arithmetic (fdtd_set_pml_eps_rw,
+                                    fdtd_set_conductivity, fdtd_set_sheet_resistance) */
+    int32_t material_two_step;   /* 1: of which pairs of steps run on the material two-step kernel */
     int32_t batch_plans;         /* plans of fdtd_step_many calls this handle led, kept for reuse */
     int32_t batch_graphs;        /* of which captured as a graph (one graph launch per call) */
 } fdtd_info;
@@ -334,6 +335,12 @@ int fdtd_get_timing(fdtd_grid* g, double* ms, int64_t* launches);
 
 /* Block until all work enqueued on the handle's stream has finished. */
 int fdtd_synchronize(fdtd_grid* g);
+
+/* The hipStream_t the handle runs on (the caller's from fdtd_grid_desc.hip_stream,
+ * else the one the handle created), written to *out: for callers that order
+ * their own work or events with the handle's (a batched call runs on its first
+ * handle's stream).  The handle keeps ownership. */
+int fdtd_get_stream(fdtd_grid* g, void** out);
 
 /* Release everything the handle holds.  NULL is accepted. */
 int fdtd_destroy_grid(fdtd_grid* g);

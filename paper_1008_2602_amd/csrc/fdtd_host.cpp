@@ -29,6 +29,10 @@ void shape2_at(int s, int* tx, int* ty);
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
                               int rel, int flip, bool wide, bool plane, hipStream_t st);
 int field_step2_occupancy(int tile_y, bool wide);
+hipError_t launch_field_step2_material(const BoardDev* boards, const TileRef* tiles, int ntiles,
+                                       int rel, int flip, bool wide, bool plane, hipStream_t st);
+int field_step2_material_occupancy(bool wide);
+int material_tile_y();
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
 hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int64_t plane_bytes,
@@ -175,7 +179,8 @@ struct fdtd_grid {
     int plane_k = -1;               // plane-DFT node plane, -1: none
     bool pml_eps_rw = false;        // Eq. 2's eps_rw requested
     double sheet_R = 0.0;           // > 0: PEC Ex/Ey edges are resistive sheets (ohm per square)
-    bool node_pass = false;         // steps run the node passes (eps_rw in a dielectric PML, or loss)
+    bool node_pass = false;         // steps run the node passes' arithmetic (eps_rw in a dielectric PML, or loss)
+    bool mat = false;               // of which pairs of steps on the material two-step kernel
     std::vector<double> plane_freqs;
     int n_classes = 0;
     bool wide = false;
@@ -250,16 +255,43 @@ hipError_t copy_sync(fdtd_grid* g, void* dst, const void* src, size_t bytes, hip
 }
 
 // Copy one field array between the packed host layout ((nx+1) nodes per row)
-// and the padded device layout (pitch nodes per row).
-hipError_t copy_field_sync(fdtd_grid* g, void* dst, const void* src, hipMemcpyKind kind)
+// and the padded device layout (pitch nodes per row): one contiguous copy of
+// the padded array through a host staging buffer (the padding columns hold
+// zeros), repacked row by row on the host, with every value multiplied by
+// `scale` on the way.
+hipError_t copy_field_sync(fdtd_grid* g, void* dst, const void* src, hipMemcpyKind kind,
+                           float scale = 1.0f)
 {
-    const size_t row = (size_t)(g->d.nx + 1) * 4, prow = (size_t)g->pitch * 4;
+    const size_t nrow = (size_t)g->d.nx + 1, pitch = (size_t)g->pitch;
     const size_t rows = (size_t)(g->d.ny + 1) * (g->d.nz + 1);
-    const bool to_dev = kind == hipMemcpyHostToDevice;
-    hipError_t e = hipMemcpy2DAsync(dst, to_dev ? prow : row, src, to_dev ? row : prow, row, rows,
-                                    kind, g->stream);
+    std::vector<float> stage(rows * pitch, 0.0f);
+    if (kind == hipMemcpyHostToDevice) {
+        const float* in = (const float*)src;
+        for (size_t r = 0; r < rows; ++r) {
+            float* o = stage.data() + r * pitch;
+            const float* x = in + r * nrow;
+            if (scale == 1.0f)
+                memcpy(o, x, nrow * 4);
+            else
+                for (size_t i = 0; i < nrow; ++i) o[i] = x[i] * scale;
+        }
+        hipError_t e = hipMemcpyAsync(dst, stage.data(), stage.size() * 4, kind, g->stream);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(g->stream);
+    }
+    hipError_t e = hipMemcpyAsync(stage.data(), src, stage.size() * 4, kind, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(g->stream);
+    float* out = (float*)dst;
+    for (size_t r = 0; r < rows; ++r) {
+        const float* x = stage.data() + r * pitch;
+        float* o = out + r * nrow;
+        if (scale == 1.0f)
+            memcpy(o, x, nrow * 4);
+        else
+            for (size_t i = 0; i < nrow; ++i) o[i] = x[i] * scale;
+    }
+    return hipSuccess;
 }
 
 int64_t row_pitch(int nx) { return ((int64_t)nx + 1 + 31) / 32 * 32; }
@@ -378,7 +410,9 @@ void board_tiles(int b, int nx, int ny, int nz, int tx, int rows, std::vector<Ti
 
 int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide)
 {
-    const int occ = steps == 2 ? field_step2_occupancy(ty, wide) : field_step_occupancy(tx, ty, wide);
+    const int occ = steps == 2 ? (g->mat ? field_step2_material_occupancy(wide)
+                                         : field_step2_occupancy(ty, wide))
+                               : field_step_occupancy(tx, ty, wide);
     return std::max(1, g->cus / kXcds) * occ;
 }
 
@@ -435,6 +469,25 @@ std::vector<float> coef_table(const fdtd_grid_desc& d, int axis, double dt)
                 t[((size_t)c * 2 + half) * (n + 1) + i] = (float)v[c];
         }
     return t;
+}
+
+// A material board's table: the coefficients as the material kernels rebuild
+// them from the FP32 q and kappa at 1/eps_rw = 1, in the same FP32 operations
+// (one rounding each: fmaf, a correctly rounded division, products), so that a
+// node whose material leaves its coefficients unscaled can read them instead.
+void material_coefs(std::vector<float>& t, int n1)
+{
+    for (int half = 0; half < 2; ++half)
+        for (int i = 0; i < n1; ++i) {
+            auto at = [&](int c) -> float& { return t[((size_t)c * 2 + half) * n1 + i]; };
+            const float q = at(kQ), k = at(kKappa);
+            const float ph = std::fmaf(0.5f, q, k);
+            const float rp = 1.0f / ph;
+            at(kPh) = ph;
+            at(kRp) = rp;
+            at(kCa) = std::fmaf(-0.5f, q, k) * rp;
+            at(kCam1) = -q * rp;
+        }
 }
 
 double waveform(const SourceH& s, double t)
@@ -616,8 +669,15 @@ int finalize(fdtd_grid* g)
                     if ((fl & kUpdEz) && lossy)
                         lz = (float)(lscale * 0.25 * (sig(i - 1, j - 1, k) + sig(i, j - 1, k) +
                                                       sig(i - 1, j, k) + sig(i, j, k)));
-                    if (lx != 0.f || ly != 0.f || lz != 0.f) g->node_pass = true;
+                    if (lx != 0.f || ly != 0.f || lz != 0.f) {
+                        g->node_pass = true;
+                        fl |= kCondE;
+                    }
                 }
+                if (fx != 1.f || fy != 1.f || fz != 1.f) fl |= kMatH;
+                if (g->pml_eps_rw && (((fl & kUpdEx) && ix != 1.f) || ((fl & kUpdEy) && iy != 1.f) ||
+                                      ((fl & kUpdEz) && iz != 1.f)))
+                    fl |= kMatE;
                 const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz),
                                    fbits(lx), fbits(ly), fbits(lz)};
                 uint32_t id;
@@ -662,12 +722,20 @@ int finalize(fdtd_grid* g)
     if (!g->ctab) return fail(FDTD_ENOMEM, "class table allocation failed");
     HIP_OR_FAIL(hipMemcpyAsync(g->ctab, table.data(), table.size() * sizeof(ClassEntry),
                                hipMemcpyHostToDevice, st));
+    std::vector<float> tabs[3];
     if (g->node_pass) {
         g->node_aux = (float*)dev_alloc(g, node_aux.size() * 4);
         if (!g->node_aux) return fail(FDTD_ENOMEM, "node table allocation failed");
         HIP_OR_FAIL(hipMemcpyAsync(g->node_aux, node_aux.data(), node_aux.size() * 4, hipMemcpyHostToDevice, st));
+        for (int a = 0; a < 3; ++a) {
+            const int n1 = (a == 0 ? nx : a == 1 ? ny : nz) + 1;
+            tabs[a] = coef_table(d, a, g->dt);
+            material_coefs(tabs[a], n1);
+            HIP_OR_FAIL(hipMemcpyAsync(g->coef[a], tabs[a].data(), tabs[a].size() * 4,
+                                       hipMemcpyHostToDevice, st));
+        }
     }
-    HIP_OR_FAIL(hipStreamSynchronize(st));   // table and node_aux are locals
+    HIP_OR_FAIL(hipStreamSynchronize(st));   // table, node_aux and tabs are locals
 
     // sources: Js = c0 dt eta0 J at the half steps (s + 1/2) dt.  A resistive
     // voltage source (R > 0) carries its Norton current c0 dt eta0 V_s / (R dx dy)
@@ -1139,12 +1207,23 @@ static int upload_list(fdtd_grid* g, int tx, int ty, int steps, TileRef** dev, i
 static int upload_tiles(fdtd_grid* g)
 {
     BoardDev& b = g->board_host;
+    if (g->node_pass) {
+        // a material board takes pairs of steps on the material two-step kernel
+        // (its one shape) when a two-step shape is set, the default; with a
+        // one-step shape, and on boards past the tiled kernels' offset window,
+        // every step runs the node passes
+        g->mat = !g->big && g->tile_steps == 2;
+        if (g->mat) {
+            g->tile_x = 64;
+            g->tile_y = material_tile_y();
+        }
+    }
     tile_counts(g->d.nx, g->d.ny, g->tile_x, owned_rows(g->tile_y, g->tile_steps), &b.tiles_x,
                 &b.tiles_y);
     if (int e = upload_list(g, g->tile_x, g->tile_y, g->tile_steps, &g->tiles_dev, &g->ntiles,
                             &g->tiles_cap))
         return e;
-    if (g->tile_steps == 2)
+    if (g->tile_steps == 2 && !g->node_pass)
         if (int e = upload_list(g, kOddX, kOddY, 1, &g->tiles1_dev, &g->ntiles1, &g->tiles1_cap))
             return e;
     HIP_OR_FAIL(copy_sync(g, g->board_dev, &b, sizeof(BoardDev), hipMemcpyHostToDevice));
@@ -1193,13 +1272,30 @@ static int fold_plane(fdtd_grid* g, int64_t rel_from, int64_t rel_to, hipStream_
     return FDTD_OK;
 }
 
+// One step of a material board on the node passes (an H pass, then an E pass).
+static hipError_t node_step(fdtd_grid* g, int rel, int flip, hipStream_t st)
+{
+    return launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz, g->pitch * (g->d.ny + 1) * 4,
+                           g->big, rel, flip, g->wide, st);
+}
+
+// One launch of the material two-step kernel.
+static hipError_t material_pair(fdtd_grid* g, int rel, int flip, hipStream_t st)
+{
+    return launch_field_step2_material(g->board_dev, g->tiles_dev, g->ntiles, rel, flip, g->wide,
+                                       g->plane_k >= 0, st);
+}
+
 // One field launch of the handle's shape (two steps, or one with the odd-step
-// shape when `single`), optionally bracketed by timing events.
+// shape when `single`; a material board's odd step runs the node passes),
+// optionally bracketed by timing events.
 static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
 {
     if (g->timing)
         if (int e = record_event(g)) return e;
-    if (single && g->tile_steps == 2)
+    if (g->mat)
+        HIP_OR_FAIL(single ? node_step(g, rel, flip, g->stream) : material_pair(g, rel, flip, g->stream));
+    else if (single && g->tile_steps == 2)
         HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, g->board_dev, g->tiles1_dev, g->ntiles1, rel, flip,
                                 g->wide, g->plane_k >= 0, g->stream));
     else
@@ -1216,14 +1312,12 @@ static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
 // one single step when n is odd); returns the launch count through *launches.
 static int enqueue_steps(fdtd_grid* g, int64_t n, int64_t* launches)
 {
-    if (g->node_pass) {
-        // eps_rw boards: one H pass and one E pass per step (one buffer flip)
+    if (g->node_pass && !g->mat) {
+        // one H pass and one E pass per step (one buffer flip)
         for (int64_t s = 0; s < n; ++s) {
             if (g->timing)
                 if (int e = record_event(g)) return e;
-            HIP_OR_FAIL(launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz,
-                                        g->pitch * (g->d.ny + 1) * 4, g->big, (int)s, (int)(s & 1),
-                                        g->wide, g->stream));
+            HIP_OR_FAIL(node_step(g, (int)s, (int)(s & 1), g->stream));
             if (g->timing) {
                 if (int e = record_event(g)) return e;
                 ++g->timed_launches;
@@ -1254,14 +1348,13 @@ static void build_graph(fdtd_grid* g)
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
     bool ok = true;
-    const int per = g->node_pass ? 1 : g->tile_steps, nl = kGraphChunk / per;
+    const int per = g->node_pass && !g->mat ? 1 : g->tile_steps, nl = kGraphChunk / per;
     for (int l = 0; l < nl && ok; ++l)
-        ok = (g->node_pass ? launch_eps_step(g->board_dev, g->d.nx, g->d.ny, g->d.nz,
-                                            g->pitch * (g->d.ny + 1) * 4, g->big, l, l & 1, g->wide,
-                                            g->stream)
-                          : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
-                                        g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
-                                        g->stream)) == hipSuccess;
+        ok = (g->mat         ? material_pair(g, l * per, l & 1, g->stream)
+              : g->node_pass ? node_step(g, l, l & 1, g->stream)
+                             : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
+                                           g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
+                                           g->stream)) == hipSuccess;
     if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, nl, g->stream) == hipSuccess;
     if (ok) ok = fold_plane(g, -kGraphChunk, 0, g->stream) == FDTD_OK;
     const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
@@ -1289,7 +1382,7 @@ int fdtd_step_n(fdtd_grid* g, int64_t n)
         if (g->graph_exec) {
             for (; done + kGraphChunk <= n; done += kGraphChunk) {
                 HIP_OR_FAIL(hipGraphLaunch(g->graph_exec, g->stream));
-                launches += kGraphChunk / (g->node_pass ? 1 : g->tile_steps);
+                launches += kGraphChunk / (g->node_pass && !g->mat ? 1 : g->tile_steps);
             }
         }
     }
@@ -1704,6 +1797,14 @@ int fdtd_synchronize(fdtd_grid* g)
     return check_bad(g);
 }
 
+int fdtd_get_stream(fdtd_grid* g, void** out)
+{
+    if (int e = check_grid(g)) return e;
+    if (!out) return fail(FDTD_EINVAL, "null output");
+    *out = (void*)g->stream;
+    return FDTD_OK;
+}
+
 int fdtd_get_probe(fdtd_grid* g, int id, float* out, int64_t n)
 {
     if (int e = check_grid(g)) return e;
@@ -1868,9 +1969,13 @@ int fdtd_get_field(fdtd_grid* g, int comp, float* out)
     if (int e = check_grid(g)) return e;
     if (comp < 0 || comp > FDTD_BZ || !out) return fail(FDTD_EINVAL, "bad component or output");
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
+    const double s = field_scale(comp);
+    if (s == 1.0) {
+        HIP_OR_FAIL(copy_field_sync(g, out, comp_ptr(g, comp), hipMemcpyDeviceToHost));
+        return FDTD_OK;
+    }
     std::vector<float> h((size_t)g->nodes);
     HIP_OR_FAIL(copy_field_sync(g, h.data(), comp_ptr(g, comp), hipMemcpyDeviceToHost));
-    const double s = field_scale(comp);
     for (size_t t = 0; t < h.size(); ++t) out[t] = (float)((double)h[t] * s);
     return FDTD_OK;
 }
@@ -1900,39 +2005,45 @@ int fdtd_set_field(fdtd_grid* g, int comp, const float* in)
     const fdtd_grid_desc& d = g->d;
     const double s = 1.0 / field_scale(comp);
     std::vector<float> h((size_t)g->nodes);
-    // auxiliaries exist only where their PML predicate holds
-    auto in_pml = [](int idx, int n, int lo, int hi) { return idx < lo || (hi > 0 && idx >= n - hi); };
+    // State entries only: an E edge exists for index < n along its own axis and
+    // is tangential to the wall (held at zero) at 0 or n along the others; an H
+    // face exists for index < n along the other two axes and, on the wall normal
+    // to it (0 or n along its own axis), touches only such E edges, so it
+    // carries nothing either.  Auxiliaries exist only where their PML predicate
+    // holds (the component's own or cyclic-next axis in a PML slab).
     const int axis = comp >= FDTD_DX ? (comp - FDTD_DX) % 3 : -1;
-    // E-like components (E, D) and H-like ones (H, B) by axis
     const bool e_like = comp <= FDTD_EZ || (comp >= FDTD_DX && comp <= FDTD_DZ);
     const int u = comp % 3;
     const int n3[3] = {d.nx, d.ny, d.nz};
+    std::vector<uint8_t> ok[3], pml[3];
+    for (int a = 0; a < 3; ++a) {
+        const int n = n3[a], lo = d.npml[2 * a], hi = d.npml[2 * a + 1];
+        const bool own = a == u;
+        ok[a].resize((size_t)n + 1);
+        pml[a].resize((size_t)n + 1);
+        for (int q = 0; q <= n; ++q) {
+            ok[a][q] = (e_like ? own : !own) ? q < n : (q > 0 && q < n);
+            pml[a][q] = q < lo || (hi > 0 && q >= n - hi);
+        }
+    }
+    // the aux predicate: axis 0 (x or y PML), 1 (y or z), 2 (z or x)
+    const int pa = axis < 0 ? 0 : axis, pb = axis < 0 ? 0 : (axis + 1) % 3;
+    const size_t row = (size_t)d.nx + 1;
     for (int k = 0; k <= d.nz; ++k)
-        for (int j = 0; j <= d.ny; ++j)
-            for (int i = 0; i <= d.nx; ++i) {
-                const int64_t n = node_index(g, i, j, k);
-                // state entries only: an E edge exists for index < n along its own
-                // axis and is tangential to the wall (held at zero) at 0 or n along
-                // the others; an H face exists for index < n along the other two
-                // axes and, on the wall normal to it (0 or n along its own axis),
-                // touches only such E edges, so it carries nothing either
-                const int q[3] = {i, j, k};
-                bool keep = true;
-                for (int a = 0; a < 3; ++a) {
-                    const bool own = a == u;
-                    if (e_like ? own : !own)
-                        keep &= q[a] < n3[a];
-                    else
-                        keep &= q[a] > 0 && q[a] < n3[a];
-                }
+        for (int j = 0; j <= d.ny; ++j) {
+            const int64_t base = node_index(g, 0, j, k);
+            const bool rok = ok[1][j] && ok[2][k];
+            const int qj[3] = {0, j, k};
+            for (size_t i = 0; i < row; ++i) {
+                bool keep = rok && ok[0][i];
                 if (keep && axis >= 0) {
-                    const bool px = in_pml(i, d.nx, d.npml[0], d.npml[1]);
-                    const bool py = in_pml(j, d.ny, d.npml[2], d.npml[3]);
-                    const bool pz = in_pml(k, d.nz, d.npml[4], d.npml[5]);
-                    keep = axis == 0 ? (px || py) : axis == 1 ? (py || pz) : (pz || px);
+                    const bool ia = pa == 0 ? pml[0][i] : pml[pa][qj[pa]];
+                    const bool ib = pb == 0 ? pml[0][i] : pml[pb][qj[pb]];
+                    keep = ia || ib;
                 }
-                h[(size_t)n] = keep ? (float)((double)in[n] * s) : 0.0f;
+                h[(size_t)base + i] = keep ? (float)((double)in[base + i] * s) : 0.0f;
             }
+        }
     HIP_OR_FAIL(hipStreamSynchronize(g->stream));
     HIP_OR_FAIL(copy_field_sync(g, comp_ptr(g, comp), h.data(), hipMemcpyHostToDevice));
     return FDTD_OK;
@@ -2053,6 +2164,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->plane_k = g->plane_k;
     out->plane_nf = (int32_t)g->plane_freqs.size();
     out->node_passes = g->node_pass ? 1 : 0;
+    out->material_two_step = g->mat ? 1 : 0;
     out->batch_plans = (int32_t)g->plans.size();
     out->batch_graphs = 0;
     for (const BatchPlan* p : g->plans) out->batch_graphs += p->exec != nullptr;

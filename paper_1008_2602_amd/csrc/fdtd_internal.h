@@ -36,16 +36,27 @@ static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly o
 // ping-pong buffers (32 B per point, 32 MiB) sit in a fixed device array
 constexpr int kNoAllocFftMax = 1 << 20;
 
+// tile rows of the two-step kernel's material variant (64 x kMatTY x 2)
+constexpr int kMatTY = 10;
+
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;
 
 // per-axis coefficient table: 6 quantities x {node, half node} x (n+1) entries
-// (kappa is read only by the node passes, which rebuild the others from it)
+// (kappa is read only by the material kernels, which rebuild the others from
+// it; on a material board the table's others are those rebuilt values at
+// 1/eps_rw = 1, in FP32, so that reading them gives the same bits)
 enum CoefKind { kCam1 = 0, kCa = 1, kRp = 2, kPh = 3, kQ = 4, kKappa = 5, kNumCoef = 6 };
 
 // class flags (per node): which E components are stepped, and source/probe marks
-// (kPlnEz: the node lies on the plane-DFT plane, its Ez goes to the sample ring)
-enum : uint32_t { kUpdEx = 1u, kUpdEy = 2u, kUpdEz = 4u, kSrcEz = 8u, kPrbEz = 16u, kPlnEz = 32u };
+// (kPlnEz: the node lies on the plane-DFT plane, its Ez goes to the sample ring).
+// On a material board: kMatH, some H face has 1/eps_rw != 1 (its PML
+// coefficients are rebuilt); kMatE, the same for a stepped E edge (eps_rw on);
+// kCondE, some E edge conducts (lossy cell, resistive sheet).
+enum : uint32_t {
+    kUpdEx = 1u, kUpdEy = 2u, kUpdEz = 4u, kSrcEz = 8u, kPrbEz = 16u, kPlnEz = 32u,
+    kMatH = 64u, kMatE = 128u, kCondE = 256u
+};
 
 struct ClassEntry {
     float inv_x, inv_y, inv_z;  // 1/eps_r of the Ex, Ey, Ez edges owned by the node

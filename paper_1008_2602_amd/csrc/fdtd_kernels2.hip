@@ -34,13 +34,39 @@
 
 namespace fdtd {
 
-// coefficient set of one axis at one node position (node "n" and half-node "h")
+// coefficient set of one axis at one node position (node "n" and half-node "h");
+// kappa only in the material variant
 struct AxisCoef {
     float cam1_n, ca_n, rp_n, ph_n, q_n;
     float cam1_h, ca_h, rp_h, ph_h, q_h;
+    float k_n, k_h;
 };
 
-template <int TY, typename CT, bool PL>
+// The material variant (MT): a PML node's coefficients rebuilt from q scaled by
+// the field location's 1/eps_rw (Eq. 2) and kappa, in exactly the node passes'
+// arithmetic, so that the two give the same bits (the node passes take the odd
+// step of a material board).  A material board's table holds these values
+// rebuilt at 1/eps_rw = 1, so nodes whose class flags no scaled location read
+// the table instead (most of the PML, where the board holds air).
+__device__ __forceinline__ AxisCoef scale_coef(const AxisCoef& a, float w)
+{
+    AxisCoef o;
+    o.q_n = a.q_n * w;
+    o.ph_n = fmaf(0.5f, o.q_n, a.k_n);
+    o.rp_n = 1.0f / o.ph_n;
+    o.ca_n = fmaf(-0.5f, o.q_n, a.k_n) * o.rp_n;
+    o.cam1_n = -o.q_n * o.rp_n;
+    o.q_h = a.q_h * w;
+    o.ph_h = fmaf(0.5f, o.q_h, a.k_h);
+    o.rp_h = 1.0f / o.ph_h;
+    o.ca_h = fmaf(-0.5f, o.q_h, a.k_h) * o.rp_h;
+    o.cam1_h = -o.q_h * o.rp_h;
+    o.k_n = a.k_n;
+    o.k_h = a.k_h;
+    return o;
+}
+
+template <int TY, typename CT, bool PL, bool MT>
 __global__ __launch_bounds__(64 * TY + 128)
 __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const BoardDev* __restrict__ boards,
                                                              const TileRef* __restrict__ tiles,
@@ -64,9 +90,14 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     __shared__ float sH2z[TY][SC];
     constexpr int kLdsClasses = sizeof(CT) == 1 ? 256 : 1;
     __shared__ ClassEntry sTab[kLdsClasses];
+    // material variant: each class's 1/eps_r at the H faces and the conduction
+    // of its E edges (six floats), in LDS for one-byte class indices
+    constexpr int kLdsAux = MT && sizeof(CT) == 1 ? 256 : 1;
+    __shared__ float sAux[kLdsAux][6];
     // z coefficients of plane p in slot p & 3 (planes k-1, k and k+1 are live at
-    // once), staged by the last wave
-    __shared__ float sZ[4][10];
+    // once), staged by the last wave; the material variant also keeps kappa
+    constexpr int NZE = MT ? 12 : 10;
+    __shared__ float sZ[4][NZE];
 
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (t.board < 0) return;   // idle entry padding an XCD's list
@@ -160,6 +191,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         a.rp_h = tab[(kRp * 2 + 1) * n1 + q];
         a.ph_h = tab[(kPh * 2 + 1) * n1 + q];
         a.q_h = tab[(kQ * 2 + 1) * n1 + q];
+        a.k_n = MT ? tab[(kKappa * 2 + 0) * n1 + q] : 1.0f;
+        a.k_h = MT ? tab[(kKappa * 2 + 1) * n1 + q] : 1.0f;
         return a;
     };
     // z coefficients from the LDS ring (entry kind*2 + half of the table)
@@ -176,10 +209,12 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         a.rp_h = z[kRp * 2 + 1];
         a.ph_h = z[kPh * 2 + 1];
         a.q_h = z[kQ * 2 + 1];
+        a.k_n = MT ? z[(kKappa * 2 + 0) % NZE] : 1.0f;
+        a.k_h = MT ? z[(kKappa * 2 + 1) % NZE] : 1.0f;
         return a;
     };
-    const bool z_lane = wave == TY + 1 && lane < 10;   // writes entry `lane` of the ring
-    const int zent = lane % 10;
+    const bool z_lane = wave == TY + 1 && lane < NZE;   // writes entry `lane` of the ring
+    const int zent = lane % NZE;
 
     if (sizeof(CT) == 1) {
         for (int e = tid; e < kLdsClasses; e += NT) {
@@ -188,8 +223,16 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
             sTab[e].inv_y = ctab[q].inv_y;
             sTab[e].inv_z = ctab[q].inv_z;
             sTab[e].flags = ctab[q].flags;
+            if (MT)
+                for (int v = 0; v < 6; ++v) sAux[e % kLdsAux][v] = ((cgfloat*)B.node_aux)[6 * q + v];
         }
     }
+    // a class's material data: 1/eps_r at the Hx, Hy, Hz faces, then the
+    // conduction of the Ex, Ey, Ez edges
+    auto aux_of = [&](CT id, int v) {
+        if (sizeof(CT) == 1) return sAux[(int)id % kLdsAux][v];
+        return ((cgfloat*)B.node_aux)[6 * (int)id + v];
+    };
     auto class_entry = [&](CT id) {
         ClassEntry ce;
         if (sizeof(CT) == 1) {
@@ -252,7 +295,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         const uint32_t n = node0b + (uint32_t)p * szb;
         const bool pz = in_pz(p);
         const bool oke = rE1 && ib && p <= nz;
-        const uint32_t ne = oke ? n : guardb;
+        // the material variant's H1 needs the class on every H1 lane
+        const uint32_t ne = (MT ? rH1 && ib && p <= nz : oke) ? n : guardb;
         o.c = ld_at_t<CT>(cls, sizeof(CT) == 1 ? ne >> 2 : ne >> 1);
         o.dx = ld_at(gD, oke && (px || py) ? n : guardb);
         o.dy = ld_at(gD, (oke && (py || pz) ? n : guardb) + cs);
@@ -277,6 +321,126 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         ddz = fmaf(X.cam1_n, d_old, X.rp_n * chs);
         ezn = fmaf(Y.ca_n, e_old, Y.rp_n * (inv_z * fmaf(Zc.ph_h, ddz, Zc.q_h * d_old)));
         if (bs != 0.0f) ezn = conductive_e(e_old, chs, inv_z, bs);
+    };
+    // B then H of one node from the curls of E (the material variant's non-PML
+    // nodes; the plain kernel writes the same expressions in place)
+    auto h_plain = [&](const AxisCoef& Z, float cxe, float cye, float cze, float hxo, float hyo,
+                       float hzo, float bxo, float byo, float bzo, float& dbx, float& dby, float& dbz,
+                       float& hx, float& hy, float& hz) {
+        dbx = fmaf(Y.cam1_h, bxo, -Y.rp_h * cxe);
+        hx = fmaf(Z.ca_h, hxo, Z.rp_h * fmaf(X.ph_n, dbx, X.q_n * bxo));
+        dby = fmaf(Z.cam1_h, byo, -Z.rp_h * cye);
+        hy = fmaf(X.ca_h, hyo, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * byo));
+        dbz = fmaf(X.cam1_h, bzo, -X.rp_h * cze);
+        hz = fmaf(Y.ca_h, hzo, Y.rp_h * fmaf(Z.ph_n, dbz, Z.q_n * bzo));
+    };
+    // D then E of one node without sources or conduction from the table's
+    // coefficients (the material variant's nodes whose 1/eps_rw leaves them
+    // unscaled; the plain kernel writes the same expressions in place)
+    auto e_plain = [&](const ClassEntry& ce, const AxisCoef& Z, float chx, float chy, float chz,
+                       float exo, float eyo, float ezo, float dxo, float dyo, float dzo, float& ddx,
+                       float& ddy, float& ddz, float& exn, float& eyn, float& ezn) {
+        ddx = fmaf(Y.cam1_n, dxo, Y.rp_n * chx);
+        exn = fmaf(Z.ca_n, exo, Z.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * dxo)));
+        ddy = fmaf(Z.cam1_n, dyo, Z.rp_n * chy);
+        eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * dyo)));
+        ddz = fmaf(X.cam1_n, dzo, X.rp_n * chz);
+        ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Z.ph_h, ddz, Z.q_h * dzo)));
+    };
+    // the same in a PML node of a material board: every axis's coefficients
+    // rebuilt for the face's 1/eps_rw (one at each of the Hx, Hy, Hz faces)
+    auto h_material = [&](CT id, const AxisCoef& Z, float cxe, float cye, float cze, float hxo,
+                          float hyo, float hzo, float bxo, float byo, float bzo, float& dbx,
+                          float& dby, float& dbz, float& hx, float& hy, float& hz) {
+        {
+            const float w = aux_of(id, 0);
+            const AxisCoef Ys = scale_coef(Y, w), Zs = scale_coef(Z, w), Xs = scale_coef(X, w);
+            dbx = fmaf(Ys.cam1_h, bxo, -Ys.rp_h * cxe);
+            hx = fmaf(Zs.ca_h, hxo, Zs.rp_h * fmaf(Xs.ph_n, dbx, Xs.q_n * bxo));
+        }
+        {
+            const float w = aux_of(id, 1);
+            const AxisCoef Zs = scale_coef(Z, w), Xs = scale_coef(X, w), Ys = scale_coef(Y, w);
+            dby = fmaf(Zs.cam1_h, byo, -Zs.rp_h * cye);
+            hy = fmaf(Xs.ca_h, hyo, Xs.rp_h * fmaf(Ys.ph_n, dby, Ys.q_n * byo));
+        }
+        {
+            const float w = aux_of(id, 2);
+            const AxisCoef Xs = scale_coef(X, w), Ys = scale_coef(Y, w), Zs = scale_coef(Z, w);
+            dbz = fmaf(Xs.cam1_h, bzo, -Xs.rp_h * cze);
+            hz = fmaf(Ys.ca_h, hzo, Ys.rp_h * fmaf(Zs.ph_n, dbz, Zs.q_n * bzo));
+        }
+    };
+    // D then E of one node on a material board, in the node passes' arithmetic:
+    // with `rebuild` (a PML node with some edge's 1/eps_rw != 1) every axis's
+    // coefficients rebuilt for each edge's 1/eps_rw, else the table's (the same
+    // bits as rebuilt at 1); an edge that conducts (lossy dielectric, resistive
+    // sheet, resistive source) solved for E^{n+1} with its conduction
+    auto e_material = [&](const ClassEntry& ce, CT id, bool rebuild, int node, int64_t s,
+                          const AxisCoef& Z, float chx, float chy, float chz, float exo, float eyo,
+                          float ezo, float dxo, float dyo, float dzo, float& ddx, float& ddy,
+                          float& ddz, float& exn, float& eyn, float& ezn) {
+        const float wx = B.eps_rw ? ce.inv_x : 1.0f, wy = B.eps_rw ? ce.inv_y : 1.0f,
+                    wz = B.eps_rw ? ce.inv_z : 1.0f;
+        {
+            AxisCoef Ys = Y, Zs = Z, Xs = X;
+            if (rebuild) {
+                Ys = scale_coef(Y, wx);
+                Zs = scale_coef(Z, wx);
+                Xs = scale_coef(X, wx);
+            }
+            ddx = fmaf(Ys.cam1_n, dxo, Ys.rp_n * chx);
+            exn = fmaf(Zs.ca_n, exo, Zs.rp_n * (ce.inv_x * fmaf(Xs.ph_h, ddx, Xs.q_h * dxo)));
+        }
+        const float lx = aux_of(id, 3);
+        if (lx != 0.0f) {
+            exn = conductive_e(exo, chx, ce.inv_x, lx);
+            ddx = chx - lx * (exn + exo);
+        }
+        {
+            AxisCoef Zs = Z, Xs = X, Ys = Y;
+            if (rebuild) {
+                Zs = scale_coef(Z, wy);
+                Xs = scale_coef(X, wy);
+                Ys = scale_coef(Y, wy);
+            }
+            ddy = fmaf(Zs.cam1_n, dyo, Zs.rp_n * chy);
+            eyn = fmaf(Xs.ca_n, eyo, Xs.rp_n * (ce.inv_y * fmaf(Ys.ph_h, ddy, Ys.q_h * dyo)));
+        }
+        const float ly = aux_of(id, 4);
+        if (ly != 0.0f) {
+            eyn = conductive_e(eyo, chy, ce.inv_y, ly);
+            ddy = chy - ly * (eyn + eyo);
+        }
+        float chs = chz, bs = 0.0f;
+        if (ce.flags & kSrcEz) {
+            const __attribute__((address_space(1))) int32_t* sn =
+                (const __attribute__((address_space(1))) int32_t*)B.src_node;
+            cgfloat* sj = (cgfloat*)B.src_j;
+            cgfloat* sb = (cgfloat*)B.src_beta;
+            float js = 0.0f;
+            for (int q = 0; q < B.nsrc; ++q)
+                if (sn[q] == node) {
+                    js += sj[q * ms + s];
+                    bs += sb[q];
+                }
+            chs -= js;
+        }
+        {
+            AxisCoef Xs = X, Ys = Y, Zs = Z;
+            if (rebuild) {
+                Xs = scale_coef(X, wz);
+                Ys = scale_coef(Y, wz);
+                Zs = scale_coef(Z, wz);
+            }
+            ddz = fmaf(Xs.cam1_n, dzo, Xs.rp_n * chs);
+            ezn = fmaf(Ys.ca_n, ezo, Ys.rp_n * (ce.inv_z * fmaf(Zs.ph_h, ddz, Zs.q_h * dzo)));
+        }
+        bs += aux_of(id, 5);   // a resistive source's lumped conductance adds to the medium's
+        if (bs != 0.0f) {
+            ezn = conductive_e(ezo, chs, ce.inv_z, bs);
+            ddz = chs - bs * (ezn + ezo);
+        }
     };
     auto record_probe = [&](int node, int64_t s, float ez) {
         const __attribute__((address_space(1))) int32_t* pn =
@@ -336,15 +500,28 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         float h1x = 0.f, h1y = 0.f, h1z = 0.f, b1x = 0.f, b1y = 0.f, b1z = 0.f;
         if (rH1 && okk) {
             const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
-            const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
-            const float dbx = fmaf(Y.cam1_h, o.bx, -Y.rp_h * cxe);
-            h1x = fmaf(Zk.ca_h, o.hx, Zk.rp_h * fmaf(X.ph_n, dbx, X.q_n * o.bx));
-            const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
-            const float dby = fmaf(Zk.cam1_h, o.by, -Zk.rp_h * cye);
-            h1y = fmaf(X.ca_h, o.hy, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * o.by));
-            const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
-            const float dbz = fmaf(X.cam1_h, o.bz, -X.rp_h * cze);
-            h1z = fmaf(Y.ca_h, o.hz, Y.rp_h * fmaf(Zk.ph_n, dbz, Zk.q_n * o.bz));
+            float dbx, dby, dbz;
+            if constexpr (MT) {
+                const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
+                const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
+                const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
+                if ((px || py || pz) && (class_entry(o.c).flags & kMatH))
+                    h_material(o.c, Zk, cxe, cye, cze, o.hx, o.hy, o.hz, o.bx, o.by, o.bz, dbx, dby,
+                               dbz, h1x, h1y, h1z);
+                else
+                    h_plain(Zk, cxe, cye, cze, o.hx, o.hy, o.hz, o.bx, o.by, o.bz, dbx, dby, dbz, h1x,
+                            h1y, h1z);
+            } else {
+                const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
+                dbx = fmaf(Y.cam1_h, o.bx, -Y.rp_h * cxe);
+                h1x = fmaf(Zk.ca_h, o.hx, Zk.rp_h * fmaf(X.ph_n, dbx, X.q_n * o.bx));
+                const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
+                dby = fmaf(Zk.cam1_h, o.by, -Zk.rp_h * cye);
+                h1y = fmaf(X.ca_h, o.hy, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * o.by));
+                const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
+                dbz = fmaf(X.cam1_h, o.bz, -X.rp_h * cze);
+                h1z = fmaf(Y.ca_h, o.hz, Y.rp_h * fmaf(Zk.ph_n, dbz, Zk.q_n * o.bz));
+            }
             b1x = (px || py) ? o.bx + dbx : 0.f;
             b1y = (py || pz) ? o.by + dby : 0.f;
             b1z = (pz || px) ? o.bz + dbz : 0.f;
@@ -366,16 +543,30 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
             const ClassEntry ce = class_entry(o.c);
             const int node = (int)(node0b >> 2) + k * sz;   // node index (source/probe match)
             const float exo = sE0x[cur][r][c], eyo = sE0y[cur][r][c], ezo = sE0z[r][c];
-            const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
-            const float ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
-            float exn = fmaf(Zk.ca_n, exo, Zk.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * o.dx)));
-            const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
-            const float ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
-            float eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
-            const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
-            float ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
-            float ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
-            if (ce.flags & kSrcEz) source_ez(node, step, chz, ezo, o.dz, ce.inv_z, Zk, ddz, ezn);
+            float ddx, ddy, ddz, exn, eyn, ezn;
+            if constexpr (MT) {
+                const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
+                const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
+                const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
+                const bool rebuild = (px || py || pz) && (ce.flags & kMatE);
+                if (rebuild || (ce.flags & (kCondE | kSrcEz)))
+                    e_material(ce, o.c, rebuild, node, step, Zk, chx, chy, chz, exo, eyo, ezo, o.dx,
+                               o.dy, o.dz, ddx, ddy, ddz, exn, eyn, ezn);
+                else
+                    e_plain(ce, Zk, chx, chy, chz, exo, eyo, ezo, o.dx, o.dy, o.dz, ddx, ddy, ddz, exn,
+                            eyn, ezn);
+            } else {
+                const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
+                ddx = fmaf(Y.cam1_n, o.dx, Y.rp_n * chx);
+                exn = fmaf(Zk.ca_n, exo, Zk.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * o.dx)));
+                const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
+                ddy = fmaf(Zk.cam1_n, o.dy, Zk.rp_n * chy);
+                eyn = fmaf(X.ca_n, eyo, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * o.dy)));
+                const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
+                ddz = fmaf(X.cam1_n, o.dz, X.rp_n * chz);
+                ezn = fmaf(Y.ca_n, ezo, Y.rp_n * (ce.inv_z * fmaf(Zk.ph_h, ddz, Zk.q_h * o.dz)));
+                if (ce.flags & kSrcEz) source_ez(node, step, chz, ezo, o.dz, ce.inv_z, Zk, ddz, ezn);
+            }
             e1x = (ce.flags & kUpdEx) ? exn : 0.0f;
             e1y = (ce.flags & kUpdEy) ? eyn : 0.0f;
             e1z = (ce.flags & kUpdEz) ? ezn : 0.0f;
@@ -401,15 +592,28 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         if (rH2 && okm) {
             const int pe = e ^ 1;
             const float exo = sE1x[pe][r][c], eyo = sE1y[pe][r][c], ezo = sE1z[pe][r][c];
-            const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
-            const float dbx = fmaf(Y.cam1_h, p_b1x, -Y.rp_h * cxe);
-            h2x = fmaf(Zm.ca_h, p_h1x, Zm.rp_h * fmaf(X.ph_n, dbx, X.q_n * p_b1x));
-            const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
-            const float dby = fmaf(Zm.cam1_h, p_b1y, -Zm.rp_h * cye);
-            h2y = fmaf(X.ca_h, p_h1y, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * p_b1y));
-            const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
-            const float dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
-            h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
+            float dbx, dby, dbz;
+            if constexpr (MT) {
+                const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
+                const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
+                const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
+                if ((px || py || pzm) && (class_entry(p_c).flags & kMatH))
+                    h_material(p_c, Zm, cxe, cye, cze, p_h1x, p_h1y, p_h1z, p_b1x, p_b1y, p_b1z, dbx,
+                               dby, dbz, h2x, h2y, h2z);
+                else
+                    h_plain(Zm, cxe, cye, cze, p_h1x, p_h1y, p_h1z, p_b1x, p_b1y, p_b1z, dbx, dby, dbz,
+                            h2x, h2y, h2z);
+            } else {
+                const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
+                dbx = fmaf(Y.cam1_h, p_b1x, -Y.rp_h * cxe);
+                h2x = fmaf(Zm.ca_h, p_h1x, Zm.rp_h * fmaf(X.ph_n, dbx, X.q_n * p_b1x));
+                const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
+                dby = fmaf(Zm.cam1_h, p_b1y, -Zm.rp_h * cye);
+                h2y = fmaf(X.ca_h, p_h1y, X.rp_h * fmaf(Y.ph_n, dby, Y.q_n * p_b1y));
+                const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
+                dbz = fmaf(X.cam1_h, p_b1z, -X.rp_h * cze);
+                h2z = fmaf(Y.ca_h, p_h1z, Y.rp_h * fmaf(Zm.ph_n, dbz, Zm.q_n * p_b1z));
+            }
             if (own && livem) {
                 const uint32_t nb = node0b + (uint32_t)m * szb;
                 st_at(dH, nb, h2x);
@@ -437,16 +641,30 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         if (own && livem) {
             const ClassEntry ce = class_entry(p_c);
             const int node = (int)(node0b >> 2) + m * sz;
-            const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
-            const float ddx = fmaf(Y.cam1_n, p_d1x, Y.rp_n * chx);
-            float exn = fmaf(Zm.ca_n, p_e1x, Zm.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * p_d1x)));
-            const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
-            const float ddy = fmaf(Zm.cam1_n, p_d1y, Zm.rp_n * chy);
-            float eyn = fmaf(X.ca_n, p_e1y, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * p_d1y)));
-            const float chz = (h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy;
-            float ddz = fmaf(X.cam1_n, p_d1z, X.rp_n * chz);
-            float ezn = fmaf(Y.ca_n, p_e1z, Y.rp_n * (ce.inv_z * fmaf(Zm.ph_h, ddz, Zm.q_h * p_d1z)));
-            if (ce.flags & kSrcEz) source_ez(node, step + 1, chz, p_e1z, p_d1z, ce.inv_z, Zm, ddz, ezn);
+            float ddx, ddy, ddz, exn, eyn, ezn;
+            if constexpr (MT) {
+                const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
+                const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
+                const float chz = (h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy;
+                const bool rebuild = (px || py || pzm) && (ce.flags & kMatE);
+                if (rebuild || (ce.flags & (kCondE | kSrcEz)))
+                    e_material(ce, p_c, rebuild, node, step + 1, Zm, chx, chy, chz, p_e1x, p_e1y,
+                               p_e1z, p_d1x, p_d1y, p_d1z, ddx, ddy, ddz, exn, eyn, ezn);
+                else
+                    e_plain(ce, Zm, chx, chy, chz, p_e1x, p_e1y, p_e1z, p_d1x, p_d1y, p_d1z, ddx, ddy,
+                            ddz, exn, eyn, ezn);
+            } else {
+                const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
+                ddx = fmaf(Y.cam1_n, p_d1x, Y.rp_n * chx);
+                exn = fmaf(Zm.ca_n, p_e1x, Zm.rp_n * (ce.inv_x * fmaf(X.ph_h, ddx, X.q_h * p_d1x)));
+                const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
+                ddy = fmaf(Zm.cam1_n, p_d1y, Zm.rp_n * chy);
+                eyn = fmaf(X.ca_n, p_e1y, X.rp_n * (ce.inv_y * fmaf(Y.ph_h, ddy, Y.q_h * p_d1y)));
+                const float chz = (h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy;
+                ddz = fmaf(X.cam1_n, p_d1z, X.rp_n * chz);
+                ezn = fmaf(Y.ca_n, p_e1z, Y.rp_n * (ce.inv_z * fmaf(Zm.ph_h, ddz, Zm.q_h * p_d1z)));
+                if (ce.flags & kSrcEz) source_ez(node, step + 1, chz, p_e1z, p_d1z, ce.inv_z, Zm, ddz, ezn);
+            }
             exn = (ce.flags & kUpdEx) ? exn : 0.0f;
             eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
             ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
@@ -495,15 +713,15 @@ void shape2_at(int s, int* tx, int* ty)
     *ty = kShapes2[s].ty;
 }
 
-template <int TY, bool PL>
+template <int TY, bool PL, bool MT>
 static void launch2_tp(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
                        bool wide, hipStream_t st)
 {
     if (wide)
-        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL>), dim3(ntiles), dim3(64 * TY + 128), 0,
+        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL, MT>), dim3(ntiles), dim3(64 * TY + 128), 0,
                            st, boards, tiles, rel, flip);
     else
-        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL>), dim3(ntiles), dim3(64 * TY + 128), 0,
+        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL, MT>), dim3(ntiles), dim3(64 * TY + 128), 0,
                            st, boards, tiles, rel, flip);
 }
 
@@ -514,9 +732,9 @@ static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int nt
                             int flip, bool wide, bool plane, hipStream_t st)
 {
     if (plane)
-        launch2_tp<TY, true>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, false>(boards, tiles, ntiles, rel, flip, wide, st);
     else
-        launch2_tp<TY, false>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, false>(boards, tiles, ntiles, rel, flip, wide, st);
     return hipGetLastError();
 }
 
@@ -525,9 +743,9 @@ static int occupancy2_t(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t, false>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, false>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t, false>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, false>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -556,6 +774,31 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
         case 6: return launch2_t<6>(boards, tiles, ntiles, rel, flip, wide, plane, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// The material variant (Eq. 2's eps_rw in a dielectric PML, conduction): one
+// shape, 64 x kMatTY x 2, whose three waves per SIMD leave the registers the
+// rebuilt coefficients need.
+int material_tile_y() { return kMatTY; }
+
+int field_step2_material_occupancy(bool wide)
+{
+    int n = 0;
+    hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step2<kMatTY, uint16_t, false, true>, 64 * kMatTY + 128, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &n, field_step2<kMatTY, uint8_t, false, true>, 64 * kMatTY + 128, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_field_step2_material(const BoardDev* boards, const TileRef* tiles, int ntiles,
+                                       int rel, int flip, bool wide, bool plane, hipStream_t st)
+{
+    if (plane)
+        launch2_tp<kMatTY, true, true>(boards, tiles, ntiles, rel, flip, wide, st);
+    else
+        launch2_tp<kMatTY, false, true>(boards, tiles, ntiles, rel, flip, wide, st);
+    return hipGetLastError();
 }
 
 }  // namespace fdtd

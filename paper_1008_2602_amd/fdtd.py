@@ -63,7 +63,8 @@ class fdtd_info(C.Structure):
                 ("n_sources", C.c_int32), ("n_probes", C.c_int32), ("n_freqs", C.c_int32),
                 ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("tile_steps", C.c_int32), ("plane_k", C.c_int32), ("plane_nf", C.c_int32),
-                ("node_passes", C.c_int32), ("batch_plans", C.c_int32), ("batch_graphs", C.c_int32)]
+                ("node_passes", C.c_int32), ("material_two_step", C.c_int32),
+                ("batch_plans", C.c_int32), ("batch_graphs", C.c_int32)]
 
 
 class FdtdError(RuntimeError):
@@ -110,6 +111,7 @@ _sigs = {
     "fdtd_set_timing": ([_P, C.c_int], C.c_int),
     "fdtd_get_timing": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "fdtd_synchronize": ([_P], C.c_int),
+    "fdtd_get_stream": ([_P, C.POINTER(C.c_void_p)], C.c_int),
     "fdtd_destroy_grid": ([_P], C.c_int),
     "fdtd_last_error": ([], C.c_char_p),
 }
@@ -395,6 +397,13 @@ def fdtd_get_timing(g):
     n = C.c_int64()
     _check(_lib.fdtd_get_timing(g, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def fdtd_get_stream(g) -> int:
+    """The handle's hipStream_t as an integer (e.g. for torch.cuda.ExternalStream)."""
+    p = C.c_void_p()
+    _check(_lib.fdtd_get_stream(g, C.byref(p)))
+    return int(p.value or 0)
 
 
 def fdtd_synchronize(g):

@@ -77,10 +77,50 @@ class _Resident:
     admit_s: float
 
 
+class _StreamPool:
+    """HIP streams (non-blocking, default priority) owned by the executor for its
+    whole life: each resident board has one to itself, and a finished board's
+    stream goes back to the pool.  Streams outlive every event recorded on them,
+    and no two live boards share one (a batched call captures its launches on
+    its first board's stream, which no other thread may touch meanwhile)."""
+
+    def __init__(self):
+        import ctypes
+        # the HIP runtime the library and PyTorch already use
+        self._hip = ctypes.CDLL("libamdhip64.so.7")
+        self._c = ctypes
+        self._free: List[int] = []
+        self._all: List[int] = []
+        self._lock = threading.Lock()
+
+    def get(self) -> int:
+        with self._lock:
+            if self._free:
+                return self._free.pop()
+        s = self._c.c_void_p()
+        rc = self._hip.hipStreamCreateWithFlags(self._c.byref(s), 1)   # hipStreamNonBlocking
+        if rc != 0 or not s.value:
+            raise RuntimeError(f"hipStreamCreateWithFlags failed ({rc})")
+        with self._lock:
+            self._all.append(int(s.value))
+        return int(s.value)
+
+    def put(self, stream: int) -> None:
+        with self._lock:
+            self._free.append(stream)
+
+    def close(self) -> None:
+        with self._lock:
+            for st in self._all:
+                self._hip.hipStreamSynchronize(self._c.c_void_p(st))
+                self._hip.hipStreamDestroy(self._c.c_void_p(st))
+            self._all, self._free = [], []
+
+
 class GpuExecutor:
-    """Runs boards through libfdtd on the current device.  Every board gets a
-    stream of its own; a chunk runs on its first board's stream (the library's
-    batched call), bracketed by events for the device-busy figure."""
+    """Runs boards through libfdtd on the current device.  Every resident board
+    runs on a stream of its own from the executor's pool; a chunk runs on its
+    first board's stream, bracketed by events for the device-busy figure."""
 
     def __init__(self, allocator=None, tile=None, collect=True):
         import torch
@@ -90,7 +130,8 @@ class GpuExecutor:
         self.allocator = allocator
         self.tile = tile
         self.collect = collect
-        self.streams = {}
+        self.pool = _StreamPool()
+        self.streams = {}               # id(handle) -> (raw stream, torch view of it)
         self._lock = threading.Lock()
         self.chunk_events = []          # (start, end) events of every chunk
 
@@ -100,19 +141,23 @@ class GpuExecutor:
     def create(self, req: SolveRequest):
         """Set up a board (device buffers, classes, tables, work lists) on its own
         stream; returns when the board is ready to step."""
-        st = self.torch.cuda.Stream()
-        g, ids = self.F.grid_from_board(req.board, max_steps=req.n_steps,
-                                        allocator=self.allocator, tile=self.tile,
-                                        hip_stream=st.cuda_stream)
+        raw = self.pool.get()
+        try:
+            g, ids = self.F.grid_from_board(req.board, max_steps=req.n_steps,
+                                            allocator=self.allocator, tile=self.tile,
+                                            hip_stream=raw)
+        except Exception:
+            self.pool.put(raw)
+            raise
         self.F.fdtd_step_n(g, 0)               # finalise now, not inside a chunk
         self.F.fdtd_synchronize(g)
         with self._lock:
-            self.streams[id(g)] = st
+            self.streams[id(g)] = (raw, self.torch.cuda.ExternalStream(raw))
         return g, ids
 
     def step_async(self, handles: Sequence, ns: Sequence[int]):
         """Enqueue one chunk (no wait); returns its completion token."""
-        st = self.streams[id(handles[0])]
+        st = self.streams[id(handles[0])][1]
         start = self.torch.cuda.Event(enable_timing=True)
         end = self.torch.cuda.Event(enable_timing=True)
         start.record(st)
@@ -132,8 +177,7 @@ class GpuExecutor:
         that some chunk ran on the device."""
         if not self.chunk_events:
             return None
-        for _, e in self.chunk_events:
-            e.synchronize()
+        self.chunk_events[-1][1].synchronize()     # chunks run in order
         first = self.chunk_events[0][0]
         busy = 0.0
         last_end = 0.0
@@ -152,10 +196,16 @@ class GpuExecutor:
                 if probe_ids else np.zeros((0, req.n_steps), np.float32)
             if req.board.dft_freqs is not None and probe_ids:
                 dft = np.stack([F.fdtd_get_dft(handle, p) for p in probe_ids])
-        F.fdtd_destroy_grid(handle)
+        F.fdtd_destroy_grid(handle)             # waits for the handle's stream
         with self._lock:
-            self.streams.pop(id(handle), None)
+            raw, _ = self.streams.pop(id(handle), (None, None))
+        if raw is not None:
+            self.pool.put(raw)
         return probes, dft
+
+    def close(self) -> None:
+        """Release the stream pool (after every board is finished)."""
+        self.pool.close()
 
     def now(self) -> float:
         return time.perf_counter()
@@ -296,8 +346,10 @@ class Server:
         nxt = 0
         pool = ThreadPoolExecutor(max_workers=self.workers)
 
-        def finish_job(e: _Resident, token):
-            ex.wait(token)
+        def finish_job(e: _Resident):
+            # the board's reads wait on its own stream, which the batched call
+            # orders after the chunk the board completed in; only the main
+            # thread waits on chunk tokens
             probes, dft = ex.finish(e.handle, e.probe_ids, e.req)
             b = e.req.board
             return SolveResult(e.req.rid, e.req.arrival_s, e.admit_s, ex.now() - t0,
@@ -338,7 +390,7 @@ class Server:
                     resident = still
                     inflight.append((token, done))
                     for e in done:
-                        finishing[pool.submit(finish_job, e, token)] = e
+                        finishing[pool.submit(finish_job, e)] = e
                     if self.log:
                         self.log(dict(t=ex.now() - t0, chunk=self.chunks, resident=len(resident),
                                       waiting=len(waiting), used=used,

@@ -1,10 +1,13 @@
 """Eq. 2's eps_rw on the HIP path: boards whose dielectric reaches into a PML slab
-step with the per-node eps_rw passes, against the FP64 oracle.
+step in the node passes' arithmetic (pairs of steps on the material two-step
+kernel, an odd step on the node passes; or, with a one-step shape set, every
+step on the node passes), against the FP64 oracle.
 
 Tolerances as for the fused kernels: all 12 arrays within a relative L2 of 2e-5
 after a few steps from arbitrary states, probes and the plane DFT within 1e-4;
-call splits, graphs, checkpoints and the batched call give the same bits; with
-the PML in air the flag changes nothing and the fused kernels run.
+the two-step kernel and the node passes give the same bits, and so do call
+splits, graphs, checkpoints and the batched call; with the PML in air the flag
+changes nothing and the fused kernels run.
 """
 import dataclasses
 
@@ -42,6 +45,36 @@ def eps_board(seed, steps, nx=30, ny=21, nz=14):
     kp = int(np.nonzero((b.pec_edge_mask & 3).any(axis=(1, 2)))[0][0])
     b.plane_dft = (kp, np.array([2e9, 11e9]))
     return b
+
+
+NODE_ONLY = (64, 8, 1)   # a one-step shape: every step of a material board on the node passes
+
+
+def step_from_state(F, b, init, tile=None):
+    """All 12 arrays set from `init`, b.steps steps: (info, fields)."""
+    g, _ = F.grid_from_board(b, max_steps=b.steps, tile=tile)
+    try:
+        for c, n in enumerate(FIELDS):
+            F.fdtd_set_field(g, c, init[n].astype(np.float32))
+        F.fdtd_step_n(g, b.steps)
+        F.fdtd_synchronize(g)
+        return F.fdtd_get_info(g), gpu_fields(F, g, b)
+    finally:
+        F.fdtd_destroy_grid(g)
+
+
+def two_step_equals_node_passes(F, b, init):
+    """The default (material two-step kernel, the odd step on the node passes)
+    and the node passes alone from the same state: the same bits.  Returns the
+    fields."""
+    info, fields = step_from_state(F, b, init)
+    info1, fields1 = step_from_state(F, b, init, tile=NODE_ONLY)
+    assert info.node_passes == 1 and info1.node_passes == 1
+    assert info.material_two_step == 1 and info1.material_two_step == 0
+    assert (info.tile_x, info.tile_steps) == (64, 2)
+    for n in FIELDS:
+        assert np.array_equal(fields[n], fields1[n]), n
+    return fields
 
 
 def run(F, b, chunks=None, timing=False, tile=None):
@@ -95,16 +128,7 @@ def test_eps_rw_random_state_few_steps(F, oracle_mod, shape, npml):
     init = {n: st[n].copy() for n in FIELDS}
     announce(f"eps_rw random state {shape} npml={npml}")
     ref = oracle_mod.run(b, state=st)
-    g, _ = F.grid_from_board(b, max_steps=b.steps)
-    try:
-        for c, n in enumerate(FIELDS):
-            F.fdtd_set_field(g, c, init[n].astype(np.float32))
-        F.fdtd_step_n(g, b.steps)
-        F.fdtd_synchronize(g)
-        assert F.fdtd_get_info(g).node_passes == 1
-        fields = gpu_fields(F, g, b)
-    finally:
-        F.fdtd_destroy_grid(g)
+    fields = two_step_equals_node_passes(F, b, init)
     compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
 
@@ -144,25 +168,22 @@ def test_node_pass_z_chunks_random_state(F, oracle_mod, shape, lossy):
     init = {n: st[n].copy() for n in FIELDS}
     announce(f"node-pass z chunks {shape} lossy={lossy}")
     ref = oracle_mod.run(b, state=st, threads=16)
-    g, _ = F.grid_from_board(b, max_steps=b.steps)
-    try:
-        for c, n in enumerate(FIELDS):
-            F.fdtd_set_field(g, c, init[n].astype(np.float32))
-        F.fdtd_step_n(g, b.steps)
-        F.fdtd_synchronize(g)
-        assert F.fdtd_get_info(g).node_passes == 1
-        fields = gpu_fields(F, g, b)
-    finally:
-        F.fdtd_destroy_grid(g)
+    # every step on the node passes (their z chunks), then the default (one pair
+    # on the two-step kernel, the last step on the node passes): the same bits
+    fields = two_step_equals_node_passes(F, b, init)
     rep = compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
     for n, (whole, elem, reg, where) in rep.items():
         print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
 
 
 def test_eps_rw_bitwise_across_calls_graphs_checkpoints_and_batches(F):
+    """75 steps (two 32-step graph chunks and a tail with an odd step) against
+    odd call splits (each odd count ends on the node passes), timed launches,
+    the node passes alone, a checkpoint at step 40 and a batched call."""
     b = eps_board(3, steps=75)
     ref = run(F, b)
-    for out in (run(F, b, chunks=[7, 1, 33, 34]), run(F, b, timing=True), run(F, b, tile=(64, 8, 1))):
+    assert ref[0].material_two_step == 1
+    for out in (run(F, b, chunks=[7, 1, 33, 34]), run(F, b, timing=True), run(F, b, tile=NODE_ONLY)):
         assert np.array_equal(out[1], ref[1]) and np.array_equal(out[2], ref[2])
         for n in FIELDS:
             assert np.array_equal(out[3][n], ref[3][n]), n

@@ -1,8 +1,9 @@
 """Lossy dielectrics and resistive sheets (conductor loss) on the HIP path (the
-node passes), against the FP64 oracle: probes within 1e-4 (relative L2), all 12
-arrays within 2e-5 after a few steps from arbitrary states, a resistive source
-on a lossy edge (the two conductances add), sheet edges on lossy cells, and the
-argument checks."""
+material two-step kernel and the node passes), against the FP64 oracle: probes
+within 1e-4 (relative L2), all 12 arrays within 2e-5 after a few steps from
+arbitrary states, a resistive source on a lossy edge (the two conductances
+add), sheet edges on lossy cells, the two-step kernel bitwise equal to the node
+passes across call splits, graphs and checkpoints, and the argument checks."""
 import dataclasses
 
 import numpy as np
@@ -10,6 +11,7 @@ import pytest
 
 import boardgen
 from _util import rel_l2
+from test_gpu_eps import NODE_ONLY, run, two_step_equals_node_passes
 from test_gpu_parity import FIELDS, announce, compare_fields, gpu_fields, random_state
 
 pytestmark = pytest.mark.gpu
@@ -72,15 +74,7 @@ def test_lossy_random_state_few_steps(F, oracle_mod, eps_rw):
     init = {n: st[n].copy() for n in FIELDS}
     announce(f"lossy random state eps_rw={eps_rw}")
     ref = oracle_mod.run(b, state=st)
-    g, _ = F.grid_from_board(b, max_steps=b.steps)
-    try:
-        for c, n in enumerate(FIELDS):
-            F.fdtd_set_field(g, c, init[n].astype(np.float32))
-        F.fdtd_step_n(g, b.steps)
-        F.fdtd_synchronize(g)
-        fields = gpu_fields(F, g, b)
-    finally:
-        F.fdtd_destroy_grid(g)
+    fields = two_step_equals_node_passes(F, b, init)
     compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
 
@@ -184,16 +178,47 @@ def test_sheet_random_state_few_steps(F, oracle_mod, eps_rw):
     init = {n: st[n].copy() for n in FIELDS}
     announce(f"resistive sheet random state eps_rw={eps_rw}")
     ref = oracle_mod.run(b, state=st)
+    fields = two_step_equals_node_passes(F, b, init)
+    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_lossy_sheet_bitwise_across_calls_graphs_and_checkpoints(F, wide):
+    """A lossy board with a resistive sheet and a resistive source, 75 steps
+    (two 32-step graph chunks and an odd tail): odd call splits, timed launches
+    and the node passes alone give the same bits, and so does a checkpoint at
+    step 41 (an odd step count on each side).  wide: per-cell eps_r as well, so
+    that the board has more than 256 material classes (16-bit class map)."""
+    b = sheet_board(5, steps=75)
+    b.probes.append((b.nx // 2 + 2, b.ny // 2, b.nz // 2 + 1))
+    if wide:
+        rng = np.random.default_rng(12)
+        b.eps_r_cell[:] = rng.choice([1.0, 2.2, 3.3, 4.4], size=b.eps_r_cell.shape).astype(np.float32)
+        b.pml_eps_rw = True
+    else:     # one conductivity over the inner region: few classes (8-bit class map)
+        p = b.npml
+        b.sigma_cell[:] = 0.0
+        b.sigma_cell[p[4]:b.nz - p[5], p[2]:b.ny - p[3], p[0]:b.nx - p[1]] = 0.5
+    ref = run(F, b)
+    assert ref[0].material_two_step == 1 and (ref[0].n_classes > 256) == wide
+    assert np.abs(ref[1]).max() > 0
+    for out in (run(F, b, chunks=[7, 1, 33, 34]), run(F, b, timing=True), run(F, b, tile=NODE_ONLY)):
+        assert np.array_equal(out[1], ref[1])
+        for n in FIELDS:
+            assert np.array_equal(out[3][n], ref[3][n]), n
     g, _ = F.grid_from_board(b, max_steps=b.steps)
+    g2, _ = F.grid_from_board(b, max_steps=b.steps)
     try:
-        for c, n in enumerate(FIELDS):
-            F.fdtd_set_field(g, c, init[n].astype(np.float32))
-        F.fdtd_step_n(g, b.steps)
-        F.fdtd_synchronize(g)
-        fields = gpu_fields(F, g, b)
+        F.fdtd_step_n(g, 41)
+        F.fdtd_load_state(g2, F.fdtd_save_state(g))
+        F.fdtd_step_n(g2, 34)
+        F.fdtd_synchronize(g2)
+        fields = gpu_fields(F, g2, b)
+        for n in FIELDS:
+            assert np.array_equal(fields[n], ref[3][n]), n
     finally:
         F.fdtd_destroy_grid(g)
-    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
+        F.fdtd_destroy_grid(g2)
 
 
 def test_conductor_loss_table1_board_against_oracle(F, oracle_mod):

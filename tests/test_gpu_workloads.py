@@ -52,8 +52,14 @@ def set_arbitrary_eh(F, g, board, q, pool):
     for c in range(6):
         src = pool[0] if c < 3 else pool[1]
         start = (7919 * (6 * q + c)) % (src.size - 1)
-        idx = (start + np.arange(size, dtype=np.int64)) % src.size
-        F.fdtd_set_field(g, c, src[idx].reshape(shp))
+        out = np.empty(size, np.float32)
+        pos = 0
+        while pos < size:                 # the pool from `start` on, wrapped around
+            n = min(size - pos, src.size - start)
+            out[pos:pos + n] = src[start:start + n]
+            pos += n
+            start = 0
+        F.fdtd_set_field(g, c, out.reshape(shp))
 
 
 @pytest.mark.timeout(900)

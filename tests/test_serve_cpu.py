@@ -176,6 +176,7 @@ class AsyncModelExecutor(ModelExecutor):
         import queue
         import threading
         self.setup_s = setup_s
+        self.last_chunk = {}
         self.q = queue.Queue()
         self.lock = threading.Lock()
         self.t0 = __import__("time").perf_counter()
@@ -210,6 +211,9 @@ class AsyncModelExecutor(ModelExecutor):
                 b = self.reqs[h].board
                 work += b.nx * b.ny * b.nz * n
         ev = threading.Event()
+        with self.lock:
+            for h in handles:
+                self.last_chunk[h] = ev
         self.q.put((work, ev))
         return ev
 
@@ -217,6 +221,10 @@ class AsyncModelExecutor(ModelExecutor):
         token.wait()
 
     def finish(self, h, ids, req):
+        # as a board's own stream does on the device: reads wait for its last chunk
+        with self.lock:
+            ev = self.last_chunk[h]
+        ev.wait()
         with self.lock:
             steps = self.live.pop(h)
         assert steps == req.n_steps
