@@ -11,14 +11,15 @@ Beside it, the same line carries
   * "batched": 64 uneven board variants advanced together by fdtd_step_many
     (one field launch per step over all boards), Gcell-updates/s and the HBM
     fraction on algorithmic bytes;
-  * "served": seeded Poisson arrivals of board variants (5 % large 800x800x64
-    boards) at 0.7x the measured batched capacity, admitted by device footprint
-    into 85 % of free HBM, advanced in 500-step chunks, each finished solve
-    read back with its probe spectra; p50/p99 latency and throughput.  Each solve
-    is 8000 steps; the number of requests is reduced (default 24) so the run
-    stays short; both are stated in the output.  Unless --no-cpu-baseline, the
-    oracle re-runs the smallest served solve and the largest probe relative L2
-    is reported beside the latencies;
+  * "served": 512 seeded Poisson arrivals of board variants (5 % large
+    800x800x64 boards) offered at 0.7x the measured batched capacity for the
+    stream's mean board, admitted by device footprint into 85 % of free HBM,
+    advanced in 500-step chunks in the tuned batched shape, each finished solve
+    read back with its probe spectra; p50/p99 latency over all solves,
+    throughput and the GPU-busy fraction.  Each solve is 8000 steps; the arrivals
+    span about 7 minutes, most of the default run (--serve-requests cuts it).
+    Unless --no-cpu-baseline, the oracle re-runs the smallest served solve and
+    the largest probe relative L2 is reported beside the latencies;
   * "plane_dft": the large board with a 16-frequency DFT of its ground-plane Ez
     over the whole plane, against the plain step;
   * "node_passes": boards in the node passes' arithmetic: the large board run
@@ -275,8 +276,11 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
         info = F.fdtd_get_info(g)
         F.fdtd_destroy_grid(g)
         assert info.node_passes == (1 if mat >= 0 else 0) and info.material_two_step == max(mat, 0)
+        split = {1: "per tile, material variant 64x14x2", 2: "per plane, material variant 64x10x2"}
         out[name] = {
-            "kernel": ("material two-step (odd steps on the node passes)" if mat == 1 else
+            "kernel": (f"plain 64x14x2 and its material variant ({split.get(info.material_split)}; "
+                       f"{info.material_permille / 10:.1f} % of tile planes on it), odd steps on the "
+                       f"node passes" if mat == 1 else
                        "node passes" if mat == 0 else f"fused {info.tile_x}x{info.tile_y}x{info.tile_steps}"),
             "ms_per_step": round(wall / K * 1e3, 4),
             "gcell_updates_per_s": round(bb.cells * K / wall / 1e9, 3),
@@ -672,7 +676,7 @@ def main():
     ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
                                        "eps", "eps_large", "shard", "realistic"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")

@@ -94,6 +94,11 @@ typedef struct {
     int32_t node_passes;         /* 1: steps run the node passes' arithmetic (fdtd_set_pml_eps_rw,
                                     fdtd_set_conductivity, fdtd_set_sheet_resistance) */
     int32_t material_two_step;   /* 1: of which pairs of steps run on the material two-step kernel */
+    int32_t material_permille;   /* of its tiles' node planes, the share (per mille) on the material
+                                    variant; the others run the plain two-step kernel */
+    int32_t material_split;      /* how: 1 per tile (the variant in the plain kernel's 64 x 14 tiles),
+                                    2 per plane (planes near material nodes in any tile run the
+                                    64 x 10 variant for every tile) */
     int32_t batch_plans;         /* plans of fdtd_step_many calls this handle led, kept for reuse */
     int32_t batch_graphs;        /* of which captured as a graph (one graph launch per call) */
 } fdtd_info;
@@ -167,11 +172,19 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
  * for H and B, since Eq. 1 puts the same s-bar on mu.  Off (the default),
  * eps_rw = 1, which is the same wherever the PML holds air (eps_r = 1).  When it
  * is on and some PML location has eps_r != 1 (a board running into the PML),
- * steps run the node passes (two per-node passes, H then E, coefficients rebuilt
- * from kappa and sigma / eps_rw) instead of the tiled field kernels;
- * fdtd_info.node_passes reports it, tile shapes are then ignored, and
- * fdtd_step_many steps such handles on their own streams.  ESTATE after the
- * first step. */
+ * steps run in the node passes' arithmetic (each PML node's coefficients rebuilt
+ * from kappa and sigma / eps_rw; fdtd_info.node_passes = 1).  With a two-step
+ * tile shape (the default) pairs of steps run two-step kernels of the shape
+ * 64 x 14 x 2 and their material variant (fdtd_info.material_two_step = 1): a
+ * tile's planes whose footprint holds, within two planes below or one above, a
+ * node that needs the material arithmetic (a PML node with eps_r != 1 at a field
+ * location, or a conducting edge) run the material variant, in that tile (few
+ * tiles hold such nodes) or, for every tile, in 64 x 10 x 2 tiles (such nodes
+ * fill those planes), whichever is estimated cheaper; the other planes run the
+ * plain kernel (fdtd_info.material_permille, material_split).  The odd last
+ * step of a call runs the node passes (two per-node passes, H then E).  With a one-step shape set, and on
+ * boards past the tiled kernels' 4 GiB offset window, every step runs the node
+ * passes.  All give the same bits.  ESTATE after the first step. */
 int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);
 
 /* Lossy dielectric (the Results section notes the lossless model overstates how
@@ -181,8 +194,8 @@ int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);
  * current sigma_c Ebar (Ebar the mean of E^n and E^{n+1}), solved for E^{n+1}
  * as for a resistive source, whose lumped conductance it adds to.  Cells in a
  * PML slab must be lossless (EINVAL otherwise).  A board with any conductive
- * edge steps with the node passes (see fdtd_set_pml_eps_rw).  ESTATE after the
- * first step. */
+ * edge steps in the node passes' arithmetic (see fdtd_set_pml_eps_rw).  ESTATE
+ * after the first step. */
 int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell);
 
 /* Conductor loss (the Results section names the perfect conductors, beside the
@@ -194,7 +207,7 @@ int fdtd_set_conductivity(fdtd_grid* g, const float* sigma_cell);
  * carries the conductivity 1 / (R_s dz), is solved for E^{n+1} like a lossy
  * dielectric and adds to any conductivity set by fdtd_set_conductivity; PEC Ez
  * edges stay perfect.  0 (the default) keeps perfect conductors.  A board with
- * sheets steps with the node passes (see fdtd_set_pml_eps_rw).  EINVAL if the
+ * sheets steps in the node passes' arithmetic (see fdtd_set_pml_eps_rw).  EINVAL if the
  * value is negative or not finite, and at the first step if a stepped sheet
  * edge touches a cell of a PML slab; ESTATE after the first step. */
 int fdtd_set_sheet_resistance(fdtd_grid* g, double ohms_per_square);
@@ -223,7 +236,10 @@ int fdtd_step_n(fdtd_grid* g, int64_t n);
 
 /* Batched stepping: advance ng handles by n[h] steps each in shared launches
  * (one field launch per pass covers every handle still running; handles whose
- * class index widths differ go to two launches).  Handles must be distinct and
+ * class index widths differ, and material boards (fdtd_info.material_two_step),
+ * go to launches of their own, the latter on the material variant over all
+ * their planes, with their odd last steps on the node passes).  Handles must be
+ * distinct and
  * share one device; results are bitwise those of stepping each alone (the probe
  * DFT to rounding: it sums each call's samples in one pass).  Runs on the first
  * handle's stream, ordered after (and before) work on the other handles'
@@ -232,8 +248,8 @@ int fdtd_step_n(fdtd_grid* g, int64_t n);
  * per-board tables and work lists in device memory, and the call's launches
  * captured as a HIP graph when the lead's stream can be captured; later calls
  * with the same plan replay it as one graph launch and return without waiting
- * for the device.  The lead keeps its last 4 plans.  Boards on the node passes
- * step on their own streams.  Same errors as fdtd_step_n. */
+ * for the device.  The lead keeps its last 4 plans.  Boards whose every step
+ * runs the node passes step on their own streams.  Same errors as fdtd_step_n. */
 int fdtd_step_many(fdtd_grid* const* g, int ng, const int64_t* n);
 
 /* Upper bound of the device memory (bytes) fdtd_create_grid with this

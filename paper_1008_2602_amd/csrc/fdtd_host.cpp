@@ -29,10 +29,11 @@ void shape2_at(int s, int* tx, int* ty);
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
                               int rel, int flip, bool wide, bool plane, hipStream_t st);
 int field_step2_occupancy(int tile_y, bool wide);
-hipError_t launch_field_step2_material(const BoardDev* boards, const TileRef* tiles, int ntiles,
-                                       int rel, int flip, bool wide, bool plane, hipStream_t st);
-int field_step2_material_occupancy(bool wide);
-int material_tile_y();
+hipError_t launch_field_step2_material(int tile_y, const BoardDev* boards, const TileRef* tiles,
+                                       int ntiles, int rel, int flip, bool wide, bool plane,
+                                       hipStream_t st);
+int field_step2_material_occupancy(int tile_y, bool wide);
+int material_tile_y(int tile_y);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
 hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int64_t plane_bytes,
@@ -163,6 +164,24 @@ struct fdtd_grid {
     TileRef* tiles1_dev = nullptr;  // one-step list for the odd step of a two-step shape
     int ntiles1 = 0;
     int tiles1_cap = 0;
+    // material boards: planes whose nodes need the material arithmetic (a
+    // conducting edge, or a PML node with a scaled 1/eps_rw), the tiles of the
+    // plain kernel's grid that hold such nodes per plane, and the list of plain
+    // two-step pieces (64 x kHybridTY x 2) clear of them, which the plain kernel
+    // steps with the same bits
+    std::vector<uint8_t> mat_plane;
+    std::vector<uint8_t> tile_need;  // per tile of the hybrid grid and node plane
+    TileRef* tilesP_dev = nullptr;
+    int ntilesP = 0;
+    int tilesP_cap = 0;
+    int mat_permille = 0;           // share of tile planes on the material variant
+    int mat_ty = kHybridTY;         // the material variant's tile rows (kHybridTY or kMatTY)
+    int mat_split = 0;              // 1: per tile, 2: per plane
+    // the material variant's launch runs beside the plain one on a second stream
+    // (forked from and joined to the handle's stream by events), so that each
+    // fills the other's last partial round
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int buf = 0;                    // field buffer (0/1) holding the current step
     int tiles_cap = 0;
     BoardDev board_host{};
@@ -408,10 +427,10 @@ void board_tiles(int b, int nx, int ny, int nz, int tx, int rows, std::vector<Ti
         for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz});
 }
 
-int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide)
+int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide, bool mat)
 {
-    const int occ = steps == 2 ? (g->mat ? field_step2_material_occupancy(wide)
-                                         : field_step2_occupancy(ty, wide))
+    const int occ = steps == 2 ? (mat ? field_step2_material_occupancy(ty, wide)
+                                      : field_step2_occupancy(ty, wide))
                                : field_step_occupancy(tx, ty, wide);
     return std::max(1, g->cus / kXcds) * occ;
 }
@@ -605,7 +624,15 @@ int finalize(fdtd_grid* g)
                in_slab(k, nz, d.npml[4], d.npml[5]);
     };
     g->node_pass = g->big;
-    for (int k = 0; k <= nz; ++k)
+    // material boards: the nodes that need the material arithmetic, one node
+    // plane at a time; every tile of the hybrid grid (64 x kHybridTY x 2) whose
+    // footprint holds one is marked for that plane
+    std::vector<uint8_t> mat_plane((size_t)nz + 1, 0), need((size_t)(nx + 1) * (ny + 1), 0);
+    int hcx = 0, hcy = 0;
+    tile_counts(nx, ny, 64, owned_rows(kHybridTY, 2), &hcx, &hcy);
+    std::vector<uint8_t> tile_need;
+    std::vector<int32_t> pre;
+    for (int k = 0; k <= nz; ++k) {
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
                 const int64_t n = node_index(g, i, j, k);
@@ -678,6 +705,14 @@ int finalize(fdtd_grid* g)
                 if (g->pml_eps_rw && (((fl & kUpdEx) && ix != 1.f) || ((fl & kUpdEy) && iy != 1.f) ||
                                       ((fl & kUpdEz) && iz != 1.f)))
                     fl |= kMatE;
+                // the material variant rebuilds only PML nodes' coefficients and
+                // solves conducting edges; every other node is the plain kernel's
+                const bool node_pml = in_slab(i, nx, d.npml[0], d.npml[1]) ||
+                                      in_slab(j, ny, d.npml[2], d.npml[3]) ||
+                                      in_slab(k, nz, d.npml[4], d.npml[5]);
+                const bool needs = (fl & kCondE) || ((fl & (kMatH | kMatE)) && node_pml);
+                need[(size_t)j * (nx + 1) + i] = needs;
+                if (needs) mat_plane[k] = 1;
                 const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz),
                                    fbits(lx), fbits(ly), fbits(lz)};
                 uint32_t id;
@@ -702,8 +737,35 @@ int finalize(fdtd_grid* g)
                 }
                 ids[(size_t)dev_index(g, i, j, k)] = (uint16_t)id;
             }
+        if (!mat_plane[k]) continue;
+        // 2-D prefix sums of the plane's marks; a tile's footprint is the nodes
+        // its block computes or reads: columns i0-2 .. i0+65, rows j0-2 .. j0+TY-1
+        if (tile_need.empty()) {
+            tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
+            pre.assign((size_t)(nx + 2) * (ny + 2), 0);
+        }
+        const int px = nx + 2;
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i)
+                pre[(size_t)(j + 1) * px + i + 1] = need[(size_t)j * (nx + 1) + i] +
+                                                    pre[(size_t)j * px + i + 1] +
+                                                    pre[(size_t)(j + 1) * px + i] -
+                                                    pre[(size_t)j * px + i];
+        for (int y = 0; y < hcy; ++y)
+            for (int x = 0; x < hcx; ++x) {
+                const int j0 = y * owned_rows(kHybridTY, 2), i0 = 64 * x;
+                const int ja = std::max(0, j0 - 2), jb = std::min(ny, j0 + kHybridTY - 1);
+                const int ia = std::max(0, i0 - 2), ib = std::min(nx, i0 + 65);
+                const int64_t sum = (int64_t)pre[(size_t)(jb + 1) * px + ib + 1] -
+                                    pre[(size_t)ja * px + ib + 1] - pre[(size_t)(jb + 1) * px + ia] +
+                                    pre[(size_t)ja * px + ia];
+                if (sum > 0) tile_need[((size_t)y * hcx + x) * (nz + 1) + k] = 1;
+            }
+    }
     g->n_classes = (int)table.size();
     g->wide = table.size() > 256;
+    g->mat_plane.swap(mat_plane);
+    g->tile_need.swap(tile_need);
     hipStream_t st = g->stream;
     if (g->wide) {
         g->cls = dev_alloc(g, (size_t)NC * 2);
@@ -1188,11 +1250,41 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf)
 
 // Work list of the handle's board for a shape, in device memory (reallocated when
 // it grows).
+static int upload_work(fdtd_grid* g, const std::vector<TileRef>& tl, TileRef** dev, int* n, int* cap)
+{
+    if (tl.empty()) {
+        *n = 0;
+        return FDTD_OK;
+    }
+    const int nt = (int)tl.size();
+    if (nt > *cap) {
+        *dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
+        if (!*dev) return fail(FDTD_ENOMEM, "tile list allocation failed");
+        *cap = nt;
+    }
+    HIP_OR_FAIL(copy_sync(g, *dev, tl.data(), tl.size() * sizeof(TileRef), hipMemcpyHostToDevice));
+    *n = nt;
+    return FDTD_OK;
+}
+
+// Work list of given two-step pieces of the handle's board (64 x ty tiles).
+static int upload_pieces(fdtd_grid* g, int ty, const std::vector<TileRef>& pieces, bool mat,
+                         TileRef** dev, int* n, int* cap)
+{
+    std::vector<TileRef> tl;
+    build_work(pieces, slots_per_xcd(g, 64, ty, 2, g->wide, mat), tl);
+    return upload_work(g, tl, dev, n, cap);
+}
+
 static int upload_list(fdtd_grid* g, int tx, int ty, int steps, TileRef** dev, int* n, int* cap)
 {
     std::vector<TileRef> whole, tl;
     board_tiles(0, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, steps), whole);
-    build_work(whole, slots_per_xcd(g, tx, ty, steps, g->wide), tl);
+    build_work(whole, slots_per_xcd(g, tx, ty, steps, g->wide, g->mat), tl);
+    if (tl.empty()) {
+        *n = 0;
+        return FDTD_OK;
+    }
     const int nt = (int)tl.size();
     if (nt > *cap) {
         *dev = (TileRef*)dev_alloc(g, tl.size() * sizeof(TileRef));
@@ -1208,21 +1300,108 @@ static int upload_tiles(fdtd_grid* g)
 {
     BoardDev& b = g->board_host;
     if (g->node_pass) {
-        // a material board takes pairs of steps on the material two-step kernel
-        // (its one shape) when a two-step shape is set, the default; with a
-        // one-step shape, and on boards past the tiled kernels' offset window,
-        // every step runs the node passes
+        // a material board takes pairs of steps on two-step kernels of one shape,
+        // 64 x kHybridTY x 2 (the plain kernel and its material variant), when a
+        // two-step shape is set, the default; with a one-step shape, and on
+        // boards past the tiled kernels' offset window, every step runs the
+        // node passes
         g->mat = !g->big && g->tile_steps == 2;
         if (g->mat) {
             g->tile_x = 64;
-            g->tile_y = material_tile_y();
+            g->tile_y = kHybridTY;
         }
     }
     tile_counts(g->d.nx, g->d.ny, g->tile_x, owned_rows(g->tile_y, g->tile_steps), &b.tiles_x,
                 &b.tiles_y);
-    if (int e = upload_list(g, g->tile_x, g->tile_y, g->tile_steps, &g->tiles_dev, &g->ntiles,
-                            &g->tiles_cap))
+    g->ntilesP = 0;
+    g->mat_permille = 0;
+    if (g->mat) {
+        // Tile planes near nodes that need the material arithmetic run the
+        // material variant, the rest the plain kernel (64 x kHybridTY x 2).  A
+        // piece [kb, ke) computes first-step H and E on planes kb-2 .. ke, so a
+        // tile's plane k is clear when no node of its footprint needs it on
+        // planes k-2 .. k+1.  Two ways to split, the cheaper by the measured cost
+        // of a tile plane on each kernel (large board, per step: plain 64 x 14
+        // 0.615 ms, material 64 x 14 1.00 ms, material 64 x 10 0.82 ms):
+        //  * per tile: each tile's unclear planes on the material variant of the
+        //    plain kernel's shape (which spills at 128 VGPRs), its clear planes
+        //    on the plain kernel: best when few tiles touch such nodes (a board
+        //    running into the PML with eps_rw);
+        //  * per plane: planes unclear in any tile on the 64 x kMatTY material
+        //    variant for every tile, the rest on the plain kernel: best when the
+        //    nodes fill those planes (a lossy layer).
+        // Both read one field copy and write the other, each its own pieces'
+        // nodes, and give the node passes' bits.
+        const int nz = g->d.nz;
+        int cx, cy;
+        tile_counts(g->d.nx, g->d.ny, 64, owned_rows(kHybridTY, 2), &cx, &cy);
+        std::vector<TileRef> tile_mat, tile_plain;
+        std::vector<uint8_t> dirty((size_t)nz), any((size_t)nz, 0);
+        int64_t mat_tp = 0;
+        for (int y = 0; y < cy; ++y)
+            for (int x = 0; x < cx; ++x) {
+                const uint8_t* tn =
+                    g->tile_need.empty() ? nullptr : &g->tile_need[((size_t)y * cx + x) * (nz + 1)];
+                for (int k = 0; k < nz; ++k) {
+                    dirty[k] = 0;
+                    for (int q = std::max(0, k - 2); tn && q <= std::min(nz, k + 1) && !dirty[k]; ++q)
+                        dirty[k] = tn[q];
+                    any[k] |= dirty[k];
+                }
+                for (int k = 0; k < nz;) {
+                    int e = k;
+                    while (e < nz && dirty[e] == dirty[k]) ++e;
+                    (dirty[k] ? tile_mat : tile_plain).push_back(TileRef{0, x, y, k, e});
+                    if (dirty[k]) mat_tp += e - k;
+                    k = e;
+                }
+            }
+        const double all = std::max<double>(1.0, (double)cx * cy * nz);
+        int64_t any_planes = 0;
+        for (int k = 0; k < nz; ++k) any_planes += any[k];
+        const double f_tile = mat_tp / all, f_plane = any_planes / (double)nz;
+        const double cost_tile = (1.0 - f_tile) * 0.615 + f_tile * 1.00;
+        const double cost_plane = (1.0 - f_plane) * 0.615 + f_plane * 0.82;
+        std::vector<TileRef> mat_pieces, plain_pieces;
+        if (cost_tile <= cost_plane) {
+            g->mat_ty = kHybridTY;
+            g->mat_split = 1;
+            g->mat_permille = (int)(1000.0 * f_tile);
+            mat_pieces.swap(tile_mat);
+            plain_pieces.swap(tile_plain);
+        } else {
+            g->mat_ty = kMatTY;
+            g->mat_split = 2;
+            g->mat_permille = (int)(1000.0 * f_plane);
+            std::vector<TileRef> mt, pt;
+            board_tiles(0, g->d.nx, g->d.ny, nz, 64, owned_rows(kMatTY, 2), mt);
+            board_tiles(0, g->d.nx, g->d.ny, nz, 64, owned_rows(kHybridTY, 2), pt);
+            for (int k = 0; k < nz;) {
+                int e = k;
+                while (e < nz && any[e] == any[k]) ++e;
+                for (TileRef t : any[k] ? mt : pt) {
+                    t.kb = k;
+                    t.ke = e;
+                    (any[k] ? mat_pieces : plain_pieces).push_back(t);
+                }
+                k = e;
+            }
+        }
+        if (int e = upload_pieces(g, g->mat_ty, mat_pieces, true, &g->tiles_dev, &g->ntiles,
+                                  &g->tiles_cap))
+            return e;
+        if (int e = upload_pieces(g, kHybridTY, plain_pieces, false, &g->tilesP_dev, &g->ntilesP,
+                                  &g->tilesP_cap))
+            return e;
+        if (g->ntilesP > 0 && g->ntiles > 0 && !g->aux_stream) {
+            HIP_OR_FAIL(hipStreamCreateWithFlags(&g->aux_stream, hipStreamNonBlocking));
+            HIP_OR_FAIL(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming));
+            HIP_OR_FAIL(hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming));
+        }
+    } else if (int e = upload_list(g, g->tile_x, g->tile_y, g->tile_steps, &g->tiles_dev, &g->ntiles,
+                                   &g->tiles_cap)) {
         return e;
+    }
     if (g->tile_steps == 2 && !g->node_pass)
         if (int e = upload_list(g, kOddX, kOddY, 1, &g->tiles1_dev, &g->ntiles1, &g->tiles1_cap))
             return e;
@@ -1279,11 +1458,31 @@ static hipError_t node_step(fdtd_grid* g, int rel, int flip, hipStream_t st)
                            g->big, rel, flip, g->wide, st);
 }
 
-// One launch of the material two-step kernel.
+// A pair of steps of a material board: the plain two-step kernel over the z runs
+// clear of material nodes, the material variant over the rest.
 static hipError_t material_pair(fdtd_grid* g, int rel, int flip, hipStream_t st)
 {
-    return launch_field_step2_material(g->board_dev, g->tiles_dev, g->ntiles, rel, flip, g->wide,
-                                       g->plane_k >= 0, st);
+    if (g->ntilesP > 0 && g->ntiles > 0 && g->aux_stream) {
+        hipError_t e = hipEventRecord(g->fork_ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(g->aux_stream, g->fork_ev, 0);
+        if (e == hipSuccess)
+            e = launch_field_step2_material(g->mat_ty, g->board_dev, g->tiles_dev, g->ntiles, rel,
+                                            flip, g->wide, g->plane_k >= 0, g->aux_stream);
+        if (e == hipSuccess)
+            e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel, flip,
+                                   g->wide, g->plane_k >= 0, st);
+        if (e == hipSuccess) e = hipEventRecord(g->join_ev, g->aux_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, g->join_ev, 0);
+        return e;
+    }
+    if (g->ntilesP > 0) {
+        const hipError_t e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel,
+                                                flip, g->wide, g->plane_k >= 0, st);
+        if (e != hipSuccess) return e;
+    }
+    if (g->ntiles == 0) return hipSuccess;
+    return launch_field_step2_material(g->mat_ty, g->board_dev, g->tiles_dev, g->ntiles, rel, flip,
+                                       g->wide, g->plane_k >= 0, st);
 }
 
 // One field launch of the handle's shape (two steps, or one with the odd-step
@@ -1429,6 +1628,13 @@ struct Span {
     int64_t s0, s1;
     int off, count;   // into the round's tile list
     bool tail;
+    bool mat;         // material boards (the material variant)
+};
+
+// A material board's odd last step of a round, on the node passes.
+struct NodeTail {
+    int h;            // handle (call order)
+    int rel, flip;    // after the board's pairs of the round
 };
 
 // One round: every handle advances by n[h] steps (at most kPlaneRing when some
@@ -1440,6 +1646,7 @@ struct RoundHost {
     std::vector<int64_t> adv;       // per board: steps, launches (field-buffer flips)
     std::vector<Span> spans;
     std::vector<TileRef> items;
+    std::vector<NodeTail> node_tails;
 };
 
 }  // namespace
@@ -1464,14 +1671,17 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
 {
     fdtd_grid* lead = gs[0];
     const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
+    const int mty = material_tile_y(per == 2 ? ty : kMatTY);   // material boards' shape
     r.n.assign(n, n + ng);
     // order boards by step count (descending): at pass s the boards still running
-    // form a prefix, and so do their tiles; narrow and wide class maps go to
-    // separate launches (the kernel is specialised on the class index width)
+    // form a prefix, and so do their tiles; narrow and wide class maps, and
+    // material boards, go to separate launches (the kernel is specialised on
+    // the class index width and on the material arithmetic)
     r.order.resize(ng);
     for (int h = 0; h < ng; ++h) r.order[h] = h;
+    auto group = [&](int h) { return 2 * (int)gs[h]->mat + (int)gs[h]->wide; };
     std::stable_sort(r.order.begin(), r.order.end(), [&](int a, int b) {
-        if (gs[a]->wide != gs[b]->wide) return gs[a]->wide < gs[b]->wide;
+        if (group(a) != group(b)) return group(a) < group(b);
         return n[a] > n[b];
     });
     // board b runs np[b] passes of `per` steps, then (two-step shapes) one single
@@ -1483,28 +1693,35 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
     int64_t max_np = 0;
     for (int b = 0; b < ng; ++b) {
         const int64_t nb = n[r.order[b]];
-        np[b] = nb / per;
-        odd[b] = nb - np[b] * per;
+        const int pb = gs[r.order[b]]->mat ? 2 : per;
+        np[b] = nb / pb;
+        odd[b] = nb - np[b] * pb;
         max_np = std::max(max_np, np[b]);
         r.boards[b] = gs[r.order[b]]->board_host;
         r.boards[ng + b] = r.boards[b];
-        r.boards[ng + b].rel0 = (int32_t)(np[b] * per);
+        r.boards[ng + b].rel0 = (int32_t)(np[b] * pb);
         r.boards[ng + b].flip0 = (int32_t)(np[b] & 1);
         r.adv[2 * b] = nb;
         r.adv[2 * b + 1] = np[b] + odd[b];
     }
-    // Each class width forms a group [b0, b1) of the order; at pass s the boards
-    // still running are a prefix [b0, active) of it.  One balanced work list per
-    // distinct prefix, plus one for the single-step tail, all in one buffer.
+    // Each group (class width, material or not) is a range [b0, b1) of the
+    // order; at pass s the boards still running are a prefix [b0, active) of it.
+    // One balanced work list per distinct prefix, plus one for the single-step
+    // tail, all in one buffer; a material board's single step runs the node
+    // passes on its own.
     r.spans.clear();
     r.items.clear();
+    r.node_tails.clear();
     std::vector<TileRef> whole, list;
-    for (int w = 0; w < 2; ++w) {
+    for (int grp = 0; grp < 4; ++grp) {
+        const int w = grp & 1;
+        const bool mat = grp >= 2;
+        const int gtx = mat ? 64 : tx, gty = mat ? mty : ty, gper = mat ? 2 : per;
         int b0 = 0;
-        while (b0 < ng && gs[r.order[b0]]->wide != (w == 1)) ++b0;
+        while (b0 < ng && group(r.order[b0]) != grp) ++b0;
         if (b0 == ng) continue;
         int b1 = b0;
-        while (b1 < ng && gs[r.order[b1]]->wide == (w == 1)) ++b1;
+        while (b1 < ng && group(r.order[b1]) == grp) ++b1;
         int64_t s = 0;
         for (int active = b1; active > b0 && s < max_np;) {
             const int64_t s_end = np[active - 1];  // boards [b0, active) all run through s_end
@@ -1512,14 +1729,21 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
                 whole.clear();
                 for (int b = b0; b < active; ++b) {
                     const fdtd_grid* g = gs[r.order[b]];
-                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, per), whole);
+                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, gtx, owned_rows(gty, gper), whole);
                 }
-                build_work(whole, slots_per_xcd(lead, tx, ty, per, w == 1), list);
-                r.spans.push_back(Span{w, per, s, s_end, (int)r.items.size(), (int)list.size(), false});
+                build_work(whole, slots_per_xcd(lead, gtx, gty, gper, w == 1, mat), list);
+                r.spans.push_back(
+                    Span{w, gper, s, s_end, (int)r.items.size(), (int)list.size(), false, mat});
                 r.items.insert(r.items.end(), list.begin(), list.end());
                 s = s_end;
             }
             --active;
+        }
+        if (mat) {
+            for (int b = b0; b < b1; ++b)
+                if (odd[b])
+                    r.node_tails.push_back(NodeTail{r.order[b], (int)(np[b] * 2), (int)(np[b] & 1)});
+            continue;
         }
         whole.clear();
         for (int b = b0; b < b1; ++b)
@@ -1528,8 +1752,8 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
                 board_tiles(b, g->d.nx, g->d.ny, g->d.nz, kOddX, owned_rows(kOddY, 1), whole);
             }
         if (!whole.empty()) {
-            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1), list);
-            r.spans.push_back(Span{w, 1, 0, 1, (int)r.items.size(), (int)list.size(), true});
+            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1, false), list);
+            r.spans.push_back(Span{w, 1, 0, 1, (int)r.items.size(), (int)list.size(), true, false});
             r.items.insert(r.items.end(), list.begin(), list.end());
         }
     }
@@ -1560,6 +1784,7 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
 {
     const fdtd_grid* lead = gs[0];
     const int tx = lead->tile_x, ty = lead->tile_y;
+    const int mty = material_tile_y(lead->tile_steps == 2 ? ty : kMatTY);
     const bool planes = any_plane(gs, ng);
     for (size_t q = 0; q < P.rounds.size(); ++q) {
         const RoundHost& R = P.rounds[q];
@@ -1573,9 +1798,15 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
                 continue;
             }
             for (int64_t k = sp.s0; k < sp.s1; ++k)
-                HIP_OR_FAIL(launch_pass(tx, ty, sp.steps, db, dt + sp.off, sp.count,
-                                        (int)(k * sp.steps), (int)(k & 1), sp.w == 1, planes, st));
+                HIP_OR_FAIL(sp.mat ? launch_field_step2_material(mty, db, dt + sp.off, sp.count,
+                                                                 (int)(k * 2), (int)(k & 1),
+                                                                 sp.w == 1, planes, st)
+                                   : launch_pass(tx, ty, sp.steps, db, dt + sp.off, sp.count,
+                                                 (int)(k * sp.steps), (int)(k & 1), sp.w == 1,
+                                                 planes, st));
         }
+        for (const NodeTail& t : R.node_tails)
+            HIP_OR_FAIL(node_step(gs[t.h], t.rel, t.flip, st));
         HIP_OR_FAIL(launch_advance((BoardDev*)db, ng, dn, st));
         for (int h = 0; h < ng; ++h)
             if (R.n[h] > 0)
@@ -1720,12 +1951,13 @@ int fdtd_step_many(fdtd_grid* const* gs, int ng, const int64_t* n)
     }
     for (int h = 0; h < ng; ++h)
         if (int e = finalize(gs[h])) return e;
-    // boards on the node passes step alone (on their own streams); the rest
-    // share the batched launches
+    // boards whose every step runs the node passes (past the tiled kernels'
+    // offset window, or a one-step shape set) step alone on their own streams;
+    // the rest, material boards included, share the batched launches
     std::vector<fdtd_grid*> fused;
     std::vector<int64_t> nfused;
     for (int h = 0; h < ng; ++h) {
-        if (gs[h]->node_pass) {
+        if (gs[h]->node_pass && !gs[h]->mat) {
             if (int e = fdtd_step_n(gs[h], n[h])) return e;
         } else {
             fused.push_back(gs[h]);
@@ -2165,6 +2397,8 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->plane_nf = (int32_t)g->plane_freqs.size();
     out->node_passes = g->node_pass ? 1 : 0;
     out->material_two_step = g->mat ? 1 : 0;
+    out->material_permille = g->mat ? g->mat_permille : 0;
+    out->material_split = g->mat ? g->mat_split : 0;
     out->batch_plans = (int32_t)g->plans.size();
     out->batch_graphs = 0;
     for (const BatchPlan* p : g->plans) out->batch_graphs += p->exec != nullptr;
@@ -2207,7 +2441,11 @@ int fdtd_destroy_grid(fdtd_grid* g)
     for (BatchPlan* p : g->retired) free_plan(g, p);
     g->plans.clear();
     g->retired.clear();
+    if (g->aux_stream) (void)hipStreamSynchronize(g->aux_stream);
     dev_free_all(g);
+    if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+    if (g->join_ev) (void)hipEventDestroy(g->join_ev);
+    if (g->aux_stream) (void)hipStreamDestroy(g->aux_stream);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
     return FDTD_OK;

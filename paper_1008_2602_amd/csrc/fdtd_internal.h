@@ -36,8 +36,11 @@ static_assert(kGraphChunk == kPlaneRing, "a graph chunk fills the ring exactly o
 // ping-pong buffers (32 B per point, 32 MiB) sit in a fixed device array
 constexpr int kNoAllocFftMax = 1 << 20;
 
-// tile rows of the two-step kernel's material variant (64 x kMatTY x 2)
+// tile rows of the two-step kernel's material variant (64 x kMatTY x 2), and of
+// the plain two-step pieces that step a material board's planes clear of
+// material nodes (64 x kHybridTY x 2)
 constexpr int kMatTY = 10;
+constexpr int kHybridTY = 14;
 
 // zero words allocated past the last node of every field array
 constexpr int64_t kGuard = 64;

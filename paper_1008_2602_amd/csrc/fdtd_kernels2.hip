@@ -776,28 +776,50 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
     }
 }
 
-// The material variant (Eq. 2's eps_rw in a dielectric PML, conduction): one
-// shape, 64 x kMatTY x 2, whose three waves per SIMD leave the registers the
-// rebuilt coefficients need.
-int material_tile_y() { return kMatTY; }
+// The material variant (Eq. 2's eps_rw in a dielectric PML, conduction), in two
+// shapes.  64 x kHybridTY x 2 shares the plain kernel's tiles on a material
+// board (which runs each tile's planes near material nodes on it and the rest
+// on the plain kernel); at 128 VGPRs it spills about 15 values.  64 x kMatTY x 2,
+// whose three waves per SIMD leave it the registers it needs, runs material
+// boards in batched calls, where it takes every plane.
+int material_tile_y(int) { return kMatTY; }
 
-int field_step2_material_occupancy(bool wide)
+template <int TY>
+static int mat_occupancy(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<kMatTY, uint16_t, false, true>, 64 * kMatTY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, true>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<kMatTY, uint8_t, false, true>, 64 * kMatTY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, true>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-hipError_t launch_field_step2_material(const BoardDev* boards, const TileRef* tiles, int ntiles,
-                                       int rel, int flip, bool wide, bool plane, hipStream_t st)
+int field_step2_material_occupancy(int tile_y, bool wide)
+{
+    return tile_y == kHybridTY ? mat_occupancy<kHybridTY>(wide) : mat_occupancy<kMatTY>(wide);
+}
+
+template <int TY>
+static void mat_launch(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
+                       bool wide, bool plane, hipStream_t st)
 {
     if (plane)
-        launch2_tp<kMatTY, true, true>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, true>(boards, tiles, ntiles, rel, flip, wide, st);
     else
-        launch2_tp<kMatTY, false, true>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, true>(boards, tiles, ntiles, rel, flip, wide, st);
+}
+
+hipError_t launch_field_step2_material(int tile_y, const BoardDev* boards, const TileRef* tiles,
+                                       int ntiles, int rel, int flip, bool wide, bool plane,
+                                       hipStream_t st)
+{
+    if (tile_y == kHybridTY)
+        mat_launch<kHybridTY>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+    else if (tile_y == kMatTY)
+        mat_launch<kMatTY>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

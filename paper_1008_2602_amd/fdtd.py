@@ -64,6 +64,8 @@ class fdtd_info(C.Structure):
                 ("n_classes", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("tile_steps", C.c_int32), ("plane_k", C.c_int32), ("plane_nf", C.c_int32),
                 ("node_passes", C.c_int32), ("material_two_step", C.c_int32),
+                ("material_permille", C.c_int32),
+                ("material_split", C.c_int32),
                 ("batch_plans", C.c_int32), ("batch_graphs", C.c_int32)]
 
 

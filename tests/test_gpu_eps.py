@@ -74,6 +74,7 @@ def two_step_equals_node_passes(F, b, init):
     assert (info.tile_x, info.tile_steps) == (64, 2)
     for n in FIELDS:
         assert np.array_equal(fields[n], fields1[n]), n
+    two_step_equals_node_passes.info = info
     return fields
 
 

@@ -273,3 +273,135 @@ def test_sheet_argument_errors(F):
         assert ei.value.code == F.FDTD_ESTATE
     finally:
         F.fdtd_destroy_grid(g)
+
+
+def test_material_boards_batched_bitwise(F):
+    """Material boards join fdtd_step_many: an eps_rw board (with a plane DFT), a
+    lossy board with a resistive sheet and one with per-cell eps_r as well
+    (more than 256 classes) beside two plain boards, uneven step counts (odd
+    ones end on the node passes), in two calls; every array, probe series and
+    plane DFT bitwise equal to the board stepped alone, and the second call
+    replays the first call's plan (one graph)."""
+    from test_gpu_eps import eps_board
+    wide = sheet_board(6, steps=60)
+    rng = np.random.default_rng(21)
+    wide.eps_r_cell[:] = rng.choice([1.0, 2.2, 3.3, 4.4], size=wide.eps_r_cell.shape).astype(np.float32)
+    wide.pml_eps_rw = True
+    boards = [boardgen.random_tiny(4, nx=40, ny=20, nz=10, npml=2, steps=60), eps_board(3, steps=60),
+              sheet_board(5, steps=60), wide, boardgen.random_tiny(7, nx=33, ny=25, nz=9, npml=3, steps=60)]
+    call = [17, 21, 9, 16, 20]
+    totals = [2 * n for n in call]
+    alone = [run(F, dataclasses.replace(b, steps=t)) for b, t in zip(boards, totals)]
+    hs = [F.grid_from_board(b, max_steps=60) for b in boards]
+    try:
+        for _ in range(2):
+            F.fdtd_step_many([g for g, _ in hs], call)
+        F.fdtd_synchronize(hs[0][0])
+        infos = [F.fdtd_get_info(g) for g, _ in hs]
+        assert [i.material_two_step for i in infos] == [0, 1, 1, 1, 0]
+        assert infos[3].n_classes > 256
+        assert infos[0].batch_plans == 1 and infos[0].batch_graphs == 1
+        for q, ((g, ids), b) in enumerate(zip(hs, boards)):
+            if ids:
+                probes = np.stack([F.fdtd_get_probe(g, p, totals[q]) for p in ids])
+                assert np.array_equal(probes, alone[q][1]), b.name
+            if b.plane_dft is not None:
+                assert np.array_equal(F.fdtd_get_plane_dft(g, b.ny, b.nx), alone[q][2]), b.name
+            fields = gpu_fields(F, g, b)
+            for n in FIELDS:
+                assert np.array_equal(fields[n], alone[q][3][n]), (b.name, n)
+    finally:
+        for g, _ in hs:
+            F.fdtd_destroy_grid(g)
+
+
+def slab_board(steps, lossy=True, nx=70, ny=40, nz=44):
+    """A board whose material sits in a few planes: an eps_r 4.2 slab (6 planes
+    from nz // 2 - 6) through the x/y PML with eps_rw on between two PEC sheets,
+    a resistive source and probes in it.  lossy: the slab is lossy inside the
+    PML's inner region and the sheets resistive, so every tile holds material
+    nodes near the slab (split per plane); else only tiles at the x/y PML do
+    (split per tile on a board this wide)."""
+    eps, mask = boardgen.air(nx, ny, nz)
+    k0 = nz // 2 - 6
+    eps[k0:k0 + 6] = 4.2
+    boardgen.pec_sheet(mask, k0, 6, nx - 7, 6, ny - 7)
+    boardgen.pec_sheet(mask, k0 + 6, 6, nx - 7, 6, ny - 7)
+    p = 4
+    b = boardgen.Board("slab", nx, ny, nz, 0.5e-3, 0.5e-3, 0.1e-3, eps, mask, npml=(p,) * 6,
+                       steps=steps, pml_eps_rw=True, sheet_R=0.02 if lossy else 0.0)
+    if lossy:
+        sig = np.zeros(eps.shape, np.float32)
+        sig[k0:k0 + 6, p:ny - p, p:nx - p] = 0.05
+        b.sigma_cell = sig
+    b.sources = [boardgen.Source(nx // 3, ny // 2, k0 + 2, boardgen.GAUSS, 2.0, 4e-12, 1.2e-12, R=20.0),
+                 boardgen.Source(2 * nx // 3, ny // 3, k0 + 4, boardgen.DGAUSS, 1e6, 5e-12, 1.5e-12)]
+    b.probes = [(nx // 3 + 4, ny // 2, k0 + 3), (2 * nx // 3 - 5, ny // 3 + 3, k0 + 1),
+                (nx // 3, ny // 2 + 6, k0 + 9)]
+    b.plane_dft = (k0 + 1, np.array([3e9, 20e9]))
+    return b
+
+
+@pytest.mark.parametrize("lossy,shape,split", [(True, (70, 40, 44), 2), (False, (512, 132, 30), 1)])
+def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, shape, split):
+    """The split of a material board's tile planes between the plain kernel and
+    its material variant (per plane on the lossy board, per tile on the wide
+    lossless one): from an arbitrary state, 5 steps (two pairs and an odd one)
+    give the node passes' bits and match the oracle; from zero, odd call splits,
+    timed launches, the node passes alone and a checkpoint give the same bits,
+    probes and the plane DFT against the oracle."""
+    nx, ny, nz = shape
+    b = slab_board(5, lossy, nx, ny, nz)
+    st = random_state(oracle_mod, b, seed=31)
+    if lossy:
+        for n, bit in (("ex", 1), ("ey", 2)):        # the sheets' edges are state too
+            on = (b.pec_edge_mask & bit) != 0
+            st[n][on] = np.random.default_rng(bit).standard_normal(int(on.sum()))
+    init = {n: st[n].copy() for n in FIELDS}
+    announce(f"slab board lossy={lossy} {shape}: random state")
+    ref = oracle_mod.run(b, state=st, threads=16)
+    fields = two_step_equals_node_passes(F, b, init)
+    info = two_step_equals_node_passes.info
+    assert 0 < info.material_permille < 1000, info.material_permille
+    assert info.material_split == split, info.material_split
+    compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
+
+    b = slab_board(71, lossy, nx, ny, nz)
+    announce(f"slab board lossy={lossy} {shape}: from zero")
+    ref = oracle_mod.run(b, threads=16)
+    out = run(F, b)
+    assert out[0].material_two_step == 1 and out[0].material_split == split
+    for other in (run(F, b, chunks=[7, 1, 33, 30]), run(F, b, timing=True), run(F, b, tile=NODE_ONLY)):
+        assert np.array_equal(other[1], out[1]) and np.array_equal(other[2], out[2])
+        for n in FIELDS:
+            assert np.array_equal(other[3][n], out[3][n]), n
+    reach = max(np.abs(x).max() for x in ref.probes)
+    for p in range(len(b.probes)):
+        if np.abs(ref.probes[p]).max() > 1e-3 * reach:      # probes the pulse has reached
+            assert rel_l2(out[1][p], ref.probes[p]) <= 1e-4, p
+    for f in range(2):
+        assert rel_l2(out[2][f], ref.plane_dft[f]) <= 1e-4, f
+    # from zero after 71 steps: the stated 1e-4, with denominators at least 1e-2
+    # of the whole E field's norm (in each array's units).  Between the nearly
+    # perfect sheets the field is TM-like and has no Hz or Bz of its own: they
+    # are residuals about 1e-3 of the other components (lossy board: Hz norm
+    # 0.028 against 39 A/m for Hx and Hy in the oracle, and 6e-5 against 15 in
+    # the slab's middle plane), so their own norms are no scale for FP32
+    # round-off (8e-7 A/m there, 5e-8 of the H field).  The floor binds only for
+    # such arrays.
+    rep = compare_fields(ref.state, out[3], b, 1e-4, floor_rel=1e-2)
+    for n, (whole, elem, reg, where) in rep.items():
+        print(f"{n}: whole {whole:.2e} element {elem:.2e} worst region {reg:.2e} ({where})")
+    g, _ = F.grid_from_board(b, max_steps=b.steps)
+    g2, _ = F.grid_from_board(b, max_steps=b.steps)
+    try:
+        F.fdtd_step_n(g, 37)
+        F.fdtd_load_state(g2, F.fdtd_save_state(g))
+        F.fdtd_step_n(g2, 34)
+        F.fdtd_synchronize(g2)
+        fields = gpu_fields(F, g2, b)
+        for n in FIELDS:
+            assert np.array_equal(fields[n], out[3][n]), n
+    finally:
+        F.fdtd_destroy_grid(g)
+        F.fdtd_destroy_grid(g2)
