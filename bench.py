@@ -240,16 +240,18 @@ def run_plane_dft(F, torch, K, W, plain_ms_per_step):
     }
 
 
-def run_eps(F, torch, K=200, W=10, large_only=False):
+def run_eps(F, torch, K=200, W=10, large_only=False, only=None):
     """Boards in the node passes' arithmetic (Eq. 2's eps_rw, lossy dielectrics,
     resistive sheets).  (1) The large board with its eps_r 4.2 slab run through
     the x/y PML to the outer wall (1048x792x88), eps_rw on: pairs of steps on the
-    material two-step kernel (the default), and every step on the node passes,
+    two-step kernels (the plain one and its material variant, the default), and
+    every step on the node passes,
     against the fused kernels on the same board with eps_rw = 1; (2) the large
     board with a lossy dielectric (loss tangent 0.02 at 5 GHz) and copper planes
     (resistive sheets, 18.4 milliohm per square); (3) the paper's Fig. 3 board
     (100x60x0.8 mm running into the UPML), 1000 steps of 1 ps; (4) the Table 1 run
-    with a lossy dielectric.  large_only: (1) and (2) alone."""
+    with a lossy dielectric.  large_only: (1) and (2) alone; only: the one case
+    of (1) and (2) so named (for a profiler run)."""
     import boardgen
     from paper_1008_2602_amd import tune
     b = boardgen.large_board(steps=W + K)
@@ -264,6 +266,8 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
              ("fused_eps_rw_1", b, "tune", -1),
              ("lossy_copper", lossy, None, 1))
     for name, bb, tile, mat in cases:
+        if only is not None and name != only:
+            continue
         if tile == "tune":
             tile = tune.tune_board(bb)
         g, _ = F.grid_from_board(bb, max_steps=W + K, tile=tile)
@@ -287,7 +291,7 @@ def run_eps(F, torch, K=200, W=10, large_only=False):
             # the survey's algorithmic bytes of a step of this board
             "hbm_frac_algorithmic": round(sec8d_step_bytes(info) * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         }
-    if large_only:
+    if large_only or only is not None:
         return out
     f3 = boardgen.fig3_board(steps=1000)
     g, _ = F.grid_from_board(f3, max_steps=f3.steps)
@@ -674,7 +678,8 @@ def main():
                     help="field-kernel shape tile_x x tile_y x steps per pass, e.g. 64x15x1 or "
                          "64x10x2 (default: autotuned)")
     ap.add_argument("--only", choices=["single", "batch", "serve", "table1", "plane", "zconv",
-                                       "eps", "eps_large", "shard", "realistic"], default=None)
+                                       "eps", "eps_large", "eps_rw", "lossy_copper", "shard",
+                                       "realistic"], default=None)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=8000)
@@ -788,8 +793,9 @@ def main():
             plain = wall0 / K * 1e3
         out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
         section("plane_dft")
-    if args.only in (None, "eps", "eps_large"):
-        out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large")
+    if args.only in (None, "eps", "eps_large", "eps_rw", "lossy_copper"):
+        out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large",
+                                     only=args.only if args.only in ("eps_rw", "lossy_copper") else None)
         section("node_passes")
     if args.only in (None, "zconv"):
         out["zconv"] = run_zconv(F, torch)
