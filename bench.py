@@ -625,6 +625,10 @@ def run_serve(F, torch, capacity_gcells, n_requests, steps):
     s = summarize(res, wall_s=wall)
     busy = ex.busy_fraction()
     ex.close()
+    large = {r.rid for r in requests if (r.board.nx, r.board.ny) == (800, 800)}
+    lat_large = np.array([r.latency_s for r in res if r.rid in large])
+    lat_var = np.array([r.latency_s for r in res if r.rid not in large])
+    wait = np.array([r.wait_s for r in res])
     out = {
         "workload": f"{n_requests} seeded Poisson arrivals at {rate:.3f}/s (0.7x the measured "
                     f"batched capacity for the stream's mean board of {mean_cells / 1e6:.2f} M "
@@ -636,10 +640,17 @@ def run_serve(F, torch, capacity_gcells, n_requests, steps):
         "solves_per_s": round(s["solves_per_s"], 4),
         "gcell_updates_per_s": round(s["gcell_updates_per_s"], 3),
         "requests": n_requests,
-        "large_boards": sum(1 for r in requests if (r.board.nx, r.board.ny) == (800, 800)),
+        "large_boards": len(large),
         "latency_samples": s["completed"],
         "completed": s["completed"],
         "gpu_busy_frac": round(busy, 4) if busy is not None else None,
+        # the two kinds of solve apart (arrival to result), and the wait for
+        # admission (arrival to the first chunk that holds the solve)
+        "variant_p50_p99_latency_s": [round(float(np.percentile(lat_var, q)), 4) for q in (50, 99)]
+                                     if lat_var.size else None,
+        "large_p50_max_latency_s": [round(float(np.percentile(lat_large, 50)), 4),
+                                    round(float(lat_large.max()), 4)] if lat_large.size else None,
+        "wait_p50_p99_s": [round(float(np.percentile(wait, q)), 4) for q in (50, 99)],
         "chunks": srv.chunks,
         "tile": "x".join(str(v) for v in tile),
         "peak_resident": srv.peak_resident,
