@@ -569,6 +569,41 @@ def table1_cpu(board):
             "sample": f"the whole {board.steps}-step run ({dt:.1f} s; FP64)"}
 
 
+def oracle_full_realistic(F, torch, chunk=1000):
+    """The oracle's whole run of the realistic board (444x364x60 cells, 20000
+    steps, 16 probes) on all host threads, in chunks that carry the state and the
+    DFT accumulators over (progress on stderr), timed; then the GPU's plain solve
+    of the same board, whose probe series are compared with it (largest relative
+    L2 over the probes)."""
+    import numpy as np
+    import boardgen
+    import oracle
+    from paper_1008_2602_amd import tune
+    b = boardgen.realistic_board()
+    st, dft, series = oracle.new_state(b), None, []
+    t0 = time.perf_counter()
+    for s0 in range(0, b.steps, chunk):
+        r = oracle.run(b, nsteps=min(chunk, b.steps - s0), state=st, dft=dft, threads=None)
+        st, dft = r.state, r.dft
+        series.append(r.probes)
+        print(f"[oracle] {s0 + r.probes.shape[1]} of {b.steps} steps at "
+              f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    cpu_s = time.perf_counter() - t0
+    ref = np.concatenate(series, axis=1)
+    g, ids = F.grid_from_board(b, max_steps=b.steps, tile=tune.tune_board(b))
+    try:
+        F.fdtd_step_n(g, b.steps)
+        got = np.stack([F.fdtd_get_probe(g, p, b.steps) for p in ids]).astype(np.float64)
+    finally:
+        F.fdtd_destroy_grid(g)
+    errs = [float(np.linalg.norm(got[p] - ref[p]) / np.linalg.norm(ref[p])) for p in range(len(ids))]
+    return {"workload": f"realistic board {b.nx}x{b.ny}x{b.nz} cells, {b.steps} steps, "
+                        f"{len(ids)} probes: the oracle's whole run",
+            "value": round(b.cells * b.steps / cpu_s / 1e9, 4), "unit": "Gcell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle", "wall_s": round(cpu_s, 1),
+            "gpu_max_probe_rel_l2": float(f"{max(errs):.3g}")}
+
+
 def sampled_cpu(board, budget_s=15.0):
     """The oracle on a bounded sample of a board's steps (all host threads), with
     the whole run's time extrapolated from it."""
@@ -696,6 +731,9 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="time the oracle's whole realistic-board run (several minutes) "
+                         "and compare the GPU's probes with it; prints that alone")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -712,6 +750,9 @@ def main():
         return
 
     from paper_1008_2602_amd import fdtd as F
+    if args.oracle_full:
+        print(json.dumps({"oracle_full_run": oracle_full_realistic(F, torch)}), flush=True)
+        return
 
     K, W = int(args.steps), int(args.warmup)
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
