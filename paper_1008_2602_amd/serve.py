@@ -216,11 +216,16 @@ class GpuExecutor:
             time.sleep(d)
 
 
+def _cells(req: SolveRequest) -> int:
+    b = req.board
+    return b.nx * b.ny * b.nz
+
+
 class Server:
     def __init__(self, executor, budget_bytes: int, chunk: int = 500,
                  max_resident: Optional[int] = None, max_bypass_s: float = 5.0,
                  log: Optional[Callable[[dict], None]] = None, workers: int = 0,
-                 depth: int = 2):
+                 depth: int = 2, solo_cells: Optional[int] = None):
         if budget_bytes <= 0 or chunk <= 0:
             raise ValueError("budget and chunk must be positive")
         self.ex = executor
@@ -231,10 +236,23 @@ class Server:
         self.log = log
         self.workers = int(workers)
         self.depth = max(1, int(depth))
+        # boards of at least solo_cells cells run their chunks without the
+        # smaller resident boards (which wait, resident, until none is left):
+        # a large solve then runs at about its own rate instead of pacing, and
+        # being paced by, every chunk it shares; None: every chunk holds every
+        # resident board
+        self.solo_cells = solo_cells
         self.chunks = 0
         self.peak_bytes = 0
         self.peak_resident = 0
         self.rejected: List[int] = []
+
+    def _chunk_boards(self, resident: List["_Resident"]) -> List["_Resident"]:
+        """The resident boards the next chunk advances."""
+        if self.solo_cells is None:
+            return resident
+        solo = [e for e in resident if _cells(e.req) >= self.solo_cells]
+        return solo or resident
 
     def run(self, requests: Sequence[SolveRequest]) -> List[SolveResult]:
         if self.workers > 0 and hasattr(self.ex, "step_async"):
@@ -286,10 +304,11 @@ class Server:
                 if waiting:
                     raise RuntimeError("a waiting request can never be admitted")
                 break
-            ns = [min(self.chunk, e.req.n_steps - e.done) for e in resident]
-            ex.step([e.handle for e in resident], ns)
+            batch = self._chunk_boards(resident)
+            ns = [min(self.chunk, e.req.n_steps - e.done) for e in batch]
+            ex.step([e.handle for e in batch], ns)
             self.chunks += 1
-            for e, n in zip(resident, ns):
+            for e, n in zip(batch, ns):
                 e.done += n
             fin_t = ex.now() - t0
             still = []
@@ -380,14 +399,14 @@ class Server:
                 self.peak_bytes = max(self.peak_bytes, used)
                 self.peak_resident = max(self.peak_resident, len(resident))
                 if resident and len(inflight) < self.depth:
-                    ns = [min(self.chunk, e.req.n_steps - e.done) for e in resident]
-                    token = ex.step_async([e.handle for e in resident], ns)
+                    batch = self._chunk_boards(resident)
+                    ns = [min(self.chunk, e.req.n_steps - e.done) for e in batch]
+                    token = ex.step_async([e.handle for e in batch], ns)
                     self.chunks += 1
-                    done, still = [], []
-                    for e, n in zip(resident, ns):
+                    for e, n in zip(batch, ns):
                         e.done += n
-                        (done if e.done >= e.req.n_steps else still).append(e)
-                    resident = still
+                    done = [e for e in batch if e.done >= e.req.n_steps]
+                    resident = [e for e in resident if e.done < e.req.n_steps]
                     inflight.append((token, done))
                     for e in done:
                         finishing[pool.submit(finish_job, e)] = e

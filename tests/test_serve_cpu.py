@@ -264,3 +264,42 @@ def test_pipelined_loop_completes_within_budget_and_batches_arrivals():
     # boards admitted while others were on the device joined later chunks
     joined = [d for d in log[1:] if d["resident"] > 0 and d["admitted"]]
     assert joined
+
+
+def test_solo_boards_run_their_chunks_alone():
+    """With solo_cells, a chunk that holds a board at or above the threshold holds
+    no smaller board; every request still completes with all its steps, and
+    the large solves finish sooner than when every chunk holds every board."""
+    reqs = _requests(60, seed=3, rate=4.0, big_every=10)
+    big = {r.rid for r in reqs if r.board.nx == 400}
+    solo_cells = 400 * 400 * 60
+    budget = 40 * 300 * 300 * 30 * 100
+    ex, srv, res, _ = _run(reqs, budget, chunk=100, solo_cells=solo_cells)
+    assert [r.rid for r in res] == list(range(60))
+    assert all(r.probes[0, 0] == r.rid for r in res)
+    for b in ex.batches:
+        if any(h in big for h in b):
+            assert all(h in big for h in b), b
+    assert any(len(b) > 1 for b in ex.batches)
+    ex0, _, res0, _ = _run(reqs, budget, chunk=100)
+    lat = lambda rs: np.array([r.latency_s for r in rs if r.rid in big])
+    assert lat(res).mean() < lat(res0).mean()
+
+
+def test_pipelined_solo_boards_run_their_chunks_alone():
+    reqs = _requests(30, seed=11, rate=300.0, big_every=6)
+    big = {r.rid for r in reqs if r.board.nx == 400}
+    ex = AsyncModelExecutor()
+    ex.reqs = {r.rid: r for r in reqs}
+    srv = Server(ex, 40 * 300 * 300 * 30 * 100, chunk=100, workers=2, depth=2,
+                 solo_cells=400 * 400 * 60)
+    try:
+        res = srv.run(reqs)
+    finally:
+        ex.close()
+    assert [r.rid for r in res] == list(range(30))
+    assert all(r.probes[0, 0] == r.rid for r in res)
+    assert not ex.live
+    for b in ex.batches:
+        if any(h in big for h in b):
+            assert all(h in big for h in b), b
