@@ -653,10 +653,7 @@ def run_serve(F, torch, capacity_gcells, n_requests, steps):
             print(f"[served] chunk {d['chunk']} at {d['t']:.0f} s: {d['resident']} resident, "
                   f"{d['waiting']} waiting", file=sys.stderr, flush=True)
 
-    # the 800x800x64 boards (41 M cells; the largest variant is 600x600x64, 23 M)
-    # run their chunks without the variants, which wait resident meanwhile
-    solo_cells = 30_000_000
-    srv = Server(ex, budget, chunk=500, workers=2, depth=2, log=progress, solo_cells=solo_cells)
+    srv = Server(ex, budget, chunk=500, workers=2, depth=2, log=progress)
     t0 = time.perf_counter()
     res = srv.run(requests)
     wall = time.perf_counter() - t0
@@ -672,8 +669,7 @@ def run_serve(F, torch, capacity_gcells, n_requests, steps):
                     f"batched capacity for the stream's mean board of {mean_cells / 1e6:.2f} M "
                     f"cells) of board variants, 5% 800x800x64, {steps} steps each, "
                     f"500-step chunks (up to two in flight, set-up and read-back on two "
-                    f"worker threads; the 800x800x64 boards' chunks run without the "
-                    f"variants), probe FFT per solve",
+                    f"worker threads), probe FFT per solve",
         "p50_latency_s": round(s["p50_latency_s"], 4),
         "p99_latency_s": round(s["p99_latency_s"], 4),
         "solves_per_s": round(s["solves_per_s"], 4),
@@ -692,7 +688,6 @@ def run_serve(F, torch, capacity_gcells, n_requests, steps):
         "wait_p50_p99_s": [round(float(np.percentile(wait, q)), 4) for q in (50, 99)],
         "chunks": srv.chunks,
         "tile": "x".join(str(v) for v in tile),
-        "solo_cells": solo_cells,
         "peak_resident": srv.peak_resident,
         "budget_gb": round(budget / 1e9, 1),
     }
