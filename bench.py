@@ -280,11 +280,15 @@ def run_eps(F, torch, K=200, W=10, large_only=False, only=None):
         info = F.fdtd_get_info(g)
         F.fdtd_destroy_grid(g)
         assert info.node_passes == (1 if mat >= 0 else 0) and info.material_two_step == max(mat, 0)
-        split = {1: "per tile, material variant 64x14x2", 2: "per plane, material variant 64x10x2"}
+        split = {0: "no tile plane needs the material variant",
+                 1: f"material variant per tile, 64x14x2, on {info.material_permille / 10:.1f} % of "
+                    f"the tile planes",
+                 2: f"material variant per plane, 64x10x2, on {info.material_permille / 10:.1f} % of "
+                    f"the tile planes"}
         out[name] = {
-            "kernel": (f"plain 64x14x2 and its material variant ({split.get(info.material_split)}; "
-                       f"{info.material_permille / 10:.1f} % of tile planes on it), odd steps on the "
-                       f"node passes" if mat == 1 else
+            "kernel": (f"plain 64x14x2 and its variants ({split[info.material_split]}; "
+                       f"conduction-only flavour, 64x14x2, on {info.conduct_permille / 10:.1f} %), "
+                       f"odd steps on the node passes" if mat == 1 else
                        "node passes" if mat == 0 else f"fused {info.tile_x}x{info.tile_y}x{info.tile_steps}"),
             "ms_per_step": round(wall / K * 1e3, 4),
             "gcell_updates_per_s": round(bb.cells * K / wall / 1e9, 3),

@@ -98,7 +98,9 @@ typedef struct {
                                     variant; the others run the plain two-step kernel */
     int32_t material_split;      /* how: 1 per tile (the variant in the plain kernel's 64 x 14 tiles),
                                     2 per plane (planes near material nodes in any tile run the
-                                    64 x 10 variant for every tile) */
+                                    64 x 10 variant for every tile), 0 no such planes */
+    int32_t conduct_permille;    /* the share (per mille) on the conduction-only flavour of the
+                                    variant (planes near conducting edges only, 64 x 14 tiles) */
     int32_t batch_plans;         /* plans of fdtd_step_many calls this handle led, kept for reuse */
     int32_t batch_graphs;        /* of which captured as a graph (one graph launch per call) */
 } fdtd_info;
@@ -175,14 +177,15 @@ int fdtd_set_dft_freqs(fdtd_grid* g, const double* f_hz, int nf);
  * steps run in the node passes' arithmetic (each PML node's coefficients rebuilt
  * from kappa and sigma / eps_rw; fdtd_info.node_passes = 1).  With a two-step
  * tile shape (the default) pairs of steps run two-step kernels of the shape
- * 64 x 14 x 2 and their material variant (fdtd_info.material_two_step = 1): a
- * tile's planes whose footprint holds, within two planes below or one above, a
- * node that needs the material arithmetic (a PML node with eps_r != 1 at a field
- * location, or a conducting edge) run the material variant, in that tile (few
- * tiles hold such nodes) or, for every tile, in 64 x 10 x 2 tiles (such nodes
- * fill those planes), whichever is estimated cheaper; the other planes run the
- * plain kernel (fdtd_info.material_permille, material_split).  The odd last
- * step of a call runs the node passes (two per-node passes, H then E).  With a one-step shape set, and on
+ * 64 x 14 x 2 and their variants (fdtd_info.material_two_step = 1): a tile's
+ * planes whose footprint holds, within two planes below or one above, a PML
+ * node with eps_r != 1 at a field location run the material variant, in that
+ * tile (few tiles hold such nodes) or, for every tile, in 64 x 10 x 2 tiles (such
+ * nodes fill those planes), whichever is estimated cheaper; planes near
+ * conducting edges only run its conduction-only flavour in that tile; the
+ * other planes run the plain kernel (fdtd_info.material_permille,
+ * material_split, conduct_permille).  The odd last step of a call runs the node
+ * passes (two per-node passes, H then E).  With a one-step shape set, and on
  * boards past the tiled kernels' 4 GiB offset window, every step runs the node
  * passes.  All give the same bits.  ESTATE after the first step. */
 int fdtd_set_pml_eps_rw(fdtd_grid* g, int on);

@@ -29,10 +29,10 @@ void shape2_at(int s, int* tx, int* ty);
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
                               int rel, int flip, bool wide, bool plane, hipStream_t st);
 int field_step2_occupancy(int tile_y, bool wide);
-hipError_t launch_field_step2_material(int tile_y, const BoardDev* boards, const TileRef* tiles,
-                                       int ntiles, int rel, int flip, bool wide, bool plane,
-                                       hipStream_t st);
-int field_step2_material_occupancy(int tile_y, bool wide);
+hipError_t launch_field_step2_material(int tile_y, int mode, const BoardDev* boards,
+                                       const TileRef* tiles, int ntiles, int rel, int flip,
+                                       bool wide, bool plane, hipStream_t st);
+int field_step2_material_occupancy(int tile_y, int mode, bool wide);
 int material_tile_y(int tile_y);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
@@ -174,6 +174,10 @@ struct fdtd_grid {
     TileRef* tilesP_dev = nullptr;
     int ntilesP = 0;
     int tilesP_cap = 0;
+    TileRef* tilesC_dev = nullptr;  // pieces of the conduction-only flavour (64 x kHybridTY x 2)
+    int ntilesC = 0;
+    int tilesC_cap = 0;
+    int cond_permille = 0;          // share of tile planes on the conduction-only flavour
     int mat_permille = 0;           // share of tile planes on the material variant
     int mat_ty = kHybridTY;         // the material variant's tile rows (kHybridTY or kMatTY)
     int mat_split = 0;              // 1: per tile, 2: per plane
@@ -427,9 +431,10 @@ void board_tiles(int b, int nx, int ny, int nz, int tx, int rows, std::vector<Ti
         for (int x = 0; x < cx; ++x) out.push_back(TileRef{b, x, y, 0, nz});
 }
 
-int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide, bool mat)
+// mode: 0 the plain kernels, 1 the material variant, 2 its conduction-only flavour
+int slots_per_xcd(const fdtd_grid* g, int tx, int ty, int steps, bool wide, int mode)
 {
-    const int occ = steps == 2 ? (mat ? field_step2_material_occupancy(ty, wide)
+    const int occ = steps == 2 ? (mode ? field_step2_material_occupancy(ty, mode, wide)
                                       : field_step2_occupancy(ty, wide))
                                : field_step_occupancy(tx, ty, wide);
     return std::max(1, g->cus / kXcds) * occ;
@@ -710,9 +715,12 @@ int finalize(fdtd_grid* g)
                 const bool node_pml = in_slab(i, nx, d.npml[0], d.npml[1]) ||
                                       in_slab(j, ny, d.npml[2], d.npml[3]) ||
                                       in_slab(k, nz, d.npml[4], d.npml[5]);
-                const bool needs = (fl & kCondE) || ((fl & (kMatH | kMatE)) && node_pml);
+                // bit 1: coefficients rebuilt (the material variant); bit 2: a
+                // conducting edge (its conduction-only flavour will do)
+                const uint8_t needs = (uint8_t)((((fl & (kMatH | kMatE)) && node_pml) ? 1 : 0) |
+                                                ((fl & kCondE) ? 2 : 0));
                 need[(size_t)j * (nx + 1) + i] = needs;
-                if (needs) mat_plane[k] = 1;
+                mat_plane[k] |= needs;
                 const ClassKey key{fbits(ix), fbits(iy), fbits(iz), fl, fbits(fx), fbits(fy), fbits(fz),
                                    fbits(lx), fbits(ly), fbits(lz)};
                 uint32_t id;
@@ -738,29 +746,33 @@ int finalize(fdtd_grid* g)
                 ids[(size_t)dev_index(g, i, j, k)] = (uint16_t)id;
             }
         if (!mat_plane[k]) continue;
-        // 2-D prefix sums of the plane's marks; a tile's footprint is the nodes
-        // its block computes or reads: columns i0-2 .. i0+65, rows j0-2 .. j0+TY-1
+        // 2-D prefix sums of the plane's marks, one kind at a time; a tile's
+        // footprint is the nodes its block computes or reads: columns i0-2 ..
+        // i0+65, rows j0-2 .. j0+TY-1
         if (tile_need.empty()) {
             tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
             pre.assign((size_t)(nx + 2) * (ny + 2), 0);
         }
         const int px = nx + 2;
-        for (int j = 0; j <= ny; ++j)
-            for (int i = 0; i <= nx; ++i)
-                pre[(size_t)(j + 1) * px + i + 1] = need[(size_t)j * (nx + 1) + i] +
-                                                    pre[(size_t)j * px + i + 1] +
-                                                    pre[(size_t)(j + 1) * px + i] -
-                                                    pre[(size_t)j * px + i];
-        for (int y = 0; y < hcy; ++y)
-            for (int x = 0; x < hcx; ++x) {
-                const int j0 = y * owned_rows(kHybridTY, 2), i0 = 64 * x;
-                const int ja = std::max(0, j0 - 2), jb = std::min(ny, j0 + kHybridTY - 1);
-                const int ia = std::max(0, i0 - 2), ib = std::min(nx, i0 + 65);
-                const int64_t sum = (int64_t)pre[(size_t)(jb + 1) * px + ib + 1] -
-                                    pre[(size_t)ja * px + ib + 1] - pre[(size_t)(jb + 1) * px + ia] +
-                                    pre[(size_t)ja * px + ia];
-                if (sum > 0) tile_need[((size_t)y * hcx + x) * (nz + 1) + k] = 1;
-            }
+        for (uint8_t bit = 1; bit <= 2; bit <<= 1) {
+            if (!(mat_plane[k] & bit)) continue;
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i)
+                    pre[(size_t)(j + 1) * px + i + 1] = ((need[(size_t)j * (nx + 1) + i] & bit) ? 1 : 0) +
+                                                        pre[(size_t)j * px + i + 1] +
+                                                        pre[(size_t)(j + 1) * px + i] -
+                                                        pre[(size_t)j * px + i];
+            for (int y = 0; y < hcy; ++y)
+                for (int x = 0; x < hcx; ++x) {
+                    const int j0 = y * owned_rows(kHybridTY, 2), i0 = 64 * x;
+                    const int ja = std::max(0, j0 - 2), jb = std::min(ny, j0 + kHybridTY - 1);
+                    const int ia = std::max(0, i0 - 2), ib = std::min(nx, i0 + 65);
+                    const int64_t sum = (int64_t)pre[(size_t)(jb + 1) * px + ib + 1] -
+                                        pre[(size_t)ja * px + ib + 1] -
+                                        pre[(size_t)(jb + 1) * px + ia] + pre[(size_t)ja * px + ia];
+                    if (sum > 0) tile_need[((size_t)y * hcx + x) * (nz + 1) + k] |= bit;
+                }
+        }
     }
     g->n_classes = (int)table.size();
     g->wide = table.size() > 256;
@@ -1267,12 +1279,13 @@ static int upload_work(fdtd_grid* g, const std::vector<TileRef>& tl, TileRef** d
     return FDTD_OK;
 }
 
-// Work list of given two-step pieces of the handle's board (64 x ty tiles).
-static int upload_pieces(fdtd_grid* g, int ty, const std::vector<TileRef>& pieces, bool mat,
+// Work list of given two-step pieces of the handle's board (64 x ty tiles) for
+// the kernel of `mode` (as slots_per_xcd).
+static int upload_pieces(fdtd_grid* g, int ty, int mode, const std::vector<TileRef>& pieces,
                          TileRef** dev, int* n, int* cap)
 {
     std::vector<TileRef> tl;
-    build_work(pieces, slots_per_xcd(g, 64, ty, 2, g->wide, mat), tl);
+    build_work(pieces, slots_per_xcd(g, 64, ty, 2, g->wide, mode), tl);
     return upload_work(g, tl, dev, n, cap);
 }
 
@@ -1280,7 +1293,7 @@ static int upload_list(fdtd_grid* g, int tx, int ty, int steps, TileRef** dev, i
 {
     std::vector<TileRef> whole, tl;
     board_tiles(0, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, steps), whole);
-    build_work(whole, slots_per_xcd(g, tx, ty, steps, g->wide, g->mat), tl);
+    build_work(whole, slots_per_xcd(g, tx, ty, steps, g->wide, 0), tl);
     if (tl.empty()) {
         *n = 0;
         return FDTD_OK;
@@ -1314,86 +1327,105 @@ static int upload_tiles(fdtd_grid* g)
     tile_counts(g->d.nx, g->d.ny, g->tile_x, owned_rows(g->tile_y, g->tile_steps), &b.tiles_x,
                 &b.tiles_y);
     g->ntilesP = 0;
+    g->ntilesC = 0;
     g->mat_permille = 0;
+    g->cond_permille = 0;
+    g->mat_split = 0;
     if (g->mat) {
-        // Tile planes near nodes that need the material arithmetic run the
-        // material variant, the rest the plain kernel (64 x kHybridTY x 2).  A
+        // Tile planes near nodes that need the material arithmetic run a variant
+        // of the plain kernel (64 x kHybridTY x 2), the rest the plain kernel.  A
         // piece [kb, ke) computes first-step H and E on planes kb-2 .. ke, so a
-        // tile's plane k is clear when no node of its footprint needs it on
-        // planes k-2 .. k+1.  Two ways to split, the cheaper by the measured cost
-        // of a tile plane on each kernel (large board, per step: plain 64 x 14
-        // 0.615 ms, material 64 x 14 1.00 ms, material 64 x 10 0.82 ms):
-        //  * per tile: each tile's unclear planes on the material variant of the
-        //    plain kernel's shape (which spills at 128 VGPRs), its clear planes
-        //    on the plain kernel: best when few tiles touch such nodes (a board
-        //    running into the PML with eps_rw);
-        //  * per plane: planes unclear in any tile on the 64 x kMatTY material
-        //    variant for every tile, the rest on the plain kernel: best when the
-        //    nodes fill those planes (a lossy layer).
-        // Both read one field copy and write the other, each its own pieces'
-        // nodes, and give the node passes' bits.
+        // tile's plane k is clear of a kind of node when no node of its
+        // footprint is of that kind on planes k-2 .. k+1.  Planes near PML nodes
+        // whose coefficients are rebuilt run the material variant; the others
+        // near conducting edges its conduction-only flavour (which fits the
+        // shape without spilling).  The material variant's planes are split one
+        // of two ways, the cheaper by the measured cost of a tile plane on each
+        // kernel (large board, per step: plain 64 x 14 0.615 ms, material 64 x 14
+        // 1.00 ms, material 64 x 10 0.82 ms):
+        //  * per tile: each tile's planes near such nodes on the variant in the
+        //    plain kernel's tiles (where it spills), best when few tiles hold
+        //    them (a board running into the PML with eps_rw);
+        //  * per plane: planes near such nodes in any tile on the 64 x kMatTY
+        //    variant for every tile, best when such nodes fill those planes.
+        // The kernels read one field copy and write the other, each its own
+        // pieces' nodes, and give the node passes' bits.
         const int nz = g->d.nz;
         int cx, cy;
         tile_counts(g->d.nx, g->d.ny, 64, owned_rows(kHybridTY, 2), &cx, &cy);
-        std::vector<TileRef> tile_mat, tile_plain;
-        std::vector<uint8_t> dirty((size_t)nz), any((size_t)nz, 0);
-        int64_t mat_tp = 0;
+        std::vector<uint8_t> kind((size_t)cx * cy * nz, 0), anyR((size_t)nz, 0);
+        int64_t rb_tp = 0;
+        for (size_t t = 0; t < (size_t)cx * cy; ++t) {
+            const uint8_t* tn = g->tile_need.empty() ? nullptr : &g->tile_need[t * (nz + 1)];
+            for (int k = 0; k < nz && tn; ++k) {
+                uint8_t m = 0;
+                for (int q = std::max(0, k - 2); q <= std::min(nz, k + 1); ++q) m |= tn[q];
+                const uint8_t kd = (m & 1) ? 1 : (m & 2) ? 2 : 0;   // 1 material, 2 conduction
+                kind[t * nz + k] = kd;
+                rb_tp += kd == 1;
+                anyR[k] |= kd == 1;
+            }
+        }
+        const double all = std::max<double>(1.0, (double)cx * cy * nz);
+        int64_t any_planes = 0;
+        for (int k = 0; k < nz; ++k) any_planes += anyR[k];
+        const double f_tile = rb_tp / all, f_plane = any_planes / (double)nz;
+        const double cost_tile = (1.0 - f_tile) * 0.615 + f_tile * 1.00;
+        const double cost_plane = (1.0 - f_plane) * 0.615 + f_plane * 0.82;
+        const bool per_plane = any_planes > 0 && cost_plane < cost_tile;
+        g->mat_ty = per_plane ? kMatTY : kHybridTY;
+        g->mat_split = any_planes == 0 ? 0 : per_plane ? 2 : 1;
+        // pieces: runs of one kind in each tile (per plane: the material planes
+        // leave the tiles and go to 64 x kMatTY tiles over the whole board)
+        std::vector<TileRef> rb_pieces, cd_pieces, plain_pieces;
+        int64_t cd_tp = 0, rb_planes = 0;
         for (int y = 0; y < cy; ++y)
             for (int x = 0; x < cx; ++x) {
-                const uint8_t* tn =
-                    g->tile_need.empty() ? nullptr : &g->tile_need[((size_t)y * cx + x) * (nz + 1)];
-                for (int k = 0; k < nz; ++k) {
-                    dirty[k] = 0;
-                    for (int q = std::max(0, k - 2); tn && q <= std::min(nz, k + 1) && !dirty[k]; ++q)
-                        dirty[k] = tn[q];
-                    any[k] |= dirty[k];
-                }
+                const uint8_t* kd = &kind[((size_t)y * cx + x) * nz];
+                auto k_of = [&](int k) -> int { return per_plane && anyR[k] ? 3 : kd[k]; };
                 for (int k = 0; k < nz;) {
+                    const int c = k_of(k);
                     int e = k;
-                    while (e < nz && dirty[e] == dirty[k]) ++e;
-                    (dirty[k] ? tile_mat : tile_plain).push_back(TileRef{0, x, y, k, e});
-                    if (dirty[k]) mat_tp += e - k;
+                    while (e < nz && k_of(e) == c) ++e;
+                    if (c == 1) {
+                        rb_pieces.push_back(TileRef{0, x, y, k, e});
+                        rb_planes += e - k;
+                    } else if (c == 2) {
+                        cd_pieces.push_back(TileRef{0, x, y, k, e});
+                        cd_tp += e - k;
+                    } else if (c == 0) {
+                        plain_pieces.push_back(TileRef{0, x, y, k, e});
+                    }
                     k = e;
                 }
             }
-        const double all = std::max<double>(1.0, (double)cx * cy * nz);
-        int64_t any_planes = 0;
-        for (int k = 0; k < nz; ++k) any_planes += any[k];
-        const double f_tile = mat_tp / all, f_plane = any_planes / (double)nz;
-        const double cost_tile = (1.0 - f_tile) * 0.615 + f_tile * 1.00;
-        const double cost_plane = (1.0 - f_plane) * 0.615 + f_plane * 0.82;
-        std::vector<TileRef> mat_pieces, plain_pieces;
-        if (cost_tile <= cost_plane) {
-            g->mat_ty = kHybridTY;
-            g->mat_split = 1;
-            g->mat_permille = (int)(1000.0 * f_tile);
-            mat_pieces.swap(tile_mat);
-            plain_pieces.swap(tile_plain);
-        } else {
-            g->mat_ty = kMatTY;
-            g->mat_split = 2;
-            g->mat_permille = (int)(1000.0 * f_plane);
-            std::vector<TileRef> mt, pt;
+        if (per_plane) {
+            std::vector<TileRef> mt;
             board_tiles(0, g->d.nx, g->d.ny, nz, 64, owned_rows(kMatTY, 2), mt);
-            board_tiles(0, g->d.nx, g->d.ny, nz, 64, owned_rows(kHybridTY, 2), pt);
             for (int k = 0; k < nz;) {
                 int e = k;
-                while (e < nz && any[e] == any[k]) ++e;
-                for (TileRef t : any[k] ? mt : pt) {
-                    t.kb = k;
-                    t.ke = e;
-                    (any[k] ? mat_pieces : plain_pieces).push_back(t);
-                }
+                while (e < nz && anyR[e] == anyR[k]) ++e;
+                if (anyR[k])
+                    for (TileRef t : mt) {
+                        t.kb = k;
+                        t.ke = e;
+                        rb_pieces.push_back(t);
+                    }
                 k = e;
             }
+            rb_planes = (int64_t)(f_plane * all + 0.5);
         }
-        if (int e = upload_pieces(g, g->mat_ty, mat_pieces, true, &g->tiles_dev, &g->ntiles,
-                                  &g->tiles_cap))
+        g->mat_permille = (int)(1000.0 * rb_planes / all);
+        g->cond_permille = (int)(1000.0 * cd_tp / all);
+        if (int e = upload_pieces(g, g->mat_ty, 1, rb_pieces, &g->tiles_dev, &g->ntiles, &g->tiles_cap))
             return e;
-        if (int e = upload_pieces(g, kHybridTY, plain_pieces, false, &g->tilesP_dev, &g->ntilesP,
+        if (int e = upload_pieces(g, kHybridTY, 2, cd_pieces, &g->tilesC_dev, &g->ntilesC,
+                                  &g->tilesC_cap))
+            return e;
+        if (int e = upload_pieces(g, kHybridTY, 0, plain_pieces, &g->tilesP_dev, &g->ntilesP,
                                   &g->tilesP_cap))
             return e;
-        if (g->ntilesP > 0 && g->ntiles > 0 && !g->aux_stream) {
+        if (g->ntilesP > 0 && g->ntiles + g->ntilesC > 0 && !g->aux_stream) {
             HIP_OR_FAIL(hipStreamCreateWithFlags(&g->aux_stream, hipStreamNonBlocking));
             HIP_OR_FAIL(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming));
             HIP_OR_FAIL(hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming));
@@ -1462,27 +1494,29 @@ static hipError_t node_step(fdtd_grid* g, int rel, int flip, hipStream_t st)
 // clear of material nodes, the material variant over the rest.
 static hipError_t material_pair(fdtd_grid* g, int rel, int flip, hipStream_t st)
 {
-    if (g->ntilesP > 0 && g->ntiles > 0 && g->aux_stream) {
-        hipError_t e = hipEventRecord(g->fork_ev, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(g->aux_stream, g->fork_ev, 0);
-        if (e == hipSuccess)
-            e = launch_field_step2_material(g->mat_ty, g->board_dev, g->tiles_dev, g->ntiles, rel,
-                                            flip, g->wide, g->plane_k >= 0, g->aux_stream);
-        if (e == hipSuccess)
-            e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel, flip,
-                                   g->wide, g->plane_k >= 0, st);
-        if (e == hipSuccess) e = hipEventRecord(g->join_ev, g->aux_stream);
+    const bool plane = g->plane_k >= 0;
+    // the variants' pieces on the second stream beside the plain kernel's
+    const bool fork = g->ntilesP > 0 && g->ntiles + g->ntilesC > 0 && g->aux_stream;
+    hipStream_t vs = fork ? g->aux_stream : st;
+    hipError_t e = hipSuccess;
+    if (fork) {
+        e = hipEventRecord(g->fork_ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(vs, g->fork_ev, 0);
+    }
+    if (e == hipSuccess && g->ntiles > 0)
+        e = launch_field_step2_material(g->mat_ty, 1, g->board_dev, g->tiles_dev, g->ntiles, rel, flip,
+                                        g->wide, plane, vs);
+    if (e == hipSuccess && g->ntilesC > 0)
+        e = launch_field_step2_material(kHybridTY, 2, g->board_dev, g->tilesC_dev, g->ntilesC, rel,
+                                        flip, g->wide, plane, vs);
+    if (e == hipSuccess && g->ntilesP > 0)
+        e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel, flip, g->wide,
+                               plane, st);
+    if (fork) {
+        if (e == hipSuccess) e = hipEventRecord(g->join_ev, vs);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, g->join_ev, 0);
-        return e;
     }
-    if (g->ntilesP > 0) {
-        const hipError_t e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel,
-                                                flip, g->wide, g->plane_k >= 0, st);
-        if (e != hipSuccess) return e;
-    }
-    if (g->ntiles == 0) return hipSuccess;
-    return launch_field_step2_material(g->mat_ty, g->board_dev, g->tiles_dev, g->ntiles, rel, flip,
-                                       g->wide, g->plane_k >= 0, st);
+    return e;
 }
 
 // One field launch of the handle's shape (two steps, or one with the odd-step
@@ -1731,7 +1765,7 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
                     const fdtd_grid* g = gs[r.order[b]];
                     board_tiles(b, g->d.nx, g->d.ny, g->d.nz, gtx, owned_rows(gty, gper), whole);
                 }
-                build_work(whole, slots_per_xcd(lead, gtx, gty, gper, w == 1, mat), list);
+                build_work(whole, slots_per_xcd(lead, gtx, gty, gper, w == 1, mat ? 1 : 0), list);
                 r.spans.push_back(
                     Span{w, gper, s, s_end, (int)r.items.size(), (int)list.size(), false, mat});
                 r.items.insert(r.items.end(), list.begin(), list.end());
@@ -1752,7 +1786,7 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
                 board_tiles(b, g->d.nx, g->d.ny, g->d.nz, kOddX, owned_rows(kOddY, 1), whole);
             }
         if (!whole.empty()) {
-            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1, false), list);
+            build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1, 0), list);
             r.spans.push_back(Span{w, 1, 0, 1, (int)r.items.size(), (int)list.size(), true, false});
             r.items.insert(r.items.end(), list.begin(), list.end());
         }
@@ -1798,7 +1832,7 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
                 continue;
             }
             for (int64_t k = sp.s0; k < sp.s1; ++k)
-                HIP_OR_FAIL(sp.mat ? launch_field_step2_material(mty, db, dt + sp.off, sp.count,
+                HIP_OR_FAIL(sp.mat ? launch_field_step2_material(mty, 1, db, dt + sp.off, sp.count,
                                                                  (int)(k * 2), (int)(k & 1),
                                                                  sp.w == 1, planes, st)
                                    : launch_pass(tx, ty, sp.steps, db, dt + sp.off, sp.count,
@@ -2399,6 +2433,7 @@ int fdtd_get_info(fdtd_grid* g, fdtd_info* out)
     out->material_two_step = g->mat ? 1 : 0;
     out->material_permille = g->mat ? g->mat_permille : 0;
     out->material_split = g->mat ? g->mat_split : 0;
+    out->conduct_permille = g->mat ? g->cond_permille : 0;
     out->batch_plans = (int32_t)g->plans.size();
     out->batch_graphs = 0;
     for (const BatchPlan* p : g->plans) out->batch_graphs += p->exec != nullptr;

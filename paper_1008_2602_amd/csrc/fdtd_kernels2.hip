@@ -66,12 +66,17 @@ __device__ __forceinline__ AxisCoef scale_coef(const AxisCoef& a, float w)
     return o;
 }
 
-template <int TY, typename CT, bool PL, bool MT>
+// MM: 0 the plain kernel; 1 the material variant (PML coefficients rebuilt,
+// conducting edges solved); 2 its conduction-only flavour (conducting edges
+// solved, no rebuild: tile planes whose nodes need no rebuilt coefficient)
+template <int TY, typename CT, bool PL, int MM>
 __global__ __launch_bounds__(64 * TY + 128)
 __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const BoardDev* __restrict__ boards,
                                                              const TileRef* __restrict__ tiles,
                                                              int rel, int flip)
 {
+    constexpr bool MT = MM != 0;     // the material arithmetic (class aux data, conduction)
+    constexpr bool RB = MM == 1;     // and PML coefficients rebuilt for 1/eps_rw
     constexpr int W = 64;            // owned columns
     constexpr int SC = W + 4;        // LDS columns: c = i - (i0 - 2), i0-2 .. i0+W+1
     constexpr int NT = 64 * TY + 128;
@@ -96,7 +101,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     __shared__ float sAux[kLdsAux][6];
     // z coefficients of plane p in slot p & 3 (planes k-1, k and k+1 are live at
     // once), staged by the last wave; the material variant also keeps kappa
-    constexpr int NZE = MT ? 12 : 10;
+    constexpr int NZE = RB ? 12 : 10;
     __shared__ float sZ[4][NZE];
 
     const TileRef t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
@@ -191,8 +196,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         a.rp_h = tab[(kRp * 2 + 1) * n1 + q];
         a.ph_h = tab[(kPh * 2 + 1) * n1 + q];
         a.q_h = tab[(kQ * 2 + 1) * n1 + q];
-        a.k_n = MT ? tab[(kKappa * 2 + 0) * n1 + q] : 1.0f;
-        a.k_h = MT ? tab[(kKappa * 2 + 1) * n1 + q] : 1.0f;
+        a.k_n = RB ? tab[(kKappa * 2 + 0) * n1 + q] : 1.0f;
+        a.k_h = RB ? tab[(kKappa * 2 + 1) * n1 + q] : 1.0f;
         return a;
     };
     // z coefficients from the LDS ring (entry kind*2 + half of the table)
@@ -209,8 +214,8 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         a.rp_h = z[kRp * 2 + 1];
         a.ph_h = z[kPh * 2 + 1];
         a.q_h = z[kQ * 2 + 1];
-        a.k_n = MT ? z[(kKappa * 2 + 0) % NZE] : 1.0f;
-        a.k_h = MT ? z[(kKappa * 2 + 1) % NZE] : 1.0f;
+        a.k_n = RB ? z[(kKappa * 2 + 0) % NZE] : 1.0f;
+        a.k_h = RB ? z[(kKappa * 2 + 1) % NZE] : 1.0f;
         return a;
     };
     const bool z_lane = wave == TY + 1 && lane < NZE;   // writes entry `lane` of the ring
@@ -296,7 +301,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
         const bool pz = in_pz(p);
         const bool oke = rE1 && ib && p <= nz;
         // the material variant's H1 needs the class on every H1 lane
-        const uint32_t ne = (MT ? rH1 && ib && p <= nz : oke) ? n : guardb;
+        const uint32_t ne = (RB ? rH1 && ib && p <= nz : oke) ? n : guardb;
         o.c = ld_at_t<CT>(cls, sizeof(CT) == 1 ? ne >> 2 : ne >> 1);
         o.dx = ld_at(gD, oke && (px || py) ? n : guardb);
         o.dy = ld_at(gD, (oke && (py || pz) ? n : guardb) + cs);
@@ -505,7 +510,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
                 const float cxe = (sE0z[r + 1][c] - ezo) * crdy - (sE0y[nxt][r][c] - eyo) * crdz;
                 const float cye = (sE0x[nxt][r][c] - exo) * crdz - (sE0z[r][c + 1] - ezo) * crdx;
                 const float cze = (sE0y[cur][r][c + 1] - eyo) * crdx - (sE0x[cur][r + 1][c] - exo) * crdy;
-                if ((px || py || pz) && (class_entry(o.c).flags & kMatH))
+                if (RB && (px || py || pz) && (class_entry(o.c).flags & kMatH))
                     h_material(o.c, Zk, cxe, cye, cze, o.hx, o.hy, o.hz, o.bx, o.by, o.bz, dbx, dby,
                                dbz, h1x, h1y, h1z);
                 else
@@ -548,7 +553,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
                 const float chx = (h1z - sH1z[r - 1][c]) * crdy - (h1y - p_h1y) * crdz;
                 const float chy = (h1x - p_h1x) * crdz - (h1z - sH1z[r][c - 1]) * crdx;
                 const float chz = (h1y - sH1y[r][c - 1]) * crdx - (h1x - sH1x[r - 1][c]) * crdy;
-                const bool rebuild = (px || py || pz) && (ce.flags & kMatE);
+                const bool rebuild = RB && (px || py || pz) && (ce.flags & kMatE);
                 if (rebuild || (ce.flags & (kCondE | kSrcEz)))
                     e_material(ce, o.c, rebuild, node, step, Zk, chx, chy, chz, exo, eyo, ezo, o.dx,
                                o.dy, o.dz, ddx, ddy, ddz, exn, eyn, ezn);
@@ -597,7 +602,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
                 const float cxe = (sE1z[pe][r + 1][c] - ezo) * crdy - (sE1y[e][r][c] - eyo) * crdz;
                 const float cye = (sE1x[e][r][c] - exo) * crdz - (sE1z[pe][r][c + 1] - ezo) * crdx;
                 const float cze = (sE1y[pe][r][c + 1] - eyo) * crdx - (sE1x[pe][r + 1][c] - exo) * crdy;
-                if ((px || py || pzm) && (class_entry(p_c).flags & kMatH))
+                if (RB && (px || py || pzm) && (class_entry(p_c).flags & kMatH))
                     h_material(p_c, Zm, cxe, cye, cze, p_h1x, p_h1y, p_h1z, p_b1x, p_b1y, p_b1z, dbx,
                                dby, dbz, h2x, h2y, h2z);
                 else
@@ -646,7 +651,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
                 const float chx = (h2z - sH2z[r - 1][c]) * crdy - (h2y - p_h2y) * crdz;
                 const float chy = (h2x - p_h2x) * crdz - (h2z - sH2z[r][c - 1]) * crdx;
                 const float chz = (h2y - sH2y[r][c - 1]) * crdx - (h2x - sH2x[r - 1][c]) * crdy;
-                const bool rebuild = (px || py || pzm) && (ce.flags & kMatE);
+                const bool rebuild = RB && (px || py || pzm) && (ce.flags & kMatE);
                 if (rebuild || (ce.flags & (kCondE | kSrcEz)))
                     e_material(ce, p_c, rebuild, node, step + 1, Zm, chx, chy, chz, p_e1x, p_e1y,
                                p_e1z, p_d1x, p_d1y, p_d1z, ddx, ddy, ddz, exn, eyn, ezn);
@@ -713,15 +718,15 @@ void shape2_at(int s, int* tx, int* ty)
     *ty = kShapes2[s].ty;
 }
 
-template <int TY, bool PL, bool MT>
+template <int TY, bool PL, int MM>
 static void launch2_tp(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
                        bool wide, hipStream_t st)
 {
     if (wide)
-        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL, MT>), dim3(ntiles), dim3(64 * TY + 128), 0,
+        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL, MM>), dim3(ntiles), dim3(64 * TY + 128), 0,
                            st, boards, tiles, rel, flip);
     else
-        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL, MT>), dim3(ntiles), dim3(64 * TY + 128), 0,
+        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL, MM>), dim3(ntiles), dim3(64 * TY + 128), 0,
                            st, boards, tiles, rel, flip);
 }
 
@@ -732,9 +737,9 @@ static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int nt
                             int flip, bool wide, bool plane, hipStream_t st)
 {
     if (plane)
-        launch2_tp<TY, true, false>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, 0>(boards, tiles, ntiles, rel, flip, wide, st);
     else
-        launch2_tp<TY, false, false>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, 0>(boards, tiles, ntiles, rel, flip, wide, st);
     return hipGetLastError();
 }
 
@@ -743,9 +748,9 @@ static int occupancy2_t(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t, false, false>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, 0>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t, false, false>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, 0>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -781,43 +786,50 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
 // board (which runs each tile's planes near material nodes on it and the rest
 // on the plain kernel); at 128 VGPRs it spills about 15 values.  64 x kMatTY x 2,
 // whose three waves per SIMD leave it the registers it needs, runs material
-// boards in batched calls, where it takes every plane.
+// boards in batched calls, where it takes every plane, and planes where such
+// nodes fill the board.  The conduction-only flavour (no rebuilt coefficients)
+// fits 64 x kHybridTY x 2 in 128 VGPRs without spilling.
 int material_tile_y(int) { return kMatTY; }
 
-template <int TY>
+template <int TY, int MM>
 static int mat_occupancy(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t, false, true>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, MM>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t, false, true>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, MM>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-int field_step2_material_occupancy(int tile_y, bool wide)
+// mode 1: the material variant (tile_y kHybridTY or kMatTY); mode 2: its
+// conduction-only flavour (kHybridTY)
+int field_step2_material_occupancy(int tile_y, int mode, bool wide)
 {
-    return tile_y == kHybridTY ? mat_occupancy<kHybridTY>(wide) : mat_occupancy<kMatTY>(wide);
+    if (mode == 2) return mat_occupancy<kHybridTY, 2>(wide);
+    return tile_y == kHybridTY ? mat_occupancy<kHybridTY, 1>(wide) : mat_occupancy<kMatTY, 1>(wide);
 }
 
-template <int TY>
+template <int TY, int MM>
 static void mat_launch(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
                        bool wide, bool plane, hipStream_t st)
 {
     if (plane)
-        launch2_tp<TY, true, true>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, MM>(boards, tiles, ntiles, rel, flip, wide, st);
     else
-        launch2_tp<TY, false, true>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, MM>(boards, tiles, ntiles, rel, flip, wide, st);
 }
 
-hipError_t launch_field_step2_material(int tile_y, const BoardDev* boards, const TileRef* tiles,
-                                       int ntiles, int rel, int flip, bool wide, bool plane,
-                                       hipStream_t st)
+hipError_t launch_field_step2_material(int tile_y, int mode, const BoardDev* boards,
+                                       const TileRef* tiles, int ntiles, int rel, int flip,
+                                       bool wide, bool plane, hipStream_t st)
 {
-    if (tile_y == kHybridTY)
-        mat_launch<kHybridTY>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-    else if (tile_y == kMatTY)
-        mat_launch<kMatTY>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+    if (mode == 2 && tile_y == kHybridTY)
+        mat_launch<kHybridTY, 2>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+    else if (mode == 1 && tile_y == kHybridTY)
+        mat_launch<kHybridTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+    else if (mode == 1 && tile_y == kMatTY)
+        mat_launch<kMatTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, st);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -66,6 +66,7 @@ class fdtd_info(C.Structure):
                 ("node_passes", C.c_int32), ("material_two_step", C.c_int32),
                 ("material_permille", C.c_int32),
                 ("material_split", C.c_int32),
+                ("conduct_permille", C.c_int32),
                 ("batch_plans", C.c_int32), ("batch_graphs", C.c_int32)]
 
 

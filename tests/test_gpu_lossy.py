@@ -315,13 +315,15 @@ def test_material_boards_batched_bitwise(F):
             F.fdtd_destroy_grid(g)
 
 
-def slab_board(steps, lossy=True, nx=70, ny=40, nz=44):
+def slab_board(steps, lossy=True, nx=70, ny=40, nz=44, eps_rw=True):
     """A board whose material sits in a few planes: an eps_r 4.2 slab (6 planes
     from nz // 2 - 6) through the x/y PML with eps_rw on between two PEC sheets,
     a resistive source and probes in it.  lossy: the slab is lossy inside the
     PML's inner region and the sheets resistive, so every tile holds material
     nodes near the slab (split per plane); else only tiles at the x/y PML do
-    (split per tile on a board this wide)."""
+    (split per tile on a board this wide).  Without eps_rw only the lossy
+    layer's conducting edges need more than the plain kernel (its
+    conduction-only flavour)."""
     eps, mask = boardgen.air(nx, ny, nz)
     k0 = nz // 2 - 6
     eps[k0:k0 + 6] = 4.2
@@ -329,7 +331,7 @@ def slab_board(steps, lossy=True, nx=70, ny=40, nz=44):
     boardgen.pec_sheet(mask, k0 + 6, 6, nx - 7, 6, ny - 7)
     p = 4
     b = boardgen.Board("slab", nx, ny, nz, 0.5e-3, 0.5e-3, 0.1e-3, eps, mask, npml=(p,) * 6,
-                       steps=steps, pml_eps_rw=True, sheet_R=0.02 if lossy else 0.0)
+                       steps=steps, pml_eps_rw=eps_rw, sheet_R=0.02 if lossy else 0.0)
     if lossy:
         sig = np.zeros(eps.shape, np.float32)
         sig[k0:k0 + 6, p:ny - p, p:nx - p] = 0.05
@@ -342,16 +344,19 @@ def slab_board(steps, lossy=True, nx=70, ny=40, nz=44):
     return b
 
 
-@pytest.mark.parametrize("lossy,shape,split", [(True, (70, 40, 44), 2), (False, (512, 132, 30), 1)])
-def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, shape, split):
-    """The split of a material board's tile planes between the plain kernel and
-    its material variant (per plane on the lossy board, per tile on the wide
-    lossless one): from an arbitrary state, 5 steps (two pairs and an odd one)
-    give the node passes' bits and match the oracle; from zero, odd call splits,
-    timed launches, the node passes alone and a checkpoint give the same bits,
-    probes and the plane DFT against the oracle."""
+@pytest.mark.parametrize("lossy,eps_rw,shape,split", [(True, True, (70, 40, 44), 2),
+                                                      (False, True, (512, 132, 30), 1),
+                                                      (True, False, (70, 40, 44), 0)])
+def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, eps_rw, shape, split):
+    """The split of a material board's tile planes between the plain kernel, its
+    material variant (per plane on the small lossy eps_rw board, per tile on the
+    wide lossless one) and the variant's conduction-only flavour (the lossy
+    board without eps_rw): from an arbitrary state, 5 steps (two pairs and an
+    odd one) give the node passes' bits and match the oracle; from zero, odd
+    call splits, timed launches, the node passes alone and a checkpoint give the
+    same bits, probes and the plane DFT against the oracle."""
     nx, ny, nz = shape
-    b = slab_board(5, lossy, nx, ny, nz)
+    b = slab_board(5, lossy, nx, ny, nz, eps_rw)
     st = random_state(oracle_mod, b, seed=31)
     if lossy:
         for n, bit in (("ex", 1), ("ey", 2)):        # the sheets' edges are state too
@@ -362,11 +367,14 @@ def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, shape, split
     ref = oracle_mod.run(b, state=st, threads=16)
     fields = two_step_equals_node_passes(F, b, init)
     info = two_step_equals_node_passes.info
-    assert 0 < info.material_permille < 1000, info.material_permille
     assert info.material_split == split, info.material_split
+    if eps_rw:
+        assert 0 < info.material_permille < 1000, info.material_permille
+    else:
+        assert info.material_permille == 0 and 0 < info.conduct_permille < 1000, info.conduct_permille
     compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
-    b = slab_board(71, lossy, nx, ny, nz)
+    b = slab_board(71, lossy, nx, ny, nz, eps_rw)
     announce(f"slab board lossy={lossy} {shape}: from zero")
     ref = oracle_mod.run(b, threads=16)
     out = run(F, b)
