@@ -44,7 +44,8 @@ def _interior_edge(b, rng, taken):
 
 def resistive_tiny(seed, steps, nx=14, ny=12, nz=10, V0=5.0, R=10.0):
     """random_tiny (a current source of each waveform, a PEC sheet, an eps_r block,
-    PML on every face) plus a resistive source of each waveform inside the PML."""
+    PML on every face) plus a resistive source of each waveform on free edges
+    clear of every PML slab (where the library accepts them)."""
     b = boardgen.random_tiny(seed, nx=nx, ny=ny, nz=nz, npml=2, steps=steps)
     rng = np.random.default_rng(seed + 77)
     taken = {(s.i, s.j, s.k) for s in b.sources}
