@@ -33,7 +33,6 @@ hipError_t launch_field_step2_material(int tile_y, int mode, const BoardDev* boa
                                        const TileRef* tiles, int ntiles, int rel, int flip,
                                        bool wide, bool plane, hipStream_t st);
 int field_step2_material_occupancy(int tile_y, int mode, bool wide);
-int material_tile_y(int tile_y);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
 hipError_t launch_eps_step(const BoardDev* board, int nx, int ny, int nz, int64_t plane_bytes,
@@ -174,6 +173,8 @@ struct fdtd_grid {
     TileRef* tilesP_dev = nullptr;
     int ntilesP = 0;
     int tilesP_cap = 0;
+    // the same pieces on the host (board index 0), for batched calls
+    std::vector<TileRef> pc_plain, pc_cd, pc_rb;
     TileRef* tilesC_dev = nullptr;  // pieces of the conduction-only flavour (64 x kHybridTY x 2)
     int ntilesC = 0;
     int tilesC_cap = 0;
@@ -1417,6 +1418,9 @@ static int upload_tiles(fdtd_grid* g)
         }
         g->mat_permille = (int)(1000.0 * rb_planes / all);
         g->cond_permille = (int)(1000.0 * cd_tp / all);
+        g->pc_plain = plain_pieces;
+        g->pc_cd = cd_pieces;
+        g->pc_rb = rb_pieces;
         if (int e = upload_pieces(g, g->mat_ty, 1, rb_pieces, &g->tiles_dev, &g->ntiles, &g->tiles_cap))
             return e;
         if (int e = upload_pieces(g, kHybridTY, 2, cd_pieces, &g->tilesC_dev, &g->ntilesC,
@@ -1657,12 +1661,17 @@ namespace {
 
 // launches of one work list: passes s0 .. s1-1 of `steps` steps each, or the
 // single-step tail launch (which reads the boards' tail copies)
+// Passes s0 .. s1-1 of a set of boards: each pass is one launch per list, in
+// list order (the lists of one board's pieces depend on each other pass by pass).
 struct Span {
     int w, steps;
     int64_t s0, s1;
-    int off, count;   // into the round's tile list
+    int nl = 0;       // lists
+    int kind[4];      // 0 the plain group's whole tiles (the lead's shape); a material board's
+                      // pieces: 1 plain, 2 conduction-only, 3 material 64 x kHybridTY, 4 material
+                      // 64 x kMatTY
+    int off[4], count[4];   // into the round's tile list
     bool tail;
-    bool mat;         // material boards (the material variant)
 };
 
 // A material board's odd last step of a round, on the node passes.
@@ -1705,7 +1714,6 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
 {
     fdtd_grid* lead = gs[0];
     const int tx = lead->tile_x, ty = lead->tile_y, per = lead->tile_steps;
-    const int mty = material_tile_y(per == 2 ? ty : kMatTY);   // material boards' shape
     r.n.assign(n, n + ng);
     // order boards by step count (descending): at pass s the boards still running
     // form a prefix, and so do their tiles; narrow and wide class maps, and
@@ -1750,7 +1758,6 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
     for (int grp = 0; grp < 4; ++grp) {
         const int w = grp & 1;
         const bool mat = grp >= 2;
-        const int gtx = mat ? 64 : tx, gty = mat ? mty : ty, gper = mat ? 2 : per;
         int b0 = 0;
         while (b0 < ng && group(r.order[b0]) != grp) ++b0;
         if (b0 == ng) continue;
@@ -1760,15 +1767,43 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
         for (int active = b1; active > b0 && s < max_np;) {
             const int64_t s_end = np[active - 1];  // boards [b0, active) all run through s_end
             if (s_end > s) {
-                whole.clear();
-                for (int b = b0; b < active; ++b) {
-                    const fdtd_grid* g = gs[r.order[b]];
-                    board_tiles(b, g->d.nx, g->d.ny, g->d.nz, gtx, owned_rows(gty, gper), whole);
+                // plain boards: whole tiles of the lead's shape; material boards:
+                // their own pieces (plain, conduction-only, material), each kind a
+                // list (and a launch per pass) of its own
+                Span sp{w, mat ? 2 : per, s, s_end};
+                sp.tail = false;
+                for (int kind = mat ? 1 : 0; kind <= (mat ? 4 : 0); ++kind) {
+                    const int kty = kind == 0 ? ty : kind == 4 ? kMatTY : kHybridTY;
+                    const int ktx = kind == 0 ? tx : 64, kper = kind == 0 ? per : 2;
+                    const int mode = kind >= 3 ? 1 : kind == 2 ? 2 : 0;
+                    whole.clear();
+                    for (int b = b0; b < active; ++b) {
+                        const fdtd_grid* g = gs[r.order[b]];
+                        if (kind == 0) {
+                            board_tiles(b, g->d.nx, g->d.ny, g->d.nz, tx, owned_rows(ty, per), whole);
+                            continue;
+                        }
+                        const std::vector<TileRef>* pc =
+                            kind == 1 ? &g->pc_plain
+                                      : kind == 2 ? &g->pc_cd
+                                                  : (g->mat_ty == (kind == 3 ? kHybridTY : kMatTY)
+                                                         ? &g->pc_rb
+                                                         : nullptr);
+                        if (pc)
+                            for (TileRef t : *pc) {
+                                t.board = b;
+                                whole.push_back(t);
+                            }
+                    }
+                    if (whole.empty()) continue;
+                    build_work(whole, slots_per_xcd(lead, ktx, kty, kper, w == 1, mode), list);
+                    sp.kind[sp.nl] = kind;
+                    sp.off[sp.nl] = (int)r.items.size();
+                    sp.count[sp.nl] = (int)list.size();
+                    ++sp.nl;
+                    r.items.insert(r.items.end(), list.begin(), list.end());
                 }
-                build_work(whole, slots_per_xcd(lead, gtx, gty, gper, w == 1, mat ? 1 : 0), list);
-                r.spans.push_back(
-                    Span{w, gper, s, s_end, (int)r.items.size(), (int)list.size(), false, mat});
-                r.items.insert(r.items.end(), list.begin(), list.end());
+                if (sp.nl > 0) r.spans.push_back(sp);
                 s = s_end;
             }
             --active;
@@ -1787,7 +1822,13 @@ void plan_round(fdtd_grid* const* gs, int ng, const int64_t* n, RoundHost& r)
             }
         if (!whole.empty()) {
             build_work(whole, slots_per_xcd(lead, kOddX, kOddY, 1, w == 1, 0), list);
-            r.spans.push_back(Span{w, 1, 0, 1, (int)r.items.size(), (int)list.size(), true, false});
+            Span sp{w, 1, 0, 1};
+            sp.nl = 1;
+            sp.kind[0] = 0;
+            sp.off[0] = (int)r.items.size();
+            sp.count[0] = (int)list.size();
+            sp.tail = true;
+            r.spans.push_back(sp);
             r.items.insert(r.items.end(), list.begin(), list.end());
         }
     }
@@ -1818,7 +1859,6 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
 {
     const fdtd_grid* lead = gs[0];
     const int tx = lead->tile_x, ty = lead->tile_y;
-    const int mty = material_tile_y(lead->tile_steps == 2 ? ty : kMatTY);
     const bool planes = any_plane(gs, ng);
     for (size_t q = 0; q < P.rounds.size(); ++q) {
         const RoundHost& R = P.rounds[q];
@@ -1827,17 +1867,40 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
         const TileRef* dt = (const TileRef*)(P.dev + P.off_tiles[q]);
         for (const Span& sp : R.spans) {
             if (sp.tail) {
-                HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, db + ng, dt + sp.off, sp.count, 0, 0,
+                HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, db + ng, dt + sp.off[0], sp.count[0], 0, 0,
                                         sp.w == 1, planes, st));
                 continue;
             }
-            for (int64_t k = sp.s0; k < sp.s1; ++k)
-                HIP_OR_FAIL(sp.mat ? launch_field_step2_material(mty, 1, db, dt + sp.off, sp.count,
-                                                                 (int)(k * 2), (int)(k & 1),
-                                                                 sp.w == 1, planes, st)
-                                   : launch_pass(tx, ty, sp.steps, db, dt + sp.off, sp.count,
-                                                 (int)(k * sp.steps), (int)(k & 1), sp.w == 1,
-                                                 planes, st));
+            const bool wide = sp.w == 1;
+            for (int64_t k = sp.s0; k < sp.s1; ++k) {
+                const int rel = (int)(k * sp.steps), flip = (int)(k & 1);
+                for (int l = 0; l < sp.nl; ++l) {
+                    const TileRef* tl = dt + sp.off[l];
+                    const int n = sp.count[l];
+                    hipError_t e;
+                    switch (sp.kind[l]) {
+                        case 0:
+                            e = launch_pass(tx, ty, sp.steps, db, tl, n, rel, flip, wide, planes, st);
+                            break;
+                        case 1:
+                            e = launch_field_step2(kHybridTY, db, tl, n, rel, flip, wide, planes, st);
+                            break;
+                        case 2:
+                            e = launch_field_step2_material(kHybridTY, 2, db, tl, n, rel, flip, wide,
+                                                            planes, st);
+                            break;
+                        case 3:
+                            e = launch_field_step2_material(kHybridTY, 1, db, tl, n, rel, flip, wide,
+                                                            planes, st);
+                            break;
+                        default:
+                            e = launch_field_step2_material(kMatTY, 1, db, tl, n, rel, flip, wide,
+                                                            planes, st);
+                            break;
+                    }
+                    HIP_OR_FAIL(e);
+                }
+            }
         }
         for (const NodeTail& t : R.node_tails)
             HIP_OR_FAIL(node_step(gs[t.h], t.rel, t.flip, st));

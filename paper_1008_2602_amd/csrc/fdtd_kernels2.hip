@@ -785,12 +785,9 @@ hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef*
 // shapes.  64 x kHybridTY x 2 shares the plain kernel's tiles on a material
 // board (which runs each tile's planes near material nodes on it and the rest
 // on the plain kernel); at 128 VGPRs it spills about 15 values.  64 x kMatTY x 2,
-// whose three waves per SIMD leave it the registers it needs, runs material
-// boards in batched calls, where it takes every plane, and planes where such
-// nodes fill the board.  The conduction-only flavour (no rebuilt coefficients)
+// whose three waves per SIMD leave it the registers it needs, takes planes where
+// such nodes fill the board.  The conduction-only flavour (no rebuilt coefficients)
 // fits 64 x kHybridTY x 2 in 128 VGPRs without spilling.
-int material_tile_y(int) { return kMatTY; }
-
 template <int TY, int MM>
 static int mat_occupancy(bool wide)
 {

@@ -276,20 +276,24 @@ def test_sheet_argument_errors(F):
 
 
 def test_material_boards_batched_bitwise(F):
-    """Material boards join fdtd_step_many: an eps_rw board (with a plane DFT), a
-    lossy board with a resistive sheet and one with per-cell eps_r as well
-    (more than 256 classes) beside two plain boards, uneven step counts (odd
-    ones end on the node passes), in two calls; every array, probe series and
-    plane DFT bitwise equal to the board stepped alone, and the second call
-    replays the first call's plan (one graph)."""
+    """Material boards join fdtd_step_many with their own split of tile planes:
+    an eps_rw board (with a plane DFT; the material variant per plane), a lossy
+    board with a resistive sheet and one with per-cell eps_r as well (more than
+    256 classes), the wide slab board (the material variant per tile) and a
+    lossy slab board without eps_rw (the conduction-only flavour) beside two
+    plain boards, uneven step counts (odd ones end on the node passes), in two
+    calls; every array, probe series and plane DFT bitwise equal to the board
+    stepped alone, and the second call replays the first call's plan (one
+    graph)."""
     from test_gpu_eps import eps_board
     wide = sheet_board(6, steps=60)
     rng = np.random.default_rng(21)
     wide.eps_r_cell[:] = rng.choice([1.0, 2.2, 3.3, 4.4], size=wide.eps_r_cell.shape).astype(np.float32)
     wide.pml_eps_rw = True
     boards = [boardgen.random_tiny(4, nx=40, ny=20, nz=10, npml=2, steps=60), eps_board(3, steps=60),
-              sheet_board(5, steps=60), wide, boardgen.random_tiny(7, nx=33, ny=25, nz=9, npml=3, steps=60)]
-    call = [17, 21, 9, 16, 20]
+              sheet_board(5, steps=60), wide, boardgen.random_tiny(7, nx=33, ny=25, nz=9, npml=3, steps=60),
+              slab_board(60, False, 512, 132, 30), slab_board(60, True, 70, 40, 44, eps_rw=False)]
+    call = [17, 21, 9, 16, 20, 13, 19]
     totals = [2 * n for n in call]
     alone = [run(F, dataclasses.replace(b, steps=t)) for b, t in zip(boards, totals)]
     hs = [F.grid_from_board(b, max_steps=60) for b in boards]
@@ -298,8 +302,9 @@ def test_material_boards_batched_bitwise(F):
             F.fdtd_step_many([g for g, _ in hs], call)
         F.fdtd_synchronize(hs[0][0])
         infos = [F.fdtd_get_info(g) for g, _ in hs]
-        assert [i.material_two_step for i in infos] == [0, 1, 1, 1, 0]
+        assert [i.material_two_step for i in infos] == [0, 1, 1, 1, 0, 1, 1]
         assert infos[3].n_classes > 256
+        assert infos[5].material_split == 1 and infos[6].conduct_permille > 0
         assert infos[0].batch_plans == 1 and infos[0].batch_graphs == 1
         for q, ((g, ids), b) in enumerate(zip(hs, boards)):
             if ids:
