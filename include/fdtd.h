@@ -239,11 +239,11 @@ int fdtd_step_n(fdtd_grid* g, int64_t n);
 
 /* Batched stepping: advance ng handles by n[h] steps each in shared launches
  * (one field launch per pass covers every handle still running; handles whose
- * class index widths differ, and material boards (fdtd_info.material_two_step),
- * go to launches of their own, the latter on the material variant over all
- * their planes, with their odd last steps on the node passes).  Handles must be
- * distinct and
- * share one device; results are bitwise those of stepping each alone (the probe
+ * class index widths differ go to launches of their own, and material boards
+ * (fdtd_info.material_two_step) to one launch per kind of their pieces per pass
+ * (plain, conduction-only, material), the split each has alone, with their odd
+ * last steps on the node passes).  Handles must be distinct and share one
+ * device; results are bitwise those of stepping each alone (the probe
  * DFT to rounding: it sums each call's samples in one pass).  Runs on the first
  * handle's stream, ordered after (and before) work on the other handles'
  * streams by events; uses the first handle's tile shape.  The first call with a
