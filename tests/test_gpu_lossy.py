@@ -351,12 +351,14 @@ def slab_board(steps, lossy=True, nx=70, ny=40, nz=44, eps_rw=True):
 
 @pytest.mark.parametrize("lossy,eps_rw,shape,split", [(True, True, (70, 40, 44), 2),
                                                       (False, True, (512, 132, 30), 1),
-                                                      (True, False, (70, 40, 44), 0)])
+                                                      (True, False, (70, 40, 44), 0),
+                                                      (True, True, (512, 132, 30), 1)])
 def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, eps_rw, shape, split):
     """The split of a material board's tile planes between the plain kernel, its
     material variant (per plane on the small lossy eps_rw board, per tile on the
-    wide lossless one) and the variant's conduction-only flavour (the lossy
-    board without eps_rw): from an arbitrary state, 5 steps (two pairs and an
+    wide ones) and the variant's conduction-only flavour (the lossy boards but
+    the small eps_rw one; on the wide lossy one beside the material variant's
+    pieces in the same pair): from an arbitrary state, 5 steps (two pairs and an
     odd one) give the node passes' bits and match the oracle; from zero, odd
     call splits, timed launches, the node passes alone and a checkpoint give the
     same bits, probes and the plane DFT against the oracle."""
@@ -376,7 +378,8 @@ def test_slab_board_plain_and_material_pieces(F, oracle_mod, lossy, eps_rw, shap
     if eps_rw:
         assert 0 < info.material_permille < 1000, info.material_permille
     else:
-        assert info.material_permille == 0 and 0 < info.conduct_permille < 1000, info.conduct_permille
+        assert info.material_permille == 0, info.material_permille
+    assert (info.conduct_permille > 0) == (lossy and split != 2), info.conduct_permille
     compare_fields(ref.state, fields, b, 2e-5, elem_tol=1e-5)
 
     b = slab_board(71, lossy, nx, ny, nz, eps_rw)
