@@ -162,7 +162,8 @@ def cpu_baseline(board, budget_s=20.0, single_budget_s=8.0):
 
 
 def sec8d_step_bytes(info):
-    """Algorithmic bytes of one step by the survey's count for the split layout:
+    """Algorithmic bytes of one step, counted as two separate passes per step in
+    the split layout (D/B kept only where a PML loss acts):
     per cell 72 B (separate H and E passes: E, H read and H written, then H, E
     read and E written, FP32) plus the class index, plus 8 B (read and write) for
     every kept D/B component.  The kept D/B bytes are the library's own count
@@ -292,7 +293,7 @@ def run_eps(F, torch, K=200, W=10, large_only=False, only=None):
                        "node passes" if mat == 0 else f"fused {info.tile_x}x{info.tile_y}x{info.tile_steps}"),
             "ms_per_step": round(wall / K * 1e3, 4),
             "gcell_updates_per_s": round(bb.cells * K / wall / 1e9, 3),
-            # the survey's algorithmic bytes of a step of this board
+            # the algorithmic bytes of a step of this board (sec8d_step_bytes)
             "hbm_frac_algorithmic": round(sec8d_step_bytes(info) * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         }
     if large_only or only is not None:
@@ -477,7 +478,7 @@ def run_batch(F, torch, K, W):
         "steps": K,
         "ms_per_step": round(wall / K * 1e3, 4),
         "tile": "x".join(str(v) for v in tile),
-        # on the survey's algorithmic bytes; effective (two steps per pass)
+        # on the algorithmic bytes (sec8d_step_bytes); effective (two steps per pass)
         "frac_effective": round(step_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_step": int(step_bytes),
         "frac_on_fused_bytes": round(fused_bytes * K / wall / 1e9 / HBM_PEAK_GBS, 4),
@@ -801,8 +802,8 @@ def main():
             },
             "roofline": {
                 "bound": "hbm",
-                # algorithmic bytes: the survey's per cell-update count for the
-                # layout used (D/B kept only where a PML loss acts): 72 B of E and H
+                # algorithmic bytes: the per cell-update count of two separate passes
+                # in the layout used (D/B kept only where a PML loss acts): 72 B of E and H
                 # for separate H and E passes, the class byte(s), 8 B per kept D/B
                 # component, times the steps one launch advances
                 "achieved": round(achieved, 1),
@@ -810,7 +811,7 @@ def main():
                 "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 # above 1 is possible: the kernel keeps step n+1 on chip, so it moves
-                # fewer bytes than two separate steps of the survey's count
+                # fewer bytes than two separate steps of that count
                 "frac_kind": "effective (temporally blocked: two steps per pass)",
                 "traffic": traffic,
                 # HBM bytes actually moved (PMC) over the launch time, against the peak
