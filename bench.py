@@ -831,52 +831,81 @@ def main():
             },
         })
         section("single")
+    def guarded(key, fn):
+        # a secondary part that fails leaves its error in the line (traceback on
+        # stderr) instead of ending the run without one
+        try:
+            fn()
+        except Exception as e:                     # noqa: BLE001 (reported, not hidden)
+            import traceback
+            traceback.print_exc(file=sys.stderr)
+            part = out.get(key)
+            if not isinstance(part, dict):
+                part = out[key] = {}
+            part["error"] = f"{type(e).__name__}: {e}"
+        section(key)
+
     if args.only in (None, "batch", "serve"):
-        batch, _ = run_batch(F, torch, args.batch_steps, 5)
-        if args.only != "serve":
-            out["batched"] = batch
-        section("batched")
-        if args.only in (None, "serve"):
-            out["served"], served_res, served_req = run_serve(F, torch, batch["value"],
-                                                              args.serve_requests, args.serve_steps)
-            section("served")
-            if not args.no_cpu_baseline:
-                out["served"]["oracle_check"] = served_oracle_check(served_res, served_req)
-                section("served oracle check")
+        def batched():
+            out["batched"], _ = run_batch(F, torch, args.batch_steps, 5)
+        guarded("batched", batched)
+        if args.only == "serve":
+            batch = out.pop("batched", {})
+        else:
+            batch = out.get("batched", {})
+        if args.only in (None, "serve") and "value" in batch:
+            def served():
+                out["served"], served_res, served_req = run_serve(F, torch, batch["value"],
+                                                                  args.serve_requests,
+                                                                  args.serve_steps)
+                if not args.no_cpu_baseline:
+                    out["served"]["oracle_check"] = served_oracle_check(served_res, served_req)
+            guarded("served", served)
     if args.only in (None, "plane"):
-        plain = out.get("ms_per_step")
-        if plain is None:
-            _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
-            plain = wall0 / K * 1e3
-        out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
-        section("plane_dft")
+        def plane():
+            plain = out.get("ms_per_step")
+            if plain is None:
+                _, _, _, wall0, _, _ = run_single(F, torch, K, W, tile)
+                plain = wall0 / K * 1e3
+            out["plane_dft"] = run_plane_dft(F, torch, K, W, plain)
+        guarded("plane_dft", plane)
     if args.only in (None, "eps", "eps_large", "eps_rw", "lossy_copper"):
-        out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large",
-                                     only=args.only if args.only in ("eps_rw", "lossy_copper") else None)
-        section("node_passes")
+        def material():
+            out["node_passes"] = run_eps(F, torch, large_only=args.only == "eps_large",
+                                         only=args.only if args.only in ("eps_rw", "lossy_copper")
+                                         else None)
+        guarded("node_passes", material)
     if args.only in (None, "zconv"):
-        out["zconv"] = run_zconv(F, torch)
-        section("zconv")
+        def zconv():
+            out["zconv"] = run_zconv(F, torch)
+        guarded("zconv", zconv)
     if args.only in (None, "shard"):
-        out["shard"] = run_shard(F, torch)
-        section("shard")
+        def shard():
+            out["shard"] = run_shard(F, torch)
+        guarded("shard", shard)
     if args.only in (None, "realistic"):
-        out["realistic"], real_board = run_realistic(F, torch)
-        if not args.no_cpu_baseline:
-            out["realistic"]["cpu_baseline"] = sampled_cpu(real_board)
-        out["small"], small_board = run_realistic(F, torch, "small")
-        if not args.no_cpu_baseline:
-            out["small"]["cpu_baseline"] = table1_cpu(small_board)
-        section("realistic and small")
+        def realistic():
+            out["realistic"], real_board = run_realistic(F, torch)
+            if not args.no_cpu_baseline:
+                out["realistic"]["cpu_baseline"] = sampled_cpu(real_board)
+        guarded("realistic", realistic)
+
+        def small():
+            out["small"], small_board = run_realistic(F, torch, "small")
+            if not args.no_cpu_baseline:
+                out["small"]["cpu_baseline"] = table1_cpu(small_board)
+        guarded("small", small)
     if args.only in (None, "table1"):
-        out["table1"], t1_board = run_table1(F, torch)
-        if not args.no_cpu_baseline:
-            out["table1"]["cpu_baseline"] = table1_cpu(t1_board)
-        section("table1")
+        def table1():
+            out["table1"], t1_board = run_table1(F, torch)
+            if not args.no_cpu_baseline:
+                out["table1"]["cpu_baseline"] = table1_cpu(t1_board)
+        guarded("table1", table1)
     if args.only in (None, "single") and not args.no_cpu_baseline:
-        import boardgen
-        out["cpu_baseline"] = cpu_baseline(boardgen.large_board())
-        section("cpu_baseline")
+        def cpu():
+            import boardgen
+            out["cpu_baseline"] = cpu_baseline(boardgen.large_board())
+        guarded("cpu_baseline", cpu)
     print(json.dumps(out), flush=True)
 
 
