@@ -84,3 +84,51 @@ def test_autotuned_tile_keeps_results(F, tmp_path):
     batch = _boards(5, 3)
     bshape = tune.tune_batch(batch, path=path)
     assert bshape in F.fdtd_tile_shapes()
+
+
+def _material(b, kind):
+    """A variant board in the node passes' arithmetic: "lossy" a lossy dielectric
+    (tan d 0.02) between copper planes; "eps_rw" its dielectric run through the
+    x/y PML to the outer wall, with Eq. 2's eps_rw."""
+    if kind == "lossy":
+        return boardgen.conductor_loss(boardgen.lossy_dielectric(b, 0.02))
+    ks = np.nonzero((b.eps_r_cell > 1.0).any(axis=(1, 2)))[0]
+    b.eps_r_cell[ks.min():ks.max() + 1] = b.eps_r_cell.max()
+    b.pml_eps_rw = True
+    return b
+
+
+def test_served_material_and_plain_boards_equal_alone(F):
+    """The pipelined loop (two workers, two chunks in flight) serving plain and
+    material boards together in odd-sized chunks: every probe series bitwise
+    equal to the board run alone, and every material board on the two-step
+    kernels."""
+    from paper_1008_2602_amd.serve import GpuExecutor, Server, SolveRequest
+    boards = _boards(33, 6)
+    boards[1] = _material(boards[1], "lossy")
+    boards[2] = _material(boards[2], "eps_rw")
+    boards[4] = _material(boards[4], "lossy")
+    reqs = [SolveRequest(i, 0.001 * i, b) for i, b in enumerate(boards)]
+    ex = GpuExecutor(allocator=F.TorchAllocator())
+    budget = sum(F.board_bytes(b) for b in boards)
+    announce(f"serving {len(reqs)} boards (3 material), chunk 37, pipelined")
+    srv = Server(ex, budget, chunk=37, workers=2, depth=2)
+    try:
+        res = srv.run(reqs)
+    finally:
+        ex.close()
+    assert [r.rid for r in res] == list(range(len(boards)))
+    assert srv.peak_resident >= 2
+    for r, b in zip(res, boards):
+        g, ids = F.grid_from_board(b)
+        try:
+            info = F.fdtd_get_info(g)
+            F.fdtd_step_n(g, b.steps)
+            F.fdtd_synchronize(g)
+            info = F.fdtd_get_info(g)
+            alone = np.stack([F.fdtd_get_probe(g, p, b.steps) for p in ids])
+        finally:
+            F.fdtd_destroy_grid(g)
+        assert info.material_two_step == (1 if b.pml_eps_rw or b.sigma_cell is not None else 0), b.name
+        assert np.abs(alone).max() > 0, b.name
+        assert np.array_equal(r.probes, alone), b.name
