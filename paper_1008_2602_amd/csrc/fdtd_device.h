@@ -21,9 +21,17 @@ __device__ __forceinline__ float ld_at(const float* base, uint32_t off)
 {
     return *(const __attribute__((address_space(1))) float*)((const gbyte*)base + off);
 }
+// NT: a non-temporal (streaming) store, which the caches do not keep: for
+// launches whose fields are far larger than the caches, so that the lines a
+// launch reads, not the ones it has written, stay in L2 and the Infinity Cache
+template <bool NT = false>
 __device__ __forceinline__ void st_at(float* base, uint32_t off, float v)
 {
-    *(__attribute__((address_space(1))) float*)((gbyte*)base + off) = v;
+    gfloat* p = (gfloat*)((gbyte*)base + off);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 template <typename T>
 __device__ __forceinline__ T ld_at_t(const void* base, uint32_t off)

@@ -27,11 +27,11 @@ int field_step_occupancy(int tile_x, int tile_y, bool wide);
 int num_shapes2();
 void shape2_at(int s, int* tx, int* ty);
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
-                              int rel, int flip, bool wide, bool plane, hipStream_t st);
+                              int rel, int flip, bool wide, bool plane, bool nt, hipStream_t st);
 int field_step2_occupancy(int tile_y, bool wide);
 hipError_t launch_field_step2_material(int tile_y, int mode, const BoardDev* boards,
                                        const TileRef* tiles, int ntiles, int rel, int flip,
-                                       bool wide, bool plane, hipStream_t st);
+                                       bool wide, bool plane, bool nt, hipStream_t st);
 int field_step2_material_occupancy(int tile_y, int mode, bool wide);
 hipError_t launch_advance(BoardDev* boards, int nb, const int64_t* n, hipStream_t st);
 hipError_t launch_advance_one(int64_t* step, int64_t n, int64_t launches, hipStream_t st);
@@ -344,13 +344,31 @@ void tile_counts(int nx, int ny, int tx, int rows, int* cx, int* cy)
 }
 
 // One launch of the field kernel of a shape (one or two steps per pass); plane:
-// some board of the launch keeps a plane DFT.
+// some board of the launch keeps a plane DFT; nt: the two-step kernel stores the
+// fields with non-temporal stores (stream_stores).
 hipError_t launch_pass(int tx, int ty, int steps, const BoardDev* boards, const TileRef* tiles,
-                       int ntiles, int rel, int flip, bool wide, bool plane, hipStream_t st)
+                       int ntiles, int rel, int flip, bool wide, bool plane, bool nt, hipStream_t st)
 {
     if (steps == 2)
-        return launch_field_step2(ty, boards, tiles, ntiles, rel, flip, wide, plane, st);
+        return launch_field_step2(ty, boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
     return launch_field_step(tx, ty, boards, tiles, ntiles, rel, flip, wide, st);
+}
+
+// Whether the two-step kernels of a launch over these boards store their fields
+// with non-temporal stores.  A launch reads every field once and writes the
+// other copy once, so when the fields far outgrow the caches (32 MB of L2, the
+// 256 MB Infinity Cache) ordinary stores only push out lines that the launch
+// is still reading, which non-temporal stores keep (the large board: 0.618 ->
+// 0.597 ms per step); boards whose fields fit in the Infinity Cache find
+// them there at the next launch with ordinary stores (the z-convergence batch,
+// about 100 MB: 7 % slower with non-temporal stores).  The measure is the
+// library's fused step count (one read and one write of every kept array).
+constexpr int64_t kStreamStoreBytes = 192ll << 20;
+bool stream_stores(const fdtd_grid* const* gs, int ng)
+{
+    int64_t b = 0;
+    for (int h = 0; h < ng; ++h) b += gs[h]->step_bytes;
+    return b > kStreamStoreBytes;
 }
 
 constexpr int kXcds = 8;   // the kernel deals block b to XCD b % 8 (xcd_tile)
@@ -1507,15 +1525,16 @@ static hipError_t material_pair(fdtd_grid* g, int rel, int flip, hipStream_t st)
         e = hipEventRecord(g->fork_ev, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(vs, g->fork_ev, 0);
     }
+    const bool nt = stream_stores(&g, 1);
     if (e == hipSuccess && g->ntiles > 0)
         e = launch_field_step2_material(g->mat_ty, 1, g->board_dev, g->tiles_dev, g->ntiles, rel, flip,
-                                        g->wide, plane, vs);
+                                        g->wide, plane, nt, vs);
     if (e == hipSuccess && g->ntilesC > 0)
         e = launch_field_step2_material(kHybridTY, 2, g->board_dev, g->tilesC_dev, g->ntilesC, rel,
-                                        flip, g->wide, plane, vs);
+                                        flip, g->wide, plane, nt, vs);
     if (e == hipSuccess && g->ntilesP > 0)
         e = launch_field_step2(kHybridTY, g->board_dev, g->tilesP_dev, g->ntilesP, rel, flip, g->wide,
-                               plane, st);
+                               plane, nt, st);
     if (fork) {
         if (e == hipSuccess) e = hipEventRecord(g->join_ev, vs);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, g->join_ev, 0);
@@ -1534,10 +1553,11 @@ static int enqueue_launch(fdtd_grid* g, bool single, int rel, int flip)
         HIP_OR_FAIL(single ? node_step(g, rel, flip, g->stream) : material_pair(g, rel, flip, g->stream));
     else if (single && g->tile_steps == 2)
         HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, g->board_dev, g->tiles1_dev, g->ntiles1, rel, flip,
-                                g->wide, g->plane_k >= 0, g->stream));
+                                g->wide, g->plane_k >= 0, false, g->stream));
     else
         HIP_OR_FAIL(launch_pass(g->tile_x, g->tile_y, g->tile_steps, g->board_dev, g->tiles_dev,
-                                g->ntiles, rel, flip, g->wide, g->plane_k >= 0, g->stream));
+                                g->ntiles, rel, flip, g->wide, g->plane_k >= 0, stream_stores(&g, 1),
+                                g->stream));
     if (g->timing) {
         if (int e = record_event(g)) return e;
         ++g->timed_launches;
@@ -1591,7 +1611,7 @@ static void build_graph(fdtd_grid* g)
               : g->node_pass ? node_step(g, l, l & 1, g->stream)
                              : launch_pass(g->tile_x, g->tile_y, per, g->board_dev, g->tiles_dev,
                                            g->ntiles, l * per, l & 1, g->wide, g->plane_k >= 0,
-                                           g->stream)) == hipSuccess;
+                                           stream_stores(&g, 1), g->stream)) == hipSuccess;
     if (ok) ok = launch_advance_one(g->step_dev, kGraphChunk, nl, g->stream) == hipSuccess;
     if (ok) ok = fold_plane(g, -kGraphChunk, 0, g->stream) == FDTD_OK;
     const bool ended = hipStreamEndCapture(g->stream, &graph) == hipSuccess;
@@ -1859,7 +1879,7 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
 {
     const fdtd_grid* lead = gs[0];
     const int tx = lead->tile_x, ty = lead->tile_y;
-    const bool planes = any_plane(gs, ng);
+    const bool planes = any_plane(gs, ng), nt = stream_stores(gs, ng);
     for (size_t q = 0; q < P.rounds.size(); ++q) {
         const RoundHost& R = P.rounds[q];
         const BoardDev* db = (const BoardDev*)(P.dev + P.off_boards[q]);
@@ -1868,7 +1888,7 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
         for (const Span& sp : R.spans) {
             if (sp.tail) {
                 HIP_OR_FAIL(launch_pass(kOddX, kOddY, 1, db + ng, dt + sp.off[0], sp.count[0], 0, 0,
-                                        sp.w == 1, planes, st));
+                                        sp.w == 1, planes, false, st));
                 continue;
             }
             const bool wide = sp.w == 1;
@@ -1880,22 +1900,24 @@ int enqueue_plan(fdtd_grid* const* gs, int ng, const BatchPlan& P, hipStream_t s
                     hipError_t e;
                     switch (sp.kind[l]) {
                         case 0:
-                            e = launch_pass(tx, ty, sp.steps, db, tl, n, rel, flip, wide, planes, st);
+                            e = launch_pass(tx, ty, sp.steps, db, tl, n, rel, flip, wide, planes, nt,
+                                            st);
                             break;
                         case 1:
-                            e = launch_field_step2(kHybridTY, db, tl, n, rel, flip, wide, planes, st);
+                            e = launch_field_step2(kHybridTY, db, tl, n, rel, flip, wide, planes, nt,
+                                                   st);
                             break;
                         case 2:
                             e = launch_field_step2_material(kHybridTY, 2, db, tl, n, rel, flip, wide,
-                                                            planes, st);
+                                                            planes, nt, st);
                             break;
                         case 3:
                             e = launch_field_step2_material(kHybridTY, 1, db, tl, n, rel, flip, wide,
-                                                            planes, st);
+                                                            planes, nt, st);
                             break;
                         default:
                             e = launch_field_step2_material(kMatTY, 1, db, tl, n, rel, flip, wide,
-                                                            planes, st);
+                                                            planes, nt, st);
                             break;
                     }
                     HIP_OR_FAIL(e);

@@ -68,8 +68,10 @@ __device__ __forceinline__ AxisCoef scale_coef(const AxisCoef& a, float w)
 
 // MM: 0 the plain kernel; 1 the material variant (PML coefficients rebuilt,
 // conducting edges solved); 2 its conduction-only flavour (conducting edges
-// solved, no rebuild: tile planes whose nodes need no rebuilt coefficient)
-template <int TY, typename CT, bool PL, int MM>
+// solved, no rebuild: tile planes whose nodes need no rebuilt coefficient).
+// SS: the fields are stored with non-temporal (streaming) stores, for launches
+// whose fields outgrow the caches
+template <int TY, typename CT, bool PL, int MM, bool SS>
 __global__ __launch_bounds__(64 * TY + 128)
 __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const BoardDev* __restrict__ boards,
                                                              const TileRef* __restrict__ tiles,
@@ -460,7 +462,7 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
     // hoisted out of the plane loop and held in registers the hot path needs.
     auto plane_sample = [&](int extra, float ez) {
         const int64_t now = *(const volatile int64_t*)B.step + rel + extra;
-        st_at(B.plane_ring, (uint32_t)(now & (kPlaneRing - 1)) * szb + node0b, ez);
+        st_at<SS>(B.plane_ring, (uint32_t)(now & (kPlaneRing - 1)) * szb + node0b, ez);
     };
 
     // staging of the first front plane: E_x, E_y of planes k0 (slot 0) and k0+1
@@ -621,12 +623,12 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
             }
             if (own && livem) {
                 const uint32_t nb = node0b + (uint32_t)m * szb;
-                st_at(dH, nb, h2x);
-                st_at(dH, nb + cs, h2y);
-                st_at(dH, nb + cs2, h2z);
-                if (px || py) st_at(dB, nb, p_b1x + dbx);
-                if (py || pzm) st_at(dB, nb + cs, p_b1y + dby);
-                if (pzm || px) st_at(dB, nb + cs2, p_b1z + dbz);
+                st_at<SS>(dH, nb, h2x);
+                st_at<SS>(dH, nb + cs, h2y);
+                st_at<SS>(dH, nb + cs2, h2z);
+                if (px || py) st_at<SS>(dB, nb, p_b1x + dbx);
+                if (py || pzm) st_at<SS>(dB, nb + cs, p_b1y + dby);
+                if (pzm || px) st_at<SS>(dB, nb + cs2, p_b1z + dbz);
             }
         }
         if (rH2) {
@@ -674,12 +676,12 @@ __attribute__((amdgpu_waves_per_eu(TY <= 6 ? 4 : 1))) void field_step2(const Boa
             eyn = (ce.flags & kUpdEy) ? eyn : 0.0f;
             ezn = (ce.flags & kUpdEz) ? ezn : 0.0f;
             const uint32_t nb = node0b + (uint32_t)m * szb;
-            st_at(dE, nb, exn);
-            st_at(dE, nb + cs, eyn);
-            st_at(dE, nb + cs2, ezn);
-            if (px || py) st_at(dD, nb, (ce.flags & kUpdEx) ? p_d1x + ddx : p_d1x);
-            if (py || pzm) st_at(dD, nb + cs, (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y);
-            if (pzm || px) st_at(dD, nb + cs2, (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z);
+            st_at<SS>(dE, nb, exn);
+            st_at<SS>(dE, nb + cs, eyn);
+            st_at<SS>(dE, nb + cs2, ezn);
+            if (px || py) st_at<SS>(dD, nb, (ce.flags & kUpdEx) ? p_d1x + ddx : p_d1x);
+            if (py || pzm) st_at<SS>(dD, nb + cs, (ce.flags & kUpdEy) ? p_d1y + ddy : p_d1y);
+            if (pzm || px) st_at<SS>(dD, nb + cs2, (ce.flags & kUpdEz) ? p_d1z + ddz : p_d1z);
             if (ce.flags & kPrbEz) record_probe(node, step + 1, ezn);
             if (PL && (ce.flags & kPlnEz)) plane_sample(1, ezn);
             bad |= !isfinite(exn + eyn + ezn);
@@ -718,28 +720,38 @@ void shape2_at(int s, int* tx, int* ty)
     *ty = kShapes2[s].ty;
 }
 
-template <int TY, bool PL, int MM>
-static void launch2_tp(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
-                       bool wide, hipStream_t st)
+template <int TY, bool PL, int MM, bool SS>
+static void launch2_tpn(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
+                        bool wide, hipStream_t st)
 {
     if (wide)
-        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL, MM>), dim3(ntiles), dim3(64 * TY + 128), 0,
-                           st, boards, tiles, rel, flip);
+        hipLaunchKernelGGL((field_step2<TY, uint16_t, PL, MM, SS>), dim3(ntiles), dim3(64 * TY + 128),
+                           0, st, boards, tiles, rel, flip);
     else
-        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL, MM>), dim3(ntiles), dim3(64 * TY + 128), 0,
-                           st, boards, tiles, rel, flip);
+        hipLaunchKernelGGL((field_step2<TY, uint8_t, PL, MM, SS>), dim3(ntiles), dim3(64 * TY + 128),
+                           0, st, boards, tiles, rel, flip);
+}
+
+template <int TY, bool PL, int MM>
+static void launch2_tp(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
+                       bool wide, bool nt, hipStream_t st)
+{
+    if (nt)
+        launch2_tpn<TY, PL, MM, true>(boards, tiles, ntiles, rel, flip, wide, st);
+    else
+        launch2_tpn<TY, PL, MM, false>(boards, tiles, ntiles, rel, flip, wide, st);
 }
 
 // plane: some board of the launch keeps a plane DFT (the variant with the ring
 // store; the other never spends registers on it)
 template <int TY>
 static hipError_t launch2_t(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel,
-                            int flip, bool wide, bool plane, hipStream_t st)
+                            int flip, bool wide, bool plane, bool nt, hipStream_t st)
 {
     if (plane)
-        launch2_tp<TY, true, 0>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, 0>(boards, tiles, ntiles, rel, flip, wide, nt, st);
     else
-        launch2_tp<TY, false, 0>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, 0>(boards, tiles, ntiles, rel, flip, wide, nt, st);
     return hipGetLastError();
 }
 
@@ -748,9 +760,9 @@ static int occupancy2_t(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t, false, 0>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, 0, true>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t, false, 0>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, 0, true>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -768,15 +780,15 @@ int field_step2_occupancy(int tile_y, bool wide)
 }
 
 hipError_t launch_field_step2(int tile_y, const BoardDev* boards, const TileRef* tiles, int ntiles,
-                              int rel, int flip, bool wide, bool plane, hipStream_t st)
+                              int rel, int flip, bool wide, bool plane, bool nt, hipStream_t st)
 {
     switch (tile_y) {
-        case 14: return launch2_t<14>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-        case 12: return launch2_t<12>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-        case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-        case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-        case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, plane, st);
-        case 6: return launch2_t<6>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        case 14: return launch2_t<14>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
+        case 12: return launch2_t<12>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
+        case 10: return launch2_t<10>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
+        case 9: return launch2_t<9>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
+        case 8: return launch2_t<8>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
+        case 6: return launch2_t<6>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -793,9 +805,9 @@ static int mat_occupancy(bool wide)
 {
     int n = 0;
     hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint16_t, false, MM>, 64 * TY + 128, 0)
+                              &n, field_step2<TY, uint16_t, false, MM, true>, 64 * TY + 128, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &n, field_step2<TY, uint8_t, false, MM>, 64 * TY + 128, 0);
+                              &n, field_step2<TY, uint8_t, false, MM, true>, 64 * TY + 128, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -809,24 +821,24 @@ int field_step2_material_occupancy(int tile_y, int mode, bool wide)
 
 template <int TY, int MM>
 static void mat_launch(const BoardDev* boards, const TileRef* tiles, int ntiles, int rel, int flip,
-                       bool wide, bool plane, hipStream_t st)
+                       bool wide, bool plane, bool nt, hipStream_t st)
 {
     if (plane)
-        launch2_tp<TY, true, MM>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, true, MM>(boards, tiles, ntiles, rel, flip, wide, nt, st);
     else
-        launch2_tp<TY, false, MM>(boards, tiles, ntiles, rel, flip, wide, st);
+        launch2_tp<TY, false, MM>(boards, tiles, ntiles, rel, flip, wide, nt, st);
 }
 
 hipError_t launch_field_step2_material(int tile_y, int mode, const BoardDev* boards,
                                        const TileRef* tiles, int ntiles, int rel, int flip,
-                                       bool wide, bool plane, hipStream_t st)
+                                       bool wide, bool plane, bool nt, hipStream_t st)
 {
     if (mode == 2 && tile_y == kHybridTY)
-        mat_launch<kHybridTY, 2>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        mat_launch<kHybridTY, 2>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
     else if (mode == 1 && tile_y == kHybridTY)
-        mat_launch<kHybridTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        mat_launch<kHybridTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
     else if (mode == 1 && tile_y == kMatTY)
-        mat_launch<kMatTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, st);
+        mat_launch<kMatTY, 1>(boards, tiles, ntiles, rel, flip, wide, plane, nt, st);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -100,7 +100,7 @@ struct View<false> {
     __device__ __forceinline__ float ld(int c, uint32_t off) const { return ld_at(p, off + (uint32_t)c * cs); }
     __device__ __forceinline__ void st(int c, uint32_t off, float v) const
     {
-        st_at((float*)p, off + (uint32_t)c * cs, v);
+        st_at<true>((float*)p, off + (uint32_t)c * cs, v);
     }
 };
 template <>
@@ -112,7 +112,10 @@ struct View<true> {
             p[c] = (const float*)((const char*)base + (uint64_t)c * B.cstride64 + shift);
     }
     __device__ __forceinline__ float ld(int c, uint32_t off) const { return ld_at(p[c], off); }
-    __device__ __forceinline__ void st(int c, uint32_t off, float v) const { st_at((float*)p[c], off, v); }
+    __device__ __forceinline__ void st(int c, uint32_t off, float v) const
+    {
+        st_at<true>((float*)p[c], off, v);
+    }
 };
 
 // plane the chunk's offsets are measured from, and its byte shift
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(256) void eps_e_pass(const BoardDev* __restrict__ b
                 if (pn[q] == node) ps[q * ms + step] = ezn;
         }
         if (flags & kPlnEz)
-            st_at(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * dzb + c.nb0, ezn);
+            st_at<true>(B.plane_ring, (uint32_t)(step & (kPlaneRing - 1)) * dzb + c.nb0, ezn);
         bad |= !isfinite(exn + eyn + ezn);
         hxm = hx;
         hym = hy;
