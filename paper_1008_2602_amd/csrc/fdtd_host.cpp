@@ -562,6 +562,132 @@ int64_t dev_index(const fdtd_grid* g, int i, int j, int k)
 // written once per stepped node (i < nx, j < ny, k < nz: one per cell), the
 // class byte(s) once, and each stored D/B component read and written once where
 // its PML predicate holds.
+// Marks, for one node plane, every tile of the 64 x kHybridTY x 2 grid whose
+// footprint holds a node with need bit `bit` (need: one byte per node of the
+// plane, x fastest): out[tile * stride] |= bit, tiles row-major.  A tile's
+// footprint is the nodes its block computes or reads: columns i0-2 .. i0+65,
+// rows j0-2 .. j0+kHybridTY-1.  2-D prefix sums of the plane's marks (pre is
+// scratch) make each tile one lookup.
+void mark_tile_need(const uint8_t* need, int nx, int ny, uint8_t bit, std::vector<int32_t>& pre,
+                    uint8_t* out, size_t stride)
+{
+    int hcx = 0, hcy = 0;
+    tile_counts(nx, ny, 64, owned_rows(kHybridTY, 2), &hcx, &hcy);
+    const int px = nx + 2;
+    // row 0 and column 0 stay zero; every other entry is written below
+    if (pre.size() != (size_t)(nx + 2) * (ny + 2)) pre.assign((size_t)(nx + 2) * (ny + 2), 0);
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i)
+            pre[(size_t)(j + 1) * px + i + 1] = ((need[(size_t)j * (nx + 1) + i] & bit) ? 1 : 0) +
+                                                pre[(size_t)j * px + i + 1] + pre[(size_t)(j + 1) * px + i] -
+                                                pre[(size_t)j * px + i];
+    for (int y = 0; y < hcy; ++y)
+        for (int x = 0; x < hcx; ++x) {
+            const int j0 = y * owned_rows(kHybridTY, 2), i0 = 64 * x;
+            const int ja = std::max(0, j0 - 2), jb = std::min(ny, j0 + kHybridTY - 1);
+            const int ia = std::max(0, i0 - 2), ib = std::min(nx, i0 + 65);
+            const int64_t sum = (int64_t)pre[(size_t)(jb + 1) * px + ib + 1] - pre[(size_t)ja * px + ib + 1] -
+                                pre[(size_t)(jb + 1) * px + ia] + pre[(size_t)ja * px + ia];
+            if (sum > 0) out[((size_t)y * hcx + x) * stride] |= bit;
+        }
+}
+
+// How a material board's pairs of steps are split between the plain two-step
+// kernel and the material variants.
+struct MaterialSplit {
+    std::vector<TileRef> rb, cd, plain;   // material variant, conduction-only flavour, plain kernel
+    int mat_ty = kHybridTY;               // the material variant's tile rows
+    int split = 0;                        // 0 none, 1 per tile, 2 per plane
+    int mat_permille = 0, cond_permille = 0;
+};
+
+// The split of a board of nx x ny x nz cells from tile_need (per tile of the
+// 64 x kHybridTY x 2 grid and node plane, bits 1 rebuilt coefficients, 2
+// conduction; empty: none).  A piece [kb, ke) of a tile computes first-step H
+// and E on planes kb-2 .. ke, so its plane k needs the kind of node found in
+// the footprint on planes k-2 .. k+1.  Planes near PML nodes whose
+// coefficients are rebuilt run the material variant; the others near
+// conducting edges its conduction-only flavour (which fits the hybrid shape
+// without spilling); the rest the plain kernel.  Runs of one kind in a tile
+// are one piece.  The material variant's planes are split one of two ways, the
+// cheaper by the measured cost of a tile plane on each kernel (large board, per
+// step: plain 64 x 14 0.615 ms, material 64 x 14 1.00 ms, material 64 x 10
+// 0.82 ms):
+//  * per tile: each tile's planes near such nodes on the variant in the plain
+//    kernel's tiles (where it spills), best when few tiles hold them (a board
+//    running into the PML with eps_rw);
+//  * per plane: planes near such nodes in any tile on the 64 x kMatTY variant
+//    for every tile, best when such nodes fill those planes.
+void split_material(int nx, int ny, int nz, const std::vector<uint8_t>& tile_need, MaterialSplit& out)
+{
+    out = MaterialSplit();
+    int cx, cy;
+    tile_counts(nx, ny, 64, owned_rows(kHybridTY, 2), &cx, &cy);
+    std::vector<uint8_t> kind((size_t)cx * cy * nz, 0), anyR((size_t)nz, 0);
+    int64_t rb_tp = 0;
+    for (size_t t = 0; t < (size_t)cx * cy; ++t) {
+        const uint8_t* tn = tile_need.empty() ? nullptr : &tile_need[t * (nz + 1)];
+        for (int k = 0; k < nz && tn; ++k) {
+            uint8_t m = 0;
+            for (int q = std::max(0, k - 2); q <= std::min(nz, k + 1); ++q) m |= tn[q];
+            const uint8_t kd = (m & 1) ? 1 : (m & 2) ? 2 : 0;   // 1 material, 2 conduction
+            kind[t * nz + k] = kd;
+            rb_tp += kd == 1;
+            anyR[k] |= kd == 1;
+        }
+    }
+    const double all = std::max<double>(1.0, (double)cx * cy * nz);
+    int64_t any_planes = 0;
+    for (int k = 0; k < nz; ++k) any_planes += anyR[k];
+    const double f_tile = rb_tp / all, f_plane = any_planes / (double)nz;
+    const double cost_tile = (1.0 - f_tile) * 0.615 + f_tile * 1.00;
+    const double cost_plane = (1.0 - f_plane) * 0.615 + f_plane * 0.82;
+    const bool per_plane = any_planes > 0 && cost_plane < cost_tile;
+    out.mat_ty = per_plane ? kMatTY : kHybridTY;
+    out.split = any_planes == 0 ? 0 : per_plane ? 2 : 1;
+    // pieces: runs of one kind in each tile (per plane: the material planes
+    // leave the tiles and go to 64 x kMatTY tiles over the whole board)
+    int64_t cd_tp = 0, rb_planes = 0;
+    for (int y = 0; y < cy; ++y)
+        for (int x = 0; x < cx; ++x) {
+            const uint8_t* kd = &kind[((size_t)y * cx + x) * nz];
+            auto k_of = [&](int k) -> int { return per_plane && anyR[k] ? 3 : kd[k]; };
+            for (int k = 0; k < nz;) {
+                const int c = k_of(k);
+                int e = k;
+                while (e < nz && k_of(e) == c) ++e;
+                if (c == 1) {
+                    out.rb.push_back(TileRef{0, x, y, k, e});
+                    rb_planes += e - k;
+                } else if (c == 2) {
+                    out.cd.push_back(TileRef{0, x, y, k, e});
+                    cd_tp += e - k;
+                } else if (c == 0) {
+                    out.plain.push_back(TileRef{0, x, y, k, e});
+                }
+                k = e;
+            }
+        }
+    if (per_plane) {
+        std::vector<TileRef> mt;
+        board_tiles(0, nx, ny, nz, 64, owned_rows(kMatTY, 2), mt);
+        for (int k = 0; k < nz;) {
+            int e = k;
+            while (e < nz && anyR[e] == anyR[k]) ++e;
+            if (anyR[k])
+                for (TileRef t : mt) {
+                    t.kb = k;
+                    t.ke = e;
+                    out.rb.push_back(t);
+                }
+            k = e;
+        }
+        rb_planes = (int64_t)(f_plane * all + 0.5);
+    }
+    out.mat_permille = (int)(1000.0 * rb_planes / all);
+    out.cond_permille = (int)(1000.0 * cd_tp / all);
+}
+
 int64_t count_step_bytes(const fdtd_grid* g)
 {
     const fdtd_grid_desc& d = g->d;
@@ -765,33 +891,9 @@ int finalize(fdtd_grid* g)
                 ids[(size_t)dev_index(g, i, j, k)] = (uint16_t)id;
             }
         if (!mat_plane[k]) continue;
-        // 2-D prefix sums of the plane's marks, one kind at a time; a tile's
-        // footprint is the nodes its block computes or reads: columns i0-2 ..
-        // i0+65, rows j0-2 .. j0+TY-1
-        if (tile_need.empty()) {
-            tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
-            pre.assign((size_t)(nx + 2) * (ny + 2), 0);
-        }
-        const int px = nx + 2;
-        for (uint8_t bit = 1; bit <= 2; bit <<= 1) {
-            if (!(mat_plane[k] & bit)) continue;
-            for (int j = 0; j <= ny; ++j)
-                for (int i = 0; i <= nx; ++i)
-                    pre[(size_t)(j + 1) * px + i + 1] = ((need[(size_t)j * (nx + 1) + i] & bit) ? 1 : 0) +
-                                                        pre[(size_t)j * px + i + 1] +
-                                                        pre[(size_t)(j + 1) * px + i] -
-                                                        pre[(size_t)j * px + i];
-            for (int y = 0; y < hcy; ++y)
-                for (int x = 0; x < hcx; ++x) {
-                    const int j0 = y * owned_rows(kHybridTY, 2), i0 = 64 * x;
-                    const int ja = std::max(0, j0 - 2), jb = std::min(ny, j0 + kHybridTY - 1);
-                    const int ia = std::max(0, i0 - 2), ib = std::min(nx, i0 + 65);
-                    const int64_t sum = (int64_t)pre[(size_t)(jb + 1) * px + ib + 1] -
-                                        pre[(size_t)ja * px + ib + 1] -
-                                        pre[(size_t)(jb + 1) * px + ia] + pre[(size_t)ja * px + ia];
-                    if (sum > 0) tile_need[((size_t)y * hcx + x) * (nz + 1) + k] |= bit;
-                }
-        }
+        if (tile_need.empty()) tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
+        for (uint8_t bit = 1; bit <= 2; bit <<= 1)
+            if (mat_plane[k] & bit) mark_tile_need(need.data(), nx, ny, bit, pre, &tile_need[k], nz + 1);
     }
     g->n_classes = (int)table.size();
     g->wide = table.size() > 256;
@@ -1352,100 +1454,23 @@ static int upload_tiles(fdtd_grid* g)
     g->mat_split = 0;
     if (g->mat) {
         // Tile planes near nodes that need the material arithmetic run a variant
-        // of the plain kernel (64 x kHybridTY x 2), the rest the plain kernel.  A
-        // piece [kb, ke) computes first-step H and E on planes kb-2 .. ke, so a
-        // tile's plane k is clear of a kind of node when no node of its
-        // footprint is of that kind on planes k-2 .. k+1.  Planes near PML nodes
-        // whose coefficients are rebuilt run the material variant; the others
-        // near conducting edges its conduction-only flavour (which fits the
-        // shape without spilling).  The material variant's planes are split one
-        // of two ways, the cheaper by the measured cost of a tile plane on each
-        // kernel (large board, per step: plain 64 x 14 0.615 ms, material 64 x 14
-        // 1.00 ms, material 64 x 10 0.82 ms):
-        //  * per tile: each tile's planes near such nodes on the variant in the
-        //    plain kernel's tiles (where it spills), best when few tiles hold
-        //    them (a board running into the PML with eps_rw);
-        //  * per plane: planes near such nodes in any tile on the 64 x kMatTY
-        //    variant for every tile, best when such nodes fill those planes.
-        // The kernels read one field copy and write the other, each its own
-        // pieces' nodes, and give the node passes' bits.
-        const int nz = g->d.nz;
-        int cx, cy;
-        tile_counts(g->d.nx, g->d.ny, 64, owned_rows(kHybridTY, 2), &cx, &cy);
-        std::vector<uint8_t> kind((size_t)cx * cy * nz, 0), anyR((size_t)nz, 0);
-        int64_t rb_tp = 0;
-        for (size_t t = 0; t < (size_t)cx * cy; ++t) {
-            const uint8_t* tn = g->tile_need.empty() ? nullptr : &g->tile_need[t * (nz + 1)];
-            for (int k = 0; k < nz && tn; ++k) {
-                uint8_t m = 0;
-                for (int q = std::max(0, k - 2); q <= std::min(nz, k + 1); ++q) m |= tn[q];
-                const uint8_t kd = (m & 1) ? 1 : (m & 2) ? 2 : 0;   // 1 material, 2 conduction
-                kind[t * nz + k] = kd;
-                rb_tp += kd == 1;
-                anyR[k] |= kd == 1;
-            }
-        }
-        const double all = std::max<double>(1.0, (double)cx * cy * nz);
-        int64_t any_planes = 0;
-        for (int k = 0; k < nz; ++k) any_planes += anyR[k];
-        const double f_tile = rb_tp / all, f_plane = any_planes / (double)nz;
-        const double cost_tile = (1.0 - f_tile) * 0.615 + f_tile * 1.00;
-        const double cost_plane = (1.0 - f_plane) * 0.615 + f_plane * 0.82;
-        const bool per_plane = any_planes > 0 && cost_plane < cost_tile;
-        g->mat_ty = per_plane ? kMatTY : kHybridTY;
-        g->mat_split = any_planes == 0 ? 0 : per_plane ? 2 : 1;
-        // pieces: runs of one kind in each tile (per plane: the material planes
-        // leave the tiles and go to 64 x kMatTY tiles over the whole board)
-        std::vector<TileRef> rb_pieces, cd_pieces, plain_pieces;
-        int64_t cd_tp = 0, rb_planes = 0;
-        for (int y = 0; y < cy; ++y)
-            for (int x = 0; x < cx; ++x) {
-                const uint8_t* kd = &kind[((size_t)y * cx + x) * nz];
-                auto k_of = [&](int k) -> int { return per_plane && anyR[k] ? 3 : kd[k]; };
-                for (int k = 0; k < nz;) {
-                    const int c = k_of(k);
-                    int e = k;
-                    while (e < nz && k_of(e) == c) ++e;
-                    if (c == 1) {
-                        rb_pieces.push_back(TileRef{0, x, y, k, e});
-                        rb_planes += e - k;
-                    } else if (c == 2) {
-                        cd_pieces.push_back(TileRef{0, x, y, k, e});
-                        cd_tp += e - k;
-                    } else if (c == 0) {
-                        plain_pieces.push_back(TileRef{0, x, y, k, e});
-                    }
-                    k = e;
-                }
-            }
-        if (per_plane) {
-            std::vector<TileRef> mt;
-            board_tiles(0, g->d.nx, g->d.ny, nz, 64, owned_rows(kMatTY, 2), mt);
-            for (int k = 0; k < nz;) {
-                int e = k;
-                while (e < nz && anyR[e] == anyR[k]) ++e;
-                if (anyR[k])
-                    for (TileRef t : mt) {
-                        t.kb = k;
-                        t.ke = e;
-                        rb_pieces.push_back(t);
-                    }
-                k = e;
-            }
-            rb_planes = (int64_t)(f_plane * all + 0.5);
-        }
-        g->mat_permille = (int)(1000.0 * rb_planes / all);
-        g->cond_permille = (int)(1000.0 * cd_tp / all);
-        g->pc_plain = plain_pieces;
-        g->pc_cd = cd_pieces;
-        g->pc_rb = rb_pieces;
-        if (int e = upload_pieces(g, g->mat_ty, 1, rb_pieces, &g->tiles_dev, &g->ntiles, &g->tiles_cap))
+        // of the plain kernel, the rest the plain kernel (split_material).  The
+        // kernels read one field copy and write the other, each its own pieces'
+        // nodes, and give the node passes' bits.
+        MaterialSplit ms;
+        split_material(g->d.nx, g->d.ny, g->d.nz, g->tile_need, ms);
+        g->mat_ty = ms.mat_ty;
+        g->mat_split = ms.split;
+        g->mat_permille = ms.mat_permille;
+        g->cond_permille = ms.cond_permille;
+        g->pc_plain = ms.plain;
+        g->pc_cd = ms.cd;
+        g->pc_rb = ms.rb;
+        if (int e = upload_pieces(g, g->mat_ty, 1, ms.rb, &g->tiles_dev, &g->ntiles, &g->tiles_cap))
             return e;
-        if (int e = upload_pieces(g, kHybridTY, 2, cd_pieces, &g->tilesC_dev, &g->ntilesC,
-                                  &g->tilesC_cap))
+        if (int e = upload_pieces(g, kHybridTY, 2, ms.cd, &g->tilesC_dev, &g->ntilesC, &g->tilesC_cap))
             return e;
-        if (int e = upload_pieces(g, kHybridTY, 0, plain_pieces, &g->tilesP_dev, &g->ntilesP,
-                                  &g->tilesP_cap))
+        if (int e = upload_pieces(g, kHybridTY, 0, ms.plain, &g->tilesP_dev, &g->ntilesP, &g->tilesP_cap))
             return e;
         if (g->ntilesP > 0 && g->ntiles + g->ntilesC > 0 && !g->aux_stream) {
             HIP_OR_FAIL(hipStreamCreateWithFlags(&g->aux_stream, hipStreamNonBlocking));

@@ -10,6 +10,11 @@
 //   host_logic coefs NX NY NZ DX DY DZ NLX NHX NLY NHY NLZ NHZ M R KMAX DT AXIS
 //       the FP32 coefficient table of one axis (Eq. 5 grading): one line per
 //       coefficient kind and half (node, half node), NAXIS + 1 values each
+//   host_logic matsplit NX NY NZ FILE
+//       a material board's split between the plain two-step kernel and its
+//       material variants, from FILE: one byte per node, x fastest, bit 1 where
+//       the node's PML coefficients are rebuilt, bit 2 where an edge conducts;
+//       "split S mat_ty T" then one line "rb|cd|plain tx ty kb ke" per piece
 #include "fdtd_host.cpp"
 
 #include <cstdlib>
@@ -48,6 +53,34 @@ int main(int argc, char** argv)
         }
         return 0;
     }
-    fprintf(stderr, "usage: host_logic worklist ... | coefs ...\n");
+    if (argc >= 6 && !strcmp(argv[1], "matsplit")) {
+        const int nx = atoi(argv[2]), ny = atoi(argv[3]), nz = atoi(argv[4]);
+        const size_t plane = (size_t)(nx + 1) * (ny + 1);
+        std::vector<uint8_t> need(plane * (nz + 1));
+        FILE* f = fopen(argv[5], "rb");
+        if (!f || fread(need.data(), 1, need.size(), f) != need.size()) return 3;
+        fclose(f);
+        // as the class build does: plane by plane, each kind of need on its own
+        int hcx = 0, hcy = 0;
+        tile_counts(nx, ny, 64, owned_rows(kHybridTY, 2), &hcx, &hcy);
+        std::vector<uint8_t> tile_need;
+        std::vector<int32_t> pre;
+        for (int k = 0; k <= nz; ++k) {
+            uint8_t bits = 0;
+            for (size_t n = 0; n < plane; ++n) bits |= need[k * plane + n];
+            if (!bits) continue;
+            if (tile_need.empty()) tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
+            for (uint8_t bit = 1; bit <= 2; bit <<= 1)
+                if (bits & bit) mark_tile_need(&need[k * plane], nx, ny, bit, pre, &tile_need[k], nz + 1);
+        }
+        MaterialSplit ms;
+        split_material(nx, ny, nz, tile_need, ms);
+        printf("split %d mat_ty %d\n", ms.split, ms.mat_ty);
+        for (const TileRef& t : ms.rb) printf("rb %d %d %d %d\n", t.tx, t.ty, t.kb, t.ke);
+        for (const TileRef& t : ms.cd) printf("cd %d %d %d %d\n", t.tx, t.ty, t.kb, t.ke);
+        for (const TileRef& t : ms.plain) printf("plain %d %d %d %d\n", t.tx, t.ty, t.kb, t.ke);
+        return 0;
+    }
+    fprintf(stderr, "usage: host_logic worklist ... | coefs ... | matsplit ...\n");
     return 2;
 }

@@ -12,6 +12,12 @@ kernel): the work list of a field launch and the FP32 coefficient tables.
 * Coefficient tables (set-up, the Eq. 5 grading rounded once to FP32): every
   entry of every axis equals the value built in FP64 from the oracle's own
   (sigma, kappa) at that node or half node, rounded once.
+* Material boards' split between the plain two-step kernel and its material
+  variants: from a map of the nodes that need the rebuilt coefficients or
+  conduct, every tile plane runs exactly once, on the kind of kernel that a brute
+  force over its footprint (columns i0-2 .. i0+65, rows j0-2 .. j0+13, planes
+  k-2 .. k+1) asks for; planes moved to the per-plane variant are covered by its
+  64x10 tiles over the whole board; a tile's pieces are maximal runs of one kind.
 """
 import os
 import shutil
@@ -137,3 +143,112 @@ def test_coefficient_tables_match_the_oracle_profiles(host_logic, oracle_mod, bi
         np.testing.assert_array_equal(got, want)
         if any(b.npml[2 * axis:2 * axis + 2]):
             assert (got[4] > 0).any()                 # the grading is there
+
+
+HY, HROWS = 14, 11      # the hybrid grid: 64 x 14 x 2 tiles own 11 rows
+MROWS = 7               # the per-plane material variant: 64 x 10 x 2 tiles own 7 rows
+
+
+def _need_maps():
+    """(name, nx, ny, nz, need[k, j, i]) with bit 1: rebuilt PML coefficients,
+    bit 2: a conducting edge."""
+    out = []
+    nx, ny, nz = 200, 120, 24
+    n = np.zeros((nz + 1, ny + 1, nx + 1), np.uint8)
+    out.append(("none", nx, ny, nz, n.copy()))
+    # a dielectric slab running into an 8-cell x/y PML (eps_rw): rebuilt nodes in
+    # the PML columns and rows of planes 9 .. 12, on a board wide enough that few
+    # tiles hold them (the per-tile split)
+    ex, ey = 640, 330
+    e = np.zeros((nz + 1, ey + 1, ex + 1), np.uint8)
+    pml = np.zeros((ey + 1, ex + 1), bool)
+    pml[:, :8] = pml[:, -8:] = True
+    pml[:8, :] = pml[-8:, :] = True
+    e[9:13][:, pml] = 1
+    out.append(("eps_rw_slab", ex, ey, nz, e))
+    # a lossy layer filling planes 6 .. 9 and a resistive sheet on plane 15
+    c = n.copy()
+    c[6:10] = 2
+    c[15, 20:100, 30:170] = 2
+    out.append(("lossy_layer", nx, ny, nz, c))
+    # rebuilt nodes filling planes 3 .. 4 (the per-plane split) and a few conducting edges
+    f = n.copy()
+    f[3:5] = 1
+    f[18, 50, 60] = 2
+    out.append(("filled_planes", nx, ny, nz, f))
+    # scattered nodes of both kinds on a board with ragged tiles
+    rng = np.random.default_rng(5)
+    nx, ny, nz = 170, 93, 17
+    r = np.zeros((nz + 1, ny + 1, nx + 1), np.uint8)
+    for bit, count in ((1, 6), (2, 9)):
+        for _ in range(count):
+            r[rng.integers(0, nz + 1), rng.integers(0, ny + 1), rng.integers(0, nx + 1)] |= bit
+    out.append(("scattered", nx, ny, nz, r))
+    return out
+
+
+def _expected_kinds(need, nx, ny, nz):
+    """kind[ty, tx, k] of the hybrid grid by brute force: 1 if the footprint on
+    planes k-2 .. k+1 holds a rebuilt node, else 2 if it holds a conducting edge,
+    else 0."""
+    cx, cy = -(-nx // 64), -(-ny // HROWS)
+    kind = np.zeros((cy, cx, nz), np.int64)
+    for ty in range(cy):
+        for tx in range(cx):
+            j0, i0 = ty * HROWS, tx * 64
+            fp = need[:, max(0, j0 - 2):min(ny, j0 + HY - 1) + 1, max(0, i0 - 2):min(nx, i0 + 65) + 1]
+            per_plane = np.bitwise_or.reduce(fp.reshape(nz + 1, -1), axis=1)
+            for k in range(nz):
+                m = np.bitwise_or.reduce(per_plane[max(0, k - 2):min(nz, k + 1) + 1])
+                kind[ty, tx, k] = 1 if m & 1 else (2 if m & 2 else 0)
+    return kind
+
+
+@pytest.mark.parametrize("case", _need_maps(), ids=lambda c: c[0])
+def test_material_split_runs_every_tile_plane_on_the_kind_its_footprint_needs(host_logic, tmp_path, case):
+    name, nx, ny, nz, need = case
+    path = tmp_path / "need.bin"
+    need.tofile(path)
+    lines = host_logic("matsplit", nx, ny, nz, path)
+    assert lines[0][0] == "split"
+    split, mat_ty = int(lines[0][1]), int(lines[0][3])
+    pieces = [(l[0], *map(int, l[1:])) for l in lines[1:]]
+    want = _expected_kinds(need, nx, ny, nz)
+    cy, cx = want.shape[:2]
+    any_r = (want == 1).any(axis=(0, 1))
+    # the documented choice between the two ways of splitting rebuilt planes
+    f_tile, f_plane = (want == 1).mean(), any_r.mean()
+    per_plane = any_r.any() and (1 - f_plane) * 0.615 + f_plane * 0.82 < (1 - f_tile) * 0.615 + f_tile * 1.00
+    assert split == (0 if not any_r.any() else 2 if per_plane else 1)
+    assert mat_ty == (10 if split == 2 else 14)
+    if name == "none":
+        assert split == 0 and all(p[0] == "plain" for p in pieces)
+    if name == "filled_planes":
+        assert split == 2
+    if name == "eps_rw_slab":
+        assert split == 1
+    got = np.full((cy, cx, nz), -1, np.int64)
+    mt_cx, mt_cy = -(-nx // 64), -(-ny // MROWS)
+    mt_seen = np.zeros((mt_cy, mt_cx, nz), np.int64)
+    code = {"plain": 0, "rb": 1, "cd": 2}
+    per_tile = {}
+    for kind, tx, ty, kb, ke in pieces:
+        assert 0 <= kb < ke <= nz
+        if kind == "rb" and split == 2:
+            assert 0 <= tx < mt_cx and 0 <= ty < mt_cy
+            mt_seen[ty, tx, kb:ke] += 1
+            continue
+        assert 0 <= tx < cx and 0 <= ty < cy
+        assert (got[ty, tx, kb:ke] == -1).all(), "a tile plane in two pieces"
+        got[ty, tx, kb:ke] = code[kind]
+        per_tile.setdefault((tx, ty), []).append((kb, ke, kind))
+    if split == 2:
+        # the rebuilt planes: every 64x10 tile once, and no hybrid piece there
+        assert (mt_seen[:, :, any_r] == 1).all() and (mt_seen[:, :, ~any_r] == 0).all()
+        assert (got[:, :, any_r] == -1).all()
+        assert (got[:, :, ~any_r] == want[:, :, ~any_r]).all()
+    else:
+        assert (got == want).all()
+    for spans in per_tile.values():
+        spans.sort()
+        assert all(a[2] != b[2] or a[1] != b[0] for a, b in zip(spans, spans[1:])), "runs not merged"
