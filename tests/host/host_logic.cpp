@@ -15,9 +15,54 @@
 //       material variants, from FILE: one byte per node, x fastest, bit 1 where
 //       the node's PML coefficients are rebuilt, bit 2 where an edge conducts;
 //       "split S mat_ty T" then one line "rb|cd|plain tx ty kb ke" per piece
+//   host_logic plan TX TY PER CUS SPEC
+//       one round of a batched call (fdtd_step_many) in the lead's shape
+//       TX x TY x PER on a device of CUS compute units (occupancy 1), for the
+//       boards of SPEC, one a line: "NX NY NZ STEPS MAT WIDE NEEDFILE" (MAT 1: a
+//       material board split by NEEDFILE as for matsplit; "-": none).  Prints
+//       "order h..." (boards in launch order), per span "span W STEPS S0 S1 TAIL",
+//       per list of the span "list KIND" and one line "e b tx ty kb ke" per entry,
+//       "node_tail H REL FLIP" per material board's single step, and
+//       "adv B STEPS LAUNCHES" per board of the order
 #include "fdtd_host.cpp"
 
 #include <cstdlib>
+#include <fstream>
+#include <memory>
+#include <sstream>
+
+// The kernels' occupancy is a property of the device; the plans here are built
+// for one block per compute unit of every shape.
+namespace fdtd {
+int field_step_occupancy(int, int, bool) { return 1; }
+int field_step2_occupancy(int, bool) { return 1; }
+int field_step2_material_occupancy(int, int, bool) { return 1; }
+}  // namespace fdtd
+
+static bool read_need(const char* path, int nx, int ny, int nz, std::vector<uint8_t>& tile_need)
+{
+    const size_t plane = (size_t)(nx + 1) * (ny + 1);
+    std::vector<uint8_t> need(plane * (nz + 1));
+    FILE* f = fopen(path, "rb");
+    if (!f) return false;
+    const bool ok = fread(need.data(), 1, need.size(), f) == need.size();
+    fclose(f);
+    if (!ok) return false;
+    // as the class build does: plane by plane, each kind of need on its own
+    int hcx = 0, hcy = 0;
+    tile_counts(nx, ny, 64, owned_rows(fdtd::kHybridTY, 2), &hcx, &hcy);
+    tile_need.clear();
+    std::vector<int32_t> pre;
+    for (int k = 0; k <= nz; ++k) {
+        uint8_t bits = 0;
+        for (size_t n = 0; n < plane; ++n) bits |= need[k * plane + n];
+        if (!bits) continue;
+        if (tile_need.empty()) tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
+        for (uint8_t bit = 1; bit <= 2; bit <<= 1)
+            if (bits & bit) mark_tile_need(&need[k * plane], nx, ny, bit, pre, &tile_need[k], nz + 1);
+    }
+    return true;
+}
 
 int main(int argc, char** argv)
 {
@@ -55,24 +100,8 @@ int main(int argc, char** argv)
     }
     if (argc >= 6 && !strcmp(argv[1], "matsplit")) {
         const int nx = atoi(argv[2]), ny = atoi(argv[3]), nz = atoi(argv[4]);
-        const size_t plane = (size_t)(nx + 1) * (ny + 1);
-        std::vector<uint8_t> need(plane * (nz + 1));
-        FILE* f = fopen(argv[5], "rb");
-        if (!f || fread(need.data(), 1, need.size(), f) != need.size()) return 3;
-        fclose(f);
-        // as the class build does: plane by plane, each kind of need on its own
-        int hcx = 0, hcy = 0;
-        tile_counts(nx, ny, 64, owned_rows(kHybridTY, 2), &hcx, &hcy);
         std::vector<uint8_t> tile_need;
-        std::vector<int32_t> pre;
-        for (int k = 0; k <= nz; ++k) {
-            uint8_t bits = 0;
-            for (size_t n = 0; n < plane; ++n) bits |= need[k * plane + n];
-            if (!bits) continue;
-            if (tile_need.empty()) tile_need.assign((size_t)hcx * hcy * (nz + 1), 0);
-            for (uint8_t bit = 1; bit <= 2; bit <<= 1)
-                if (bits & bit) mark_tile_need(&need[k * plane], nx, ny, bit, pre, &tile_need[k], nz + 1);
-        }
+        if (!read_need(argv[5], nx, ny, nz, tile_need)) return 3;
         MaterialSplit ms;
         split_material(nx, ny, nz, tile_need, ms);
         printf("split %d mat_ty %d\n", ms.split, ms.mat_ty);
@@ -81,6 +110,62 @@ int main(int argc, char** argv)
         for (const TileRef& t : ms.plain) printf("plain %d %d %d %d\n", t.tx, t.ty, t.kb, t.ke);
         return 0;
     }
-    fprintf(stderr, "usage: host_logic worklist ... | coefs ... | matsplit ...\n");
+    if (argc >= 7 && !strcmp(argv[1], "plan")) {
+        std::vector<std::unique_ptr<fdtd_grid>> hs;
+        std::vector<int64_t> n;
+        std::ifstream spec(argv[6]);
+        std::string line;
+        while (std::getline(spec, line)) {
+            std::istringstream in(line);
+            int nx, ny, nz, mat, wide;
+            int64_t steps;
+            std::string needfile;
+            if (!(in >> nx >> ny >> nz >> steps >> mat >> wide >> needfile)) continue;
+            auto g = std::make_unique<fdtd_grid>();
+            g->d.nx = nx;
+            g->d.ny = ny;
+            g->d.nz = nz;
+            g->wide = wide != 0;
+            g->mat = mat != 0;
+            g->cus = atoi(argv[5]);
+            g->tile_x = atoi(argv[2]);
+            g->tile_y = atoi(argv[3]);
+            g->tile_steps = atoi(argv[4]);
+            if (g->mat) {
+                std::vector<uint8_t> tile_need;
+                if (needfile != "-" && !read_need(needfile.c_str(), nx, ny, nz, tile_need)) return 3;
+                MaterialSplit ms;
+                split_material(nx, ny, nz, tile_need, ms);
+                g->mat_ty = ms.mat_ty;
+                g->pc_plain = ms.plain;
+                g->pc_cd = ms.cd;
+                g->pc_rb = ms.rb;
+            }
+            hs.push_back(std::move(g));
+            n.push_back(steps);
+        }
+        std::vector<fdtd_grid*> gs;
+        for (auto& g : hs) gs.push_back(g.get());
+        RoundHost r;
+        plan_round(gs.data(), (int)gs.size(), n.data(), r);
+        printf("order");
+        for (int h : r.order) printf(" %d", h);
+        printf("\n");
+        for (const Span& sp : r.spans) {
+            printf("span %d %d %lld %lld %d\n", sp.w, sp.steps, (long long)sp.s0, (long long)sp.s1, (int)sp.tail);
+            for (int l = 0; l < sp.nl; ++l) {
+                printf("list %d\n", sp.kind[l]);
+                for (int q = 0; q < sp.count[l]; ++q) {
+                    const TileRef& t = r.items[(size_t)sp.off[l] + q];
+                    printf("e %d %d %d %d %d\n", t.board, t.tx, t.ty, t.kb, t.ke);
+                }
+            }
+        }
+        for (const NodeTail& t : r.node_tails) printf("node_tail %d %d %d\n", t.h, t.rel, t.flip);
+        for (size_t b = 0; b < gs.size(); ++b)
+            printf("adv %zu %lld %lld\n", b, (long long)r.adv[2 * b], (long long)r.adv[2 * b + 1]);
+        return 0;
+    }
+    fprintf(stderr, "usage: host_logic worklist ... | coefs ... | matsplit ... | plan ...\n");
     return 2;
 }

@@ -18,6 +18,12 @@ kernel): the work list of a field launch and the FP32 coefficient tables.
   force over its footprint (columns i0-2 .. i0+65, rows j0-2 .. j0+13, planes
   k-2 .. k+1) asks for; planes moved to the per-plane variant are covered by its
   64x10 tiles over the whole board; a tile's pieces are maximal runs of one kind.
+* One round of a batched call (`fdtd_step_many`): boards go in launch order by
+  group (class width, material or not) and falling step count; every board runs
+  exactly its steps (passes of the shape, then one single step or, for a
+  material board, a node-pass step when the count is odd); every pass of a span
+  steps every plane of every tile (or piece) of exactly the boards still running,
+  and no other.
 """
 import os
 import shutil
@@ -252,3 +258,123 @@ def test_material_split_runs_every_tile_plane_on_the_kind_its_footprint_needs(ho
     for spans in per_tile.values():
         spans.sort()
         assert all(a[2] != b[2] or a[1] != b[0] for a, b in zip(spans, spans[1:])), "runs not merged"
+
+
+def _parse_plan(lines):
+    order, spans, node_tails, adv = None, [], [], {}
+    for l in lines:
+        if l[0] == "order":
+            order = [int(v) for v in l[1:]]
+        elif l[0] == "span":
+            spans.append(dict(w=int(l[1]), steps=int(l[2]), s0=int(l[3]), s1=int(l[4]), tail=l[5] == "1",
+                              lists=[]))
+        elif l[0] == "list":
+            spans[-1]["lists"].append((int(l[1]), []))
+        elif l[0] == "e":
+            spans[-1]["lists"][-1][1].append(tuple(int(v) for v in l[1:]))
+        elif l[0] == "node_tail":
+            node_tails.append(tuple(int(v) for v in l[1:]))
+        elif l[0] == "adv":
+            adv[int(l[1])] = (int(l[2]), int(l[3]))
+    return order, spans, node_tails, adv
+
+
+def _tiles(nx, ny, nz, tx, rows):
+    return {(ix, iy) for ix in range(-(-nx // tx)) for iy in range(-(-ny // rows))}
+
+
+def _check_cover(entries, tiles, nz, what):
+    seen = {}
+    for ix, iy, kb, ke in entries:
+        assert (ix, iy) in tiles, what
+        seen.setdefault((ix, iy), []).append((kb, ke))
+    assert set(seen) == tiles, what
+    for spans in seen.values():
+        spans.sort()
+        assert spans[0][0] == 0 and spans[-1][1] == nz and all(a[1] == b[0] for a, b in zip(spans, spans[1:])), what
+
+
+PLAN_CASES = [
+    # lead shape (tx, ty, steps per pass); boards (nx, ny, nz, steps, material need map or None, wide)
+    ("plain_mixed", (64, 14, 2), [(100, 80, 20, 7, None, 0), (150, 90, 30, 4, None, 0), (90, 70, 20, 5, None, 1)]),
+    ("plain_many", (64, 8, 2), [(130, 120, 25, n, None, 0) for n in (6, 6, 3, 1, 0, 9)]),
+    ("one_step", (64, 15, 1), [(200, 90, 22, 5, None, 0), (70, 60, 18, 2, None, 0)]),
+    ("material", (64, 14, 2), [(200, 120, 24, 7, "lossy_layer", 0), (640, 330, 24, 6, "eps_rw_slab", 0),
+                               (200, 120, 24, 3, "filled_planes", 1), (300, 100, 24, 5, None, 0),
+                               (120, 100, 24, 4, None, 0)]),
+]
+
+
+@pytest.mark.parametrize("case", PLAN_CASES, ids=lambda c: c[0])
+def test_batched_round_runs_every_board_its_steps_on_every_tile(host_logic, tmp_path, case):
+    name, (tx, ty, per), boards = case
+    maps = {m[0]: m for m in _need_maps()}
+    spec, split = [], {}
+    for h, (nx, ny, nz, n, need, wide) in enumerate(boards):
+        path = "-"
+        if need is not None:
+            mname, mx, my, mz, arr = maps[need]
+            assert (mx, my, mz) == (nx, ny, nz)
+            path = str(tmp_path / f"need{h}.bin")
+            arr.tofile(path)
+            lines = host_logic("matsplit", nx, ny, nz, path)
+            mat_ty = int(lines[0][3])
+            split[h] = {k: {(int(l[1]), int(l[2]), int(l[3]), int(l[4])) for l in lines[1:] if l[0] == k}
+                        for k in ("plain", "cd", "rb")}
+            split[h]["mat_ty"] = mat_ty
+        spec.append(f"{nx} {ny} {nz} {n} {1 if need else 0} {wide} {path}")
+    (tmp_path / "spec.txt").write_text("\n".join(spec) + "\n")
+    order, spans, node_tails, adv = _parse_plan(host_logic("plan", tx, ty, per, 256, tmp_path / "spec.txt"))
+    ng = len(boards)
+    assert sorted(order) == list(range(ng))
+    group = [2 * (boards[h][4] is not None) + boards[h][5] for h in range(ng)]
+    keys = [(group[h], -boards[h][3]) for h in order]
+    assert keys == sorted(keys), "launch order: by group, then falling step count"
+    done = [0] * ng
+    per_of = [2 if boards[h][4] is not None else per for h in range(ng)]
+    npass = [boards[h][3] // per_of[h] for h in range(ng)]
+    for sp in spans:
+        in_span = {}
+        for kind, ents in sp["lists"]:
+            for b, ix, iy, kb, ke in ents:
+                if b < 0:
+                    continue
+                in_span.setdefault(order[b], {}).setdefault(kind, []).append((ix, iy, kb, ke))
+        for h, by_kind in in_span.items():
+            nx, ny, nz, n, need, wide = boards[h]
+            assert sp["w"] == wide
+            if sp["tail"]:
+                assert need is None and per == 2 and n % 2 == 1
+                _check_cover(by_kind[0], _tiles(nx, ny, nz, 64, 14), nz, (name, h, "tail"))
+                done[h] += 1
+                continue
+            assert sp["steps"] == per_of[h]
+            if need is None:
+                assert set(by_kind) == {0}
+                _check_cover(by_kind[0], _tiles(nx, ny, nz, tx, ty - 3 if per == 2 else ty - 1), nz, (name, h))
+            else:
+                # each kind's list steps the planes of the board's pieces of that
+                # kind once (the work list may cut a piece into shorter ones)
+                sh = split[h]
+
+                def planes(pcs):
+                    out = [(ix, iy, k) for ix, iy, kb, ke in pcs for k in range(kb, ke)]
+                    assert len(out) == len(set(out)), (name, h, "a plane twice")
+                    return set(out)
+                rb_kind = 3 if sh["mat_ty"] == 14 else 4
+                for kind, key in ((1, "plain"), (2, "cd"), (rb_kind, "rb")):
+                    assert planes(by_kind.get(kind, [])) == planes(sh[key]), (name, h, key)
+                assert not by_kind.get(7 - rb_kind)
+            done[h] += (sp["s1"] - sp["s0"]) * sp["steps"]
+        # the boards of a span are exactly those of its group still running through it
+        if not sp["tail"]:
+            want = {h for h in range(ng) if group[h] == group[next(iter(in_span))] and npass[h] >= sp["s1"]}
+            assert set(in_span) == want, (name, sp["s0"], sp["s1"])
+    for h, rel, flip in node_tails:
+        assert boards[h][4] is not None and boards[h][3] % 2 == 1
+        assert rel == npass[h] * 2 and flip == npass[h] % 2
+        done[h] += 1
+    assert done == [b[3] for b in boards]
+    for b, h in enumerate(order):
+        n = boards[h][3]
+        assert adv[b] == (n, npass[h] + n % per_of[h])
